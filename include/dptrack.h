@@ -1,0 +1,153 @@
+/*
+ * dptrack.h - C ABI of the MI355X (gfx950) direct photometric tracker.
+ *
+ * Pose-only direct photometric tracking of a frame against a sparse map
+ * (paper Sec. III): an image pyramid, an inverse-compositional (IC) precompute
+ * per reference frame, and a per-frame coarse-to-fine Gauss-Newton track whose
+ * normal equations are reduced and solved on the GPU.
+ *
+ * Conventions shared by every entry point
+ *   - Return value: DPT_OK (0) or a negative dpt_error.  dpt_last_error() gives a
+ *     message for the calling thread, valid until that thread's next call.
+ *     Nothing throws across the ABI and nothing aborts.
+ *   - A tracking failure is not an API error: dpt_track_frame returns DPT_OK and
+ *     reports it in dpt_result.status together with the best pose reached.
+ *   - Poses are world -> camera, row-major 4x4 doubles (Eq.(1): u = pi(T P)).
+ *   - Images are uint8 grayscale, row-major, with a row pitch in bytes >= width.
+ *     Pixel centres sit at integer coordinates.
+ *   - The caller owns every input buffer; it is only borrowed for the duration
+ *     of the call.  A context copies what it keeps into device memory it owns.
+ *   - "on_device" flags say whether a pointer is device memory (HIP) or host
+ *     memory.  Device inputs must stay valid until the call returns.
+ *   - All GPU work of a context is ordered on the HIP stream given at creation
+ *     (NULL = the null stream).  Calls that return host results synchronise that
+ *     stream before returning.
+ *   - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef DPTRACK_H
+#define DPTRACK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DPT_OK = 0,
+  DPT_E_ARG = -1,   /* invalid argument: NULL pointer, size or flag out of range */
+  DPT_E_HIP = -2,   /* a HIP runtime call or kernel launch failed */
+  DPT_E_STATE = -3, /* call out of order (no pyramid / no reference points yet) */
+  DPT_E_OOM = -4    /* device or pinned host allocation failed */
+} dpt_error;
+
+/* dpt_result.status */
+enum {
+  DPT_TRACK_OK = 0,             /* converged at level 0 */
+  DPT_TRACK_MAX_ITERS = 1,      /* level 0 used all max_iters iterations (pose still returned) */
+  DPT_TRACK_TOO_FEW_POINTS = 2, /* fewer than min_points valid points at some iteration */
+  DPT_TRACK_NOT_PD = 3          /* normal matrix not positive definite (Cholesky pivot too small) */
+};
+
+/* dpt_params.precision */
+enum { DPT_PREC_FP32 = 0, DPT_PREC_MIXED = 1 };
+
+/* pyramid slots */
+enum { DPT_SLOT_REF = 0, DPT_SLOT_CUR = 1 };
+
+/* Level-0 pinhole camera: u = fx X/Z + cx, v = fy Y/Z + cy.  Level l uses
+ * f/2^l and (c + 0.5)/2^l - 0.5, consistent with the 2x2 box pyramid. */
+typedef struct {
+  int32_t width, height; /* 16 <= width, height <= 8192 */
+  double fx, fy, cx, cy;
+} dpt_camera;
+
+typedef struct {
+  int32_t levels;       /* pyramid levels, 1..8; level l is floor(W/2^l) x floor(H/2^l) */
+  int32_t max_iters;    /* Gauss-Newton iterations per level, 1..100 */
+  float huber_k;        /* Huber threshold in intensity levels; <= 0 = plain least squares */
+  float step_eps;       /* a level ends when max_j |delta_j| < step_eps (rad, m) */
+  float z_min;          /* points with camera depth <= z_min (m) are invalid */
+  int32_t min_points;   /* fewer valid points: DPT_TRACK_TOO_FEW_POINTS */
+  int32_t n_pattern;    /* patch samples per point K, 1..128 */
+  int8_t pattern[256];  /* K (dx, dy) offsets in level pixels, |d| <= 16, same at every level */
+  int32_t precision;    /* DPT_PREC_FP32 */
+  int32_t flags;        /* reserved, 0 */
+} dpt_params;
+
+typedef struct {
+  double T_cw[16];             /* world -> current camera */
+  double final_cost;           /* mean Huber cost over the valid level-0 samples at T_cw (0 if none) */
+  int32_t iterations;          /* Gauss-Newton updates applied, all levels */
+  int32_t iters_per_level[8];  /* updates per level (index = level) */
+  int32_t n_valid_points;      /* valid level-0 points at T_cw */
+  int32_t status;              /* DPT_TRACK_* */
+  int64_t samples;             /* residual samples evaluated, all passes */
+} dpt_result;
+
+typedef struct dpt_ctx dpt_ctx;
+
+/* Thread-local message of the last failed call on this thread ("" if none). */
+const char* dpt_last_error(void);
+
+/* Create a single-stream tracker.  max_points bounds every later reference map
+ * (1..65536).  hip_stream: a hipStream_t, or NULL.  Allocates all device memory
+ * the context needs: two pyramids, the per-level IC cache (12 bytes per sample
+ * and level), staging buffers.  *out receives the context. */
+int dpt_create(const dpt_camera* cam, const dpt_params* prm, int32_t max_points, void* hip_stream, dpt_ctx** out);
+
+/* Release a context and all its memory (NULL is a no-op). */
+void dpt_destroy(dpt_ctx* ctx);
+
+/* Build the uint8 pyramid of one slot from an image (paper Sec. III-C, "Image
+ * pyramids"; read here as 2x2 box means rounded half up, floor sizes).
+ * slot: DPT_SLOT_REF or DPT_SLOT_CUR.  img: width x height bytes, row pitch
+ * `pitch` >= width, in device memory if img_on_device else host memory.
+ * Building the REF slot invalidates the reference points. */
+int dpt_build_pyramid(dpt_ctx* ctx, int32_t slot, const uint8_t* img, int64_t pitch, int32_t img_on_device);
+
+/* Copy level `level` of a slot's pyramid (floor(W/2^l) x floor(H/2^l), packed
+ * rows) to host memory.  Test hook for bit-exact comparison. */
+int dpt_get_pyramid(dpt_ctx* ctx, int32_t slot, int32_t level, uint8_t* host_dst);
+
+/* Map-point selection on the REF slot's level 0 (stand-in for the map points the
+ * indirect pipeline provides, Sec. II): the n pixels with the largest integer
+ * score (I[y][x+1]-I[y][x-1])^2 + (I[y+1][x]-I[y-1][x])^2 inside
+ * margin <= x <= W-1-margin, margin <= y <= H-1-margin (margin >= 1), ties to the
+ * smaller linear index y*W+x.  Writes min(n, candidates) indices in ascending
+ * order to host_idx (capacity n) and their count to *n_out. */
+int dpt_select_points(dpt_ctx* ctx, int32_t n, int32_t margin, int32_t* host_idx, int32_t* n_out);
+
+/* Set the reference map and run the IC precompute on the REF pyramid (Sec.
+ * III-C "Precompute Inverse Compositional", Eq.(6)): for each level and point,
+ * x0 = T_rw P, the patch intensities I0 and reference-side gradients are cached;
+ * the Jacobian is rebuilt from them and x0 during tracking.
+ * xyz_world: n x 3 floats (device memory if xyz_on_device).  T_rw: world ->
+ * reference camera.  0 <= n <= max_points. */
+int dpt_set_reference_points(dpt_ctx* ctx, const float* xyz_world, int32_t n, const double T_rw[16],
+                             int32_t xyz_on_device);
+
+/* Track the CUR pyramid against the reference (Sec. III-C "Track"; Eq.(2)-(5)):
+ * coarse to fine, per level up to max_iters Huber-weighted Gauss-Newton steps,
+ * the 21 + 6 normal-equation terms reduced on the GPU, a Cholesky solve and the
+ * inverse-compositional update T_rel <- T_rel exp(delta)^-1 on the GPU, then a
+ * cost-only pass at level 0.  T_cw_init: start pose.  Synchronises the stream
+ * and fills *out. */
+int dpt_track_frame(dpt_ctx* ctx, const double T_cw_init[16], dpt_result* out);
+
+/* Test hook: copies of level `level`'s IC cache.  Any pointer may be NULL.
+ * valid: n bytes; I0, gx, gy: n*K floats (sample i*K+k); x0: n*3 floats. */
+int dpt_get_reference_cache(dpt_ctx* ctx, int32_t level, uint8_t* valid, float* I0, float* gx, float* gy, float* x0);
+
+/* Test hook: one normal-equation pass (Eq.(5), Huber-weighted) at `level` and the
+ * relative pose T_rel = T_cw T_rw^-1 (4x4 row-major doubles, used in FP32).
+ * H21: upper triangle of H, row-major (H00 H01 .. H05 H11 .. H55); b6; E: sum of
+ * Huber costs; n: valid samples; npts: valid points. */
+int dpt_normal_equations(dpt_ctx* ctx, int32_t level, const double T_rel[16], float* H21, float* b6, double* E,
+                         int64_t* n, int32_t* npts);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DPTRACK_H */

@@ -1,0 +1,210 @@
+"""Python binding of the MI355X direct photometric tracker (libdptrack.so).
+
+Argument marshalling only: every step of the tracking path runs in the HIP
+kernels behind the C ABI declared in ``include/dptrack.h``.  Host inputs are
+NumPy arrays; device inputs are torch CUDA tensors (``data_ptr()``), and the
+HIP stream defaults to torch's current stream.  There is no CPU fallback: if
+the library is not built, :func:`load` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdptrack.so")
+_lib = None
+
+DPT_OK, DPT_E_ARG, DPT_E_HIP, DPT_E_STATE, DPT_E_OOM = 0, -1, -2, -3, -4
+TRACK_OK, TRACK_MAX_ITERS, TRACK_TOO_FEW_POINTS, TRACK_NOT_PD = 0, 1, 2, 3
+PREC_FP32, PREC_MIXED = 0, 1
+SLOT_REF, SLOT_CUR = 0, 1
+DEFAULT_PATTERN = ((-2, 0), (2, 0), (0, -2), (0, 2), (-1, -1), (1, -1), (-1, 1), (1, 1))
+
+
+class DptError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"dptrack error {code}: {msg}")
+        self.code = code
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("fx", ctypes.c_double),
+                ("fy", ctypes.c_double), ("cx", ctypes.c_double), ("cy", ctypes.c_double)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("huber_k", ctypes.c_float),
+                ("step_eps", ctypes.c_float), ("z_min", ctypes.c_float), ("min_points", ctypes.c_int32),
+                ("n_pattern", ctypes.c_int32), ("pattern", ctypes.c_int8 * 256), ("precision", ctypes.c_int32),
+                ("flags", ctypes.c_int32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("T_cw", ctypes.c_double * 16), ("final_cost", ctypes.c_double), ("iterations", ctypes.c_int32),
+                ("iters_per_level", ctypes.c_int32 * 8), ("n_valid_points", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("samples", ctypes.c_int64)]
+
+    def as_dict(self) -> dict:
+        return dict(T_cw=np.array(self.T_cw[:]).reshape(4, 4), final_cost=self.final_cost,
+                    iterations=self.iterations, iters_per_level=list(self.iters_per_level),
+                    n_valid_points=self.n_valid_points, status=self.status, samples=self.samples)
+
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+
+# name -> (restype, argtypes); the ABI test checks this list against include/dptrack.h
+SIGNATURES = {
+    "dpt_last_error": (ctypes.c_char_p, []),
+    "dpt_create": (ctypes.c_int, [ctypes.POINTER(Camera), ctypes.POINTER(Params), _i32, _vp, ctypes.POINTER(_vp)]),
+    "dpt_destroy": (None, [_vp]),
+    "dpt_build_pyramid": (ctypes.c_int, [_vp, _i32, _vp, _i64, _i32]),
+    "dpt_get_pyramid": (ctypes.c_int, [_vp, _i32, _i32, _vp]),
+    "dpt_select_points": (ctypes.c_int, [_vp, _i32, _i32, _vp, ctypes.POINTER(_i32)]),
+    "dpt_set_reference_points": (ctypes.c_int, [_vp, _vp, _i32, ctypes.POINTER(ctypes.c_double), _i32]),
+    "dpt_track_frame": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(Result)]),
+    "dpt_get_reference_cache": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, _vp, _vp]),
+    "dpt_normal_equations": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ctypes.c_double), _vp, _vp,
+                                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64),
+                                            ctypes.POINTER(_i32)]),
+}
+
+
+def load():
+    """Load libdptrack.so (built by ``paper_2607_16897_amd.build``); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; g.build()'`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(code: int):
+    if code != DPT_OK:
+        raise DptError(code, load().dpt_last_error().decode())
+
+
+def _mat(T) -> ctypes.Array:
+    T = np.ascontiguousarray(np.asarray(T, dtype=np.float64).reshape(16))
+    return (ctypes.c_double * 16)(*T.tolist())
+
+
+def _ptr(x):
+    """(pointer, on_device, keepalive) for a NumPy array or a torch CUDA tensor."""
+    if isinstance(x, np.ndarray):
+        x = np.ascontiguousarray(x)
+        return x.ctypes.data, 0, x
+    import torch
+
+    if isinstance(x, torch.Tensor):
+        if not x.is_contiguous():
+            x = x.contiguous()
+        return x.data_ptr(), int(x.is_cuda), x
+    raise TypeError(f"unsupported buffer type {type(x)}")
+
+
+def make_camera(cam) -> Camera:
+    return Camera(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy)
+
+
+def make_params(levels=3, max_iters=10, huber_k=9.0, step_eps=1e-5, z_min=1e-3, min_points=10,
+                pattern=DEFAULT_PATTERN, precision=PREC_FP32, flags=0) -> Params:
+    p = Params()
+    p.levels, p.max_iters, p.huber_k, p.step_eps, p.z_min = levels, max_iters, huber_k, step_eps, z_min
+    p.min_points, p.precision, p.flags = min_points, precision, flags
+    pat = np.asarray(pattern, np.int32).reshape(-1, 2)
+    p.n_pattern = len(pat)
+    for i, v in enumerate(pat.reshape(-1)):
+        p.pattern[i] = int(v)
+    return p
+
+
+def current_stream() -> int:
+    import torch
+
+    return int(torch.cuda.current_stream().cuda_stream) if torch.cuda.is_available() else 0
+
+
+class Tracker:
+    """One camera stream: pyramids, reference IC cache and the per-frame track."""
+
+    def __init__(self, cam, params: Params, max_points: int, stream: int | None = None):
+        self._lib = load()
+        self.cam = cam if isinstance(cam, Camera) else make_camera(cam)
+        self.params = params
+        self.stream = current_stream() if stream is None else stream
+        h = _vp()
+        _check(self._lib.dpt_create(ctypes.byref(self.cam), ctypes.byref(params), max_points, self.stream,
+                                    ctypes.byref(h)))
+        self._h = h
+        self.n_points = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.dpt_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def build_pyramid(self, slot: int, img, pitch: int | None = None):
+        p, dev, keep = _ptr(img)
+        pitch = self.cam.width if pitch is None else pitch
+        _check(self._lib.dpt_build_pyramid(self._h, slot, p, pitch, dev))
+
+    def get_pyramid(self, slot: int, level: int) -> np.ndarray:
+        w, h = self.cam.width >> level, self.cam.height >> level
+        out = np.empty((h, w), np.uint8)
+        _check(self._lib.dpt_get_pyramid(self._h, slot, level, out.ctypes.data))
+        return out
+
+    def select_points(self, n: int, margin: int = 8) -> np.ndarray:
+        out = np.empty(n, np.int32)
+        cnt = _i32()
+        _check(self._lib.dpt_select_points(self._h, n, margin, out.ctypes.data, ctypes.byref(cnt)))
+        return out[:cnt.value].copy()
+
+    def set_reference_points(self, xyz, T_rw):
+        if isinstance(xyz, np.ndarray):
+            xyz = np.ascontiguousarray(xyz, dtype=np.float32).reshape(-1, 3)
+        p, dev, keep = _ptr(xyz)
+        n = int(xyz.shape[0])
+        _check(self._lib.dpt_set_reference_points(self._h, p, n, _mat(T_rw), dev))
+        self.n_points = n
+
+    def track(self, T_cw_init) -> dict:
+        r = Result()
+        _check(self._lib.dpt_track_frame(self._h, _mat(T_cw_init), ctypes.byref(r)))
+        return r.as_dict()
+
+    def reference_cache(self, level: int) -> dict:
+        n, K = self.n_points, self.params.n_pattern
+        valid = np.empty(max(n, 1), np.uint8)
+        I0, gx, gy = (np.empty(max(n * K, 1), np.float32) for _ in range(3))
+        x0 = np.empty(max(n * 3, 1), np.float32)
+        _check(self._lib.dpt_get_reference_cache(self._h, level, valid.ctypes.data, I0.ctypes.data, gx.ctypes.data,
+                                                 gy.ctypes.data, x0.ctypes.data))
+        return dict(valid=valid[:n].astype(bool), I0=I0[:n * K].reshape(n, K), gx=gx[:n * K].reshape(n, K),
+                    gy=gy[:n * K].reshape(n, K), x0=x0[:n * 3].reshape(n, 3))
+
+    def normal_equations(self, level: int, T_rel) -> dict:
+        H21, b6 = np.empty(21, np.float32), np.empty(6, np.float32)
+        E, n, npts = ctypes.c_double(), _i64(), _i32()
+        _check(self._lib.dpt_normal_equations(self._h, level, _mat(T_rel), H21.ctypes.data, b6.ctypes.data,
+                                              ctypes.byref(E), ctypes.byref(n), ctypes.byref(npts)))
+        H = np.zeros((6, 6))
+        q = 0
+        for i in range(6):
+            for j in range(i, 6):
+                H[i, j] = H[j, i] = H21[q]
+                q += 1
+        return dict(H=H, b=b6.astype(np.float64), E=E.value, n=n.value, npts=npts.value)
