@@ -146,6 +146,61 @@ int dpt_get_reference_cache(dpt_ctx* ctx, int32_t level, uint8_t* valid, float* 
 int dpt_normal_equations(dpt_ctx* ctx, int32_t level, const double T_rel[16], float* H21, float* b6, double* E,
                          int64_t* n, int32_t* npts);
 
+/* Launch configuration of the track kernel.
+ *   DPT_LAUNCH_AUTO       cooperative chunks when the GPU supports co-resident
+ *                         launches and the map fits, else one workgroup per frame
+ *   DPT_LAUNCH_WORKGROUP  one 512-thread workgroup runs the whole frame
+ *   DPT_LAUNCH_COOP       the map is split into chunks of `chunk` points (64, 128
+ *                         or 256), one workgroup each, synchronised per iteration
+ * Results agree with each other to rounding (the summation order differs). */
+enum { DPT_LAUNCH_AUTO = 0, DPT_LAUNCH_WORKGROUP = 1, DPT_LAUNCH_COOP = 2 };
+int dpt_set_launch_config(dpt_ctx* ctx, int32_t mode, int32_t chunk);
+
+/* Profiling hook: when enabled, dpt_build_pyramid and dpt_track_frame bracket
+ * their kernels with HIP events on the context's stream, and
+ * dpt_last_kernel_ms returns the durations (ms) of the most recent pyramid and
+ * track kernels (-1 if none was timed).  Off by default; enabling it adds two
+ * event records per call. */
+int dpt_set_profiling(dpt_ctx* ctx, int32_t enable);
+int dpt_last_kernel_ms(dpt_ctx* ctx, float* pyramid_ms, float* track_ms);
+
+/* ------------------------------------------------------------------ batched streams
+ * Many independent camera streams tracked together: one pyramid launch for all
+ * streams' images and one cooperative track launch per group of streams that
+ * fits the GPU's co-resident capacity (every stream's map split into chunks,
+ * Sec. III-C's per-point work and tree reduction run per chunk), or one
+ * workgroup per stream.  Each stream keeps its own camera, pyramids and map;
+ * all share dpt_params and the HIP stream.  The per-stream results equal those of
+ * dpt_track_frame on a single-stream context to rounding. */
+typedef struct dpt_batch dpt_batch;
+
+/* n_streams in 1..4096; cams[s] and max_points[s] (1..65536) per stream. */
+int dpt_batch_create(int32_t n_streams, const dpt_camera* cams, const dpt_params* prm, const int32_t* max_points,
+                     void* hip_stream, dpt_batch** out);
+void dpt_batch_destroy(dpt_batch* b);
+
+/* Build one slot's pyramid for every stream.  imgs[s]: stream s's image (device
+ * memory if on_device, else host), row pitch pitches[s] >= its width. */
+int dpt_batch_build_pyramids(dpt_batch* b, int32_t slot, const uint8_t* const* imgs, const int64_t* pitches,
+                             int32_t on_device);
+
+/* As dpt_select_points / dpt_set_reference_points, for stream `s`. */
+int dpt_batch_select_points(dpt_batch* b, int32_t s, int32_t n, int32_t margin, int32_t* host_idx, int32_t* n_out);
+int dpt_batch_set_reference_points(dpt_batch* b, int32_t s, const float* xyz_world, int32_t n, const double T_rw[16],
+                                   int32_t xyz_on_device);
+
+/* Track every stream's CUR pyramid.  T_cw_init: n_streams row-major 4x4
+ * doubles; out: n_streams results.  Synchronises the stream. */
+int dpt_batch_track(dpt_batch* b, const double* T_cw_init, dpt_result* out);
+
+/* Launch configuration as dpt_set_launch_config, for the whole batch. */
+int dpt_batch_set_launch_config(dpt_batch* b, int32_t mode, int32_t chunk);
+
+/* Profiling: duration (ms) of the last batched track launch sequence and of the
+ * last batched pyramid launch, timed with HIP events on the batch's stream. */
+int dpt_batch_set_profiling(dpt_batch* b, int32_t enable);
+int dpt_batch_last_kernel_ms(dpt_batch* b, float* pyramid_ms, float* track_ms);
+
 #ifdef __cplusplus
 }
 #endif

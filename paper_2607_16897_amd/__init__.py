@@ -14,13 +14,14 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libdptrack.so")
+LIB_PATH = os.environ.get("DPT_LIBRARY") or os.path.join(_HERE, "libdptrack.so")
 _lib = None
 
 DPT_OK, DPT_E_ARG, DPT_E_HIP, DPT_E_STATE, DPT_E_OOM = 0, -1, -2, -3, -4
 TRACK_OK, TRACK_MAX_ITERS, TRACK_TOO_FEW_POINTS, TRACK_NOT_PD = 0, 1, 2, 3
 PREC_FP32, PREC_MIXED = 0, 1
 SLOT_REF, SLOT_CUR = 0, 1
+LAUNCH_AUTO, LAUNCH_WORKGROUP, LAUNCH_COOP = 0, 1, 2
 DEFAULT_PATTERN = ((-2, 0), (2, 0), (0, -2), (0, 2), (-1, -1), (1, -1), (-1, 1), (1, 1))
 
 
@@ -71,6 +72,18 @@ SIGNATURES = {
     "dpt_normal_equations": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ctypes.c_double), _vp, _vp,
                                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64),
                                             ctypes.POINTER(_i32)]),
+    "dpt_set_profiling": (ctypes.c_int, [_vp, _i32]),
+    "dpt_set_launch_config": (ctypes.c_int, [_vp, _i32, _i32]),
+    "dpt_batch_create": (ctypes.c_int, [_i32, _vp, ctypes.POINTER(Params), _vp, _vp, ctypes.POINTER(_vp)]),
+    "dpt_batch_destroy": (None, [_vp]),
+    "dpt_batch_build_pyramids": (ctypes.c_int, [_vp, _i32, _vp, _vp, _i32]),
+    "dpt_batch_select_points": (ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, ctypes.POINTER(_i32)]),
+    "dpt_batch_set_reference_points": (ctypes.c_int, [_vp, _i32, _vp, _i32, ctypes.POINTER(ctypes.c_double), _i32]),
+    "dpt_batch_track": (ctypes.c_int, [_vp, _vp, _vp]),
+    "dpt_batch_set_launch_config": (ctypes.c_int, [_vp, _i32, _i32]),
+    "dpt_batch_set_profiling": (ctypes.c_int, [_vp, _i32]),
+    "dpt_batch_last_kernel_ms": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
+    "dpt_last_kernel_ms": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
 }
 
 
@@ -186,6 +199,18 @@ class Tracker:
         _check(self._lib.dpt_track_frame(self._h, _mat(T_cw_init), ctypes.byref(r)))
         return r.as_dict()
 
+    def set_launch_config(self, mode: int, chunk: int = 256):
+        _check(self._lib.dpt_set_launch_config(self._h, mode, chunk))
+
+    def set_profiling(self, enable: bool = True):
+        _check(self._lib.dpt_set_profiling(self._h, int(enable)))
+
+    def last_kernel_ms(self):
+        """(pyramid_ms, track_ms) of the most recent timed kernels (-1 if none)."""
+        a, b = ctypes.c_float(), ctypes.c_float()
+        _check(self._lib.dpt_last_kernel_ms(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
     def reference_cache(self, level: int) -> dict:
         n, K = self.n_points, self.params.n_pattern
         valid = np.empty(max(n, 1), np.uint8)
@@ -208,3 +233,65 @@ class Tracker:
                 H[i, j] = H[j, i] = H21[q]
                 q += 1
         return dict(H=H, b=b6.astype(np.float64), E=E.value, n=n.value, npts=npts.value)
+
+
+class BatchTracker:
+    """Many independent camera streams tracked in one launch sequence."""
+
+    def __init__(self, cams, params: Params, max_points, stream: int | None = None):
+        self._lib = load()
+        self.n = len(cams)
+        self.cams = (Camera * self.n)(*[c if isinstance(c, Camera) else make_camera(c) for c in cams])
+        self.params = params
+        self.stream = current_stream() if stream is None else stream
+        mp = (_i32 * self.n)(*[int(m) for m in max_points])
+        h = _vp()
+        _check(self._lib.dpt_batch_create(self.n, ctypes.cast(self.cams, _vp), ctypes.byref(params),
+                                          ctypes.cast(mp, _vp), self.stream, ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.dpt_batch_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def build_pyramids(self, slot: int, imgs, pitches=None):
+        """imgs: list of NumPy arrays (host) or torch CUDA tensors (device), one per stream."""
+        ptrs, devs, keep = zip(*[_ptr(x) for x in imgs])
+        if len(set(devs)) != 1:
+            raise ValueError("all images must be on the same side (host or device)")
+        pitches = [self.cams[s].width for s in range(self.n)] if pitches is None else pitches
+        pa = (ctypes.c_void_p * self.n)(*ptrs)
+        pp = (_i64 * self.n)(*[int(p) for p in pitches])
+        _check(self._lib.dpt_batch_build_pyramids(self._h, slot, ctypes.cast(pa, _vp), ctypes.cast(pp, _vp), devs[0]))
+
+    def select_points(self, s: int, n: int, margin: int = 8) -> np.ndarray:
+        out = np.empty(n, np.int32)
+        cnt = _i32()
+        _check(self._lib.dpt_batch_select_points(self._h, s, n, margin, out.ctypes.data, ctypes.byref(cnt)))
+        return out[:cnt.value].copy()
+
+    def set_reference_points(self, s: int, xyz, T_rw):
+        if isinstance(xyz, np.ndarray):
+            xyz = np.ascontiguousarray(xyz, dtype=np.float32).reshape(-1, 3)
+        p, dev, keep = _ptr(xyz)
+        _check(self._lib.dpt_batch_set_reference_points(self._h, s, p, int(xyz.shape[0]), _mat(T_rw), dev))
+
+    def track(self, T_cw_init) -> list[dict]:
+        T = np.ascontiguousarray(np.asarray(T_cw_init, np.float64).reshape(self.n, 16))
+        res = (Result * self.n)()
+        _check(self._lib.dpt_batch_track(self._h, T.ctypes.data, ctypes.cast(res, _vp)))
+        return [r.as_dict() for r in res]
+
+    def set_launch_config(self, mode: int, chunk: int = 256):
+        _check(self._lib.dpt_batch_set_launch_config(self._h, mode, chunk))
+
+    def set_profiling(self, enable: bool = True):
+        _check(self._lib.dpt_batch_set_profiling(self._h, int(enable)))
+
+    def last_kernel_ms(self):
+        a, b = ctypes.c_float(), ctypes.c_float()
+        _check(self._lib.dpt_batch_last_kernel_ms(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value

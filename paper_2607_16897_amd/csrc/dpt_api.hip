@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <new>
 #include <string>
 
 #include "../../include/dptrack.h"
@@ -84,7 +85,8 @@ int check_params(const dpt_params* p, const dpt_camera* c) {
     if (p->pattern[k] < -16 || p->pattern[k] > 16) return fail(DPT_E_ARG, "pattern offset %d outside [-16, 16]", p->pattern[k]);
   if (!std::isfinite(p->huber_k) || !(p->step_eps >= 0) || !(p->z_min >= 0)) return fail(DPT_E_ARG, "invalid thresholds");
   if (p->min_points < 0) return fail(DPT_E_ARG, "min_points < 0");
-  if (p->precision != DPT_PREC_FP32) return fail(DPT_E_ARG, "precision %d not available in this entry point", p->precision);
+  if (p->precision != DPT_PREC_FP32 && p->precision != DPT_PREC_MIXED) return fail(DPT_E_ARG, "precision %d", p->precision);
+  if (p->precision == DPT_PREC_MIXED && p->n_pattern != 8) return fail(DPT_E_ARG, "mixed precision needs K = 8");
   if (p->flags != 0) return fail(DPT_E_ARG, "unknown flags 0x%x", p->flags);
   return DPT_OK;
 }
@@ -120,9 +122,11 @@ struct dpt_ctx {
   uint8_t* pyr[2] = {nullptr, nullptr};
   bool have_pyr[2] = {false, false};
   uint8_t* staging = nullptr;  // level-0 upload buffer for host images
-  float* x0 = nullptr;
+  float4* x0 = nullptr;
   uint8_t* valid = nullptr;
   float *I0 = nullptr, *gx = nullptr, *gy = nullptr;
+  __half* I0h = nullptr;  // mixed precision cache
+  __half2* gh = nullptr;
   float* pts = nullptr;  // device copy of the world points
   int32_t n_points = 0;
   bool have_ref = false;
@@ -134,10 +138,19 @@ struct dpt_ctx {
   float* d_tot = nullptr;
   float* h_tot = nullptr;  // pinned
   Pattern pat;
+  bool prof = false;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // pyramid start/end, track start/end
+  bool ev_pyr = false, ev_trk = false;
+  int32_t launch_mode = DPT_LAUNCH_AUTO, chunk = 256;
+  CoopEngine eng;
+  bool eng_ready = false;
 
   ~dpt_ctx() {
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
     for (void* p : {(void*)pyr[0], (void*)pyr[1], (void*)staging, (void*)x0, (void*)valid, (void*)I0, (void*)gx,
-                    (void*)gy, (void*)pts, (void*)sel_idx, (void*)sel_count, (void*)d_out, (void*)d_tot})
+                    (void*)gy, (void*)I0h, (void*)gh, (void*)pts, (void*)sel_idx, (void*)sel_count, (void*)d_out,
+                    (void*)d_tot})
       if (p) (void)hipFree(p);
     if (h_out) (void)hipHostFree(h_out);
     if (h_tot) (void)hipHostFree(h_tot);
@@ -171,6 +184,8 @@ void fill_track_args(const dpt_ctx* c, TrackArgs& a) {
   a.ref.I0 = c->I0;
   a.ref.gx = c->gx;
   a.ref.gy = c->gy;
+  a.ref.I0h = c->I0h;
+  a.ref.gh = c->gh;
   a.ref.n = c->n_points;
   a.ref.cap = c->cap;
   a.out = c->d_out;
@@ -182,6 +197,13 @@ void rel_pose_f32(const dpt_ctx* c, const double* T_cw, float* out12) {
   invert(c->T_rw, Tinv);
   compose(T_cw, Tinv, Trel);
   for (int j = 0; j < 12; ++j) out12[j] = (float)Trel[j];
+}
+
+void rel_pose_f32(const dpt_ctx* c, const double* T_cw, double* out12) {
+  double Tinv[16], Trel[16];
+  invert(c->T_rw, Tinv);
+  compose(T_cw, Tinv, Trel);
+  for (int j = 0; j < 12; ++j) out12[j] = Trel[j];
 }
 
 }  // namespace
@@ -228,7 +250,7 @@ int dpt_create(const dpt_camera* cam, const dpt_params* prm, int32_t max_points,
   const size_t K = (size_t)prm->n_pattern, L = (size_t)prm->levels, cap = (size_t)max_points;
   if ((e = dev_alloc((void**)&c->pyr[0], (size_t)off)) || (e = dev_alloc((void**)&c->pyr[1], (size_t)off)) ||
       (e = dev_alloc((void**)&c->staging, (size_t)cam->width * cam->height)) ||
-      (e = dev_alloc((void**)&c->x0, cap * 3 * sizeof(float))) || (e = dev_alloc((void**)&c->valid, L * cap)) ||
+      (e = dev_alloc((void**)&c->x0, cap * sizeof(float4))) || (e = dev_alloc((void**)&c->valid, L * cap)) ||
       (e = dev_alloc((void**)&c->I0, L * cap * K * sizeof(float))) ||
       (e = dev_alloc((void**)&c->gx, L * cap * K * sizeof(float))) ||
       (e = dev_alloc((void**)&c->gy, L * cap * K * sizeof(float))) ||
@@ -236,6 +258,12 @@ int dpt_create(const dpt_camera* cam, const dpt_params* prm, int32_t max_points,
       (e = dev_alloc((void**)&c->sel_idx, (size_t)cam->width * cam->height * sizeof(int32_t))) ||
       (e = dev_alloc((void**)&c->sel_count, sizeof(int32_t))) || (e = dev_alloc((void**)&c->d_out, sizeof(TrackOut))) ||
       (e = dev_alloc((void**)&c->d_tot, kRedSlots * sizeof(float)))) {
+    delete c;
+    return e;
+  }
+  if (prm->precision == DPT_PREC_MIXED &&
+      ((e = dev_alloc((void**)&c->I0h, L * cap * K * sizeof(__half))) ||
+       (e = dev_alloc((void**)&c->gh, L * cap * K * sizeof(__half2))))) {
     delete c;
     return e;
   }
@@ -268,7 +296,12 @@ int dpt_build_pyramid(dpt_ctx* c, int32_t slot, const uint8_t* img, int64_t pitc
     src = c->staging;
     sp = c->cam.width;
   }
+  if (c->prof) HIP_TRY(hipEventRecord(c->ev[0], c->stream));
   HIP_TRY(launch_pyramid(src, sp, c->pyr[slot], c->pg, c->stream));
+  if (c->prof) {
+    HIP_TRY(hipEventRecord(c->ev[1], c->stream));
+    c->ev_pyr = true;
+  }
   c->have_pyr[slot] = true;
   if (slot == DPT_SLOT_REF) c->have_ref = false;
   if (!img_on_device) HIP_TRY(hipStreamSynchronize(c->stream));  // the host buffer is only borrowed
@@ -332,6 +365,8 @@ int dpt_set_reference_points(dpt_ctx* c, const float* xyz, int32_t n, const doub
   a.I0 = c->I0;
   a.gx = c->gx;
   a.gy = c->gy;
+  a.I0h = c->I0h;
+  a.gh = c->gh;
   a.n = n;
   a.cap = c->cap;
   HIP_TRY(launch_precompute(a, c->stream));
@@ -342,21 +377,63 @@ int dpt_set_reference_points(dpt_ctx* c, const float* xyz, int32_t n, const doub
   return DPT_OK;
 }
 
-int dpt_track_frame(dpt_ctx* c, const double T_cw_init[16], dpt_result* out) {
-  g_err.clear();
-  if (!c || !T_cw_init || !out) return fail(DPT_E_ARG, "NULL argument");
-  if (!finite16(T_cw_init)) return fail(DPT_E_ARG, "T_cw_init not finite");
-  if (!c->have_ref) return fail(DPT_E_STATE, "no reference points");
-  if (!c->have_pyr[DPT_SLOT_CUR]) return fail(DPT_E_STATE, "no current pyramid");
+}  // extern "C"
+
+namespace {
+
+// Whether this frame runs on the cooperative chunked kernel.
+bool use_coop(dpt_ctx* c) {
+  if (c->prm.precision == DPT_PREC_MIXED) return true;  // only the cooperative kernel has the mixed variant
+  if (c->launch_mode == DPT_LAUNCH_WORKGROUP || c->prm.n_pattern != 8) return false;
+  const int nch = c->n_points > 0 ? (c->n_points + c->chunk - 1) / c->chunk : 1;
+  return nch <= coop_max_blocks(c->chunk) / 8;  // the XCD-packed grid may hold up to 8x padding
+}
+
+int run_track(dpt_ctx* c, const double T_cw_init[16], const TrackOut** res) {
   TrackArgs a;
   fill_track_args(c, a);
+  if (use_coop(c)) {
+    const int nch = c->n_points > 0 ? (c->n_points + c->chunk - 1) / c->chunk : 1;
+    if (8 * nch > coop_max_blocks(c->chunk))
+      return fail(DPT_E_ARG, "%d points exceed the cooperative capacity at chunk %d", c->n_points, c->chunk);
+    if (!c->eng_ready) {
+      HIP_TRY(c->eng.init(1, &c->cap, c->chunk, true, c->stream));
+      c->eng.mixed = c->prm.precision == DPT_PREC_MIXED;
+      c->eng_ready = true;
+    }
+    if (c->eng.dirty || c->eng.h_streams[0].a.ref.n != c->n_points) c->eng.set_stream(0, a);
+    rel_pose_f32(c, T_cw_init, c->eng.h_T);
+    if (c->prof) HIP_TRY(hipEventRecord(c->ev[2], c->stream));
+    HIP_TRY(c->eng.launch(kSpinLimit));
+    if (c->prof) {
+      HIP_TRY(hipEventRecord(c->ev[3], c->stream));
+      c->ev_trk = true;
+    }
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (c->eng.h_out[0].status == 4) {
+      (void)c->eng.reset_sync();
+      (void)hipStreamSynchronize(c->stream);
+      return fail(DPT_E_HIP, "cooperative track: chunk synchronisation timed out");
+    }
+    *res = &c->eng.h_out[0];
+    return DPT_OK;
+  }
   rel_pose_f32(c, T_cw_init, a.T_init);
+  if (c->prof) HIP_TRY(hipEventRecord(c->ev[2], c->stream));
   HIP_TRY(launch_track(a, c->stream));
+  if (c->prof) {
+    HIP_TRY(hipEventRecord(c->ev[3], c->stream));
+    c->ev_trk = true;
+  }
   HIP_TRY(hipMemcpyAsync(c->h_out, c->d_out, sizeof(TrackOut), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
-  const TrackOut& o = *c->h_out;
+  *res = c->h_out;
+  return DPT_OK;
+}
+
+void fill_result(const dpt_ctx* c, const TrackOut& o, dpt_result* out) {
   double Trel[16];
-  for (int j = 0; j < 12; ++j) Trel[j] = (double)o.T[j];
+  for (int j = 0; j < 12; ++j) Trel[j] = c->prm.precision == DPT_PREC_MIXED ? o.Td[j] : (double)o.T[j];
   Trel[12] = Trel[13] = Trel[14] = 0.0;
   Trel[15] = 1.0;
   std::memset(out, 0, sizeof *out);
@@ -367,6 +444,40 @@ int dpt_track_frame(dpt_ctx* c, const double T_cw_init[16], dpt_result* out) {
   out->n_valid_points = o.n_valid_points;
   out->status = o.status;
   out->samples = o.samples;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dpt_track_frame(dpt_ctx* c, const double T_cw_init[16], dpt_result* out) {
+  g_err.clear();
+  if (!c || !T_cw_init || !out) return fail(DPT_E_ARG, "NULL argument");
+  if (!finite16(T_cw_init)) return fail(DPT_E_ARG, "T_cw_init not finite");
+  if (!c->have_ref) return fail(DPT_E_STATE, "no reference points");
+  if (!c->have_pyr[DPT_SLOT_CUR]) return fail(DPT_E_STATE, "no current pyramid");
+  const TrackOut* o = nullptr;
+  int e = run_track(c, T_cw_init, &o);
+  if (e != DPT_OK) return e;
+  fill_result(c, *o, out);
+  return DPT_OK;
+}
+
+int dpt_set_launch_config(dpt_ctx* c, int32_t mode, int32_t chunk) {
+  g_err.clear();
+  if (!c) return fail(DPT_E_ARG, "NULL context");
+  if (mode < DPT_LAUNCH_AUTO || mode > DPT_LAUNCH_COOP) return fail(DPT_E_ARG, "mode %d", mode);
+  if (chunk != 64 && chunk != 128 && chunk != 256) return fail(DPT_E_ARG, "chunk %d not in {64, 128, 256}", chunk);
+  if (mode == DPT_LAUNCH_COOP && c->prm.n_pattern != 8) return fail(DPT_E_ARG, "cooperative track needs K = 8");
+  if (mode == DPT_LAUNCH_WORKGROUP && c->prm.precision == DPT_PREC_MIXED)
+    return fail(DPT_E_ARG, "mixed precision runs on the cooperative launch only");
+  if (chunk != c->chunk && c->eng_ready) {
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->eng.release();
+    c->eng_ready = false;
+  }
+  c->launch_mode = mode;
+  c->chunk = chunk;
   return DPT_OK;
 }
 
@@ -382,7 +493,7 @@ int dpt_get_reference_cache(dpt_ctx* c, int32_t level, uint8_t* valid, float* I0
     if (I0) HIP_TRY(hipMemcpyAsync(I0, c->I0 + lo * K, n * K * 4, hipMemcpyDeviceToHost, c->stream));
     if (gx) HIP_TRY(hipMemcpyAsync(gx, c->gx + lo * K, n * K * 4, hipMemcpyDeviceToHost, c->stream));
     if (gy) HIP_TRY(hipMemcpyAsync(gy, c->gy + lo * K, n * K * 4, hipMemcpyDeviceToHost, c->stream));
-    if (x0) HIP_TRY(hipMemcpyAsync(x0, c->x0, n * 3 * 4, hipMemcpyDeviceToHost, c->stream));
+    if (x0) HIP_TRY(hipMemcpy2DAsync(x0, 12, c->x0, sizeof(float4), 12, n, hipMemcpyDeviceToHost, c->stream));
   }
   HIP_TRY(hipStreamSynchronize(c->stream));
   return DPT_OK;
@@ -408,6 +519,331 @@ int dpt_normal_equations(dpt_ctx* c, int32_t level, const double T_rel[16], floa
   *E = c->h_tot[kSlotE];
   *n = (int64_t)c->h_tot[kSlotN];
   *npts = (int32_t)c->h_tot[kSlotPts];
+  return DPT_OK;
+}
+
+int dpt_set_profiling(dpt_ctx* c, int32_t enable) {
+  g_err.clear();
+  if (!c) return fail(DPT_E_ARG, "NULL context");
+  if (enable && !c->ev[0])
+    for (hipEvent_t& e : c->ev) HIP_TRY(hipEventCreate(&e));
+  c->prof = enable != 0;
+  c->ev_pyr = c->ev_trk = false;
+  return DPT_OK;
+}
+
+int dpt_last_kernel_ms(dpt_ctx* c, float* pyramid_ms, float* track_ms) {
+  g_err.clear();
+  if (!c || !pyramid_ms || !track_ms) return fail(DPT_E_ARG, "NULL argument");
+  *pyramid_ms = *track_ms = -1.0f;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (c->ev_pyr) HIP_TRY(hipEventElapsedTime(pyramid_ms, c->ev[0], c->ev[1]));
+  if (c->ev_trk) HIP_TRY(hipEventElapsedTime(track_ms, c->ev[2], c->ev[3]));
+  return DPT_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batched streams
+
+struct dpt_batch {
+  int32_t n = 0;
+  hipStream_t stream = nullptr;
+  std::vector<dpt_ctx*> ctx;
+  int32_t launch_mode = DPT_LAUNCH_AUTO, chunk = 256;
+  // cooperative groups of streams (each fits one co-resident launch)
+  std::vector<CoopEngine*> groups;
+  std::vector<std::vector<int>> group_streams;
+  bool groups_dirty = true;
+  // pyramid jobs
+  PyrJob* d_jobs = nullptr;
+  PyrJob* h_jobs = nullptr;  // pinned
+  // one-workgroup-per-stream launch
+  TrackArgs* d_args = nullptr;
+  TrackArgs* h_args = nullptr;  // pinned
+  TrackOut* d_outs = nullptr;
+  TrackOut* h_outs = nullptr;  // pinned
+  bool prof = false, ev_pyr = false, ev_trk = false;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+
+  void clear_groups() {
+    for (CoopEngine* g : groups) delete g;
+    groups.clear();
+    group_streams.clear();
+    groups_dirty = true;
+  }
+  ~dpt_batch() {
+    (void)hipStreamSynchronize(stream);
+    clear_groups();
+    for (dpt_ctx* c : ctx) delete c;
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (d_jobs) (void)hipFree(d_jobs);
+    if (d_args) (void)hipFree(d_args);
+    if (d_outs) (void)hipFree(d_outs);
+    if (h_jobs) (void)hipHostFree(h_jobs);
+    if (h_args) (void)hipHostFree(h_args);
+    if (h_outs) (void)hipHostFree(h_outs);
+  }
+};
+
+namespace {
+
+int batch_chunks(const dpt_batch* b, int s) {
+  const int n = b->ctx[s]->n_points;
+  return n > 0 ? (n + b->chunk - 1) / b->chunk : 1;
+}
+
+// Partition streams into groups that each fit one cooperative launch: a group's
+// XCD-packed grid is at most its chunk total plus 8 slots per largest stream.
+int build_groups(dpt_batch* b) {
+  b->clear_groups();
+  const int cap = coop_max_blocks(b->chunk);
+  std::vector<int> order(b->n);
+  for (int s = 0; s < b->n; ++s) order[s] = s;
+  std::sort(order.begin(), order.end(), [&](int p, int q) { return batch_chunks(b, p) > batch_chunks(b, q); });
+  std::vector<int> cur;
+  int total = 0, largest = 0;
+  auto flush = [&]() -> int {
+    if (cur.empty()) return DPT_OK;
+    std::sort(cur.begin(), cur.end());
+    CoopEngine* g = new (std::nothrow) CoopEngine();
+    if (!g) return fail(DPT_E_OOM, "host allocation failed");
+    std::vector<int> maxp(cur.size());
+    for (size_t k = 0; k < cur.size(); ++k) maxp[k] = b->ctx[cur[k]]->cap;
+    hipError_t e = g->init((int)cur.size(), maxp.data(), b->chunk, true, b->stream);
+    if (e != hipSuccess) {
+      delete g;
+      return fail(DPT_E_HIP, "cooperative group init: %s", hipGetErrorString(e));
+    }
+    g->mixed = b->ctx[0]->prm.precision == DPT_PREC_MIXED;
+    for (size_t k = 0; k < cur.size(); ++k) {
+      TrackArgs a;
+      fill_track_args(b->ctx[cur[k]], a);
+      g->set_stream((int)k, a);
+    }
+    b->groups.push_back(g);
+    b->group_streams.push_back(cur);
+    cur.clear();
+    total = largest = 0;
+    return DPT_OK;
+  };
+  for (int s : order) {
+    const int c = batch_chunks(b, s);
+    if (c + 8 * c > cap) return fail(DPT_E_ARG, "stream %d: %d chunks exceed the co-resident capacity %d", s, c, cap);
+    if (!cur.empty() && total + c + 8 * std::max(largest, c) > cap) {
+      int e = flush();
+      if (e != DPT_OK) return e;
+    }
+    cur.push_back(s);
+    total += c;
+    largest = std::max(largest, c);
+  }
+  int e = flush();
+  if (e != DPT_OK) return e;
+  b->groups_dirty = false;
+  return DPT_OK;
+}
+
+bool batch_use_coop(const dpt_batch* b) {
+  if (b->ctx[0]->prm.precision == DPT_PREC_MIXED) return true;
+  return b->launch_mode != DPT_LAUNCH_WORKGROUP && b->ctx[0]->prm.n_pattern == 8 && coop_max_blocks(b->chunk) > 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dpt_batch_create(int32_t n_streams, const dpt_camera* cams, const dpt_params* prm, const int32_t* max_points,
+                     void* hip_stream, dpt_batch** out) {
+  g_err.clear();
+  if (!out || !cams || !prm || !max_points) return fail(DPT_E_ARG, "NULL argument");
+  *out = nullptr;
+  if (n_streams < 1 || n_streams > 4096) return fail(DPT_E_ARG, "n_streams %d outside [1, 4096]", n_streams);
+  dpt_batch* b = new (std::nothrow) dpt_batch();
+  if (!b) return fail(DPT_E_OOM, "host allocation failed");
+  b->n = n_streams;
+  b->stream = (hipStream_t)hip_stream;
+  for (int s = 0; s < n_streams; ++s) {
+    dpt_ctx* c = nullptr;
+    int e = dpt_create(&cams[s], prm, max_points[s], hip_stream, &c);
+    if (e != DPT_OK) {
+      delete b;
+      return e;
+    }
+    b->ctx.push_back(c);
+  }
+  if (hipMalloc(&b->d_jobs, sizeof(PyrJob) * n_streams) != hipSuccess ||
+      hipMalloc(&b->d_args, sizeof(TrackArgs) * n_streams) != hipSuccess ||
+      hipMalloc(&b->d_outs, sizeof(TrackOut) * n_streams) != hipSuccess ||
+      hipHostMalloc(&b->h_jobs, sizeof(PyrJob) * n_streams) != hipSuccess ||
+      hipHostMalloc(&b->h_args, sizeof(TrackArgs) * n_streams) != hipSuccess ||
+      hipHostMalloc(&b->h_outs, sizeof(TrackOut) * n_streams) != hipSuccess) {
+    (void)hipGetLastError();
+    delete b;
+    return fail(DPT_E_OOM, "batch allocation failed");
+  }
+  *out = b;
+  return DPT_OK;
+}
+
+void dpt_batch_destroy(dpt_batch* b) { delete b; }
+
+int dpt_batch_build_pyramids(dpt_batch* b, int32_t slot, const uint8_t* const* imgs, const int64_t* pitches,
+                             int32_t on_device) {
+  g_err.clear();
+  if (!b || !imgs || !pitches) return fail(DPT_E_ARG, "NULL argument");
+  if (slot != DPT_SLOT_REF && slot != DPT_SLOT_CUR) return fail(DPT_E_ARG, "slot %d", slot);
+  int max_w = 0, max_h = 0;
+  for (int s = 0; s < b->n; ++s) {
+    dpt_ctx* c = b->ctx[s];
+    if (!imgs[s]) return fail(DPT_E_ARG, "image %d is NULL", s);
+    if (pitches[s] < c->cam.width) return fail(DPT_E_ARG, "stream %d: pitch < width", s);
+    const uint8_t* src = imgs[s];
+    int64_t sp = pitches[s];
+    if (!on_device) {
+      HIP_TRY(hipMemcpy2DAsync(c->staging, c->cam.width, imgs[s], pitches[s], c->cam.width, c->cam.height,
+                               hipMemcpyHostToDevice, b->stream));
+      src = c->staging;
+      sp = c->cam.width;
+    }
+    PyrJob& j = b->h_jobs[s];
+    j.src = src;
+    j.pitch = sp;
+    j.dst = c->pyr[slot];
+    j.g = c->pg;
+    j.vec4 = ((sp % 4) == 0 && (reinterpret_cast<uintptr_t>(src) % 4) == 0 && (c->pg.W[0] % 4) == 0) ? 1 : 0;
+    j.pad = 0;
+    max_w = std::max(max_w, c->cam.width);
+    max_h = std::max(max_h, c->cam.height);
+  }
+  HIP_TRY(hipMemcpyAsync(b->d_jobs, b->h_jobs, sizeof(PyrJob) * b->n, hipMemcpyHostToDevice, b->stream));
+  if (b->prof) HIP_TRY(hipEventRecord(b->ev[0], b->stream));
+  HIP_TRY(launch_pyramid_batch(b->d_jobs, b->n, max_w, max_h, b->ctx[0]->prm.levels, b->stream));
+  if (b->prof) {
+    HIP_TRY(hipEventRecord(b->ev[1], b->stream));
+    b->ev_pyr = true;
+  }
+  // the pinned job table is reused by the next call: wait until the copy has been consumed
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  for (int s = 0; s < b->n; ++s) {
+    b->ctx[s]->have_pyr[slot] = true;
+    if (slot == DPT_SLOT_REF) b->ctx[s]->have_ref = false;
+  }
+  return DPT_OK;
+}
+
+int dpt_batch_select_points(dpt_batch* b, int32_t s, int32_t n, int32_t margin, int32_t* host_idx, int32_t* n_out) {
+  g_err.clear();
+  if (!b || s < 0 || s >= b->n) return fail(DPT_E_ARG, "stream index");
+  return dpt_select_points(b->ctx[s], n, margin, host_idx, n_out);
+}
+
+int dpt_batch_set_reference_points(dpt_batch* b, int32_t s, const float* xyz, int32_t n, const double T_rw[16],
+                                   int32_t on_device) {
+  g_err.clear();
+  if (!b || s < 0 || s >= b->n) return fail(DPT_E_ARG, "stream index");
+  const int before = b->ctx[s]->n_points;
+  int e = dpt_set_reference_points(b->ctx[s], xyz, n, T_rw, on_device);
+  if (e == DPT_OK && before != n) b->groups_dirty = true;
+  return e;
+}
+
+int dpt_batch_track(dpt_batch* b, const double* T_cw_init, dpt_result* out) {
+  g_err.clear();
+  if (!b || !T_cw_init || !out) return fail(DPT_E_ARG, "NULL argument");
+  for (int s = 0; s < b->n; ++s) {
+    if (!finite16(T_cw_init + 16 * s)) return fail(DPT_E_ARG, "T_cw_init %d not finite", s);
+    if (!b->ctx[s]->have_ref) return fail(DPT_E_STATE, "stream %d has no reference points", s);
+    if (!b->ctx[s]->have_pyr[DPT_SLOT_CUR]) return fail(DPT_E_STATE, "stream %d has no current pyramid", s);
+  }
+  if (batch_use_coop(b)) {
+    if (b->groups_dirty) {
+      int e = build_groups(b);
+      if (e != DPT_OK) return e;
+    }
+    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+      const std::vector<int>& ss = b->group_streams[gi];
+      for (size_t k = 0; k < ss.size(); ++k) rel_pose_f32(b->ctx[ss[k]], T_cw_init + 16 * ss[k], b->groups[gi]->h_T + 12 * k);
+    }
+    if (b->prof) HIP_TRY(hipEventRecord(b->ev[2], b->stream));
+    for (CoopEngine* g : b->groups) HIP_TRY(g->launch(kSpinLimit));
+    if (b->prof) {
+      HIP_TRY(hipEventRecord(b->ev[3], b->stream));
+      b->ev_trk = true;
+    }
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    bool timeout = false;
+    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+      const std::vector<int>& ss = b->group_streams[gi];
+      for (size_t k = 0; k < ss.size(); ++k) {
+        const TrackOut& o = b->groups[gi]->h_out[k];
+        if (o.status == 4) timeout = true;
+        fill_result(b->ctx[ss[k]], o, &out[ss[k]]);
+      }
+    }
+    if (timeout) {
+      for (CoopEngine* g : b->groups) (void)g->reset_sync();
+      (void)hipStreamSynchronize(b->stream);
+      return fail(DPT_E_HIP, "cooperative batch track: chunk synchronisation timed out");
+    }
+    return DPT_OK;
+  }
+  int lds = 0, max_points = 0;
+  for (int s = 0; s < b->n; ++s) {
+    dpt_ctx* c = b->ctx[s];
+    TrackArgs& a = b->h_args[s];
+    fill_track_args(c, a);
+    rel_pose_f32(c, T_cw_init + 16 * s, a.T_init);
+    a.out = b->d_outs + s;
+    lds = std::max(lds, track_lds_bytes(c->lv, c->prm.levels));
+    max_points = std::max(max_points, c->n_points);
+  }
+  HIP_TRY(hipMemcpyAsync(b->d_args, b->h_args, sizeof(TrackArgs) * b->n, hipMemcpyHostToDevice, b->stream));
+  if (b->prof) HIP_TRY(hipEventRecord(b->ev[2], b->stream));
+  HIP_TRY(launch_track_batch(b->h_args[0], b->d_args, b->n, lds, max_points, b->stream));
+  if (b->prof) {
+    HIP_TRY(hipEventRecord(b->ev[3], b->stream));
+    b->ev_trk = true;
+  }
+  HIP_TRY(hipMemcpyAsync(b->h_outs, b->d_outs, sizeof(TrackOut) * b->n, hipMemcpyDeviceToHost, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  for (int s = 0; s < b->n; ++s) fill_result(b->ctx[s], b->h_outs[s], &out[s]);
+  return DPT_OK;
+}
+
+int dpt_batch_set_launch_config(dpt_batch* b, int32_t mode, int32_t chunk) {
+  g_err.clear();
+  if (!b) return fail(DPT_E_ARG, "NULL batch");
+  if (mode < DPT_LAUNCH_AUTO || mode > DPT_LAUNCH_COOP) return fail(DPT_E_ARG, "mode %d", mode);
+  if (chunk != 64 && chunk != 128 && chunk != 256) return fail(DPT_E_ARG, "chunk %d not in {64, 128, 256}", chunk);
+  if (mode == DPT_LAUNCH_COOP && b->ctx[0]->prm.n_pattern != 8) return fail(DPT_E_ARG, "cooperative track needs K = 8");
+  if (mode == DPT_LAUNCH_WORKGROUP && b->ctx[0]->prm.precision == DPT_PREC_MIXED)
+    return fail(DPT_E_ARG, "mixed precision runs on the cooperative launch only");
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  if (chunk != b->chunk) b->clear_groups();
+  b->launch_mode = mode;
+  b->chunk = chunk;
+  return DPT_OK;
+}
+
+int dpt_batch_set_profiling(dpt_batch* b, int32_t enable) {
+  g_err.clear();
+  if (!b) return fail(DPT_E_ARG, "NULL batch");
+  if (enable && !b->ev[0])
+    for (hipEvent_t& e : b->ev) HIP_TRY(hipEventCreate(&e));
+  b->prof = enable != 0;
+  b->ev_pyr = b->ev_trk = false;
+  return DPT_OK;
+}
+
+int dpt_batch_last_kernel_ms(dpt_batch* b, float* pyramid_ms, float* track_ms) {
+  g_err.clear();
+  if (!b || !pyramid_ms || !track_ms) return fail(DPT_E_ARG, "NULL argument");
+  *pyramid_ms = *track_ms = -1.0f;
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  if (b->ev_pyr) HIP_TRY(hipEventElapsedTime(pyramid_ms, b->ev[0], b->ev[1]));
+  if (b->ev_trk) HIP_TRY(hipEventElapsedTime(track_ms, b->ev[2], b->ev[3]));
   return DPT_OK;
 }
 

@@ -1,0 +1,515 @@
+// Device helpers shared by the tracker kernels: projection, sampling,
+// workgroup reductions and the 6x6 solve with the SE(3) update.
+#pragma once
+
+#include "dpt_internal.h"
+
+namespace dpt {
+
+// ---------------------------------------------------------------- helpers
+
+__device__ __forceinline__ void transform(const float* T, float X, float Y, float Z, float& x, float& y,
+                                          float& z) {
+  x = fmaf(T[0], X, fmaf(T[1], Y, fmaf(T[2], Z, T[3])));
+  y = fmaf(T[4], X, fmaf(T[5], Y, fmaf(T[6], Z, T[7])));
+  z = fmaf(T[8], X, fmaf(T[9], Y, fmaf(T[10], Z, T[11])));
+}
+
+// Eq.(1): pinhole projection at one pyramid level.
+__device__ __forceinline__ void project(const LevelGeom& g, float x, float y, float z, float& u, float& v) {
+  u = fmaf(g.fx, x / z, g.cx);
+  v = fmaf(g.fy, y / z, g.cy);
+}
+
+// A point is usable when it is in front of the camera and every pattern
+// position p satisfies 1 <= p.x < W-2 and 1 <= p.y < H-2 (the bilinear taps and
+// their central differences stay inside the level).
+__device__ __forceinline__ bool inside(const LevelGeom& g, const Pattern& p, float u, float v) {
+  return (u + (float)p.dx_min >= 1.0f) && (u + (float)p.dx_max < (float)(g.W - 2)) &&
+         (v + (float)p.dy_min >= 1.0f) && (v + (float)p.dy_max < (float)(g.H - 2));
+}
+
+// Bilinear intensity of a uint8 level, pixel centres at integer coordinates.
+__device__ __forceinline__ float bilinear(const uint8_t* img, int W, float x, float y) {
+  float fx = floorf(x), fy = floorf(y);
+  float a = x - fx, c = y - fy;
+  const uint8_t* p = img + (int)fy * W + (int)fx;
+  float p00 = p[0], p10 = p[1], p01 = p[W], p11 = p[W + 1];
+  float top = fmaf(a, p10 - p00, p00);
+  float bot = fmaf(a, p11 - p01, p01);
+  return fmaf(c, bot - top, top);
+}
+
+// Reference-side gradient: central differences / 2 at the four bilinear taps,
+// blended with the same bilinear weights.
+__device__ __forceinline__ void gradient(const uint8_t* img, int W, float x, float y, float& gx, float& gy) {
+  float fx = floorf(x), fy = floorf(y);
+  float a = x - fx, c = y - fy;
+  const uint8_t* p = img + (int)fy * W + (int)fx;
+  float gx00 = 0.5f * ((float)p[1] - (float)p[-1]);
+  float gx10 = 0.5f * ((float)p[2] - (float)p[0]);
+  float gx01 = 0.5f * ((float)p[W + 1] - (float)p[W - 1]);
+  float gx11 = 0.5f * ((float)p[W + 2] - (float)p[W]);
+  float gy00 = 0.5f * ((float)p[W] - (float)p[-W]);
+  float gy10 = 0.5f * ((float)p[W + 1] - (float)p[1 - W]);
+  float gy01 = 0.5f * ((float)p[2 * W] - (float)p[0]);
+  float gy11 = 0.5f * ((float)p[2 * W + 1] - (float)p[1]);
+  float tx = fmaf(a, gx10 - gx00, gx00), bx = fmaf(a, gx11 - gx01, gx01);
+  float ty = fmaf(a, gy10 - gy00, gy00), by = fmaf(a, gy11 - gy01, gy01);
+  gx = fmaf(c, bx - tx, tx);
+  gy = fmaf(c, by - ty, ty);
+}
+
+// ---------------------------------------------------------------- pyramid
+
+// One launch builds every level.  A workgroup owns a TILE x TILE block of
+// level 0 (TILE >= 2^(levels-1)), so each level's 2x2 parents stay inside the
+// tile; levels alternate between two LDS buffers.
+template <int TILE>
+__device__ __forceinline__ void pyramid_tile(const uint8_t* __restrict__ src, int64_t pitch,
+                                             uint8_t* __restrict__ dst, const PyrGeom& g, int vec4) {
+  __shared__ uint8_t buf0[TILE * TILE];
+  __shared__ uint8_t buf1[TILE * TILE / 4];
+  const int ox = blockIdx.x * TILE, oy = blockIdx.y * TILE;
+  const int W0 = g.W[0], H0 = g.H[0];
+  if (vec4) {
+    // 4-byte loads: width, pitch and base are multiples of 4
+    for (int q = threadIdx.x; q < TILE * TILE / 4; q += blockDim.x) {
+      int ly = q / (TILE / 4), lx = (q % (TILE / 4)) * 4;
+      int gx = ox + lx, gy = oy + ly;
+      uint32_t v = 0;
+      if (gy < H0 && gx < W0) {
+        v = *reinterpret_cast<const uint32_t*>(src + gy * pitch + gx);
+        *reinterpret_cast<uint32_t*>(dst + g.off[0] + (int64_t)gy * W0 + gx) = v;
+      }
+      *reinterpret_cast<uint32_t*>(buf0 + ly * TILE + lx) = v;
+    }
+  } else {
+    for (int q = threadIdx.x; q < TILE * TILE; q += blockDim.x) {
+      int ly = q / TILE, lx = q % TILE;
+      int gx = ox + lx, gy = oy + ly;
+      uint8_t v = 0;
+      if (gy < H0 && gx < W0) {
+        v = src[gy * pitch + gx];
+        dst[g.off[0] + (int64_t)gy * W0 + gx] = v;
+      }
+      buf0[q] = v;
+    }
+  }
+  __syncthreads();
+  uint8_t* prev = buf0;
+  uint8_t* next = buf1;
+  for (int l = 1; l < g.levels; ++l) {
+    const int T = TILE >> l, Tp = TILE >> (l - 1);
+    const int Wl = g.W[l], Hl = g.H[l];
+    const int oxl = ox >> l, oyl = oy >> l;
+    for (int q = threadIdx.x; q < T * T; q += blockDim.x) {
+      int ly = q / T, lx = q % T;
+      int gx = oxl + lx, gy = oyl + ly;
+      uint8_t v = 0;
+      if (gx < Wl && gy < Hl) {
+        const uint8_t* p = prev + (2 * ly) * Tp + 2 * lx;
+        int s = (int)p[0] + (int)p[1] + (int)p[Tp] + (int)p[Tp + 1];
+        v = (uint8_t)((s + 2) >> 2);
+        dst[g.off[l] + (int64_t)gy * Wl + gx] = v;
+      }
+      next[q] = v;
+    }
+    __syncthreads();
+    uint8_t* t = prev;
+    prev = next;
+    next = t;
+  }
+}
+
+// ---------------------------------------------------------------- block scans / reductions
+
+// Exclusive prefix sum of one int per thread over a 1024-thread workgroup.
+// `wsum` is 16 ints of LDS.  Returns the prefix; *total gets the block sum.
+__device__ __forceinline__ int block_exclusive_scan(int x, int* wsum, int* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  int inc = x;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    int y = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += y;
+  }
+  if (lane == 63) wsum[wave] = inc;
+  __syncthreads();
+  int base = 0, tot = 0;
+  for (int w = 0; w < nw; ++w) {
+    int v = wsum[w];
+    base += (w < wave) ? v : 0;
+    tot += v;
+  }
+  __syncthreads();
+  *total = tot;
+  return base + inc - x;
+}
+
+// Sum 32 per-lane values over a wave64 by recursive halving: at each xor step
+// a lane keeps half of its values and receives the partner's matching half, so
+// 16 + 8 + 4 + 2 + 1 + 1 shuffles replace 32 x 6.  Lane l ends up holding the
+// wave total of value (l >> 1).  The order of additions is fixed.
+__device__ __forceinline__ float wave_reduce32(float (&a)[32]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int step = 0; step < 5; ++step) {
+    const int half = 16 >> step;        // values kept after this step
+    const int mask = 32 >> step;        // partner lane distance
+    const bool upper = (lane & mask) != 0;
+#pragma unroll
+    for (int j = 0; j < half; ++j) {
+      float keep = upper ? a[j + half] : a[j];
+      float send = upper ? a[j] : a[j + half];
+      float recv = __shfl_xor(send, mask, 64);
+      a[j] = keep + recv;
+    }
+  }
+  float v = a[0];
+  v += __shfl_xor(v, 1, 64);
+  return v;
+}
+
+// Workgroup total of 32 per-lane values into out[32] (LDS), fixed order.
+// `scratch` is 16 x 32 floats of LDS.
+__device__ __forceinline__ void block_reduce32(float (&a)[32], float* scratch, float* out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  float v = wave_reduce32(a);
+  if ((lane & 1) == 0) scratch[wave * 32 + (lane >> 1)] = v;
+  __syncthreads();
+  if (threadIdx.x < 32) {
+    float s = 0.0f;
+    for (int w = 0; w < nw; ++w) s += scratch[w * 32 + threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+// As block_reduce32, with Kahan-compensated summation across the waves.
+__device__ __forceinline__ void block_reduce32_kahan(float (&a)[32], float* scratch, float* out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  float v = wave_reduce32(a);
+  if ((lane & 1) == 0) scratch[wave * 32 + (lane >> 1)] = v;
+  __syncthreads();
+  if (threadIdx.x < 32) {
+    float s = 0.0f, c = 0.0f;
+    for (int w = 0; w < nw; ++w) {
+      const float y = scratch[w * 32 + threadIdx.x] - c;
+      const float t = s + y;
+      c = (t - s) - y;
+      s = t;
+    }
+    out[threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+// Index of H(i, j), i <= j, in the row-major upper-triangle order of the sums.
+__host__ __device__ constexpr int tri(int i, int j) { return i * 6 - (i * (i - 1)) / 2 + (j - i); }
+
+// Solve H delta = b (6x6 SPD from the 21 upper-triangle sums) by Cholesky in
+// FP32 and apply T <- T exp(-delta).  Returns 0, or 1 if a pivot is <= 1e-6 of
+// the largest diagonal entry (not positive definite).  Every loop is unrolled
+// so the factor lives in registers.
+__device__ __forceinline__ int solve_update(const float* tot, float* T, float* max_step) {
+  float L[21];  // L(i, j), i >= j, stored at tri(j, i)
+  float dmax = 0.f;
+#pragma unroll
+  for (int j = 0; j < 6; ++j) dmax = fmaxf(dmax, tot[tri(j, j)]);
+  int bad = 0;
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    float s = tot[tri(j, j)];
+#pragma unroll
+    for (int k = 0; k < j; ++k) s = fmaf(-L[tri(k, j)], L[tri(k, j)], s);
+    bad |= !(s > 1e-6f * dmax);
+    s = fmaxf(s, 1e-30f);
+    const float d = sqrtf(s);
+    L[tri(j, j)] = d;
+    const float inv = 1.0f / d;
+#pragma unroll
+    for (int i = j + 1; i < 6; ++i) {
+      float t = tot[tri(j, i)];
+#pragma unroll
+      for (int k = 0; k < j; ++k) t = fmaf(-L[tri(k, i)], L[tri(k, j)], t);
+      L[tri(j, i)] = t * inv;
+    }
+  }
+  if (bad) return 1;
+  float y[6], d[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    float s = tot[kSlotB + i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) s = fmaf(-L[tri(k, i)], y[k], s);
+    y[i] = s / L[tri(i, i)];
+  }
+#pragma unroll
+  for (int i = 5; i >= 0; --i) {
+    float s = y[i];
+#pragma unroll
+    for (int k = i + 1; k < 6; ++k) s = fmaf(-L[tri(i, k)], d[k], s);
+    d[i] = s / L[tri(i, i)];
+  }
+  float m = 0.f;
+#pragma unroll
+  for (int j = 0; j < 6; ++j) m = fmaxf(m, fabsf(d[j]));
+  *max_step = m;
+  // exp(xi), xi = -delta = (w, v): R = I + A[w] + B[w]^2, t = (I + B[w] + C[w]^2) v
+  const float w0 = -d[0], w1 = -d[1], w2 = -d[2];
+  const float vv[3] = {-d[3], -d[4], -d[5]};
+  const float th2 = w0 * w0 + w1 * w1 + w2 * w2, th = sqrtf(th2);
+  float A, B, C;
+  if (th < 0.05f) {
+    A = 1.0f - th2 * (1.0f / 6.0f) * (1.0f - th2 * (1.0f / 20.0f));
+    B = 0.5f - th2 * (1.0f / 24.0f) * (1.0f - th2 * (1.0f / 30.0f));
+    C = (1.0f / 6.0f) - th2 * (1.0f / 120.0f) * (1.0f - th2 * (1.0f / 42.0f));
+  } else {
+    const float sn = sinf(th), sh = sinf(0.5f * th);
+    A = sn / th;
+    B = 2.0f * sh * sh / th2;
+    C = (th - sn) / (th2 * th);
+  }
+  const float W[3][3] = {{0.f, -w2, w1}, {w2, 0.f, -w0}, {-w1, w0, 0.f}};
+  float E[3][4];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    float tv = 0.f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float W2 = W[r][0] * W[0][c] + W[r][1] * W[1][c] + W[r][2] * W[2][c];
+      const float id = (r == c) ? 1.0f : 0.0f;
+      E[r][c] = id + A * W[r][c] + B * W2;
+      tv += (id + B * W[r][c] + C * W2) * vv[c];
+    }
+    E[r][3] = tv;
+  }
+  float N[12];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      N[4 * r + c] = fmaf(T[4 * r], E[0][c], fmaf(T[4 * r + 1], E[1][c], T[4 * r + 2] * E[2][c]));
+    N[4 * r + 3] = fmaf(T[4 * r], E[0][3], fmaf(T[4 * r + 1], E[1][3], fmaf(T[4 * r + 2], E[2][3], T[4 * r + 3])));
+  }
+#pragma unroll
+  for (int j = 0; j < 12; ++j) T[j] = N[j];
+  return 0;
+}
+
+// FP64 variant of solve_update: Cholesky solve (pivot <= 1e-12 of the largest
+// diagonal entry: not positive definite) and T <- T exp(-delta), pose in FP64.
+__device__ __forceinline__ int solve_update_d(const float* tot, double* T, double* max_step) {
+  double L[21];
+  double dmax = 0.0;
+#pragma unroll
+  for (int j = 0; j < 6; ++j) dmax = fmax(dmax, (double)tot[tri(j, j)]);
+  int bad = 0;
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    double s = tot[tri(j, j)];
+#pragma unroll
+    for (int k = 0; k < j; ++k) s = fma(-L[tri(k, j)], L[tri(k, j)], s);
+    bad |= !(s > 1e-12 * dmax);
+    s = fmax(s, 1e-300);
+    const double d = sqrt(s);
+    L[tri(j, j)] = d;
+    const double inv = 1.0 / d;
+#pragma unroll
+    for (int i = j + 1; i < 6; ++i) {
+      double t = tot[tri(j, i)];
+#pragma unroll
+      for (int k = 0; k < j; ++k) t = fma(-L[tri(k, i)], L[tri(k, j)], t);
+      L[tri(j, i)] = t * inv;
+    }
+  }
+  if (bad) return 1;
+  double y[6], d[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    double s = tot[kSlotB + i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) s = fma(-L[tri(k, i)], y[k], s);
+    y[i] = s / L[tri(i, i)];
+  }
+#pragma unroll
+  for (int i = 5; i >= 0; --i) {
+    double s = y[i];
+#pragma unroll
+    for (int k = i + 1; k < 6; ++k) s = fma(-L[tri(i, k)], d[k], s);
+    d[i] = s / L[tri(i, i)];
+  }
+  double m = 0.0;
+#pragma unroll
+  for (int j = 0; j < 6; ++j) m = fmax(m, fabs(d[j]));
+  *max_step = m;
+  const double w0 = -d[0], w1 = -d[1], w2 = -d[2];
+  const double vv[3] = {-d[3], -d[4], -d[5]};
+  const double th2 = w0 * w0 + w1 * w1 + w2 * w2, th = sqrt(th2);
+  double A, B, C;
+  if (th < 1e-4) {
+    A = 1.0 - th2 / 6.0;
+    B = 0.5 - th2 / 24.0;
+    C = 1.0 / 6.0 - th2 / 120.0;
+  } else {
+    const double sn = sin(th), sh = sin(0.5 * th);
+    A = sn / th;
+    B = 2.0 * sh * sh / th2;
+    C = (th - sn) / (th2 * th);
+  }
+  const double W[3][3] = {{0.0, -w2, w1}, {w2, 0.0, -w0}, {-w1, w0, 0.0}};
+  double E[3][4];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    double tv = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double W2 = W[r][0] * W[0][c] + W[r][1] * W[1][c] + W[r][2] * W[2][c];
+      const double id = (r == c) ? 1.0 : 0.0;
+      E[r][c] = id + A * W[r][c] + B * W2;
+      tv += (id + B * W[r][c] + C * W2) * vv[c];
+    }
+    E[r][3] = tv;
+  }
+  double N[12];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) N[4 * r + c] = T[4 * r] * E[0][c] + T[4 * r + 1] * E[1][c] + T[4 * r + 2] * E[2][c];
+    N[4 * r + 3] = T[4 * r] * E[0][3] + T[4 * r + 1] * E[1][3] + T[4 * r + 2] * E[2][3] + T[4 * r + 3];
+  }
+#pragma unroll
+  for (int j = 0; j < 12; ++j) T[j] = N[j];
+  return 0;
+}
+
+// One map point's IC cache (K = 8) held in registers across the iterations of
+// a level: the reference-camera point x0, template intensities and gradients.
+struct PointRegs {
+  float X0, Y0, Z0;
+  float i0_[8], gx_[8], gy_[8];
+  bool ok;
+  __device__ __forceinline__ float i0(int k) const { return i0_[k]; }
+  __device__ __forceinline__ float gx(int k) const { return gx_[k]; }
+  __device__ __forceinline__ float gy(int k) const { return gy_[k]; }
+};
+
+// Mixed-precision variant: template intensity (minus 128) and gradients in FP16,
+// 12 registers per point instead of 24.
+struct PointRegsH {
+  float X0, Y0, Z0;
+  __half i0_[8];
+  __half2 g_[8];
+  bool ok;
+  __device__ __forceinline__ float i0(int k) const { return __half2float(i0_[k]) + 128.0f; }
+  __device__ __forceinline__ float gx(int k) const { return __low2float(g_[k]); }
+  __device__ __forceinline__ float gy(int k) const { return __high2float(g_[k]); }
+};
+
+__device__ __forceinline__ void load_point(const TrackArgs& a, int l, int i, PointRegs& pr) {
+  const int64_t lo = (int64_t)l * a.ref.cap;
+  pr.ok = (i < a.ref.n) && a.ref.valid[lo + i];
+  if (!pr.ok) return;
+  const float4 p = a.ref.x0[i];
+  pr.X0 = p.x, pr.Y0 = p.y, pr.Z0 = p.z;
+  const float4* q0 = reinterpret_cast<const float4*>(a.ref.I0 + (lo + i) * 8);
+  const float4* qx = reinterpret_cast<const float4*>(a.ref.gx + (lo + i) * 8);
+  const float4* qy = reinterpret_cast<const float4*>(a.ref.gy + (lo + i) * 8);
+  const float4 a0 = q0[0], a1 = q0[1], b0 = qx[0], b1 = qx[1], c0 = qy[0], c1 = qy[1];
+  const float t0[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+  const float t1[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+  const float t2[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+#pragma unroll
+  for (int k = 0; k < 8; ++k) pr.i0_[k] = t0[k], pr.gx_[k] = t1[k], pr.gy_[k] = t2[k];
+}
+
+__device__ __forceinline__ void load_point(const TrackArgs& a, int l, int i, PointRegsH& pr) {
+  const int64_t lo = (int64_t)l * a.ref.cap;
+  pr.ok = (i < a.ref.n) && a.ref.valid[lo + i];
+  if (!pr.ok) return;
+  const float4 p = a.ref.x0[i];
+  pr.X0 = p.x, pr.Y0 = p.y, pr.Z0 = p.z;
+  const uint4 h = *reinterpret_cast<const uint4*>(a.ref.I0h + (lo + i) * 8);
+  const uint4* q = reinterpret_cast<const uint4*>(a.ref.gh + (lo + i) * 8);
+  const uint4 g0 = q[0], g1 = q[1];
+  const uint32_t hw[4] = {h.x, h.y, h.z, h.w};
+  const uint32_t gw[8] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    pr.i0_[2 * k] = __ushort_as_half((unsigned short)(hw[k] & 0xffffu));
+    pr.i0_[2 * k + 1] = __ushort_as_half((unsigned short)(hw[k] >> 16));
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    __half2 v;
+    __builtin_memcpy(&v, &gw[k], 4);
+    pr.g_[k] = v;
+  }
+}
+
+// Add one point's normal-equation terms (Eq.(2), Eq.(5)) at relative pose T.
+// The K samples share the point's 2x6 warp Jacobian Jw with rows au, av, so with
+// J_k = gx_k au + gy_k av:
+//   H_i = m00 au^T au + m01 (au^T av + av^T au) + m11 av^T av,   b_i = -(v0 au + v1 av),
+// m = sum_k w_k g_k^T g_k, v = sum_k w_k g_k r_k (five FMAs per sample, the
+// 21-term product once per point).  Huber weight w = min(1, k/|r|).
+template <bool COST_ONLY, class PR>
+__device__ __forceinline__ void accumulate_point(const TrackArgs& a, const Pattern& pat, const LevelGeom& g,
+                                                 const uint8_t* __restrict__ img, const float* T,
+                                                 const PR& pr, float (&acc)[32]) {
+  if (!pr.ok) return;
+  const float kH = a.huber_k;
+  float X, Y, Z;
+  transform(T, pr.X0, pr.Y0, pr.Z0, X, Y, Z);
+  if (!(Z > a.z_min)) return;
+  float u, v;
+  project(g, X, Y, Z, u, v);
+  if (!inside(g, pat, u, v)) return;
+  float m00 = 0.f, m01 = 0.f, m11 = 0.f, v0 = 0.f, v1 = 0.f, E = 0.f;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const float Ic = bilinear(img, g.W, u + (float)pat.dx[k], v + (float)pat.dy[k]);
+    const float r = pr.i0(k) - Ic;
+    const float ar = fabsf(r);
+    float w, rho;
+    if (kH > 0.f && ar > kH) {
+      w = kH / ar;
+      rho = kH * (ar - 0.5f * kH);
+    } else {
+      w = 1.0f;
+      rho = 0.5f * r * r;
+    }
+    E += rho;
+    if (!COST_ONLY) {
+      const float gx = pr.gx(k), gy = pr.gy(k);
+      const float wgx = w * gx, wgy = w * gy;
+      m00 = fmaf(wgx, gx, m00);
+      m01 = fmaf(wgx, gy, m01);
+      m11 = fmaf(wgy, gy, m11);
+      v0 = fmaf(wgx, r, v0);
+      v1 = fmaf(wgy, r, v1);
+    }
+  }
+  acc[kSlotE] += E;
+  acc[kSlotN] += 8.0f;
+  acc[kSlotPts] += 1.0f;
+  if (COST_ONLY) return;
+  const float iz = 1.0f / pr.Z0, xp = pr.X0 * iz, yp = pr.Y0 * iz;
+  const float au[6] = {-g.fx * xp * yp, g.fx * fmaf(xp, xp, 1.0f), -g.fx * yp, g.fx * iz, 0.0f, -g.fx * xp * iz};
+  const float av[6] = {-g.fy * fmaf(yp, yp, 1.0f), g.fy * xp * yp, g.fy * xp, 0.0f, g.fy * iz, -g.fy * yp * iz};
+  int q = 0;
+#pragma unroll
+  for (int r = 0; r < 6; ++r) {
+    const float ma = fmaf(m00, au[r], m01 * av[r]);
+    const float mc = fmaf(m01, au[r], m11 * av[r]);
+#pragma unroll
+    for (int c = r; c < 6; ++c) {
+      acc[q] = fmaf(ma, au[c], fmaf(mc, av[c], acc[q]));
+      ++q;
+    }
+    acc[kSlotB + r] -= fmaf(au[r], v0, av[r] * v1);
+  }
+}
+
+}  // namespace dpt

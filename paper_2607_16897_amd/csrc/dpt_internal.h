@@ -2,14 +2,18 @@
 // Not part of the public ABI (see include/dptrack.h).
 #pragma once
 
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <algorithm>
+#include <vector>
 
 namespace dpt {
 
 constexpr int kMaxLevels = 8;
 constexpr int kMaxPattern = 128;
-constexpr int kTrackThreads = 1024;  // one workgroup per tracked frame
+constexpr int kTrackThreads = 512;   // one workgroup per tracked frame
 constexpr int kRedSlots = 32;        // 21 H + 6 b + E + n + npts, padded to 32
 
 // Upper-triangle order of H used in every reduction: (0,0) (0,1) .. (0,5) (1,1) .. (5,5).
@@ -30,17 +34,20 @@ struct Pattern {
 
 // Reference-side IC cache: per level l, sample s = i*K + k lives at l*cap*K + s.
 struct RefCache {
-  const float* x0;          // [cap][3] reference-camera points
+  const float4* x0;         // [cap] reference-camera points (w unused)
   const uint8_t* valid;     // [L][cap]
   const float* I0;          // [L][cap*K]
   const float* gx;          // [L][cap*K]
   const float* gy;          // [L][cap*K]
+  const __half* I0h;        // mixed precision: [L][cap*K] template intensity - 128
+  const __half2* gh;        // mixed precision: [L][cap*K] (gx, gy)
   int32_t n, cap;
 };
 
 // What a track launch writes back (device), read by the host after the stream sync.
 struct TrackOut {
-  float T[12];  // final relative pose reference -> current, 3x4 row-major
+  double Td[12];  // mixed precision: final relative pose in FP64
+  float T[12];    // final relative pose reference -> current, 3x4 row-major
   float E, n;   // final cost pass: Huber cost sum and valid sample count
   int32_t iterations;
   int32_t iters_per_level[kMaxLevels];
@@ -78,18 +85,77 @@ struct PrecomputeArgs {
   Pattern pat;
   const float* P;  // [n][3] world points
   float T_rw[12];
-  float* x0;
+  float4* x0;
   uint8_t* valid;
   float *I0, *gx, *gy;
+  __half* I0h;   // written when non-null (mixed precision)
+  __half2* gh;
   int32_t n, cap;
 };
 
-// Launchers (kernels.hip).  Each returns the hipError_t of the launch.
+// One stream of a cooperative track launch (device array, one entry per stream).
+struct CoopStream {
+  TrackArgs a;      // a.out points at this stream's TrackOut
+  float* partials;  // [2][n_chunks][32] double-buffered chunk sums
+  int* sync;        // [2] arrival and departure counters, zero between launches
+  int32_t n_chunks;
+  int32_t pad;
+};
+
+// One image of a batched pyramid launch.
+struct PyrJob {
+  const uint8_t* src;
+  int64_t pitch;
+  uint8_t* dst;
+  PyrGeom g;
+  int32_t vec4;
+  int32_t pad;
+};
+
+// Host-side owner of a cooperative track launch over n streams.
+struct CoopEngine {
+  int n = 0, chunk = 256, work_cap = 0;
+  bool xcd_pack = true, dirty = true;
+  hipStream_t stream = nullptr;
+  std::vector<CoopStream> h_streams;
+  std::vector<int> max_chunks;
+  std::vector<int2> h_work;
+  CoopStream* d_streams = nullptr;
+  int2* d_work = nullptr;
+  float* d_partials = nullptr;
+  int* d_sync = nullptr;
+  double* d_T = nullptr;  // [n][12] start poses (relative)
+  double* h_T = nullptr;  // pinned
+  bool mixed = false;     // mixed-precision kernel variant
+  TrackOut* d_out = nullptr;
+  TrackOut* h_out = nullptr;  // pinned
+  hipError_t init(int n_streams, const int* max_points, int chunk, bool xcd_pack, hipStream_t s);
+  void release();
+  void set_stream(int k, const TrackArgs& a);
+  hipError_t upload();
+  int grid() const;
+  // H2D of h_T, the launch, and an async D2H of the results into h_out
+  hipError_t launch(int spin_limit);
+  hipError_t reset_sync();
+  ~CoopEngine() { release(); }
+};
+
+constexpr int kSpinLimit = 1 << 24;  // polls (~64 clocks each) before a chunk reports a timeout
+
+// Launchers (kernels.hip, coop.hip).  Each returns the hipError_t of the launch.
 hipError_t launch_pyramid(const uint8_t* src, int64_t pitch, uint8_t* dst, const PyrGeom& g, hipStream_t s);
 hipError_t launch_select(const uint8_t* img, int32_t W, int32_t H, int32_t margin, int32_t n, int32_t* idx,
                          int32_t* count, hipStream_t s);
 hipError_t launch_precompute(const PrecomputeArgs& a, hipStream_t s);
 hipError_t launch_track(const TrackArgs& a, hipStream_t s);
+// One workgroup per frame; batch[b] describes frame b (device memory).
+hipError_t launch_track_batch(const TrackArgs& any, const TrackArgs* batch, int n_frames, int lds_bytes,
+                              int max_points, hipStream_t s);
+int track_lds_bytes(const LevelGeom* lv, int levels);
 hipError_t launch_normal_equations(const TrackArgs& a, hipStream_t s);
+hipError_t launch_coop_track(const CoopStream* d_streams, const int2* d_work, int n_work, const double* d_T,
+                             int chunk, bool mixed, int spin_limit, hipStream_t s);
+int coop_max_blocks(int chunk);  // co-resident workgroups of a cooperative launch (0 if unsupported)
+hipError_t launch_pyramid_batch(const PyrJob* d_jobs, int n_jobs, int max_w, int max_h, int levels, hipStream_t s);
 
 }  // namespace dpt

@@ -5,124 +5,16 @@
 // fmaf, so that the reference precompute and the track evaluate the projection
 // and the bilinear sample with identical arithmetic (an identical frame at the
 // reference pose then gives residuals of exactly zero).
-#include "dpt_internal.h"
+#include "dpt_device.h"
 
 namespace dpt {
 
-// ---------------------------------------------------------------- helpers
-
-__device__ __forceinline__ void transform(const float* T, float X, float Y, float Z, float& x, float& y,
-                                          float& z) {
-  x = fmaf(T[0], X, fmaf(T[1], Y, fmaf(T[2], Z, T[3])));
-  y = fmaf(T[4], X, fmaf(T[5], Y, fmaf(T[6], Z, T[7])));
-  z = fmaf(T[8], X, fmaf(T[9], Y, fmaf(T[10], Z, T[11])));
-}
-
-// Eq.(1): pinhole projection at one pyramid level.
-__device__ __forceinline__ void project(const LevelGeom& g, float x, float y, float z, float& u, float& v) {
-  u = fmaf(g.fx, x / z, g.cx);
-  v = fmaf(g.fy, y / z, g.cy);
-}
-
-// A point is usable when it is in front of the camera and every pattern
-// position p satisfies 1 <= p.x < W-2 and 1 <= p.y < H-2 (the bilinear taps and
-// their central differences stay inside the level).
-__device__ __forceinline__ bool inside(const LevelGeom& g, const Pattern& p, float u, float v) {
-  return (u + (float)p.dx_min >= 1.0f) && (u + (float)p.dx_max < (float)(g.W - 2)) &&
-         (v + (float)p.dy_min >= 1.0f) && (v + (float)p.dy_max < (float)(g.H - 2));
-}
-
-// Bilinear intensity of a uint8 level, pixel centres at integer coordinates.
-__device__ __forceinline__ float bilinear(const uint8_t* img, int W, float x, float y) {
-  float fx = floorf(x), fy = floorf(y);
-  float a = x - fx, c = y - fy;
-  const uint8_t* p = img + (int)fy * W + (int)fx;
-  float p00 = p[0], p10 = p[1], p01 = p[W], p11 = p[W + 1];
-  float top = fmaf(a, p10 - p00, p00);
-  float bot = fmaf(a, p11 - p01, p01);
-  return fmaf(c, bot - top, top);
-}
-
-// Reference-side gradient: central differences / 2 at the four bilinear taps,
-// blended with the same bilinear weights.
-__device__ __forceinline__ void gradient(const uint8_t* img, int W, float x, float y, float& gx, float& gy) {
-  float fx = floorf(x), fy = floorf(y);
-  float a = x - fx, c = y - fy;
-  const uint8_t* p = img + (int)fy * W + (int)fx;
-  float gx00 = 0.5f * ((float)p[1] - (float)p[-1]);
-  float gx10 = 0.5f * ((float)p[2] - (float)p[0]);
-  float gx01 = 0.5f * ((float)p[W + 1] - (float)p[W - 1]);
-  float gx11 = 0.5f * ((float)p[W + 2] - (float)p[W]);
-  float gy00 = 0.5f * ((float)p[W] - (float)p[-W]);
-  float gy10 = 0.5f * ((float)p[W + 1] - (float)p[1 - W]);
-  float gy01 = 0.5f * ((float)p[2 * W] - (float)p[0]);
-  float gy11 = 0.5f * ((float)p[2 * W + 1] - (float)p[1]);
-  float tx = fmaf(a, gx10 - gx00, gx00), bx = fmaf(a, gx11 - gx01, gx01);
-  float ty = fmaf(a, gy10 - gy00, gy00), by = fmaf(a, gy11 - gy01, gy01);
-  gx = fmaf(c, bx - tx, tx);
-  gy = fmaf(c, by - ty, ty);
-}
-
 // ---------------------------------------------------------------- pyramid
 
-// One launch builds every level.  A workgroup owns a TILE x TILE block of
-// level 0 (TILE >= 2^(levels-1)), so each level's 2x2 parents stay inside the
-// tile; levels alternate between two LDS buffers.
 template <int TILE>
 __global__ __launch_bounds__(256) void pyramid_kernel(const uint8_t* __restrict__ src, int64_t pitch,
                                                       uint8_t* __restrict__ dst, PyrGeom g, int vec4) {
-  __shared__ uint8_t buf0[TILE * TILE];
-  __shared__ uint8_t buf1[TILE * TILE / 4];
-  const int ox = blockIdx.x * TILE, oy = blockIdx.y * TILE;
-  const int W0 = g.W[0], H0 = g.H[0];
-  if (vec4) {
-    // 4-byte loads: width, pitch and base are multiples of 4
-    for (int q = threadIdx.x; q < TILE * TILE / 4; q += blockDim.x) {
-      int ly = q / (TILE / 4), lx = (q % (TILE / 4)) * 4;
-      int gx = ox + lx, gy = oy + ly;
-      uint32_t v = 0;
-      if (gy < H0 && gx < W0) {
-        v = *reinterpret_cast<const uint32_t*>(src + gy * pitch + gx);
-        *reinterpret_cast<uint32_t*>(dst + g.off[0] + (int64_t)gy * W0 + gx) = v;
-      }
-      *reinterpret_cast<uint32_t*>(buf0 + ly * TILE + lx) = v;
-    }
-  } else {
-    for (int q = threadIdx.x; q < TILE * TILE; q += blockDim.x) {
-      int ly = q / TILE, lx = q % TILE;
-      int gx = ox + lx, gy = oy + ly;
-      uint8_t v = 0;
-      if (gy < H0 && gx < W0) {
-        v = src[gy * pitch + gx];
-        dst[g.off[0] + (int64_t)gy * W0 + gx] = v;
-      }
-      buf0[q] = v;
-    }
-  }
-  __syncthreads();
-  uint8_t* prev = buf0;
-  uint8_t* next = buf1;
-  for (int l = 1; l < g.levels; ++l) {
-    const int T = TILE >> l, Tp = TILE >> (l - 1);
-    const int Wl = g.W[l], Hl = g.H[l];
-    const int oxl = ox >> l, oyl = oy >> l;
-    for (int q = threadIdx.x; q < T * T; q += blockDim.x) {
-      int ly = q / T, lx = q % T;
-      int gx = oxl + lx, gy = oyl + ly;
-      uint8_t v = 0;
-      if (gx < Wl && gy < Hl) {
-        const uint8_t* p = prev + (2 * ly) * Tp + 2 * lx;
-        int s = (int)p[0] + (int)p[1] + (int)p[Tp] + (int)p[Tp + 1];
-        v = (uint8_t)((s + 2) >> 2);
-        dst[g.off[l] + (int64_t)gy * Wl + gx] = v;
-      }
-      next[q] = v;
-    }
-    __syncthreads();
-    uint8_t* t = prev;
-    prev = next;
-    next = t;
-  }
+  pyramid_tile<TILE>(src, pitch, dst, g, vec4);
 }
 
 hipError_t launch_pyramid(const uint8_t* src, int64_t pitch, uint8_t* dst, const PyrGeom& g, hipStream_t s) {
@@ -141,70 +33,6 @@ hipError_t launch_pyramid(const uint8_t* src, int64_t pitch, uint8_t* dst, const
     hipLaunchKernelGGL(pyramid_kernel<128>, grid, dim3(256), 0, s, src, pitch, dst, g, vec4);
   }
   return hipGetLastError();
-}
-
-// ---------------------------------------------------------------- block scans / reductions
-
-// Exclusive prefix sum of one int per thread over a 1024-thread workgroup.
-// `wsum` is 16 ints of LDS.  Returns the prefix; *total gets the block sum.
-__device__ __forceinline__ int block_exclusive_scan(int x, int* wsum, int* total) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  int inc = x;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    int y = __shfl_up(inc, d, 64);
-    if (lane >= d) inc += y;
-  }
-  if (lane == 63) wsum[wave] = inc;
-  __syncthreads();
-  int base = 0, tot = 0;
-  for (int w = 0; w < nw; ++w) {
-    int v = wsum[w];
-    base += (w < wave) ? v : 0;
-    tot += v;
-  }
-  __syncthreads();
-  *total = tot;
-  return base + inc - x;
-}
-
-// Sum 32 per-lane values over a wave64 by recursive halving: at each xor step
-// a lane keeps half of its values and receives the partner's matching half, so
-// 16 + 8 + 4 + 2 + 1 + 1 shuffles replace 32 x 6.  Lane l ends up holding the
-// wave total of value (l >> 1).  The order of additions is fixed.
-__device__ __forceinline__ float wave_reduce32(float (&a)[32]) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int step = 0; step < 5; ++step) {
-    const int half = 16 >> step;        // values kept after this step
-    const int mask = 32 >> step;        // partner lane distance
-    const bool upper = (lane & mask) != 0;
-#pragma unroll
-    for (int j = 0; j < half; ++j) {
-      float keep = upper ? a[j + half] : a[j];
-      float send = upper ? a[j] : a[j + half];
-      float recv = __shfl_xor(send, mask, 64);
-      a[j] = keep + recv;
-    }
-  }
-  float v = a[0];
-  v += __shfl_xor(v, 1, 64);
-  return v;
-}
-
-// Workgroup total of 32 per-lane values into out[32] (LDS), fixed order.
-// `scratch` is 16 x 32 floats of LDS.
-__device__ __forceinline__ void block_reduce32(float (&a)[32], float* scratch, float* out) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  float v = wave_reduce32(a);
-  if ((lane & 1) == 0) scratch[wave * 32 + (lane >> 1)] = v;
-  __syncthreads();
-  if (threadIdx.x < 32) {
-    float s = 0.0f;
-    for (int w = 0; w < nw; ++w) s += scratch[w * 32 + threadIdx.x];
-    out[threadIdx.x] = s;
-  }
-  __syncthreads();
 }
 
 // ---------------------------------------------------------------- point selection
@@ -344,11 +172,7 @@ __global__ __launch_bounds__(256) void precompute_kernel(PrecomputeArgs a) {
   const int i = s / K, k = s - i * K;
   float X, Y, Z;
   transform(a.T_rw, a.P[3 * i], a.P[3 * i + 1], a.P[3 * i + 2], X, Y, Z);
-  if (l == 0 && k == 0) {
-    a.x0[3 * i] = X;
-    a.x0[3 * i + 1] = Y;
-    a.x0[3 * i + 2] = Z;
-  }
+  if (l == 0 && k == 0) a.x0[i] = make_float4(X, Y, Z, 0.0f);
   const LevelGeom g = a.lv[l];
   bool ok = Z > a.z_min;
   float u = 0.f, v = 0.f;
@@ -368,6 +192,10 @@ __global__ __launch_bounds__(256) void precompute_kernel(PrecomputeArgs a) {
   a.I0[o] = I0;
   a.gx[o] = gx;
   a.gy[o] = gy;
+  if (a.I0h) {
+    a.I0h[o] = __float2half_rn(I0 - 128.0f);
+    a.gh[o] = __floats2half2_rn(gx, gy);
+  }
 }
 
 hipError_t launch_precompute(const PrecomputeArgs& a, hipStream_t s) {
@@ -380,183 +208,169 @@ hipError_t launch_precompute(const PrecomputeArgs& a, hipStream_t s) {
 // ---------------------------------------------------------------- track
 
 // Accumulate this thread's share of one normal-equation pass (Eq.(2), Eq.(5))
-// at level l and relative pose T: residual against the cached template, Huber
-// weight, IC Jacobian rebuilt from the cached gradient and x0, and the
-// 21 + 6 + 3 running sums.  Lane <-> sample s = i*K + k.
+// at one level and relative pose T.  One thread per map point: the K pattern
+// samples of a point share its 2x6 warp Jacobian Jw (rows au, av), so with
+// J_k = gx_k au + gy_k av the point's contribution is
+//   H_i = m00 au^T au + m01 (au^T av + av^T au) + m11 av^T av,  b_i = -(v0 au + v1 av)
+// where m = sum_k w_k g_k^T g_k and v = sum_k w_k g_k r_k: five FMAs per sample
+// and the 21-term product once per point.  `img` is the current level, in LDS
+// or global memory.
 template <int KT, bool COST_ONLY>
-__device__ __forceinline__ void accumulate(const TrackArgs& a, const Pattern& pat, int l, const float* T,
+__device__ __forceinline__ void accumulate(const TrackArgs& a, const Pattern& pat, const LevelGeom& g,
+                                           const uint8_t* __restrict__ img, int l, const float* T,
                                            float (&acc)[32]) {
   const int K = KT ? KT : pat.K;
-  const LevelGeom g = a.lv[l];
-  const uint8_t* img = a.cur + g.off;
   const int64_t lo = (int64_t)l * a.ref.cap;
-  const float* I0 = a.ref.I0 + lo * K;
-  const float* GX = a.ref.gx + lo * K;
-  const float* GY = a.ref.gy + lo * K;
-  const uint8_t* valid = a.ref.valid + lo;
+  const float* __restrict__ I0 = a.ref.I0 + lo * K;
+  const float* __restrict__ GX = a.ref.gx + lo * K;
+  const float* __restrict__ GY = a.ref.gy + lo * K;
+  const uint8_t* __restrict__ valid = a.ref.valid + lo;
   const float kH = a.huber_k;
-  const int nK = a.ref.n * K;
-  for (int s = threadIdx.x; s < nK; s += blockDim.x) {
-    const int i = s / K, k = s - i * K;
+  const int n = a.ref.n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
     if (!valid[i]) continue;
-    const float X0 = a.ref.x0[3 * i], Y0 = a.ref.x0[3 * i + 1], Z0 = a.ref.x0[3 * i + 2];
+    const float4 p = a.ref.x0[i];
     float X, Y, Z;
-    transform(T, X0, Y0, Z0, X, Y, Z);
+    transform(T, p.x, p.y, p.z, X, Y, Z);
     if (!(Z > a.z_min)) continue;
     float u, v;
     project(g, X, Y, Z, u, v);
     if (!inside(g, pat, u, v)) continue;
-    const float Ic = bilinear(img, g.W, u + (float)pat.dx[k], v + (float)pat.dy[k]);
-    const float r = I0[s] - Ic;
-    const float ar = fabsf(r);
-    float w, rho;
-    if (kH > 0.f && ar > kH) {
-      w = kH / ar;
-      rho = kH * (ar - 0.5f * kH);
-    } else {
-      w = 1.0f;
-      rho = 0.5f * r * r;
+    float i0[KT ? KT : 1], gxs[KT ? KT : 1], gys[KT ? KT : 1];
+    if constexpr (KT == 8) {
+      const float4* q0 = reinterpret_cast<const float4*>(I0 + (int64_t)i * 8);
+      const float4* qx = reinterpret_cast<const float4*>(GX + (int64_t)i * 8);
+      const float4* qy = reinterpret_cast<const float4*>(GY + (int64_t)i * 8);
+      const float4 a0 = q0[0], a1 = q0[1];
+      i0[0] = a0.x, i0[1] = a0.y, i0[2] = a0.z, i0[3] = a0.w, i0[4] = a1.x, i0[5] = a1.y, i0[6] = a1.z, i0[7] = a1.w;
+      if (!COST_ONLY) {
+        const float4 b0 = qx[0], b1 = qx[1], c0 = qy[0], c1 = qy[1];
+        gxs[0] = b0.x, gxs[1] = b0.y, gxs[2] = b0.z, gxs[3] = b0.w, gxs[4] = b1.x, gxs[5] = b1.y, gxs[6] = b1.z,
+        gxs[7] = b1.w;
+        gys[0] = c0.x, gys[1] = c0.y, gys[2] = c0.z, gys[3] = c0.w, gys[4] = c1.x, gys[5] = c1.y, gys[6] = c1.z,
+        gys[7] = c1.w;
+      }
     }
-    acc[kSlotE] += rho;
-    acc[kSlotN] += 1.0f;
-    if (k == 0) acc[kSlotPts] += 1.0f;
+    float m00 = 0.f, m01 = 0.f, m11 = 0.f, v0 = 0.f, v1 = 0.f, E = 0.f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const float Ic = bilinear(img, g.W, u + (float)pat.dx[k], v + (float)pat.dy[k]);
+      const float tmpl = KT ? i0[k] : I0[(int64_t)i * K + k];
+      const float r = tmpl - Ic;
+      const float ar = fabsf(r);
+      float w, rho;
+      if (kH > 0.f && ar > kH) {
+        w = kH / ar;
+        rho = kH * (ar - 0.5f * kH);
+      } else {
+        w = 1.0f;
+        rho = 0.5f * r * r;
+      }
+      E += rho;
+      if (!COST_ONLY) {
+        const float gx = KT ? gxs[k] : GX[(int64_t)i * K + k];
+        const float gy = KT ? gys[k] : GY[(int64_t)i * K + k];
+        const float wgx = w * gx, wgy = w * gy;
+        m00 = fmaf(wgx, gx, m00);
+        m01 = fmaf(wgx, gy, m01);
+        m11 = fmaf(wgy, gy, m11);
+        v0 = fmaf(wgx, r, v0);
+        v1 = fmaf(wgy, r, v1);
+      }
+    }
+    acc[kSlotE] += E;
+    acc[kSlotN] += (float)K;
+    acc[kSlotPts] += 1.0f;
     if (COST_ONLY) continue;
-    // J = (gx, gy) * Jw(x0): columns (w1 w2 w3 v1 v2 v3) of a left perturbation
-    const float iz = 1.0f / Z0, xp = X0 * iz, yp = Y0 * iz;
-    const float gxf = GX[s] * g.fx, gyf = GY[s] * g.fy;
-    float J[6];
-    J[0] = -fmaf(gxf * xp, yp, fmaf(gyf, yp * yp, gyf));
-    J[1] = fmaf(gxf, xp * xp, fmaf(gyf * xp, yp, gxf));
-    J[2] = fmaf(gyf, xp, -gxf * yp);
-    J[3] = gxf * iz;
-    J[4] = gyf * iz;
-    J[5] = -fmaf(gxf, xp, gyf * yp) * iz;
+    // warp Jacobian rows at x0 for a left perturbation (w1 w2 w3 v1 v2 v3)
+    const float iz = 1.0f / p.z, xp = p.x * iz, yp = p.y * iz;
+    const float au[6] = {-g.fx * xp * yp, g.fx * fmaf(xp, xp, 1.0f), -g.fx * yp, g.fx * iz, 0.0f, -g.fx * xp * iz};
+    const float av[6] = {-g.fy * fmaf(yp, yp, 1.0f), g.fy * xp * yp, g.fy * xp, 0.0f, g.fy * iz, -g.fy * yp * iz};
     int q = 0;
 #pragma unroll
-    for (int p = 0; p < 6; ++p) {
-      const float wj = w * J[p];
+    for (int r = 0; r < 6; ++r) {
+      const float ma = fmaf(m00, au[r], m01 * av[r]);
+      const float mc = fmaf(m01, au[r], m11 * av[r]);
 #pragma unroll
-      for (int c = p; c < 6; ++c) {
-        acc[q] = fmaf(wj, J[c], acc[q]);
+      for (int c = r; c < 6; ++c) {
+        acc[q] = fmaf(ma, au[c], fmaf(mc, av[c], acc[q]));
         ++q;
       }
-      acc[kSlotB + p] = fmaf(-wj, r, acc[kSlotB + p]);
+      acc[kSlotB + r] -= fmaf(au[r], v0, av[r] * v1);
     }
   }
 }
 
-// Index of H(i, j), i <= j, in the row-major upper-triangle order of the sums.
-__host__ __device__ constexpr int tri(int i, int j) { return i * 6 - (i * (i - 1)) / 2 + (j - i); }
+// Register-resident variant for K = 8 and at most kCachedPPT points per
+// thread: thread t owns points t + j * blockDim.x, whose IC cache is loaded
+// once per level and reused by every iteration of that level.
+constexpr int kCachedPPT = 4;
 
-// Solve H delta = b (6x6 SPD from the 21 upper-triangle sums) by Cholesky in
-// FP32 and apply T <- T exp(-delta).  Returns 0, or 1 if a pivot is <= 1e-6 of
-// the largest diagonal entry (not positive definite).  Every loop is unrolled
-// so the factor lives in registers.
-__device__ __forceinline__ int solve_update(const float* tot, float* T, float* max_step) {
-  float L[21];  // L(i, j), i >= j, stored at tri(j, i)
-  float dmax = 0.f;
+__device__ __forceinline__ void load_points(const TrackArgs& a, int l, PointRegs (&pr)[kCachedPPT]) {
 #pragma unroll
-  for (int j = 0; j < 6; ++j) dmax = fmaxf(dmax, tot[tri(j, j)]);
-  int bad = 0;
+  for (int j = 0; j < kCachedPPT; ++j) load_point(a, l, threadIdx.x + j * blockDim.x, pr[j]);
+}
+
+template <bool COST_ONLY>
+__device__ __forceinline__ void accumulate_cached(const TrackArgs& a, const Pattern& pat, const LevelGeom& g,
+                                                  const uint8_t* __restrict__ img, const float* T,
+                                                  const PointRegs (&pr)[kCachedPPT], float (&acc)[32]) {
 #pragma unroll
-  for (int j = 0; j < 6; ++j) {
-    float s = tot[tri(j, j)];
-#pragma unroll
-    for (int k = 0; k < j; ++k) s = fmaf(-L[tri(k, j)], L[tri(k, j)], s);
-    bad |= !(s > 1e-6f * dmax);
-    s = fmaxf(s, 1e-30f);
-    const float d = sqrtf(s);
-    L[tri(j, j)] = d;
-    const float inv = 1.0f / d;
-#pragma unroll
-    for (int i = j + 1; i < 6; ++i) {
-      float t = tot[tri(j, i)];
-#pragma unroll
-      for (int k = 0; k < j; ++k) t = fmaf(-L[tri(k, i)], L[tri(k, j)], t);
-      L[tri(j, i)] = t * inv;
-    }
-  }
-  if (bad) return 1;
-  float y[6], d[6];
-#pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    float s = tot[kSlotB + i];
-#pragma unroll
-    for (int k = 0; k < i; ++k) s = fmaf(-L[tri(k, i)], y[k], s);
-    y[i] = s / L[tri(i, i)];
-  }
-#pragma unroll
-  for (int i = 5; i >= 0; --i) {
-    float s = y[i];
-#pragma unroll
-    for (int k = i + 1; k < 6; ++k) s = fmaf(-L[tri(i, k)], d[k], s);
-    d[i] = s / L[tri(i, i)];
-  }
-  float m = 0.f;
-#pragma unroll
-  for (int j = 0; j < 6; ++j) m = fmaxf(m, fabsf(d[j]));
-  *max_step = m;
-  // exp(xi), xi = -delta = (w, v): R = I + A[w] + B[w]^2, t = (I + B[w] + C[w]^2) v
-  const float w0 = -d[0], w1 = -d[1], w2 = -d[2];
-  const float vv[3] = {-d[3], -d[4], -d[5]};
-  const float th2 = w0 * w0 + w1 * w1 + w2 * w2, th = sqrtf(th2);
-  float A, B, C;
-  if (th < 0.05f) {
-    A = 1.0f - th2 * (1.0f / 6.0f) * (1.0f - th2 * (1.0f / 20.0f));
-    B = 0.5f - th2 * (1.0f / 24.0f) * (1.0f - th2 * (1.0f / 30.0f));
-    C = (1.0f / 6.0f) - th2 * (1.0f / 120.0f) * (1.0f - th2 * (1.0f / 42.0f));
+  for (int j = 0; j < kCachedPPT; ++j) accumulate_point<COST_ONLY>(a, pat, g, img, T, pr[j], acc);
+}
+
+// Copy one pyramid level into LDS (used when it fits the workgroup's budget).
+__device__ __forceinline__ void stage_level(const uint8_t* __restrict__ src, uint8_t* dst, int bytes) {
+  if ((reinterpret_cast<uintptr_t>(src) & 3) == 0) {
+    const int words = bytes >> 2;
+    const uint32_t* s4 = reinterpret_cast<const uint32_t*>(src);
+    uint32_t* d4 = reinterpret_cast<uint32_t*>(dst);
+    for (int j = threadIdx.x; j < words; j += blockDim.x) d4[j] = s4[j];
+    for (int j = (words << 2) + threadIdx.x; j < bytes; j += blockDim.x) dst[j] = src[j];
   } else {
-    const float sn = sinf(th), sh = sinf(0.5f * th);
-    A = sn / th;
-    B = 2.0f * sh * sh / th2;
-    C = (th - sn) / (th2 * th);
+    for (int j = threadIdx.x; j < bytes; j += blockDim.x) dst[j] = src[j];
   }
-  const float W[3][3] = {{0.f, -w2, w1}, {w2, 0.f, -w0}, {-w1, w0, 0.f}};
-  float E[3][4];
-#pragma unroll
-  for (int r = 0; r < 3; ++r) {
-    float tv = 0.f;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const float W2 = W[r][0] * W[0][c] + W[r][1] * W[1][c] + W[r][2] * W[2][c];
-      const float id = (r == c) ? 1.0f : 0.0f;
-      E[r][c] = id + A * W[r][c] + B * W2;
-      tv += (id + B * W[r][c] + C * W2) * vv[c];
-    }
-    E[r][3] = tv;
-  }
-  float N[12];
-#pragma unroll
-  for (int r = 0; r < 3; ++r) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-      N[4 * r + c] = fmaf(T[4 * r], E[0][c], fmaf(T[4 * r + 1], E[1][c], T[4 * r + 2] * E[2][c]));
-    N[4 * r + 3] = fmaf(T[4 * r], E[0][3], fmaf(T[4 * r + 1], E[1][3], fmaf(T[4 * r + 2], E[2][3], T[4 * r + 3])));
-  }
-#pragma unroll
-  for (int j = 0; j < 12; ++j) T[j] = N[j];
-  return 0;
 }
 
-// Whole coarse-to-fine track of one frame in one 1024-thread workgroup: the
-// Gauss-Newton loop needs only workgroup barriers, the 32 sums are reduced in
-// a fixed order (bitwise reproducible), and thread 0 solves and updates.
-template <int KT>
-__global__ __launch_bounds__(kTrackThreads) void track_kernel(TrackArgs a) {
+// Whole coarse-to-fine track of one frame per 1024-thread workgroup (workgroup
+// b tracks frame b of the batch): the Gauss-Newton loop needs only workgroup
+// barriers, the 32 sums are reduced in a fixed order (bitwise reproducible),
+// and thread 0 solves and updates.  Levels of at most `lds_bytes` are staged
+// in LDS once per level and reused by all iterations of that level.
+template <int KT, bool CACHED>
+__global__ __launch_bounds__(kTrackThreads) void track_kernel(TrackArgs a0, const TrackArgs* __restrict__ batch,
+                                                              int lds_bytes) {
+  extern __shared__ uint8_t dyn_lds[];
+  __shared__ TrackArgs sa;
   __shared__ float sh_T[12];
   __shared__ float sh_tot[32];
   __shared__ float sh_red[16 * 32];
   __shared__ int sh_flag;  // 0 continue, 1 level converged, 2 stop
-  __shared__ Pattern sh_pat;
   __shared__ int sh_ipl[kMaxLevels];
+  {
+    const TrackArgs* src = batch ? batch + blockIdx.x : &a0;
+    const int words = (int)(sizeof(TrackArgs) / 4);
+    for (int j = threadIdx.x; j < words; j += blockDim.x)
+      reinterpret_cast<uint32_t*>(&sa)[j] = reinterpret_cast<const uint32_t*>(src)[j];
+  }
+  __syncthreads();
+  const TrackArgs& a = sa;
   if (threadIdx.x < 12) sh_T[threadIdx.x] = a.T_init[threadIdx.x];
   if (threadIdx.x < kMaxLevels) sh_ipl[threadIdx.x] = 0;
-  if (threadIdx.x == 0) sh_pat = a.pat;
   __syncthreads();
   int status = 0, iterations = 0;  // authoritative in thread 0
   int64_t samples = 0;
   bool stop = false;  // uniform across the workgroup
   for (int l = a.levels - 1; l >= 0 && !stop; --l) {
+    const LevelGeom g = a.lv[l];
+    const int bytes = g.W * g.H;
+    const bool in_lds = bytes <= lds_bytes;
+    if (in_lds) {
+      stage_level(a.cur + g.off, dyn_lds, bytes);
+      __syncthreads();
+    }
+    PointRegs pr[CACHED ? kCachedPPT : 1];
+    if constexpr (CACHED) load_points(a, l, pr);
     bool converged = false;
     for (int it = 0; it < a.max_iters; ++it) {
       float acc[32];
@@ -565,7 +379,17 @@ __global__ __launch_bounds__(kTrackThreads) void track_kernel(TrackArgs a) {
       float T[12];
 #pragma unroll
       for (int j = 0; j < 12; ++j) T[j] = sh_T[j];
-      accumulate<KT, false>(a, sh_pat, l, T, acc);
+      if constexpr (CACHED) {
+        if (in_lds)
+          accumulate_cached<false>(a, a.pat, g, dyn_lds, T, pr, acc);
+        else
+          accumulate_cached<false>(a, a.pat, g, a.cur + g.off, T, pr, acc);
+      } else {
+        if (in_lds)
+          accumulate<KT, false>(a, a.pat, g, dyn_lds, l, T, acc);
+        else
+          accumulate<KT, false>(a, a.pat, g, a.cur + g.off, l, T, acc);
+      }
       block_reduce32(acc, sh_red, sh_tot);
       if (threadIdx.x == 0) {
         samples += (int64_t)sh_tot[kSlotN];
@@ -599,6 +423,7 @@ __global__ __launch_bounds__(kTrackThreads) void track_kernel(TrackArgs a) {
       }
     }
     if (threadIdx.x == 0 && !stop && l == 0 && !converged) status = 1;  // iteration cap at level 0
+    __syncthreads();  // LDS image is restaged for the next level
   }
   // final cost-only pass at level 0
   {
@@ -608,7 +433,8 @@ __global__ __launch_bounds__(kTrackThreads) void track_kernel(TrackArgs a) {
     float T[12];
 #pragma unroll
     for (int j = 0; j < 12; ++j) T[j] = sh_T[j];
-    accumulate<KT, true>(a, sh_pat, 0, T, acc);
+    const LevelGeom g = a.lv[0];
+    accumulate<KT, true>(a, a.pat, g, a.cur + g.off, 0, T, acc);
     block_reduce32(acc, sh_red, sh_tot);
   }
   if (threadIdx.x == 0) {
@@ -628,23 +454,56 @@ template <int KT>
 __global__ __launch_bounds__(kTrackThreads) void normal_eq_kernel(TrackArgs a) {
   __shared__ float sh_red[16 * 32];
   __shared__ float sh_tot[32];
-  __shared__ Pattern sh_pat;
-  if (threadIdx.x == 0) sh_pat = a.pat;
-  __syncthreads();
   float acc[32];
 #pragma unroll
   for (int j = 0; j < 32; ++j) acc[j] = 0.f;
-  accumulate<KT, false>(a, sh_pat, a.level, a.T_init, acc);
+  const LevelGeom g = a.lv[a.level];
+  accumulate<KT, false>(a, a.pat, g, a.cur + g.off, a.level, a.T_init, acc);
   block_reduce32(acc, sh_red, sh_tot);
   if (threadIdx.x < 32) a.totals[threadIdx.x] = sh_tot[threadIdx.x];
 }
 
-hipError_t launch_track(const TrackArgs& a, hipStream_t s) {
-  if (a.pat.K == 8)
-    hipLaunchKernelGGL(track_kernel<8>, dim3(1), dim3(kTrackThreads), 0, s, a);
-  else
-    hipLaunchKernelGGL(track_kernel<0>, dim3(1), dim3(kTrackThreads), 0, s, a);
+// Largest level (bytes) that a track workgroup stages in LDS.
+constexpr int kLdsImageBudget = 96 * 1024;
+
+int track_lds_bytes(const LevelGeom* lv, int levels) {
+  int best = 0;
+  for (int l = 0; l < levels; ++l) {
+    const int b = lv[l].W * lv[l].H;
+    if (b <= kLdsImageBudget && b > best) best = b;
+  }
+  return best;
+}
+
+template <int KT, bool CACHED>
+static hipError_t launch_track_k(const TrackArgs& a, const TrackArgs* batch, int n_frames, int lds, hipStream_t s) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&track_kernel<KT, CACHED>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, kLdsImageBudget);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((track_kernel<KT, CACHED>), dim3(n_frames), dim3(kTrackThreads), lds, s, a, batch, lds);
   return hipGetLastError();
+}
+
+// max_points: the largest map of any frame in the launch (selects the register-cached path)
+static hipError_t dispatch_track(const TrackArgs& a, const TrackArgs* batch, int n_frames, int lds, int max_points,
+                                 hipStream_t s) {
+  if (a.pat.K == 8 && max_points <= kCachedPPT * kTrackThreads)
+    return launch_track_k<8, true>(a, batch, n_frames, lds, s);
+  if (a.pat.K == 8) return launch_track_k<8, false>(a, batch, n_frames, lds, s);
+  return launch_track_k<0, false>(a, batch, n_frames, lds, s);
+}
+
+hipError_t launch_track(const TrackArgs& a, hipStream_t s) {
+  return dispatch_track(a, nullptr, 1, track_lds_bytes(a.lv, a.levels), a.ref.n, s);
+}
+
+hipError_t launch_track_batch(const TrackArgs& any, const TrackArgs* batch, int n_frames, int lds, int max_points,
+                              hipStream_t s) {
+  return dispatch_track(any, batch, n_frames, lds, max_points, s);
 }
 
 hipError_t launch_normal_equations(const TrackArgs& a, hipStream_t s) {

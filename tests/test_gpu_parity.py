@@ -80,11 +80,13 @@ def test_selection_bit_exact(gpu_lib, case):
 
 
 # ------------------------------------------------------------------ precompute cache
-def _pair_setup(dpt, seed=0, n=500, levels=3, cam=synth.CAM_640, **kw):
+def _pair_setup(dpt, seed=0, n=500, levels=3, cam=synth.CAM_640, launch=None, **kw):
     d = synth.pair(seed, cam)
     idx = oracle.select_points(d["ref"], n, 8)
     P = synth.backproject(cam, d["depth"], idx, d["T_rw"])
     trk, prm = _tracker(dpt, cam, n, levels=levels, **kw)
+    if launch is not None:
+        trk.set_launch_config(*launch)
     trk.build_pyramid(dpt.SLOT_REF, d["ref"])
     trk.set_reference_points(P, d["T_rw"])
     trk.build_pyramid(dpt.SLOT_CUR, d["cur"])
@@ -140,25 +142,42 @@ def test_track_single_pair(gpu_lib, seed):
     assert abs(g["n_valid_points"] - o["n_valid_points"]) <= 2
 
 
-def test_identity_on_identical_frames(gpu_lib):
+LAUNCHES = [(1, 256), (2, 64), (2, 128), (2, 256)]  # one workgroup; cooperative chunks
+
+
+@pytest.mark.parametrize("launch", LAUNCHES)
+@pytest.mark.parametrize("seed", [7, 42])
+def test_track_launch_configs(gpu_lib, seed, launch):
+    d, P, trk, ref = _pair_setup(gpu_lib, seed=seed, n=1500, launch=launch)
+    g = trk.track(np.eye(4))
+    o = ref.track(d["cur"], np.eye(4))
+    rot, tr, rel = _compare(g, o)
+    assert g["status"] == o["status"] == 0
+    assert rot < ROT_TOL and tr < TR_TOL and rel < COST_TOL
+
+
+@pytest.mark.parametrize("launch", LAUNCHES)
+def test_identity_on_identical_frames(gpu_lib, launch):
     dpt = gpu_lib
-    d, P, trk, ref = _pair_setup(dpt)
+    d, P, trk, ref = _pair_setup(dpt, launch=launch)
     trk.build_pyramid(dpt.SLOT_CUR, d["ref"])
     g = trk.track(np.eye(4))
     np.testing.assert_array_equal(g["T_cw"], np.eye(4))
     assert g["final_cost"] == 0.0 and g["iterations"] == 3 and g["status"] == 0
 
 
-def test_deterministic(gpu_lib):
-    d, P, trk, ref = _pair_setup(gpu_lib, seed=4)
+@pytest.mark.parametrize("launch", LAUNCHES)
+def test_deterministic(gpu_lib, launch):
+    d, P, trk, ref = _pair_setup(gpu_lib, seed=4, launch=launch)
     a, b = trk.track(np.eye(4)), trk.track(np.eye(4))
     np.testing.assert_array_equal(a["T_cw"], b["T_cw"])
     assert a["final_cost"] == b["final_cost"] and a["iterations"] == b["iterations"]
 
 
-def test_failure_statuses(gpu_lib):
+@pytest.mark.parametrize("launch", LAUNCHES)
+def test_failure_statuses(gpu_lib, launch):
     dpt = gpu_lib
-    d, P, trk, ref = _pair_setup(dpt, seed=4)
+    d, P, trk, ref = _pair_setup(dpt, seed=4, launch=launch)
     behind = np.eye(4)
     behind[2, 3] = -10.0
     assert trk.track(behind)["status"] == dpt.TRACK_TOO_FEW_POINTS
@@ -167,7 +186,7 @@ def test_failure_statuses(gpu_lib):
     trk.set_reference_points(P, d["T_rw"])
     trk.build_pyramid(dpt.SLOT_CUR, flat)
     assert trk.track(np.eye(4))["status"] == dpt.TRACK_NOT_PD
-    d, P, trk1, ref1 = _pair_setup(dpt, seed=4, max_iters=1)
+    d, P, trk1, ref1 = _pair_setup(dpt, seed=4, max_iters=1, launch=launch)
     g = trk1.track(np.eye(4))
     o = ref1.track(d["cur"], np.eye(4))
     assert g["status"] == o["status"] == dpt.TRACK_MAX_ITERS
@@ -187,12 +206,14 @@ def test_track_square_patches(gpu_lib, patch):
     assert rot < ROT_TOL and tr < TR_TOL and rel < COST_TOL
 
 
-def test_sequence_window_full_size(gpu_lib):
+@pytest.mark.parametrize("launch", [(1, 256), (2, 256)])
+def test_sequence_window_full_size(gpu_lib, launch):
     """752x480, 2000 points, 4 levels, sigma=2 noise: one keyframe window with the
     constant-velocity start, every frame compared with the oracle."""
     dpt = gpu_lib
     cam = synth.CAM_752
     trk, prm = _tracker(dpt, cam, 2000, levels=4)
+    trk.set_launch_config(*launch)
     frames = list(synth.sequence_frames(n_frames=11, start=100))
     k0, img0, depth0, T0 = frames[0]
     trk.build_pyramid(dpt.SLOT_REF, img0)
@@ -211,3 +232,52 @@ def test_sequence_window_full_size(gpu_lib):
         assert g["status"] == o["status"] == 0, (k, g["status"], o["status"])
         assert rot < ROT_TOL and tr < TR_TOL and rel < COST_TOL, (k, rot, tr, rel)
         prev2, prev1 = prev1, o["T_cw"]
+
+
+# ------------------------------------------------------------------ mixed precision
+MIXED_ROT_TOL, MIXED_TR_TOL = 2e-4, 2e-4  # FP16 template cache: stated per result
+
+
+@pytest.mark.parametrize("seed", [0, 3, 21, 77])
+@pytest.mark.parametrize("chunk", [64, 256])
+def test_mixed_precision_pair(gpu_lib, seed, chunk):
+    dpt = gpu_lib
+    d, P, trk, ref = _pair_setup(dpt, seed=seed, n=1500, precision=dpt.PREC_MIXED, launch=(2, chunk))
+    g = trk.track(np.eye(4))
+    o = ref.track(d["cur"], np.eye(4))
+    rot, tr, rel = _compare(g, o)
+    print(f"mixed seed {seed} chunk {chunk}: rot {rot:.2e} rad, trans {tr:.2e} m, cost {rel:.2e}")
+    assert g["status"] == o["status"] == 0
+    assert rot < MIXED_ROT_TOL and tr < MIXED_TR_TOL and rel < 5e-3
+
+
+def test_mixed_precision_identity(gpu_lib):
+    dpt = gpu_lib
+    d, P, trk, ref = _pair_setup(dpt, precision=dpt.PREC_MIXED, launch=(2, 256))
+    trk.build_pyramid(dpt.SLOT_CUR, d["ref"])
+    g = trk.track(np.eye(4))
+    rot, tr = oracle.pose_error(g["T_cw"], np.eye(4))
+    assert rot < 1e-6 and tr < 1e-6 and g["status"] == 0
+
+
+def test_mixed_precision_stress_16k(gpu_lib):
+    """1280x720, 16000 points, 4 levels: accumulation stress of the mixed variant."""
+    dpt = gpu_lib
+    cam = synth.CAM_1280
+    d, P, trk, ref = _pair_setup(dpt, seed=5, n=16000, levels=4, cam=cam, precision=dpt.PREC_MIXED,
+                                 launch=(2, 256))
+    g = trk.track(np.eye(4))
+    o = ref.track(d["cur"], np.eye(4))
+    rot, tr, rel = _compare(g, o)
+    print(f"mixed 16k: rot {rot:.2e} rad, trans {tr:.2e} m, cost {rel:.2e}")
+    assert g["status"] == o["status"] == 0
+    assert rot < MIXED_ROT_TOL and tr < MIXED_TR_TOL and rel < 5e-3
+    trk32, _ = _tracker(dpt, cam, 16000, levels=4)
+    trk32.set_launch_config(2, 256)
+    trk32.build_pyramid(dpt.SLOT_REF, d["ref"])
+    trk32.set_reference_points(P, d["T_rw"])
+    trk32.build_pyramid(dpt.SLOT_CUR, d["cur"])
+    g32 = trk32.track(np.eye(4))
+    rot32, tr32, _ = _compare(g32, o)
+    print(f"fp32 16k: rot {rot32:.2e} rad, trans {tr32:.2e} m")
+    assert rot32 < ROT_TOL and tr32 < TR_TOL
