@@ -182,11 +182,12 @@ def bench_batched_sequences(dpt, synth, n_streams: int, steps: int, warmup: int,
                 stats["samples"].append(sum(r["samples"] for r in res))
                 stats["iters"].extend(r["iterations"] for r in res)
                 stats["status"].extend(r["status"] for r in res)
+        return prev1
 
-    # autotune on the first window's first frame
-    window(0, False)
+    # autotune on the last frame of the first window, started from its estimates
+    last = window(0, False)
     key = autotune.shape_key([CAM] * n_streams, [N_POINTS] * n_streams, LEVELS, 8)
-    mode, chunk, timings = autotune.tune(bt, np.stack([np.eye(4)] * n_streams), key, cache=None)
+    mode, chunk, timings = autotune.tune(bt, np.stack(last), key, cache=None)
     for w in range(warmup):
         window(w % n_win, False)
     bt.set_profiling(True)

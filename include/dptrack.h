@@ -189,6 +189,11 @@ int dpt_batch_select_points(dpt_batch* b, int32_t s, int32_t n, int32_t margin, 
 int dpt_batch_set_reference_points(dpt_batch* b, int32_t s, const float* xyz_world, int32_t n, const double T_rw[16],
                                    int32_t xyz_on_device);
 
+/* Copy pyramid level `level` of slot `slot` of every stream, packed, into dst:
+ * stream s's level at dst + s * W_l * H_l (all streams must have the same
+ * level size).  dst in device memory if dst_on_device, else host. */
+int dpt_batch_get_level(dpt_batch* b, int32_t slot, int32_t level, uint8_t* dst, int32_t dst_on_device);
+
 /* Track every stream's CUR pyramid.  T_cw_init: n_streams row-major 4x4
  * doubles; out: n_streams results.  Synchronises the stream. */
 int dpt_batch_track(dpt_batch* b, const double* T_cw_init, dpt_result* out);
@@ -200,6 +205,45 @@ int dpt_batch_set_launch_config(dpt_batch* b, int32_t mode, int32_t chunk);
  * last batched pyramid launch, timed with HIP events on the batch's stream. */
 int dpt_batch_set_profiling(dpt_batch* b, int32_t enable);
 int dpt_batch_last_kernel_ms(dpt_batch* b, float* pyramid_ms, float* track_ms);
+
+/* ------------------------------------------------------------------ learned initialiser
+ * A small CNN proposes the reference-to-current twist from the coarsest pyramid
+ * pair, as the start pose of the coarse-to-fine Gauss-Newton track (which the
+ * paper starts from the previous estimate, Sec. II and Sec. III-A).  Not in the
+ * paper.  Input: the reference and current levels of size 94 x 60, (I - 128)/64.
+ * Network: conv 3x3 stride 2 pad 1 + ReLU, 2-16-32-64-64 channels; global
+ * average pool; FC 64-64 + ReLU; FC 64-6.  Output: the twist (omega, v) divided
+ * by (5 deg x3, 0.1 m x3).  BF16 activations and conv weights, FP32 master
+ * weights, matrix-core (MFMA) forward convolutions with FP32 accumulation.
+ * Parameters (dpt_cnn_num_params() floats) in tensor order w1 b1 w2 b2 w3 b3 w4
+ * b4 fw1 fb1 fw2 fb2, conv weights [co][ci][ky][kx], FC weights [out][in]. */
+typedef struct dpt_cnn dpt_cnn;
+
+int32_t dpt_cnn_num_params(void);
+/* max_batch: 1..65536 pairs per call.  Parameters start at zero: set them. */
+int dpt_cnn_create(int32_t max_batch, void* hip_stream, dpt_cnn** out);
+void dpt_cnn_destroy(dpt_cnn* c);
+/* host FP32 parameter vectors; set also resets the Adam state */
+int dpt_cnn_set_params(dpt_cnn* c, const float* params);
+int dpt_cnn_get_params(dpt_cnn* c, float* params);
+/* gradients of the last training step, same layout */
+int dpt_cnn_get_grads(dpt_cnn* c, float* grads);
+/* pairs: B x 2 x 60 x 94 uint8 (reference plane, then current), device memory
+ * if on_device.  out_host: B x 6 normalised twists. */
+int dpt_cnn_forward(dpt_cnn* c, const uint8_t* pairs, int32_t B, int32_t on_device, float* out_host);
+/* One step: forward, mean squared error against targets (B x 6 normalised
+ * twists, same memory side as pairs), backward, Adam (beta 0.9/0.999, eps 1e-8)
+ * with learning rate lr (lr == 0: gradients only).  *loss_out: the loss. */
+int dpt_cnn_train_step(dpt_cnn* c, const uint8_t* pairs, const float* targets, int32_t B, float lr,
+                       int32_t on_device, float* loss_out);
+/* Test hook: activation of layer l = 1..4 of the last forward (FP32, NHWC), or the
+ * network outputs for l = 5. */
+int dpt_cnn_get_activation(dpt_cnn* c, int32_t l, int32_t B, float* host_out);
+/* Start poses from the network for a single-stream context / every stream of a
+ * batch: the REF and CUR pyramids' level (levels-1) must be 94 x 60.  Writes
+ * T_cw = exp(xi) T_rw (4x4 row-major doubles per stream). */
+int dpt_cnn_predict(dpt_cnn* c, dpt_ctx* ctx, double T_cw_out[16]);
+int dpt_cnn_predict_batch(dpt_cnn* c, dpt_batch* b, double* T_cw_out);
 
 #ifdef __cplusplus
 }

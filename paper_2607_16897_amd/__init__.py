@@ -83,6 +83,18 @@ SIGNATURES = {
     "dpt_batch_set_launch_config": (ctypes.c_int, [_vp, _i32, _i32]),
     "dpt_batch_set_profiling": (ctypes.c_int, [_vp, _i32]),
     "dpt_batch_last_kernel_ms": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
+    "dpt_batch_get_level": (ctypes.c_int, [_vp, _i32, _i32, _vp, _i32]),
+    "dpt_cnn_num_params": (_i32, []),
+    "dpt_cnn_create": (ctypes.c_int, [_i32, _vp, ctypes.POINTER(_vp)]),
+    "dpt_cnn_destroy": (None, [_vp]),
+    "dpt_cnn_set_params": (ctypes.c_int, [_vp, _vp]),
+    "dpt_cnn_get_params": (ctypes.c_int, [_vp, _vp]),
+    "dpt_cnn_get_grads": (ctypes.c_int, [_vp, _vp]),
+    "dpt_cnn_forward": (ctypes.c_int, [_vp, _vp, _i32, _i32, _vp]),
+    "dpt_cnn_train_step": (ctypes.c_int, [_vp, _vp, _vp, _i32, ctypes.c_float, _i32, ctypes.POINTER(ctypes.c_float)]),
+    "dpt_cnn_get_activation": (ctypes.c_int, [_vp, _i32, _i32, _vp]),
+    "dpt_cnn_predict": (ctypes.c_int, [_vp, _vp, _vp]),
+    "dpt_cnn_predict_batch": (ctypes.c_int, [_vp, _vp, _vp]),
     "dpt_last_kernel_ms": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
 }
 
@@ -288,6 +300,18 @@ class BatchTracker:
     def set_launch_config(self, mode: int, chunk: int = 256):
         _check(self._lib.dpt_batch_set_launch_config(self._h, mode, chunk))
 
+    def get_level(self, slot: int, level: int, dst=None):
+        """Pyramid level of every stream, packed [n][H_l][W_l]: into `dst` (a torch CUDA
+        tensor) on the device, else returned as a NumPy array."""
+        h, w = self.cams[0].height >> level, self.cams[0].width >> level
+        if dst is None:
+            out = np.empty((self.n, h, w), np.uint8)
+            _check(self._lib.dpt_batch_get_level(self._h, slot, level, out.ctypes.data, 0))
+            return out
+        assert dst.is_cuda and dst.is_contiguous() and dst.numel() == self.n * h * w
+        _check(self._lib.dpt_batch_get_level(self._h, slot, level, dst.data_ptr(), 1))
+        return dst
+
     def set_profiling(self, enable: bool = True):
         _check(self._lib.dpt_batch_set_profiling(self._h, int(enable)))
 
@@ -295,3 +319,95 @@ class BatchTracker:
         a, b = ctypes.c_float(), ctypes.c_float()
         _check(self._lib.dpt_batch_last_kernel_ms(self._h, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
+
+
+CNN_TWIST_SCALE = np.array([np.deg2rad(5.0)] * 3 + [0.1] * 3)
+CNN_SHAPES = (("w1", (16, 2, 3, 3)), ("b1", (16,)), ("w2", (32, 16, 3, 3)), ("b2", (32,)), ("w3", (64, 32, 3, 3)),
+              ("b3", (64,)), ("w4", (64, 64, 3, 3)), ("b4", (64,)), ("fw1", (64, 64)), ("fb1", (64,)),
+              ("fw2", (6, 64)), ("fb2", (6,)))
+
+
+def cnn_flatten(params: dict) -> np.ndarray:
+    return np.concatenate([np.asarray(params[k], np.float32).reshape(-1) for k, _ in CNN_SHAPES])
+
+
+def cnn_unflatten(flat: np.ndarray) -> dict:
+    out, o = {}, 0
+    for k, shp in CNN_SHAPES:
+        n = int(np.prod(shp))
+        out[k] = flat[o:o + n].reshape(shp)
+        o += n
+    return out
+
+
+class Cnn:
+    """The learned start-pose network (BF16 MFMA forward, FP32 master weights)."""
+
+    def __init__(self, max_batch: int = 256, stream: int | None = None):
+        self._lib = load()
+        self.n_params = int(self._lib.dpt_cnn_num_params())
+        self.stream = current_stream() if stream is None else stream
+        h = _vp()
+        _check(self._lib.dpt_cnn_create(max_batch, self.stream, ctypes.byref(h)))
+        self._h = h
+        self.max_batch = max_batch
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.dpt_cnn_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def set_params(self, params):
+        flat = cnn_flatten(params) if isinstance(params, dict) else np.ascontiguousarray(params, np.float32)
+        assert flat.size == self.n_params
+        _check(self._lib.dpt_cnn_set_params(self._h, flat.ctypes.data))
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.n_params, np.float32)
+        _check(self._lib.dpt_cnn_get_params(self._h, out.ctypes.data))
+        return out
+
+    def get_grads(self) -> np.ndarray:
+        out = np.empty(self.n_params, np.float32)
+        _check(self._lib.dpt_cnn_get_grads(self._h, out.ctypes.data))
+        return out
+
+    def forward(self, pairs) -> np.ndarray:
+        """pairs: (B, 2, 60, 94) uint8, NumPy (host) or torch CUDA tensor."""
+        p, dev, keep = _ptr(pairs)
+        B = int(pairs.shape[0])
+        out = np.empty((B, 6), np.float32)
+        _check(self._lib.dpt_cnn_forward(self._h, p, B, dev, out.ctypes.data))
+        return out
+
+    def train_step(self, pairs, targets, lr: float) -> float:
+        p, dev, keep = _ptr(pairs)
+        if dev:
+            import torch
+
+            targets = torch.as_tensor(targets, dtype=torch.float32, device=pairs.device).contiguous()
+        else:
+            targets = np.ascontiguousarray(targets, np.float32)
+        t, tdev, keep2 = _ptr(targets)
+        assert tdev == dev
+        loss = ctypes.c_float()
+        _check(self._lib.dpt_cnn_train_step(self._h, p, t, int(pairs.shape[0]), float(lr), dev, ctypes.byref(loss)))
+        return loss.value
+
+    def activation(self, layer: int, B: int) -> np.ndarray:
+        shapes = {1: (30, 47, 16), 2: (15, 24, 32), 3: (8, 12, 64), 4: (4, 6, 64), 5: (6,)}
+        out = np.empty((B,) + shapes[layer], np.float32)
+        _check(self._lib.dpt_cnn_get_activation(self._h, layer, B, out.ctypes.data))
+        return out
+
+    def predict(self, tracker) -> np.ndarray:
+        """Start pose(s) T_cw from a Tracker (4x4) or a BatchTracker (n x 4 x 4)."""
+        if isinstance(tracker, BatchTracker):
+            T = np.empty((tracker.n, 16))
+            _check(self._lib.dpt_cnn_predict_batch(self._h, tracker._h, T.ctypes.data))
+            return T.reshape(-1, 4, 4)
+        T = np.empty(16)
+        _check(self._lib.dpt_cnn_predict(self._h, tracker._h, T.ctypes.data))
+        return T.reshape(4, 4)

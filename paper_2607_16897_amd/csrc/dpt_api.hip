@@ -111,6 +111,11 @@ Pattern make_pattern(const dpt_params* p) {
 
 }  // namespace
 
+int dpt::set_error(int code, const char* msg) {
+  g_err = msg;
+  return code;
+}
+
 struct dpt_ctx {
   dpt_camera cam;
   dpt_params prm;
@@ -848,3 +853,99 @@ int dpt_batch_last_kernel_ms(dpt_batch* b, float* pyramid_ms, float* track_ms) {
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ learned initialiser (tracker side)
+
+namespace {
+
+// exp of a twist (omega, v) as a 4x4 rigid transform (FP64), for the CNN's start pose
+void twist_exp(const double* xi, double* T) {
+  const double* w = xi;
+  const double* v = xi + 3;
+  const double th2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2], th = std::sqrt(th2);
+  double A, B, C;
+  if (th < 1e-4) {
+    A = 1.0 - th2 / 6.0;
+    B = 0.5 - th2 / 24.0;
+    C = 1.0 / 6.0 - th2 / 120.0;
+  } else {
+    A = std::sin(th) / th;
+    B = (1.0 - std::cos(th)) / th2;
+    C = (th - std::sin(th)) / (th2 * th);
+  }
+  const double W[3][3] = {{0, -w[2], w[1]}, {w[2], 0, -w[0]}, {-w[1], w[0], 0}};
+  for (int r = 0; r < 3; ++r) {
+    double tv = 0;
+    for (int c = 0; c < 3; ++c) {
+      const double W2 = W[r][0] * W[0][c] + W[r][1] * W[1][c] + W[r][2] * W[2][c];
+      const double id = r == c ? 1.0 : 0.0;
+      T[4 * r + c] = id + A * W[r][c] + B * W2;
+      tv += (id + B * W[r][c] + C * W2) * v[c];
+    }
+    T[4 * r + 3] = tv;
+  }
+  T[12] = T[13] = T[14] = 0.0;
+  T[15] = 1.0;
+}
+
+constexpr double kTwistScale[6] = {0.08726646259971647, 0.08726646259971647, 0.08726646259971647, 0.1, 0.1, 0.1};
+
+int predict_streams(dpt_cnn* cnn, dpt_ctx* const* ctxs, int n, double* T_out) {
+  std::vector<const uint8_t*> refs(n), curs(n);
+  for (int s = 0; s < n; ++s) {
+    dpt_ctx* c = ctxs[s];
+    const int L = c->prm.levels - 1;
+    if (c->lv[L].W != 94 || c->lv[L].H != 60) return fail(DPT_E_ARG, "stream %d: coarsest level is not 94 x 60", s);
+    if (!c->have_pyr[DPT_SLOT_REF] || !c->have_pyr[DPT_SLOT_CUR] || !c->have_ref)
+      return fail(DPT_E_STATE, "stream %d: pyramids or reference missing", s);
+    refs[s] = c->pyr[DPT_SLOT_REF] + c->lv[L].off;
+    curs[s] = c->pyr[DPT_SLOT_CUR] + c->lv[L].off;
+  }
+  std::vector<float> out(6 * (size_t)n);
+  int e = cnn_forward_levels(cnn, refs.data(), curs.data(), n, out.data());
+  if (e != DPT_OK) return e;
+  for (int s = 0; s < n; ++s) {
+    double xi[6], Trel[16];
+    for (int j = 0; j < 6; ++j) xi[j] = (double)out[6 * s + j] * kTwistScale[j];
+    twist_exp(xi, Trel);
+    compose(Trel, ctxs[s]->T_rw, T_out + 16 * s);
+  }
+  return DPT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dpt_cnn_predict(dpt_cnn* cnn, dpt_ctx* c, double T_cw_out[16]) {
+  g_err.clear();
+  if (!cnn || !c || !T_cw_out) return fail(DPT_E_ARG, "NULL argument");
+  return predict_streams(cnn, &c, 1, T_cw_out);
+}
+
+int dpt_cnn_predict_batch(dpt_cnn* cnn, dpt_batch* b, double* T_cw_out) {
+  g_err.clear();
+  if (!cnn || !b || !T_cw_out) return fail(DPT_E_ARG, "NULL argument");
+  return predict_streams(cnn, b->ctx.data(), b->n, T_cw_out);
+}
+
+}  // extern "C"
+
+extern "C" int dpt_batch_get_level(dpt_batch* b, int32_t slot, int32_t level, uint8_t* dst, int32_t dst_on_device) {
+  g_err.clear();
+  if (!b || !dst) return fail(DPT_E_ARG, "NULL argument");
+  if (slot != DPT_SLOT_REF && slot != DPT_SLOT_CUR) return fail(DPT_E_ARG, "slot %d", slot);
+  if (level < 0 || level >= b->ctx[0]->prm.levels) return fail(DPT_E_ARG, "level %d", level);
+  const LevelGeom& g0 = b->ctx[0]->lv[level];
+  const size_t bytes = (size_t)g0.W * g0.H;
+  for (int s = 0; s < b->n; ++s) {
+    const dpt_ctx* c = b->ctx[s];
+    if (c->lv[level].W != g0.W || c->lv[level].H != g0.H) return fail(DPT_E_ARG, "level sizes differ across streams");
+    if (!c->have_pyr[slot]) return fail(DPT_E_STATE, "stream %d has no pyramid in slot %d", s, slot);
+  }
+  for (int s = 0; s < b->n; ++s)
+    HIP_TRY(hipMemcpyAsync(dst + s * bytes, b->ctx[s]->pyr[slot] + g0.off, bytes,
+                           dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  return DPT_OK;
+}

@@ -147,36 +147,50 @@ __device__ __forceinline__ int block_exclusive_scan(int x, int* wsum, int* total
   return base + inc - x;
 }
 
-// Sum 32 per-lane values over a wave64 by recursive halving: at each xor step
-// a lane keeps half of its values and receives the partner's matching half, so
-// 16 + 8 + 4 + 2 + 1 + 1 shuffles replace 32 x 6.  Lane l ends up holding the
-// wave total of value (l >> 1).  The order of additions is fixed.
-__device__ __forceinline__ float wave_reduce32(float (&a)[32]) {
-  const int lane = threadIdx.x & 63;
+// Row rotation within 16 lanes (DPP row_ror:K), a VALU operand modifier.
+template <int K>
+__device__ __forceinline__ float dpp_ror(float v) {
+  return __uint_as_float(__builtin_amdgcn_update_dpp(0u, __float_as_uint(v), 0x120 + K, 0xf, 0xf, false));
+}
+
+// Sum 32 per-lane values over a wave64.  Two halving steps exchange whole
+// half-waves with the gfx950 lane-swap instructions: v_permlane32_swap pairs
+// lane L with L ^ 32 and v_permlane16_swap pairs L with L ^ 16, each lane keeping
+// half of its values, so 16 + 8 swaps leave 8 values per lane summed over 4
+// lanes.  DPP row rotations then sum each over the 16 lanes of a row.  On return
+// a[j] of every lane in row r = lane / 16 holds the wave total of value 8 r + j.
+// No shuffle through LDS and no data-dependent indexing; fixed addition order.
+__device__ __forceinline__ void wave_reduce32(float (&a)[32]) {
 #pragma unroll
-  for (int step = 0; step < 5; ++step) {
-    const int half = 16 >> step;        // values kept after this step
-    const int mask = 32 >> step;        // partner lane distance
-    const bool upper = (lane & mask) != 0;
-#pragma unroll
-    for (int j = 0; j < half; ++j) {
-      float keep = upper ? a[j + half] : a[j];
-      float send = upper ? a[j] : a[j + half];
-      float recv = __shfl_xor(send, mask, 64);
-      a[j] = keep + recv;
-    }
+  for (int j = 0; j < 16; ++j) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a[j]), __float_as_uint(a[j + 16]), false, false);
+    a[j] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
   }
-  float v = a[0];
-  v += __shfl_xor(v, 1, 64);
-  return v;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a[j]), __float_as_uint(a[j + 8]), false, false);
+    a[j] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    float v = a[j];
+    v += dpp_ror<8>(v);
+    v += dpp_ror<4>(v);
+    v += dpp_ror<2>(v);
+    v += dpp_ror<1>(v);
+    a[j] = v;
+  }
 }
 
 // Workgroup total of 32 per-lane values into out[32] (LDS), fixed order.
 // `scratch` is 16 x 32 floats of LDS.
 __device__ __forceinline__ void block_reduce32(float (&a)[32], float* scratch, float* out) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  float v = wave_reduce32(a);
-  if ((lane & 1) == 0) scratch[wave * 32 + (lane >> 1)] = v;
+  wave_reduce32(a);
+  if ((lane & 15) == 0) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) scratch[wave * 32 + 8 * (lane >> 4) + j] = a[j];
+  }
   __syncthreads();
   if (threadIdx.x < 32) {
     float s = 0.0f;
@@ -189,8 +203,11 @@ __device__ __forceinline__ void block_reduce32(float (&a)[32], float* scratch, f
 // As block_reduce32, with Kahan-compensated summation across the waves.
 __device__ __forceinline__ void block_reduce32_kahan(float (&a)[32], float* scratch, float* out) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  float v = wave_reduce32(a);
-  if ((lane & 1) == 0) scratch[wave * 32 + (lane >> 1)] = v;
+  wave_reduce32(a);
+  if ((lane & 15) == 0) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) scratch[wave * 32 + 8 * (lane >> 4) + j] = a[j];
+  }
   __syncthreads();
   if (threadIdx.x < 32) {
     float s = 0.0f, c = 0.0f;
@@ -466,20 +483,31 @@ __device__ __forceinline__ void accumulate_point(const TrackArgs& a, const Patte
   float u, v;
   project(g, X, Y, Z, u, v);
   if (!inside(g, pat, u, v)) return;
+  // Phase 1: all 32 bilinear taps of the point are issued before any is used
+  // (one memory round trip per point instead of one per sample).
+  float ta[8], tc[8], t00[8], t10[8], t01[8], t11[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const float x = u + (float)pat.dx[k], y = v + (float)pat.dy[k];
+    const float fx = floorf(x), fy = floorf(y);
+    ta[k] = x - fx;
+    tc[k] = y - fy;
+    const uint8_t* p = img + (int)fy * g.W + (int)fx;
+    t00[k] = p[0], t10[k] = p[1], t01[k] = p[g.W], t11[k] = p[g.W + 1];
+  }
+  // Phase 2: residuals, Huber weights (branch-free) and the point's sums.  The
+  // interpolation repeats bilinear()'s arithmetic exactly.
   float m00 = 0.f, m01 = 0.f, m11 = 0.f, v0 = 0.f, v1 = 0.f, E = 0.f;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    const float Ic = bilinear(img, g.W, u + (float)pat.dx[k], v + (float)pat.dy[k]);
+    const float top = fmaf(ta[k], t10[k] - t00[k], t00[k]);
+    const float bot = fmaf(ta[k], t11[k] - t01[k], t01[k]);
+    const float Ic = fmaf(tc[k], bot - top, top);
     const float r = pr.i0(k) - Ic;
     const float ar = fabsf(r);
-    float w, rho;
-    if (kH > 0.f && ar > kH) {
-      w = kH / ar;
-      rho = kH * (ar - 0.5f * kH);
-    } else {
-      w = 1.0f;
-      rho = 0.5f * r * r;
-    }
+    const bool hub = (kH > 0.f) & (ar > kH);
+    const float w = hub ? kH / ar : 1.0f;
+    const float rho = hub ? kH * (ar - 0.5f * kH) : 0.5f * r * r;
     E += rho;
     if (!COST_ONLY) {
       const float gx = pr.gx(k), gy = pr.gy(k);

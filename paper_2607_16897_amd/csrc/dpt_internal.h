@@ -9,6 +9,8 @@
 #include <algorithm>
 #include <vector>
 
+struct dpt_cnn;
+
 namespace dpt {
 
 constexpr int kMaxLevels = 8;
@@ -141,6 +143,13 @@ struct CoopEngine {
 };
 
 constexpr int kSpinLimit = 1 << 24;  // polls (~64 clocks each) before a chunk reports a timeout
+
+// Record an error message for dpt_last_error() and return `code`.
+int set_error(int code, const char* msg);
+
+// Learned initialiser forward pass on coarsest-level pairs (device pointers).
+int cnn_forward_levels(struct ::dpt_cnn* c, const uint8_t* const* refs, const uint8_t* const* curs, int B,
+                       float* out_host);
 
 // Launchers (kernels.hip, coop.hip).  Each returns the hipError_t of the launch.
 hipError_t launch_pyramid(const uint8_t* src, int64_t pitch, uint8_t* dst, const PyrGeom& g, hipStream_t s);

@@ -258,14 +258,9 @@ __device__ __forceinline__ void accumulate(const TrackArgs& a, const Pattern& pa
       const float tmpl = KT ? i0[k] : I0[(int64_t)i * K + k];
       const float r = tmpl - Ic;
       const float ar = fabsf(r);
-      float w, rho;
-      if (kH > 0.f && ar > kH) {
-        w = kH / ar;
-        rho = kH * (ar - 0.5f * kH);
-      } else {
-        w = 1.0f;
-        rho = 0.5f * r * r;
-      }
+      const bool hub = (kH > 0.f) & (ar > kH);  // branch-free, so the taps of later samples can issue early
+      const float w = hub ? kH / ar : 1.0f;
+      const float rho = hub ? kH * (ar - 0.5f * kH) : 0.5f * r * r;
       E += rho;
       if (!COST_ONLY) {
         const float gx = KT ? gxs[k] : GX[(int64_t)i * K + k];

@@ -36,6 +36,46 @@ def build(force: bool = True) -> str:
     return _LIB_PATH
 
 
+_GPU_LIB_PATH = os.path.join(_HERE, "libsynth_gpu.so")
+_gpu_lib = None
+
+
+def build_gpu(force: bool = True) -> str:
+    """Compile the GPU port of the renderer (training-set generation) for gfx950."""
+    if force or not os.path.exists(_GPU_LIB_PATH):
+        cmd = ["/opt/rocm/bin/hipcc", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+               os.path.join(_HERE, "render_gpu.hip"), "-o", _GPU_LIB_PATH + ".tmp"]
+        subprocess.check_call(cmd, stderr=subprocess.DEVNULL)
+        os.replace(_GPU_LIB_PATH + ".tmp", _GPU_LIB_PATH)
+    return _GPU_LIB_PATH
+
+
+def render_gpu(scene: "Scene", cam: "Camera", poses: np.ndarray, imgs, depths=None, stream: int = 0):
+    """Render len(poses) views of `scene` on the GPU into torch uint8 tensor `imgs`
+    [views, H, W] (and float32 `depths`, optional).  Noiseless."""
+    global _gpu_lib
+    if _gpu_lib is None:
+        build_gpu(force=False)
+        _gpu_lib = ctypes.CDLL(_GPU_LIB_PATH)
+        _gpu_lib.syn_gpu_render.restype = ctypes.c_int
+        dp = ctypes.POINTER(ctypes.c_double)
+        _gpu_lib.syn_gpu_render.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                            ctypes.c_double, ctypes.c_double, dp, ctypes.c_int32, ctypes.c_int32,
+                                            dp, dp, ctypes.c_uint64, ctypes.c_double, ctypes.c_double,
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    P = np.ascontiguousarray(np.asarray(poses, np.float64).reshape(-1, 16))
+    assert tuple(imgs.shape) == (len(P), cam.height, cam.width) and imgs.is_contiguous()
+    dp = ctypes.POINTER(ctypes.c_double)
+    rc = _gpu_lib.syn_gpu_render(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy, P.ctypes.data_as(dp), len(P),
+                                 scene.blobs.shape[1], scene.blobs.ctypes.data_as(dp),
+                                 np.ascontiguousarray(_WINDOWS).ctypes.data_as(dp), scene.noise_seed,
+                                 scene.noise_amp, scene.noise_cell, imgs.data_ptr(),
+                                 depths.data_ptr() if depths is not None else None, stream)
+    if rc != 0:
+        raise RuntimeError(f"GPU render failed ({rc})")
+
+
 def _load():
     global _lib
     if _lib is None:
