@@ -138,6 +138,7 @@ struct dpt_ctx {
   double T_rw[16];
   int32_t* sel_idx = nullptr;
   int32_t* sel_count = nullptr;
+  int32_t* sel_scratch = nullptr;
   TrackOut* d_out = nullptr;
   TrackOut* h_out = nullptr;  // pinned
   float* d_tot = nullptr;
@@ -154,7 +155,7 @@ struct dpt_ctx {
     for (hipEvent_t e : ev)
       if (e) (void)hipEventDestroy(e);
     for (void* p : {(void*)pyr[0], (void*)pyr[1], (void*)staging, (void*)x0, (void*)valid, (void*)I0, (void*)gx,
-                    (void*)gy, (void*)I0h, (void*)gh, (void*)pts, (void*)sel_idx, (void*)sel_count, (void*)d_out,
+                    (void*)gy, (void*)I0h, (void*)gh, (void*)pts, (void*)sel_idx, (void*)sel_count, (void*)sel_scratch, (void*)d_out,
                     (void*)d_tot})
       if (p) (void)hipFree(p);
     if (h_out) (void)hipHostFree(h_out);
@@ -261,7 +262,8 @@ int dpt_create(const dpt_camera* cam, const dpt_params* prm, int32_t max_points,
       (e = dev_alloc((void**)&c->gy, L * cap * K * sizeof(float))) ||
       (e = dev_alloc((void**)&c->pts, cap * 3 * sizeof(float))) ||
       (e = dev_alloc((void**)&c->sel_idx, (size_t)cam->width * cam->height * sizeof(int32_t))) ||
-      (e = dev_alloc((void**)&c->sel_count, sizeof(int32_t))) || (e = dev_alloc((void**)&c->d_out, sizeof(TrackOut))) ||
+      (e = dev_alloc((void**)&c->sel_count, sizeof(int32_t))) ||
+      (e = dev_alloc((void**)&c->sel_scratch, sizeof(int32_t) * select_scratch_ints(cam->width, cam->height))) || (e = dev_alloc((void**)&c->d_out, sizeof(TrackOut))) ||
       (e = dev_alloc((void**)&c->d_tot, kRedSlots * sizeof(float)))) {
     delete c;
     return e;
@@ -332,6 +334,7 @@ int dpt_select_points(dpt_ctx* c, int32_t n, int32_t margin, int32_t* host_idx, 
   if (margin < 1 || 2 * margin >= c->cam.width || 2 * margin >= c->cam.height) return fail(DPT_E_ARG, "margin %d", margin);
   if (!c->have_pyr[DPT_SLOT_REF]) return fail(DPT_E_STATE, "no reference pyramid");
   HIP_TRY(launch_select(c->pyr[DPT_SLOT_REF], c->cam.width, c->cam.height, margin, n, c->sel_idx, c->sel_count,
+                        c->sel_scratch,
                         c->stream));
   int32_t cnt = 0;
   HIP_TRY(hipMemcpyAsync(&cnt, c->sel_count, sizeof cnt, hipMemcpyDeviceToHost, c->stream));

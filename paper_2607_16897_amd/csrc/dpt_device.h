@@ -229,8 +229,12 @@ __host__ __device__ constexpr int tri(int i, int j) { return i * 6 - (i * (i - 1
 // FP32 and apply T <- T exp(-delta).  Returns 0, or 1 if a pivot is <= 1e-6 of
 // the largest diagonal entry (not positive definite).  Every loop is unrolled
 // so the factor lives in registers.
-__device__ __forceinline__ int solve_update(const float* tot, float* T, float* max_step) {
+__device__ __forceinline__ int solve_update(const float* tot_lds, float* T, float* max_step) {
+  float tot[27];  // one batch of LDS reads, then registers only
+#pragma unroll
+  for (int q = 0; q < 27; ++q) tot[q] = tot_lds[q];
   float L[21];  // L(i, j), i >= j, stored at tri(j, i)
+  float invd[6];
   float dmax = 0.f;
 #pragma unroll
   for (int j = 0; j < 6; ++j) dmax = fmaxf(dmax, tot[tri(j, j)]);
@@ -245,6 +249,7 @@ __device__ __forceinline__ int solve_update(const float* tot, float* T, float* m
     const float d = sqrtf(s);
     L[tri(j, j)] = d;
     const float inv = 1.0f / d;
+    invd[j] = inv;
 #pragma unroll
     for (int i = j + 1; i < 6; ++i) {
       float t = tot[tri(j, i)];
@@ -260,14 +265,14 @@ __device__ __forceinline__ int solve_update(const float* tot, float* T, float* m
     float s = tot[kSlotB + i];
 #pragma unroll
     for (int k = 0; k < i; ++k) s = fmaf(-L[tri(k, i)], y[k], s);
-    y[i] = s / L[tri(i, i)];
+    y[i] = s * invd[i];
   }
 #pragma unroll
   for (int i = 5; i >= 0; --i) {
     float s = y[i];
 #pragma unroll
     for (int k = i + 1; k < 6; ++k) s = fmaf(-L[tri(i, k)], d[k], s);
-    d[i] = s / L[tri(i, i)];
+    d[i] = s * invd[i];
   }
   float m = 0.f;
 #pragma unroll
@@ -317,8 +322,11 @@ __device__ __forceinline__ int solve_update(const float* tot, float* T, float* m
 
 // FP64 variant of solve_update: Cholesky solve (pivot <= 1e-12 of the largest
 // diagonal entry: not positive definite) and T <- T exp(-delta), pose in FP64.
-__device__ __forceinline__ int solve_update_d(const float* tot, double* T, double* max_step) {
-  double L[21];
+__device__ __forceinline__ int solve_update_d(const float* tot_lds, double* T, double* max_step) {
+  float tot[27];
+#pragma unroll
+  for (int q = 0; q < 27; ++q) tot[q] = tot_lds[q];
+  double L[21], invd[6];
   double dmax = 0.0;
 #pragma unroll
   for (int j = 0; j < 6; ++j) dmax = fmax(dmax, (double)tot[tri(j, j)]);
@@ -333,6 +341,7 @@ __device__ __forceinline__ int solve_update_d(const float* tot, double* T, doubl
     const double d = sqrt(s);
     L[tri(j, j)] = d;
     const double inv = 1.0 / d;
+    invd[j] = inv;
 #pragma unroll
     for (int i = j + 1; i < 6; ++i) {
       double t = tot[tri(j, i)];
@@ -348,14 +357,14 @@ __device__ __forceinline__ int solve_update_d(const float* tot, double* T, doubl
     double s = tot[kSlotB + i];
 #pragma unroll
     for (int k = 0; k < i; ++k) s = fma(-L[tri(k, i)], y[k], s);
-    y[i] = s / L[tri(i, i)];
+    y[i] = s * invd[i];
   }
 #pragma unroll
   for (int i = 5; i >= 0; --i) {
     double s = y[i];
 #pragma unroll
     for (int k = i + 1; k < 6; ++k) s = fma(-L[tri(i, k)], d[k], s);
-    d[i] = s / L[tri(i, i)];
+    d[i] = s * invd[i];
   }
   double m = 0.0;
 #pragma unroll
@@ -506,7 +515,7 @@ __device__ __forceinline__ void accumulate_point(const TrackArgs& a, const Patte
     const float r = pr.i0(k) - Ic;
     const float ar = fabsf(r);
     const bool hub = (kH > 0.f) & (ar > kH);
-    const float w = hub ? kH / ar : 1.0f;
+    const float w = hub ? kH * __builtin_amdgcn_rcpf(ar) : 1.0f;  // v_rcp_f32, 1 ulp
     const float rho = hub ? kH * (ar - 0.5f * kH) : 0.5f * r * r;
     E += rho;
     if (!COST_ONLY) {

@@ -153,8 +153,10 @@ int cnn_forward_levels(struct ::dpt_cnn* c, const uint8_t* const* refs, const ui
 
 // Launchers (kernels.hip, coop.hip).  Each returns the hipError_t of the launch.
 hipError_t launch_pyramid(const uint8_t* src, int64_t pitch, uint8_t* dst, const PyrGeom& g, hipStream_t s);
+// Point selection; `scratch` holds select_scratch_ints(W, H) ints of device memory.
+int64_t select_scratch_ints(int32_t W, int32_t H);
 hipError_t launch_select(const uint8_t* img, int32_t W, int32_t H, int32_t margin, int32_t n, int32_t* idx,
-                         int32_t* count, hipStream_t s);
+                         int32_t* count, int32_t* scratch, hipStream_t s);
 hipError_t launch_precompute(const PrecomputeArgs& a, hipStream_t s);
 hipError_t launch_track(const TrackArgs& a, hipStream_t s);
 // One workgroup per frame; batch[b] describes frame b (device memory).

@@ -35,129 +35,6 @@ hipError_t launch_pyramid(const uint8_t* src, int64_t pitch, uint8_t* dst, const
   return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- point selection
-
-__device__ __forceinline__ int sel_score(const uint8_t* img, int W, int x, int y) {
-  const uint8_t* p = img + y * W + x;
-  int dx = (int)p[1] - (int)p[-1];
-  int dy = (int)p[W] - (int)p[-W];
-  return dx * dx + dy * dy;
-}
-
-// Top-n candidates by (score desc, index asc), written in ascending index order.
-// One 1024-thread workgroup: a 256-bin histogram of score >> 9 finds the coarse
-// bucket of the n-th score, a 512-bin histogram of its low bits the exact
-// threshold; an ordered compaction then keeps every score above the threshold
-// and the first `need` ties in index order.  Scores are at most 2 * 255^2.
-constexpr int kSelPPT = 8;
-
-__global__ __launch_bounds__(1024) void select_kernel(const uint8_t* __restrict__ img, int W, int H, int m, int n,
-                                                      int32_t* __restrict__ idx, int32_t* __restrict__ count) {
-  __shared__ int hist[512];
-  __shared__ int wsum[16];
-  __shared__ int sh_T, sh_need;
-  const int Wc = W - 2 * m, Hc = H - 2 * m;
-  const int C = (Wc > 0 && Hc > 0) ? Wc * Hc : 0;
-  const int tid = threadIdx.x;
-  if (C <= n) {
-    if (tid == 0) {
-      sh_T = -1;
-      sh_need = 0;
-    }
-  } else {
-    for (int b = tid; b < 512; b += blockDim.x) hist[b] = 0;
-    __syncthreads();
-    for (int c = tid; c < C; c += blockDim.x) {
-      int y = m + c / Wc, x = m + c % Wc;
-      atomicAdd(&hist[sel_score(img, W, x, y) >> 9], 1);
-    }
-    __syncthreads();
-    __shared__ int sh_B, sh_cum;
-    if (tid == 0) {
-      int cum = 0, B = 0;
-      for (int b = 255; b >= 0; --b) {
-        if (cum + hist[b] >= n) {
-          B = b;
-          break;
-        }
-        cum += hist[b];
-      }
-      sh_B = B;
-      sh_cum = cum;
-    }
-    __syncthreads();
-    for (int b = tid; b < 512; b += blockDim.x) hist[b] = 0;
-    __syncthreads();
-    const int B = sh_B;
-    for (int c = tid; c < C; c += blockDim.x) {
-      int y = m + c / Wc, x = m + c % Wc;
-      int s = sel_score(img, W, x, y);
-      if ((s >> 9) == B) atomicAdd(&hist[s & 511], 1);
-    }
-    __syncthreads();
-    if (tid == 0) {
-      int cum = sh_cum, T = B * 512, need = 0;
-      for (int f = 511; f >= 0; --f) {
-        if (cum + hist[f] >= n) {
-          T = B * 512 + f;
-          need = n - cum;
-          break;
-        }
-        cum += hist[f];
-      }
-      sh_T = T;
-      sh_need = need;
-    }
-  }
-  __syncthreads();
-  const int T = sh_T, need = sh_need;
-  int tie_base = 0, out_base = 0;
-  for (int base = 0; base < C; base += blockDim.x * kSelPPT) {
-    int c0 = base + tid * kSelPPT;
-    int sc[kSelPPT];
-    int eq_local = 0;
-#pragma unroll
-    for (int j = 0; j < kSelPPT; ++j) {
-      int c = c0 + j;
-      sc[j] = -2;
-      if (c < C) {
-        int y = m + c / Wc, x = m + c % Wc;
-        sc[j] = sel_score(img, W, x, y);
-      }
-      eq_local += (sc[j] == T) ? 1 : 0;
-    }
-    int eq_total;
-    int eq_prefix = block_exclusive_scan(eq_local, wsum, &eq_total) + tie_base;
-    bool sel[kSelPPT];
-    int sel_local = 0;
-#pragma unroll
-    for (int j = 0; j < kSelPPT; ++j) {
-      bool is_eq = sc[j] == T;
-      sel[j] = (sc[j] > T) || (is_eq && eq_prefix < need);
-      eq_prefix += is_eq ? 1 : 0;
-      sel_local += sel[j] ? 1 : 0;
-    }
-    int sel_total;
-    int pos = block_exclusive_scan(sel_local, wsum, &sel_total) + out_base;
-#pragma unroll
-    for (int j = 0; j < kSelPPT; ++j) {
-      if (sel[j]) {
-        int c = c0 + j;
-        idx[pos++] = (m + c / Wc) * W + (m + c % Wc);
-      }
-    }
-    tie_base += eq_total;
-    out_base += sel_total;
-  }
-  if (tid == 0) *count = out_base;
-}
-
-hipError_t launch_select(const uint8_t* img, int32_t W, int32_t H, int32_t margin, int32_t n, int32_t* idx,
-                         int32_t* count, hipStream_t s) {
-  hipLaunchKernelGGL(select_kernel, dim3(1), dim3(1024), 0, s, img, W, H, margin, n, idx, count);
-  return hipGetLastError();
-}
-
 // ---------------------------------------------------------------- IC precompute (Eq.(6))
 
 // One lane per (point, pattern sample) and level: x0 = T_rw P, the point's
