@@ -205,3 +205,43 @@ def evaluate(net: Cnn | None, n_streams: int, n_frames: int, seed: int, jerk_deg
                      "frames_per_s": round(fps, 1)}
     out["gt_start_iterations_mean"] = float(its_gt.mean())
     return out
+
+
+def init_params(seed: int = 0) -> np.ndarray:
+    """He-normal conv / FC weights, zero biases, as the flat FP32 parameter vector."""
+    from . import CNN_SHAPES
+
+    rng = np.random.default_rng(seed)
+    out = []
+    for name, shp in CNN_SHAPES:
+        if name.startswith("w"):
+            fan_in = shp[1] * shp[2] * shp[3]
+            out.append(rng.normal(0.0, np.sqrt(2.0 / fan_in), shp))
+        elif name == "fw1":
+            out.append(rng.normal(0.0, np.sqrt(2.0 / shp[1]), shp))
+        elif name == "fw2":
+            out.append(rng.normal(0.0, np.sqrt(1.0 / shp[1]), shp))
+        else:
+            out.append(np.zeros(shp))
+    return np.concatenate([o.reshape(-1) for o in out]).astype(np.float32)
+
+
+def save_checkpoint(path: str, params: np.ndarray, meta: dict):
+    """Flat FP32 parameters (tensor order of CNN_SHAPES) plus a JSON header."""
+    import json
+
+    np.save(path + ".npy", np.asarray(params, np.float32))
+    with open(path + ".json", "w") as f:
+        json.dump(meta, f, indent=1)
+
+
+def load_checkpoint(path: str) -> np.ndarray:
+    return np.load(path + ".npy", allow_pickle=False)
+
+
+def validation_loss(net: Cnn, pairs, targets, batch: int = 256) -> float:
+    errs = []
+    for b0 in range(0, pairs.shape[0], batch):
+        out = net.forward(pairs[b0:b0 + batch].contiguous())
+        errs.append(((out - targets[b0:b0 + batch]) ** 2).reshape(-1))
+    return float(np.mean(np.concatenate(errs)))

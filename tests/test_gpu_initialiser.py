@@ -1,0 +1,73 @@
+"""Training-set pipeline of the learned initialiser on the GPU: the GPU scene
+renderer against the CPU renderer, tracker labels against the true motion,
+and the network's proposals feeding the tracker."""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def test_gpu_renderer_matches_cpu(gpu_lib):
+    import torch
+
+    scene = synth.Scene(42)
+    poses = [np.eye(4), synth.random_perturbation(np.random.default_rng(3), 5.0, 0.1)]
+    imgs = torch.empty((2, 480, 752), dtype=torch.uint8, device="cuda")
+    dep = torch.empty((2, 480, 752), dtype=torch.float32, device="cuda")
+    synth.render_gpu(scene, synth.CAM_752, np.stack(poses), imgs, dep)
+    for v, T in enumerate(poses):
+        cpu, d = scene.render(synth.CAM_752, T)
+        g = imgs[v].cpu().numpy().astype(int)
+        diff = np.abs(g - cpu.astype(int))
+        assert (diff == 0).mean() > 0.999 and diff.max() <= 1
+        np.testing.assert_allclose(dep[v].cpu().numpy(), d, rtol=1e-6)
+
+
+def test_dataset_labels_follow_true_motion(gpu_lib):
+    from paper_2607_16897_amd import initialiser as ini
+    from paper_2607_16897_amd import CNN_TWIST_SCALE
+
+    pairs, targets, st = ini.make_dataset(4, 3, seed=123, streams=4, log=None)
+    assert tuple(pairs.shape) == (12, 2, 60, 94) and st["label_failures"] == 0
+    for r in range(4):  # one group of 4 streams: pair k = c * 4 + r
+        rng = np.random.default_rng([123, r])
+        Tr = ini._reference_pose(rng)
+        for c in range(3):
+            Tc = synth.random_perturbation(rng, 5.0, 0.10) @ Tr
+            true = ini.twist_log(Tc @ np.linalg.inv(Tr)) / CNN_TWIST_SCALE
+            # the tracker's fixed point lies within ~1 mm / 0.05 deg of the rendered motion
+            k = c * 4 + r
+            assert np.abs(targets[k] - true).max() < 0.02, (r, c, targets[k], true)
+
+
+def test_network_proposals_feed_the_tracker(gpu_lib):
+    import torch
+
+    dpt = gpu_lib
+    from paper_2607_16897_amd import initialiser as ini
+
+    net = dpt.Cnn(max_batch=8)
+    net.set_params(ini.init_params(1))
+    res = ini.evaluate(net, 4, 3, seed=9)
+    assert set(res) >= {"cv", "cnn", "gt_start_iterations_mean"}
+    assert 0.0 <= res["cnn"]["failure_rate"] <= 1.0
+
+
+def test_trained_network_beats_constant_velocity(gpu_lib):
+    """The committed network (trained on 200k tracker-labelled pairs) against the
+    constant-velocity prior on held-out scenes: fewer Gauss-Newton iterations and
+    no more failures."""
+    dpt = gpu_lib
+    from paper_2607_16897_amd import initialiser as ini
+
+    path = os.path.join(os.path.dirname(dpt.__file__), "weights", "initialiser")
+    net = dpt.Cnn(max_batch=32)
+    net.set_params(ini.load_checkpoint(path))
+    res = ini.evaluate(net, 16, 20, seed=424242)
+    print(res)
+    assert res["cnn"]["iterations_mean"] < res["cv"]["iterations_mean"]
+    assert res["cnn"]["failure_rate"] <= res["cv"]["failure_rate"]
