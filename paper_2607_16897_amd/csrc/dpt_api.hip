@@ -411,6 +411,7 @@ int run_track(dpt_ctx* c, const double T_cw_init[16], const TrackOut** res) {
     }
     if (c->eng.dirty || c->eng.h_streams[0].a.ref.n != c->n_points) c->eng.set_stream(0, a);
     rel_pose_f32(c, T_cw_init, c->eng.h_T);
+    if (c->eng.dirty) HIP_TRY(c->eng.upload());  // outside the timed region
     if (c->prof) HIP_TRY(hipEventRecord(c->ev[2], c->stream));
     HIP_TRY(c->eng.launch(kSpinLimit));
     if (c->prof) {
@@ -419,7 +420,7 @@ int run_track(dpt_ctx* c, const double T_cw_init[16], const TrackOut** res) {
     }
     HIP_TRY(hipStreamSynchronize(c->stream));
     if (c->eng.h_out[0].status == 4) {
-      (void)c->eng.reset_sync();
+      (void)c->eng.clear_partials();
       (void)hipStreamSynchronize(c->stream);
       return fail(DPT_E_HIP, "cooperative track: chunk synchronisation timed out");
     }
@@ -774,6 +775,8 @@ int dpt_batch_track(dpt_batch* b, const double* T_cw_init, dpt_result* out) {
       const std::vector<int>& ss = b->group_streams[gi];
       for (size_t k = 0; k < ss.size(); ++k) rel_pose_f32(b->ctx[ss[k]], T_cw_init + 16 * ss[k], b->groups[gi]->h_T + 12 * k);
     }
+    for (CoopEngine* g : b->groups)
+      if (g->dirty) HIP_TRY(g->upload());  // outside the timed region
     if (b->prof) HIP_TRY(hipEventRecord(b->ev[2], b->stream));
     for (CoopEngine* g : b->groups) HIP_TRY(g->launch(kSpinLimit));
     if (b->prof) {
@@ -791,7 +794,7 @@ int dpt_batch_track(dpt_batch* b, const double* T_cw_init, dpt_result* out) {
       }
     }
     if (timeout) {
-      for (CoopEngine* g : b->groups) (void)g->reset_sync();
+      for (CoopEngine* g : b->groups) (void)g->clear_partials();
       (void)hipStreamSynchronize(b->stream);
       return fail(DPT_E_HIP, "cooperative batch track: chunk synchronisation timed out");
     }

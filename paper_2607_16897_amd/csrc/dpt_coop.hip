@@ -4,12 +4,17 @@
 // covers every level and iteration of the frame.
 //
 // Per Gauss-Newton iteration the chunks of a stream exchange their 32 partial
-// sums through a double-buffered global array and a stream-local arrival
-// counter.  Each chunk then sums the partials in chunk order and solves the
-// 6x6 system itself: all chunks of a stream compute bitwise-identical poses,
-// so one barrier per iteration suffices and the result is reproducible.
-// Waits are bounded: a chunk that waits longer than `spin_limit` polls gives up
-// and reports a timeout instead of hanging.
+// sums through a double-buffered global array.  Each partial is one 64-bit
+// word holding an epoch tag above the float's bits, so a reader knows from the
+// word alone whether it is current: a chunk publishes its partials and polls
+// the stream's words until every chunk's carry the tag, with no counter, no
+// fence and no second read.  Every chunk then sums the partials in chunk order
+// and every thread solves the 6x6 system itself: all threads of all chunks of
+// a stream compute bitwise-identical poses, so one exchange per iteration
+// suffices and the result is reproducible.  Waits are bounded: a chunk that
+// polls longer than `spin_limit` times gives up and reports a timeout instead
+// of hanging.
+#include <cstring>
 #include <type_traits>
 
 #include "dpt_device.h"
@@ -18,49 +23,91 @@ namespace dpt {
 
 constexpr int kStatusTimeout = 4;
 
-// Publish this chunk's sums for `epoch`, wait for the other chunks of the stream
-// and replace sh_tot with the stream total (fixed chunk order).  Returns false
-// on timeout.
+// Wave 0 only.  Publish this chunk's column sums (`mine`, lanes < 32) under
+// `tag`, wait until all nch chunks of the stream published theirs, and return
+// the stream totals in chunk order (lanes < 32).  False on timeout.
 template <bool KAHAN>
-__device__ __forceinline__ bool stream_sync_sum(float* partials, int* sync, int chunk, int nch, int epoch,
-                                                float* sh_tot, int spin_limit, int* sh_ok) {
-  float* buf = partials + (size_t)(epoch & 1) * nch * 32;
-  const int tid = threadIdx.x;
-  if (tid < 32) buf[chunk * 32 + tid] = sh_tot[tid];
-  if (tid < 64) __threadfence();  // wave 0: make its partial stores visible device-wide
-  if (tid == 0) {
-    atomicAdd(&sync[0], 1);
-    const int target = (epoch + 1) * nch;
-    int ok = 0;
-    for (int t = 0; t < spin_limit; ++t) {
-      if (__hip_atomic_load(&sync[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) {
-        ok = 1;
-        break;
-      }
-      __builtin_amdgcn_s_sleep(1);
-    }
-    *sh_ok = ok;
-  }
-  if (tid < 64) __threadfence();  // acquire the other chunks' partials
-  __syncthreads();
-  const bool ok = *sh_ok != 0;
-  if (ok && tid < 32) {
+__device__ __forceinline__ bool exchange_partials(uint64_t* partials, int chunk, int nch, uint32_t tag, float mine,
+                                                  int spin_limit, float* total) {
+  const int lane = threadIdx.x & 63;
+  uint64_t* buf = partials + (size_t)(tag & 1u) * nch * 32;
+  const uint64_t hi = (uint64_t)tag << 32;
+  if (lane < 32)
+    __hip_atomic_store(&buf[chunk * 32 + lane], hi | __float_as_uint(mine), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  for (int t = 0; t < spin_limit; ++t) {
     float s = 0.0f, comp = 0.0f;
-    for (int c = 0; c < nch; ++c) {
-      const float x = __builtin_nontemporal_load(&buf[c * 32 + tid]);
-      if (KAHAN) {  // compensated sum over the chunks
-        const float y = x - comp;
-        const float t = s + y;
-        comp = (t - s) - y;
-        s = t;
-      } else {
-        s += x;
+    int ok = 1;
+    if (lane < 32) {
+      for (int c0 = 0; c0 < nch; c0 += 8) {
+        uint64_t v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)  // eight loads in flight, then the checks
+          v[j] = c0 + j < nch ? __hip_atomic_load(&buf[(c0 + j) * 32 + lane], __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT)
+                              : hi;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          if (c0 + j >= nch) break;
+          ok &= (uint32_t)(v[j] >> 32) == tag;
+          const float x = __uint_as_float((uint32_t)v[j]);
+          if (KAHAN) {
+            const float y = x - comp;
+            const float u = s + y;
+            comp = (u - s) - y;
+            s = u;
+          } else {
+            s += x;
+          }
+        }
       }
     }
-    sh_tot[tid] = s;
+    if (__all(ok)) {
+      *total = s;
+      return true;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return false;
+}
+
+// Block sum of acc[32] (after each thread accumulated its point), exchanged
+// across the stream's chunks; the totals land in sh_tot.  Returns false on
+// timeout (same value in every thread).
+template <bool KAHAN>
+__device__ __forceinline__ bool stream_total(float (&acc)[32], float* sh_red, float* sh_tot, int* sh_ok,
+                                             uint64_t* partials, int chunk, int nch, uint32_t tag,
+                                             int spin_limit) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  wave_reduce32(acc);
+  if ((lane & 15) == 0) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) sh_red[wave * 32 + 8 * (lane >> 4) + j] = acc[j];
   }
   __syncthreads();
-  return ok;
+  if (wave == 0) {
+    float s = 0.0f, comp = 0.0f;
+    if (lane < 32) {
+      for (int w = 0; w < nw; ++w) {
+        const float x = sh_red[w * 32 + lane];
+        if (KAHAN) {
+          const float y = x - comp;
+          const float u = s + y;
+          comp = (u - s) - y;
+          s = u;
+        } else {
+          s += x;
+        }
+      }
+    }
+    float tot = s;
+    bool ok = true;
+    if (nch > 1) ok = exchange_partials<KAHAN>(partials, chunk, nch, tag, s, spin_limit, &tot);
+    if (lane < 32) sh_tot[lane] = tot;
+    if (lane == 0) *sh_ok = ok ? 1 : 0;
+  }
+  __syncthreads();
+  return *sh_ok != 0;
 }
 
 // MIXED: FP16 reference cache, Kahan-compensated FP32 sums across waves and
@@ -68,15 +115,14 @@ __device__ __forceinline__ bool stream_sync_sum(float* partials, int* sync, int 
 template <int CH, bool MIXED>
 __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __restrict__ streams,
                                                            const int2* __restrict__ work,
-                                                           const double* __restrict__ T_init, int spin_limit) {
+                                                           const double* __restrict__ T_init, uint32_t tag_base,
+                                                           int spin_limit) {
   using PR = typename std::conditional<MIXED, PointRegsH, PointRegs>::type;
   __shared__ CoopStream ss;
-  __shared__ float sh_T[12];
-  __shared__ double sh_Td[12];
+  __shared__ double sh_T0[12];
   __shared__ float sh_tot[32];
   __shared__ float sh_red[(CH / 64) * 32];
-  __shared__ int sh_flag, sh_ok;
-  __shared__ int sh_ipl[kMaxLevels];
+  __shared__ int sh_ok;
   const int2 w = work[blockIdx.x];
   if (w.x < 0) return;  // padding slot of the XCD-aware work list
   {
@@ -84,16 +130,24 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
     for (int j = threadIdx.x; j < (int)(sizeof(CoopStream) / 4); j += blockDim.x)
       reinterpret_cast<uint32_t*>(&ss)[j] = src[j];
   }
-  if (threadIdx.x < 12) {
-    sh_Td[threadIdx.x] = T_init[w.x * 12 + threadIdx.x];
-    sh_T[threadIdx.x] = (float)T_init[w.x * 12 + threadIdx.x];
-  }
-  if (threadIdx.x < kMaxLevels) sh_ipl[threadIdx.x] = 0;
+  if (threadIdx.x < 12) sh_T0[threadIdx.x] = T_init[w.x * 12 + threadIdx.x];
   __syncthreads();
   const TrackArgs& a = ss.a;
   const int chunk = w.y, nch = ss.n_chunks;
   const int i = chunk * CH + threadIdx.x;
-  int status = 0, iterations = 0, epoch = 0;  // status / iterations authoritative in thread 0
+  // pose state, identical in every thread of every chunk of the stream
+  float T[12];
+  double Td[MIXED ? 12 : 1];
+#pragma unroll
+  for (int j = 0; j < 12; ++j) {
+    T[j] = (float)sh_T0[j];
+    if (MIXED) Td[j] = sh_T0[j];
+  }
+  int status = 0, iterations = 0;
+  int ipl[kMaxLevels];
+#pragma unroll
+  for (int j = 0; j < kMaxLevels; ++j) ipl[j] = 0;
+  uint32_t tag = tag_base;
   int64_t samples = 0;
   bool stop = false, timed_out = false;
   PR pr;
@@ -106,100 +160,68 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
       float acc[32];
 #pragma unroll
       for (int j = 0; j < 32; ++j) acc[j] = 0.f;
-      float T[12];
-#pragma unroll
-      for (int j = 0; j < 12; ++j) T[j] = sh_T[j];
       accumulate_point<false>(a, a.pat, g, img, T, pr, acc);
-      if (MIXED)
-        block_reduce32_kahan(acc, sh_red, sh_tot);
-      else
-        block_reduce32(acc, sh_red, sh_tot);
-      if (!stream_sync_sum<MIXED>(ss.partials, ss.sync, chunk, nch, epoch, sh_tot, spin_limit, &sh_ok)) {
+      if (!stream_total<MIXED>(acc, sh_red, sh_tot, &sh_ok, ss.partials, chunk, nch, tag, spin_limit)) {
         timed_out = stop = true;
         break;
       }
-      ++epoch;
-      if (threadIdx.x == 0) {
-        samples += (int64_t)sh_tot[kSlotN];
-        int flag = 0;
-        if ((int)sh_tot[kSlotPts] < a.min_points) {
-          flag = 2;
-          status = 2;  // too few points
-        } else {
-          int bad;
-          double step;
-          if (MIXED) {
-            bad = solve_update_d(sh_tot, sh_Td, &step);
-            if (!bad)
-              for (int j = 0; j < 12; ++j) sh_T[j] = (float)sh_Td[j];
-          } else {
-            float stepf;
-            bad = solve_update(sh_tot, sh_T, &stepf);
-            step = stepf;
-          }
-          if (bad) {
-            flag = 2;
-            status = 3;  // not positive definite
-          } else {
-            ++iterations;
-            ++sh_ipl[l];
-            if (step < (double)a.step_eps) flag = 1;
-          }
-        }
-        sh_flag = flag;
-      }
-      __syncthreads();
-      const int flag = sh_flag;
-      __syncthreads();
-      if (flag == 2) {
+      ++tag;
+      samples += (int64_t)sh_tot[kSlotN];
+      if ((int)sh_tot[kSlotPts] < a.min_points) {
+        status = 2;  // too few points
         stop = true;
         break;
       }
-      if (flag == 1) {
+      int bad;
+      double step;
+      if (MIXED) {
+        bad = solve_update_d(sh_tot, Td, &step);
+        if (!bad)
+#pragma unroll
+          for (int j = 0; j < 12; ++j) T[j] = (float)Td[j];
+      } else {
+        float stepf;
+        bad = solve_update(sh_tot, T, &stepf);
+        step = stepf;
+      }
+      if (bad) {
+        status = 3;  // not positive definite
+        stop = true;
+        break;
+      }
+      ++iterations;
+#pragma unroll
+      for (int j = 0; j < kMaxLevels; ++j) ipl[j] += j == l;
+      if (step < (double)a.step_eps) {
         converged = true;
         break;
       }
     }
-    if (threadIdx.x == 0 && !stop && l == 0 && !converged) status = 1;  // iteration cap at level 0
+    if (!stop && l == 0 && !converged) status = 1;  // iteration cap at level 0
   }
   if (!timed_out) {  // final cost-only pass at level 0
     float acc[32];
 #pragma unroll
     for (int j = 0; j < 32; ++j) acc[j] = 0.f;
-    float T[12];
-#pragma unroll
-    for (int j = 0; j < 12; ++j) T[j] = sh_T[j];
     const LevelGeom g = a.lv[0];
     load_point(a, 0, i, pr);
     accumulate_point<true>(a, a.pat, g, a.cur + g.off, T, pr, acc);
-    if (MIXED)
-      block_reduce32_kahan(acc, sh_red, sh_tot);
-    else
-      block_reduce32(acc, sh_red, sh_tot);
-    if (!stream_sync_sum<MIXED>(ss.partials, ss.sync, chunk, nch, epoch, sh_tot, spin_limit, &sh_ok))
+    if (!stream_total<MIXED>(acc, sh_red, sh_tot, &sh_ok, ss.partials, chunk, nch, tag, spin_limit))
       timed_out = true;
   }
   if (chunk == 0 && threadIdx.x == 0) {
     TrackOut* o = a.out;
     for (int j = 0; j < 12; ++j) {
-      o->T[j] = sh_T[j];
-      o->Td[j] = MIXED ? sh_Td[j] : (double)sh_T[j];
+      o->T[j] = T[j];
+      o->Td[j] = MIXED ? Td[j] : (double)T[j];
     }
     o->E = sh_tot[kSlotE];
     o->n = sh_tot[kSlotN];
     o->iterations = iterations;
-    for (int j = 0; j < kMaxLevels; ++j) o->iters_per_level[j] = sh_ipl[j];
+    for (int j = 0; j < kMaxLevels; ++j) o->iters_per_level[j] = ipl[j];
     o->n_valid_points = (int)sh_tot[kSlotPts];
     o->status = timed_out ? kStatusTimeout : status;
     o->samples = samples + (int64_t)sh_tot[kSlotN];
-  }
-  // the last chunk of the stream to leave resets the counters for the next launch
-  if (threadIdx.x == 0) {
-    __threadfence();
-    if (atomicAdd(&ss.sync[1], 1) == nch - 1) {
-      atomicExch(&ss.sync[0], 0);
-      atomicExch(&ss.sync[1], 0);
-    }
   }
 }
 
@@ -233,20 +255,20 @@ int coop_max_blocks(int chunk) {
 }
 
 template <int CH>
-static hipError_t coop_launch_k(const CoopStream* d_streams, const int2* d_work, int n_work, const double* d_T,
-                                bool mixed, int spin_limit, hipStream_t s) {
-  void* args[] = {(void*)&d_streams, (void*)&d_work, (void*)&d_T, (void*)&spin_limit};
+static hipError_t coop_launch_k(const CoopStream* d_streams, const int2* d_work, int n_work, const double* T_init,
+                                uint32_t tag_base, bool mixed, int spin_limit, hipStream_t s) {
+  void* args[] = {(void*)&d_streams, (void*)&d_work, (void*)&T_init, (void*)&tag_base, (void*)&spin_limit};
   const void* fn = mixed ? reinterpret_cast<const void*>(&coop_track_kernel<CH, true>)
                          : reinterpret_cast<const void*>(&coop_track_kernel<CH, false>);
   return hipLaunchCooperativeKernel(fn, dim3(n_work), dim3(CH), args, 0, s);
 }
 
-hipError_t launch_coop_track(const CoopStream* d_streams, const int2* d_work, int n_work, const double* d_T,
-                             int chunk, bool mixed, int spin_limit, hipStream_t s) {
+hipError_t launch_coop_track(const CoopStream* d_streams, const int2* d_work, int n_work, const double* T_init,
+                             uint32_t tag_base, int chunk, bool mixed, int spin_limit, hipStream_t s) {
   switch (chunk) {
-    case 64: return coop_launch_k<64>(d_streams, d_work, n_work, d_T, mixed, spin_limit, s);
-    case 128: return coop_launch_k<128>(d_streams, d_work, n_work, d_T, mixed, spin_limit, s);
-    case 256: return coop_launch_k<256>(d_streams, d_work, n_work, d_T, mixed, spin_limit, s);
+    case 64: return coop_launch_k<64>(d_streams, d_work, n_work, T_init, tag_base, mixed, spin_limit, s);
+    case 128: return coop_launch_k<128>(d_streams, d_work, n_work, T_init, tag_base, mixed, spin_limit, s);
+    case 256: return coop_launch_k<256>(d_streams, d_work, n_work, T_init, tag_base, mixed, spin_limit, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -261,24 +283,28 @@ hipError_t CoopEngine::init(int n_streams, const int* max_points, int chunk_, bo
   stream = s;
   h_streams.assign(n, CoopStream{});
   max_chunks.resize(n);
-  size_t partial_floats = 0;
+  partial_words = 0;
   for (int k = 0; k < n; ++k) {
     max_chunks[k] = (max_points[k] + chunk - 1) / chunk;
-    partial_floats += (size_t)2 * max_chunks[k] * 32;
+    partial_words += (size_t)2 * max_chunks[k] * 32;
   }
+  if (partial_words == 0) partial_words = 64;
   hipError_t e;
   if ((e = hipMalloc(&d_streams, sizeof(CoopStream) * n)) != hipSuccess) return e;
-  if ((e = hipMalloc(&d_partials, sizeof(float) * (partial_floats ? partial_floats : 32))) != hipSuccess) return e;
-  if ((e = hipMalloc(&d_sync, sizeof(int) * 2 * n)) != hipSuccess) return e;
-  if ((e = hipMemset(d_sync, 0, sizeof(int) * 2 * n)) != hipSuccess) return e;
-  if ((e = hipMalloc(&d_T, sizeof(double) * 12 * n)) != hipSuccess) return e;
-  if ((e = hipHostMalloc(&h_T, sizeof(double) * 12 * n)) != hipSuccess) return e;
-  if ((e = hipMalloc(&d_out, sizeof(TrackOut) * n)) != hipSuccess) return e;
-  if ((e = hipHostMalloc(&h_out, sizeof(TrackOut) * n)) != hipSuccess) return e;
+  if ((e = hipMalloc(&d_partials, sizeof(uint64_t) * partial_words)) != hipSuccess) return e;
+  if ((e = hipMemset(d_partials, 0, sizeof(uint64_t) * partial_words)) != hipSuccess) return e;
+  tag_base = 1;
+  // coherent (uncached on the device) pinned host memory: the kernel reads the
+  // start poses and writes the results over the host link
+  const unsigned fl = hipHostMallocMapped | hipHostMallocCoherent;
+  if ((e = hipHostMalloc((void**)&h_T, sizeof(double) * 12 * n, fl)) != hipSuccess) return e;
+  if ((e = hipHostMalloc((void**)&h_out, sizeof(TrackOut) * n, fl)) != hipSuccess) return e;
+  if ((e = hipHostGetDevicePointer((void**)&dv_T, h_T, 0)) != hipSuccess) return e;
+  if ((e = hipHostGetDevicePointer((void**)&dv_out, h_out, 0)) != hipSuccess) return e;
+  memset(h_out, 0, sizeof(TrackOut) * n);
   size_t off = 0;
   for (int k = 0; k < n; ++k) {
     h_streams[k].partials = d_partials + off;
-    h_streams[k].sync = d_sync + 2 * k;
     off += (size_t)2 * max_chunks[k] * 32;
   }
   dirty = true;
@@ -286,19 +312,20 @@ hipError_t CoopEngine::init(int n_streams, const int* max_points, int chunk_, bo
 }
 
 void CoopEngine::release() {
-  for (void* p : {(void*)d_streams, (void*)d_work, (void*)d_partials, (void*)d_sync, (void*)d_T, (void*)d_out})
+  for (void* p : {(void*)d_streams, (void*)d_work, (void*)d_partials})
     if (p) (void)hipFree(p);
   if (h_T) (void)hipHostFree(h_T);
   if (h_out) (void)hipHostFree(h_out);
-  d_streams = nullptr, d_work = nullptr, d_partials = nullptr, d_sync = nullptr, d_T = nullptr, d_out = nullptr;
-  h_T = nullptr, h_out = nullptr;
+  d_streams = nullptr, d_work = nullptr, d_partials = nullptr;
+  h_T = nullptr, h_out = nullptr, dv_T = nullptr, dv_out = nullptr;
   work_cap = 0;
+  partial_words = 0;
 }
 
 void CoopEngine::set_stream(int k, const TrackArgs& a) {
   CoopStream& c = h_streams[k];
   c.a = a;
-  c.a.out = d_out + k;
+  c.a.out = dv_out + k;
   c.n_chunks = a.ref.n > 0 ? (a.ref.n + chunk - 1) / chunk : 1;
   dirty = true;
 }
@@ -353,13 +380,21 @@ int CoopEngine::grid() const { return (int)h_work.size(); }
 hipError_t CoopEngine::launch(int spin_limit) {
   hipError_t e;
   if (dirty && (e = upload()) != hipSuccess) return e;
-  if ((e = hipMemcpyAsync(d_T, h_T, sizeof(double) * 12 * n, hipMemcpyHostToDevice, stream)) != hipSuccess) return e;
-  if ((e = launch_coop_track(d_streams, d_work, grid(), d_T, chunk, mixed, spin_limit, stream)) != hipSuccess)
-    return e;
-  return hipMemcpyAsync(h_out, d_out, sizeof(TrackOut) * n, hipMemcpyDeviceToHost, stream);
+  // tags used by this launch: at most levels * max_iters + 1 epochs per stream
+  uint32_t span = 1;
+  for (const CoopStream& c : h_streams) span = std::max(span, (uint32_t)(c.a.levels * c.a.max_iters + 1));
+  if (tag_base > 0xFFFFFFFFu - span) {  // wrap: restart the tags on cleared words
+    if ((e = clear_partials()) != hipSuccess) return e;
+  }
+  e = launch_coop_track(d_streams, d_work, grid(), dv_T, tag_base, chunk, mixed, spin_limit, stream);
+  tag_base += span;
+  return e;
 }
 
-hipError_t CoopEngine::reset_sync() { return hipMemsetAsync(d_sync, 0, sizeof(int) * 2 * n, stream); }
+hipError_t CoopEngine::clear_partials() {
+  tag_base = 1;
+  return hipMemsetAsync(d_partials, 0, sizeof(uint64_t) * partial_words, stream);
+}
 
 // ---------------------------------------------------------------- batched pyramid
 

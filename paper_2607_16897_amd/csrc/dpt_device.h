@@ -245,10 +245,8 @@ __device__ __forceinline__ int solve_update(const float* tot_lds, float* T, floa
 #pragma unroll
     for (int k = 0; k < j; ++k) s = fmaf(-L[tri(k, j)], L[tri(k, j)], s);
     bad |= !(s > 1e-6f * dmax);
-    s = fmaxf(s, 1e-30f);
-    const float d = sqrtf(s);
-    L[tri(j, j)] = d;
-    const float inv = 1.0f / d;
+    // only 1/L(j, j) is used by the elimination and the substitutions
+    const float inv = __builtin_amdgcn_rsqf(fmaxf(s, 1e-30f));
     invd[j] = inv;
 #pragma unroll
     for (int i = j + 1; i < 6; ++i) {
@@ -281,13 +279,14 @@ __device__ __forceinline__ int solve_update(const float* tot_lds, float* T, floa
   // exp(xi), xi = -delta = (w, v): R = I + A[w] + B[w]^2, t = (I + B[w] + C[w]^2) v
   const float w0 = -d[0], w1 = -d[1], w2 = -d[2];
   const float vv[3] = {-d[3], -d[4], -d[5]};
-  const float th2 = w0 * w0 + w1 * w1 + w2 * w2, th = sqrtf(th2);
+  const float th2 = w0 * w0 + w1 * w1 + w2 * w2;
   float A, B, C;
-  if (th < 0.05f) {
+  if (th2 < 0.0025f) {  // |w| < 0.05
     A = 1.0f - th2 * (1.0f / 6.0f) * (1.0f - th2 * (1.0f / 20.0f));
     B = 0.5f - th2 * (1.0f / 24.0f) * (1.0f - th2 * (1.0f / 30.0f));
     C = (1.0f / 6.0f) - th2 * (1.0f / 120.0f) * (1.0f - th2 * (1.0f / 42.0f));
   } else {
+    const float th = sqrtf(th2);
     const float sn = sinf(th), sh = sinf(0.5f * th);
     A = sn / th;
     B = 2.0f * sh * sh / th2;
@@ -338,9 +337,11 @@ __device__ __forceinline__ int solve_update_d(const float* tot_lds, double* T, d
     for (int k = 0; k < j; ++k) s = fma(-L[tri(k, j)], L[tri(k, j)], s);
     bad |= !(s > 1e-12 * dmax);
     s = fmax(s, 1e-300);
-    const double d = sqrt(s);
-    L[tri(j, j)] = d;
-    const double inv = 1.0 / d;
+    // 1/sqrt(s): hardware estimate, then two Newton steps (each squares the
+    // relative error) to full double precision; only 1/L(j, j) is used later
+    double inv = __builtin_amdgcn_rsq(s);
+    inv = inv * fma(-0.5 * s * inv, inv, 1.5);
+    inv = inv * fma(-0.5 * s * inv, inv, 1.5);
     invd[j] = inv;
 #pragma unroll
     for (int i = j + 1; i < 6; ++i) {
@@ -372,13 +373,14 @@ __device__ __forceinline__ int solve_update_d(const float* tot_lds, double* T, d
   *max_step = m;
   const double w0 = -d[0], w1 = -d[1], w2 = -d[2];
   const double vv[3] = {-d[3], -d[4], -d[5]};
-  const double th2 = w0 * w0 + w1 * w1 + w2 * w2, th = sqrt(th2);
+  const double th2 = w0 * w0 + w1 * w1 + w2 * w2;
   double A, B, C;
-  if (th < 1e-4) {
-    A = 1.0 - th2 / 6.0;
-    B = 0.5 - th2 / 24.0;
-    C = 1.0 / 6.0 - th2 / 120.0;
+  if (th2 < 0.0025) {  // |w| < 0.05: series through th^8, truncation below 1e-20
+    A = 1.0 - th2 / 6.0 * (1.0 - th2 / 20.0 * (1.0 - th2 / 42.0 * (1.0 - th2 / 72.0)));
+    B = 0.5 * (1.0 - th2 / 12.0 * (1.0 - th2 / 30.0 * (1.0 - th2 / 56.0 * (1.0 - th2 / 90.0))));
+    C = (1.0 - th2 / 20.0 * (1.0 - th2 / 42.0 * (1.0 - th2 / 72.0 * (1.0 - th2 / 110.0)))) / 6.0;
   } else {
+    const double th = sqrt(th2);
     const double sn = sin(th), sh = sin(0.5 * th);
     A = sn / th;
     B = 2.0 * sh * sh / th2;

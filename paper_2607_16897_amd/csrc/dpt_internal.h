@@ -97,9 +97,8 @@ struct PrecomputeArgs {
 
 // One stream of a cooperative track launch (device array, one entry per stream).
 struct CoopStream {
-  TrackArgs a;      // a.out points at this stream's TrackOut
-  float* partials;  // [2][n_chunks][32] double-buffered chunk sums
-  int* sync;        // [2] arrival and departure counters, zero between launches
+  TrackArgs a;         // a.out points at this stream's TrackOut (host-mapped)
+  uint64_t* partials;  // [2][n_chunks][32] chunk sums, each word = (tag << 32) | float bits
   int32_t n_chunks;
   int32_t pad;
 };
@@ -114,7 +113,9 @@ struct PyrJob {
   int32_t pad;
 };
 
-// Host-side owner of a cooperative track launch over n streams.
+// Host-side owner of a cooperative track launch over n streams.  Start poses
+// and results live in host-mapped pinned memory that the kernel reads and
+// writes directly, so a launch needs no copy commands.
 struct CoopEngine {
   int n = 0, chunk = 256, work_cap = 0;
   bool xcd_pack = true, dirty = true;
@@ -124,25 +125,27 @@ struct CoopEngine {
   std::vector<int2> h_work;
   CoopStream* d_streams = nullptr;
   int2* d_work = nullptr;
-  float* d_partials = nullptr;
-  int* d_sync = nullptr;
-  double* d_T = nullptr;  // [n][12] start poses (relative)
-  double* h_T = nullptr;  // pinned
-  bool mixed = false;     // mixed-precision kernel variant
-  TrackOut* d_out = nullptr;
-  TrackOut* h_out = nullptr;  // pinned
+  uint64_t* d_partials = nullptr;
+  size_t partial_words = 0;
+  uint32_t tag_base = 1;      // epoch tags of the next launch start here; 0 marks a cleared word
+  double* h_T = nullptr;      // [n][12] start poses (relative), host-mapped
+  double* dv_T = nullptr;     // device view of h_T
+  bool mixed = false;         // mixed-precision kernel variant
+  TrackOut* h_out = nullptr;  // [n] results, host-mapped
+  TrackOut* dv_out = nullptr; // device view of h_out
   hipError_t init(int n_streams, const int* max_points, int chunk, bool xcd_pack, hipStream_t s);
   void release();
   void set_stream(int k, const TrackArgs& a);
   hipError_t upload();
   int grid() const;
-  // H2D of h_T, the launch, and an async D2H of the results into h_out
+  // Enqueue the track of every stream from h_T; results land in h_out once the
+  // stream reaches this point.
   hipError_t launch(int spin_limit);
-  hipError_t reset_sync();
+  hipError_t clear_partials();
   ~CoopEngine() { release(); }
 };
 
-constexpr int kSpinLimit = 1 << 24;  // polls (~64 clocks each) before a chunk reports a timeout
+constexpr int kSpinLimit = 1 << 22;  // polls (one round trip to memory each) before a chunk reports a timeout
 
 // Record an error message for dpt_last_error() and return `code`.
 int set_error(int code, const char* msg);
@@ -164,8 +167,8 @@ hipError_t launch_track_batch(const TrackArgs& any, const TrackArgs* batch, int 
                               int max_points, hipStream_t s);
 int track_lds_bytes(const LevelGeom* lv, int levels);
 hipError_t launch_normal_equations(const TrackArgs& a, hipStream_t s);
-hipError_t launch_coop_track(const CoopStream* d_streams, const int2* d_work, int n_work, const double* d_T,
-                             int chunk, bool mixed, int spin_limit, hipStream_t s);
+hipError_t launch_coop_track(const CoopStream* d_streams, const int2* d_work, int n_work, const double* T_init,
+                             uint32_t tag_base, int chunk, bool mixed, int spin_limit, hipStream_t s);
 int coop_max_blocks(int chunk);  // co-resident workgroups of a cooperative launch (0 if unsupported)
 hipError_t launch_pyramid_batch(const PyrJob* d_jobs, int n_jobs, int max_w, int max_h, int levels, hipStream_t s);
 
