@@ -133,6 +133,7 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
   if (threadIdx.x < 12) sh_T0[threadIdx.x] = T_init[w.x * 12 + threadIdx.x];
   __syncthreads();
   const TrackArgs& a = ss.a;
+  const PatRegs pregs = pattern_regs(a.pat);
   const int chunk = w.y, nch = ss.n_chunks;
   const int i = chunk * CH + threadIdx.x;
   // pose state, identical in every thread of every chunk of the stream
@@ -160,7 +161,7 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
       float acc[32];
 #pragma unroll
       for (int j = 0; j < 32; ++j) acc[j] = 0.f;
-      accumulate_point<false>(a, a.pat, g, img, T, pr, acc);
+      accumulate_point<false, true>(a, pregs, g, img, T, pr, acc);
       if (!stream_total<MIXED>(acc, sh_red, sh_tot, &sh_ok, ss.partials, chunk, nch, tag, spin_limit)) {
         timed_out = stop = true;
         break;
@@ -205,7 +206,7 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
     for (int j = 0; j < 32; ++j) acc[j] = 0.f;
     const LevelGeom g = a.lv[0];
     load_point(a, 0, i, pr);
-    accumulate_point<true>(a, a.pat, g, a.cur + g.off, T, pr, acc);
+    accumulate_point<true, true>(a, pregs, g, a.cur + g.off, T, pr, acc);
     if (!stream_total<MIXED>(acc, sh_red, sh_tot, &sh_ok, ss.partials, chunk, nch, tag, spin_limit))
       timed_out = true;
   }

@@ -29,6 +29,28 @@ __device__ __forceinline__ bool inside(const LevelGeom& g, const Pattern& p, flo
          (v + (float)p.dy_min >= 1.0f) && (v + (float)p.dy_max < (float)(g.H - 2));
 }
 
+// The K = 8 pattern held in registers for the whole track: offsets and their
+// bounding box as floats (the same values inside() converts on the fly).
+struct PatRegs {
+  float dx[8], dy[8];
+  float dx_min, dx_max, dy_min, dy_max;
+};
+
+__device__ __forceinline__ PatRegs pattern_regs(const Pattern& p) {
+  PatRegs r;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) r.dx[k] = (float)p.dx[k], r.dy[k] = (float)p.dy[k];
+  r.dx_min = (float)p.dx_min, r.dx_max = (float)p.dx_max;
+  r.dy_min = (float)p.dy_min, r.dy_max = (float)p.dy_max;
+  return r;
+}
+
+// inside() on the register pattern, without branches.
+__device__ __forceinline__ bool inside(const LevelGeom& g, const PatRegs& p, float u, float v) {
+  return (u + p.dx_min >= 1.0f) & (u + p.dx_max < (float)(g.W - 2)) & (v + p.dy_min >= 1.0f) &
+         (v + p.dy_max < (float)(g.H - 2));
+}
+
 // Bilinear intensity of a uint8 level, pixel centres at integer coordinates.
 __device__ __forceinline__ float bilinear(const uint8_t* img, int W, float x, float y) {
   float fx = floorf(x), fy = floorf(y);
@@ -416,6 +438,7 @@ __device__ __forceinline__ int solve_update_d(const float* tot_lds, double* T, d
 // a level: the reference-camera point x0, template intensities and gradients.
 struct PointRegs {
   float X0, Y0, Z0;
+  float iz, xp, yp;  // 1/Z0, X0/Z0, Y0/Z0 for the warp Jacobian
   float i0_[8], gx_[8], gy_[8];
   bool ok;
   __device__ __forceinline__ float i0(int k) const { return i0_[k]; }
@@ -427,6 +450,7 @@ struct PointRegs {
 // 12 registers per point instead of 24.
 struct PointRegsH {
   float X0, Y0, Z0;
+  float iz, xp, yp;
   __half i0_[8];
   __half2 g_[8];
   bool ok;
@@ -435,15 +459,40 @@ struct PointRegsH {
   __device__ __forceinline__ float gy(int k) const { return __high2float(g_[k]); }
 };
 
-__device__ __forceinline__ void load_point(const TrackArgs& a, int l, int i, PointRegs& pr) {
+// Load point i's registers for level l.  Branch-free: a point past the map
+// (i >= n) reads entry 0 instead, and the geometry of an unusable point is
+// selected to finite values (its warp Jacobian multiplies masked zeros); the
+// template registers of such a point reach only sums that are selected away.
+// The cache arrays hold at least one entry per level, so every read is inside.
+__device__ __forceinline__ bool load_geometry(const TrackArgs& a, int l, int i, float4& p, int64_t& e) {
   const int64_t lo = (int64_t)l * a.ref.cap;
-  pr.ok = (i < a.ref.n) && a.ref.valid[lo + i];
-  if (!pr.ok) return;
-  const float4 p = a.ref.x0[i];
-  pr.X0 = p.x, pr.Y0 = p.y, pr.Z0 = p.z;
-  const float4* q0 = reinterpret_cast<const float4*>(a.ref.I0 + (lo + i) * 8);
-  const float4* qx = reinterpret_cast<const float4*>(a.ref.gx + (lo + i) * 8);
-  const float4* qy = reinterpret_cast<const float4*>(a.ref.gy + (lo + i) * 8);
+  const bool in = i < a.ref.n;
+  const int j = in ? i : 0;
+  e = lo + j;
+  p = a.ref.x0[j];
+  return in & (a.ref.valid[e] != 0);
+}
+
+template <class PR>
+__device__ __forceinline__ void set_geometry(PR& pr, bool ok, const float4& p) {
+  pr.ok = ok;
+  const float iz = 1.0f / p.z;
+  pr.X0 = ok ? p.x : 0.0f;
+  pr.Y0 = ok ? p.y : 0.0f;
+  pr.Z0 = ok ? p.z : 1.0f;
+  pr.iz = ok ? iz : 0.0f;
+  pr.xp = ok ? p.x * iz : 0.0f;
+  pr.yp = ok ? p.y * iz : 0.0f;
+}
+
+__device__ __forceinline__ void load_point(const TrackArgs& a, int l, int i, PointRegs& pr) {
+  float4 p;
+  int64_t e;
+  const bool ok = load_geometry(a, l, i, p, e);
+  set_geometry(pr, ok, p);
+  const float4* q0 = reinterpret_cast<const float4*>(a.ref.I0 + e * 8);
+  const float4* qx = reinterpret_cast<const float4*>(a.ref.gx + e * 8);
+  const float4* qy = reinterpret_cast<const float4*>(a.ref.gy + e * 8);
   const float4 a0 = q0[0], a1 = q0[1], b0 = qx[0], b1 = qx[1], c0 = qy[0], c1 = qy[1];
   const float t0[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
   const float t1[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
@@ -453,13 +502,12 @@ __device__ __forceinline__ void load_point(const TrackArgs& a, int l, int i, Poi
 }
 
 __device__ __forceinline__ void load_point(const TrackArgs& a, int l, int i, PointRegsH& pr) {
-  const int64_t lo = (int64_t)l * a.ref.cap;
-  pr.ok = (i < a.ref.n) && a.ref.valid[lo + i];
-  if (!pr.ok) return;
-  const float4 p = a.ref.x0[i];
-  pr.X0 = p.x, pr.Y0 = p.y, pr.Z0 = p.z;
-  const uint4 h = *reinterpret_cast<const uint4*>(a.ref.I0h + (lo + i) * 8);
-  const uint4* q = reinterpret_cast<const uint4*>(a.ref.gh + (lo + i) * 8);
+  float4 p;
+  int64_t e;
+  const bool ok = load_geometry(a, l, i, p, e);
+  set_geometry(pr, ok, p);
+  const uint4 h = *reinterpret_cast<const uint4*>(a.ref.I0h + e * 8);
+  const uint4* q = reinterpret_cast<const uint4*>(a.ref.gh + e * 8);
   const uint4 g0 = q[0], g1 = q[1];
   const uint32_t hw[4] = {h.x, h.y, h.z, h.w};
   const uint32_t gw[8] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w};
@@ -482,32 +530,48 @@ __device__ __forceinline__ void load_point(const TrackArgs& a, int l, int i, Poi
 //   H_i = m00 au^T au + m01 (au^T av + av^T au) + m11 av^T av,   b_i = -(v0 au + v1 av),
 // m = sum_k w_k g_k^T g_k, v = sum_k w_k g_k r_k (five FMAs per sample, the
 // 21-term product once per point).  Huber weight w = min(1, k/|r|).
-template <bool COST_ONLY, class PR>
-__device__ __forceinline__ void accumulate_point(const TrackArgs& a, const Pattern& pat, const LevelGeom& g,
+// Branch-free: a point that is not usable (reference-invalid, behind the
+// camera or a pattern position outside the level) runs the same instructions
+// with its taps at the level's first pixels and its sums and counts masked to
+// zero, so no exit path has to materialise a zeroed accumulator.
+// GLOBAL_IMG: `img` is device global memory (loads compile to global_load);
+// otherwise it may be LDS.
+template <bool COST_ONLY, bool GLOBAL_IMG, class PR>
+__device__ __forceinline__ void accumulate_point(const TrackArgs& a, const PatRegs& pat, const LevelGeom& g,
                                                  const uint8_t* __restrict__ img, const float* T,
                                                  const PR& pr, float (&acc)[32]) {
-  if (!pr.ok) return;
   const float kH = a.huber_k;
   float X, Y, Z;
   transform(T, pr.X0, pr.Y0, pr.Z0, X, Y, Z);
-  if (!(Z > a.z_min)) return;
   float u, v;
   project(g, X, Y, Z, u, v);
-  if (!inside(g, pat, u, v)) return;
+  const bool ok = pr.ok & (Z > a.z_min) & inside(g, pat, u, v);
+  // An unusable point continues from (0, 0): finite, integer sample positions
+  // (zero bilinear fractions) and a tap offset forced to 0.
+  u = ok ? u : 0.0f;
+  v = ok ? v : 0.0f;
   // Phase 1: all 32 bilinear taps of the point are issued before any is used
   // (one memory round trip per point instead of one per sample).
   float ta[8], tc[8], t00[8], t10[8], t01[8], t11[8];
+  const int W = g.W;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    const float x = u + (float)pat.dx[k], y = v + (float)pat.dy[k];
+    const float x = u + pat.dx[k], y = v + pat.dy[k];
     const float fx = floorf(x), fy = floorf(y);
     ta[k] = x - fx;
     tc[k] = y - fy;
-    const uint8_t* p = img + (int)fy * g.W + (int)fx;
-    t00[k] = p[0], t10[k] = p[1], t01[k] = p[g.W], t11[k] = p[g.W + 1];
+    const int off = ((int)fy * W + (int)fx) & -(int)ok;  // masked, not branched
+    if constexpr (GLOBAL_IMG) {
+      const __attribute__((address_space(1))) uint8_t* p =
+          (const __attribute__((address_space(1))) uint8_t*)img + off;
+      t00[k] = p[0], t10[k] = p[1], t01[k] = p[W], t11[k] = p[W + 1];
+    } else {
+      const uint8_t* p = img + off;
+      t00[k] = p[0], t10[k] = p[1], t01[k] = p[W], t11[k] = p[W + 1];
+    }
   }
-  // Phase 2: residuals, Huber weights (branch-free) and the point's sums.  The
-  // interpolation repeats bilinear()'s arithmetic exactly.
+  // Phase 2: residuals, Huber weights and the point's sums.  The interpolation
+  // repeats bilinear()'s arithmetic exactly.
   float m00 = 0.f, m01 = 0.f, m11 = 0.f, v0 = 0.f, v1 = 0.f, E = 0.f;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
@@ -530,11 +594,13 @@ __device__ __forceinline__ void accumulate_point(const TrackArgs& a, const Patte
       v1 = fmaf(wgy, r, v1);
     }
   }
-  acc[kSlotE] += E;
-  acc[kSlotN] += 8.0f;
-  acc[kSlotPts] += 1.0f;
+  acc[kSlotE] += ok ? E : 0.0f;
+  acc[kSlotN] += ok ? 8.0f : 0.0f;
+  acc[kSlotPts] += ok ? 1.0f : 0.0f;
   if (COST_ONLY) return;
-  const float iz = 1.0f / pr.Z0, xp = pr.X0 * iz, yp = pr.Y0 * iz;
+  m00 = ok ? m00 : 0.0f, m01 = ok ? m01 : 0.0f, m11 = ok ? m11 : 0.0f;
+  v0 = ok ? v0 : 0.0f, v1 = ok ? v1 : 0.0f;
+  const float iz = pr.iz, xp = pr.xp, yp = pr.yp;
   const float au[6] = {-g.fx * xp * yp, g.fx * fmaf(xp, xp, 1.0f), -g.fx * yp, g.fx * iz, 0.0f, -g.fx * xp * iz};
   const float av[6] = {-g.fy * fmaf(yp, yp, 1.0f), g.fy * xp * yp, g.fy * xp, 0.0f, g.fy * iz, -g.fy * yp * iz};
   int q = 0;

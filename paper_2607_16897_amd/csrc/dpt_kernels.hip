@@ -184,11 +184,11 @@ __device__ __forceinline__ void load_points(const TrackArgs& a, int l, PointRegs
 }
 
 template <bool COST_ONLY>
-__device__ __forceinline__ void accumulate_cached(const TrackArgs& a, const Pattern& pat, const LevelGeom& g,
+__device__ __forceinline__ void accumulate_cached(const TrackArgs& a, const PatRegs& pat, const LevelGeom& g,
                                                   const uint8_t* __restrict__ img, const float* T,
                                                   const PointRegs (&pr)[kCachedPPT], float (&acc)[32]) {
 #pragma unroll
-  for (int j = 0; j < kCachedPPT; ++j) accumulate_point<COST_ONLY>(a, pat, g, img, T, pr[j], acc);
+  for (int j = 0; j < kCachedPPT; ++j) accumulate_point<COST_ONLY, false>(a, pat, g, img, T, pr[j], acc);
 }
 
 // Copy one pyramid level into LDS (used when it fits the workgroup's budget).
@@ -227,6 +227,7 @@ __global__ __launch_bounds__(kTrackThreads) void track_kernel(TrackArgs a0, cons
   }
   __syncthreads();
   const TrackArgs& a = sa;
+  const PatRegs pregs = pattern_regs(a.pat);  // used by the K = 8 register path
   if (threadIdx.x < 12) sh_T[threadIdx.x] = a.T_init[threadIdx.x];
   if (threadIdx.x < kMaxLevels) sh_ipl[threadIdx.x] = 0;
   __syncthreads();
@@ -253,9 +254,9 @@ __global__ __launch_bounds__(kTrackThreads) void track_kernel(TrackArgs a0, cons
       for (int j = 0; j < 12; ++j) T[j] = sh_T[j];
       if constexpr (CACHED) {
         if (in_lds)
-          accumulate_cached<false>(a, a.pat, g, dyn_lds, T, pr, acc);
+          accumulate_cached<false>(a, pregs, g, dyn_lds, T, pr, acc);
         else
-          accumulate_cached<false>(a, a.pat, g, a.cur + g.off, T, pr, acc);
+          accumulate_cached<false>(a, pregs, g, a.cur + g.off, T, pr, acc);
       } else {
         if (in_lds)
           accumulate<KT, false>(a, a.pat, g, dyn_lds, l, T, acc);
