@@ -6,10 +6,11 @@ the 752x480 sequence: seeded 3-plane scene (fx = fy = 458, cx = 367, cy = 248),
 smooth 200 Hz trajectory, Gaussian pixel noise sigma = 2, 4 pyramid levels,
 2000 map points with the 8-pixel pattern, Huber k = 9, <= 10 iterations per
 level.  A step is one keyframe window: the reference frame's pyramid, point
-selection and IC precompute, then 9 frames each with its pyramid and
-coarse-to-fine track started from the constant-velocity prediction.  Frames are
-resident in device memory before the timed region; reference refreshes are
-amortised into the rate.  Residual samples/s counts every residual evaluated,
+selection, back-projection of the selected pixels from the keyframe's depth map
+and IC precompute (all on the device), then 9 frames each with its pyramid and
+coarse-to-fine track started from the constant-velocity prediction.  Frames and
+keyframe depth maps are resident in device memory before the timed region;
+reference refreshes are amortised into the rate.  Residual samples/s counts every residual evaluated,
 the final cost pass included.
 
 Further legs in the same line: batched streams (64 sequences of the headline
@@ -92,8 +93,15 @@ def make_windows(n_windows: int, seed: int = 2607, cam=None):
                 depth = dep
             imgs.append(img)
             gts.append(T)
-        wins.append(dict(k0=k0, imgs=imgs, gts=gts, depth=depth, T_prev=traj.T_cw(k0 - 1)))
+        wins.append(dict(k0=k0, imgs=imgs, gts=gts, depth=depth.astype(np.float32), T_prev=traj.T_cw(k0 - 1)))
     return wins
+
+
+def to_device(wins):
+    """Frames and keyframe depth of every window as device tensors."""
+    import torch
+
+    return [([torch.from_numpy(im).cuda() for im in w["imgs"]], torch.from_numpy(w["depth"]).cuda()) for w in wins]
 
 
 def cv_init(prev2, prev1):
@@ -105,11 +113,13 @@ def new_stats():
     return {k: [] for k in ("track_ms", "pyr_ms", "samples", "iters", "status", "T", "init", "gt")}
 
 
-def run_window_gpu(dpt, synth, trk, win, dev_imgs, stats, n_points, cam):
+def run_window_gpu(dpt, synth, trk, win, dev, stats, n_points, cam):
+    """One keyframe window: the reference refresh (pyramid, selection,
+    back-projection from the keyframe's depth and IC precompute, all on the
+    device), then 9 tracked frames.  dev = (device frames, device depth)."""
+    dev_imgs, dev_depth = dev
     trk.build_pyramid(dpt.SLOT_REF, dev_imgs[0])
-    idx = trk.select_points(n_points, 8)
-    P = synth.backproject(cam, win["depth"], idx, win["gts"][0])
-    trk.set_reference_points(P, win["gts"][0])
+    trk.set_reference_from_depth(n_points, dev_depth, win["gts"][0])
     prev2, prev1 = win["T_prev"], win["gts"][0]
     for j in range(1, WINDOW):
         trk.build_pyramid(dpt.SLOT_CUR, dev_imgs[j])
@@ -165,22 +175,20 @@ def bench_batched_sequences(dpt, synth, n_streams: int, steps: int, warmup: int,
     t_r = time.perf_counter()
     wins = [make_windows(n_win, seed=2607 + s) for s in range(n_streams)]
     render_s = time.perf_counter() - t_r
-    dev = [[[torch.from_numpy(im).cuda() for im in w["imgs"]] for w in ws] for ws in wins]
+    dev = [to_device(ws) for ws in wins]
     torch.cuda.synchronize()
     prm = dpt.make_params(levels=LEVELS, max_iters=10, huber_k=9.0, step_eps=1e-5)
     bt = dpt.BatchTracker([CAM] * n_streams, prm, [N_POINTS] * n_streams)
     stats = {"track_ms": [], "samples": [], "iters": [], "status": []}
 
     def window(w, record):
-        bt.build_pyramids(dpt.SLOT_REF, [dev[s][w][0] for s in range(n_streams)])
+        bt.build_pyramids(dpt.SLOT_REF, [dev[s][w][0][0] for s in range(n_streams)])
         for s in range(n_streams):
-            ws = wins[s][w]
-            idx = bt.select_points(s, N_POINTS, 8)
-            bt.set_reference_points(s, synth.backproject(CAM, ws["depth"], idx, ws["gts"][0]), ws["gts"][0])
+            bt.set_reference_from_depth(s, N_POINTS, dev[s][w][1], wins[s][w]["gts"][0])
         prev2 = np.stack([wins[s][w]["T_prev"] for s in range(n_streams)])
         prev1 = np.stack([wins[s][w]["gts"][0] for s in range(n_streams)])
         for j in range(1, WINDOW):
-            bt.build_pyramids(dpt.SLOT_CUR, [dev[s][w][j] for s in range(n_streams)])
+            bt.build_pyramids(dpt.SLOT_CUR, [dev[s][w][0][j] for s in range(n_streams)])
             res = bt.track(prev1 @ np.linalg.inv(prev2) @ prev1)
             prev2, prev1 = prev1, np.stack([r["T_cw"] for r in res])
             if record:
@@ -324,7 +332,7 @@ def bench_stress(dpt, synth):
 
     cam = synth.CAM_1280
     wins = make_windows(1, cam=cam)
-    dev = [[torch.from_numpy(im).cuda() for im in w["imgs"]] for w in wins]
+    dev = to_device(wins)
     out, raw = {}, {}
     for name, prec in (("fp32", dpt.PREC_FP32), ("mixed", dpt.PREC_MIXED)):
         prm = dpt.make_params(levels=4, max_iters=10, huber_k=9.0, step_eps=1e-5, precision=prec)
@@ -458,7 +466,7 @@ def main():
     t_r = time.perf_counter()
     wins = make_windows(n_render)
     render_s = time.perf_counter() - t_r
-    dev = [[torch.from_numpy(im).cuda() for im in w["imgs"]] for w in wins]
+    dev = to_device(wins)
     torch.cuda.synchronize()
     print(f"# rendered {n_render} windows in {render_s:.1f} s", file=sys.stderr, flush=True)
 

@@ -2,7 +2,7 @@
  * dptrack.h - C ABI of the MI355X (gfx950) direct photometric tracker.
  *
  * Pose-only direct photometric tracking of a frame against a sparse map
- * (paper Sec. III): an image pyramid, an inverse-compositional (IC) precompute
+ * (paper Sec. IV): an image pyramid, an inverse-compositional (IC) precompute
  * per reference frame, and a per-frame coarse-to-fine Gauss-Newton track whose
  * normal equations are reduced and solved on the GPU.
  *
@@ -99,7 +99,7 @@ int dpt_create(const dpt_camera* cam, const dpt_params* prm, int32_t max_points,
 /* Release a context and all its memory (NULL is a no-op). */
 void dpt_destroy(dpt_ctx* ctx);
 
-/* Build the uint8 pyramid of one slot from an image (paper Sec. III-C, "Image
+/* Build the uint8 pyramid of one slot from an image (paper Sec. IV-C, "Image
  * pyramids"; read here as 2x2 box means rounded half up, floor sizes).
  * slot: DPT_SLOT_REF or DPT_SLOT_CUR.  img: width x height bytes, row pitch
  * `pitch` >= width, in device memory if img_on_device else host memory.
@@ -111,7 +111,7 @@ int dpt_build_pyramid(dpt_ctx* ctx, int32_t slot, const uint8_t* img, int64_t pi
 int dpt_get_pyramid(dpt_ctx* ctx, int32_t slot, int32_t level, uint8_t* host_dst);
 
 /* Map-point selection on the REF slot's level 0 (stand-in for the map points the
- * indirect pipeline provides, Sec. II): the n pixels with the largest integer
+ * indirect pipeline provides, Sec. III): the n pixels with the largest integer
  * score (I[y][x+1]-I[y][x-1])^2 + (I[y+1][x]-I[y-1][x])^2 inside
  * margin <= x <= W-1-margin, margin <= y <= H-1-margin (margin >= 1), ties to the
  * smaller linear index y*W+x.  Writes min(n, candidates) indices in ascending
@@ -119,7 +119,7 @@ int dpt_get_pyramid(dpt_ctx* ctx, int32_t slot, int32_t level, uint8_t* host_dst
 int dpt_select_points(dpt_ctx* ctx, int32_t n, int32_t margin, int32_t* host_idx, int32_t* n_out);
 
 /* Set the reference map and run the IC precompute on the REF pyramid (Sec.
- * III-C "Precompute Inverse Compositional", Eq.(6)): for each level and point,
+ * IV-C "Precompute Inverse Compositional", Eq.(6)): for each level and point,
  * x0 = T_rw P, the patch intensities I0 and reference-side gradients are cached;
  * the Jacobian is rebuilt from them and x0 during tracking.
  * xyz_world: n x 3 floats (device memory if xyz_on_device).  T_rw: world ->
@@ -127,7 +127,22 @@ int dpt_select_points(dpt_ctx* ctx, int32_t n, int32_t margin, int32_t* host_idx
 int dpt_set_reference_points(dpt_ctx* ctx, const float* xyz_world, int32_t n, const double T_rw[16],
                              int32_t xyz_on_device);
 
-/* Track the CUR pyramid against the reference (Sec. III-C "Track"; Eq.(2)-(5)):
+/* Reference update from a depth map, all on the stream with no host round trip
+ * (the RGB-D form of the reference update: the map points of Sec. IV-A come
+ * from the reference frame's own depth instead of the indirect pipeline).
+ * Selects n points on the REF level 0 exactly as dpt_select_points, turns each
+ * selected pixel (x, y) with depth z into P = T_rw^-1 (z K^-1 [x, y, 1]^T)
+ * (FP64, rounded to FP32) and runs the IC precompute of
+ * dpt_set_reference_points on them.  The map holds n points: a selected pixel
+ * without a positive finite depth, and the entries past the selection count
+ * (only when fewer than n candidates exist), are points that are never valid.
+ * depth: level-0 depths in metres, rows of depth_pitch floats (>= width),
+ * device memory if depth_on_device (else copied, synchronously).
+ * 1 <= n <= max_points; margin as in dpt_select_points. */
+int dpt_set_reference_from_depth(dpt_ctx* ctx, int32_t n, int32_t margin, const float* depth, int64_t depth_pitch,
+                                 int32_t depth_on_device, const double T_rw[16]);
+
+/* Track the CUR pyramid against the reference (Sec. IV-C "Track"; Eq.(2)-(5)):
  * coarse to fine, per level up to max_iters Huber-weighted Gauss-Newton steps,
  * the 21 + 6 normal-equation terms reduced on the GPU, a Cholesky solve and the
  * inverse-compositional update T_rel <- T_rel exp(delta)^-1 on the GPU, then a
@@ -168,7 +183,7 @@ int dpt_last_kernel_ms(dpt_ctx* ctx, float* pyramid_ms, float* track_ms);
  * Many independent camera streams tracked together: one pyramid launch for all
  * streams' images and one cooperative track launch per group of streams that
  * fits the GPU's co-resident capacity (every stream's map split into chunks,
- * Sec. III-C's per-point work and tree reduction run per chunk), or one
+ * Sec. IV-C's per-point work and tree reduction run per chunk), or one
  * workgroup per stream.  Each stream keeps its own camera, pyramids and map;
  * all share dpt_params and the HIP stream.  The per-stream results equal those of
  * dpt_track_frame on a single-stream context to rounding. */
@@ -188,6 +203,10 @@ int dpt_batch_build_pyramids(dpt_batch* b, int32_t slot, const uint8_t* const* i
 int dpt_batch_select_points(dpt_batch* b, int32_t s, int32_t n, int32_t margin, int32_t* host_idx, int32_t* n_out);
 int dpt_batch_set_reference_points(dpt_batch* b, int32_t s, const float* xyz_world, int32_t n, const double T_rw[16],
                                    int32_t xyz_on_device);
+
+/* As dpt_set_reference_from_depth, for stream `s`. */
+int dpt_batch_set_reference_from_depth(dpt_batch* b, int32_t s, int32_t n, int32_t margin, const float* depth,
+                                       int64_t depth_pitch, int32_t depth_on_device, const double T_rw[16]);
 
 /* Copy pyramid level `level` of slot `slot` of every stream, packed, into dst:
  * stream s's level at dst + s * W_l * H_l (all streams must have the same
@@ -209,7 +228,7 @@ int dpt_batch_last_kernel_ms(dpt_batch* b, float* pyramid_ms, float* track_ms);
 /* ------------------------------------------------------------------ learned initialiser
  * A small CNN proposes the reference-to-current twist from the coarsest pyramid
  * pair, as the start pose of the coarse-to-fine Gauss-Newton track (which the
- * paper starts from the previous estimate, Sec. II and Sec. III-A).  Not in the
+ * paper starts from the previous estimate, Sec. III and Sec. IV-A).  Not in the
  * paper.  Input: the reference and current levels of size 94 x 60, (I - 128)/64.
  * Network: conv 3x3 stride 2 pad 1 + ReLU, 2-16-32-64-64 channels; global
  * average pool; FC 64-64 + ReLU; FC 64-6.  Output: the twist (omega, v) divided

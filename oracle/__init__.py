@@ -2,7 +2,7 @@
 
 Only the test suite, the package smoke check and the benchmark's CPU-baseline
 leg may import this package.  It is a plain, slow, double-precision
-implementation written from the paper (Sec. III, Eq.(1)-(6)); see the header of
+implementation written from the paper (Sec. IV, Eq.(1)-(6)); see the header of
 ``dpt_oracle.c`` for the readings taken where the paper is silent.  It shares
 no code with the HIP library.
 
@@ -202,7 +202,7 @@ def make_camera(cam) -> Camera:
 
 
 class Reference:
-    """A reference frame with its IC precompute cache (Sec. III-C)."""
+    """A reference frame with its IC precompute cache (Sec. IV-C)."""
 
     def __init__(self, cam, params: Params, ref_img: np.ndarray, points: np.ndarray, T_rw: np.ndarray):
         lib = _load()

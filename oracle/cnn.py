@@ -4,7 +4,7 @@ Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
 import this module.  It shares no code with the HIP kernels.
 
 The network is not in the paper; it replaces the start pose of the paper's
-coarse-to-fine Gauss-Newton (Sec. III-A) with a learned guess.  Shape:
+coarse-to-fine Gauss-Newton (Sec. IV-A) with a learned guess.  Shape:
 input 2 x 60 x 94 (reference and current coarsest pyramid level, (I - 128) / 64),
 four 3x3 stride-2 padding-1 convolutions with ReLU (2-16-32-64-64 channels:
 30x47, 15x24, 8x12, 4x6), global average pool, FC 64-64 with ReLU, FC 64-6.

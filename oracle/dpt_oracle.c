@@ -5,13 +5,13 @@
  * benchmark's CPU-baseline leg load this code.  It shares no source, header,
  * table or helper with the HIP library, and neither side includes the other.
  *
- * What it follows (paper, Sec. III "Direct Photometric Tracking"):
+ * What it follows (paper, Sec. IV "Direct Photometric Tracking"):
  *   Eq.(1)  u0_i = pi(T0 P_i), u_i(T) = pi(T P_i)
  *   Eq.(2)  r_ik = I0(u0_i + d_k) - I(u_i(T) + d_k), bilinear sampling
  *   Eq.(3)  least-squares cost over points and patch pixels
  *   Eq.(4)-(5) Gauss-Newton linearisation, H delta = b, H = J^T J, b = -J^T r
  *   Eq.(6)  inverse-compositional Jacobian J_ik = grad I0(u0_i + d_k) dpi/dx dx/ddelta at x = T0 P_i
- *   Sec. III-C: pyramid, IC precompute per reference and level, per-level per-iteration
+ *   Sec. IV-C: pyramid, IC precompute per reference and level, per-level per-iteration
  *   track with reduction and a Cholesky solve, coarse to fine.
  *
  * Readings where the paper is silent (each restated where it is used):
@@ -337,7 +337,7 @@ static void orc_offsets(int W, int H, int L, int64_t* off) {
   }
 }
 
-/* IC precompute (Sec. III-C, "Precompute Inverse Compositional"): per level and point,
+/* IC precompute (Sec. IV-C, "Precompute Inverse Compositional"): per level and point,
  * project with T0, sample the reference patch and its gradients, and store I0 and
  * J_ik = grad I0 * Jw (Eq.6).  Also the per-level H of the paper's fixed-H mode. */
 orc_ref* orc_ref_create(const orc_camera* cam, const orc_params* prm, const uint8_t* ref_img, int64_t pitch,
@@ -495,7 +495,7 @@ void orc_ref_normal_equations(const orc_ref* R, const uint8_t* cur_img, int64_t 
 
 /* ------------------------------------------------------------------ tracker */
 
-/* Coarse-to-fine Gauss-Newton (Sec. III-A, Sec. III-C "Track"): at each level from the
+/* Coarse-to-fine Gauss-Newton (Sec. IV-A, Sec. IV-C "Track"): at each level from the
  * coarsest, up to max_iters linearisations, each solved by Cholesky and applied by
  * inverse composition; the pose of one level starts the next.  A final cost-only
  * pass at level 0 gives the mean robust cost that the switch criterion reads. */

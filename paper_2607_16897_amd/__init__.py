@@ -67,6 +67,10 @@ SIGNATURES = {
     "dpt_get_pyramid": (ctypes.c_int, [_vp, _i32, _i32, _vp]),
     "dpt_select_points": (ctypes.c_int, [_vp, _i32, _i32, _vp, ctypes.POINTER(_i32)]),
     "dpt_set_reference_points": (ctypes.c_int, [_vp, _vp, _i32, ctypes.POINTER(ctypes.c_double), _i32]),
+    "dpt_set_reference_from_depth": (ctypes.c_int, [_vp, _i32, _i32, _vp, _i64, _i32,
+                                                    ctypes.POINTER(ctypes.c_double)]),
+    "dpt_batch_set_reference_from_depth": (ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, _i64, _i32,
+                                                          ctypes.POINTER(ctypes.c_double)]),
     "dpt_track_frame": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(Result)]),
     "dpt_get_reference_cache": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, _vp, _vp]),
     "dpt_normal_equations": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ctypes.c_double), _vp, _vp,
@@ -206,6 +210,16 @@ class Tracker:
         _check(self._lib.dpt_set_reference_points(self._h, p, n, _mat(T_rw), dev))
         self.n_points = n
 
+    def set_reference_from_depth(self, n: int, depth, T_rw, margin: int = 8, pitch: int | None = None):
+        """Select n points on the REF level 0 and back-project them with `depth`
+        (float32 H x W, NumPy or a torch CUDA tensor), all on the stream."""
+        if isinstance(depth, np.ndarray):
+            depth = np.ascontiguousarray(depth, dtype=np.float32)
+        p, dev, keep = _ptr(depth)
+        pitch = self.cam.width if pitch is None else pitch
+        _check(self._lib.dpt_set_reference_from_depth(self._h, n, margin, p, pitch, dev, _mat(T_rw)))
+        self.n_points = n
+
     def track(self, T_cw_init) -> dict:
         r = Result()
         _check(self._lib.dpt_track_frame(self._h, _mat(T_cw_init), ctypes.byref(r)))
@@ -290,6 +304,14 @@ class BatchTracker:
             xyz = np.ascontiguousarray(xyz, dtype=np.float32).reshape(-1, 3)
         p, dev, keep = _ptr(xyz)
         _check(self._lib.dpt_batch_set_reference_points(self._h, s, p, int(xyz.shape[0]), _mat(T_rw), dev))
+
+    def set_reference_from_depth(self, s: int, n: int, depth, T_rw, margin: int = 8, pitch: int | None = None):
+        """As Tracker.set_reference_from_depth, for stream s."""
+        if isinstance(depth, np.ndarray):
+            depth = np.ascontiguousarray(depth, dtype=np.float32)
+        p, dev, keep = _ptr(depth)
+        pitch = self.cams[s].width if pitch is None else pitch
+        _check(self._lib.dpt_batch_set_reference_from_depth(self._h, s, n, margin, p, pitch, dev, _mat(T_rw)))
 
     def track(self, T_cw_init) -> list[dict]:
         T = np.ascontiguousarray(np.asarray(T_cw_init, np.float64).reshape(self.n, 16))

@@ -141,6 +141,10 @@ struct dpt_ctx {
   int32_t* sel_scratch = nullptr;
   TrackOut* d_out = nullptr;
   TrackOut* h_out = nullptr;  // pinned
+  float* h_pts = nullptr;        // pinned staging of host map points
+  hipEvent_t ev_pts = nullptr;   // the last upload out of h_pts
+  int32_t* h_sel = nullptr;      // pinned: selection count, then the indices
+  float* depth_stage = nullptr;  // device copy of a host depth map (allocated on first use)
   float* d_tot = nullptr;
   float* h_tot = nullptr;  // pinned
   Pattern pat;
@@ -154,6 +158,10 @@ struct dpt_ctx {
   ~dpt_ctx() {
     for (hipEvent_t e : ev)
       if (e) (void)hipEventDestroy(e);
+    if (ev_pts) (void)hipEventDestroy(ev_pts);
+    if (h_pts) (void)hipHostFree(h_pts);
+    if (h_sel) (void)hipHostFree(h_sel);
+    if (depth_stage) (void)hipFree(depth_stage);
     for (void* p : {(void*)pyr[0], (void*)pyr[1], (void*)staging, (void*)x0, (void*)valid, (void*)I0, (void*)gx,
                     (void*)gy, (void*)I0h, (void*)gh, (void*)pts, (void*)sel_idx, (void*)sel_count, (void*)sel_scratch, (void*)d_out,
                     (void*)d_tot})
@@ -275,7 +283,10 @@ int dpt_create(const dpt_camera* cam, const dpt_params* prm, int32_t max_points,
     return e;
   }
   if (hipHostMalloc((void**)&c->h_out, sizeof(TrackOut)) != hipSuccess ||
-      hipHostMalloc((void**)&c->h_tot, kRedSlots * sizeof(float)) != hipSuccess) {
+      hipHostMalloc((void**)&c->h_tot, kRedSlots * sizeof(float)) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_pts, cap * 3 * sizeof(float)) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_sel, (cap + 1) * sizeof(int32_t)) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_pts, hipEventDisableTiming) != hipSuccess) {
     (void)hipGetLastError();
     delete c;
     return fail(DPT_E_OOM, "pinned host allocation failed");
@@ -334,31 +345,29 @@ int dpt_select_points(dpt_ctx* c, int32_t n, int32_t margin, int32_t* host_idx, 
   if (margin < 1 || 2 * margin >= c->cam.width || 2 * margin >= c->cam.height) return fail(DPT_E_ARG, "margin %d", margin);
   if (!c->have_pyr[DPT_SLOT_REF]) return fail(DPT_E_STATE, "no reference pyramid");
   HIP_TRY(launch_select(c->pyr[DPT_SLOT_REF], c->cam.width, c->cam.height, margin, n, c->sel_idx, c->sel_count,
-                        c->sel_scratch,
-                        c->stream));
-  int32_t cnt = 0;
-  HIP_TRY(hipMemcpyAsync(&cnt, c->sel_count, sizeof cnt, hipMemcpyDeviceToHost, c->stream));
+                        c->sel_scratch, c->stream));
+  // count and the first min(n, cap) indices come back with one synchronisation
+  const int32_t first = n < c->cap ? n : c->cap;
+  HIP_TRY(hipMemcpyAsync(c->h_sel, c->sel_count, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->h_sel + 1, c->sel_idx, (size_t)first * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
+  const int32_t cnt = c->h_sel[0];
   if (cnt < 0 || cnt > n) return fail(DPT_E_HIP, "selection returned %d of %d", cnt, n);
-  if (cnt) {
-    HIP_TRY(hipMemcpyAsync(host_idx, c->sel_idx, (size_t)cnt * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
+  std::memcpy(host_idx, c->h_sel + 1, (size_t)std::min(cnt, first) * sizeof(int32_t));
+  if (cnt > first) {  // more points than the map holds (selection only): copy the rest directly
+    HIP_TRY(hipMemcpy(host_idx + first, c->sel_idx + first, (size_t)(cnt - first) * sizeof(int32_t),
+                      hipMemcpyDeviceToHost));
   }
   *n_out = cnt;
   return DPT_OK;
 }
 
-int dpt_set_reference_points(dpt_ctx* c, const float* xyz, int32_t n, const double T_rw[16], int32_t on_device) {
-  g_err.clear();
-  if (!c || !T_rw || (n > 0 && !xyz)) return fail(DPT_E_ARG, "NULL argument");
-  if (n < 0 || n > c->cap) return fail(DPT_E_ARG, "n %d outside [0, %d]", n, c->cap);
-  if (!finite16(T_rw)) return fail(DPT_E_ARG, "T_rw not finite");
-  if (!c->have_pyr[DPT_SLOT_REF]) return fail(DPT_E_STATE, "no reference pyramid");
-  const float* P = xyz;
-  if (n > 0 && !on_device) {
-    HIP_TRY(hipMemcpyAsync(c->pts, xyz, (size_t)n * 3 * sizeof(float), hipMemcpyHostToDevice, c->stream));
-    P = c->pts;
-  }
+}  // extern "C"
+
+namespace {
+
+// IC precompute of the reference cache from n device points P at T_rw.
+int precompute_reference(dpt_ctx* c, const float* P, int32_t n, const double T_rw[16]) {
   PrecomputeArgs a;
   std::memset(&a, 0, sizeof a);
   a.ref = c->pyr[DPT_SLOT_REF];
@@ -378,11 +387,72 @@ int dpt_set_reference_points(dpt_ctx* c, const float* xyz, int32_t n, const doub
   a.n = n;
   a.cap = c->cap;
   HIP_TRY(launch_precompute(a, c->stream));
-  if (!on_device) HIP_TRY(hipStreamSynchronize(c->stream));
   std::memcpy(c->T_rw, T_rw, sizeof c->T_rw);
   c->n_points = n;
   c->have_ref = true;
   return DPT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dpt_set_reference_points(dpt_ctx* c, const float* xyz, int32_t n, const double T_rw[16], int32_t on_device) {
+  g_err.clear();
+  if (!c || !T_rw || (n > 0 && !xyz)) return fail(DPT_E_ARG, "NULL argument");
+  if (n < 0 || n > c->cap) return fail(DPT_E_ARG, "n %d outside [0, %d]", n, c->cap);
+  if (!finite16(T_rw)) return fail(DPT_E_ARG, "T_rw not finite");
+  if (!c->have_pyr[DPT_SLOT_REF]) return fail(DPT_E_STATE, "no reference pyramid");
+  const float* P = xyz;
+  if (n > 0 && !on_device) {
+    // staged through pinned memory: the caller's buffer is free on return and
+    // the upload does not block; the staging buffer is reused only after the
+    // previous upload out of it has run
+    HIP_TRY(hipEventSynchronize(c->ev_pts));
+    std::memcpy(c->h_pts, xyz, (size_t)n * 3 * sizeof(float));
+    HIP_TRY(hipMemcpyAsync(c->pts, c->h_pts, (size_t)n * 3 * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipEventRecord(c->ev_pts, c->stream));
+    P = c->pts;
+  }
+  return precompute_reference(c, P, n, T_rw);
+}
+
+int dpt_set_reference_from_depth(dpt_ctx* c, int32_t n, int32_t margin, const float* depth, int64_t depth_pitch,
+                                 int32_t depth_on_device, const double T_rw[16]) {
+  g_err.clear();
+  if (!c || !depth || !T_rw) return fail(DPT_E_ARG, "NULL argument");
+  if (n < 1 || n > c->cap) return fail(DPT_E_ARG, "n %d outside [1, %d]", n, c->cap);
+  if (margin < 1 || 2 * margin >= c->cam.width || 2 * margin >= c->cam.height) return fail(DPT_E_ARG, "margin %d", margin);
+  if (depth_pitch < c->cam.width) return fail(DPT_E_ARG, "depth pitch %lld < width %d", (long long)depth_pitch, c->cam.width);
+  if (!finite16(T_rw)) return fail(DPT_E_ARG, "T_rw not finite");
+  if (!c->have_pyr[DPT_SLOT_REF]) return fail(DPT_E_STATE, "no reference pyramid");
+  const float* D = depth;
+  int64_t pitch = depth_pitch;
+  if (!depth_on_device) {
+    if (!c->depth_stage) {
+      const int e = dev_alloc((void**)&c->depth_stage, (size_t)c->cam.width * c->cam.height * sizeof(float));
+      if (e) return e;
+    }
+    HIP_TRY(hipMemcpy2DAsync(c->depth_stage, c->cam.width * sizeof(float), depth, depth_pitch * sizeof(float),
+                             c->cam.width * sizeof(float), c->cam.height, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));  // pageable source
+    D = c->depth_stage;
+    pitch = c->cam.width;
+  }
+  HIP_TRY(launch_select(c->pyr[DPT_SLOT_REF], c->cam.width, c->cam.height, margin, n, c->sel_idx, c->sel_count,
+                        c->sel_scratch, c->stream));
+  BackprojectArgs b;
+  b.idx = c->sel_idx;
+  b.count = c->sel_count;
+  b.depth = D;
+  b.pitch = pitch;
+  b.W = c->cam.width;
+  b.n = n;
+  b.fx = c->cam.fx, b.fy = c->cam.fy, b.cx = c->cam.cx, b.cy = c->cam.cy;
+  for (int j = 0; j < 12; ++j) b.T_rw[j] = T_rw[j];
+  b.P = c->pts;
+  HIP_TRY(launch_backproject(b, c->stream));
+  return precompute_reference(c, c->pts, n, T_rw);
 }
 
 }  // extern "C"
@@ -754,6 +824,16 @@ int dpt_batch_set_reference_points(dpt_batch* b, int32_t s, const float* xyz, in
   if (!b || s < 0 || s >= b->n) return fail(DPT_E_ARG, "stream index");
   const int before = b->ctx[s]->n_points;
   int e = dpt_set_reference_points(b->ctx[s], xyz, n, T_rw, on_device);
+  if (e == DPT_OK && before != n) b->groups_dirty = true;
+  return e;
+}
+
+int dpt_batch_set_reference_from_depth(dpt_batch* b, int32_t s, int32_t n, int32_t margin, const float* depth,
+                                       int64_t depth_pitch, int32_t depth_on_device, const double T_rw[16]) {
+  g_err.clear();
+  if (!b || s < 0 || s >= b->n) return fail(DPT_E_ARG, "stream %d", s);
+  const int before = b->ctx[s]->n_points;
+  int e = dpt_set_reference_from_depth(b->ctx[s], n, margin, depth, depth_pitch, depth_on_device, T_rw);
   if (e == DPT_OK && before != n) b->groups_dirty = true;
   return e;
 }

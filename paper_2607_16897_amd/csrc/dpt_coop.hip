@@ -242,10 +242,19 @@ static int coop_blocks_per_cu() {
 }
 
 int coop_max_blocks(int chunk) {
-  int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+  static int cu_count[64] = {};  // per device, queried once
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
     (void)hipGetLastError();
     return 0;
+  }
+  int cus = cu_count[dev];
+  if (cus == 0) {
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+      (void)hipGetLastError();
+      return 0;
+    }
+    cu_count[dev] = cus;
   }
   switch (chunk) {
     case 64: return coop_blocks_per_cu<64>() * cus;
@@ -255,12 +264,22 @@ int coop_max_blocks(int chunk) {
   }
 }
 
+// The chunks of a stream wait for each other, so all workgroups of the grid
+// must be resident together.  A grid of at most a quarter of the device's
+// co-resident capacity is launched as an ordinary kernel: it is resident as
+// soon as the device has that much room, which leaves room for three more such
+// launches running concurrently on other streams, and it avoids the
+// cooperative launch's extra per-launch cost (about 15 us here).  Larger grids
+// use the cooperative launch, which guarantees co-residency.  Either way every
+// wait is bounded by spin_limit, so a chunk that cannot be scheduled turns
+// into a reported timeout, not a hang.
 template <int CH>
 static hipError_t coop_launch_k(const CoopStream* d_streams, const int2* d_work, int n_work, const double* T_init,
                                 uint32_t tag_base, bool mixed, int spin_limit, hipStream_t s) {
   void* args[] = {(void*)&d_streams, (void*)&d_work, (void*)&T_init, (void*)&tag_base, (void*)&spin_limit};
   const void* fn = mixed ? reinterpret_cast<const void*>(&coop_track_kernel<CH, true>)
                          : reinterpret_cast<const void*>(&coop_track_kernel<CH, false>);
+  if (4 * n_work <= coop_max_blocks(CH)) return hipLaunchKernel(fn, dim3(n_work), dim3(CH), args, 0, s);
   return hipLaunchCooperativeKernel(fn, dim3(n_work), dim3(CH), args, 0, s);
 }
 

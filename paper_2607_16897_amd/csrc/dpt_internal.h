@@ -95,6 +95,18 @@ struct PrecomputeArgs {
   int32_t n, cap;
 };
 
+// Map points from selected level-0 pixels and a depth map (device memory).
+struct BackprojectArgs {
+  const int32_t* idx;    // [n] selected pixel indices y * W + x
+  const int32_t* count;  // how many of them are valid selections
+  const float* depth;    // level-0 depth in metres, row pitch `pitch` floats
+  int64_t pitch;
+  int32_t W, n;
+  double fx, fy, cx, cy;
+  double T_rw[12];       // reference camera <- world, row-major 3x4
+  float* P;              // [n][3] world points out
+};
+
 // One stream of a cooperative track launch (device array, one entry per stream).
 struct CoopStream {
   TrackArgs a;         // a.out points at this stream's TrackOut (host-mapped)
@@ -161,6 +173,7 @@ int64_t select_scratch_ints(int32_t W, int32_t H);
 hipError_t launch_select(const uint8_t* img, int32_t W, int32_t H, int32_t margin, int32_t n, int32_t* idx,
                          int32_t* count, int32_t* scratch, hipStream_t s);
 hipError_t launch_precompute(const PrecomputeArgs& a, hipStream_t s);
+hipError_t launch_backproject(const BackprojectArgs& a, hipStream_t s);
 hipError_t launch_track(const TrackArgs& a, hipStream_t s);
 // One workgroup per frame; batch[b] describes frame b (device memory).
 hipError_t launch_track_batch(const TrackArgs& any, const TrackArgs* batch, int n_frames, int lds_bytes,

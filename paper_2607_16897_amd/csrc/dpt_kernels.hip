@@ -82,6 +82,38 @@ hipError_t launch_precompute(const PrecomputeArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// One thread per selected pixel: P = R_rw^T (z K^-1 [x, y, 1]^T - t_rw) in FP64,
+// rounded to FP32.  A pixel without a positive finite depth, and every entry
+// past the selection count, becomes a NaN point, which the precompute marks
+// invalid at every level.
+__global__ __launch_bounds__(256) void backproject_kernel(BackprojectArgs a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const float nan = __int_as_float(0x7fc00000);
+  float out[3] = {nan, nan, nan};
+  if (i < *a.count) {
+    const int p = a.idx[i];
+    const int y = p / a.W, x = p - y * a.W;
+    const double z = (double)a.depth[(int64_t)y * a.pitch + x];
+    if (z > 0.0 && z < 1e30) {
+      const double d[3] = {((double)x - a.cx) / a.fx * z - a.T_rw[3], ((double)y - a.cy) / a.fy * z - a.T_rw[7],
+                           z - a.T_rw[11]};
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        out[j] = (float)(a.T_rw[j] * d[0] + a.T_rw[4 + j] * d[1] + a.T_rw[8 + j] * d[2]);
+    }
+  }
+  a.P[3 * i] = out[0];
+  a.P[3 * i + 1] = out[1];
+  a.P[3 * i + 2] = out[2];
+}
+
+hipError_t launch_backproject(const BackprojectArgs& a, hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(backproject_kernel, dim3((a.n + 255) / 256), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- track
 
 // Accumulate this thread's share of one normal-equation pass (Eq.(2), Eq.(5))

@@ -7,12 +7,13 @@
 // pixel (m + c % Wc, m + c / Wc), so candidate order is index order):
 //   A  per-chunk LDS histograms of s >> 9 (s <= 2 * 255^2 < 2^17), summed into a
 //      global 256-bin histogram with integer atomics (order-independent)
-//   B  one thread finds the coarse bucket of the n-th largest score
-//   C  512-bin histogram of the low bits inside that bucket
-//   D  one thread finds the exact threshold T and how many ties `need` to keep
-//   E  per-chunk counts of scores > T and == T
-//   F  one workgroup turns them into per-chunk output offsets and tie bases
-//   G  each chunk writes its selected indices with a block-wide prefix sum
+//   B  every workgroup finds the coarse bucket of the n-th largest score with
+//      one wave, then the 512-bin histogram of the low bits inside it
+//   C  every workgroup finds the exact threshold T and how many ties `need` to
+//      keep, then its chunk's counts of scores > T and == T
+//   D  every workgroup scans the chunk counts before it for its output offset
+//      and tie base, then writes its selected indices with a block-wide prefix
+//      sum; the last chunk writes the count
 #include "dpt_device.h"
 
 namespace dpt {
@@ -20,12 +21,12 @@ namespace dpt {
 constexpr int kSelThreads = 256, kSelPPT = 16, kSelChunk = kSelThreads * kSelPPT;
 
 struct SelScratch {  // layout of the int32 scratch buffer
-  static constexpr int kHist1 = 0, kHist2 = 256, kParams = 768, kChunks = 776;
+  static constexpr int kHist1 = 0, kHist2 = 256, kChunks = 768;
 };
 
 int64_t select_scratch_ints(int32_t W, int32_t H) {
   const int64_t G = ((int64_t)W * H + kSelChunk - 1) / kSelChunk + 1;
-  return SelScratch::kChunks + 4 * G;
+  return SelScratch::kChunks + 2 * G;
 }
 
 __device__ __forceinline__ int sel_score(const uint8_t* img, int W, int x, int y) {
@@ -44,6 +45,14 @@ __device__ __forceinline__ int cand_score(const SelGeom& g, int c) {
   return sel_score(g.img, g.W, g.m + c % g.Wc, g.m + c / g.Wc);
 }
 
+__global__ __launch_bounds__(kSelThreads) void sel_clear(int* __restrict__ sc) {
+  for (int b = threadIdx.x; b < SelScratch::kChunks; b += blockDim.x) sc[b] = 0;
+}
+
+__global__ void sel_zero_count(int32_t* __restrict__ count) {
+  if (threadIdx.x == 0) *count = 0;
+}
+
 __global__ __launch_bounds__(kSelThreads) void sel_hist_coarse(SelGeom g, int* __restrict__ sc) {
   __shared__ int h[256];
   for (int b = threadIdx.x; b < 256; b += blockDim.x) h[b] = 0;
@@ -58,31 +67,55 @@ __global__ __launch_bounds__(kSelThreads) void sel_hist_coarse(SelGeom g, int* _
     if (h[b]) atomicAdd(&sc[SelScratch::kHist1 + b], h[b]);
 }
 
-__global__ void sel_find_coarse(SelGeom g, int* __restrict__ sc) {
-  if (threadIdx.x != 0) return;
-  int* prm = sc + SelScratch::kParams;
-  if (g.C <= g.n) {  // take every candidate
-    prm[0] = -1, prm[1] = 0, prm[2] = -1, prm[3] = 0;
-    return;
+// One wave: the largest bin b with sum_{b' >= b} h[b'] >= n over NB bins
+// (NB / 64 per lane), given `above` candidates already counted in higher bins.
+// Returns b (or -1 if the total is short of n) and the count above b.
+template <int NB>
+__device__ __forceinline__ int2 wave_find_bin(const int* __restrict__ h, int n, int above) {
+  constexpr int PB = NB / 64;
+  const int lane = threadIdx.x & 63;
+  int v[PB], t = 0;
+#pragma unroll
+  for (int j = 0; j < PB; ++j) t += (v[j] = h[lane * PB + j]);
+  // suffix sum over the lanes above this one
+  int suf = t;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_down(suf, d, 64);
+    if (lane + d < 64) suf += y;
   }
-  int cum = 0, B = 0;
-  for (int b = 255; b >= 0; --b) {
-    const int hb = sc[SelScratch::kHist1 + b];
-    if (cum + hb >= g.n) {
-      B = b;
-      break;
+  int cum = above + suf - t;  // candidates in bins above this lane's
+  int found = -1, cum_at = 0;
+  if (cum < n && cum + t >= n) {
+#pragma unroll
+    for (int j = PB - 1; j >= 0; --j) {
+      if (found < 0 && cum + v[j] >= n) found = lane * PB + j, cum_at = cum;
+      if (found < 0) cum += v[j];
     }
-    cum += hb;
   }
-  prm[0] = B, prm[1] = cum;
+  const unsigned long long hit = __ballot(found >= 0);
+  if (hit == 0) return make_int2(-1, 0);
+  const int src = __ffsll((long long)hit) - 1;
+  return make_int2(__shfl(found, src, 64), __shfl(cum_at, src, 64));
+}
+
+// Coarse bucket B and the count above it (B = -1: take every candidate).
+__device__ __forceinline__ int2 coarse_bucket(const SelGeom& g, const int* sc) {
+  if (g.C <= g.n) return make_int2(-1, 0);
+  return wave_find_bin<256>(sc + SelScratch::kHist1, g.n, 0);
 }
 
 __global__ __launch_bounds__(kSelThreads) void sel_hist_fine(SelGeom g, int* __restrict__ sc) {
-  const int B = sc[SelScratch::kParams];
-  if (B < 0) return;
   __shared__ int h[512];
+  __shared__ int sB;
+  if (threadIdx.x < 64) {
+    const int2 r = coarse_bucket(g, sc);
+    if (threadIdx.x == 0) sB = r.x;
+  }
   for (int b = threadIdx.x; b < 512; b += blockDim.x) h[b] = 0;
   __syncthreads();
+  const int B = sB;
+  if (B < 0) return;
   const int c0 = blockIdx.x * kSelChunk;
   for (int q = threadIdx.x; q < kSelChunk; q += blockDim.x) {
     const int c = c0 + q;
@@ -96,27 +129,23 @@ __global__ __launch_bounds__(kSelThreads) void sel_hist_fine(SelGeom g, int* __r
     if (h[b]) atomicAdd(&sc[SelScratch::kHist2 + b], h[b]);
 }
 
-__global__ void sel_find_fine(SelGeom g, int* __restrict__ sc) {
-  if (threadIdx.x != 0) return;
-  int* prm = sc + SelScratch::kParams;
-  const int B = prm[0];
-  if (B < 0) return;
-  int cum = prm[1], T = B * 512, need = 0;
-  for (int f = 511; f >= 0; --f) {
-    const int hf = sc[SelScratch::kHist2 + f];
-    if (cum + hf >= g.n) {
-      T = B * 512 + f;
-      need = g.n - cum;
-      break;
-    }
-    cum += hf;
-  }
-  prm[2] = T, prm[3] = need;
+// Threshold T and the number of ties at T to keep (T = -1: take everything).
+__device__ __forceinline__ int2 threshold(const SelGeom& g, const int* sc) {
+  const int2 cb = coarse_bucket(g, sc);
+  if (cb.x < 0) return make_int2(-1, 0);
+  const int2 f = wave_find_bin<512>(sc + SelScratch::kHist2, g.n, cb.y);
+  return make_int2(cb.x * 512 + f.x, g.n - f.y);
 }
 
 __global__ __launch_bounds__(kSelThreads) void sel_count(SelGeom g, int* __restrict__ sc) {
   __shared__ int s_gt[kSelThreads / 64], s_eq[kSelThreads / 64];
-  const int T = sc[SelScratch::kParams + 2];
+  __shared__ int sT;
+  if (threadIdx.x < 64) {
+    const int2 r = threshold(g, sc);
+    if (threadIdx.x == 0) sT = r.x;
+  }
+  __syncthreads();
+  const int T = sT;
   const int c0 = blockIdx.x * kSelChunk;
   int gt = 0, eq = 0;
   for (int q = threadIdx.x; q < kSelChunk; q += blockDim.x) {
@@ -137,34 +166,49 @@ __global__ __launch_bounds__(kSelThreads) void sel_count(SelGeom g, int* __restr
   if (threadIdx.x == 0) {
     int a = 0, b = 0;
     for (int w = 0; w < kSelThreads / 64; ++w) a += s_gt[w], b += s_eq[w];
-    sc[SelScratch::kChunks + 4 * blockIdx.x] = a;
-    sc[SelScratch::kChunks + 4 * blockIdx.x + 1] = b;
+    sc[SelScratch::kChunks + 2 * blockIdx.x] = a;
+    sc[SelScratch::kChunks + 2 * blockIdx.x + 1] = b;
   }
 }
 
-// per-chunk tie base and output offset (chunk order = index order), and the count
-__global__ void sel_offsets(int G, int* __restrict__ sc, int32_t* __restrict__ count) {
-  if (threadIdx.x != 0) return;
-  const int need = sc[SelScratch::kParams + 3];
-  int tie = 0, out = 0;
-  for (int k = 0; k < G; ++k) {
-    int* e = sc + SelScratch::kChunks + 4 * k;
-    const int gt = e[0], eq = e[1];
-    int take = need - tie;
-    take = take < 0 ? 0 : (take > eq ? eq : take);
-    e[2] = tie;
-    e[3] = out;
-    tie += eq;
-    out += gt + take;
+// Sum over the chunks before this one of (gt + kept ties) and of eq, where a
+// chunk keeps clamp(need - ties before it, 0, eq) of its ties.  Each of the
+// 256 threads reduces a strided share of the earlier chunks: the ties before
+// chunk k are an exclusive prefix of eq, so the kept ties before this chunk
+// total min(need, ties before it).
+__device__ __forceinline__ int2 chunk_base(const int* sc, int G, int need, int* red) {
+  int gt = 0, eq = 0;
+  for (int k = threadIdx.x; k < G; k += blockDim.x) {
+    if (k < (int)blockIdx.x) {
+      gt += sc[SelScratch::kChunks + 2 * k];
+      eq += sc[SelScratch::kChunks + 2 * k + 1];
+    }
   }
-  *count = out;
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) {
+    gt += __shfl_xor(gt, d, 64);
+    eq += __shfl_xor(eq, d, 64);
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = gt, red[4 + (threadIdx.x >> 6)] = eq;
+  __syncthreads();
+  int a = 0, b = 0;
+  for (int w = 0; w < kSelThreads / 64; ++w) a += red[w], b += red[4 + w];
+  const int kept = need < b ? need : b;  // need >= 0
+  return make_int2(a + kept, b);        // output offset, tie base
 }
 
-__global__ __launch_bounds__(kSelThreads) void sel_write(SelGeom g, const int* __restrict__ sc,
-                                                         int32_t* __restrict__ idx) {
+__global__ __launch_bounds__(kSelThreads) void sel_write(SelGeom g, const int* __restrict__ sc, int G,
+                                                         int32_t* __restrict__ idx, int32_t* __restrict__ count) {
   __shared__ int wsum[16];
-  const int T = sc[SelScratch::kParams + 2], need = sc[SelScratch::kParams + 3];
-  const int* e = sc + SelScratch::kChunks + 4 * blockIdx.x;
+  __shared__ int red[8];
+  __shared__ int sT, sNeed;
+  if (threadIdx.x < 64) {
+    const int2 r = threshold(g, sc);
+    if (threadIdx.x == 0) sT = r.x, sNeed = r.y;
+  }
+  __syncthreads();
+  const int T = sT, need = sNeed;
+  const int2 base = chunk_base(sc, G, need, red);
   const int c0 = blockIdx.x * kSelChunk + threadIdx.x * kSelPPT;
   int s[kSelPPT];
   int eq_local = 0;
@@ -175,7 +219,7 @@ __global__ __launch_bounds__(kSelThreads) void sel_write(SelGeom g, const int* _
     eq_local += s[j] == T;
   }
   int tot;
-  int tie = block_exclusive_scan(eq_local, wsum, &tot) + e[2];
+  int tie = block_exclusive_scan(eq_local, wsum, &tot) + base.y;
   bool sel[kSelPPT];
   int sel_local = 0;
 #pragma unroll
@@ -185,13 +229,14 @@ __global__ __launch_bounds__(kSelThreads) void sel_write(SelGeom g, const int* _
     tie += is_eq;
     sel_local += sel[j];
   }
-  int pos = block_exclusive_scan(sel_local, wsum, &tot) + e[3];
+  int pos = block_exclusive_scan(sel_local, wsum, &tot) + base.x;
 #pragma unroll
   for (int j = 0; j < kSelPPT; ++j)
     if (sel[j]) {
       const int c = c0 + j;
       idx[pos++] = (g.m + c / g.Wc) * g.W + (g.m + c % g.Wc);
     }
+  if (blockIdx.x == G - 1 && threadIdx.x == 0) *count = base.x + tot;
 }
 
 hipError_t launch_select(const uint8_t* img, int32_t W, int32_t H, int32_t margin, int32_t n, int32_t* idx,
@@ -205,16 +250,16 @@ hipError_t launch_select(const uint8_t* img, int32_t W, int32_t H, int32_t margi
   g.C = (g.Wc > 0 && Hc > 0) ? g.Wc * Hc : 0;
   g.n = n;
   const int G = (g.C + kSelChunk - 1) / kSelChunk;
-  hipError_t e = hipMemsetAsync(scratch, 0, sizeof(int32_t) * SelScratch::kChunks, s);
-  if (e != hipSuccess) return e;
-  if (G == 0) return hipMemsetAsync(count, 0, sizeof(int32_t), s);
+  if (G == 0) {
+    hipLaunchKernelGGL(sel_zero_count, dim3(1), dim3(64), 0, s, count);
+    return hipGetLastError();
+  }
+  // histograms start at zero: cleared by a kernel, so the sequence can be captured
+  hipLaunchKernelGGL(sel_clear, dim3(1), dim3(kSelThreads), 0, s, scratch);
   hipLaunchKernelGGL(sel_hist_coarse, dim3(G), dim3(kSelThreads), 0, s, g, scratch);
-  hipLaunchKernelGGL(sel_find_coarse, dim3(1), dim3(64), 0, s, g, scratch);
   hipLaunchKernelGGL(sel_hist_fine, dim3(G), dim3(kSelThreads), 0, s, g, scratch);
-  hipLaunchKernelGGL(sel_find_fine, dim3(1), dim3(64), 0, s, g, scratch);
   hipLaunchKernelGGL(sel_count, dim3(G), dim3(kSelThreads), 0, s, g, scratch);
-  hipLaunchKernelGGL(sel_offsets, dim3(1), dim3(64), 0, s, G, scratch, count);
-  hipLaunchKernelGGL(sel_write, dim3(G), dim3(kSelThreads), 0, s, g, scratch, idx);
+  hipLaunchKernelGGL(sel_write, dim3(G), dim3(kSelThreads), 0, s, g, scratch, G, idx, count);
   return hipGetLastError();
 }
 

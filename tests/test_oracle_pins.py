@@ -28,7 +28,7 @@ def _hat(xi):
     return M
 
 
-# ------------------------------------------------------------------ pyramid (Sec. III-C)
+# ------------------------------------------------------------------ pyramid (Sec. IV-C)
 def test_pyramid_hand_example():
     g = json.load(open(os.path.join(GOLD, "pyramid_4x4.json")))
     levels = oracle.pyramid(np.array(g["image"], np.uint8), 3)
@@ -83,7 +83,7 @@ def test_selection_rendered():
     np.testing.assert_array_equal(oracle.select_points(d["ref"], 500, 8), _brute_select(d["ref"], 500, 8))
 
 
-# ------------------------------------------------------------------ sampling (Eq.(2), Sec. III-C)
+# ------------------------------------------------------------------ sampling (Eq.(2), Sec. IV-C)
 def test_bilinear_matches_map_coordinates():
     rng = np.random.default_rng(1)
     img = rng.integers(0, 256, (40, 50), dtype=np.uint8)
@@ -117,7 +117,7 @@ def test_gradient_is_interpolated_central_difference():
     np.testing.assert_allclose(got[:, 1], wy, atol=1e-12)
 
 
-# ------------------------------------------------------------------ SE(3) (Sec. III-A update)
+# ------------------------------------------------------------------ SE(3) (Sec. IV-A update)
 def test_exp_matches_expm():
     rng = np.random.default_rng(4)
     for scale in (1e-7, 1e-5, 3e-4, 0.1, 1.0, 2.5):
@@ -142,7 +142,7 @@ def test_log_inverts_exp():
                                [L[2, 1], L[0, 2], L[1, 0], L[0, 3], L[1, 3], L[2, 3]], atol=1e-10)
 
 
-# ------------------------------------------------------------------ Cholesky solve (Sec. III-C)
+# ------------------------------------------------------------------ Cholesky solve (Sec. IV-C)
 def test_cholesky_solve_matches_numpy():
     rng = np.random.default_rng(6)
     for _ in range(50):
@@ -292,7 +292,7 @@ def test_normal_equations_brute_force(k_huber):
 
 
 def test_fixed_h_equals_irls_without_weights():
-    """Paper mode (H reduced once per reference, Sec. III-B) equals the re-reduced H
+    """Paper mode (H reduced once per reference, Sec. IV-B) equals the re-reduced H
     when no weights apply and every reference-valid point stays valid."""
     d = synth.pair(12)
     P = synth.backproject(d["cam"], d["depth"], oracle.select_points(d["ref"], 200, 8), d["T_rw"])
@@ -317,7 +317,7 @@ def test_huber_weights_from_library_rho():
     np.testing.assert_allclose(np.linalg.eigvalsh(c["H"]).max() <= np.linalg.eigvalsh(a["H"]).max() + 1e-9, True)
 
 
-# ------------------------------------------------------------------ whole tracker (Sec. III-A, III-C)
+# ------------------------------------------------------------------ whole tracker (Sec. IV-A, IV-C)
 def _setup(seed, n=500, **kw):
     d = synth.pair(seed)
     idx = oracle.select_points(d["ref"], n, 8)
