@@ -416,11 +416,45 @@ def traffic_from_profile():
     return d.get("bytes_per_launch")
 
 
+def pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, kernel="coop_track_kernel"):
+    """HBM bytes per launch of `kernel` from two rocprofv3 --pmc runs (FETCH_SIZE,
+    WRITE_SIZE; KiB per dispatch), each scaled by what the same counter reads for
+    the plain copy of --calibrate-copy (bytes moved / counter bytes).  Writes the
+    summary the roofline's `traffic` field reads and prints it."""
+    import csv
+    import glob
+
+    def rows(d, counter):
+        f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
+        return [r for r in csv.DictReader(open(f)) if r["Counter_Name"] == counter]
+
+    def copy_factor(d, counter):
+        rs = [r for r in rows(d, counter) if "copyBuffer" in r["Kernel_Name"]]
+        nbytes = float(np.median([float(r["Counter_Value"]) for r in rs])) * 1024.0
+        return COPY_MIB * (1 << 20) / nbytes
+
+    ff, wf = copy_factor(copy_fetch_dir, "FETCH_SIZE"), copy_factor(copy_write_dir, "WRITE_SIZE")
+    fk = [float(r["Counter_Value"]) for r in rows(fetch_dir, "FETCH_SIZE") if kernel in r["Kernel_Name"]]
+    wk = [float(r["Counter_Value"]) for r in rows(write_dir, "WRITE_SIZE") if kernel in r["Kernel_Name"]]
+    fetch_b, write_b = float(np.mean(fk)) * 1024.0 * ff, float(np.mean(wk)) * 1024.0 * wf
+    out = {"kernel": kernel, "dispatches": [len(fk), len(wk)], "fetch_kib_per_dispatch_raw": float(np.mean(fk)),
+           "write_kib_per_dispatch_raw": float(np.mean(wk)), "copy_scale": {"fetch": ff, "write": wf},
+           "fetch_bytes_per_launch": fetch_b, "write_bytes_per_launch": write_b,
+           "bytes_per_launch": fetch_b + write_b, "kernel_source_sha": kernel_source_hash()}
+    with open(PMC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
+COPY_MIB = 256
+
+
 def calibrate_copy(mib: int):
     """A plain device copy of known size, for scaling FETCH_SIZE / WRITE_SIZE."""
     import torch
 
     n = mib << 20
+    torch.cuda.set_device(0)
     a = torch.empty(n, dtype=torch.uint8, device="cuda")
     b = torch.empty_like(a)
     a.fill_(1)
@@ -443,6 +477,10 @@ def main():
     ap.add_argument("--chunk", type=int, default=256)
     ap.add_argument("--batch-streams", type=int, default=64)
     ap.add_argument("--only-headline", action="store_true", help="skip the batched, precision and initialiser legs")
+    ap.add_argument("--legs", default="mixed,batched,init",
+                    help="legs after the headline: any of mixed, batched, init (comma separated)")
+    ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="write the track kernel's HBM traffic per launch from rocprofv3 --pmc output and exit")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -452,6 +490,10 @@ def main():
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy)
         return
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary)
+        return
+    legs = set() if args.only_headline else set(x for x in args.legs.split(",") if x)
 
     import torch
 
@@ -518,7 +560,7 @@ def main():
     nc = WINDOW - 1  # the first timed window of each leg is compared with the oracle
     comparisons = {"headline_fp32": ([(args.warmup % n_render, j) for j in range(1, WINDOW)], stats["init"][:nc],
                                      stats["T"][:nc], CAM, wins, N_POINTS, LEVELS)}
-    if not args.only_headline:
+    if "mixed" in legs:
         mp, st_m = bench_mixed_precision(dpt, synth, wins, dev, max(4, args.steps // 2))
         comparisons["headline_mixed"] = ([(1 % n_render, j) for j in range(1, WINDOW)], st_m["init"][:nc],
                                          st_m["T"][:nc], CAM, wins, N_POINTS, LEVELS)
@@ -529,11 +571,13 @@ def main():
                                                        st["T"][:nc], synth.CAM_1280, sw, 16000, 4)
         out["mixed_precision"] = mp
         print("# precision legs done", file=sys.stderr, flush=True)
+    if "batched" in legs:
         out["batched"] = {
             "sequences": bench_batched_sequences(dpt, synth, args.batch_streams, max(2, args.steps // 4), 1),
             "mixed": bench_batched_mixed(dpt, synth, args.batch_streams, 4, 2),
         }
         print("# batched legs done", file=sys.stderr, flush=True)
+    if "init" in legs:
         out["learned_init"] = bench_learned_init(dpt, args.batch_streams, 30)
         print("# initialiser leg done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
