@@ -110,37 +110,50 @@ def cv_init(prev2, prev1):
 
 
 def new_stats():
-    return {k: [] for k in ("track_ms", "pyr_ms", "samples", "iters", "status", "T", "init", "gt")}
+    return {k: [] for k in ("samples", "iters", "status", "T", "init", "gt")}
 
 
-def run_window_gpu(dpt, synth, trk, win, dev, stats, n_points, cam):
-    """One keyframe window: the reference refresh (pyramid, selection,
-    back-projection from the keyframe's depth and IC precompute, all on the
-    device), then 9 tracked frames.  dev = (device frames, device depth)."""
+SYNC_EVERY = 6  # windows in flight between synchronisations (6 x 9 tracks fit the 64-slot ring)
+
+
+def enqueue_window(dpt, trk, win, dev, n_points):
+    """One keyframe window, enqueued without waiting: the reference refresh
+    (pyramid, selection, back-projection from the keyframe's depth and IC
+    precompute, all on the device), the pose history (the frame before the
+    keyframe and the keyframe, true poses), then 9 frames each with its
+    pyramid and a track from the constant-velocity prediction, which the GPU
+    computes from the two previous poses.  dev = (device frames, device depth)."""
     dev_imgs, dev_depth = dev
     trk.build_pyramid(dpt.SLOT_REF, dev_imgs[0])
     trk.set_reference_from_depth(n_points, dev_depth, win["gts"][0])
-    prev2, prev1 = win["T_prev"], win["gts"][0]
+    trk.set_pose_history(win["T_prev"], win["gts"][0])
     for j in range(1, WINDOW):
         trk.build_pyramid(dpt.SLOT_CUR, dev_imgs[j])
-        init = cv_init(prev2, prev1)
-        r = trk.track(init)
-        prev2, prev1 = prev1, r["T_cw"]
-        if stats is not None:
-            pm, tm = trk.last_kernel_ms()
-            stats["track_ms"].append(tm)
-            stats["pyr_ms"].append(pm)
+        trk.track_enqueue(None)
+
+
+def collect(results, wins_done, stats):
+    """Per-frame statistics of synchronised windows; the start of each frame is
+    re-derived on the host (the same constant-velocity formula)."""
+    k = 0
+    for win in wins_done:
+        prev2, prev1 = win["T_prev"], win["gts"][0]
+        for j in range(1, WINDOW):
+            r = results[k]
+            k += 1
+            stats["init"].append(cv_init(prev2, prev1))
+            prev2, prev1 = prev1, r["T_cw"]
             stats["samples"].append(r["samples"])
             stats["iters"].append(r["iterations"])
             stats["status"].append(r["status"])
             stats["T"].append(r["T_cw"])
-            stats["init"].append(init)
             stats["gt"].append(win["gts"][j])
 
 
 def timed_plain(dpt, synth, wins, dev, steps, warmup, prm, launch, chunk, n_points=N_POINTS, cam=None):
-    """warmup + steps keyframe windows through one plain context; the first
-    timed window is wins[warmup % len(wins)]."""
+    """warmup + steps keyframe windows through one context, enqueued
+    asynchronously; the first timed window is wins[warmup % len(wins)].  Returns
+    (elapsed s, stats, profile totals of the timed region)."""
     import torch
 
     cam = cam or CAM
@@ -148,19 +161,27 @@ def timed_plain(dpt, synth, wins, dev, steps, warmup, prm, launch, chunk, n_poin
     trk.set_launch_config(launch, chunk)
     n = len(wins)
     for w in range(warmup):
-        run_window_gpu(dpt, synth, trk, wins[w % n], dev[w % n], None, n_points, cam)
+        enqueue_window(dpt, trk, wins[w % n], dev[w % n], n_points)
+    trk.synchronize()
     trk.set_profiling(True)
     stats = new_stats()
+    done, results = [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(steps):
         w = (warmup + s) % n
-        run_window_gpu(dpt, synth, trk, wins[w], dev[w], stats, n_points, cam)
+        enqueue_window(dpt, trk, wins[w], dev[w], n_points)
+        done.append(wins[w])
+        if len(done) % SYNC_EVERY == 0:
+            results += trk.synchronize()
+    results += trk.synchronize()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    prof = trk.profile()
     trk.set_profiling(False)
     trk.close()
-    return el, stats
+    collect(results, done, stats)
+    return el, stats, prof
 
 
 # ---------------------------------------------------------------- batched legs
@@ -179,42 +200,46 @@ def bench_batched_sequences(dpt, synth, n_streams: int, steps: int, warmup: int,
     torch.cuda.synchronize()
     prm = dpt.make_params(levels=LEVELS, max_iters=10, huber_k=9.0, step_eps=1e-5)
     bt = dpt.BatchTracker([CAM] * n_streams, prm, [N_POINTS] * n_streams)
-    stats = {"track_ms": [], "samples": [], "iters": [], "status": []}
+    stats = {"samples": [], "iters": [], "status": []}
 
-    def window(w, record):
+    def enqueue(w):
         bt.build_pyramids(dpt.SLOT_REF, [dev[s][w][0][0] for s in range(n_streams)])
         for s in range(n_streams):
             bt.set_reference_from_depth(s, N_POINTS, dev[s][w][1], wins[s][w]["gts"][0])
-        prev2 = np.stack([wins[s][w]["T_prev"] for s in range(n_streams)])
-        prev1 = np.stack([wins[s][w]["gts"][0] for s in range(n_streams)])
+            bt.set_pose_history(s, wins[s][w]["T_prev"], wins[s][w]["gts"][0])
         for j in range(1, WINDOW):
             bt.build_pyramids(dpt.SLOT_CUR, [dev[s][w][0][j] for s in range(n_streams)])
-            res = bt.track(prev1 @ np.linalg.inv(prev2) @ prev1)
-            prev2, prev1 = prev1, np.stack([r["T_cw"] for r in res])
-            if record:
-                stats["track_ms"].append(bt.last_kernel_ms()[1])
-                stats["samples"].append(sum(r["samples"] for r in res))
-                stats["iters"].extend(r["iterations"] for r in res)
-                stats["status"].extend(r["status"] for r in res)
-        return prev1
+            bt.track_enqueue(None)
 
-    # tune on the last frame of the first window, started from its estimates
-    last = window(0, False)
+    # tune on the last frame of the first window, started from the true poses
+    enqueue(0)
+    bt.synchronize()
     key = autotune.shape_key([CAM] * n_streams, [N_POINTS] * n_streams, LEVELS, 8)
-    mode, chunk, timings = autotune.tune(bt, last, key, cache=None)
+    mode, chunk, timings = autotune.tune(bt, np.stack([wins[s][0]["gts"][WINDOW - 1] for s in range(n_streams)]),
+                                         key, cache=None, candidates=autotune.COOP_CANDIDATES)
     for w in range(warmup):
-        window(w % n_win, False)
+        enqueue(w % n_win)
+    bt.synchronize()
     bt.set_profiling(True)
+    results = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for st in range(steps):
-        window((warmup + st) % n_win, True)
+        enqueue((warmup + st) % n_win)
+        if (st + 1) % SYNC_EVERY == 0:
+            results += bt.synchronize()
+    results += bt.synchronize()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    prof = bt.profile()
     bt.set_profiling(False)
     bt.close()
+    for res in results:
+        stats["samples"].append(sum(r["samples"] for r in res))
+        stats["iters"].extend(r["iterations"] for r in res)
+        stats["status"].extend(r["status"] for r in res)
     tracked = n_streams * (WINDOW - 1) * steps
-    track_ms = float(np.mean(stats["track_ms"]))
+    track_ms = prof["track_ms"] / prof["n_track"]
     samp_launch = float(np.mean(stats["samples"]))
     achieved = samp_launch * BYTES_PER_SAMPLE_F32 / (track_ms * 1e-3) / 1e9
     return {"workload": f"{n_streams} independent 752x480 sequences, 2000 points each, 4 levels, sigma=2, "
@@ -314,8 +339,8 @@ def bench_mixed_precision(dpt, synth, wins, dev, steps):
     """The headline workload through the mixed-precision variant (FP16 template
     cache, Kahan-compensated FP32 sums, FP64 solve, exponential and pose)."""
     prm = dpt.make_params(levels=LEVELS, max_iters=10, huber_k=9.0, step_eps=1e-5, precision=dpt.PREC_MIXED)
-    el, st = timed_plain(dpt, synth, wins, dev, steps, 1, prm, dpt.LAUNCH_COOP, 256)
-    track_ms = float(np.mean(st["track_ms"]))
+    el, st, prof = timed_plain(dpt, synth, wins, dev, steps, 1, prm, dpt.LAUNCH_COOP, 256)
+    track_ms = prof["track_ms"] / prof["n_track"]
     achieved = float(np.mean(st["samples"])) * BYTES_PER_SAMPLE_MIXED / (track_ms * 1e-3) / 1e9
     out = {"workload": "the headline workload, mixed precision", "frames_per_s": round(steps * (WINDOW - 1) / el, 2),
            "track_launch_ms": round(track_ms, 5), "iterations_per_frame": round(float(np.mean(st["iters"])), 3),
@@ -336,9 +361,9 @@ def bench_stress(dpt, synth):
     out, raw = {}, {}
     for name, prec in (("fp32", dpt.PREC_FP32), ("mixed", dpt.PREC_MIXED)):
         prm = dpt.make_params(levels=4, max_iters=10, huber_k=9.0, step_eps=1e-5, precision=prec)
-        el, st = timed_plain(dpt, synth, wins, dev, 2, 1, prm, dpt.LAUNCH_COOP, 256, n_points=16000, cam=cam)
+        el, st, prof = timed_plain(dpt, synth, wins, dev, 2, 1, prm, dpt.LAUNCH_COOP, 256, n_points=16000, cam=cam)
         out[name] = {"frames_per_s": round(2 * (WINDOW - 1) / el, 1),
-                     "track_launch_ms": round(float(np.mean(st["track_ms"])), 5),
+                     "track_launch_ms": round(prof["track_ms"] / prof["n_track"], 5),
                      "iterations_per_frame": round(float(np.mean(st["iters"])), 3),
                      "pose_error_vs_gt": err_summary([pose_error(T, G) for T, G in zip(st["T"], st["gt"])])}
         raw[name] = st
@@ -473,7 +498,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB")
-    ap.add_argument("--launch", choices=["auto", "workgroup", "coop"], default="coop")
+    ap.add_argument("--launch", choices=["auto", "coop"], default="coop",
+                    help="track launch (the GPU-side constant-velocity start needs the cooperative track)")
     ap.add_argument("--chunk", type=int, default=256)
     ap.add_argument("--batch-streams", type=int, default=64)
     ap.add_argument("--only-headline", action="store_true", help="skip the batched, precision and initialiser legs")
@@ -512,18 +538,18 @@ def main():
     torch.cuda.synchronize()
     print(f"# rendered {n_render} windows in {render_s:.1f} s", file=sys.stderr, flush=True)
 
-    launch = {"auto": dpt.LAUNCH_AUTO, "workgroup": dpt.LAUNCH_WORKGROUP, "coop": dpt.LAUNCH_COOP}[args.launch]
+    launch = {"auto": dpt.LAUNCH_AUTO, "coop": dpt.LAUNCH_COOP}[args.launch]
     prm = dpt.make_params(levels=LEVELS, max_iters=10, huber_k=9.0, step_eps=1e-5)
-    elapsed, stats = timed_plain(dpt, synth, wins, dev, args.steps, args.warmup, prm, launch, args.chunk)
+    elapsed, stats, prof = timed_plain(dpt, synth, wins, dev, args.steps, args.warmup, prm, launch, args.chunk)
     print(f"# headline leg done ({elapsed:.2f} s)", file=sys.stderr, flush=True)
 
     tracked = args.steps * (WINDOW - 1)
     samples = float(np.sum(stats["samples"]))
-    track_ms = float(np.mean(stats["track_ms"]))
+    track_ms = prof["track_ms"] / prof["n_track"]
     samp_launch = float(np.mean(stats["samples"]))
     alg_bytes = samp_launch * BYTES_PER_SAMPLE_F32
     achieved = alg_bytes / (track_ms * 1e-3) / 1e9
-    kname = "track_kernel<8, true>" if args.launch == "workgroup" else f"coop_track_kernel<{args.chunk}, false>"
+    kname = f"coop_track_kernel<{args.chunk}, false>"
     out = {
         "metric": METRIC,
         "value": round(tracked / elapsed, 2),
@@ -550,7 +576,8 @@ def main():
                      "avg_launch_ms": round(track_ms, 5),
                      "note": "one launch tracks one frame; a single stream is latency-bound by its ~16 dependent "
                              "Gauss-Newton iterations, each a grid-wide reduction"},
-        "kernels_ms": {"track_kernel": round(track_ms, 5), "pyramid_kernel": round(float(np.mean(stats["pyr_ms"])), 5)},
+        "kernels_ms": {"track_kernel": round(track_ms, 5),
+                       "pyramid_kernel": round(prof["pyramid_ms"] / max(prof["n_pyramid"], 1), 5)},
         "track_only_frames_per_s": round(1.0 / (track_ms * 1e-3), 1),
         "iterations_per_frame": round(float(np.mean(stats["iters"])), 3),
         "status_counts": {str(k): int(v) for k, v in zip(*np.unique(stats["status"], return_counts=True))},

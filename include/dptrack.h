@@ -150,6 +150,34 @@ int dpt_set_reference_from_depth(dpt_ctx* ctx, int32_t n, int32_t margin, const 
  * and fills *out. */
 int dpt_track_frame(dpt_ctx* ctx, const double T_cw_init[16], dpt_result* out);
 
+/* Start pose of an enqueued track. */
+enum { DPT_INIT_GIVEN = 0, DPT_INIT_CONST_VELOCITY = 1 };
+
+/* Asynchronous form of dpt_track_frame (the same computation, Sec. IV-C
+ * "Track"): enqueue the track of the CUR pyramid on the context's stream and
+ * return at once, so frames can follow each other without the host waiting
+ * between them (the paper keeps the tracker on the GPU to avoid CPU-GPU
+ * exchange, Sec. IV-C).  The start pose is T_cw_init (DPT_INIT_GIVEN) or the
+ * constant-velocity prediction T1 T0^-1 T1 from the context's pose history
+ * (DPT_INIT_CONST_VELOCITY, computed on the GPU in FP64; T_cw_init may be NULL).
+ * The history holds the last two poses: dpt_set_pose_history sets it, and every
+ * track on the cooperative path appends its result.  The constant-velocity
+ * start needs that path (K = 8, launch mode AUTO or COOP; DPT_E_ARG
+ * otherwise); on the one-workgroup path a DPT_INIT_GIVEN enqueue runs
+ * synchronously.  *out is written by the next dpt_synchronize (or any call
+ * that synchronises the context) and must stay valid until then.  At most 64
+ * tracks may be in flight (DPT_E_STATE beyond).  Later pyramid builds and
+ * reference updates on the same stream are ordered after the enqueued track. */
+int dpt_track_enqueue(dpt_ctx* ctx, int32_t init_mode, const double T_cw_init[16], dpt_result* out);
+
+/* Wait for the context's stream and fill the results of every enqueued track.
+ * Returns DPT_E_HIP if one of them timed out (its result has status 4). */
+int dpt_synchronize(dpt_ctx* ctx);
+
+/* Set the pose history used by DPT_INIT_CONST_VELOCITY (row-major 4x4 T_cw,
+ * older first), ordered on the stream with the tracks.  Initially identity. */
+int dpt_set_pose_history(dpt_ctx* ctx, const double T_older[16], const double T_newer[16]);
+
 /* Test hook: copies of level `level`'s IC cache.  Any pointer may be NULL.
  * valid: n bytes; I0, gx, gy: n*K floats (sample i*K+k); x0: n*3 floats. */
 int dpt_get_reference_cache(dpt_ctx* ctx, int32_t level, uint8_t* valid, float* I0, float* gx, float* gy, float* x0);
@@ -171,13 +199,16 @@ int dpt_normal_equations(dpt_ctx* ctx, int32_t level, const double T_rel[16], fl
 enum { DPT_LAUNCH_AUTO = 0, DPT_LAUNCH_WORKGROUP = 1, DPT_LAUNCH_COOP = 2 };
 int dpt_set_launch_config(dpt_ctx* ctx, int32_t mode, int32_t chunk);
 
-/* Profiling hook: when enabled, dpt_build_pyramid and dpt_track_frame bracket
- * their kernels with HIP events on the context's stream, and
- * dpt_last_kernel_ms returns the durations (ms) of the most recent pyramid and
- * track kernels (-1 if none was timed).  Off by default; enabling it adds two
- * event records per call. */
+/* Profiling hook: when enabled, pyramid builds and tracks bracket their
+ * kernels with HIP events on the context's stream.  dpt_last_kernel_ms
+ * returns the durations (ms) of the most recent pyramid and track kernels (-1
+ * if none was timed); dpt_get_profile the totals (ms) and counts since
+ * profiling was enabled.  Both synchronise the context.  Off by default;
+ * enabling it (which also synchronises and resets the totals) adds two event
+ * records per launch. */
 int dpt_set_profiling(dpt_ctx* ctx, int32_t enable);
 int dpt_last_kernel_ms(dpt_ctx* ctx, float* pyramid_ms, float* track_ms);
+int dpt_get_profile(dpt_ctx* ctx, double* pyramid_ms, int64_t* n_pyramid, double* track_ms, int64_t* n_track);
 
 /* ------------------------------------------------------------------ batched streams
  * Many independent camera streams tracked together: one pyramid launch for all
@@ -217,13 +248,21 @@ int dpt_batch_get_level(dpt_batch* b, int32_t slot, int32_t level, uint8_t* dst,
  * doubles; out: n_streams results.  Synchronises the stream. */
 int dpt_batch_track(dpt_batch* b, const double* T_cw_init, dpt_result* out);
 
+/* As dpt_track_enqueue / dpt_synchronize / dpt_set_pose_history, for every
+ * stream of the batch (T_cw_init: n_streams row-major 4x4 doubles, may be NULL
+ * with DPT_INIT_CONST_VELOCITY; out: n_streams results) or for stream `s`. */
+int dpt_batch_track_enqueue(dpt_batch* b, int32_t init_mode, const double* T_cw_init, dpt_result* out);
+int dpt_batch_synchronize(dpt_batch* b);
+int dpt_batch_set_pose_history(dpt_batch* b, int32_t s, const double T_older[16], const double T_newer[16]);
+
 /* Launch configuration as dpt_set_launch_config, for the whole batch. */
 int dpt_batch_set_launch_config(dpt_batch* b, int32_t mode, int32_t chunk);
 
-/* Profiling: duration (ms) of the last batched track launch sequence and of the
- * last batched pyramid launch, timed with HIP events on the batch's stream. */
+/* Profiling as dpt_set_profiling / dpt_last_kernel_ms / dpt_get_profile: a
+ * batched track launch sequence and a batched pyramid launch each count once. */
 int dpt_batch_set_profiling(dpt_batch* b, int32_t enable);
 int dpt_batch_last_kernel_ms(dpt_batch* b, float* pyramid_ms, float* track_ms);
+int dpt_batch_get_profile(dpt_batch* b, double* pyramid_ms, int64_t* n_pyramid, double* track_ms, int64_t* n_track);
 
 /* ------------------------------------------------------------------ learned initialiser
  * A small CNN proposes the reference-to-current twist from the coarsest pyramid

@@ -22,6 +22,7 @@ TRACK_OK, TRACK_MAX_ITERS, TRACK_TOO_FEW_POINTS, TRACK_NOT_PD = 0, 1, 2, 3
 PREC_FP32, PREC_MIXED = 0, 1
 SLOT_REF, SLOT_CUR = 0, 1
 LAUNCH_AUTO, LAUNCH_WORKGROUP, LAUNCH_COOP = 0, 1, 2
+INIT_GIVEN, INIT_CONST_VELOCITY = 0, 1
 DEFAULT_PATTERN = ((-2, 0), (2, 0), (0, -2), (0, 2), (-1, -1), (1, -1), (-1, 1), (1, 1))
 
 
@@ -72,6 +73,11 @@ SIGNATURES = {
     "dpt_batch_set_reference_from_depth": (ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, _i64, _i32,
                                                           ctypes.POINTER(ctypes.c_double)]),
     "dpt_track_frame": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(Result)]),
+    "dpt_track_enqueue": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ctypes.c_double), _vp]),
+    "dpt_synchronize": (ctypes.c_int, [_vp]),
+    "dpt_set_pose_history": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "dpt_get_profile": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64),
+                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]),
     "dpt_get_reference_cache": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, _vp, _vp]),
     "dpt_normal_equations": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ctypes.c_double), _vp, _vp,
                                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64),
@@ -84,6 +90,12 @@ SIGNATURES = {
     "dpt_batch_select_points": (ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, ctypes.POINTER(_i32)]),
     "dpt_batch_set_reference_points": (ctypes.c_int, [_vp, _i32, _vp, _i32, ctypes.POINTER(ctypes.c_double), _i32]),
     "dpt_batch_track": (ctypes.c_int, [_vp, _vp, _vp]),
+    "dpt_batch_track_enqueue": (ctypes.c_int, [_vp, _i32, _vp, _vp]),
+    "dpt_batch_synchronize": (ctypes.c_int, [_vp]),
+    "dpt_batch_set_pose_history": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ctypes.c_double),
+                                                  ctypes.POINTER(ctypes.c_double)]),
+    "dpt_batch_get_profile": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64),
+                                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]),
     "dpt_batch_set_launch_config": (ctypes.c_int, [_vp, _i32, _i32]),
     "dpt_batch_set_profiling": (ctypes.c_int, [_vp, _i32]),
     "dpt_batch_last_kernel_ms": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
@@ -109,6 +121,10 @@ def load():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; g.build()'`")
+        try:  # one HIP runtime per process: let the library bind to the one PyTorch ships
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         lib = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(lib, name)
@@ -177,6 +193,7 @@ class Tracker:
                                     ctypes.byref(h)))
         self._h = h
         self.n_points = 0
+        self._pending = []
 
     def close(self):
         if getattr(self, "_h", None):
@@ -225,6 +242,26 @@ class Tracker:
         _check(self._lib.dpt_track_frame(self._h, _mat(T_cw_init), ctypes.byref(r)))
         return r.as_dict()
 
+    def track_enqueue(self, T_cw_init=None):
+        """Enqueue a track without waiting: from T_cw_init, or (None) from the
+        constant-velocity prediction of the pose history.  Results come back, in
+        order, from synchronize()."""
+        r = Result()
+        if T_cw_init is None:
+            _check(self._lib.dpt_track_enqueue(self._h, INIT_CONST_VELOCITY, None, ctypes.byref(r)))
+        else:
+            _check(self._lib.dpt_track_enqueue(self._h, INIT_GIVEN, _mat(T_cw_init), ctypes.byref(r)))
+        self._pending.append(r)
+
+    def synchronize(self) -> list[dict]:
+        _check(self._lib.dpt_synchronize(self._h))
+        out = [r.as_dict() for r in self._pending]
+        self._pending = []
+        return out
+
+    def set_pose_history(self, T_older, T_newer):
+        _check(self._lib.dpt_set_pose_history(self._h, _mat(T_older), _mat(T_newer)))
+
     def set_launch_config(self, mode: int, chunk: int = 256):
         _check(self._lib.dpt_set_launch_config(self._h, mode, chunk))
 
@@ -236,6 +273,13 @@ class Tracker:
         a, b = ctypes.c_float(), ctypes.c_float()
         _check(self._lib.dpt_last_kernel_ms(self._h, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
+
+    def profile(self) -> dict:
+        """Totals (ms) and counts of the timed pyramid and track kernels."""
+        pm, pn, tm, tn = ctypes.c_double(), _i64(), ctypes.c_double(), _i64()
+        _check(self._lib.dpt_get_profile(self._h, ctypes.byref(pm), ctypes.byref(pn), ctypes.byref(tm),
+                                         ctypes.byref(tn)))
+        return dict(pyramid_ms=pm.value, n_pyramid=pn.value, track_ms=tm.value, n_track=tn.value)
 
     def reference_cache(self, level: int) -> dict:
         n, K = self.n_points, self.params.n_pattern
@@ -275,6 +319,7 @@ class BatchTracker:
         _check(self._lib.dpt_batch_create(self.n, ctypes.cast(self.cams, _vp), ctypes.byref(params),
                                           ctypes.cast(mp, _vp), self.stream, ctypes.byref(h)))
         self._h = h
+        self._pending = []
 
     def close(self):
         if getattr(self, "_h", None):
@@ -318,6 +363,33 @@ class BatchTracker:
         res = (Result * self.n)()
         _check(self._lib.dpt_batch_track(self._h, T.ctypes.data, ctypes.cast(res, _vp)))
         return [r.as_dict() for r in res]
+
+    def track_enqueue(self, T_cw_init=None):
+        """Enqueue a track of every stream without waiting: from T_cw_init (n x 4 x 4),
+        or (None) from each stream's constant-velocity prediction."""
+        res = (Result * self.n)()
+        if T_cw_init is None:
+            _check(self._lib.dpt_batch_track_enqueue(self._h, INIT_CONST_VELOCITY, None, ctypes.cast(res, _vp)))
+        else:
+            T = np.ascontiguousarray(np.asarray(T_cw_init, np.float64).reshape(self.n, 16))
+            _check(self._lib.dpt_batch_track_enqueue(self._h, INIT_GIVEN, T.ctypes.data, ctypes.cast(res, _vp)))
+        self._pending.append(res)
+
+    def synchronize(self) -> list[list[dict]]:
+        """Results of the enqueued tracks, in order: one list of n per enqueue."""
+        _check(self._lib.dpt_batch_synchronize(self._h))
+        out = [[r.as_dict() for r in res] for res in self._pending]
+        self._pending = []
+        return out
+
+    def set_pose_history(self, s: int, T_older, T_newer):
+        _check(self._lib.dpt_batch_set_pose_history(self._h, s, _mat(T_older), _mat(T_newer)))
+
+    def profile(self) -> dict:
+        pm, pn, tm, tn = ctypes.c_double(), _i64(), ctypes.c_double(), _i64()
+        _check(self._lib.dpt_batch_get_profile(self._h, ctypes.byref(pm), ctypes.byref(pn), ctypes.byref(tm),
+                                               ctypes.byref(tn)))
+        return dict(pyramid_ms=pm.value, n_pyramid=pn.value, track_ms=tm.value, n_track=tn.value)
 
     def set_launch_config(self, mode: int, chunk: int = 256):
         _check(self._lib.dpt_batch_set_launch_config(self._h, mode, chunk))

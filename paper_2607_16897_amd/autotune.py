@@ -18,6 +18,9 @@ import numpy as np
 from . import LAUNCH_COOP, LAUNCH_WORKGROUP
 
 CANDIDATES = ((LAUNCH_WORKGROUP, 256), (LAUNCH_COOP, 64), (LAUNCH_COOP, 128), (LAUNCH_COOP, 256))
+# the cooperative configurations only (the constant-velocity start computed on
+# the GPU needs the cooperative track)
+COOP_CANDIDATES = tuple(c for c in CANDIDATES if c[0] == LAUNCH_COOP)
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "dptrack", "autotune.json")
 
 
@@ -55,7 +58,8 @@ def _save(path, data):
     os.replace(tmp, path)
 
 
-def tune(tracker, T_init, key: str, reps: int = 5, cache: str | None = DEFAULT_CACHE, pose_tol: float = 1e-4):
+def tune(tracker, T_init, key: str, reps: int = 5, cache: str | None = DEFAULT_CACHE, pose_tol: float = 1e-4,
+         candidates=CANDIDATES):
     """Pick the fastest launch configuration for `tracker` (a Tracker or a
     BatchTracker, references and CUR pyramids already loaded) and apply it.
 
@@ -64,13 +68,13 @@ def tune(tracker, T_init, key: str, reps: int = 5, cache: str | None = DEFAULT_C
     choice for `key` is applied without timing."""
     if cache:
         stored = _load(cache).get(key)
-        if stored:
+        if stored and (stored["mode"], stored["chunk"]) in candidates:
             tracker.set_launch_config(stored["mode"], stored["chunk"])
             return stored["mode"], stored["chunk"], stored.get("timings", {})
     timings, poses = {}, {}
     tracker.set_profiling(True)
     try:
-        for mode, chunk in CANDIDATES:
+        for mode, chunk in candidates:
             try:
                 tracker.set_launch_config(mode, chunk)
                 res = tracker.track(T_init)

@@ -116,6 +116,77 @@ int dpt::set_error(int code, const char* msg) {
   return code;
 }
 
+namespace dpt {
+
+// Launch timing with HIP events: a ring of (start, end) pairs recorded on the
+// stream around each launch; a pair is drained into the totals once its end
+// event has completed.
+struct ProfRing {
+  static constexpr int kN = 2 * kRing;
+  hipEvent_t ev[kN][2] = {};
+  bool created = false;
+  int next = 0, n_pending = 0;  // pending pairs: the n_pending slots before `next`
+  double total_ms = 0.0;
+  int64_t count = 0;
+  float last_ms = -1.0f;
+
+  hipError_t create() {
+    if (created) return hipSuccess;
+    for (auto& p : ev)
+      for (hipEvent_t& e : p) {
+        const hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+      }
+    created = true;
+    return hipSuccess;
+  }
+  void destroy() {
+    for (auto& p : ev)
+      for (hipEvent_t& e : p)
+        if (e) (void)hipEventDestroy(e), e = nullptr;
+    created = false;
+  }
+  hipError_t drain_one() {
+    const int s = (next - n_pending + kN) % kN;
+    hipError_t e = hipEventSynchronize(ev[s][1]);
+    if (e != hipSuccess) return e;
+    float ms = 0.0f;
+    if ((e = hipEventElapsedTime(&ms, ev[s][0], ev[s][1])) != hipSuccess) return e;
+    total_ms += ms;
+    ++count;
+    last_ms = ms;
+    --n_pending;
+    return hipSuccess;
+  }
+  hipError_t begin(hipStream_t st, int* slot) {
+    if (n_pending == kN) {
+      const hipError_t e = drain_one();
+      if (e != hipSuccess) return e;
+    }
+    *slot = next;
+    next = (next + 1) % kN;
+    return hipEventRecord(ev[*slot][0], st);
+  }
+  hipError_t end(hipStream_t st, int slot) {
+    ++n_pending;
+    return hipEventRecord(ev[slot][1], st);
+  }
+  hipError_t drain() {
+    while (n_pending) {
+      const hipError_t e = drain_one();
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  void reset() {
+    total_ms = 0.0;
+    count = 0;
+    last_ms = -1.0f;
+  }
+};
+
+}  // namespace dpt
+
 struct dpt_ctx {
   dpt_camera cam;
   dpt_params prm;
@@ -149,15 +220,18 @@ struct dpt_ctx {
   float* h_tot = nullptr;  // pinned
   Pattern pat;
   bool prof = false;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // pyramid start/end, track start/end
-  bool ev_pyr = false, ev_trk = false;
+  ProfRing prof_pyr, prof_trk;  // pyramid and track launch timings
   int32_t launch_mode = DPT_LAUNCH_AUTO, chunk = 256;
   CoopEngine eng;
   bool eng_ready = false;
+  double* d_hist = nullptr;  // pose history: the last two T_cw, 2 x 3x4 FP64 (device)
+  std::vector<std::pair<int, dpt_result*>> pending;  // tracks in flight: (ring slot, caller's result)
+  int slot_next = 0;
 
   ~dpt_ctx() {
-    for (hipEvent_t e : ev)
-      if (e) (void)hipEventDestroy(e);
+    prof_pyr.destroy();
+    prof_trk.destroy();
+    if (d_hist) (void)hipFree(d_hist);
     if (ev_pts) (void)hipEventDestroy(ev_pts);
     if (h_pts) (void)hipHostFree(h_pts);
     if (h_sel) (void)hipHostFree(h_sel);
@@ -210,6 +284,7 @@ void rel_pose_f32(const dpt_ctx* c, const double* T_cw, float* out12) {
   double Tinv[16], Trel[16];
   invert(c->T_rw, Tinv);
   compose(T_cw, Tinv, Trel);
+  orthonormalize34(Trel);
   for (int j = 0; j < 12; ++j) out12[j] = (float)Trel[j];
 }
 
@@ -218,6 +293,7 @@ void rel_pose_f32(const dpt_ctx* c, const double* T_cw, double* out12) {
   invert(c->T_rw, Tinv);
   compose(T_cw, Tinv, Trel);
   for (int j = 0; j < 12; ++j) out12[j] = Trel[j];
+  orthonormalize34(out12);
 }
 
 }  // namespace
@@ -291,6 +367,16 @@ int dpt_create(const dpt_camera* cam, const dpt_params* prm, int32_t max_points,
     delete c;
     return fail(DPT_E_OOM, "pinned host allocation failed");
   }
+  if ((e = dev_alloc((void**)&c->d_hist, 24 * sizeof(double)))) {
+    delete c;
+    return e;
+  }
+  static const double kIdentity[12] = {1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0};
+  if (launch_set_history(c->d_hist, kIdentity, kIdentity, c->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    delete c;
+    return fail(DPT_E_HIP, "pose history initialisation failed");
+  }
   *out = c;
   return DPT_OK;
 }
@@ -314,12 +400,10 @@ int dpt_build_pyramid(dpt_ctx* c, int32_t slot, const uint8_t* img, int64_t pitc
     src = c->staging;
     sp = c->cam.width;
   }
-  if (c->prof) HIP_TRY(hipEventRecord(c->ev[0], c->stream));
+  int ps = -1;
+  if (c->prof) HIP_TRY(c->prof_pyr.begin(c->stream, &ps));
   HIP_TRY(launch_pyramid(src, sp, c->pyr[slot], c->pg, c->stream));
-  if (c->prof) {
-    HIP_TRY(hipEventRecord(c->ev[1], c->stream));
-    c->ev_pyr = true;
-  }
+  if (c->prof) HIP_TRY(c->prof_pyr.end(c->stream, ps));
   c->have_pyr[slot] = true;
   if (slot == DPT_SLOT_REF) c->have_ref = false;
   if (!img_on_device) HIP_TRY(hipStreamSynchronize(c->stream));  // the host buffer is only borrowed
@@ -467,62 +551,118 @@ bool use_coop(dpt_ctx* c) {
   return nch <= coop_max_blocks(c->chunk) / 8;  // the XCD-packed grid may hold up to 8x padding
 }
 
-int run_track(dpt_ctx* c, const double T_cw_init[16], const TrackOut** res) {
-  TrackArgs a;
-  fill_track_args(c, a);
-  if (use_coop(c)) {
-    const int nch = c->n_points > 0 ? (c->n_points + c->chunk - 1) / c->chunk : 1;
-    if (8 * nch > coop_max_blocks(c->chunk))
-      return fail(DPT_E_ARG, "%d points exceed the cooperative capacity at chunk %d", c->n_points, c->chunk);
-    if (!c->eng_ready) {
-      HIP_TRY(c->eng.init(1, &c->cap, c->chunk, true, c->stream));
-      c->eng.mixed = c->prm.precision == DPT_PREC_MIXED;
-      c->eng_ready = true;
-    }
-    if (c->eng.dirty || c->eng.h_streams[0].a.ref.n != c->n_points) c->eng.set_stream(0, a);
-    rel_pose_f32(c, T_cw_init, c->eng.h_T);
-    if (c->eng.dirty) HIP_TRY(c->eng.upload());  // outside the timed region
-    if (c->prof) HIP_TRY(hipEventRecord(c->ev[2], c->stream));
-    HIP_TRY(c->eng.launch(kSpinLimit));
-    if (c->prof) {
-      HIP_TRY(hipEventRecord(c->ev[3], c->stream));
-      c->ev_trk = true;
-    }
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    if (c->eng.h_out[0].status == 4) {
-      (void)c->eng.clear_partials();
-      (void)hipStreamSynchronize(c->stream);
-      return fail(DPT_E_HIP, "cooperative track: chunk synchronisation timed out");
-    }
-    *res = &c->eng.h_out[0];
-    return DPT_OK;
+// The context's single-stream cooperative engine, built on first use and
+// refreshed when the map changed size.
+int ensure_engine(dpt_ctx* c) {
+  const int nch = c->n_points > 0 ? (c->n_points + c->chunk - 1) / c->chunk : 1;
+  if (8 * nch > coop_max_blocks(c->chunk))
+    return fail(DPT_E_ARG, "%d points exceed the cooperative capacity at chunk %d", c->n_points, c->chunk);
+  if (!c->eng_ready) {
+    HIP_TRY(c->eng.init(1, &c->cap, c->chunk, true, c->stream));
+    c->eng.mixed = c->prm.precision == DPT_PREC_MIXED;
+    c->eng_ready = true;
   }
-  rel_pose_f32(c, T_cw_init, a.T_init);
-  if (c->prof) HIP_TRY(hipEventRecord(c->ev[2], c->stream));
-  HIP_TRY(launch_track(a, c->stream));
-  if (c->prof) {
-    HIP_TRY(hipEventRecord(c->ev[3], c->stream));
-    c->ev_trk = true;
+  if (c->eng.dirty || c->eng.h_streams[0].a.ref.n != c->n_points) {
+    TrackArgs a;
+    fill_track_args(c, a);
+    c->eng.set_stream(0, a, c->d_hist);
   }
-  HIP_TRY(hipMemcpyAsync(c->h_out, c->d_out, sizeof(TrackOut), hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(hipStreamSynchronize(c->stream));
-  *res = c->h_out;
+  if (c->eng.dirty) HIP_TRY(c->eng.upload());
   return DPT_OK;
 }
 
-void fill_result(const dpt_ctx* c, const TrackOut& o, dpt_result* out) {
-  double Trel[16];
-  for (int j = 0; j < 12; ++j) Trel[j] = c->prm.precision == DPT_PREC_MIXED ? o.Td[j] : (double)o.T[j];
+// Start slot of one stream for the context's current reference.
+void fill_start(const dpt_ctx* c, int mode, const double* T_cw_init, StartSlot* st) {
+  std::memset(st, 0, sizeof *st);
+  st->mode = mode;
+  if (mode == kStartGiven) rel_pose_f32(c, T_cw_init, st->T_rel);
+  for (int j = 0; j < 12; ++j) st->T_rw[j] = c->T_rw[j];
+}
+
+// Result of a finished track: T_cw = T_rel T_rw, with the reference pose the
+// track ran against (row-major, its first 12 entries).
+void fill_result(const dpt_ctx* c, const TrackOut& o, const double* T_rw, dpt_result* out) {
+  double Trel[16], Trw[16];
+  for (int j = 0; j < 12; ++j) {
+    Trel[j] = o.Td[j];
+    Trw[j] = T_rw[j];
+  }
   Trel[12] = Trel[13] = Trel[14] = 0.0;
   Trel[15] = 1.0;
+  Trw[12] = Trw[13] = Trw[14] = 0.0;
+  Trw[15] = 1.0;
   std::memset(out, 0, sizeof *out);
-  compose(Trel, c->T_rw, out->T_cw);
+  compose(Trel, Trw, out->T_cw);
   out->final_cost = o.n > 0 ? (double)o.E / (double)o.n : 0.0;
   out->iterations = o.iterations;
   for (int l = 0; l < kMaxLevels; ++l) out->iters_per_level[l] = o.iters_per_level[l];
   out->n_valid_points = o.n_valid_points;
   out->status = o.status;
   out->samples = o.samples;
+}
+
+// Enqueue one cooperative track; its result is filled at the next synchronize().
+int enqueue_coop(dpt_ctx* c, int mode, const double* T_cw_init, dpt_result* out) {
+  if ((int)c->pending.size() >= kRing)
+    return fail(DPT_E_STATE, "%d tracks in flight: synchronise first", kRing);
+  const int e = ensure_engine(c);
+  if (e != DPT_OK) return e;
+  const int slot = c->slot_next;
+  c->slot_next = (slot + 1) % kRing;
+  fill_start(c, mode, T_cw_init, c->eng.start(slot));
+  int ps = -1;
+  if (c->prof) HIP_TRY(c->prof_trk.begin(c->stream, &ps));
+  HIP_TRY(c->eng.launch(kSpinLimit, slot));
+  if (c->prof) HIP_TRY(c->prof_trk.end(c->stream, ps));
+  c->pending.emplace_back(slot, out);
+  return DPT_OK;
+}
+
+// Wait for the stream and fill the results of every track in flight.
+int synchronize(dpt_ctx* c) {
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  bool timeout = false;
+  for (const auto& p : c->pending) {
+    const TrackOut& o = c->eng.out(p.first)[0];
+    timeout |= o.status == kStatusTimeout;
+    if (p.second) fill_result(c, o, c->eng.start(p.first)[0].T_rw, p.second);
+  }
+  c->pending.clear();
+  if (c->prof) {
+    HIP_TRY(c->prof_pyr.drain());
+    HIP_TRY(c->prof_trk.drain());
+  }
+  if (timeout) {
+    (void)c->eng.clear_partials();
+    (void)hipStreamSynchronize(c->stream);
+    return fail(DPT_E_HIP, "cooperative track: chunk synchronisation timed out");
+  }
+  return DPT_OK;
+}
+
+// One-workgroup track (any pattern), synchronous.
+int track_workgroup(dpt_ctx* c, const double T_cw_init[16], dpt_result* out) {
+  TrackArgs a;
+  fill_track_args(c, a);
+  rel_pose_f32(c, T_cw_init, a.T_init);
+  int ps = -1;
+  if (c->prof) HIP_TRY(c->prof_trk.begin(c->stream, &ps));
+  HIP_TRY(launch_track(a, c->stream));
+  if (c->prof) HIP_TRY(c->prof_trk.end(c->stream, ps));
+  HIP_TRY(hipMemcpyAsync(c->h_out, c->d_out, sizeof(TrackOut), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (c->prof) {
+    HIP_TRY(c->prof_pyr.drain());
+    HIP_TRY(c->prof_trk.drain());
+  }
+  fill_result(c, *c->h_out, c->T_rw, out);
+  return DPT_OK;
+}
+
+int check_track_state(const dpt_ctx* c) {
+  if (!c->have_ref) return fail(DPT_E_STATE, "no reference points");
+  if (!c->have_pyr[DPT_SLOT_CUR]) return fail(DPT_E_STATE, "no current pyramid");
+  return DPT_OK;
 }
 
 }  // namespace
@@ -533,12 +673,44 @@ int dpt_track_frame(dpt_ctx* c, const double T_cw_init[16], dpt_result* out) {
   g_err.clear();
   if (!c || !T_cw_init || !out) return fail(DPT_E_ARG, "NULL argument");
   if (!finite16(T_cw_init)) return fail(DPT_E_ARG, "T_cw_init not finite");
-  if (!c->have_ref) return fail(DPT_E_STATE, "no reference points");
-  if (!c->have_pyr[DPT_SLOT_CUR]) return fail(DPT_E_STATE, "no current pyramid");
-  const TrackOut* o = nullptr;
-  int e = run_track(c, T_cw_init, &o);
+  int e = check_track_state(c);
   if (e != DPT_OK) return e;
-  fill_result(c, *o, out);
+  if (use_coop(c)) {
+    if ((e = enqueue_coop(c, kStartGiven, T_cw_init, out)) != DPT_OK) return e;
+    return synchronize(c);
+  }
+  if (!c->pending.empty() && (e = synchronize(c)) != DPT_OK) return e;
+  return track_workgroup(c, T_cw_init, out);
+}
+
+int dpt_track_enqueue(dpt_ctx* c, int32_t init_mode, const double T_cw_init[16], dpt_result* out) {
+  g_err.clear();
+  if (!c || !out) return fail(DPT_E_ARG, "NULL argument");
+  if (init_mode != DPT_INIT_GIVEN && init_mode != DPT_INIT_CONST_VELOCITY)
+    return fail(DPT_E_ARG, "init_mode %d", init_mode);
+  if (init_mode == DPT_INIT_GIVEN && (!T_cw_init || !finite16(T_cw_init)))
+    return fail(DPT_E_ARG, "T_cw_init missing or not finite");
+  int e = check_track_state(c);
+  if (e != DPT_OK) return e;
+  if (!use_coop(c)) {
+    if (init_mode == DPT_INIT_CONST_VELOCITY)
+      return fail(DPT_E_ARG, "a constant-velocity start needs the cooperative track (K = 8, launch mode AUTO or COOP)");
+    return dpt_track_frame(c, T_cw_init, out);
+  }
+  return enqueue_coop(c, init_mode == DPT_INIT_GIVEN ? kStartGiven : kStartConstVelocity, T_cw_init, out);
+}
+
+int dpt_synchronize(dpt_ctx* c) {
+  g_err.clear();
+  if (!c) return fail(DPT_E_ARG, "NULL context");
+  return synchronize(c);
+}
+
+int dpt_set_pose_history(dpt_ctx* c, const double T_older[16], const double T_newer[16]) {
+  g_err.clear();
+  if (!c || !T_older || !T_newer) return fail(DPT_E_ARG, "NULL argument");
+  if (!finite16(T_older) || !finite16(T_newer)) return fail(DPT_E_ARG, "pose not finite");
+  HIP_TRY(launch_set_history(c->d_hist, T_older, T_newer, c->stream));
   return DPT_OK;
 }
 
@@ -551,7 +723,8 @@ int dpt_set_launch_config(dpt_ctx* c, int32_t mode, int32_t chunk) {
   if (mode == DPT_LAUNCH_WORKGROUP && c->prm.precision == DPT_PREC_MIXED)
     return fail(DPT_E_ARG, "mixed precision runs on the cooperative launch only");
   if (chunk != c->chunk && c->eng_ready) {
-    HIP_TRY(hipStreamSynchronize(c->stream));
+    const int e = synchronize(c);
+    if (e != DPT_OK) return e;
     c->eng.release();
     c->eng_ready = false;
   }
@@ -604,20 +777,37 @@ int dpt_normal_equations(dpt_ctx* c, int32_t level, const double T_rel[16], floa
 int dpt_set_profiling(dpt_ctx* c, int32_t enable) {
   g_err.clear();
   if (!c) return fail(DPT_E_ARG, "NULL context");
-  if (enable && !c->ev[0])
-    for (hipEvent_t& e : c->ev) HIP_TRY(hipEventCreate(&e));
+  int e = synchronize(c);
+  if (e != DPT_OK) return e;
+  if (enable) {
+    HIP_TRY(c->prof_pyr.create());
+    HIP_TRY(c->prof_trk.create());
+  }
+  c->prof_pyr.reset();
+  c->prof_trk.reset();
   c->prof = enable != 0;
-  c->ev_pyr = c->ev_trk = false;
   return DPT_OK;
 }
 
 int dpt_last_kernel_ms(dpt_ctx* c, float* pyramid_ms, float* track_ms) {
   g_err.clear();
   if (!c || !pyramid_ms || !track_ms) return fail(DPT_E_ARG, "NULL argument");
-  *pyramid_ms = *track_ms = -1.0f;
-  HIP_TRY(hipStreamSynchronize(c->stream));
-  if (c->ev_pyr) HIP_TRY(hipEventElapsedTime(pyramid_ms, c->ev[0], c->ev[1]));
-  if (c->ev_trk) HIP_TRY(hipEventElapsedTime(track_ms, c->ev[2], c->ev[3]));
+  const int e = synchronize(c);
+  if (e != DPT_OK) return e;
+  *pyramid_ms = c->prof_pyr.last_ms;
+  *track_ms = c->prof_trk.last_ms;
+  return DPT_OK;
+}
+
+int dpt_get_profile(dpt_ctx* c, double* pyramid_ms, int64_t* n_pyramid, double* track_ms, int64_t* n_track) {
+  g_err.clear();
+  if (!c || !pyramid_ms || !n_pyramid || !track_ms || !n_track) return fail(DPT_E_ARG, "NULL argument");
+  const int e = synchronize(c);
+  if (e != DPT_OK) return e;
+  *pyramid_ms = c->prof_pyr.total_ms;
+  *n_pyramid = c->prof_pyr.count;
+  *track_ms = c->prof_trk.total_ms;
+  *n_track = c->prof_trk.count;
   return DPT_OK;
 }
 
@@ -635,15 +825,19 @@ struct dpt_batch {
   std::vector<std::vector<int>> group_streams;
   bool groups_dirty = true;
   // pyramid jobs
-  PyrJob* d_jobs = nullptr;
-  PyrJob* h_jobs = nullptr;  // pinned
+  PyrJob* d_jobs = nullptr;  // two tables of n jobs, used alternately
+  PyrJob* h_jobs = nullptr;  // pinned, two tables
+  hipEvent_t ev_jobs[2] = {nullptr, nullptr};  // each table's last upload
+  int jobs_next = 0;
   // one-workgroup-per-stream launch
   TrackArgs* d_args = nullptr;
   TrackArgs* h_args = nullptr;  // pinned
   TrackOut* d_outs = nullptr;
   TrackOut* h_outs = nullptr;  // pinned
-  bool prof = false, ev_pyr = false, ev_trk = false;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool prof = false;
+  ProfRing prof_pyr, prof_trk;
+  std::vector<std::pair<int, dpt_result*>> pending;  // tracks in flight: (ring slot, caller's n results)
+  int slot_next = 0;
 
   void clear_groups() {
     for (CoopEngine* g : groups) delete g;
@@ -655,7 +849,9 @@ struct dpt_batch {
     (void)hipStreamSynchronize(stream);
     clear_groups();
     for (dpt_ctx* c : ctx) delete c;
-    for (hipEvent_t e : ev)
+    prof_pyr.destroy();
+    prof_trk.destroy();
+    for (hipEvent_t e : ev_jobs)
       if (e) (void)hipEventDestroy(e);
     if (d_jobs) (void)hipFree(d_jobs);
     if (d_args) (void)hipFree(d_args);
@@ -699,7 +895,7 @@ int build_groups(dpt_batch* b) {
     for (size_t k = 0; k < cur.size(); ++k) {
       TrackArgs a;
       fill_track_args(b->ctx[cur[k]], a);
-      g->set_stream((int)k, a);
+      g->set_stream((int)k, a, b->ctx[cur[k]]->d_hist);
     }
     b->groups.push_back(g);
     b->group_streams.push_back(cur);
@@ -729,6 +925,96 @@ bool batch_use_coop(const dpt_batch* b) {
   return b->launch_mode != DPT_LAUNCH_WORKGROUP && b->ctx[0]->prm.n_pattern == 8 && coop_max_blocks(b->chunk) > 0;
 }
 
+// Wait for the stream and fill the results of every batched track in flight.
+int batch_synchronize(dpt_batch* b) {
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  bool timeout = false;
+  for (const auto& p : b->pending) {
+    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+      const std::vector<int>& ss = b->group_streams[gi];
+      const TrackOut* o = b->groups[gi]->out(p.first);
+      const StartSlot* st = b->groups[gi]->start(p.first);
+      for (size_t k = 0; k < ss.size(); ++k) {
+        timeout |= o[k].status == kStatusTimeout;
+        if (p.second) fill_result(b->ctx[ss[k]], o[k], st[k].T_rw, &p.second[ss[k]]);
+      }
+    }
+  }
+  b->pending.clear();
+  if (b->prof) {
+    HIP_TRY(b->prof_pyr.drain());
+    HIP_TRY(b->prof_trk.drain());
+  }
+  if (timeout) {
+    for (CoopEngine* g : b->groups) (void)g->clear_partials();
+    (void)hipStreamSynchronize(b->stream);
+    return fail(DPT_E_HIP, "cooperative batch track: chunk synchronisation timed out");
+  }
+  return DPT_OK;
+}
+
+// Enqueue one cooperative track of every stream.  modes[s] is kStartGiven
+// (start from T_cw_init[s]) or kStartConstVelocity.
+int batch_enqueue_coop(dpt_batch* b, const int* modes, const double* T_cw_init, dpt_result* out) {
+  if (b->groups_dirty) {  // regrouping frees the rings: finish what is in flight first
+    int e = batch_synchronize(b);
+    if (e != DPT_OK) return e;
+    if ((e = build_groups(b)) != DPT_OK) return e;
+  }
+  if ((int)b->pending.size() >= kRing) return fail(DPT_E_STATE, "%d batched tracks in flight: synchronise first", kRing);
+  for (CoopEngine* g : b->groups)
+    if (g->dirty) HIP_TRY(g->upload());
+  const int slot = b->slot_next;
+  b->slot_next = (slot + 1) % kRing;
+  for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+    const std::vector<int>& ss = b->group_streams[gi];
+    StartSlot* st = b->groups[gi]->start(slot);
+    for (size_t k = 0; k < ss.size(); ++k)
+      fill_start(b->ctx[ss[k]], modes[ss[k]], T_cw_init ? T_cw_init + 16 * ss[k] : nullptr, &st[k]);
+  }
+  int ps = -1;
+  if (b->prof) HIP_TRY(b->prof_trk.begin(b->stream, &ps));
+  for (CoopEngine* g : b->groups) HIP_TRY(g->launch(kSpinLimit, slot));
+  if (b->prof) HIP_TRY(b->prof_trk.end(b->stream, ps));
+  b->pending.emplace_back(slot, out);
+  return DPT_OK;
+}
+
+int batch_check_state(const dpt_batch* b) {
+  for (int s = 0; s < b->n; ++s) {
+    if (!b->ctx[s]->have_ref) return fail(DPT_E_STATE, "stream %d has no reference points", s);
+    if (!b->ctx[s]->have_pyr[DPT_SLOT_CUR]) return fail(DPT_E_STATE, "stream %d has no current pyramid", s);
+  }
+  return DPT_OK;
+}
+
+// One workgroup per stream, synchronous.
+int batch_track_workgroup(dpt_batch* b, const double* T_cw_init, dpt_result* out) {
+  int lds = 0, max_points = 0;
+  for (int s = 0; s < b->n; ++s) {
+    dpt_ctx* c = b->ctx[s];
+    TrackArgs& a = b->h_args[s];
+    fill_track_args(c, a);
+    rel_pose_f32(c, T_cw_init + 16 * s, a.T_init);
+    a.out = b->d_outs + s;
+    lds = std::max(lds, track_lds_bytes(c->lv, c->prm.levels));
+    max_points = std::max(max_points, c->n_points);
+  }
+  HIP_TRY(hipMemcpyAsync(b->d_args, b->h_args, sizeof(TrackArgs) * b->n, hipMemcpyHostToDevice, b->stream));
+  int ps = -1;
+  if (b->prof) HIP_TRY(b->prof_trk.begin(b->stream, &ps));
+  HIP_TRY(launch_track_batch(b->h_args[0], b->d_args, b->n, lds, max_points, b->stream));
+  if (b->prof) HIP_TRY(b->prof_trk.end(b->stream, ps));
+  HIP_TRY(hipMemcpyAsync(b->h_outs, b->d_outs, sizeof(TrackOut) * b->n, hipMemcpyDeviceToHost, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  if (b->prof) {
+    HIP_TRY(b->prof_pyr.drain());
+    HIP_TRY(b->prof_trk.drain());
+  }
+  for (int s = 0; s < b->n; ++s) fill_result(b->ctx[s], b->h_outs[s], b->ctx[s]->T_rw, &out[s]);
+  return DPT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -752,10 +1038,12 @@ int dpt_batch_create(int32_t n_streams, const dpt_camera* cams, const dpt_params
     }
     b->ctx.push_back(c);
   }
-  if (hipMalloc(&b->d_jobs, sizeof(PyrJob) * n_streams) != hipSuccess ||
+  if (hipMalloc(&b->d_jobs, 2 * sizeof(PyrJob) * n_streams) != hipSuccess ||
       hipMalloc(&b->d_args, sizeof(TrackArgs) * n_streams) != hipSuccess ||
       hipMalloc(&b->d_outs, sizeof(TrackOut) * n_streams) != hipSuccess ||
-      hipHostMalloc(&b->h_jobs, sizeof(PyrJob) * n_streams) != hipSuccess ||
+      hipHostMalloc(&b->h_jobs, 2 * sizeof(PyrJob) * n_streams) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_jobs[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_jobs[1], hipEventDisableTiming) != hipSuccess ||
       hipHostMalloc(&b->h_args, sizeof(TrackArgs) * n_streams) != hipSuccess ||
       hipHostMalloc(&b->h_outs, sizeof(TrackOut) * n_streams) != hipSuccess) {
     (void)hipGetLastError();
@@ -773,6 +1061,12 @@ int dpt_batch_build_pyramids(dpt_batch* b, int32_t slot, const uint8_t* const* i
   g_err.clear();
   if (!b || !imgs || !pitches) return fail(DPT_E_ARG, "NULL argument");
   if (slot != DPT_SLOT_REF && slot != DPT_SLOT_CUR) return fail(DPT_E_ARG, "slot %d", slot);
+  // alternate job tables: the one written now was uploaded two calls ago
+  const int jt = b->jobs_next;
+  b->jobs_next ^= 1;
+  HIP_TRY(hipEventSynchronize(b->ev_jobs[jt]));
+  PyrJob* h_jobs = b->h_jobs + (size_t)jt * b->n;
+  PyrJob* d_jobs = b->d_jobs + (size_t)jt * b->n;
   int max_w = 0, max_h = 0;
   for (int s = 0; s < b->n; ++s) {
     dpt_ctx* c = b->ctx[s];
@@ -786,7 +1080,7 @@ int dpt_batch_build_pyramids(dpt_batch* b, int32_t slot, const uint8_t* const* i
       src = c->staging;
       sp = c->cam.width;
     }
-    PyrJob& j = b->h_jobs[s];
+    PyrJob& j = h_jobs[s];
     j.src = src;
     j.pitch = sp;
     j.dst = c->pyr[slot];
@@ -796,15 +1090,13 @@ int dpt_batch_build_pyramids(dpt_batch* b, int32_t slot, const uint8_t* const* i
     max_w = std::max(max_w, c->cam.width);
     max_h = std::max(max_h, c->cam.height);
   }
-  HIP_TRY(hipMemcpyAsync(b->d_jobs, b->h_jobs, sizeof(PyrJob) * b->n, hipMemcpyHostToDevice, b->stream));
-  if (b->prof) HIP_TRY(hipEventRecord(b->ev[0], b->stream));
-  HIP_TRY(launch_pyramid_batch(b->d_jobs, b->n, max_w, max_h, b->ctx[0]->prm.levels, b->stream));
-  if (b->prof) {
-    HIP_TRY(hipEventRecord(b->ev[1], b->stream));
-    b->ev_pyr = true;
-  }
-  // the pinned job table is reused by the next call: wait until the copy has been consumed
-  HIP_TRY(hipStreamSynchronize(b->stream));
+  HIP_TRY(hipMemcpyAsync(d_jobs, h_jobs, sizeof(PyrJob) * b->n, hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(hipEventRecord(b->ev_jobs[jt], b->stream));
+  int ps = -1;
+  if (b->prof) HIP_TRY(b->prof_pyr.begin(b->stream, &ps));
+  HIP_TRY(launch_pyramid_batch(d_jobs, b->n, max_w, max_h, b->ctx[0]->prm.levels, b->stream));
+  if (b->prof) HIP_TRY(b->prof_pyr.end(b->stream, ps));
+  if (!on_device) HIP_TRY(hipStreamSynchronize(b->stream));  // the host images are only borrowed
   for (int s = 0; s < b->n; ++s) {
     b->ctx[s]->have_pyr[slot] = true;
     if (slot == DPT_SLOT_REF) b->ctx[s]->have_ref = false;
@@ -841,66 +1133,50 @@ int dpt_batch_set_reference_from_depth(dpt_batch* b, int32_t s, int32_t n, int32
 int dpt_batch_track(dpt_batch* b, const double* T_cw_init, dpt_result* out) {
   g_err.clear();
   if (!b || !T_cw_init || !out) return fail(DPT_E_ARG, "NULL argument");
-  for (int s = 0; s < b->n; ++s) {
+  for (int s = 0; s < b->n; ++s)
     if (!finite16(T_cw_init + 16 * s)) return fail(DPT_E_ARG, "T_cw_init %d not finite", s);
-    if (!b->ctx[s]->have_ref) return fail(DPT_E_STATE, "stream %d has no reference points", s);
-    if (!b->ctx[s]->have_pyr[DPT_SLOT_CUR]) return fail(DPT_E_STATE, "stream %d has no current pyramid", s);
-  }
+  int e = batch_check_state(b);
+  if (e != DPT_OK) return e;
   if (batch_use_coop(b)) {
-    if (b->groups_dirty) {
-      int e = build_groups(b);
-      if (e != DPT_OK) return e;
-    }
-    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
-      const std::vector<int>& ss = b->group_streams[gi];
-      for (size_t k = 0; k < ss.size(); ++k) rel_pose_f32(b->ctx[ss[k]], T_cw_init + 16 * ss[k], b->groups[gi]->h_T + 12 * k);
-    }
-    for (CoopEngine* g : b->groups)
-      if (g->dirty) HIP_TRY(g->upload());  // outside the timed region
-    if (b->prof) HIP_TRY(hipEventRecord(b->ev[2], b->stream));
-    for (CoopEngine* g : b->groups) HIP_TRY(g->launch(kSpinLimit));
-    if (b->prof) {
-      HIP_TRY(hipEventRecord(b->ev[3], b->stream));
-      b->ev_trk = true;
-    }
-    HIP_TRY(hipStreamSynchronize(b->stream));
-    bool timeout = false;
-    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
-      const std::vector<int>& ss = b->group_streams[gi];
-      for (size_t k = 0; k < ss.size(); ++k) {
-        const TrackOut& o = b->groups[gi]->h_out[k];
-        if (o.status == 4) timeout = true;
-        fill_result(b->ctx[ss[k]], o, &out[ss[k]]);
-      }
-    }
-    if (timeout) {
-      for (CoopEngine* g : b->groups) (void)g->clear_partials();
-      (void)hipStreamSynchronize(b->stream);
-      return fail(DPT_E_HIP, "cooperative batch track: chunk synchronisation timed out");
-    }
-    return DPT_OK;
+    std::vector<int> modes(b->n, kStartGiven);
+    if ((e = batch_enqueue_coop(b, modes.data(), T_cw_init, out)) != DPT_OK) return e;
+    return batch_synchronize(b);
   }
-  int lds = 0, max_points = 0;
-  for (int s = 0; s < b->n; ++s) {
-    dpt_ctx* c = b->ctx[s];
-    TrackArgs& a = b->h_args[s];
-    fill_track_args(c, a);
-    rel_pose_f32(c, T_cw_init + 16 * s, a.T_init);
-    a.out = b->d_outs + s;
-    lds = std::max(lds, track_lds_bytes(c->lv, c->prm.levels));
-    max_points = std::max(max_points, c->n_points);
+  if (!b->pending.empty() && (e = batch_synchronize(b)) != DPT_OK) return e;
+  return batch_track_workgroup(b, T_cw_init, out);
+}
+
+int dpt_batch_track_enqueue(dpt_batch* b, int32_t init_mode, const double* T_cw_init, dpt_result* out) {
+  g_err.clear();
+  if (!b || !out) return fail(DPT_E_ARG, "NULL argument");
+  if (init_mode != DPT_INIT_GIVEN && init_mode != DPT_INIT_CONST_VELOCITY)
+    return fail(DPT_E_ARG, "init_mode %d", init_mode);
+  if (init_mode == DPT_INIT_GIVEN) {
+    if (!T_cw_init) return fail(DPT_E_ARG, "T_cw_init is NULL");
+    for (int s = 0; s < b->n; ++s)
+      if (!finite16(T_cw_init + 16 * s)) return fail(DPT_E_ARG, "T_cw_init %d not finite", s);
   }
-  HIP_TRY(hipMemcpyAsync(b->d_args, b->h_args, sizeof(TrackArgs) * b->n, hipMemcpyHostToDevice, b->stream));
-  if (b->prof) HIP_TRY(hipEventRecord(b->ev[2], b->stream));
-  HIP_TRY(launch_track_batch(b->h_args[0], b->d_args, b->n, lds, max_points, b->stream));
-  if (b->prof) {
-    HIP_TRY(hipEventRecord(b->ev[3], b->stream));
-    b->ev_trk = true;
+  int e = batch_check_state(b);
+  if (e != DPT_OK) return e;
+  if (!batch_use_coop(b)) {
+    if (init_mode == DPT_INIT_CONST_VELOCITY)
+      return fail(DPT_E_ARG, "a constant-velocity start needs the cooperative track (K = 8, launch mode AUTO or COOP)");
+    return dpt_batch_track(b, T_cw_init, out);
   }
-  HIP_TRY(hipMemcpyAsync(b->h_outs, b->d_outs, sizeof(TrackOut) * b->n, hipMemcpyDeviceToHost, b->stream));
-  HIP_TRY(hipStreamSynchronize(b->stream));
-  for (int s = 0; s < b->n; ++s) fill_result(b->ctx[s], b->h_outs[s], &out[s]);
-  return DPT_OK;
+  std::vector<int> modes(b->n, init_mode == DPT_INIT_GIVEN ? kStartGiven : kStartConstVelocity);
+  return batch_enqueue_coop(b, modes.data(), T_cw_init, out);
+}
+
+int dpt_batch_synchronize(dpt_batch* b) {
+  g_err.clear();
+  if (!b) return fail(DPT_E_ARG, "NULL batch");
+  return batch_synchronize(b);
+}
+
+int dpt_batch_set_pose_history(dpt_batch* b, int32_t s, const double T_older[16], const double T_newer[16]) {
+  g_err.clear();
+  if (!b || s < 0 || s >= b->n) return fail(DPT_E_ARG, "stream %d", s);
+  return dpt_set_pose_history(b->ctx[s], T_older, T_newer);
 }
 
 int dpt_batch_set_launch_config(dpt_batch* b, int32_t mode, int32_t chunk) {
@@ -911,7 +1187,8 @@ int dpt_batch_set_launch_config(dpt_batch* b, int32_t mode, int32_t chunk) {
   if (mode == DPT_LAUNCH_COOP && b->ctx[0]->prm.n_pattern != 8) return fail(DPT_E_ARG, "cooperative track needs K = 8");
   if (mode == DPT_LAUNCH_WORKGROUP && b->ctx[0]->prm.precision == DPT_PREC_MIXED)
     return fail(DPT_E_ARG, "mixed precision runs on the cooperative launch only");
-  HIP_TRY(hipStreamSynchronize(b->stream));
+  const int e = batch_synchronize(b);
+  if (e != DPT_OK) return e;
   if (chunk != b->chunk) b->clear_groups();
   b->launch_mode = mode;
   b->chunk = chunk;
@@ -921,20 +1198,37 @@ int dpt_batch_set_launch_config(dpt_batch* b, int32_t mode, int32_t chunk) {
 int dpt_batch_set_profiling(dpt_batch* b, int32_t enable) {
   g_err.clear();
   if (!b) return fail(DPT_E_ARG, "NULL batch");
-  if (enable && !b->ev[0])
-    for (hipEvent_t& e : b->ev) HIP_TRY(hipEventCreate(&e));
+  int e = batch_synchronize(b);
+  if (e != DPT_OK) return e;
+  if (enable) {
+    HIP_TRY(b->prof_pyr.create());
+    HIP_TRY(b->prof_trk.create());
+  }
+  b->prof_pyr.reset();
+  b->prof_trk.reset();
   b->prof = enable != 0;
-  b->ev_pyr = b->ev_trk = false;
   return DPT_OK;
 }
 
 int dpt_batch_last_kernel_ms(dpt_batch* b, float* pyramid_ms, float* track_ms) {
   g_err.clear();
   if (!b || !pyramid_ms || !track_ms) return fail(DPT_E_ARG, "NULL argument");
-  *pyramid_ms = *track_ms = -1.0f;
-  HIP_TRY(hipStreamSynchronize(b->stream));
-  if (b->ev_pyr) HIP_TRY(hipEventElapsedTime(pyramid_ms, b->ev[0], b->ev[1]));
-  if (b->ev_trk) HIP_TRY(hipEventElapsedTime(track_ms, b->ev[2], b->ev[3]));
+  const int e = batch_synchronize(b);
+  if (e != DPT_OK) return e;
+  *pyramid_ms = b->prof_pyr.last_ms;
+  *track_ms = b->prof_trk.last_ms;
+  return DPT_OK;
+}
+
+int dpt_batch_get_profile(dpt_batch* b, double* pyramid_ms, int64_t* n_pyramid, double* track_ms, int64_t* n_track) {
+  g_err.clear();
+  if (!b || !pyramid_ms || !n_pyramid || !track_ms || !n_track) return fail(DPT_E_ARG, "NULL argument");
+  const int e = batch_synchronize(b);
+  if (e != DPT_OK) return e;
+  *pyramid_ms = b->prof_pyr.total_ms;
+  *n_pyramid = b->prof_pyr.count;
+  *track_ms = b->prof_trk.total_ms;
+  *n_track = b->prof_trk.count;
   return DPT_OK;
 }
 

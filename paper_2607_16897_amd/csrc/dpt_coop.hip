@@ -21,8 +21,6 @@
 
 namespace dpt {
 
-constexpr int kStatusTimeout = 4;
-
 // Wave 0 only.  Publish this chunk's column sums (`mine`, lanes < 32) under
 // `tag`, wait until all nch chunks of the stream published theirs, and return
 // the stream totals in chunk order (lanes < 32).  False on timeout.
@@ -110,16 +108,66 @@ __device__ __forceinline__ bool stream_total(float (&acc)[32], float* sh_red, fl
   return *sh_ok != 0;
 }
 
+// 3x4 rigid transforms (row-major [R | t]) in FP64, one output element per
+// thread t < 12: out = A B, and out = A^-1 = [R^T | -R^T t].
+__device__ __forceinline__ double compose34_elem(const double* A, const double* B, int t) {
+  const int r = t >> 2, c = t & 3;
+  double v = A[4 * r] * B[c] + A[4 * r + 1] * B[4 + c] + A[4 * r + 2] * B[8 + c];
+  return c == 3 ? v + A[4 * r + 3] : v;
+}
+
+__device__ __forceinline__ double invert34_elem(const double* A, int t) {
+  const int r = t >> 2, c = t & 3;
+  if (c < 3) return A[4 * c + r];
+  return -(A[r] * A[3] + A[4 + r] * A[7] + A[8 + r] * A[11]);
+}
+
+// Start pose relative to the reference for this launch: the given one, or the
+// constant-velocity prediction P1 P0^-1 P1 from the stream's pose history,
+// taken relative to the reference (P T_rw^-1).  Block-wide; the result and the
+// history's latest pose land in LDS.
+__device__ __forceinline__ void start_pose(const StartSlot* __restrict__ st, const double* __restrict__ hist,
+                                           double* T0, double* rw, double* h0, double* h1, double* m1, double* m2) {
+  const int t = threadIdx.x;
+  __shared__ int sh_mode;
+  if (t < 12) {
+    T0[t] = st->T_rel[t];
+    rw[t] = st->T_rw[t];
+    h0[t] = hist[t];
+    h1[t] = hist[12 + t];
+  }
+  if (t == 0) sh_mode = st->mode > 0.5 ? kStartConstVelocity : kStartGiven;
+  __syncthreads();
+  if (sh_mode != kStartConstVelocity) return;
+  if (t < 12) m1[t] = invert34_elem(h0, t);
+  if (t >= 16 && t < 28) m2[t - 16] = invert34_elem(rw, t - 16);
+  __syncthreads();
+  double v = 0.0;
+  if (t < 12) v = compose34_elem(h1, m1, t);  // P1 P0^-1
+  __syncthreads();
+  if (t < 12) m1[t] = v;
+  __syncthreads();
+  if (t < 12) v = compose34_elem(m1, h1, t);  // (P1 P0^-1) P1
+  __syncthreads();
+  if (t < 12) m1[t] = v;
+  __syncthreads();
+  if (t < 12) T0[t] = compose34_elem(m1, m2, t);  // relative to the reference
+  __syncthreads();
+  if (t == 0) orthonormalize34(T0);
+  __syncthreads();
+}
+
 // MIXED: FP16 reference cache, Kahan-compensated FP32 sums across waves and
 // chunks, FP64 solve, exponential and pose state.
 template <int CH, bool MIXED>
 __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __restrict__ streams,
                                                            const int2* __restrict__ work,
-                                                           const double* __restrict__ T_init, uint32_t tag_base,
+                                                           const StartSlot* __restrict__ start,
+                                                           TrackOut* __restrict__ outs, uint32_t tag_base,
                                                            int spin_limit) {
   using PR = typename std::conditional<MIXED, PointRegsH, PointRegs>::type;
   __shared__ CoopStream ss;
-  __shared__ double sh_T0[12];
+  __shared__ double sh_T0[12], sh_rw[12], sh_h0[12], sh_h1[12], sh_m1[12], sh_m2[12];
   __shared__ float sh_tot[32];
   __shared__ float sh_red[(CH / 64) * 32];
   __shared__ int sh_ok;
@@ -130,8 +178,8 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
     for (int j = threadIdx.x; j < (int)(sizeof(CoopStream) / 4); j += blockDim.x)
       reinterpret_cast<uint32_t*>(&ss)[j] = src[j];
   }
-  if (threadIdx.x < 12) sh_T0[threadIdx.x] = T_init[w.x * 12 + threadIdx.x];
   __syncthreads();
+  start_pose(start + w.x, ss.hist, sh_T0, sh_rw, sh_h0, sh_h1, sh_m1, sh_m2);
   const TrackArgs& a = ss.a;
   const PatRegs pregs = pattern_regs(a.pat);
   const int chunk = w.y, nch = ss.n_chunks;
@@ -211,10 +259,19 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
       timed_out = true;
   }
   if (chunk == 0 && threadIdx.x == 0) {
-    TrackOut* o = a.out;
+    TrackOut* o = outs + w.x;
+    double Tf[12];
+    for (int j = 0; j < 12; ++j) Tf[j] = MIXED ? Td[j] : (double)T[j];
+    orthonormalize34(Tf);
     for (int j = 0; j < 12; ++j) {
       o->T[j] = T[j];
-      o->Td[j] = MIXED ? Td[j] : (double)T[j];
+      o->Td[j] = Tf[j];
+    }
+    // the pose history gains this track's estimate T_cw = T_rel T_rw (every
+    // chunk read the history at its start, before its first exchange)
+    for (int j = 0; j < 12; ++j) {
+      ss.hist[j] = sh_h1[j];
+      ss.hist[12 + j] = compose34_elem(Tf, sh_rw, j);
     }
     o->E = sh_tot[kSlotE];
     o->n = sh_tot[kSlotN];
@@ -274,21 +331,22 @@ int coop_max_blocks(int chunk) {
 // wait is bounded by spin_limit, so a chunk that cannot be scheduled turns
 // into a reported timeout, not a hang.
 template <int CH>
-static hipError_t coop_launch_k(const CoopStream* d_streams, const int2* d_work, int n_work, const double* T_init,
-                                uint32_t tag_base, bool mixed, int spin_limit, hipStream_t s) {
-  void* args[] = {(void*)&d_streams, (void*)&d_work, (void*)&T_init, (void*)&tag_base, (void*)&spin_limit};
+static hipError_t coop_launch_k(const CoopStream* d_streams, const int2* d_work, int n_work, const StartSlot* start,
+                                TrackOut* out, uint32_t tag_base, bool mixed, int spin_limit, hipStream_t s) {
+  void* args[] = {(void*)&d_streams, (void*)&d_work, (void*)&start, (void*)&out, (void*)&tag_base,
+                  (void*)&spin_limit};
   const void* fn = mixed ? reinterpret_cast<const void*>(&coop_track_kernel<CH, true>)
                          : reinterpret_cast<const void*>(&coop_track_kernel<CH, false>);
   if (4 * n_work <= coop_max_blocks(CH)) return hipLaunchKernel(fn, dim3(n_work), dim3(CH), args, 0, s);
   return hipLaunchCooperativeKernel(fn, dim3(n_work), dim3(CH), args, 0, s);
 }
 
-hipError_t launch_coop_track(const CoopStream* d_streams, const int2* d_work, int n_work, const double* T_init,
-                             uint32_t tag_base, int chunk, bool mixed, int spin_limit, hipStream_t s) {
+hipError_t launch_coop_track(const CoopStream* d_streams, const int2* d_work, int n_work, const StartSlot* start,
+                             TrackOut* out, uint32_t tag_base, int chunk, bool mixed, int spin_limit, hipStream_t s) {
   switch (chunk) {
-    case 64: return coop_launch_k<64>(d_streams, d_work, n_work, T_init, tag_base, mixed, spin_limit, s);
-    case 128: return coop_launch_k<128>(d_streams, d_work, n_work, T_init, tag_base, mixed, spin_limit, s);
-    case 256: return coop_launch_k<256>(d_streams, d_work, n_work, T_init, tag_base, mixed, spin_limit, s);
+    case 64: return coop_launch_k<64>(d_streams, d_work, n_work, start, out, tag_base, mixed, spin_limit, s);
+    case 128: return coop_launch_k<128>(d_streams, d_work, n_work, start, out, tag_base, mixed, spin_limit, s);
+    case 256: return coop_launch_k<256>(d_streams, d_work, n_work, start, out, tag_base, mixed, spin_limit, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -315,13 +373,14 @@ hipError_t CoopEngine::init(int n_streams, const int* max_points, int chunk_, bo
   if ((e = hipMemset(d_partials, 0, sizeof(uint64_t) * partial_words)) != hipSuccess) return e;
   tag_base = 1;
   // coherent (uncached on the device) pinned host memory: the kernel reads the
-  // start poses and writes the results over the host link
+  // start slots and writes the results over the host link
   const unsigned fl = hipHostMallocMapped | hipHostMallocCoherent;
-  if ((e = hipHostMalloc((void**)&h_T, sizeof(double) * 12 * n, fl)) != hipSuccess) return e;
-  if ((e = hipHostMalloc((void**)&h_out, sizeof(TrackOut) * n, fl)) != hipSuccess) return e;
-  if ((e = hipHostGetDevicePointer((void**)&dv_T, h_T, 0)) != hipSuccess) return e;
+  if ((e = hipHostMalloc((void**)&h_start, sizeof(StartSlot) * kRing * n, fl)) != hipSuccess) return e;
+  if ((e = hipHostMalloc((void**)&h_out, sizeof(TrackOut) * kRing * n, fl)) != hipSuccess) return e;
+  if ((e = hipHostGetDevicePointer((void**)&dv_start, h_start, 0)) != hipSuccess) return e;
   if ((e = hipHostGetDevicePointer((void**)&dv_out, h_out, 0)) != hipSuccess) return e;
-  memset(h_out, 0, sizeof(TrackOut) * n);
+  memset(h_start, 0, sizeof(StartSlot) * kRing * n);
+  memset(h_out, 0, sizeof(TrackOut) * kRing * n);
   size_t off = 0;
   for (int k = 0; k < n; ++k) {
     h_streams[k].partials = d_partials + off;
@@ -334,18 +393,19 @@ hipError_t CoopEngine::init(int n_streams, const int* max_points, int chunk_, bo
 void CoopEngine::release() {
   for (void* p : {(void*)d_streams, (void*)d_work, (void*)d_partials})
     if (p) (void)hipFree(p);
-  if (h_T) (void)hipHostFree(h_T);
+  if (h_start) (void)hipHostFree(h_start);
   if (h_out) (void)hipHostFree(h_out);
   d_streams = nullptr, d_work = nullptr, d_partials = nullptr;
-  h_T = nullptr, h_out = nullptr, dv_T = nullptr, dv_out = nullptr;
+  h_start = nullptr, h_out = nullptr, dv_start = nullptr, dv_out = nullptr;
   work_cap = 0;
   partial_words = 0;
 }
 
-void CoopEngine::set_stream(int k, const TrackArgs& a) {
+void CoopEngine::set_stream(int k, const TrackArgs& a, double* hist) {
   CoopStream& c = h_streams[k];
   c.a = a;
-  c.a.out = dv_out + k;
+  c.a.out = nullptr;  // results go to the launch's slot of h_out
+  c.hist = hist;
   c.n_chunks = a.ref.n > 0 ? (a.ref.n + chunk - 1) / chunk : 1;
   dirty = true;
 }
@@ -397,8 +457,9 @@ hipError_t CoopEngine::upload() {
 
 int CoopEngine::grid() const { return (int)h_work.size(); }
 
-hipError_t CoopEngine::launch(int spin_limit) {
+hipError_t CoopEngine::launch(int spin_limit, int slot) {
   hipError_t e;
+  if (slot < 0 || slot >= kRing) return hipErrorInvalidValue;
   if (dirty && (e = upload()) != hipSuccess) return e;
   // tags used by this launch: at most levels * max_iters + 1 epochs per stream
   uint32_t span = 1;
@@ -406,7 +467,8 @@ hipError_t CoopEngine::launch(int spin_limit) {
   if (tag_base > 0xFFFFFFFFu - span) {  // wrap: restart the tags on cleared words
     if ((e = clear_partials()) != hipSuccess) return e;
   }
-  e = launch_coop_track(d_streams, d_work, grid(), dv_T, tag_base, chunk, mixed, spin_limit, stream);
+  e = launch_coop_track(d_streams, d_work, grid(), dv_start + (size_t)slot * n, dv_out + (size_t)slot * n, tag_base,
+                        chunk, mixed, spin_limit, stream);
   tag_base += span;
   return e;
 }
@@ -414,6 +476,23 @@ hipError_t CoopEngine::launch(int spin_limit) {
 hipError_t CoopEngine::clear_partials() {
   tag_base = 1;
   return hipMemsetAsync(d_partials, 0, sizeof(uint64_t) * partial_words, stream);
+}
+
+// ---------------------------------------------------------------- pose history
+
+struct HistoryArgs {
+  double T[24];  // two 3x4 poses: older, newer
+};
+
+__global__ void set_history_kernel(double* hist, HistoryArgs h) {
+  if (threadIdx.x < 24) hist[threadIdx.x] = h.T[threadIdx.x];
+}
+
+hipError_t launch_set_history(double* hist, const double* T0, const double* T1, hipStream_t s) {
+  HistoryArgs h;
+  for (int j = 0; j < 12; ++j) h.T[j] = T0[j], h.T[12 + j] = T1[j];
+  hipLaunchKernelGGL(set_history_kernel, dim3(1), dim3(32), 0, s, hist, h);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- batched pyramid

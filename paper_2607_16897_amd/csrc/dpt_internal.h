@@ -109,11 +109,44 @@ struct BackprojectArgs {
 
 // One stream of a cooperative track launch (device array, one entry per stream).
 struct CoopStream {
-  TrackArgs a;         // a.out points at this stream's TrackOut (host-mapped)
+  TrackArgs a;
   uint64_t* partials;  // [2][n_chunks][32] chunk sums, each word = (tag << 32) | float bits
+  double* hist;        // the stream's last two poses T_cw, 2 x 3x4 row-major FP64 (device)
   int32_t n_chunks;
   int32_t pad;
 };
+
+// Project the rotation of a row-major 3x4 pose back onto SO(3): two
+// Newton-Schulz steps of the polar decomposition, R <- R (3I - R^T R) / 2, each
+// squaring the deviation from orthonormality (FP32 updates and products of
+// poses leave ~1e-7, which products would otherwise amplify frame by frame).
+__host__ __device__ inline void orthonormalize34(double* T) {
+  for (int it = 0; it < 2; ++it) {
+    double M[9];  // 3I - R^T R
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        const double rr = T[i] * T[j] + T[4 + i] * T[4 + j] + T[8 + i] * T[8 + j];
+        M[3 * i + j] = (i == j ? 3.0 : 0.0) - rr;
+      }
+    double R[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        R[3 * i + j] = 0.5 * (T[4 * i] * M[j] + T[4 * i + 1] * M[3 + j] + T[4 * i + 2] * M[6 + j]);
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) T[4 * i + j] = R[3 * i + j];
+  }
+}
+
+// Per-launch, per-stream start of a cooperative track (host-mapped, 32 doubles).
+struct StartSlot {
+  double T_rel[12];  // given start pose relative to the reference (mode kStartGiven)
+  double mode;       // kStartGiven, or kStartConstVelocity: P1 P0^-1 P1 from the history
+  double pad0[3];
+  double T_rw[12];   // reference pose (world -> reference camera), 3x4
+  double pad1[4];
+};
+constexpr int kStartGiven = 0, kStartConstVelocity = 1;
+constexpr int kRing = 64;  // tracks that may be in flight per context or batch
 
 // One image of a batched pyramid launch.
 struct PyrJob {
@@ -125,9 +158,10 @@ struct PyrJob {
   int32_t pad;
 };
 
-// Host-side owner of a cooperative track launch over n streams.  Start poses
+// Host-side owner of a cooperative track launch over n streams.  Start slots
 // and results live in host-mapped pinned memory that the kernel reads and
-// writes directly, so a launch needs no copy commands.
+// writes directly, in rings of kRing launches, so a launch needs no copy
+// commands and up to kRing launches can be in flight.
 struct CoopEngine {
   int n = 0, chunk = 256, work_cap = 0;
   bool xcd_pack = true, dirty = true;
@@ -139,24 +173,27 @@ struct CoopEngine {
   int2* d_work = nullptr;
   uint64_t* d_partials = nullptr;
   size_t partial_words = 0;
-  uint32_t tag_base = 1;      // epoch tags of the next launch start here; 0 marks a cleared word
-  double* h_T = nullptr;      // [n][12] start poses (relative), host-mapped
-  double* dv_T = nullptr;     // device view of h_T
-  bool mixed = false;         // mixed-precision kernel variant
-  TrackOut* h_out = nullptr;  // [n] results, host-mapped
-  TrackOut* dv_out = nullptr; // device view of h_out
+  uint32_t tag_base = 1;       // epoch tags of the next launch start here; 0 marks a cleared word
+  StartSlot* h_start = nullptr;   // [kRing][n], host-mapped
+  StartSlot* dv_start = nullptr;  // device view of h_start
+  bool mixed = false;             // mixed-precision kernel variant
+  TrackOut* h_out = nullptr;      // [kRing][n] results, host-mapped
+  TrackOut* dv_out = nullptr;     // device view of h_out
   hipError_t init(int n_streams, const int* max_points, int chunk, bool xcd_pack, hipStream_t s);
   void release();
-  void set_stream(int k, const TrackArgs& a);
+  void set_stream(int k, const TrackArgs& a, double* hist);
   hipError_t upload();
   int grid() const;
-  // Enqueue the track of every stream from h_T; results land in h_out once the
-  // stream reaches this point.
-  hipError_t launch(int spin_limit);
+  StartSlot* start(int slot) { return h_start + (size_t)slot * n; }
+  TrackOut* out(int slot) { return h_out + (size_t)slot * n; }
+  // Enqueue the track of every stream from start slot `slot`; its results land
+  // in out(slot) once the stream reaches this point.
+  hipError_t launch(int spin_limit, int slot);
   hipError_t clear_partials();
   ~CoopEngine() { release(); }
 };
 
+constexpr int kStatusTimeout = 4;  // a cooperative wait gave up (dpt_result.status)
 constexpr int kSpinLimit = 1 << 22;  // polls (one round trip to memory each) before a chunk reports a timeout
 
 // Record an error message for dpt_last_error() and return `code`.
@@ -180,8 +217,10 @@ hipError_t launch_track_batch(const TrackArgs& any, const TrackArgs* batch, int 
                               int max_points, hipStream_t s);
 int track_lds_bytes(const LevelGeom* lv, int levels);
 hipError_t launch_normal_equations(const TrackArgs& a, hipStream_t s);
-hipError_t launch_coop_track(const CoopStream* d_streams, const int2* d_work, int n_work, const double* T_init,
-                             uint32_t tag_base, int chunk, bool mixed, int spin_limit, hipStream_t s);
+hipError_t launch_coop_track(const CoopStream* d_streams, const int2* d_work, int n_work, const StartSlot* start,
+                             TrackOut* out, uint32_t tag_base, int chunk, bool mixed, int spin_limit, hipStream_t s);
+// Set a pose history (two row-major 4x4 T_cw) on the stream.
+hipError_t launch_set_history(double* hist, const double* T0, const double* T1, hipStream_t s);
 int coop_max_blocks(int chunk);  // co-resident workgroups of a cooperative launch (0 if unsupported)
 hipError_t launch_pyramid_batch(const PyrJob* d_jobs, int n_jobs, int max_w, int max_h, int levels, hipStream_t s);
 

@@ -344,7 +344,10 @@ __global__ __launch_bounds__(kTrackThreads) void track_kernel(TrackArgs a0, cons
   }
   if (threadIdx.x == 0) {
     TrackOut* o = a.out;
-    for (int j = 0; j < 12; ++j) o->T[j] = sh_T[j];
+    double Tf[12];
+    for (int j = 0; j < 12; ++j) Tf[j] = (double)sh_T[j];
+    orthonormalize34(Tf);
+    for (int j = 0; j < 12; ++j) o->T[j] = sh_T[j], o->Td[j] = Tf[j];
     o->E = sh_tot[kSlotE];
     o->n = sh_tot[kSlotN];
     o->iterations = iterations;

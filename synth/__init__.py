@@ -57,6 +57,8 @@ def render_gpu(scene: "Scene", cam: "Camera", poses: np.ndarray, imgs, depths=No
     global _gpu_lib
     if _gpu_lib is None:
         build_gpu(force=False)
+        import torch  # noqa: F401  (bind to PyTorch's HIP runtime, one per process)
+
         _gpu_lib = ctypes.CDLL(_GPU_LIB_PATH)
         _gpu_lib.syn_gpu_render.restype = ctypes.c_int
         dp = ctypes.POINTER(ctypes.c_double)
