@@ -141,12 +141,13 @@ def collect(results, wins_done, stats):
         for j in range(1, WINDOW):
             r = results[k]
             k += 1
+            T = np.array(r["T_cw"], np.float64).reshape(4, 4)
             stats["init"].append(cv_init(prev2, prev1))
-            prev2, prev1 = prev1, r["T_cw"]
-            stats["samples"].append(r["samples"])
-            stats["iters"].append(r["iterations"])
-            stats["status"].append(r["status"])
-            stats["T"].append(r["T_cw"])
+            prev2, prev1 = prev1, T
+            stats["samples"].append(int(r["samples"]))
+            stats["iters"].append(int(r["iterations"]))
+            stats["status"].append(int(r["status"]))
+            stats["T"].append(T)
             stats["gt"].append(win["gts"][j])
 
 
@@ -173,14 +174,14 @@ def timed_plain(dpt, synth, wins, dev, steps, warmup, prm, launch, chunk, n_poin
         enqueue_window(dpt, trk, wins[w], dev[w], n_points)
         done.append(wins[w])
         if len(done) % SYNC_EVERY == 0:
-            results += trk.synchronize()
-    results += trk.synchronize()
+            results.append(trk.synchronize(arrays=True))
+    results.append(trk.synchronize(arrays=True))
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     prof = trk.profile()
     trk.set_profiling(False)
     trk.close()
-    collect(results, done, stats)
+    collect(np.concatenate(results), done, stats)
     return el, stats, prof
 
 
@@ -196,19 +197,26 @@ def bench_batched_sequences(dpt, synth, n_streams: int, steps: int, warmup: int,
     t_r = time.perf_counter()
     wins = [make_windows(n_win, seed=2607 + s) for s in range(n_streams)]
     render_s = time.perf_counter() - t_r
-    dev = [to_device(ws) for ws in wins]
+    # device layout: per window, one [streams, H, W] uint8 tensor per frame index and
+    # one [streams, H, W] float32 depth tensor of the keyframes
+    frames = [[torch.from_numpy(np.stack([wins[s][w]["imgs"][j] for s in range(n_streams)])).cuda()
+               for j in range(WINDOW)] for w in range(n_win)]
+    depths = [torch.from_numpy(np.stack([wins[s][w]["depth"] for s in range(n_streams)])).cuda()
+              for w in range(n_win)]
     torch.cuda.synchronize()
     prm = dpt.make_params(levels=LEVELS, max_iters=10, huber_k=9.0, step_eps=1e-5)
     bt = dpt.BatchTracker([CAM] * n_streams, prm, [N_POINTS] * n_streams)
     stats = {"samples": [], "iters": [], "status": []}
 
+    T_rw = [np.stack([wins[s][w]["gts"][0] for s in range(n_streams)]) for w in range(n_win)]
+    T_prev = [np.stack([wins[s][w]["T_prev"] for s in range(n_streams)]) for w in range(n_win)]
+
     def enqueue(w):
-        bt.build_pyramids(dpt.SLOT_REF, [dev[s][w][0][0] for s in range(n_streams)])
-        for s in range(n_streams):
-            bt.set_reference_from_depth(s, N_POINTS, dev[s][w][1], wins[s][w]["gts"][0])
-            bt.set_pose_history(s, wins[s][w]["T_prev"], wins[s][w]["gts"][0])
+        bt.build_pyramids(dpt.SLOT_REF, frames[w][0])
+        bt.set_reference_from_depth_all(N_POINTS, depths[w], T_rw[w])
+        bt.set_pose_history_all(T_prev[w], T_rw[w])
         for j in range(1, WINDOW):
-            bt.build_pyramids(dpt.SLOT_CUR, [dev[s][w][0][j] for s in range(n_streams)])
+            bt.build_pyramids(dpt.SLOT_CUR, frames[w][j])
             bt.track_enqueue(None)
 
     # tune on the last frame of the first window, started from the true poses
@@ -227,17 +235,17 @@ def bench_batched_sequences(dpt, synth, n_streams: int, steps: int, warmup: int,
     for st in range(steps):
         enqueue((warmup + st) % n_win)
         if (st + 1) % SYNC_EVERY == 0:
-            results += bt.synchronize()
-    results += bt.synchronize()
+            results.append(bt.synchronize(arrays=True))
+    results.append(bt.synchronize(arrays=True))
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     prof = bt.profile()
     bt.set_profiling(False)
     bt.close()
-    for res in results:
-        stats["samples"].append(sum(r["samples"] for r in res))
-        stats["iters"].extend(r["iterations"] for r in res)
-        stats["status"].extend(r["status"] for r in res)
+    res = np.concatenate(results)  # (launches, streams)
+    stats["samples"] = list(res["samples"].sum(axis=1))
+    stats["iters"] = list(res["iterations"].reshape(-1))
+    stats["status"] = list(res["status"].reshape(-1))
     tracked = n_streams * (WINDOW - 1) * steps
     track_ms = prof["track_ms"] / prof["n_track"]
     samp_launch = float(np.mean(stats["samples"]))

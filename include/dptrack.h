@@ -239,6 +239,14 @@ int dpt_batch_set_reference_points(dpt_batch* b, int32_t s, const float* xyz_wor
 int dpt_batch_set_reference_from_depth(dpt_batch* b, int32_t s, int32_t n, int32_t margin, const float* depth,
                                        int64_t depth_pitch, int32_t depth_on_device, const double T_rw[16]);
 
+/* As dpt_set_reference_from_depth for every stream at once, in one launch
+ * sequence for the whole batch (selection, back-projection, IC precompute):
+ * n_points[s] points on stream s, depths[s] its level-0 depth map in device
+ * memory with rows of depth_pitches[s] floats, T_rw n_streams row-major 4x4. */
+int dpt_batch_set_reference_from_depth_all(dpt_batch* b, const int32_t* n_points, int32_t margin,
+                                           const float* const* depths, const int64_t* depth_pitches,
+                                           const double* T_rw);
+
 /* Copy pyramid level `level` of slot `slot` of every stream, packed, into dst:
  * stream s's level at dst + s * W_l * H_l (all streams must have the same
  * level size).  dst in device memory if dst_on_device, else host. */
@@ -254,6 +262,8 @@ int dpt_batch_track(dpt_batch* b, const double* T_cw_init, dpt_result* out);
 int dpt_batch_track_enqueue(dpt_batch* b, int32_t init_mode, const double* T_cw_init, dpt_result* out);
 int dpt_batch_synchronize(dpt_batch* b);
 int dpt_batch_set_pose_history(dpt_batch* b, int32_t s, const double T_older[16], const double T_newer[16]);
+/* Pose histories of every stream at once (n_streams row-major 4x4 each), one launch. */
+int dpt_batch_set_pose_history_all(dpt_batch* b, const double* T_older, const double* T_newer);
 
 /* Launch configuration as dpt_set_launch_config, for the whole batch. */
 int dpt_batch_set_launch_config(dpt_batch* b, int32_t mode, int32_t chunk);

@@ -55,6 +55,15 @@ class Result(ctypes.Structure):
                     n_valid_points=self.n_valid_points, status=self.status, samples=self.samples)
 
 
+# NumPy view of dpt_result (zero-copy reads of result arrays)
+RESULT_DTYPE = np.dtype({
+    "names": ["T_cw", "final_cost", "iterations", "iters_per_level", "n_valid_points", "status", "samples"],
+    "formats": [("<f8", (16,)), "<f8", "<i4", ("<i4", (8,)), "<i4", "<i4", "<i8"],
+    "offsets": [Result.T_cw.offset, Result.final_cost.offset, Result.iterations.offset,
+                Result.iters_per_level.offset, Result.n_valid_points.offset, Result.status.offset,
+                Result.samples.offset],
+    "itemsize": ctypes.sizeof(Result)})
+
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
 _i64 = ctypes.c_int64
@@ -92,6 +101,9 @@ SIGNATURES = {
     "dpt_batch_track": (ctypes.c_int, [_vp, _vp, _vp]),
     "dpt_batch_track_enqueue": (ctypes.c_int, [_vp, _i32, _vp, _vp]),
     "dpt_batch_synchronize": (ctypes.c_int, [_vp]),
+    "dpt_batch_set_reference_from_depth_all": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp, ctypes.POINTER(ctypes.c_double)]),
+    "dpt_batch_set_pose_history_all": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double),
+                                                      ctypes.POINTER(ctypes.c_double)]),
     "dpt_batch_set_pose_history": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ctypes.c_double),
                                                   ctypes.POINTER(ctypes.c_double)]),
     "dpt_batch_get_profile": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64),
@@ -253,9 +265,15 @@ class Tracker:
             _check(self._lib.dpt_track_enqueue(self._h, INIT_GIVEN, _mat(T_cw_init), ctypes.byref(r)))
         self._pending.append(r)
 
-    def synchronize(self) -> list[dict]:
+    def synchronize(self, arrays: bool = False):
+        """Results of the enqueued tracks, in order: a list of dicts, or (arrays=True)
+        one structured array with the fields of RESULT_DTYPE."""
         _check(self._lib.dpt_synchronize(self._h))
-        out = [r.as_dict() for r in self._pending]
+        if arrays:
+            out = np.concatenate([np.frombuffer(r, dtype=RESULT_DTYPE) for r in self._pending]) if self._pending \
+                else np.empty(0, RESULT_DTYPE)
+        else:
+            out = [r.as_dict() for r in self._pending]
         self._pending = []
         return out
 
@@ -328,8 +346,20 @@ class BatchTracker:
 
     __del__ = close
 
+    def _stacked(self, x):
+        """(pointer array, row pitch in elements) of a contiguous [n, H, W] CUDA tensor."""
+        base, step = x.data_ptr(), x.stride(0) * x.element_size()
+        ptrs = np.arange(self.n, dtype=np.uint64) * np.uint64(step) + np.uint64(base)
+        return ptrs, int(x.stride(1))
+
     def build_pyramids(self, slot: int, imgs, pitches=None):
-        """imgs: list of NumPy arrays (host) or torch CUDA tensors (device), one per stream."""
+        """imgs: list of NumPy arrays (host) or torch CUDA tensors (device), one per
+        stream, or one contiguous [n, H, W] CUDA tensor (same resolution)."""
+        if hasattr(imgs, "dim") and imgs.dim() == 3 and imgs.is_cuda and imgs.is_contiguous():
+            ptrs, pitch = self._stacked(imgs)
+            pp = np.full(self.n, pitch, np.int64)
+            _check(self._lib.dpt_batch_build_pyramids(self._h, slot, ptrs.ctypes.data, pp.ctypes.data, 1))
+            return
         ptrs, devs, keep = zip(*[_ptr(x) for x in imgs])
         if len(set(devs)) != 1:
             raise ValueError("all images must be on the same side (host or device)")
@@ -375,15 +405,47 @@ class BatchTracker:
             _check(self._lib.dpt_batch_track_enqueue(self._h, INIT_GIVEN, T.ctypes.data, ctypes.cast(res, _vp)))
         self._pending.append(res)
 
-    def synchronize(self) -> list[list[dict]]:
-        """Results of the enqueued tracks, in order: one list of n per enqueue."""
+    def synchronize(self, arrays: bool = False):
+        """Results of the enqueued tracks, in order: one list of n per enqueue, or
+        (arrays=True) one structured array of shape (enqueues, n) with the fields of
+        RESULT_DTYPE."""
         _check(self._lib.dpt_batch_synchronize(self._h))
-        out = [[r.as_dict() for r in res] for res in self._pending]
+        if arrays:
+            out = np.stack([np.frombuffer(res, dtype=RESULT_DTYPE) for res in self._pending]) if self._pending \
+                else np.empty((0, self.n), RESULT_DTYPE)
+        else:
+            out = [[r.as_dict() for r in res] for res in self._pending]
         self._pending = []
         return out
 
     def set_pose_history(self, s: int, T_older, T_newer):
         _check(self._lib.dpt_batch_set_pose_history(self._h, s, _mat(T_older), _mat(T_newer)))
+
+    def set_pose_history_all(self, T_older, T_newer):
+        """Histories of every stream: T_older, T_newer of shape (n, 4, 4)."""
+        a = np.ascontiguousarray(np.asarray(T_older, np.float64).reshape(self.n * 16))
+        b = np.ascontiguousarray(np.asarray(T_newer, np.float64).reshape(self.n * 16))
+        _check(self._lib.dpt_batch_set_pose_history_all(self._h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                        b.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+
+    def set_reference_from_depth_all(self, n_points, depths, T_rw, margin: int = 8):
+        """Reference update of every stream in one launch sequence: n_points (int or
+        one per stream), depths a list of float32 torch CUDA tensors (H x W), T_rw (n, 4, 4)."""
+        n = (_i32 * self.n)(*([int(n_points)] * self.n if np.isscalar(n_points) else [int(v) for v in n_points]))
+        if hasattr(depths, "dim") and depths.dim() == 3:
+            if not (depths.is_cuda and depths.is_contiguous()):
+                raise ValueError("stacked depths must be a contiguous CUDA tensor")
+            p, pitch = self._stacked(depths)
+            ptrs = (ctypes.c_void_p * self.n)(*[int(v) for v in p])
+            pitches = (_i64 * self.n)(*([pitch] * self.n))
+        else:
+            ptrs = (ctypes.c_void_p * self.n)(*[d.data_ptr() for d in depths])
+            pitches = (_i64 * self.n)(*[int(d.stride(0)) for d in depths])
+        T = np.ascontiguousarray(np.asarray(T_rw, np.float64).reshape(self.n * 16))
+        _check(self._lib.dpt_batch_set_reference_from_depth_all(self._h, ctypes.cast(n, _vp), margin,
+                                                                ctypes.cast(ptrs, _vp), ctypes.cast(pitches, _vp),
+                                                                T.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        self._keep = depths
 
     def profile(self) -> dict:
         pm, pn, tm, tn = ctypes.c_double(), _i64(), ctypes.c_double(), _i64()

@@ -185,6 +185,50 @@ struct ProfRing {
   }
 };
 
+// A per-call argument table uploaded through pinned memory: two alternating
+// (host, device) buffers, a buffer's host side rewritten only after its
+// previous upload has run, so calls never wait for the stream otherwise.
+template <class T>
+struct StagedTable {
+  T* h[2] = {nullptr, nullptr};
+  T* d[2] = {nullptr, nullptr};
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  int cap = 0, next = 0;
+
+  hipError_t init(int n) {
+    cap = n;
+    hipError_t e;
+    for (int i = 0; i < 2; ++i) {
+      if ((e = hipHostMalloc((void**)&h[i], sizeof(T) * n)) != hipSuccess) return e;
+      if ((e = hipMalloc((void**)&d[i], sizeof(T) * n)) != hipSuccess) return e;
+      if ((e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  void release() {
+    for (int i = 0; i < 2; ++i) {
+      if (h[i]) (void)hipHostFree(h[i]);
+      if (d[i]) (void)hipFree(d[i]);
+      if (ev[i]) (void)hipEventDestroy(ev[i]);
+      h[i] = d[i] = nullptr;
+      ev[i] = nullptr;
+    }
+  }
+  // Host buffer to fill for the next upload (waits only for that buffer's previous upload).
+  hipError_t acquire(T** host, int* which) {
+    *which = next;
+    next ^= 1;
+    *host = h[*which];
+    return hipEventSynchronize(ev[*which]);
+  }
+  hipError_t upload(int which, int n, hipStream_t s, const T** dev) {
+    hipError_t e = hipMemcpyAsync(d[which], h[which], sizeof(T) * n, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    *dev = d[which];
+    return hipEventRecord(ev[which], s);
+  }
+};
+
 }  // namespace dpt
 
 struct dpt_ctx {
@@ -450,8 +494,8 @@ int dpt_select_points(dpt_ctx* c, int32_t n, int32_t margin, int32_t* host_idx, 
 
 namespace {
 
-// IC precompute of the reference cache from n device points P at T_rw.
-int precompute_reference(dpt_ctx* c, const float* P, int32_t n, const double T_rw[16]) {
+// Arguments of the IC precompute of n device points P at T_rw for context c.
+PrecomputeArgs precompute_args(const dpt_ctx* c, const float* P, int32_t n, const double T_rw[16]) {
   PrecomputeArgs a;
   std::memset(&a, 0, sizeof a);
   a.ref = c->pyr[DPT_SLOT_REF];
@@ -470,10 +514,19 @@ int precompute_reference(dpt_ctx* c, const float* P, int32_t n, const double T_r
   a.gh = c->gh;
   a.n = n;
   a.cap = c->cap;
-  HIP_TRY(launch_precompute(a, c->stream));
+  return a;
+}
+
+void commit_reference(dpt_ctx* c, int32_t n, const double T_rw[16]) {
   std::memcpy(c->T_rw, T_rw, sizeof c->T_rw);
   c->n_points = n;
   c->have_ref = true;
+}
+
+// IC precompute of the reference cache from n device points P at T_rw.
+int precompute_reference(dpt_ctx* c, const float* P, int32_t n, const double T_rw[16]) {
+  HIP_TRY(launch_precompute(precompute_args(c, P, n, T_rw), c->stream));
+  commit_reference(c, n, T_rw);
   return DPT_OK;
 }
 
@@ -838,6 +891,12 @@ struct dpt_batch {
   ProfRing prof_pyr, prof_trk;
   std::vector<std::pair<int, dpt_result*>> pending;  // tracks in flight: (ring slot, caller's n results)
   int slot_next = 0;
+  // batched reference updates and pose histories
+  StagedTable<SelJob> sel_jobs;
+  StagedTable<BackprojectArgs> bp_args;
+  StagedTable<PrecomputeArgs> pre_args;
+  StagedTable<double> hist_vals;  // 24 per stream
+  double** d_hist_ptrs = nullptr;  // device array of the streams' history pointers
 
   void clear_groups() {
     for (CoopEngine* g : groups) delete g;
@@ -851,6 +910,11 @@ struct dpt_batch {
     for (dpt_ctx* c : ctx) delete c;
     prof_pyr.destroy();
     prof_trk.destroy();
+    sel_jobs.release();
+    bp_args.release();
+    pre_args.release();
+    hist_vals.release();
+    if (d_hist_ptrs) (void)hipFree(d_hist_ptrs);
     for (hipEvent_t e : ev_jobs)
       if (e) (void)hipEventDestroy(e);
     if (d_jobs) (void)hipFree(d_jobs);
@@ -1045,10 +1109,22 @@ int dpt_batch_create(int32_t n_streams, const dpt_camera* cams, const dpt_params
       hipEventCreateWithFlags(&b->ev_jobs[0], hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&b->ev_jobs[1], hipEventDisableTiming) != hipSuccess ||
       hipHostMalloc(&b->h_args, sizeof(TrackArgs) * n_streams) != hipSuccess ||
-      hipHostMalloc(&b->h_outs, sizeof(TrackOut) * n_streams) != hipSuccess) {
+      hipHostMalloc(&b->h_outs, sizeof(TrackOut) * n_streams) != hipSuccess ||
+      b->sel_jobs.init(n_streams) != hipSuccess || b->bp_args.init(n_streams) != hipSuccess ||
+      b->pre_args.init(n_streams) != hipSuccess || b->hist_vals.init(24 * n_streams) != hipSuccess ||
+      hipMalloc(&b->d_hist_ptrs, sizeof(double*) * n_streams) != hipSuccess) {
     (void)hipGetLastError();
     delete b;
     return fail(DPT_E_OOM, "batch allocation failed");
+  }
+  {
+    std::vector<double*> hp(n_streams);
+    for (int s = 0; s < n_streams; ++s) hp[s] = b->ctx[s]->d_hist;
+    if (hipMemcpy(b->d_hist_ptrs, hp.data(), sizeof(double*) * n_streams, hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipGetLastError();
+      delete b;
+      return fail(DPT_E_HIP, "batch history table upload failed");
+    }
   }
   *out = b;
   return DPT_OK;
@@ -1128,6 +1204,84 @@ int dpt_batch_set_reference_from_depth(dpt_batch* b, int32_t s, int32_t n, int32
   int e = dpt_set_reference_from_depth(b->ctx[s], n, margin, depth, depth_pitch, depth_on_device, T_rw);
   if (e == DPT_OK && before != n) b->groups_dirty = true;
   return e;
+}
+
+int dpt_batch_set_reference_from_depth_all(dpt_batch* b, const int32_t* n_points, int32_t margin,
+                                           const float* const* depths, const int64_t* depth_pitches,
+                                           const double* T_rw) {
+  g_err.clear();
+  if (!b || !n_points || !depths || !depth_pitches || !T_rw) return fail(DPT_E_ARG, "NULL argument");
+  for (int s = 0; s < b->n; ++s) {
+    const dpt_ctx* c = b->ctx[s];
+    if (n_points[s] < 1 || n_points[s] > c->cap) return fail(DPT_E_ARG, "stream %d: n %d outside [1, %d]", s, n_points[s], c->cap);
+    if (margin < 1 || 2 * margin >= c->cam.width || 2 * margin >= c->cam.height) return fail(DPT_E_ARG, "margin %d", margin);
+    if (!depths[s]) return fail(DPT_E_ARG, "depth %d is NULL", s);
+    if (depth_pitches[s] < c->cam.width) return fail(DPT_E_ARG, "stream %d: depth pitch < width", s);
+    if (!finite16(T_rw + 16 * s)) return fail(DPT_E_ARG, "T_rw %d not finite", s);
+    if (!c->have_pyr[DPT_SLOT_REF]) return fail(DPT_E_STATE, "stream %d has no reference pyramid", s);
+  }
+  SelJob* hs;
+  BackprojectArgs* hb;
+  PrecomputeArgs* hp;
+  int ws, wb, wp;
+  HIP_TRY(b->sel_jobs.acquire(&hs, &ws));
+  HIP_TRY(b->bp_args.acquire(&hb, &wb));
+  HIP_TRY(b->pre_args.acquire(&hp, &wp));
+  int G_max = 0, max_n = 0, max_samples = 0, max_levels = 0;
+  for (int s = 0; s < b->n; ++s) {
+    dpt_ctx* c = b->ctx[s];
+    const int n = n_points[s];
+    hs[s] = make_sel_job(c->pyr[DPT_SLOT_REF], c->cam.width, c->cam.height, margin, n, c->sel_idx, c->sel_count,
+                         c->sel_scratch);
+    BackprojectArgs& bp = hb[s];
+    bp.idx = c->sel_idx;
+    bp.count = c->sel_count;
+    bp.depth = depths[s];
+    bp.pitch = depth_pitches[s];
+    bp.W = c->cam.width;
+    bp.n = n;
+    bp.fx = c->cam.fx, bp.fy = c->cam.fy, bp.cx = c->cam.cx, bp.cy = c->cam.cy;
+    for (int j = 0; j < 12; ++j) bp.T_rw[j] = T_rw[16 * s + j];
+    bp.P = c->pts;
+    hp[s] = precompute_args(c, c->pts, n, T_rw + 16 * s);
+    G_max = std::max(G_max, hs[s].G);
+    max_n = std::max(max_n, n);
+    max_samples = std::max(max_samples, n * c->prm.n_pattern);
+    max_levels = std::max(max_levels, c->prm.levels);
+  }
+  const SelJob* ds;
+  const BackprojectArgs* db;
+  const PrecomputeArgs* dp;
+  HIP_TRY(b->sel_jobs.upload(ws, b->n, b->stream, &ds));
+  HIP_TRY(b->bp_args.upload(wb, b->n, b->stream, &db));
+  HIP_TRY(b->pre_args.upload(wp, b->n, b->stream, &dp));
+  HIP_TRY(launch_select_batch(ds, b->n, G_max, b->stream));
+  HIP_TRY(launch_backproject_batch(db, b->n, max_n, b->stream));
+  HIP_TRY(launch_precompute_batch(dp, b->n, max_samples, max_levels, b->stream));
+  for (int s = 0; s < b->n; ++s) {
+    if (b->ctx[s]->n_points != n_points[s]) b->groups_dirty = true;
+    commit_reference(b->ctx[s], n_points[s], T_rw + 16 * s);
+  }
+  return DPT_OK;
+}
+
+int dpt_batch_set_pose_history_all(dpt_batch* b, const double* T_older, const double* T_newer) {
+  g_err.clear();
+  if (!b || !T_older || !T_newer) return fail(DPT_E_ARG, "NULL argument");
+  for (int s = 0; s < b->n; ++s)
+    if (!finite16(T_older + 16 * s) || !finite16(T_newer + 16 * s)) return fail(DPT_E_ARG, "pose %d not finite", s);
+  double* h;
+  int w;
+  HIP_TRY(b->hist_vals.acquire(&h, &w));
+  for (int s = 0; s < b->n; ++s)
+    for (int j = 0; j < 12; ++j) {
+      h[24 * s + j] = T_older[16 * s + j];
+      h[24 * s + 12 + j] = T_newer[16 * s + j];
+    }
+  const double* d;
+  HIP_TRY(b->hist_vals.upload(w, 24 * b->n, b->stream, &d));
+  HIP_TRY(launch_set_history_batch(b->d_hist_ptrs, d, b->n, b->stream));
+  return DPT_OK;
 }
 
 int dpt_batch_track(dpt_batch* b, const double* T_cw_init, dpt_result* out) {

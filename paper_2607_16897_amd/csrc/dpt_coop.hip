@@ -488,6 +488,19 @@ __global__ void set_history_kernel(double* hist, HistoryArgs h) {
   if (threadIdx.x < 24) hist[threadIdx.x] = h.T[threadIdx.x];
 }
 
+// Histories of n streams: vals[s] = (older 3x4, newer 3x4) into hists[s].
+__global__ void set_history_batch_kernel(double* const* hists, const double* vals, int n) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 24 * n) return;
+  hists[e / 24][e % 24] = vals[e];
+}
+
+hipError_t launch_set_history_batch(double* const* d_hists, const double* d_vals, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(set_history_batch_kernel, dim3((24 * n + 255) / 256), dim3(256), 0, s, d_hists, d_vals, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_set_history(double* hist, const double* T0, const double* T1, hipStream_t s) {
   HistoryArgs h;
   for (int j = 0; j < 12; ++j) h.T[j] = T0[j], h.T[12 + j] = T1[j];

@@ -95,6 +95,22 @@ struct PrecomputeArgs {
   int32_t n, cap;
 };
 
+// Point selection on one image (candidate c is pixel (m + c % Wc, m + c / Wc)).
+struct SelGeom {
+  const uint8_t* img;
+  int32_t W, m, Wc, C, n;
+};
+
+// One image's selection: geometry, its scratch (select_scratch_ints ints), the
+// output indices and count, and its number of 4096-candidate chunks G.
+struct SelJob {
+  SelGeom g;
+  int32_t* sc;
+  int32_t* idx;
+  int32_t* count;
+  int32_t G, pad;
+};
+
 // Map points from selected level-0 pixels and a depth map (device memory).
 struct BackprojectArgs {
   const int32_t* idx;    // [n] selected pixel indices y * W + x
@@ -209,8 +225,17 @@ hipError_t launch_pyramid(const uint8_t* src, int64_t pitch, uint8_t* dst, const
 int64_t select_scratch_ints(int32_t W, int32_t H);
 hipError_t launch_select(const uint8_t* img, int32_t W, int32_t H, int32_t margin, int32_t n, int32_t* idx,
                          int32_t* count, int32_t* scratch, hipStream_t s);
+SelJob make_sel_job(const uint8_t* img, int32_t W, int32_t H, int32_t margin, int32_t n, int32_t* idx,
+                    int32_t* count, int32_t* scratch);
+// Selections of n_img images in one launch sequence; d_jobs in device memory,
+// G_max = the largest chunk count among them.
+hipError_t launch_select_batch(const SelJob* d_jobs, int n_img, int G_max, hipStream_t s);
 hipError_t launch_precompute(const PrecomputeArgs& a, hipStream_t s);
 hipError_t launch_backproject(const BackprojectArgs& a, hipStream_t s);
+// Batched forms: one launch over n references / maps (argument arrays in device memory).
+hipError_t launch_precompute_batch(const PrecomputeArgs* d_args, int n_ref, int max_samples, int max_levels,
+                                   hipStream_t s);
+hipError_t launch_backproject_batch(const BackprojectArgs* d_args, int n_maps, int max_n, hipStream_t s);
 hipError_t launch_track(const TrackArgs& a, hipStream_t s);
 // One workgroup per frame; batch[b] describes frame b (device memory).
 hipError_t launch_track_batch(const TrackArgs& any, const TrackArgs* batch, int n_frames, int lds_bytes,
@@ -221,6 +246,8 @@ hipError_t launch_coop_track(const CoopStream* d_streams, const int2* d_work, in
                              TrackOut* out, uint32_t tag_base, int chunk, bool mixed, int spin_limit, hipStream_t s);
 // Set a pose history (two row-major 4x4 T_cw) on the stream.
 hipError_t launch_set_history(double* hist, const double* T0, const double* T1, hipStream_t s);
+// Pose histories of n streams: d_vals[24 s ..] = (older, newer) 3x4 into d_hists[s] (device arrays).
+hipError_t launch_set_history_batch(double* const* d_hists, const double* d_vals, int n, hipStream_t s);
 int coop_max_blocks(int chunk);  // co-resident workgroups of a cooperative launch (0 if unsupported)
 hipError_t launch_pyramid_batch(const PyrJob* d_jobs, int n_jobs, int max_w, int max_h, int levels, hipStream_t s);
 

@@ -5,6 +5,8 @@
 // fmaf, so that the reference precompute and the track evaluate the projection
 // and the bilinear sample with identical arithmetic (an identical frame at the
 // reference pose then gives residuals of exactly zero).
+#include <cstring>
+
 #include "dpt_device.h"
 
 namespace dpt {
@@ -41,10 +43,12 @@ hipError_t launch_pyramid(const uint8_t* src, int64_t pitch, uint8_t* dst, const
 // reference validity, the bilinear template intensity I0 and the interpolated
 // central-difference gradient.  The Jacobian itself is rebuilt in the track
 // from (gx, gy) and x0, so the cache holds 12 bytes per sample.
-__global__ __launch_bounds__(256) void precompute_kernel(PrecomputeArgs a) {
+__global__ __launch_bounds__(256) void precompute_kernel(PrecomputeArgs one, const PrecomputeArgs* __restrict__ many) {
+  const PrecomputeArgs& a = many ? many[blockIdx.z] : one;  // one reference, or reference blockIdx.z of a batch
   const int K = a.pat.K;
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   const int l = blockIdx.y;
+  if (l >= a.levels) return;
   if (s >= a.n * K) return;
   const int i = s / K, k = s - i * K;
   float X, Y, Z;
@@ -78,7 +82,17 @@ __global__ __launch_bounds__(256) void precompute_kernel(PrecomputeArgs a) {
 hipError_t launch_precompute(const PrecomputeArgs& a, hipStream_t s) {
   if (a.n == 0) return hipSuccess;
   dim3 grid((a.n * a.pat.K + 255) / 256, a.levels);
-  hipLaunchKernelGGL(precompute_kernel, grid, dim3(256), 0, s, a);
+  hipLaunchKernelGGL(precompute_kernel, grid, dim3(256), 0, s, a, (const PrecomputeArgs*)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_precompute_batch(const PrecomputeArgs* d_args, int n_ref, int max_samples, int max_levels,
+                                   hipStream_t s) {
+  if (n_ref == 0 || max_samples == 0) return hipSuccess;
+  PrecomputeArgs none;
+  std::memset(&none, 0, sizeof none);
+  dim3 grid((max_samples + 255) / 256, max_levels, n_ref);
+  hipLaunchKernelGGL(precompute_kernel, grid, dim3(256), 0, s, none, d_args);
   return hipGetLastError();
 }
 
@@ -86,7 +100,9 @@ hipError_t launch_precompute(const PrecomputeArgs& a, hipStream_t s) {
 // rounded to FP32.  A pixel without a positive finite depth, and every entry
 // past the selection count, becomes a NaN point, which the precompute marks
 // invalid at every level.
-__global__ __launch_bounds__(256) void backproject_kernel(BackprojectArgs a) {
+__global__ __launch_bounds__(256) void backproject_kernel(BackprojectArgs one,
+                                                         const BackprojectArgs* __restrict__ many) {
+  const BackprojectArgs& a = many ? many[blockIdx.y] : one;  // one map, or map blockIdx.y of a batch
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   const float nan = __int_as_float(0x7fc00000);
@@ -110,7 +126,16 @@ __global__ __launch_bounds__(256) void backproject_kernel(BackprojectArgs a) {
 
 hipError_t launch_backproject(const BackprojectArgs& a, hipStream_t s) {
   if (a.n == 0) return hipSuccess;
-  hipLaunchKernelGGL(backproject_kernel, dim3((a.n + 255) / 256), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(backproject_kernel, dim3((a.n + 255) / 256), dim3(256), 0, s, a,
+                     (const BackprojectArgs*)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_backproject_batch(const BackprojectArgs* d_args, int n_maps, int max_n, hipStream_t s) {
+  if (n_maps == 0 || max_n == 0) return hipSuccess;
+  BackprojectArgs none;
+  std::memset(&none, 0, sizeof none);
+  hipLaunchKernelGGL(backproject_kernel, dim3((max_n + 255) / 256, n_maps), dim3(256), 0, s, none, d_args);
   return hipGetLastError();
 }
 

@@ -14,6 +14,8 @@
 //   D  every workgroup scans the chunk counts before it for its output offset
 //      and tie base, then writes its selected indices with a block-wide prefix
 //      sum; the last chunk writes the count
+#include <cstring>
+
 #include "dpt_device.h"
 
 namespace dpt {
@@ -36,24 +38,29 @@ __device__ __forceinline__ int sel_score(const uint8_t* img, int W, int x, int y
   return dx * dx + dy * dy;
 }
 
-struct SelGeom {
-  const uint8_t* img;
-  int W, m, Wc, C, n;
-};
 
 __device__ __forceinline__ int cand_score(const SelGeom& g, int c) {
   return sel_score(g.img, g.W, g.m + c % g.Wc, g.m + c / g.Wc);
 }
 
-__global__ __launch_bounds__(kSelThreads) void sel_clear(int* __restrict__ sc) {
-  for (int b = threadIdx.x; b < SelScratch::kChunks; b += blockDim.x) sc[b] = 0;
+// The selection of one image (`one`), or of image blockIdx.y of a batch (`many`
+// non-null): every kernel below runs over (chunks, images) and a workgroup past
+// its image's chunk count returns at once.
+__device__ __forceinline__ SelJob sel_job(const SelJob& one, const SelJob* many) {
+  return many ? many[blockIdx.y] : one;
 }
 
-__global__ void sel_zero_count(int32_t* __restrict__ count) {
-  if (threadIdx.x == 0) *count = 0;
+__global__ __launch_bounds__(kSelThreads) void sel_clear(SelJob one, const SelJob* many) {
+  const SelJob j = sel_job(one, many);
+  for (int b = threadIdx.x; b < SelScratch::kChunks; b += blockDim.x) j.sc[b] = 0;
+  if (j.G == 0 && threadIdx.x == 0) *j.count = 0;  // no candidates: nothing selected
 }
 
-__global__ __launch_bounds__(kSelThreads) void sel_hist_coarse(SelGeom g, int* __restrict__ sc) {
+__global__ __launch_bounds__(kSelThreads) void sel_hist_coarse(SelJob one, const SelJob* many) {
+  const SelJob j = sel_job(one, many);
+  if ((int)blockIdx.x >= j.G) return;
+  const SelGeom& g = j.g;
+  int* __restrict__ sc = j.sc;
   __shared__ int h[256];
   for (int b = threadIdx.x; b < 256; b += blockDim.x) h[b] = 0;
   __syncthreads();
@@ -105,7 +112,11 @@ __device__ __forceinline__ int2 coarse_bucket(const SelGeom& g, const int* sc) {
   return wave_find_bin<256>(sc + SelScratch::kHist1, g.n, 0);
 }
 
-__global__ __launch_bounds__(kSelThreads) void sel_hist_fine(SelGeom g, int* __restrict__ sc) {
+__global__ __launch_bounds__(kSelThreads) void sel_hist_fine(SelJob one, const SelJob* many) {
+  const SelJob j = sel_job(one, many);
+  if ((int)blockIdx.x >= j.G) return;
+  const SelGeom& g = j.g;
+  int* __restrict__ sc = j.sc;
   __shared__ int h[512];
   __shared__ int sB;
   if (threadIdx.x < 64) {
@@ -137,7 +148,11 @@ __device__ __forceinline__ int2 threshold(const SelGeom& g, const int* sc) {
   return make_int2(cb.x * 512 + f.x, g.n - f.y);
 }
 
-__global__ __launch_bounds__(kSelThreads) void sel_count(SelGeom g, int* __restrict__ sc) {
+__global__ __launch_bounds__(kSelThreads) void sel_count(SelJob one, const SelJob* many) {
+  const SelJob j = sel_job(one, many);
+  if ((int)blockIdx.x >= j.G) return;
+  const SelGeom& g = j.g;
+  int* __restrict__ sc = j.sc;
   __shared__ int s_gt[kSelThreads / 64], s_eq[kSelThreads / 64];
   __shared__ int sT;
   if (threadIdx.x < 64) {
@@ -197,8 +212,14 @@ __device__ __forceinline__ int2 chunk_base(const int* sc, int G, int need, int* 
   return make_int2(a + kept, b);        // output offset, tie base
 }
 
-__global__ __launch_bounds__(kSelThreads) void sel_write(SelGeom g, const int* __restrict__ sc, int G,
-                                                         int32_t* __restrict__ idx, int32_t* __restrict__ count) {
+__global__ __launch_bounds__(kSelThreads) void sel_write(SelJob one, const SelJob* many) {
+  const SelJob j = sel_job(one, many);
+  if ((int)blockIdx.x >= j.G) return;
+  const SelGeom& g = j.g;
+  const int* __restrict__ sc = j.sc;
+  const int G = j.G;
+  int32_t* __restrict__ idx = j.idx;
+  int32_t* __restrict__ count = j.count;
   __shared__ int wsum[16];
   __shared__ int red[8];
   __shared__ int sT, sNeed;
@@ -239,28 +260,49 @@ __global__ __launch_bounds__(kSelThreads) void sel_write(SelGeom g, const int* _
   if (blockIdx.x == G - 1 && threadIdx.x == 0) *count = base.x + tot;
 }
 
+SelJob make_sel_job(const uint8_t* img, int32_t W, int32_t H, int32_t margin, int32_t n, int32_t* idx,
+                    int32_t* count, int32_t* scratch) {
+  SelJob j;
+  j.g.img = img;
+  j.g.W = W;
+  j.g.m = margin;
+  j.g.Wc = W - 2 * margin;
+  const int Hc = H - 2 * margin;
+  j.g.C = (j.g.Wc > 0 && Hc > 0) ? j.g.Wc * Hc : 0;
+  j.g.n = n;
+  j.sc = scratch;
+  j.idx = idx;
+  j.count = count;
+  j.G = (j.g.C + kSelChunk - 1) / kSelChunk;
+  j.pad = 0;
+  return j;
+}
+
+// The pipeline for one image (many == nullptr) or for n_img images whose
+// chunk counts are at most G_max.  The histograms are cleared by a kernel, so
+// the sequence can be captured.
+static hipError_t run_select(const SelJob& one, const SelJob* many, int n_img, int G_max, hipStream_t s) {
+  const dim3 grid(G_max > 0 ? G_max : 1, n_img);
+  hipLaunchKernelGGL(sel_clear, dim3(1, n_img), dim3(kSelThreads), 0, s, one, many);
+  if (G_max > 0) {
+    hipLaunchKernelGGL(sel_hist_coarse, grid, dim3(kSelThreads), 0, s, one, many);
+    hipLaunchKernelGGL(sel_hist_fine, grid, dim3(kSelThreads), 0, s, one, many);
+    hipLaunchKernelGGL(sel_count, grid, dim3(kSelThreads), 0, s, one, many);
+    hipLaunchKernelGGL(sel_write, grid, dim3(kSelThreads), 0, s, one, many);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_select(const uint8_t* img, int32_t W, int32_t H, int32_t margin, int32_t n, int32_t* idx,
                          int32_t* count, int32_t* scratch, hipStream_t s) {
-  SelGeom g;
-  g.img = img;
-  g.W = W;
-  g.m = margin;
-  g.Wc = W - 2 * margin;
-  const int Hc = H - 2 * margin;
-  g.C = (g.Wc > 0 && Hc > 0) ? g.Wc * Hc : 0;
-  g.n = n;
-  const int G = (g.C + kSelChunk - 1) / kSelChunk;
-  if (G == 0) {
-    hipLaunchKernelGGL(sel_zero_count, dim3(1), dim3(64), 0, s, count);
-    return hipGetLastError();
-  }
-  // histograms start at zero: cleared by a kernel, so the sequence can be captured
-  hipLaunchKernelGGL(sel_clear, dim3(1), dim3(kSelThreads), 0, s, scratch);
-  hipLaunchKernelGGL(sel_hist_coarse, dim3(G), dim3(kSelThreads), 0, s, g, scratch);
-  hipLaunchKernelGGL(sel_hist_fine, dim3(G), dim3(kSelThreads), 0, s, g, scratch);
-  hipLaunchKernelGGL(sel_count, dim3(G), dim3(kSelThreads), 0, s, g, scratch);
-  hipLaunchKernelGGL(sel_write, dim3(G), dim3(kSelThreads), 0, s, g, scratch, G, idx, count);
-  return hipGetLastError();
+  const SelJob j = make_sel_job(img, W, H, margin, n, idx, count, scratch);
+  return run_select(j, nullptr, 1, j.G, s);
+}
+
+hipError_t launch_select_batch(const SelJob* d_jobs, int n_img, int G_max, hipStream_t s) {
+  SelJob none;
+  std::memset(&none, 0, sizeof none);
+  return run_select(none, d_jobs, n_img, G_max, s);
 }
 
 }  // namespace dpt

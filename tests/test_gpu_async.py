@@ -210,3 +210,37 @@ def test_workgroup_path_and_profile_counts(gpu_lib):
     p = trk.profile()
     assert p["n_track"] == 3 and p["n_pyramid"] == 3
     assert p["track_ms"] > 0 and p["pyramid_ms"] > 0
+
+
+def test_batch_reference_update_all_equals_per_stream(gpu_lib):
+    """The one-launch-sequence reference update and history of every stream give
+    the same caches and tracks as the per-stream calls."""
+    import torch
+
+    dpt = gpu_lib
+    cams = [synth.CAM_752, synth.CAM_640, synth.CAM_752]
+    n_pts = [1800, 700, 2000]
+    wins = [_windows(1, seed=70 + s, cam=cams[s])[0] for s in range(3)]
+    prm = dpt.make_params(levels=3)
+    dev = [[torch.from_numpy(im).cuda() for im in w["imgs"]] for w in wins]
+    depth = [torch.from_numpy(w["depth"]).cuda() for w in wins]
+    res = []
+    for mode in ("all", "each"):
+        bt = dpt.BatchTracker(cams, prm, [2000] * 3)
+        bt.build_pyramids(dpt.SLOT_REF, [d[0] for d in dev])
+        if mode == "all":
+            bt.set_reference_from_depth_all(n_pts, depth, np.stack([w["gts"][0] for w in wins]))
+            bt.set_pose_history_all(np.stack([w["T_prev"] for w in wins]), np.stack([w["gts"][0] for w in wins]))
+        else:
+            for s, w in enumerate(wins):
+                bt.set_reference_from_depth(s, n_pts[s], depth[s], w["gts"][0])
+                bt.set_pose_history(s, w["T_prev"], w["gts"][0])
+        for j in range(1, WINDOW):
+            bt.build_pyramids(dpt.SLOT_CUR, [d[j] for d in dev])
+            bt.track_enqueue(None)
+        res.append(bt.synchronize())
+    for j in range(WINDOW - 1):
+        for s in range(3):
+            np.testing.assert_array_equal(res[0][j][s]["T_cw"], res[1][j][s]["T_cw"])
+            assert res[0][j][s]["n_valid_points"] == res[1][j][s]["n_valid_points"]
+            assert oracle.pose_error(res[0][j][s]["T_cw"], wins[s]["gts"][j + 1])[0] < 2e-3
