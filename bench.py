@@ -16,7 +16,8 @@ the final cost pass included.
 Further legs in the same line: batched streams (64 sequences of the headline
 shape; the mixed-resolution 64-stream batch against the same tracks through
 plain contexts), the mixed-precision variant (headline workload and a
-1280x720 / 16k-point stress case), the learned initialiser against the
+1280x720 / 16k-point stress case), the fixed-H mode (the paper's constant-H
+track on the headline workload), the learned initialiser against the
 constant-velocity prior, and the FP64 oracle on the host (cpu_baseline), which
 also tracks the first timed window of each leg from the same starts to give
 the per-frame pose differences between the GPU path and the oracle.
@@ -358,6 +359,27 @@ def bench_mixed_precision(dpt, synth, wins, dev, steps):
     return out, st
 
 
+def bench_fixed_h(dpt, synth, wins, dev, steps):
+    """The headline workload through the paper's own inverse-compositional track:
+    per level a constant H reduced once per reference, only b and the cost
+    reduced per iteration, no robust weights."""
+    prm = dpt.make_params(levels=LEVELS, max_iters=10, huber_k=9.0, step_eps=1e-5, fixed_h=True)
+    el, st, prof = timed_plain(dpt, synth, wins, dev, steps, 1, prm, dpt.LAUNCH_COOP, 256)
+    track_ms = prof["track_ms"] / prof["n_track"]
+    iters = float(np.mean(st["iters"]))
+    achieved = float(np.mean(st["samples"])) * BYTES_PER_SAMPLE_F32 / (track_ms * 1e-3) / 1e9
+    out = {"workload": "the headline workload, fixed-H mode (constant H per level, b only, no weights)",
+           "frames_per_s": round(steps * (WINDOW - 1) / el, 2), "track_launch_ms": round(track_ms, 5),
+           "iterations_per_frame": round(iters, 3),
+           "track_us_per_iteration": round(track_ms * 1e3 / (iters + 1), 3),
+           "status_counts": {str(k): int(v) for k, v in zip(*np.unique(st["status"], return_counts=True))},
+           "pose_error_vs_gt": err_summary([pose_error(T, G) for T, G in zip(st["T"], st["gt"])]),
+           "roofline": {"kernel": "coop_track_kernel<256, false, true>", "bound": "hbm", "unit": "GB/s",
+                        "peak": HBM_PEAK_GBS, "achieved": round(achieved, 3),
+                        "frac": round(achieved / HBM_PEAK_GBS, 6)}}
+    return out, st
+
+
 def bench_stress(dpt, synth):
     """1280x720, 16000 points, 4 levels: one keyframe window of the sequence,
     tracked in FP32 and in mixed precision."""
@@ -424,8 +446,8 @@ def cpu_baseline(wins, seconds: float, comparisons):
            "sample": f"{n} keyframe windows ({(WINDOW - 1) * n} tracked frames) of the headline sequence in "
                      f"{el:.1f} s, FP64 C oracle (gcc -O2) on one host thread"}
     diffs = {}
-    for name, (frames, starts, poses, cam, wset, npts, levels) in comparisons.items():
-        p = oracle.make_params(levels=levels)
+    for name, (frames, starts, poses, cam, wset, npts, levels, *mode) in comparisons.items():
+        p = oracle.make_params(levels=levels, fixed_h=bool(mode and mode[0] == "fixed_h"))
         refs, errs = {}, []
         for (w, j), T0, Tg in zip(frames, starts, poses):
             if w not in refs:
@@ -510,9 +532,9 @@ def main():
                     help="track launch (the GPU-side constant-velocity start needs the cooperative track)")
     ap.add_argument("--chunk", type=int, default=256)
     ap.add_argument("--batch-streams", type=int, default=64)
-    ap.add_argument("--only-headline", action="store_true", help="skip the batched, precision and initialiser legs")
-    ap.add_argument("--legs", default="mixed,batched,init",
-                    help="legs after the headline: any of mixed, batched, init (comma separated)")
+    ap.add_argument("--only-headline", action="store_true", help="skip the batched, precision, fixed-H and initialiser legs")
+    ap.add_argument("--legs", default="mixed,fixed,batched,init",
+                    help="legs after the headline: any of mixed, fixed, batched, init (comma separated)")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="write the track kernel's HBM traffic per launch from rocprofv3 --pmc output and exit")
     args = ap.parse_args()
@@ -588,6 +610,7 @@ def main():
                        "pyramid_kernel": round(prof["pyramid_ms"] / max(prof["n_pyramid"], 1), 5)},
         "track_only_frames_per_s": round(1.0 / (track_ms * 1e-3), 1),
         "iterations_per_frame": round(float(np.mean(stats["iters"])), 3),
+        "track_us_per_iteration": round(track_ms * 1e3 / (float(np.mean(stats["iters"])) + 1), 3),
         "status_counts": {str(k): int(v) for k, v in zip(*np.unique(stats["status"], return_counts=True))},
         "pose_error_vs_gt": err_summary([pose_error(T, G) for T, G in zip(stats["T"], stats["gt"])]),
         "setup_render_s": round(render_s, 2),
@@ -606,6 +629,12 @@ def main():
                                                        st["T"][:nc], synth.CAM_1280, sw, 16000, 4)
         out["mixed_precision"] = mp
         print("# precision legs done", file=sys.stderr, flush=True)
+    if "fixed" in legs:
+        fh, st_f = bench_fixed_h(dpt, synth, wins, dev, max(4, args.steps // 2))
+        comparisons["headline_fixed_h"] = ([(1 % n_render, j) for j in range(1, WINDOW)], st_f["init"][:nc],
+                                           st_f["T"][:nc], CAM, wins, N_POINTS, LEVELS, "fixed_h")
+        out["fixed_h"] = fh
+        print("# fixed-H leg done", file=sys.stderr, flush=True)
     if "batched" in legs:
         out["batched"] = {
             "sequences": bench_batched_sequences(dpt, synth, args.batch_streams, max(2, args.steps // 4), 1),

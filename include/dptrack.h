@@ -52,6 +52,16 @@ enum {
 /* dpt_params.precision */
 enum { DPT_PREC_FP32 = 0, DPT_PREC_MIXED = 1 };
 
+/* dpt_params.flags
+ *   DPT_FLAG_FIXED_H  the paper's own inverse-compositional track (Sec. IV-B,
+ *                     Sec. IV-C precompute and track): per level, H = sum of J^T J
+ *                     over every reference-valid point and sample is reduced
+ *                     once when the reference is set, and each iteration reduces
+ *                     only b = -sum J^T r over the points valid in the current
+ *                     frame; no robust weights (huber_k is ignored, the cost is
+ *                     r^2/2).  FP32 precision only. */
+enum { DPT_FLAG_FIXED_H = 1 };
+
 /* pyramid slots */
 enum { DPT_SLOT_REF = 0, DPT_SLOT_CUR = 1 };
 
@@ -72,7 +82,7 @@ typedef struct {
   int32_t n_pattern;    /* patch samples per point K, 1..128 */
   int8_t pattern[256];  /* K (dx, dy) offsets in level pixels, |d| <= 16, same at every level */
   int32_t precision;    /* DPT_PREC_FP32 */
-  int32_t flags;        /* reserved, 0 */
+  int32_t flags;        /* 0 or DPT_FLAG_FIXED_H */
 } dpt_params;
 
 typedef struct {
@@ -188,6 +198,15 @@ int dpt_get_reference_cache(dpt_ctx* ctx, int32_t level, uint8_t* valid, float* 
  * Huber costs; n: valid samples; npts: valid points. */
 int dpt_normal_equations(dpt_ctx* ctx, int32_t level, const double T_rel[16], float* H21, float* b6, double* E,
                          int64_t* n, int32_t* npts);
+/* In the fixed-H mode H21 is the level's precomputed H, and b, E are unweighted. */
+
+/* Fixed-H mode (DPT_FLAG_FIXED_H, Sec. IV-C precompute): the level's H of the
+ * current reference as a full symmetric 6x6 row-major (FP64 sum of the FP32
+ * per-point terms), and not_pd = 1 when its Cholesky factor failed (a pivot at
+ * most 1e-6 of the largest diagonal entry: every track then ends with
+ * DPT_TRACK_NOT_PD at that level).  Waits for the stream.  DPT_E_STATE when the
+ * context is not in the fixed-H mode or has no reference. */
+int dpt_get_fixed_hessian(dpt_ctx* ctx, int32_t level, double H36[36], int32_t* not_pd);
 
 /* Launch configuration of the track kernel.
  *   DPT_LAUNCH_AUTO       cooperative chunks when the GPU supports co-resident

@@ -20,6 +20,7 @@ _lib = None
 DPT_OK, DPT_E_ARG, DPT_E_HIP, DPT_E_STATE, DPT_E_OOM = 0, -1, -2, -3, -4
 TRACK_OK, TRACK_MAX_ITERS, TRACK_TOO_FEW_POINTS, TRACK_NOT_PD = 0, 1, 2, 3
 PREC_FP32, PREC_MIXED = 0, 1
+FLAG_FIXED_H = 1  # dpt_params.flags: the paper's constant-H track
 SLOT_REF, SLOT_CUR = 0, 1
 LAUNCH_AUTO, LAUNCH_WORKGROUP, LAUNCH_COOP = 0, 1, 2
 INIT_GIVEN, INIT_CONST_VELOCITY = 0, 1
@@ -91,6 +92,7 @@ SIGNATURES = {
     "dpt_normal_equations": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ctypes.c_double), _vp, _vp,
                                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64),
                                             ctypes.POINTER(_i32)]),
+    "dpt_get_fixed_hessian": (ctypes.c_int, [_vp, _i32, _vp, ctypes.POINTER(_i32)]),
     "dpt_set_profiling": (ctypes.c_int, [_vp, _i32]),
     "dpt_set_launch_config": (ctypes.c_int, [_vp, _i32, _i32]),
     "dpt_batch_create": (ctypes.c_int, [_i32, _vp, ctypes.POINTER(Params), _vp, _vp, ctypes.POINTER(_vp)]),
@@ -175,7 +177,10 @@ def make_camera(cam) -> Camera:
 
 
 def make_params(levels=3, max_iters=10, huber_k=9.0, step_eps=1e-5, z_min=1e-3, min_points=10,
-                pattern=DEFAULT_PATTERN, precision=PREC_FP32, flags=0) -> Params:
+                pattern=DEFAULT_PATTERN, precision=PREC_FP32, flags=0, fixed_h=False) -> Params:
+    """fixed_h=True sets FLAG_FIXED_H (the paper's constant-H track, no weights)."""
+    if fixed_h:
+        flags |= FLAG_FIXED_H
     p = Params()
     p.levels, p.max_iters, p.huber_k, p.step_eps, p.z_min = levels, max_iters, huber_k, step_eps, z_min
     p.min_points, p.precision, p.flags = min_points, precision, flags
@@ -321,6 +326,13 @@ class Tracker:
                 H[i, j] = H[j, i] = H21[q]
                 q += 1
         return dict(H=H, b=b6.astype(np.float64), E=E.value, n=n.value, npts=npts.value)
+
+    def fixed_hessian(self, level: int):
+        """Fixed-H mode: (H 6x6 float64 of the current reference at `level`, not_pd)."""
+        H = np.empty((6, 6), np.float64)
+        bad = _i32()
+        _check(self._lib.dpt_get_fixed_hessian(self._h, level, H.ctypes.data, ctypes.byref(bad)))
+        return H, bool(bad.value)
 
 
 class BatchTracker:

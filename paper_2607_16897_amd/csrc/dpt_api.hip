@@ -87,7 +87,9 @@ int check_params(const dpt_params* p, const dpt_camera* c) {
   if (p->min_points < 0) return fail(DPT_E_ARG, "min_points < 0");
   if (p->precision != DPT_PREC_FP32 && p->precision != DPT_PREC_MIXED) return fail(DPT_E_ARG, "precision %d", p->precision);
   if (p->precision == DPT_PREC_MIXED && p->n_pattern != 8) return fail(DPT_E_ARG, "mixed precision needs K = 8");
-  if (p->flags != 0) return fail(DPT_E_ARG, "unknown flags 0x%x", p->flags);
+  if (p->flags & ~DPT_FLAG_FIXED_H) return fail(DPT_E_ARG, "unknown flags 0x%x", p->flags);
+  if ((p->flags & DPT_FLAG_FIXED_H) && p->precision != DPT_PREC_FP32)
+    return fail(DPT_E_ARG, "the fixed-H mode computes in FP32");
   return DPT_OK;
 }
 
@@ -262,6 +264,8 @@ struct dpt_ctx {
   float* depth_stage = nullptr;  // device copy of a host depth map (allocated on first use)
   float* d_tot = nullptr;
   float* h_tot = nullptr;  // pinned
+  FixedH* d_fixed = nullptr;  // fixed-H mode: [levels]
+  float* d_hpart = nullptr;   // fixed-H mode: [levels][ceil(cap / 256)][21]
   Pattern pat;
   bool prof = false;
   ProfRing prof_pyr, prof_trk;  // pyramid and track launch timings
@@ -282,7 +286,7 @@ struct dpt_ctx {
     if (depth_stage) (void)hipFree(depth_stage);
     for (void* p : {(void*)pyr[0], (void*)pyr[1], (void*)staging, (void*)x0, (void*)valid, (void*)I0, (void*)gx,
                     (void*)gy, (void*)I0h, (void*)gh, (void*)pts, (void*)sel_idx, (void*)sel_count, (void*)sel_scratch, (void*)d_out,
-                    (void*)d_tot})
+                    (void*)d_tot, (void*)d_fixed, (void*)d_hpart})
       if (p) (void)hipFree(p);
     if (h_out) (void)hipHostFree(h_out);
     if (h_tot) (void)hipHostFree(h_tot);
@@ -307,7 +311,8 @@ void fill_track_args(const dpt_ctx* c, TrackArgs& a) {
   a.levels = c->prm.levels;
   a.max_iters = c->prm.max_iters;
   a.min_points = c->prm.min_points;
-  a.huber_k = c->prm.huber_k;
+  const bool fixed = (c->prm.flags & DPT_FLAG_FIXED_H) != 0;
+  a.huber_k = fixed ? 0.0f : c->prm.huber_k;  // the fixed-H mode has no weights
   a.step_eps = c->prm.step_eps;
   a.z_min = c->prm.z_min;
   a.pat = c->pat;
@@ -318,6 +323,7 @@ void fill_track_args(const dpt_ctx* c, TrackArgs& a) {
   a.ref.gy = c->gy;
   a.ref.I0h = c->I0h;
   a.ref.gh = c->gh;
+  a.ref.fixed = fixed ? c->d_fixed : nullptr;
   a.ref.n = c->n_points;
   a.ref.cap = c->cap;
   a.out = c->d_out;
@@ -393,6 +399,12 @@ int dpt_create(const dpt_camera* cam, const dpt_params* prm, int32_t max_points,
       (e = dev_alloc((void**)&c->sel_count, sizeof(int32_t))) ||
       (e = dev_alloc((void**)&c->sel_scratch, sizeof(int32_t) * select_scratch_ints(cam->width, cam->height))) || (e = dev_alloc((void**)&c->d_out, sizeof(TrackOut))) ||
       (e = dev_alloc((void**)&c->d_tot, kRedSlots * sizeof(float)))) {
+    delete c;
+    return e;
+  }
+  if ((prm->flags & DPT_FLAG_FIXED_H) &&
+      ((e = dev_alloc((void**)&c->d_fixed, L * sizeof(FixedH))) ||
+       (e = dev_alloc((void**)&c->d_hpart, L * ((cap + 255) / 256) * 21 * sizeof(float))))) {
     delete c;
     return e;
   }
@@ -512,6 +524,8 @@ PrecomputeArgs precompute_args(const dpt_ctx* c, const float* P, int32_t n, cons
   a.gy = c->gy;
   a.I0h = c->I0h;
   a.gh = c->gh;
+  a.fixed = c->d_fixed;
+  a.hpart = c->d_hpart;
   a.n = n;
   a.cap = c->cap;
   return a;
@@ -525,7 +539,9 @@ void commit_reference(dpt_ctx* c, int32_t n, const double T_rw[16]) {
 
 // IC precompute of the reference cache from n device points P at T_rw.
 int precompute_reference(dpt_ctx* c, const float* P, int32_t n, const double T_rw[16]) {
-  HIP_TRY(launch_precompute(precompute_args(c, P, n, T_rw), c->stream));
+  const PrecomputeArgs a = precompute_args(c, P, n, T_rw);
+  HIP_TRY(launch_precompute(a, c->stream));
+  if (c->prm.flags & DPT_FLAG_FIXED_H) HIP_TRY(launch_fixed_h(a, c->stream));
   commit_reference(c, n, T_rw);
   return DPT_OK;
 }
@@ -596,6 +612,11 @@ int dpt_set_reference_from_depth(dpt_ctx* c, int32_t n, int32_t margin, const fl
 
 namespace {
 
+int coop_variant(const dpt_params& p) {
+  if (p.precision == DPT_PREC_MIXED) return kCoopMixed;
+  return (p.flags & DPT_FLAG_FIXED_H) ? kCoopFixedH : kCoopFP32;
+}
+
 // Whether this frame runs on the cooperative chunked kernel.
 bool use_coop(dpt_ctx* c) {
   if (c->prm.precision == DPT_PREC_MIXED) return true;  // only the cooperative kernel has the mixed variant
@@ -612,7 +633,7 @@ int ensure_engine(dpt_ctx* c) {
     return fail(DPT_E_ARG, "%d points exceed the cooperative capacity at chunk %d", c->n_points, c->chunk);
   if (!c->eng_ready) {
     HIP_TRY(c->eng.init(1, &c->cap, c->chunk, true, c->stream));
-    c->eng.mixed = c->prm.precision == DPT_PREC_MIXED;
+    c->eng.variant = coop_variant(c->prm);
     c->eng_ready = true;
   }
   if (c->eng.dirty || c->eng.h_streams[0].a.ref.n != c->n_points) {
@@ -819,11 +840,32 @@ int dpt_normal_equations(dpt_ctx* c, int32_t level, const double T_rel[16], floa
   HIP_TRY(launch_normal_equations(a, c->stream));
   HIP_TRY(hipMemcpyAsync(c->h_tot, c->d_tot, kRedSlots * sizeof(float), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
-  for (int j = 0; j < 21; ++j) H21[j] = c->h_tot[j];
+  if (c->prm.flags & DPT_FLAG_FIXED_H) {  // H is the level's precomputed one
+    FixedH f;
+    HIP_TRY(hipMemcpy(&f, c->d_fixed + level, sizeof f, hipMemcpyDeviceToHost));
+    for (int j = 0; j < 21; ++j) H21[j] = (float)f.H[j];
+  } else {
+    for (int j = 0; j < 21; ++j) H21[j] = c->h_tot[j];
+  }
   for (int j = 0; j < 6; ++j) b6[j] = c->h_tot[kSlotB + j];
   *E = c->h_tot[kSlotE];
   *n = (int64_t)c->h_tot[kSlotN];
   *npts = (int32_t)c->h_tot[kSlotPts];
+  return DPT_OK;
+}
+
+int dpt_get_fixed_hessian(dpt_ctx* c, int32_t level, double* H36, int32_t* not_pd) {
+  g_err.clear();
+  if (!c || !H36 || !not_pd) return fail(DPT_E_ARG, "NULL argument");
+  if (!(c->prm.flags & DPT_FLAG_FIXED_H)) return fail(DPT_E_STATE, "the context is not in the fixed-H mode");
+  if (level < 0 || level >= c->prm.levels) return fail(DPT_E_ARG, "level %d", level);
+  if (!c->have_ref) return fail(DPT_E_STATE, "no reference points");
+  FixedH f;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  HIP_TRY(hipMemcpy(&f, c->d_fixed + level, sizeof f, hipMemcpyDeviceToHost));
+  for (int i = 0; i < 6; ++i)
+    for (int j = i; j < 6; ++j) H36[6 * i + j] = H36[6 * j + i] = f.H[i * 6 - (i * (i - 1)) / 2 + (j - i)];
+  *not_pd = f.bad;
   return DPT_OK;
 }
 
@@ -955,7 +997,7 @@ int build_groups(dpt_batch* b) {
       delete g;
       return fail(DPT_E_HIP, "cooperative group init: %s", hipGetErrorString(e));
     }
-    g->mixed = b->ctx[0]->prm.precision == DPT_PREC_MIXED;
+    g->variant = coop_variant(b->ctx[0]->prm);
     for (size_t k = 0; k < cur.size(); ++k) {
       TrackArgs a;
       fill_track_args(b->ctx[cur[k]], a);
@@ -1258,6 +1300,7 @@ int dpt_batch_set_reference_from_depth_all(dpt_batch* b, const int32_t* n_points
   HIP_TRY(launch_select_batch(ds, b->n, G_max, b->stream));
   HIP_TRY(launch_backproject_batch(db, b->n, max_n, b->stream));
   HIP_TRY(launch_precompute_batch(dp, b->n, max_samples, max_levels, b->stream));
+  if (b->ctx[0]->prm.flags & DPT_FLAG_FIXED_H) HIP_TRY(launch_fixed_h_batch(dp, b->n, max_n, max_levels, b->stream));
   for (int s = 0; s < b->n; ++s) {
     if (b->ctx[s]->n_points != n_points[s]) b->groups_dirty = true;
     commit_reference(b->ctx[s], n_points[s], T_rw + 16 * s);

@@ -21,22 +21,23 @@
 
 namespace dpt {
 
-// Wave 0 only.  Publish this chunk's column sums (`mine`, lanes < 32) under
+// Wave 0 only.  Publish this chunk's column sums (`mine`, lanes < NV) under
 // `tag`, wait until all nch chunks of the stream published theirs, and return
-// the stream totals in chunk order (lanes < 32).  False on timeout.
-template <bool KAHAN>
+// the stream totals in chunk order (lanes < NV).  False on timeout.  A chunk's
+// words are 32 apart whatever NV is.
+template <bool KAHAN, int NV>
 __device__ __forceinline__ bool exchange_partials(uint64_t* partials, int chunk, int nch, uint32_t tag, float mine,
                                                   int spin_limit, float* total) {
   const int lane = threadIdx.x & 63;
   uint64_t* buf = partials + (size_t)(tag & 1u) * nch * 32;
   const uint64_t hi = (uint64_t)tag << 32;
-  if (lane < 32)
+  if (lane < NV)
     __hip_atomic_store(&buf[chunk * 32 + lane], hi | __float_as_uint(mine), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
   for (int t = 0; t < spin_limit; ++t) {
     float s = 0.0f, comp = 0.0f;
     int ok = 1;
-    if (lane < 32) {
+    if (lane < NV) {
       for (int c0 = 0; c0 < nch; c0 += 8) {
         uint64_t v[8];
 #pragma unroll
@@ -69,25 +70,29 @@ __device__ __forceinline__ bool exchange_partials(uint64_t* partials, int chunk,
   return false;
 }
 
-// Block sum of acc[32] (after each thread accumulated its point), exchanged
+// Block sum of acc[NV] (after each thread accumulated its point), exchanged
 // across the stream's chunks; the totals land in sh_tot.  Returns false on
-// timeout (same value in every thread).
-template <bool KAHAN>
-__device__ __forceinline__ bool stream_total(float (&acc)[32], float* sh_red, float* sh_tot, int* sh_ok,
+// timeout (same value in every thread).  NV = 32 or 16.
+template <bool KAHAN, int NV>
+__device__ __forceinline__ bool stream_total(float (&acc)[NV], float* sh_red, float* sh_tot, int* sh_ok,
                                              uint64_t* partials, int chunk, int nch, uint32_t tag,
                                              int spin_limit) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  wave_reduce32(acc);
+  constexpr int PER_ROW = NV / 4;  // values per 16-lane row after the wave reduction
+  if constexpr (NV == 32)
+    wave_reduce32(acc);
+  else
+    wave_reduce16(acc);
   if ((lane & 15) == 0) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) sh_red[wave * 32 + 8 * (lane >> 4) + j] = acc[j];
+    for (int j = 0; j < PER_ROW; ++j) sh_red[wave * NV + PER_ROW * (lane >> 4) + j] = acc[j];
   }
   __syncthreads();
   if (wave == 0) {
     float s = 0.0f, comp = 0.0f;
-    if (lane < 32) {
+    if (lane < NV) {
       for (int w = 0; w < nw; ++w) {
-        const float x = sh_red[w * 32 + lane];
+        const float x = sh_red[w * NV + lane];
         if (KAHAN) {
           const float y = x - comp;
           const float u = s + y;
@@ -100,8 +105,8 @@ __device__ __forceinline__ bool stream_total(float (&acc)[32], float* sh_red, fl
     }
     float tot = s;
     bool ok = true;
-    if (nch > 1) ok = exchange_partials<KAHAN>(partials, chunk, nch, tag, s, spin_limit, &tot);
-    if (lane < 32) sh_tot[lane] = tot;
+    if (nch > 1) ok = exchange_partials<KAHAN, NV>(partials, chunk, nch, tag, s, spin_limit, &tot);
+    if (lane < NV) sh_tot[lane] = tot;
     if (lane == 0) *sh_ok = ok ? 1 : 0;
   }
   __syncthreads();
@@ -159,14 +164,21 @@ __device__ __forceinline__ void start_pose(const StartSlot* __restrict__ st, con
 
 // MIXED: FP16 reference cache, Kahan-compensated FP32 sums across waves and
 // chunks, FP64 solve, exponential and pose state.
-template <int CH, bool MIXED>
+// FIXED: fixed-H mode (FP32): unweighted residuals, only b, the cost and the
+// counts are reduced and exchanged (16 slots), and each level's constant H
+// comes factored from the precompute.
+template <int CH, bool MIXED, bool FIXED>
 __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __restrict__ streams,
                                                            const int2* __restrict__ work,
                                                            const StartSlot* __restrict__ start,
                                                            TrackOut* __restrict__ outs, uint32_t tag_base,
                                                            int spin_limit) {
+  static_assert(!(MIXED && FIXED), "the fixed-H mode computes in FP32");
   using PR = typename std::conditional<MIXED, PointRegsH, PointRegs>::type;
+  constexpr int NV = FIXED ? kFixSlots : 32;
+  constexpr int sE = FIXED ? kFixE : kSlotE, sN = FIXED ? kFixN : kSlotN, sP = FIXED ? kFixPts : kSlotPts;
   __shared__ CoopStream ss;
+  __shared__ float sh_fac[FIXED ? 2 : 1][28];  // fixed H: factor of the level (L, invd, bad), by level parity
   __shared__ double sh_T0[12], sh_rw[12], sh_h0[12], sh_h1[12], sh_m1[12], sh_m2[12];
   __shared__ float sh_tot[32];
   __shared__ float sh_red[(CH / 64) * 32];
@@ -204,26 +216,40 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
     const LevelGeom g = a.lv[l];
     const uint8_t* img = a.cur + g.off;
     load_point(a, l, i, pr);
+    if constexpr (FIXED) {
+      // read by every thread after the next exchange's barrier; the other
+      // parity's copy may still be in use by a previous level's solve
+      const FixedH& f = a.ref.fixed[l];
+      if (threadIdx.x < 21) sh_fac[l & 1][threadIdx.x] = f.L[threadIdx.x];
+      if (threadIdx.x >= 32 && threadIdx.x < 38) sh_fac[l & 1][21 + threadIdx.x - 32] = f.invd[threadIdx.x - 32];
+      if (threadIdx.x == 40) sh_fac[l & 1][27] = f.bad ? 1.0f : 0.0f;
+    }
     bool converged = false;
     for (int it = 0; it < a.max_iters; ++it) {
-      float acc[32];
+      float acc[NV];
 #pragma unroll
-      for (int j = 0; j < 32; ++j) acc[j] = 0.f;
-      accumulate_point<false, true>(a, pregs, g, img, T, pr, acc);
-      if (!stream_total<MIXED>(acc, sh_red, sh_tot, &sh_ok, ss.partials, chunk, nch, tag, spin_limit)) {
+      for (int j = 0; j < NV; ++j) acc[j] = 0.f;
+      accumulate_point<false, true, PR, NV>(a, pregs, g, img, T, pr, acc);
+      if (!stream_total<MIXED, NV>(acc, sh_red, sh_tot, &sh_ok, ss.partials, chunk, nch, tag, spin_limit)) {
         timed_out = stop = true;
         break;
       }
       ++tag;
-      samples += (int64_t)sh_tot[kSlotN];
-      if ((int)sh_tot[kSlotPts] < a.min_points) {
+      samples += (int64_t)sh_tot[sN];
+      if ((int)sh_tot[sP] < a.min_points) {
         status = 2;  // too few points
         stop = true;
         break;
       }
       int bad;
       double step;
-      if (MIXED) {
+      if (FIXED) {
+        const float* fac = sh_fac[FIXED ? (l & 1) : 0];
+        bad = fac[27] != 0.0f;
+        float stepf = 0.0f;
+        if (!bad) solve_fixed(fac, fac + 21, sh_tot + kFixB, T, &stepf);
+        step = stepf;
+      } else if (MIXED) {
         bad = solve_update_d(sh_tot, Td, &step);
         if (!bad)
 #pragma unroll
@@ -249,13 +275,13 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
     if (!stop && l == 0 && !converged) status = 1;  // iteration cap at level 0
   }
   if (!timed_out) {  // final cost-only pass at level 0
-    float acc[32];
+    float acc[NV];
 #pragma unroll
-    for (int j = 0; j < 32; ++j) acc[j] = 0.f;
+    for (int j = 0; j < NV; ++j) acc[j] = 0.f;
     const LevelGeom g = a.lv[0];
     load_point(a, 0, i, pr);
-    accumulate_point<true, true>(a, pregs, g, a.cur + g.off, T, pr, acc);
-    if (!stream_total<MIXED>(acc, sh_red, sh_tot, &sh_ok, ss.partials, chunk, nch, tag, spin_limit))
+    accumulate_point<true, true, PR, NV>(a, pregs, g, a.cur + g.off, T, pr, acc);
+    if (!stream_total<MIXED, NV>(acc, sh_red, sh_tot, &sh_ok, ss.partials, chunk, nch, tag, spin_limit))
       timed_out = true;
   }
   if (chunk == 0 && threadIdx.x == 0) {
@@ -273,13 +299,13 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
       ss.hist[j] = sh_h1[j];
       ss.hist[12 + j] = compose34_elem(Tf, sh_rw, j);
     }
-    o->E = sh_tot[kSlotE];
-    o->n = sh_tot[kSlotN];
+    o->E = sh_tot[sE];
+    o->n = sh_tot[sN];
     o->iterations = iterations;
     for (int j = 0; j < kMaxLevels; ++j) o->iters_per_level[j] = ipl[j];
-    o->n_valid_points = (int)sh_tot[kSlotPts];
+    o->n_valid_points = (int)sh_tot[sP];
     o->status = timed_out ? kStatusTimeout : status;
-    o->samples = samples + (int64_t)sh_tot[kSlotN];
+    o->samples = samples + (int64_t)sh_tot[sN];
   }
 }
 
@@ -287,13 +313,14 @@ template <int CH>
 static int coop_blocks_per_cu() {
   static int nb = -1;
   if (nb < 0) {
-    int v = 0, v2 = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, coop_track_kernel<CH, false>, CH, 0) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&v2, coop_track_kernel<CH, true>, CH, 0) != hipSuccess) {
+    int v = 0, v2 = 0, v3 = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, coop_track_kernel<CH, false, false>, CH, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&v2, coop_track_kernel<CH, true, false>, CH, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&v3, coop_track_kernel<CH, false, true>, CH, 0) != hipSuccess) {
       (void)hipGetLastError();
-      v = v2 = 0;
+      v = v2 = v3 = 0;
     }
-    nb = std::min(v, v2);
+    nb = std::min(v, std::min(v2, v3));
   }
   return nb;
 }
@@ -332,21 +359,22 @@ int coop_max_blocks(int chunk) {
 // into a reported timeout, not a hang.
 template <int CH>
 static hipError_t coop_launch_k(const CoopStream* d_streams, const int2* d_work, int n_work, const StartSlot* start,
-                                TrackOut* out, uint32_t tag_base, bool mixed, int spin_limit, hipStream_t s) {
+                                TrackOut* out, uint32_t tag_base, int variant, int spin_limit, hipStream_t s) {
   void* args[] = {(void*)&d_streams, (void*)&d_work, (void*)&start, (void*)&out, (void*)&tag_base,
                   (void*)&spin_limit};
-  const void* fn = mixed ? reinterpret_cast<const void*>(&coop_track_kernel<CH, true>)
-                         : reinterpret_cast<const void*>(&coop_track_kernel<CH, false>);
+  const void* fn = variant == kCoopMixed    ? reinterpret_cast<const void*>(&coop_track_kernel<CH, true, false>)
+                   : variant == kCoopFixedH ? reinterpret_cast<const void*>(&coop_track_kernel<CH, false, true>)
+                                            : reinterpret_cast<const void*>(&coop_track_kernel<CH, false, false>);
   if (4 * n_work <= coop_max_blocks(CH)) return hipLaunchKernel(fn, dim3(n_work), dim3(CH), args, 0, s);
   return hipLaunchCooperativeKernel(fn, dim3(n_work), dim3(CH), args, 0, s);
 }
 
 hipError_t launch_coop_track(const CoopStream* d_streams, const int2* d_work, int n_work, const StartSlot* start,
-                             TrackOut* out, uint32_t tag_base, int chunk, bool mixed, int spin_limit, hipStream_t s) {
+                             TrackOut* out, uint32_t tag_base, int chunk, int variant, int spin_limit, hipStream_t s) {
   switch (chunk) {
-    case 64: return coop_launch_k<64>(d_streams, d_work, n_work, start, out, tag_base, mixed, spin_limit, s);
-    case 128: return coop_launch_k<128>(d_streams, d_work, n_work, start, out, tag_base, mixed, spin_limit, s);
-    case 256: return coop_launch_k<256>(d_streams, d_work, n_work, start, out, tag_base, mixed, spin_limit, s);
+    case 64: return coop_launch_k<64>(d_streams, d_work, n_work, start, out, tag_base, variant, spin_limit, s);
+    case 128: return coop_launch_k<128>(d_streams, d_work, n_work, start, out, tag_base, variant, spin_limit, s);
+    case 256: return coop_launch_k<256>(d_streams, d_work, n_work, start, out, tag_base, variant, spin_limit, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -468,7 +496,7 @@ hipError_t CoopEngine::launch(int spin_limit, int slot) {
     if ((e = clear_partials()) != hipSuccess) return e;
   }
   e = launch_coop_track(d_streams, d_work, grid(), dv_start + (size_t)slot * n, dv_out + (size_t)slot * n, tag_base,
-                        chunk, mixed, spin_limit, stream);
+                        chunk, variant, spin_limit, stream);
   tag_base += span;
   return e;
 }

@@ -204,6 +204,30 @@ __device__ __forceinline__ void wave_reduce32(float (&a)[32]) {
   }
 }
 
+// wave_reduce32 for 16 values: one lane-swap step less.  On return a[j] of
+// every lane in row r = lane / 16 holds the wave total of value 4 r + j, j < 4.
+__device__ __forceinline__ void wave_reduce16(float (&a)[16]) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a[j]), __float_as_uint(a[j + 8]), false, false);
+    a[j] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a[j]), __float_as_uint(a[j + 4]), false, false);
+    a[j] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    float v = a[j];
+    v += dpp_ror<8>(v);
+    v += dpp_ror<4>(v);
+    v += dpp_ror<2>(v);
+    v += dpp_ror<1>(v);
+    a[j] = v;
+  }
+}
+
 // Workgroup total of 32 per-lane values into out[32] (LDS), fixed order.
 // `scratch` is 16 x 32 floats of LDS.
 __device__ __forceinline__ void block_reduce32(float (&a)[32], float* scratch, float* out) {
@@ -247,6 +271,12 @@ __device__ __forceinline__ void block_reduce32_kahan(float (&a)[32], float* scra
 // Index of H(i, j), i <= j, in the row-major upper-triangle order of the sums.
 __host__ __device__ constexpr int tri(int i, int j) { return i * 6 - (i * (i - 1)) / 2 + (j - i); }
 
+// With H = L L^T given by its factor (L(i, j), i >= j, at tri(j, i), and
+// invd = 1 / diag(L)), solve H delta = b by forward and back substitution and
+// apply T <- T exp(-delta) in FP32; *max_step = max_j |delta_j|.
+__device__ __forceinline__ void substitute_update(const float (&L)[21], const float (&invd)[6], const float (&b)[6],
+                                                  float* T, float* max_step);
+
 // Solve H delta = b (6x6 SPD from the 21 upper-triangle sums) by Cholesky in
 // FP32 and apply T <- T exp(-delta).  Returns 0, or 1 if a pivot is <= 1e-6 of
 // the largest diagonal entry (not positive definite).  Every loop is unrolled
@@ -279,10 +309,32 @@ __device__ __forceinline__ int solve_update(const float* tot_lds, float* T, floa
     }
   }
   if (bad) return 1;
+  float b[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) b[i] = tot[kSlotB + i];
+  substitute_update(L, invd, b, T, max_step);
+  return 0;
+}
+
+// Fixed-H mode: the factor of the level's constant H comes precomputed
+// (Lp[21], invdp[6], as in substitute_update); only the substitutions and the
+// update remain.  b: the 6 reduced right-hand-side sums.
+__device__ __forceinline__ void solve_fixed(const float* Lp, const float* invdp, const float* bp, float* T,
+                                            float* max_step) {
+  float L[21], invd[6], b[6];
+#pragma unroll
+  for (int q = 0; q < 21; ++q) L[q] = Lp[q];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) invd[q] = invdp[q], b[q] = bp[q];
+  substitute_update(L, invd, b, T, max_step);
+}
+
+__device__ __forceinline__ void substitute_update(const float (&L)[21], const float (&invd)[6], const float (&b)[6],
+                                                  float* T, float* max_step) {
   float y[6], d[6];
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
-    float s = tot[kSlotB + i];
+    float s = b[i];
 #pragma unroll
     for (int k = 0; k < i; ++k) s = fmaf(-L[tri(k, i)], y[k], s);
     y[i] = s * invd[i];
@@ -338,7 +390,6 @@ __device__ __forceinline__ int solve_update(const float* tot_lds, float* T, floa
   }
 #pragma unroll
   for (int j = 0; j < 12; ++j) T[j] = N[j];
-  return 0;
 }
 
 // FP64 variant of solve_update: Cholesky solve (pivot <= 1e-12 of the largest
@@ -536,11 +587,16 @@ __device__ __forceinline__ void load_point(const TrackArgs& a, int l, int i, Poi
 // zero, so no exit path has to materialise a zeroed accumulator.
 // GLOBAL_IMG: `img` is device global memory (loads compile to global_load);
 // otherwise it may be LDS.
-template <bool COST_ONLY, bool GLOBAL_IMG, class PR>
+// NV = 32: robust mode, the kSlot* layout.  NV = kFixSlots: fixed-H mode, no
+// weights (w = 1, cost r^2 / 2) and only b, E and the counts (kFix* layout).
+template <bool COST_ONLY, bool GLOBAL_IMG, class PR, int NV = 32>
 __device__ __forceinline__ void accumulate_point(const TrackArgs& a, const PatRegs& pat, const LevelGeom& g,
                                                  const uint8_t* __restrict__ img, const float* T,
-                                                 const PR& pr, float (&acc)[32]) {
-  const float kH = a.huber_k;
+                                                 const PR& pr, float (&acc)[NV]) {
+  constexpr bool FIXED = NV == kFixSlots;
+  static_assert(NV == 32 || FIXED, "slot layout");
+  constexpr int sE = FIXED ? kFixE : kSlotE, sN = FIXED ? kFixN : kSlotN, sP = FIXED ? kFixPts : kSlotPts;
+  const float kH = FIXED ? 0.0f : a.huber_k;
   float X, Y, Z;
   transform(T, pr.X0, pr.Y0, pr.Z0, X, Y, Z);
   float u, v;
@@ -586,34 +642,44 @@ __device__ __forceinline__ void accumulate_point(const TrackArgs& a, const PatRe
     E += rho;
     if (!COST_ONLY) {
       const float gx = pr.gx(k), gy = pr.gy(k);
-      const float wgx = w * gx, wgy = w * gy;
-      m00 = fmaf(wgx, gx, m00);
-      m01 = fmaf(wgx, gy, m01);
-      m11 = fmaf(wgy, gy, m11);
-      v0 = fmaf(wgx, r, v0);
-      v1 = fmaf(wgy, r, v1);
+      if (FIXED) {
+        v0 = fmaf(gx, r, v0);
+        v1 = fmaf(gy, r, v1);
+      } else {
+        const float wgx = w * gx, wgy = w * gy;
+        m00 = fmaf(wgx, gx, m00);
+        m01 = fmaf(wgx, gy, m01);
+        m11 = fmaf(wgy, gy, m11);
+        v0 = fmaf(wgx, r, v0);
+        v1 = fmaf(wgy, r, v1);
+      }
     }
   }
-  acc[kSlotE] += ok ? E : 0.0f;
-  acc[kSlotN] += ok ? 8.0f : 0.0f;
-  acc[kSlotPts] += ok ? 1.0f : 0.0f;
+  acc[sE] += ok ? E : 0.0f;
+  acc[sN] += ok ? 8.0f : 0.0f;
+  acc[sP] += ok ? 1.0f : 0.0f;
   if (COST_ONLY) return;
-  m00 = ok ? m00 : 0.0f, m01 = ok ? m01 : 0.0f, m11 = ok ? m11 : 0.0f;
   v0 = ok ? v0 : 0.0f, v1 = ok ? v1 : 0.0f;
   const float iz = pr.iz, xp = pr.xp, yp = pr.yp;
   const float au[6] = {-g.fx * xp * yp, g.fx * fmaf(xp, xp, 1.0f), -g.fx * yp, g.fx * iz, 0.0f, -g.fx * xp * iz};
   const float av[6] = {-g.fy * fmaf(yp, yp, 1.0f), g.fy * xp * yp, g.fy * xp, 0.0f, g.fy * iz, -g.fy * yp * iz};
-  int q = 0;
+  if constexpr (FIXED) {
 #pragma unroll
-  for (int r = 0; r < 6; ++r) {
-    const float ma = fmaf(m00, au[r], m01 * av[r]);
-    const float mc = fmaf(m01, au[r], m11 * av[r]);
+    for (int r = 0; r < 6; ++r) acc[kFixB + r] -= fmaf(au[r], v0, av[r] * v1);
+  } else {
+    m00 = ok ? m00 : 0.0f, m01 = ok ? m01 : 0.0f, m11 = ok ? m11 : 0.0f;
+    int q = 0;
 #pragma unroll
-    for (int c = r; c < 6; ++c) {
-      acc[q] = fmaf(ma, au[c], fmaf(mc, av[c], acc[q]));
-      ++q;
+    for (int r = 0; r < 6; ++r) {
+      const float ma = fmaf(m00, au[r], m01 * av[r]);
+      const float mc = fmaf(m01, au[r], m11 * av[r]);
+#pragma unroll
+      for (int c = r; c < 6; ++c) {
+        acc[q] = fmaf(ma, au[c], fmaf(mc, av[c], acc[q]));
+        ++q;
+      }
+      acc[kSlotB + r] -= fmaf(au[r], v0, av[r] * v1);
     }
-    acc[kSlotB + r] -= fmaf(au[r], v0, av[r] * v1);
   }
 }
 

@@ -34,6 +34,23 @@ struct Pattern {
   int8_t dx[kMaxPattern], dy[kMaxPattern];
 };
 
+// Fixed-H mode (Sec. IV-C, precompute and track): the inverse-compositional
+// Gauss-Newton matrix of one level, H = sum over every reference-valid point and
+// pattern sample of J J^T without weights, reduced once per reference, with its
+// Cholesky factor.  The track then reduces only b and the cost.
+struct FixedH {
+  double H[21];    // upper triangle, tri() order
+  float L[21];     // factor L(i, j), i >= j, stored at tri(j, i)
+  float invd[6];   // 1 / L(j, j)
+  int32_t bad;     // 1: a pivot <= 1e-6 of the largest diagonal entry (not positive definite)
+  int32_t pad;
+};
+static_assert(sizeof(FixedH) % 16 == 0, "FixedH is copied as 16-byte words");
+
+// Slots of the fixed-H reductions: [0,6) b, 6 cost E, 7 valid samples, 8 valid points.
+constexpr int kFixSlots = 16;
+enum { kFixB = 0, kFixE = 6, kFixN = 7, kFixPts = 8 };
+
 // Reference-side IC cache: per level l, sample s = i*K + k lives at l*cap*K + s.
 struct RefCache {
   const float4* x0;         // [cap] reference-camera points (w unused)
@@ -43,6 +60,7 @@ struct RefCache {
   const float* gy;          // [L][cap*K]
   const __half* I0h;        // mixed precision: [L][cap*K] template intensity - 128
   const __half2* gh;        // mixed precision: [L][cap*K] (gx, gy)
+  const FixedH* fixed;      // fixed-H mode: [L]; null in the robust (IRLS) mode
   int32_t n, cap;
 };
 
@@ -92,6 +110,8 @@ struct PrecomputeArgs {
   float *I0, *gx, *gy;
   __half* I0h;   // written when non-null (mixed precision)
   __half2* gh;
+  FixedH* fixed;   // fixed-H mode: [L] per-level matrix and factor, else null
+  float* hpart;    // fixed-H mode: [L][ceil(cap / 256)][21] per-workgroup partial sums
   int32_t n, cap;
 };
 
@@ -174,6 +194,9 @@ struct PyrJob {
   int32_t pad;
 };
 
+// Variants of the cooperative track kernel.
+enum { kCoopFP32 = 0, kCoopMixed = 1, kCoopFixedH = 2 };
+
 // Host-side owner of a cooperative track launch over n streams.  Start slots
 // and results live in host-mapped pinned memory that the kernel reads and
 // writes directly, in rings of kRing launches, so a launch needs no copy
@@ -192,7 +215,7 @@ struct CoopEngine {
   uint32_t tag_base = 1;       // epoch tags of the next launch start here; 0 marks a cleared word
   StartSlot* h_start = nullptr;   // [kRing][n], host-mapped
   StartSlot* dv_start = nullptr;  // device view of h_start
-  bool mixed = false;             // mixed-precision kernel variant
+  int variant = kCoopFP32;        // kernel variant (kCoopFP32, kCoopMixed, kCoopFixedH)
   TrackOut* h_out = nullptr;      // [kRing][n] results, host-mapped
   TrackOut* dv_out = nullptr;     // device view of h_out
   hipError_t init(int n_streams, const int* max_points, int chunk, bool xcd_pack, hipStream_t s);
@@ -236,6 +259,9 @@ hipError_t launch_backproject(const BackprojectArgs& a, hipStream_t s);
 hipError_t launch_precompute_batch(const PrecomputeArgs* d_args, int n_ref, int max_samples, int max_levels,
                                    hipStream_t s);
 hipError_t launch_backproject_batch(const BackprojectArgs* d_args, int n_maps, int max_n, hipStream_t s);
+// Fixed-H mode: per-level H and its factor from a finished precompute (a.fixed, a.hpart set).
+hipError_t launch_fixed_h(const PrecomputeArgs& a, hipStream_t s);
+hipError_t launch_fixed_h_batch(const PrecomputeArgs* d_args, int n_ref, int max_n, int max_levels, hipStream_t s);
 hipError_t launch_track(const TrackArgs& a, hipStream_t s);
 // One workgroup per frame; batch[b] describes frame b (device memory).
 hipError_t launch_track_batch(const TrackArgs& any, const TrackArgs* batch, int n_frames, int lds_bytes,
@@ -243,7 +269,7 @@ hipError_t launch_track_batch(const TrackArgs& any, const TrackArgs* batch, int 
 int track_lds_bytes(const LevelGeom* lv, int levels);
 hipError_t launch_normal_equations(const TrackArgs& a, hipStream_t s);
 hipError_t launch_coop_track(const CoopStream* d_streams, const int2* d_work, int n_work, const StartSlot* start,
-                             TrackOut* out, uint32_t tag_base, int chunk, bool mixed, int spin_limit, hipStream_t s);
+                             TrackOut* out, uint32_t tag_base, int chunk, int variant, int spin_limit, hipStream_t s);
 // Set a pose history (two row-major 4x4 T_cw) on the stream.
 hipError_t launch_set_history(double* hist, const double* T0, const double* T1, hipStream_t s);
 // Pose histories of n streams: d_vals[24 s ..] = (older, newer) 3x4 into d_hists[s] (device arrays).

@@ -96,6 +96,109 @@ hipError_t launch_precompute_batch(const PrecomputeArgs* d_args, int n_ref, int 
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- fixed-H mode (Sec. IV-C)
+
+// Per-point H contributions at the reference pose (x = x0), reduced per
+// workgroup: thread = point i of level blockIdx.y, J_k = gx_k au + gy_k av with
+// the warp Jacobian rows (au, av) at x0, so H_i = m00 au^T au + m01 (au^T av +
+// av^T au) + m11 av^T av over the point's K cached gradients.  Workgroup
+// partial sums go to hpart[l][blockIdx.x][21].
+__global__ __launch_bounds__(256) void fixed_h_partial_kernel(PrecomputeArgs one,
+                                                             const PrecomputeArgs* __restrict__ many) {
+  __shared__ float sh_red[4 * 32];
+  __shared__ float sh_tot[32];
+  const PrecomputeArgs& a = many ? many[blockIdx.z] : one;
+  const int l = blockIdx.y;
+  if (l >= a.levels || (int)blockIdx.x * 256 >= a.n) return;  // uniform over the workgroup
+  const int K = a.pat.K, i = blockIdx.x * 256 + threadIdx.x;
+  float acc[32];
+#pragma unroll
+  for (int j = 0; j < 32; ++j) acc[j] = 0.f;
+  if (i < a.n && a.valid[(int64_t)l * a.cap + i]) {
+    const int64_t o = ((int64_t)l * a.cap + i) * K;
+    float m00 = 0.f, m01 = 0.f, m11 = 0.f;
+    for (int k = 0; k < K; ++k) {
+      const float gx = a.gx[o + k], gy = a.gy[o + k];
+      m00 = fmaf(gx, gx, m00);
+      m01 = fmaf(gx, gy, m01);
+      m11 = fmaf(gy, gy, m11);
+    }
+    const float4 p = a.x0[i];
+    const LevelGeom g = a.lv[l];
+    const float iz = 1.0f / p.z, xp = p.x * iz, yp = p.y * iz;
+    const float au[6] = {-g.fx * xp * yp, g.fx * fmaf(xp, xp, 1.0f), -g.fx * yp, g.fx * iz, 0.0f, -g.fx * xp * iz};
+    const float av[6] = {-g.fy * fmaf(yp, yp, 1.0f), g.fy * xp * yp, g.fy * xp, 0.0f, g.fy * iz, -g.fy * yp * iz};
+    int q = 0;
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+      const float ma = fmaf(m00, au[r], m01 * av[r]);
+      const float mc = fmaf(m01, au[r], m11 * av[r]);
+#pragma unroll
+      for (int c = r; c < 6; ++c) acc[q++] = fmaf(ma, au[c], mc * av[c]);
+    }
+  }
+  block_reduce32(acc, sh_red, sh_tot);
+  const int pblk = (a.cap + 255) / 256;
+  if (threadIdx.x < 21) a.hpart[((int64_t)l * pblk + blockIdx.x) * 21 + threadIdx.x] = sh_tot[threadIdx.x];
+}
+
+// Level blockIdx.x: H = the workgroup partials summed in FP64 in workgroup
+// order, and its Cholesky factor in FP64 (pivot <= 1e-6 of the largest
+// diagonal entry: not positive definite, the FP32 solve's criterion), stored
+// rounded to FP32 for the track's substitutions.
+__global__ __launch_bounds__(64) void fixed_h_final_kernel(PrecomputeArgs one, const PrecomputeArgs* __restrict__ many) {
+  __shared__ double sh_H[21];
+  const PrecomputeArgs& a = many ? many[blockIdx.y] : one;
+  const int l = blockIdx.x;
+  if (l >= a.levels) return;
+  const int nblk = (a.n + 255) / 256, pblk = (a.cap + 255) / 256;
+  if (threadIdx.x < 21) {
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += (double)a.hpart[((int64_t)l * pblk + b) * 21 + threadIdx.x];
+    sh_H[threadIdx.x] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  FixedH& f = a.fixed[l];
+  double L[21], invd[6], dmax = 0.0;
+  for (int j = 0; j < 6; ++j) dmax = fmax(dmax, sh_H[tri(j, j)]);
+  int bad = 0;
+  for (int j = 0; j < 6; ++j) {
+    double d = sh_H[tri(j, j)];
+    for (int k = 0; k < j; ++k) d -= L[tri(k, j)] * L[tri(k, j)];
+    bad |= !(d > 1e-6 * dmax);
+    const double inv = 1.0 / sqrt(fmax(d, 1e-300));
+    invd[j] = inv;
+    for (int i = j + 1; i < 6; ++i) {
+      double t = sh_H[tri(j, i)];
+      for (int k = 0; k < j; ++k) t -= L[tri(k, i)] * L[tri(k, j)];
+      L[tri(j, i)] = t * inv;
+    }
+  }
+  for (int q = 0; q < 21; ++q) f.H[q] = sh_H[q], f.L[q] = (float)L[q];
+  for (int j = 0; j < 6; ++j) f.invd[j] = (float)invd[j];
+  f.bad = bad;
+}
+
+hipError_t launch_fixed_h(const PrecomputeArgs& a, hipStream_t s) {
+  if (a.n > 0)
+    hipLaunchKernelGGL(fixed_h_partial_kernel, dim3((a.n + 255) / 256, a.levels), dim3(256), 0, s, a,
+                       (const PrecomputeArgs*)nullptr);
+  hipLaunchKernelGGL(fixed_h_final_kernel, dim3(a.levels), dim3(64), 0, s, a, (const PrecomputeArgs*)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_fixed_h_batch(const PrecomputeArgs* d_args, int n_ref, int max_n, int max_levels, hipStream_t s) {
+  if (n_ref == 0) return hipSuccess;
+  PrecomputeArgs none;
+  std::memset(&none, 0, sizeof none);
+  if (max_n > 0)
+    hipLaunchKernelGGL(fixed_h_partial_kernel, dim3((max_n + 255) / 256, max_levels, n_ref), dim3(256), 0, s, none,
+                       d_args);
+  hipLaunchKernelGGL(fixed_h_final_kernel, dim3(max_levels, n_ref), dim3(64), 0, s, none, d_args);
+  return hipGetLastError();
+}
+
 // One thread per selected pixel: P = R_rw^T (z K^-1 [x, y, 1]^T - t_rw) in FP64,
 // rounded to FP32.  A pixel without a positive finite depth, and every entry
 // past the selection count, becomes a NaN point, which the precompute marks
@@ -328,8 +431,16 @@ __global__ __launch_bounds__(kTrackThreads) void track_kernel(TrackArgs a0, cons
           flag = 2;
           status = 2;  // too few points
         } else {
-          float step;
-          if (solve_update(sh_tot, sh_T, &step)) {
+          float step = 0.0f;
+          int bad;
+          if (a.ref.fixed) {  // fixed-H mode: the level's factor from the precompute
+            const FixedH& f = a.ref.fixed[l];
+            bad = f.bad;
+            if (!bad) solve_fixed(f.L, f.invd, sh_tot + kSlotB, sh_T, &step);
+          } else {
+            bad = solve_update(sh_tot, sh_T, &step);
+          }
+          if (bad) {
             flag = 2;
             status = 3;  // not positive definite
           } else {
