@@ -43,7 +43,8 @@ class Camera(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("huber_k", ctypes.c_double),
                 ("step_eps", ctypes.c_double), ("min_points", ctypes.c_int32), ("n_pattern", ctypes.c_int32),
-                ("pattern", ctypes.c_int32 * 256), ("z_min", ctypes.c_double), ("fixed_h", ctypes.c_int32)]
+                ("pattern", ctypes.c_int32 * 256), ("z_min", ctypes.c_double), ("fixed_h", ctypes.c_int32),
+                ("pyramid", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):
@@ -73,6 +74,12 @@ def _load():
         L.orc_pyramid_bytes.argtypes = [ctypes.c_int32] * 3
         L.orc_pyramid.restype = None
         L.orc_pyramid.argtypes = [_u8p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _u8p]
+        L.orc_pyramid_gauss.restype = None
+        L.orc_pyramid_gauss.argtypes = [_u8p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _dp]
+        L.orc_sample_f.restype = ctypes.c_double
+        L.orc_sample_f.argtypes = [_dp, ctypes.c_int32, ctypes.c_double, ctypes.c_double]
+        L.orc_gradient_f.restype = None
+        L.orc_gradient_f.argtypes = [_dp, ctypes.c_int32, ctypes.c_double, ctypes.c_double, _dp, _dp]
         L.orc_select_points.restype = ctypes.c_int32
         L.orc_select_points.argtypes = [_u8p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                         ctypes.c_int32, _i32p]
@@ -131,6 +138,21 @@ def pyramid(img: np.ndarray, levels: int) -> list[np.ndarray]:
     return res
 
 
+def pyramid_gauss(img: np.ndarray, levels: int) -> list[np.ndarray]:
+    """The floating-point Gaussian pyramid (binomial [1 3 3 1]/8, clamped), FP64."""
+    lib = _load()
+    img, p = _u8(img)
+    H, W = img.shape
+    out = np.empty(lib.orc_pyramid_bytes(W, H, levels), np.float64)
+    lib.orc_pyramid_gauss(p, W, W, H, levels, out.ctypes.data_as(_dp))
+    res, off = [], 0
+    for l in range(levels):
+        w, h = W >> l, H >> l
+        res.append(out[off:off + w * h].reshape(h, w))
+        off += w * h
+    return res
+
+
 def select_points(img: np.ndarray, n: int, margin: int = 8) -> np.ndarray:
     lib = _load()
     img, p = _u8(img)
@@ -149,6 +171,19 @@ def gradient(img, x, y):
     img, p = _u8(img)
     gx, gy = ctypes.c_double(), ctypes.c_double()
     _load().orc_gradient(p, img.shape[1], float(x), float(y), ctypes.byref(gx), ctypes.byref(gy))
+    return gx.value, gy.value
+
+
+def sample_f(img, x, y) -> float:
+    """Bilinear sample of a level stored as doubles."""
+    img, p = _f64(img)
+    return _load().orc_sample_f(p, img.shape[1], float(x), float(y))
+
+
+def gradient_f(img, x, y):
+    img, p = _f64(img)
+    gx, gy = ctypes.c_double(), ctypes.c_double()
+    _load().orc_gradient_f(p, img.shape[1], float(x), float(y), ctypes.byref(gx), ctypes.byref(gy))
     return gx.value, gy.value
 
 
@@ -186,10 +221,12 @@ DEFAULT_PATTERN = ((-2, 0), (2, 0), (0, -2), (0, 2), (-1, -1), (1, -1), (-1, 1),
 
 
 def make_params(levels=3, max_iters=10, huber_k=9.0, step_eps=1e-5, min_points=10, pattern=DEFAULT_PATTERN,
-                z_min=1e-3, fixed_h=False) -> Params:
+                z_min=1e-3, fixed_h=False, gauss=False) -> Params:
+    """gauss=True: track on the floating-point Gaussian pyramid instead of the uint8 box pyramid."""
     p = Params()
     p.levels, p.max_iters, p.huber_k, p.step_eps = levels, max_iters, huber_k, step_eps
     p.min_points, p.z_min, p.fixed_h = min_points, z_min, int(bool(fixed_h))
+    p.pyramid = 1 if gauss else 0
     pat = np.asarray(pattern, np.int32).reshape(-1, 2)
     p.n_pattern = len(pat)
     for i, v in enumerate(pat.reshape(-1)):

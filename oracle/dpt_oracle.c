@@ -15,7 +15,10 @@
  *   track with reduction and a Cholesky solve, coarse to fine.
  *
  * Readings where the paper is silent (each restated where it is used):
- *   pyramid    uint8 2x2 box mean, round half up, floor sizes (paper: FP32 Gaussian)
+ *   pyramid    uint8 2x2 box mean, round half up, floor sizes; or (flag) the paper's
+ *              floating-point Gaussian pyramid: separable binomial [1 3 3 1]/8, vertical
+ *              pass then horizontal pass, clamped borders, every second sample
+
  *   camera     f_l = f / 2^l, c_l = (c + 0.5) / 2^l - 0.5 (pixel centres at integers)
  *   gradient   central differences / 2 at integer pixels, bilinearly interpolated
  *   validity   a point counts only if Z > z_min and every pattern position p satisfies
@@ -52,6 +55,7 @@ typedef struct {
   int32_t pattern[256]; /* (dx, dy) pairs, level pixels */
   double z_min;         /* metres */
   int32_t fixed_h;      /* 1: paper mode, H reduced once per reference, no weights */
+  int32_t pyramid;      /* 0: uint8 box pyramid; 1: floating-point Gaussian pyramid */
 } orc_params;
 
 typedef struct {
@@ -91,6 +95,66 @@ void orc_pyramid(const uint8_t* img, int64_t pitch, int32_t W, int32_t H, int32_
     w = w2;
     h = h2;
   }
+}
+
+/* Floating-point Gaussian pyramid (Sec. IV-C, image pyramids): level 0 is the
+ * image as numbers; level l+1 blurs level l vertically, then horizontally, with
+ * the binomial kernel w = [1 3 3 1]/8 over samples 2y-1 .. 2y+2 (indices clamped
+ * to the level) and keeps every second sample, so that level-(l+1) pixel x sits
+ * at level-l position 2x + 1/2, the same pixel-centre convention as the box
+ * pyramid.  Sizes floor(W/2) x floor(H/2).  out: sum over levels of w_l h_l doubles. */
+void orc_pyramid_gauss(const uint8_t* img, int64_t pitch, int32_t W, int32_t H, int32_t L, double* out) {
+  static const double w[4] = {1.0 / 8.0, 3.0 / 8.0, 3.0 / 8.0, 1.0 / 8.0};
+  for (int y = 0; y < H; ++y)
+    for (int x = 0; x < W; ++x) out[(int64_t)y * W + x] = (double)img[y * pitch + x];
+  const double* src = out;
+  double* dst = out + (int64_t)W * H;
+  int ww = W, hh = H;
+  for (int l = 1; l < L; ++l) {
+    int w2 = ww / 2, h2 = hh / 2;
+    double* tmp = (double*)malloc(sizeof(double) * (size_t)h2 * ww); /* vertical pass, kept rows only */
+    for (int y = 0; y < h2; ++y)
+      for (int x = 0; x < ww; ++x) {
+        double acc = 0.0;
+        for (int i = 0; i < 4; ++i) {
+          int yy = 2 * y - 1 + i;
+          yy = yy < 0 ? 0 : (yy > hh - 1 ? hh - 1 : yy);
+          acc += w[i] * src[(int64_t)yy * ww + x];
+        }
+        tmp[(int64_t)y * ww + x] = acc;
+      }
+    for (int y = 0; y < h2; ++y)
+      for (int x = 0; x < w2; ++x) {
+        double acc = 0.0;
+        for (int j = 0; j < 4; ++j) {
+          int xx = 2 * x - 1 + j;
+          xx = xx < 0 ? 0 : (xx > ww - 1 ? ww - 1 : xx);
+          acc += w[j] * tmp[(int64_t)y * ww + xx];
+        }
+        dst[(int64_t)y * w2 + x] = acc;
+      }
+    free(tmp);
+    src = dst;
+    dst += (int64_t)w2 * h2;
+    ww = w2;
+    hh = h2;
+  }
+}
+
+/* The pyramid the tracker samples, as doubles: the box pyramid's uint8 values, or
+ * the Gaussian pyramid (prm->pyramid). */
+static double* orc_levels(const orc_params* prm, const uint8_t* img, int64_t pitch, int32_t W, int32_t H) {
+  int64_t n = orc_pyramid_bytes(W, H, prm->levels);
+  double* out = (double*)malloc(sizeof(double) * (size_t)n);
+  if (prm->pyramid == 1) {
+    orc_pyramid_gauss(img, pitch, W, H, prm->levels, out);
+  } else {
+    uint8_t* u = (uint8_t*)malloc((size_t)n);
+    orc_pyramid(img, pitch, W, H, prm->levels, u);
+    for (int64_t i = 0; i < n; ++i) out[i] = (double)u[i];
+    free(u);
+  }
+  return out;
 }
 
 /* ------------------------------------------------------------------ point selection */
@@ -171,6 +235,32 @@ void orc_gradient(const uint8_t* img, int32_t W, double x, double y, double* gx,
     const uint8_t* p = img + (int64_t)py[t] * W + px[t];
     sx += wt[t] * 0.5 * ((double)p[1] - (double)p[-1]);
     sy += wt[t] * 0.5 * ((double)p[W] - (double)p[-W]);
+  }
+  *gx = sx;
+  *gy = sy;
+}
+
+/* orc_sample and orc_gradient on a level stored as doubles (what the tracker uses). */
+double orc_sample_f(const double* img, int32_t W, double x, double y) {
+  double fx = floor(x), fy = floor(y);
+  int x0 = (int)fx, y0 = (int)fy;
+  double a = x - fx, c = y - fy;
+  const double* r0 = img + (int64_t)y0 * W + x0;
+  const double* r1 = r0 + W;
+  return (1 - a) * (1 - c) * r0[0] + a * (1 - c) * r0[1] + (1 - a) * c * r1[0] + a * c * r1[1];
+}
+
+void orc_gradient_f(const double* img, int32_t W, double x, double y, double* gx, double* gy) {
+  double fx = floor(x), fy = floor(y);
+  int x0 = (int)fx, y0 = (int)fy;
+  double a = x - fx, c = y - fy;
+  double wt[4] = {(1 - a) * (1 - c), a * (1 - c), (1 - a) * c, a * c};
+  int px[4] = {x0, x0 + 1, x0, x0 + 1}, py[4] = {y0, y0, y0 + 1, y0 + 1};
+  double sx = 0, sy = 0;
+  for (int t = 0; t < 4; ++t) {
+    const double* p = img + (int64_t)py[t] * W + px[t];
+    sx += wt[t] * 0.5 * (p[1] - p[-1]);
+    sy += wt[t] * 0.5 * (p[W] - p[-W]);
   }
   *gx = sx;
   *gy = sy;
@@ -319,7 +409,7 @@ typedef struct {
   orc_params prm;
   int32_t n;
   double T_rw[12];
-  uint8_t* pyr;          /* reference pyramid */
+  double* pyr;           /* reference pyramid (values as doubles) */
   int64_t off[8];        /* level offsets */
   double* x0;            /* [n][3] reference-camera points */
   uint8_t* refvalid;     /* [L][n] */
@@ -348,8 +438,7 @@ orc_ref* orc_ref_create(const orc_camera* cam, const orc_params* prm, const uint
   R->n = n;
   memcpy(R->T_rw, T_rw16, 12 * sizeof(double));
   int L = prm->levels, K = prm->n_pattern, W = cam->width, H = cam->height;
-  R->pyr = (uint8_t*)malloc((size_t)orc_pyramid_bytes(W, H, L));
-  orc_pyramid(ref_img, pitch, W, H, L, R->pyr);
+  R->pyr = orc_levels(prm, ref_img, pitch, W, H);
   orc_offsets(W, H, L, R->off);
   size_t nk = (size_t)n * K;
   R->x0 = (double*)malloc(sizeof(double) * 3 * (n > 0 ? n : 1));
@@ -366,7 +455,7 @@ orc_ref* orc_ref_create(const orc_camera* cam, const orc_params* prm, const uint
     double fx, fy, cx, cy;
     orc_level_camera(cam, l, &fx, &fy, &cx, &cy);
     int Wl = W >> l, Hl = H >> l;
-    const uint8_t* img = R->pyr + R->off[l];
+    const double* img = R->pyr + R->off[l];
     memset(R->Hfix[l], 0, sizeof R->Hfix[l]);
     for (int i = 0; i < n; ++i) {
       const double* x0 = R->x0 + 3 * i;
@@ -381,9 +470,9 @@ orc_ref* orc_ref_create(const orc_camera* cam, const orc_params* prm, const uint
       for (int k = 0; k < K; ++k) {
         double px = u + prm->pattern[2 * k], py = v + prm->pattern[2 * k + 1];
         size_t s = (size_t)l * nk + (size_t)i * K + k;
-        R->I0[s] = orc_sample(img, Wl, px, py);
+        R->I0[s] = orc_sample_f(img, Wl, px, py);
         double gx, gy;
-        orc_gradient(img, Wl, px, py, &gx, &gy);
+        orc_gradient_f(img, Wl, px, py, &gx, &gy);
         R->g[2 * s] = gx;
         R->g[2 * s + 1] = gy;
         double* J = R->J + 6 * s;
@@ -430,12 +519,12 @@ typedef struct {
 /* One Gauss-Newton linearisation at level l and relative pose T_rel (3x4):
  * residuals of Eq.(2) with the cached I0 and J, Huber weights, and the weighted
  * normal equations H = sum w J^T J, b = -sum w J^T r of Eq.(5). */
-static void orc_accumulate(const orc_ref* R, const uint8_t* cur_pyr, int l, const double* Trel, int cost_only,
+static void orc_accumulate(const orc_ref* R, const double* cur_pyr, int l, const double* Trel, int cost_only,
                            orc_ne* ne) {
   const orc_params* prm = &R->prm;
   int K = prm->n_pattern, n = R->n;
   int Wl = R->cam.width >> l, Hl = R->cam.height >> l;
-  const uint8_t* img = cur_pyr + R->off[l];
+  const double* img = cur_pyr + R->off[l];
   double fx, fy, cx, cy;
   orc_level_camera(&R->cam, l, &fx, &fy, &cx, &cy);
   double k = prm->huber_k;
@@ -455,7 +544,7 @@ static void orc_accumulate(const orc_ref* R, const uint8_t* cur_pyr, int l, cons
     ne->npts++;
     for (int q = 0; q < K; ++q) {
       size_t s = (size_t)l * nk + (size_t)i * K + q;
-      double r = R->I0[s] - orc_sample(img, Wl, u + prm->pattern[2 * q], v + prm->pattern[2 * q + 1]);
+      double r = R->I0[s] - orc_sample_f(img, Wl, u + prm->pattern[2 * q], v + prm->pattern[2 * q + 1]);
       double ar = fabs(r), w, rho;
       if (robust && ar > k) {
         w = k / ar;
@@ -481,8 +570,7 @@ static void orc_accumulate(const orc_ref* R, const uint8_t* cur_pyr, int l, cons
 /* Test hook: normal equations at level l for T_rel (4x4 row-major). */
 void orc_ref_normal_equations(const orc_ref* R, const uint8_t* cur_img, int64_t pitch, int32_t l, const double* Trel16,
                               double* H36, double* b6, double* E, int64_t* n, int32_t* npts) {
-  uint8_t* cur = (uint8_t*)malloc((size_t)orc_pyramid_bytes(R->cam.width, R->cam.height, R->prm.levels));
-  orc_pyramid(cur_img, pitch, R->cam.width, R->cam.height, R->prm.levels, cur);
+  double* cur = orc_levels(&R->prm, cur_img, pitch, R->cam.width, R->cam.height);
   orc_ne ne;
   orc_accumulate(R, cur, l, Trel16, 0, &ne);
   memcpy(H36, ne.H, sizeof ne.H);
@@ -503,8 +591,7 @@ int32_t orc_ref_track(const orc_ref* R, const uint8_t* cur_img, int64_t pitch, c
                       orc_result* out) {
   const orc_params* prm = &R->prm;
   int L = prm->levels;
-  uint8_t* cur = (uint8_t*)malloc((size_t)orc_pyramid_bytes(R->cam.width, R->cam.height, L));
-  orc_pyramid(cur_img, pitch, R->cam.width, R->cam.height, L, cur);
+  double* cur = orc_levels(prm, cur_img, pitch, R->cam.width, R->cam.height);
   memset(out, 0, sizeof *out);
   double Tinv[12], Trel[12];
   orc_invert(R->T_rw, Tinv);
