@@ -61,6 +61,17 @@ enum { DPT_PREC_FP32 = 0, DPT_PREC_MIXED = 1 };
  *                     frame; no robust weights (huber_k is ignored, the cost is
  *                     r^2/2).  FP32 precision only. */
 enum { DPT_FLAG_FIXED_H = 1 };
+/*   DPT_FLAG_GAUSS_F32  track on the paper's floating-point Gaussian pyramid
+ *                     (Sec. IV-C, image pyramids) instead of the uint8 box
+ *                     pyramid: level 0 is the frame as FP32, each coarser level
+ *                     blurs the previous one by a vertical and then a horizontal
+ *                     pass of the binomial kernel [1 3 3 1]/8 (samples 2y-1 ..
+ *                     2y+2, clamped to the level) and keeps every second sample,
+ *                     so pixel centres and per-level intrinsics are those of the
+ *                     box pyramid.  Point selection still reads the uint8 frame.
+ *                     FP32 precision, one-workgroup launch (DPT_LAUNCH_COOP is
+ *                     rejected). */
+enum { DPT_FLAG_GAUSS_F32 = 2 };
 
 /* pyramid slots */
 enum { DPT_SLOT_REF = 0, DPT_SLOT_CUR = 1 };
@@ -82,7 +93,7 @@ typedef struct {
   int32_t n_pattern;    /* patch samples per point K, 1..128 */
   int8_t pattern[256];  /* K (dx, dy) offsets in level pixels, |d| <= 16, same at every level */
   int32_t precision;    /* DPT_PREC_FP32 */
-  int32_t flags;        /* 0 or DPT_FLAG_FIXED_H */
+  int32_t flags;        /* 0, or DPT_FLAG_FIXED_H and/or DPT_FLAG_GAUSS_F32 */
 } dpt_params;
 
 typedef struct {
@@ -119,6 +130,9 @@ int dpt_build_pyramid(dpt_ctx* ctx, int32_t slot, const uint8_t* img, int64_t pi
 /* Copy level `level` of a slot's pyramid (floor(W/2^l) x floor(H/2^l), packed
  * rows) to host memory.  Test hook for bit-exact comparison. */
 int dpt_get_pyramid(dpt_ctx* ctx, int32_t slot, int32_t level, uint8_t* host_dst);
+/* DPT_FLAG_GAUSS_F32 contexts: level `level` of the slot's floating-point
+ * Gaussian pyramid, W_l x H_l floats, into host memory (waits for the stream). */
+int dpt_get_pyramid_f32(dpt_ctx* ctx, int32_t slot, int32_t level, float* host_dst);
 
 /* Map-point selection on the REF slot's level 0 (stand-in for the map points the
  * indirect pipeline provides, Sec. III): the n pixels with the largest integer

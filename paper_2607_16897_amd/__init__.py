@@ -21,6 +21,7 @@ DPT_OK, DPT_E_ARG, DPT_E_HIP, DPT_E_STATE, DPT_E_OOM = 0, -1, -2, -3, -4
 TRACK_OK, TRACK_MAX_ITERS, TRACK_TOO_FEW_POINTS, TRACK_NOT_PD = 0, 1, 2, 3
 PREC_FP32, PREC_MIXED = 0, 1
 FLAG_FIXED_H = 1  # dpt_params.flags: the paper's constant-H track
+FLAG_GAUSS_F32 = 2  # dpt_params.flags: track on the floating-point Gaussian pyramid
 SLOT_REF, SLOT_CUR = 0, 1
 LAUNCH_AUTO, LAUNCH_WORKGROUP, LAUNCH_COOP = 0, 1, 2
 INIT_GIVEN, INIT_CONST_VELOCITY = 0, 1
@@ -76,6 +77,7 @@ SIGNATURES = {
     "dpt_destroy": (None, [_vp]),
     "dpt_build_pyramid": (ctypes.c_int, [_vp, _i32, _vp, _i64, _i32]),
     "dpt_get_pyramid": (ctypes.c_int, [_vp, _i32, _i32, _vp]),
+    "dpt_get_pyramid_f32": (ctypes.c_int, [_vp, _i32, _i32, _vp]),
     "dpt_select_points": (ctypes.c_int, [_vp, _i32, _i32, _vp, ctypes.POINTER(_i32)]),
     "dpt_set_reference_points": (ctypes.c_int, [_vp, _vp, _i32, ctypes.POINTER(ctypes.c_double), _i32]),
     "dpt_set_reference_from_depth": (ctypes.c_int, [_vp, _i32, _i32, _vp, _i64, _i32,
@@ -177,10 +179,13 @@ def make_camera(cam) -> Camera:
 
 
 def make_params(levels=3, max_iters=10, huber_k=9.0, step_eps=1e-5, z_min=1e-3, min_points=10,
-                pattern=DEFAULT_PATTERN, precision=PREC_FP32, flags=0, fixed_h=False) -> Params:
-    """fixed_h=True sets FLAG_FIXED_H (the paper's constant-H track, no weights)."""
+                pattern=DEFAULT_PATTERN, precision=PREC_FP32, flags=0, fixed_h=False, gauss=False) -> Params:
+    """fixed_h=True sets FLAG_FIXED_H (the paper's constant-H track, no weights);
+    gauss=True sets FLAG_GAUSS_F32 (the floating-point Gaussian pyramid)."""
     if fixed_h:
         flags |= FLAG_FIXED_H
+    if gauss:
+        flags |= FLAG_GAUSS_F32
     p = Params()
     p.levels, p.max_iters, p.huber_k, p.step_eps, p.z_min = levels, max_iters, huber_k, step_eps, z_min
     p.min_points, p.precision, p.flags = min_points, precision, flags
@@ -228,6 +233,13 @@ class Tracker:
         w, h = self.cam.width >> level, self.cam.height >> level
         out = np.empty((h, w), np.uint8)
         _check(self._lib.dpt_get_pyramid(self._h, slot, level, out.ctypes.data))
+        return out
+
+    def get_pyramid_f32(self, slot: int, level: int) -> np.ndarray:
+        """Level of the floating-point Gaussian pyramid (FLAG_GAUSS_F32 contexts)."""
+        w, h = self.cam.width >> level, self.cam.height >> level
+        out = np.empty((h, w), np.float32)
+        _check(self._lib.dpt_get_pyramid_f32(self._h, slot, level, out.ctypes.data))
         return out
 
     def select_points(self, n: int, margin: int = 8) -> np.ndarray:

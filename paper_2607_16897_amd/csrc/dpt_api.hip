@@ -87,9 +87,11 @@ int check_params(const dpt_params* p, const dpt_camera* c) {
   if (p->min_points < 0) return fail(DPT_E_ARG, "min_points < 0");
   if (p->precision != DPT_PREC_FP32 && p->precision != DPT_PREC_MIXED) return fail(DPT_E_ARG, "precision %d", p->precision);
   if (p->precision == DPT_PREC_MIXED && p->n_pattern != 8) return fail(DPT_E_ARG, "mixed precision needs K = 8");
-  if (p->flags & ~DPT_FLAG_FIXED_H) return fail(DPT_E_ARG, "unknown flags 0x%x", p->flags);
+  if (p->flags & ~(DPT_FLAG_FIXED_H | DPT_FLAG_GAUSS_F32)) return fail(DPT_E_ARG, "unknown flags 0x%x", p->flags);
   if ((p->flags & DPT_FLAG_FIXED_H) && p->precision != DPT_PREC_FP32)
     return fail(DPT_E_ARG, "the fixed-H mode computes in FP32");
+  if ((p->flags & DPT_FLAG_GAUSS_F32) && p->precision != DPT_PREC_FP32)
+    return fail(DPT_E_ARG, "the Gaussian float pyramid runs in FP32");
   return DPT_OK;
 }
 
@@ -242,6 +244,7 @@ struct dpt_ctx {
   PyrGeom pg;
   int64_t pyr_bytes = 0;
   uint8_t* pyr[2] = {nullptr, nullptr};
+  float* pyrf[2] = {nullptr, nullptr};  // DPT_FLAG_GAUSS_F32: the floating-point Gaussian pyramids
   bool have_pyr[2] = {false, false};
   uint8_t* staging = nullptr;  // level-0 upload buffer for host images
   float4* x0 = nullptr;
@@ -286,7 +289,7 @@ struct dpt_ctx {
     if (depth_stage) (void)hipFree(depth_stage);
     for (void* p : {(void*)pyr[0], (void*)pyr[1], (void*)staging, (void*)x0, (void*)valid, (void*)I0, (void*)gx,
                     (void*)gy, (void*)I0h, (void*)gh, (void*)pts, (void*)sel_idx, (void*)sel_count, (void*)sel_scratch, (void*)d_out,
-                    (void*)d_tot, (void*)d_fixed, (void*)d_hpart})
+                    (void*)d_tot, (void*)d_fixed, (void*)d_hpart, (void*)pyrf[0], (void*)pyrf[1]})
       if (p) (void)hipFree(p);
     if (h_out) (void)hipHostFree(h_out);
     if (h_tot) (void)hipHostFree(h_tot);
@@ -307,6 +310,7 @@ int dev_alloc(void** p, size_t bytes) {
 void fill_track_args(const dpt_ctx* c, TrackArgs& a) {
   std::memset(&a, 0, sizeof a);
   a.cur = c->pyr[DPT_SLOT_CUR];
+  a.curf = c->pyrf[DPT_SLOT_CUR];
   for (int l = 0; l < kMaxLevels; ++l) a.lv[l] = c->lv[l];
   a.levels = c->prm.levels;
   a.max_iters = c->prm.max_iters;
@@ -402,6 +406,11 @@ int dpt_create(const dpt_camera* cam, const dpt_params* prm, int32_t max_points,
     delete c;
     return e;
   }
+  if ((prm->flags & DPT_FLAG_GAUSS_F32) && ((e = dev_alloc((void**)&c->pyrf[0], (size_t)off * sizeof(float))) ||
+                                            (e = dev_alloc((void**)&c->pyrf[1], (size_t)off * sizeof(float))))) {
+    delete c;
+    return e;
+  }
   if ((prm->flags & DPT_FLAG_FIXED_H) &&
       ((e = dev_alloc((void**)&c->d_fixed, L * sizeof(FixedH))) ||
        (e = dev_alloc((void**)&c->d_hpart, L * ((cap + 255) / 256) * 21 * sizeof(float))))) {
@@ -459,6 +468,7 @@ int dpt_build_pyramid(dpt_ctx* c, int32_t slot, const uint8_t* img, int64_t pitc
   int ps = -1;
   if (c->prof) HIP_TRY(c->prof_pyr.begin(c->stream, &ps));
   HIP_TRY(launch_pyramid(src, sp, c->pyr[slot], c->pg, c->stream));
+  if (c->pyrf[slot]) HIP_TRY(launch_pyramid_gauss(src, sp, c->pyrf[slot], c->pg, c->stream));
   if (c->prof) HIP_TRY(c->prof_pyr.end(c->stream, ps));
   c->have_pyr[slot] = true;
   if (slot == DPT_SLOT_REF) c->have_ref = false;
@@ -474,6 +484,20 @@ int dpt_get_pyramid(dpt_ctx* c, int32_t slot, int32_t level, uint8_t* host_dst) 
   if (!c->have_pyr[slot]) return fail(DPT_E_STATE, "slot %d has no pyramid", slot);
   const LevelGeom& g = c->lv[level];
   HIP_TRY(hipMemcpyAsync(host_dst, c->pyr[slot] + g.off, (size_t)g.W * g.H, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return DPT_OK;
+}
+
+int dpt_get_pyramid_f32(dpt_ctx* c, int32_t slot, int32_t level, float* host_dst) {
+  g_err.clear();
+  if (!c || !host_dst) return fail(DPT_E_ARG, "NULL argument");
+  if (!(c->prm.flags & DPT_FLAG_GAUSS_F32)) return fail(DPT_E_STATE, "the context has no Gaussian float pyramid");
+  if (slot != DPT_SLOT_REF && slot != DPT_SLOT_CUR) return fail(DPT_E_ARG, "slot %d", slot);
+  if (level < 0 || level >= c->prm.levels) return fail(DPT_E_ARG, "level %d", level);
+  if (!c->have_pyr[slot]) return fail(DPT_E_STATE, "slot %d has no pyramid", slot);
+  const LevelGeom& g = c->lv[level];
+  HIP_TRY(hipMemcpyAsync(host_dst, c->pyrf[slot] + g.off, (size_t)g.W * g.H * sizeof(float), hipMemcpyDeviceToHost,
+                         c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   return DPT_OK;
 }
@@ -511,6 +535,7 @@ PrecomputeArgs precompute_args(const dpt_ctx* c, const float* P, int32_t n, cons
   PrecomputeArgs a;
   std::memset(&a, 0, sizeof a);
   a.ref = c->pyr[DPT_SLOT_REF];
+  a.reff = c->pyrf[DPT_SLOT_REF];
   for (int l = 0; l < kMaxLevels; ++l) a.lv[l] = c->lv[l];
   a.levels = c->prm.levels;
   a.z_min = c->prm.z_min;
@@ -620,6 +645,7 @@ int coop_variant(const dpt_params& p) {
 // Whether this frame runs on the cooperative chunked kernel.
 bool use_coop(dpt_ctx* c) {
   if (c->prm.precision == DPT_PREC_MIXED) return true;  // only the cooperative kernel has the mixed variant
+  if (c->prm.flags & DPT_FLAG_GAUSS_F32) return false;  // float levels: the one-workgroup kernel
   if (c->launch_mode == DPT_LAUNCH_WORKGROUP || c->prm.n_pattern != 8) return false;
   const int nch = c->n_points > 0 ? (c->n_points + c->chunk - 1) / c->chunk : 1;
   return nch <= coop_max_blocks(c->chunk) / 8;  // the XCD-packed grid may hold up to 8x padding
@@ -794,6 +820,8 @@ int dpt_set_launch_config(dpt_ctx* c, int32_t mode, int32_t chunk) {
   if (mode < DPT_LAUNCH_AUTO || mode > DPT_LAUNCH_COOP) return fail(DPT_E_ARG, "mode %d", mode);
   if (chunk != 64 && chunk != 128 && chunk != 256) return fail(DPT_E_ARG, "chunk %d not in {64, 128, 256}", chunk);
   if (mode == DPT_LAUNCH_COOP && c->prm.n_pattern != 8) return fail(DPT_E_ARG, "cooperative track needs K = 8");
+  if (mode == DPT_LAUNCH_COOP && (c->prm.flags & DPT_FLAG_GAUSS_F32))
+    return fail(DPT_E_ARG, "the Gaussian float pyramid runs on the one-workgroup launch");
   if (mode == DPT_LAUNCH_WORKGROUP && c->prm.precision == DPT_PREC_MIXED)
     return fail(DPT_E_ARG, "mixed precision runs on the cooperative launch only");
   if (chunk != c->chunk && c->eng_ready) {
@@ -1028,6 +1056,7 @@ int build_groups(dpt_batch* b) {
 
 bool batch_use_coop(const dpt_batch* b) {
   if (b->ctx[0]->prm.precision == DPT_PREC_MIXED) return true;
+  if (b->ctx[0]->prm.flags & DPT_FLAG_GAUSS_F32) return false;
   return b->launch_mode != DPT_LAUNCH_WORKGROUP && b->ctx[0]->prm.n_pattern == 8 && coop_max_blocks(b->chunk) > 0;
 }
 
@@ -1103,7 +1132,7 @@ int batch_track_workgroup(dpt_batch* b, const double* T_cw_init, dpt_result* out
     fill_track_args(c, a);
     rel_pose_f32(c, T_cw_init + 16 * s, a.T_init);
     a.out = b->d_outs + s;
-    lds = std::max(lds, track_lds_bytes(c->lv, c->prm.levels));
+    lds = std::max(lds, track_lds_bytes(c->lv, c->prm.levels, c->pyrf[0] ? 4 : 1));
     max_points = std::max(max_points, c->n_points);
   }
   HIP_TRY(hipMemcpyAsync(b->d_args, b->h_args, sizeof(TrackArgs) * b->n, hipMemcpyHostToDevice, b->stream));
@@ -1213,6 +1242,9 @@ int dpt_batch_build_pyramids(dpt_batch* b, int32_t slot, const uint8_t* const* i
   int ps = -1;
   if (b->prof) HIP_TRY(b->prof_pyr.begin(b->stream, &ps));
   HIP_TRY(launch_pyramid_batch(d_jobs, b->n, max_w, max_h, b->ctx[0]->prm.levels, b->stream));
+  for (int s = 0; s < b->n; ++s)
+    if (b->ctx[s]->pyrf[slot])
+      HIP_TRY(launch_pyramid_gauss(h_jobs[s].src, h_jobs[s].pitch, b->ctx[s]->pyrf[slot], b->ctx[s]->pg, b->stream));
   if (b->prof) HIP_TRY(b->prof_pyr.end(b->stream, ps));
   if (!on_device) HIP_TRY(hipStreamSynchronize(b->stream));  // the host images are only borrowed
   for (int s = 0; s < b->n; ++s) {
@@ -1382,6 +1414,8 @@ int dpt_batch_set_launch_config(dpt_batch* b, int32_t mode, int32_t chunk) {
   if (mode < DPT_LAUNCH_AUTO || mode > DPT_LAUNCH_COOP) return fail(DPT_E_ARG, "mode %d", mode);
   if (chunk != 64 && chunk != 128 && chunk != 256) return fail(DPT_E_ARG, "chunk %d not in {64, 128, 256}", chunk);
   if (mode == DPT_LAUNCH_COOP && b->ctx[0]->prm.n_pattern != 8) return fail(DPT_E_ARG, "cooperative track needs K = 8");
+  if (mode == DPT_LAUNCH_COOP && (b->ctx[0]->prm.flags & DPT_FLAG_GAUSS_F32))
+    return fail(DPT_E_ARG, "the Gaussian float pyramid runs on the one-workgroup launch");
   if (mode == DPT_LAUNCH_WORKGROUP && b->ctx[0]->prm.precision == DPT_PREC_MIXED)
     return fail(DPT_E_ARG, "mixed precision runs on the cooperative launch only");
   const int e = batch_synchronize(b);

@@ -51,11 +51,13 @@ __device__ __forceinline__ bool inside(const LevelGeom& g, const PatRegs& p, flo
          (v + p.dy_max < (float)(g.H - 2));
 }
 
-// Bilinear intensity of a uint8 level, pixel centres at integer coordinates.
-__device__ __forceinline__ float bilinear(const uint8_t* img, int W, float x, float y) {
+// Bilinear intensity of a level (uint8 or float pixels), pixel centres at
+// integer coordinates.
+template <class PIX>
+__device__ __forceinline__ float bilinear(const PIX* img, int W, float x, float y) {
   float fx = floorf(x), fy = floorf(y);
   float a = x - fx, c = y - fy;
-  const uint8_t* p = img + (int)fy * W + (int)fx;
+  const PIX* p = img + (int)fy * W + (int)fx;
   float p00 = p[0], p10 = p[1], p01 = p[W], p11 = p[W + 1];
   float top = fmaf(a, p10 - p00, p00);
   float bot = fmaf(a, p11 - p01, p01);
@@ -64,10 +66,11 @@ __device__ __forceinline__ float bilinear(const uint8_t* img, int W, float x, fl
 
 // Reference-side gradient: central differences / 2 at the four bilinear taps,
 // blended with the same bilinear weights.
-__device__ __forceinline__ void gradient(const uint8_t* img, int W, float x, float y, float& gx, float& gy) {
+template <class PIX>
+__device__ __forceinline__ void gradient(const PIX* img, int W, float x, float y, float& gx, float& gy) {
   float fx = floorf(x), fy = floorf(y);
   float a = x - fx, c = y - fy;
-  const uint8_t* p = img + (int)fy * W + (int)fx;
+  const PIX* p = img + (int)fy * W + (int)fx;
   float gx00 = 0.5f * ((float)p[1] - (float)p[-1]);
   float gx10 = 0.5f * ((float)p[2] - (float)p[0]);
   float gx01 = 0.5f * ((float)p[W + 1] - (float)p[W - 1]);

@@ -79,6 +79,7 @@ struct TrackOut {
 
 struct TrackArgs {
   const uint8_t* cur;  // current pyramid base
+  const float* curf;   // floating-point Gaussian pyramid of the current frame (same offsets), or null
   LevelGeom lv[kMaxLevels];
   int32_t levels, max_iters, min_points;
   float huber_k, step_eps, z_min;
@@ -99,6 +100,7 @@ struct PyrGeom {
 
 struct PrecomputeArgs {
   const uint8_t* ref;  // reference pyramid base
+  const float* reff;   // floating-point Gaussian pyramid of the reference (same offsets), or null
   LevelGeom lv[kMaxLevels];
   int32_t levels;
   float z_min;
@@ -244,6 +246,8 @@ int cnn_forward_levels(struct ::dpt_cnn* c, const uint8_t* const* refs, const ui
 
 // Launchers (kernels.hip, coop.hip).  Each returns the hipError_t of the launch.
 hipError_t launch_pyramid(const uint8_t* src, int64_t pitch, uint8_t* dst, const PyrGeom& g, hipStream_t s);
+// Floating-point Gaussian pyramid of a uint8 frame (levels at the offsets of g, in floats).
+hipError_t launch_pyramid_gauss(const uint8_t* src, int64_t pitch, float* dst, const PyrGeom& g, hipStream_t s);
 // Point selection; `scratch` holds select_scratch_ints(W, H) ints of device memory.
 int64_t select_scratch_ints(int32_t W, int32_t H);
 hipError_t launch_select(const uint8_t* img, int32_t W, int32_t H, int32_t margin, int32_t n, int32_t* idx,
@@ -266,7 +270,7 @@ hipError_t launch_track(const TrackArgs& a, hipStream_t s);
 // One workgroup per frame; batch[b] describes frame b (device memory).
 hipError_t launch_track_batch(const TrackArgs& any, const TrackArgs* batch, int n_frames, int lds_bytes,
                               int max_points, hipStream_t s);
-int track_lds_bytes(const LevelGeom* lv, int levels);
+int track_lds_bytes(const LevelGeom* lv, int levels, int pixel_bytes);  // pixel_bytes: 1 uint8, 4 float
 hipError_t launch_normal_equations(const TrackArgs& a, hipStream_t s);
 hipError_t launch_coop_track(const CoopStream* d_streams, const int2* d_work, int n_work, const StartSlot* start,
                              TrackOut* out, uint32_t tag_base, int chunk, int variant, int spin_limit, hipStream_t s);

@@ -6,6 +6,7 @@
 // and the bilinear sample with identical arithmetic (an identical frame at the
 // reference pose then gives residuals of exactly zero).
 #include <cstring>
+#include <type_traits>
 
 #include "dpt_device.h"
 
@@ -37,6 +38,50 @@ hipError_t launch_pyramid(const uint8_t* src, int64_t pitch, uint8_t* dst, const
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- Gaussian pyramid (Sec. IV-C)
+
+// Level 0 of the floating-point pyramid: the frame's uint8 values as floats.
+__global__ __launch_bounds__(256) void gauss_level0_kernel(const uint8_t* __restrict__ src, int64_t pitch,
+                                                           float* __restrict__ dst, int W, int H) {
+  const int x = blockIdx.x * 64 + (threadIdx.x & 63), y = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (x < W && y < H) dst[(int64_t)y * W + x] = (float)src[y * pitch + x];
+}
+
+// Level l+1 from level l (w x h): the binomial kernel [1 3 3 1]/8 over samples
+// 2y-1 .. 2y+2, clamped to the level, first down the four columns (the
+// vertical pass), then across them (the horizontal pass), kept at every second
+// sample: level-(l+1) pixel x sits at level-l position 2x + 1/2.
+__global__ __launch_bounds__(256) void gauss_down_kernel(const float* __restrict__ src, int w, int h,
+                                                         float* __restrict__ dst, int w2, int h2) {
+  const int x = blockIdx.x * 64 + (threadIdx.x & 63), y = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (x >= w2 || y >= h2) return;
+  const float wt[4] = {0.125f, 0.375f, 0.375f, 0.125f};
+  int rows[4], cols[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    rows[i] = min(max(2 * y - 1 + i, 0), h - 1) * w;
+    cols[i] = min(max(2 * x - 1 + i, 0), w - 1);
+  }
+  float acc = 0.0f;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    float col = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) col += wt[i] * src[rows[i] + cols[j]];
+    acc += wt[j] * col;
+  }
+  dst[(int64_t)y * w2 + x] = acc;
+}
+
+hipError_t launch_pyramid_gauss(const uint8_t* src, int64_t pitch, float* dst, const PyrGeom& g, hipStream_t s) {
+  hipLaunchKernelGGL(gauss_level0_kernel, dim3((g.W[0] + 63) / 64, (g.H[0] + 3) / 4), dim3(256), 0, s, src, pitch,
+                     dst + g.off[0], g.W[0], g.H[0]);
+  for (int l = 1; l < g.levels; ++l)
+    hipLaunchKernelGGL(gauss_down_kernel, dim3((g.W[l] + 63) / 64, (g.H[l] + 3) / 4), dim3(256), 0, s,
+                       (const float*)(dst + g.off[l - 1]), g.W[l - 1], g.H[l - 1], dst + g.off[l], g.W[l], g.H[l]);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- IC precompute (Eq.(6))
 
 // One lane per (point, pattern sample) and level: x0 = T_rw P, the point's
@@ -64,10 +109,14 @@ __global__ __launch_bounds__(256) void precompute_kernel(PrecomputeArgs one, con
   if (k == 0) a.valid[(int64_t)l * a.cap + i] = ok ? 1 : 0;
   float I0 = 0.f, gx = 0.f, gy = 0.f;
   if (ok) {
-    const uint8_t* img = a.ref + g.off;
-    float px = u + (float)a.pat.dx[k], py = v + (float)a.pat.dy[k];
-    I0 = bilinear(img, g.W, px, py);
-    gradient(img, g.W, px, py, gx, gy);
+    const float px = u + (float)a.pat.dx[k], py = v + (float)a.pat.dy[k];
+    if (a.reff) {  // floating-point Gaussian pyramid
+      I0 = bilinear(a.reff + g.off, g.W, px, py);
+      gradient(a.reff + g.off, g.W, px, py, gx, gy);
+    } else {
+      I0 = bilinear(a.ref + g.off, g.W, px, py);
+      gradient(a.ref + g.off, g.W, px, py, gx, gy);
+    }
   }
   const int64_t o = (int64_t)l * a.cap * K + s;
   a.I0[o] = I0;
@@ -250,11 +299,11 @@ hipError_t launch_backproject_batch(const BackprojectArgs* d_args, int n_maps, i
 // J_k = gx_k au + gy_k av the point's contribution is
 //   H_i = m00 au^T au + m01 (au^T av + av^T au) + m11 av^T av,  b_i = -(v0 au + v1 av)
 // where m = sum_k w_k g_k^T g_k and v = sum_k w_k g_k r_k: five FMAs per sample
-// and the 21-term product once per point.  `img` is the current level, in LDS
-// or global memory.
-template <int KT, bool COST_ONLY>
+// and the 21-term product once per point.  `img` is the current level (uint8
+// or float pixels), in LDS or global memory.
+template <int KT, bool COST_ONLY, class PIX>
 __device__ __forceinline__ void accumulate(const TrackArgs& a, const Pattern& pat, const LevelGeom& g,
-                                           const uint8_t* __restrict__ img, int l, const float* T,
+                                           const PIX* __restrict__ img, int l, const float* T,
                                            float (&acc)[32]) {
   const int K = KT ? KT : pat.K;
   const int64_t lo = (int64_t)l * a.ref.cap;
@@ -369,7 +418,8 @@ __device__ __forceinline__ void stage_level(const uint8_t* __restrict__ src, uin
 // barriers, the 32 sums are reduced in a fixed order (bitwise reproducible),
 // and thread 0 solves and updates.  Levels of at most `lds_bytes` are staged
 // in LDS once per level and reused by all iterations of that level.
-template <int KT, bool CACHED>
+// PIX = float: the current frame's floating-point Gaussian pyramid (a.curf).
+template <int KT, bool CACHED, class PIX = uint8_t>
 __global__ __launch_bounds__(kTrackThreads) void track_kernel(TrackArgs a0, const TrackArgs* __restrict__ batch,
                                                               int lds_bytes) {
   extern __shared__ uint8_t dyn_lds[];
@@ -394,12 +444,16 @@ __global__ __launch_bounds__(kTrackThreads) void track_kernel(TrackArgs a0, cons
   int status = 0, iterations = 0;  // authoritative in thread 0
   int64_t samples = 0;
   bool stop = false;  // uniform across the workgroup
+  constexpr bool FLOAT_PYR = std::is_same<PIX, float>::value;
+  static_assert(!(FLOAT_PYR && CACHED), "the register-cached path reads uint8 levels");
+  const PIX* cur = FLOAT_PYR ? reinterpret_cast<const PIX*>(a.curf) : reinterpret_cast<const PIX*>(a.cur);
+  const PIX* lds_img = reinterpret_cast<const PIX*>(dyn_lds);
   for (int l = a.levels - 1; l >= 0 && !stop; --l) {
     const LevelGeom g = a.lv[l];
-    const int bytes = g.W * g.H;
+    const int bytes = g.W * g.H * (int)sizeof(PIX);
     const bool in_lds = bytes <= lds_bytes;
     if (in_lds) {
-      stage_level(a.cur + g.off, dyn_lds, bytes);
+      stage_level(reinterpret_cast<const uint8_t*>(cur + g.off), dyn_lds, bytes);
       __syncthreads();
     }
     PointRegs pr[CACHED ? kCachedPPT : 1];
@@ -419,9 +473,9 @@ __global__ __launch_bounds__(kTrackThreads) void track_kernel(TrackArgs a0, cons
           accumulate_cached<false>(a, pregs, g, a.cur + g.off, T, pr, acc);
       } else {
         if (in_lds)
-          accumulate<KT, false>(a, a.pat, g, dyn_lds, l, T, acc);
+          accumulate<KT, false>(a, a.pat, g, lds_img, l, T, acc);
         else
-          accumulate<KT, false>(a, a.pat, g, a.cur + g.off, l, T, acc);
+          accumulate<KT, false>(a, a.pat, g, cur + g.off, l, T, acc);
       }
       block_reduce32(acc, sh_red, sh_tot);
       if (threadIdx.x == 0) {
@@ -475,7 +529,7 @@ __global__ __launch_bounds__(kTrackThreads) void track_kernel(TrackArgs a0, cons
 #pragma unroll
     for (int j = 0; j < 12; ++j) T[j] = sh_T[j];
     const LevelGeom g = a.lv[0];
-    accumulate<KT, true>(a, a.pat, g, a.cur + g.off, 0, T, acc);
+    accumulate<KT, true>(a, a.pat, g, cur + g.off, 0, T, acc);
     block_reduce32(acc, sh_red, sh_tot);
   }
   if (threadIdx.x == 0) {
@@ -502,7 +556,10 @@ __global__ __launch_bounds__(kTrackThreads) void normal_eq_kernel(TrackArgs a) {
 #pragma unroll
   for (int j = 0; j < 32; ++j) acc[j] = 0.f;
   const LevelGeom g = a.lv[a.level];
-  accumulate<KT, false>(a, a.pat, g, a.cur + g.off, a.level, a.T_init, acc);
+  if (a.curf)
+    accumulate<KT, false>(a, a.pat, g, a.curf + g.off, a.level, a.T_init, acc);
+  else
+    accumulate<KT, false>(a, a.pat, g, a.cur + g.off, a.level, a.T_init, acc);
   block_reduce32(acc, sh_red, sh_tot);
   if (threadIdx.x < 32) a.totals[threadIdx.x] = sh_tot[threadIdx.x];
 }
@@ -510,31 +567,32 @@ __global__ __launch_bounds__(kTrackThreads) void normal_eq_kernel(TrackArgs a) {
 // Largest level (bytes) that a track workgroup stages in LDS.
 constexpr int kLdsImageBudget = 96 * 1024;
 
-int track_lds_bytes(const LevelGeom* lv, int levels) {
+int track_lds_bytes(const LevelGeom* lv, int levels, int pixel_bytes) {
   int best = 0;
   for (int l = 0; l < levels; ++l) {
-    const int b = lv[l].W * lv[l].H;
+    const int b = lv[l].W * lv[l].H * pixel_bytes;
     if (b <= kLdsImageBudget && b > best) best = b;
   }
   return best;
 }
 
-template <int KT, bool CACHED>
+template <int KT, bool CACHED, class PIX = uint8_t>
 static hipError_t launch_track_k(const TrackArgs& a, const TrackArgs* batch, int n_frames, int lds, hipStream_t s) {
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&track_kernel<KT, CACHED>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&track_kernel<KT, CACHED, PIX>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, kLdsImageBudget);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL((track_kernel<KT, CACHED>), dim3(n_frames), dim3(kTrackThreads), lds, s, a, batch, lds);
+  hipLaunchKernelGGL((track_kernel<KT, CACHED, PIX>), dim3(n_frames), dim3(kTrackThreads), lds, s, a, batch, lds);
   return hipGetLastError();
 }
 
 // max_points: the largest map of any frame in the launch (selects the register-cached path)
 static hipError_t dispatch_track(const TrackArgs& a, const TrackArgs* batch, int n_frames, int lds, int max_points,
                                  hipStream_t s) {
+  if (a.curf) return launch_track_k<0, false, float>(a, batch, n_frames, lds, s);  // Gaussian float pyramid
   if (a.pat.K == 8 && max_points <= kCachedPPT * kTrackThreads)
     return launch_track_k<8, true>(a, batch, n_frames, lds, s);
   if (a.pat.K == 8) return launch_track_k<8, false>(a, batch, n_frames, lds, s);
@@ -542,7 +600,7 @@ static hipError_t dispatch_track(const TrackArgs& a, const TrackArgs* batch, int
 }
 
 hipError_t launch_track(const TrackArgs& a, hipStream_t s) {
-  return dispatch_track(a, nullptr, 1, track_lds_bytes(a.lv, a.levels), a.ref.n, s);
+  return dispatch_track(a, nullptr, 1, track_lds_bytes(a.lv, a.levels, a.curf ? 4 : 1), a.ref.n, s);
 }
 
 hipError_t launch_track_batch(const TrackArgs& any, const TrackArgs* batch, int n_frames, int lds, int max_points,
