@@ -246,6 +246,7 @@ class Reference:
         self._lib = lib
         self.cam = make_camera(cam) if not isinstance(cam, Camera) else cam
         self.params = params
+        self.T_rw = np.array(T_rw, np.float64)
         self.n = int(len(points))
         img, ip = _u8(ref_img)
         pts = np.ascontiguousarray(points, dtype=np.float32).reshape(-1, 3)

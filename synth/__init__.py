@@ -288,6 +288,32 @@ def sequence_frames(seed: int = 2607, cam: Camera = CAM_752, n_frames: int = 200
         yield k, img, depth, T
 
 
+def tween_frames(seed: int = 2607, cam: Camera = CAM_752, n_frames: int = 200, noise_sigma: float = 2.0,
+                 p_jump: float = 0.04, jump=(15, 40), p_flicker: float = 0.05, gain=(1.15, 1.35)):
+    """A sequence for the tween-window schedule: the sequence trajectory sampled
+    at 200 Hz, except that with probability p_jump a frame skips ahead by a
+    seeded 15-40 samples (dropped frames: a large, unpredicted motion), and with
+    probability p_flicker a frame's intensities are scaled by a seeded gain
+    (exposure flicker, which the photometric model does not absorb).  Every frame
+    comes with its depth.  Yields (k, img, depth, T_cw_gt, events)."""
+    rng = np.random.default_rng([seed, 31])
+    traj = Trajectory(seed)
+    scene = Scene(seed)
+    t = 0
+    for k in range(n_frames):
+        step = 0
+        if k > 0:
+            step = int(rng.integers(jump[0], jump[1] + 1)) if rng.random() < p_jump else 1
+            t += step
+        g = float(rng.uniform(*gain)) if (k > 0 and rng.random() < p_flicker) else 1.0
+        T = traj.T_cw(t)
+        noise = pixel_noise(seed, t, cam, noise_sigma) if noise_sigma > 0 else None
+        img, depth = scene.render(cam, T, noise)
+        if g != 1.0:
+            img = np.clip(np.rint(img.astype(np.float64) * g), 0, 255).astype(np.uint8)
+        yield k, img, depth, T, dict(step=step, gain=g)
+
+
 def stream_spec(s: int):
     """Per-stream draw of the batched workload: camera and map size for stream s."""
     rng = np.random.default_rng(1000 + s)
