@@ -17,7 +17,8 @@ Further legs in the same line: batched streams (64 sequences of the headline
 shape; the mixed-resolution 64-stream batch against the same tracks through
 plain contexts), the mixed-precision variant (headline workload and a
 1280x720 / 16k-point stress case), the fixed-H mode (the paper's constant-H
-track on the headline workload), the learned initialiser against the
+track on the headline workload), the paper's per-point shape (Gaussian FP32
+pyramid, 6 levels, 7x7 patches), the learned initialiser against the
 constant-velocity prior, and the FP64 oracle on the host (cpu_baseline), which
 also tracks the first timed window of each leg from the same starts to give
 the per-frame pose differences between the GPU path and the oracle.
@@ -380,6 +381,63 @@ def bench_fixed_h(dpt, synth, wins, dev, steps):
     return out, st
 
 
+def bench_paper_shape(dpt, synth, wins, dev, steps):
+    """The paper's per-point shape on the headline sequence: the floating-point
+    Gaussian pyramid, 6 levels, 7x7 patches (49 samples per point), 2000 points.
+    One-workgroup track; each frame is waited for, its start being the
+    constant-velocity prediction from the two previous estimates (host)."""
+    import torch
+
+    prm = dpt.make_params(levels=6, max_iters=10, huber_k=9.0, step_eps=1e-5, gauss=True,
+                          pattern=synth.square_pattern(7))
+    trk = dpt.Tracker(CAM, prm, max_points=N_POINTS)
+    n = len(wins)
+    stats = new_stats()
+
+    def window(w, keep):
+        win = wins[w % n]
+        dev_imgs, dev_depth = dev[w % n]
+        trk.build_pyramid(dpt.SLOT_REF, dev_imgs[0])
+        trk.set_reference_from_depth(N_POINTS, dev_depth, win["gts"][0])
+        prev2, prev1 = win["T_prev"], win["gts"][0]
+        for j in range(1, WINDOW):
+            trk.build_pyramid(dpt.SLOT_CUR, dev_imgs[j])
+            T0 = cv_init(prev2, prev1)
+            r = trk.track(T0)
+            prev2, prev1 = prev1, r["T_cw"]
+            if keep:
+                for k, v in (("samples", r["samples"]), ("iters", r["iterations"]), ("status", r["status"]),
+                             ("T", r["T_cw"]), ("init", T0), ("gt", win["gts"][j])):
+                    stats[k].append(v)
+
+    window(0, False)
+    trk.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s_ in range(steps):
+        window(1 + s_, True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = trk.profile()
+    trk.close()
+    track_ms = prof["track_ms"] / prof["n_track"]
+    samp = float(np.mean(stats["samples"]))
+    # per sample: 12 B of template and gradient, x0 shared by 49 samples, four FP32 taps
+    bps = 12.0 + 12.0 / 49 + 16.0
+    achieved = samp * bps / (track_ms * 1e-3) / 1e9
+    out = {"workload": "the headline sequence at the paper's shape: FP32 Gaussian pyramid, 6 levels, 7x7 patches, "
+                       "2000 points, one-workgroup track, one frame at a time",
+           "frames_per_s": round(steps * (WINDOW - 1) / el, 2), "track_launch_ms": round(track_ms, 5),
+           "iterations_per_frame": round(float(np.mean(stats["iters"])), 3),
+           "samples_per_frame": round(samp, 1),
+           "status_counts": {str(k): int(v) for k, v in zip(*np.unique(stats["status"], return_counts=True))},
+           "pose_error_vs_gt": err_summary([pose_error(T, G) for T, G in zip(stats["T"], stats["gt"])]),
+           "roofline": {"kernel": "track_kernel<0, false, float>", "bound": "hbm", "unit": "GB/s",
+                        "peak": HBM_PEAK_GBS, "bytes_per_sample": round(bps, 3), "achieved": round(achieved, 3),
+                        "frac": round(achieved / HBM_PEAK_GBS, 6)}}
+    return out, stats
+
+
 def bench_stress(dpt, synth):
     """1280x720, 16000 points, 4 levels: one keyframe window of the sequence,
     tracked in FP32 and in mixed precision."""
@@ -446,8 +504,8 @@ def cpu_baseline(wins, seconds: float, comparisons):
            "sample": f"{n} keyframe windows ({(WINDOW - 1) * n} tracked frames) of the headline sequence in "
                      f"{el:.1f} s, FP64 C oracle (gcc -O2) on one host thread"}
     diffs = {}
-    for name, (frames, starts, poses, cam, wset, npts, levels, *mode) in comparisons.items():
-        p = oracle.make_params(levels=levels, fixed_h=bool(mode and mode[0] == "fixed_h"))
+    for name, (frames, starts, poses, cam, wset, npts, levels, *extra) in comparisons.items():
+        p = oracle.make_params(levels=levels, **(extra[0] if extra else {}))
         refs, errs = {}, []
         for (w, j), T0, Tg in zip(frames, starts, poses):
             if w not in refs:
@@ -533,8 +591,8 @@ def main():
     ap.add_argument("--chunk", type=int, default=256)
     ap.add_argument("--batch-streams", type=int, default=64)
     ap.add_argument("--only-headline", action="store_true", help="skip the batched, precision, fixed-H and initialiser legs")
-    ap.add_argument("--legs", default="mixed,fixed,batched,init",
-                    help="legs after the headline: any of mixed, fixed, batched, init (comma separated)")
+    ap.add_argument("--legs", default="mixed,fixed,paper,batched,init",
+                    help="legs after the headline: any of mixed, fixed, paper, batched, init (comma separated)")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="write the track kernel's HBM traffic per launch from rocprofv3 --pmc output and exit")
     args = ap.parse_args()
@@ -632,9 +690,16 @@ def main():
     if "fixed" in legs:
         fh, st_f = bench_fixed_h(dpt, synth, wins, dev, max(4, args.steps // 2))
         comparisons["headline_fixed_h"] = ([(1 % n_render, j) for j in range(1, WINDOW)], st_f["init"][:nc],
-                                           st_f["T"][:nc], CAM, wins, N_POINTS, LEVELS, "fixed_h")
+                                           st_f["T"][:nc], CAM, wins, N_POINTS, LEVELS, {"fixed_h": True})
         out["fixed_h"] = fh
         print("# fixed-H leg done", file=sys.stderr, flush=True)
+    if "paper" in legs:
+        ps, st_p = bench_paper_shape(dpt, synth, wins, dev, max(2, args.steps // 10))
+        comparisons["paper_shape"] = ([(1 % n_render, j) for j in range(1, WINDOW)], st_p["init"][:nc],
+                                      st_p["T"][:nc], CAM, wins, N_POINTS, 6,
+                                      {"gauss": True, "pattern": synth.square_pattern(7)})
+        out["paper_shape"] = ps
+        print("# paper-shape leg done", file=sys.stderr, flush=True)
     if "batched" in legs:
         out["batched"] = {
             "sequences": bench_batched_sequences(dpt, synth, args.batch_streams, max(2, args.steps // 4), 1),

@@ -202,6 +202,67 @@ int dpt_synchronize(dpt_ctx* ctx);
  * older first), ordered on the stream with the tracks.  Initially identity. */
 int dpt_set_pose_history(dpt_ctx* ctx, const double T_older[16], const double T_newer[16]);
 
+/* ------------------------------------------------------------------ tween-window schedule
+ * The schedule of Sec. III and Sec. IV-D: direct tracking handles the tween
+ * frames between references that the indirect pipeline provides, and hands a
+ * frame back to it when
+ *   - the track fails (status TOO_FEW_POINTS, NOT_PD or a timeout; a pose that
+ *     reached the iteration cap counts as valid),
+ *   - its robust error (final_cost, the mean Huber cost) exceeds max_cost,
+ *   - the camera centre moved more than max_baseline metres from the
+ *     reference's (max_baseline <= 0: no baseline test), or
+ *   - max_direct frames were already tracked directly against this reference
+ *     (then no direct attempt is made).
+ * The paper names a switching and a failure threshold on the error; here they
+ * are one value, max_cost.  The indirect side (ORB-SLAM2 in the paper) is the
+ * caller: after any decision other than DPT_TWEEN_DIRECT it gives the frame's
+ * pose and depth to dpt_tween_anchor, which makes that frame the new reference
+ * (selection, back-projection, IC precompute on the device). */
+typedef struct {
+  float max_cost;      /* accept a direct frame only if final_cost <= max_cost */
+  float max_baseline;  /* metres; <= 0: unlimited */
+  int32_t max_direct;  /* direct frames per reference, >= 0 */
+  int32_t n_points;    /* map points selected at each anchor, 1..max_points */
+  int32_t margin;      /* selection margin at each anchor (pixels) */
+  int32_t pad;
+} dpt_tween_policy;
+
+enum {
+  DPT_TWEEN_DIRECT = 0,           /* the direct pose is accepted */
+  DPT_TWEEN_INDIRECT_FAILED = 1,  /* the track failed */
+  DPT_TWEEN_INDIRECT_COST = 2,    /* final_cost > max_cost */
+  DPT_TWEEN_INDIRECT_BASELINE = 3,
+  DPT_TWEEN_INDIRECT_MAX_FRAMES = 4
+};
+
+typedef struct {
+  int32_t decision;          /* DPT_TWEEN_* */
+  int32_t direct_since_ref;  /* direct frames accepted against the current reference, this one included */
+  int32_t tracked;           /* 1 if a direct track was run (its result is in `track`) */
+  int32_t pad;
+  double baseline;           /* camera-centre distance of the direct estimate to the reference (m) */
+  dpt_result track;
+} dpt_tween_result;
+
+/* Set the schedule's policy (copied).  DPT_E_ARG on invalid values. */
+int dpt_tween_set_policy(dpt_ctx* ctx, const dpt_tween_policy* policy);
+
+/* Reference from an indirect frame: its image (host or device, `pitch` bytes per
+ * row), level-0 depth (as dpt_set_reference_from_depth) and pose T_cw from the
+ * indirect pipeline.  Builds the REF pyramid, selects policy.n_points points,
+ * back-projects and precomputes, sets the constant-velocity history to (the
+ * previous accepted or anchored pose, T_cw) and restarts the direct count.
+ * The first anchor of a context uses T_cw as both history entries. */
+int dpt_tween_anchor(dpt_ctx* ctx, const uint8_t* img, int64_t pitch, int32_t img_on_device, const float* depth,
+                     int64_t depth_pitch, int32_t depth_on_device, const double T_cw[16]);
+
+/* One tween frame: builds the CUR pyramid, tracks from the constant-velocity
+ * prediction of the last two accepted or anchored poses and applies the policy.
+ * Waits for the result.  After a decision other than DPT_TWEEN_DIRECT the
+ * context needs dpt_tween_anchor before the next tween frame (DPT_E_STATE
+ * otherwise, and before the first anchor). */
+int dpt_tween_frame(dpt_ctx* ctx, const uint8_t* img, int64_t pitch, int32_t img_on_device, dpt_tween_result* out);
+
 /* Test hook: copies of level `level`'s IC cache.  Any pointer may be NULL.
  * valid: n bytes; I0, gx, gy: n*K floats (sample i*K+k); x0: n*3 floats. */
 int dpt_get_reference_cache(dpt_ctx* ctx, int32_t level, uint8_t* valid, float* I0, float* gx, float* gy, float* x0);

@@ -57,6 +57,18 @@ class Result(ctypes.Structure):
                     n_valid_points=self.n_valid_points, status=self.status, samples=self.samples)
 
 
+class TweenPolicy(ctypes.Structure):
+    _fields_ = [("max_cost", ctypes.c_float), ("max_baseline", ctypes.c_float), ("max_direct", ctypes.c_int32),
+                ("n_points", ctypes.c_int32), ("margin", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class TweenResult(ctypes.Structure):
+    _fields_ = [("decision", ctypes.c_int32), ("direct_since_ref", ctypes.c_int32), ("tracked", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("baseline", ctypes.c_double), ("track", Result)]
+
+
+TWEEN_DIRECT, TWEEN_FAILED, TWEEN_COST, TWEEN_BASELINE, TWEEN_MAX_FRAMES = 0, 1, 2, 3, 4
+
 # NumPy view of dpt_result (zero-copy reads of result arrays)
 RESULT_DTYPE = np.dtype({
     "names": ["T_cw", "final_cost", "iterations", "iters_per_level", "n_valid_points", "status", "samples"],
@@ -78,6 +90,9 @@ SIGNATURES = {
     "dpt_build_pyramid": (ctypes.c_int, [_vp, _i32, _vp, _i64, _i32]),
     "dpt_get_pyramid": (ctypes.c_int, [_vp, _i32, _i32, _vp]),
     "dpt_get_pyramid_f32": (ctypes.c_int, [_vp, _i32, _i32, _vp]),
+    "dpt_tween_set_policy": (ctypes.c_int, [_vp, ctypes.POINTER(TweenPolicy)]),
+    "dpt_tween_anchor": (ctypes.c_int, [_vp, _vp, _i64, _i32, _vp, _i64, _i32, ctypes.POINTER(ctypes.c_double)]),
+    "dpt_tween_frame": (ctypes.c_int, [_vp, _vp, _i64, _i32, ctypes.POINTER(TweenResult)]),
     "dpt_select_points": (ctypes.c_int, [_vp, _i32, _i32, _vp, ctypes.POINTER(_i32)]),
     "dpt_set_reference_points": (ctypes.c_int, [_vp, _vp, _i32, ctypes.POINTER(ctypes.c_double), _i32]),
     "dpt_set_reference_from_depth": (ctypes.c_int, [_vp, _i32, _i32, _vp, _i64, _i32,
@@ -270,6 +285,29 @@ class Tracker:
         r = Result()
         _check(self._lib.dpt_track_frame(self._h, _mat(T_cw_init), ctypes.byref(r)))
         return r.as_dict()
+
+    # tween-window schedule (Sec. III, Sec. IV-D)
+    def tween_set_policy(self, max_cost: float, max_direct: int, n_points: int, max_baseline: float = 0.0,
+                         margin: int = 8):
+        p = TweenPolicy(max_cost, max_baseline, max_direct, n_points, margin, 0)
+        _check(self._lib.dpt_tween_set_policy(self._h, ctypes.byref(p)))
+        self.n_points = n_points
+
+    def tween_anchor(self, img, depth, T_cw):
+        """The indirect pipeline's frame: image, level-0 depth and pose become the reference."""
+        pi, di, k1 = _ptr(img)
+        if isinstance(depth, np.ndarray):
+            depth = np.ascontiguousarray(depth, dtype=np.float32)
+        pd, dd, k2 = _ptr(depth)
+        _check(self._lib.dpt_tween_anchor(self._h, pi, self.cam.width, di, pd, self.cam.width, dd, _mat(T_cw)))
+
+    def tween_frame(self, img) -> dict:
+        """Direct attempt on a tween frame and the schedule's decision (TWEEN_*)."""
+        p, dev, keep = _ptr(img)
+        r = TweenResult()
+        _check(self._lib.dpt_tween_frame(self._h, p, self.cam.width, dev, ctypes.byref(r)))
+        return dict(decision=r.decision, direct_since_ref=r.direct_since_ref, tracked=bool(r.tracked),
+                    baseline=r.baseline, track=r.track.as_dict() if r.tracked else None)
 
     def track_enqueue(self, T_cw_init=None):
         """Enqueue a track without waiting: from T_cw_init, or (None) from the

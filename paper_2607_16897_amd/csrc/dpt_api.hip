@@ -278,6 +278,11 @@ struct dpt_ctx {
   double* d_hist = nullptr;  // pose history: the last two T_cw, 2 x 3x4 FP64 (device)
   std::vector<std::pair<int, dpt_result*>> pending;  // tracks in flight: (ring slot, caller's result)
   int slot_next = 0;
+  // tween-window schedule (host state)
+  dpt_tween_policy tween{};
+  bool tween_policy = false, tween_anchored = false, tween_needs_anchor = false;
+  int32_t tween_direct = 0;
+  double tween_hist[2][16];  // the last two accepted or anchored T_cw, older first
 
   ~dpt_ctx() {
     prof_pyr.destroy();
@@ -631,6 +636,94 @@ int dpt_set_reference_from_depth(dpt_ctx* c, int32_t n, int32_t margin, const fl
   b.P = c->pts;
   HIP_TRY(launch_backproject(b, c->stream));
   return precompute_reference(c, c->pts, n, T_rw);
+}
+
+int dpt_tween_set_policy(dpt_ctx* c, const dpt_tween_policy* p) {
+  g_err.clear();
+  if (!c || !p) return fail(DPT_E_ARG, "NULL argument");
+  if (!(p->max_cost >= 0.0f) || !std::isfinite(p->max_baseline) || p->max_direct < 0)
+    return fail(DPT_E_ARG, "invalid tween thresholds");
+  if (p->n_points < 1 || p->n_points > c->cap) return fail(DPT_E_ARG, "n_points %d outside [1, %d]", p->n_points, c->cap);
+  if (p->margin < 1 || 2 * p->margin >= c->cam.width || 2 * p->margin >= c->cam.height)
+    return fail(DPT_E_ARG, "margin %d", p->margin);
+  c->tween = *p;
+  c->tween_policy = true;
+  return DPT_OK;
+}
+
+int dpt_tween_anchor(dpt_ctx* c, const uint8_t* img, int64_t pitch, int32_t img_on_device, const float* depth,
+                     int64_t depth_pitch, int32_t depth_on_device, const double T_cw[16]) {
+  g_err.clear();
+  if (!c || !img || !depth || !T_cw) return fail(DPT_E_ARG, "NULL argument");
+  if (!c->tween_policy) return fail(DPT_E_STATE, "no tween policy");
+  if (!finite16(T_cw)) return fail(DPT_E_ARG, "T_cw not finite");
+  int e;
+  if (!c->pending.empty() && (e = dpt_synchronize(c)) != DPT_OK) return e;
+  if ((e = dpt_build_pyramid(c, DPT_SLOT_REF, img, pitch, img_on_device)) != DPT_OK) return e;
+  if ((e = dpt_set_reference_from_depth(c, c->tween.n_points, c->tween.margin, depth, depth_pitch, depth_on_device,
+                                        T_cw)) != DPT_OK)
+    return e;
+  double T[16];
+  std::memcpy(T, T_cw, sizeof T);
+  orthonormalize34(T);
+  std::memcpy(c->tween_hist[0], c->tween_anchored ? c->tween_hist[1] : T, sizeof T);
+  std::memcpy(c->tween_hist[1], T, sizeof T);
+  if ((e = dpt_set_pose_history(c, c->tween_hist[0], c->tween_hist[1])) != DPT_OK) return e;
+  c->tween_anchored = true;
+  c->tween_needs_anchor = false;
+  c->tween_direct = 0;
+  return DPT_OK;
+}
+
+int dpt_tween_frame(dpt_ctx* c, const uint8_t* img, int64_t pitch, int32_t img_on_device, dpt_tween_result* out) {
+  g_err.clear();
+  if (!c || !img || !out) return fail(DPT_E_ARG, "NULL argument");
+  if (!c->tween_policy || !c->tween_anchored) return fail(DPT_E_STATE, "the tween schedule has no reference yet");
+  if (c->tween_needs_anchor) return fail(DPT_E_STATE, "the last tween frame went to the indirect pipeline: anchor first");
+  std::memset(out, 0, sizeof *out);
+  if (c->tween_direct >= c->tween.max_direct) {
+    out->decision = DPT_TWEEN_INDIRECT_MAX_FRAMES;
+    out->direct_since_ref = c->tween_direct;
+    c->tween_needs_anchor = true;
+    return DPT_OK;
+  }
+  int e;
+  if ((e = dpt_build_pyramid(c, DPT_SLOT_CUR, img, pitch, img_on_device)) != DPT_OK) return e;
+  // constant velocity: T1 T0^-1 T1 (rigid inverse), back on SO(3)
+  double inv0[16], m[16], start[16];
+  invert(c->tween_hist[0], inv0);
+  compose(c->tween_hist[1], inv0, m);
+  compose(m, c->tween_hist[1], start);
+  orthonormalize34(start);
+  if ((e = dpt_track_frame(c, start, &out->track)) != DPT_OK) return e;
+  out->tracked = 1;
+  const double* T = out->track.T_cw;
+  // camera centres -R^T t of the estimate and of the reference
+  double ce[3], cr[3];
+  for (int j = 0; j < 3; ++j) {
+    ce[j] = -(T[j] * T[3] + T[4 + j] * T[7] + T[8 + j] * T[11]);
+    cr[j] = -(c->T_rw[j] * c->T_rw[3] + c->T_rw[4 + j] * c->T_rw[7] + c->T_rw[8 + j] * c->T_rw[11]);
+  }
+  out->baseline = std::sqrt((ce[0] - cr[0]) * (ce[0] - cr[0]) + (ce[1] - cr[1]) * (ce[1] - cr[1]) +
+                            (ce[2] - cr[2]) * (ce[2] - cr[2]));
+  const int st = out->track.status;
+  if (st != DPT_TRACK_OK && st != DPT_TRACK_MAX_ITERS)
+    out->decision = DPT_TWEEN_INDIRECT_FAILED;
+  else if (!(out->track.final_cost <= (double)c->tween.max_cost))
+    out->decision = DPT_TWEEN_INDIRECT_COST;
+  else if (c->tween.max_baseline > 0.0f && out->baseline > (double)c->tween.max_baseline)
+    out->decision = DPT_TWEEN_INDIRECT_BASELINE;
+  else
+    out->decision = DPT_TWEEN_DIRECT;
+  if (out->decision == DPT_TWEEN_DIRECT) {
+    ++c->tween_direct;
+    std::memcpy(c->tween_hist[0], c->tween_hist[1], sizeof c->tween_hist[0]);
+    std::memcpy(c->tween_hist[1], T, sizeof c->tween_hist[1]);
+  } else {
+    c->tween_needs_anchor = true;
+  }
+  out->direct_since_ref = c->tween_direct;
+  return DPT_OK;
 }
 
 }  // extern "C"
