@@ -18,7 +18,8 @@ shape; the mixed-resolution 64-stream batch against the same tracks through
 plain contexts), the mixed-precision variant (headline workload and a
 1280x720 / 16k-point stress case), the fixed-H mode (the paper's constant-H
 track on the headline workload), the paper's per-point shape (Gaussian FP32
-pyramid, 6 levels, 7x7 patches), the learned initialiser against the
+pyramid, 6 levels, 7x7 patches), the tween-window schedule (share of direct
+frames, camera-centre error), the learned initialiser against the
 constant-velocity prior, and the FP64 oracle on the host (cpu_baseline), which
 also tracks the first timed window of each leg from the same starts to give
 the per-frame pose differences between the GPU path and the oracle.
@@ -375,7 +376,7 @@ def bench_fixed_h(dpt, synth, wins, dev, steps):
            "track_us_per_iteration": round(track_ms * 1e3 / (iters + 1), 3),
            "status_counts": {str(k): int(v) for k, v in zip(*np.unique(st["status"], return_counts=True))},
            "pose_error_vs_gt": err_summary([pose_error(T, G) for T, G in zip(st["T"], st["gt"])]),
-           "roofline": {"kernel": "coop_track_kernel<256, false, true>", "bound": "hbm", "unit": "GB/s",
+           "roofline": {"kernel": "coop_track_kernel<256, false, true, false, unsigned char>", "bound": "hbm", "unit": "GB/s",
                         "peak": HBM_PEAK_GBS, "achieved": round(achieved, 3),
                         "frac": round(achieved / HBM_PEAK_GBS, 6)}}
     return out, st
@@ -383,59 +384,83 @@ def bench_fixed_h(dpt, synth, wins, dev, steps):
 
 def bench_paper_shape(dpt, synth, wins, dev, steps):
     """The paper's per-point shape on the headline sequence: the floating-point
-    Gaussian pyramid, 6 levels, 7x7 patches (49 samples per point), 2000 points.
-    One-workgroup track; each frame is waited for, its start being the
-    constant-velocity prediction from the two previous estimates (host)."""
-    import torch
-
+    Gaussian pyramid, 6 levels, 7x7 patches (49 samples per point), 2000 points;
+    cooperative generic-pattern track (four lanes per point), windows enqueued
+    like the headline's."""
     prm = dpt.make_params(levels=6, max_iters=10, huber_k=9.0, step_eps=1e-5, gauss=True,
                           pattern=synth.square_pattern(7))
-    trk = dpt.Tracker(CAM, prm, max_points=N_POINTS)
-    n = len(wins)
-    stats = new_stats()
-
-    def window(w, keep):
-        win = wins[w % n]
-        dev_imgs, dev_depth = dev[w % n]
-        trk.build_pyramid(dpt.SLOT_REF, dev_imgs[0])
-        trk.set_reference_from_depth(N_POINTS, dev_depth, win["gts"][0])
-        prev2, prev1 = win["T_prev"], win["gts"][0]
-        for j in range(1, WINDOW):
-            trk.build_pyramid(dpt.SLOT_CUR, dev_imgs[j])
-            T0 = cv_init(prev2, prev1)
-            r = trk.track(T0)
-            prev2, prev1 = prev1, r["T_cw"]
-            if keep:
-                for k, v in (("samples", r["samples"]), ("iters", r["iterations"]), ("status", r["status"]),
-                             ("T", r["T_cw"]), ("init", T0), ("gt", win["gts"][j])):
-                    stats[k].append(v)
-
-    window(0, False)
-    trk.set_profiling(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s_ in range(steps):
-        window(1 + s_, True)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    prof = trk.profile()
-    trk.close()
+    el, st, prof = timed_plain(dpt, synth, wins, dev, steps, 1, prm, dpt.LAUNCH_AUTO, 256)
     track_ms = prof["track_ms"] / prof["n_track"]
-    samp = float(np.mean(stats["samples"]))
+    samp = float(np.mean(st["samples"]))
     # per sample: 12 B of template and gradient, x0 shared by 49 samples, four FP32 taps
     bps = 12.0 + 12.0 / 49 + 16.0
     achieved = samp * bps / (track_ms * 1e-3) / 1e9
     out = {"workload": "the headline sequence at the paper's shape: FP32 Gaussian pyramid, 6 levels, 7x7 patches, "
-                       "2000 points, one-workgroup track, one frame at a time",
+                       "2000 points",
            "frames_per_s": round(steps * (WINDOW - 1) / el, 2), "track_launch_ms": round(track_ms, 5),
-           "iterations_per_frame": round(float(np.mean(stats["iters"])), 3),
+           "iterations_per_frame": round(float(np.mean(st["iters"])), 3),
            "samples_per_frame": round(samp, 1),
-           "status_counts": {str(k): int(v) for k, v in zip(*np.unique(stats["status"], return_counts=True))},
-           "pose_error_vs_gt": err_summary([pose_error(T, G) for T, G in zip(stats["T"], stats["gt"])]),
-           "roofline": {"kernel": "track_kernel<0, false, float>", "bound": "hbm", "unit": "GB/s",
-                        "peak": HBM_PEAK_GBS, "bytes_per_sample": round(bps, 3), "achieved": round(achieved, 3),
-                        "frac": round(achieved / HBM_PEAK_GBS, 6)}}
-    return out, stats
+           "status_counts": {str(k): int(v) for k, v in zip(*np.unique(st["status"], return_counts=True))},
+           "pose_error_vs_gt": err_summary([pose_error(T, G) for T, G in zip(st["T"], st["gt"])]),
+           "roofline": {"kernel": "coop_track_kernel<256, false, false, true, float>", "bound": "hbm",
+                        "unit": "GB/s", "peak": HBM_PEAK_GBS, "bytes_per_sample": round(bps, 3),
+                        "achieved": round(achieved, 3), "frac": round(achieved / HBM_PEAK_GBS, 6)}}
+    return out, st
+
+
+TWEEN_POLICY = dict(max_cost=20.0, max_baseline=0.035, max_direct=12, n_points=N_POINTS, margin=8)
+
+
+def bench_tween(dpt, synth, n_frames: int):
+    """The tween-window schedule (Sec. III, Sec. IV-D) over a 752x480 sequence
+    with exposure flicker and dropped frames; the true pose and depth stand in
+    for the indirect pipeline whenever the schedule hands a frame back.  Frames
+    and depths are resident in device memory; the rate covers direct tracks and
+    re-anchoring (pyramid, selection, back-projection, precompute)."""
+    import torch
+
+    frames = [(im, d.astype(np.float32), T) for _, im, d, T, _ in
+              synth.tween_frames(n_frames=n_frames, jump=(40, 160), p_jump=0.05)]
+    dev = [(torch.from_numpy(im).cuda(), torch.from_numpy(d).cuda()) for im, d, _ in frames]
+    p = TWEEN_POLICY
+
+    def run():
+        # a fresh context: its first anchor seeds both history entries, as in the oracle's schedule
+        trk = dpt.Tracker(CAM, dpt.make_params(levels=LEVELS), max_points=N_POINTS)
+        trk.tween_set_policy(p["max_cost"], p["max_direct"], p["n_points"], max_baseline=p["max_baseline"],
+                             margin=p["margin"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        recs = []
+        trk.tween_anchor(dev[0][0], dev[0][1], frames[0][2])
+        recs.append(dict(decision=None, pose=frames[0][2]))
+        for k in range(1, len(frames)):
+            r = trk.tween_frame(dev[k][0])
+            if r["decision"] == dpt.TWEEN_DIRECT:
+                recs.append(dict(decision=0, pose=r["track"]["T_cw"]))
+            else:
+                trk.tween_anchor(dev[k][0], dev[k][1], frames[k][2])
+                recs.append(dict(decision=r["decision"], pose=frames[k][2]))
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        trk.close()
+        return recs, el
+
+    run()  # warm-up
+    recs, el = run()
+    dec = [r["decision"] for r in recs[1:]]
+    counts = {name: int(sum(d == v for d in dec)) for name, v in
+              (("direct", 0), ("failed", 1), ("cost", 2), ("baseline", 3), ("max_frames", 4))}
+    err = [pose_error(r["pose"], T)[1] for r, (_, _, T) in zip(recs, frames)]
+    centre = lambda T: -T[:3, :3].T @ T[:3, 3]
+    cerr = [float(np.linalg.norm(centre(np.asarray(r["pose"])) - centre(T))) for r, (_, _, T) in zip(recs, frames)]
+    out = {"workload": f"{n_frames}-frame 752x480 sequence with exposure flicker (p=0.05, gain 1.15-1.35) and "
+                       "dropped frames (p=0.05, jumps of 40-160 samples), 2000 points, 4 levels",
+           "policy": p, "frames_per_s": round((len(frames) - 1) / el, 2),
+           "direct_pct": round(100.0 * counts["direct"] / len(dec), 2), "decisions": counts,
+           "centre_error_rmse_m": round(float(np.sqrt(np.mean(np.square(cerr)))), 7),
+           "centre_error_max_m": round(float(np.max(cerr)), 7), "pose_translation_error_max_m": round(max(err), 7)}
+    return out, frames, dec
 
 
 def bench_stress(dpt, synth):
@@ -476,7 +501,7 @@ def bench_learned_init(dpt, n_streams: int, n_frames: int):
 
 
 # ---------------------------------------------------------------- CPU baseline (the oracle)
-def cpu_baseline(wins, seconds: float, comparisons):
+def cpu_baseline(wins, seconds: float, comparisons, tween_run=None):
     """The FP64 oracle on one host thread, on the headline windows until
     `seconds` elapse.  `comparisons` maps a leg name to (frames [(window, j)],
     starts, GPU poses, camera, windows, points, levels): the oracle tracks each
@@ -515,6 +540,17 @@ def cpu_baseline(wins, seconds: float, comparisons):
                                            synth.backproject(cam, win["depth"], idx, win["gts"][0]), win["gts"][0])
             errs.append(pose_error(Tg, refs[w].track(wset[w]["imgs"][j], T0)["T_cw"]))
         diffs[name] = dict(frames=len(errs), **err_summary(errs))
+    if tween_run is not None:  # the oracle's schedule on the same frames: decisions must agree
+        from oracle import tween
+
+        frames, gpu_dec = tween_run
+        recs = tween.run(frames, TWEEN_POLICY, tween.oracle_reference(CAM, oracle.make_params(levels=LEVELS),
+                                                                      TWEEN_POLICY))
+        s = tween.summary(recs, [f[2] for f in frames])
+        odec = [r["decision"] for r in recs[1:]]
+        diffs["tween_schedule"] = dict(frames=len(odec), same_decisions=int(sum(a == b for a, b in zip(odec, gpu_dec))),
+                                       oracle_direct_pct=round(s["direct_pct"], 2),
+                                       oracle_centre_error_rmse_m=round(s["ate_rmse_m"], 7))
     return out, diffs
 
 
@@ -591,8 +627,8 @@ def main():
     ap.add_argument("--chunk", type=int, default=256)
     ap.add_argument("--batch-streams", type=int, default=64)
     ap.add_argument("--only-headline", action="store_true", help="skip the batched, precision, fixed-H and initialiser legs")
-    ap.add_argument("--legs", default="mixed,fixed,paper,batched,init",
-                    help="legs after the headline: any of mixed, fixed, paper, batched, init (comma separated)")
+    ap.add_argument("--legs", default="mixed,fixed,paper,tween,batched,init",
+                    help="legs after the headline: any of mixed, fixed, paper, tween, batched, init (comma separated)")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="write the track kernel's HBM traffic per launch from rocprofv3 --pmc output and exit")
     args = ap.parse_args()
@@ -637,7 +673,7 @@ def main():
     samp_launch = float(np.mean(stats["samples"]))
     alg_bytes = samp_launch * BYTES_PER_SAMPLE_F32
     achieved = alg_bytes / (track_ms * 1e-3) / 1e9
-    kname = f"coop_track_kernel<{args.chunk}, false>"
+    kname = f"coop_track_kernel<{args.chunk}, false, false, false, unsigned char>"
     out = {
         "metric": METRIC,
         "value": round(tracked / elapsed, 2),
@@ -694,12 +730,17 @@ def main():
         out["fixed_h"] = fh
         print("# fixed-H leg done", file=sys.stderr, flush=True)
     if "paper" in legs:
-        ps, st_p = bench_paper_shape(dpt, synth, wins, dev, max(2, args.steps // 10))
+        ps, st_p = bench_paper_shape(dpt, synth, wins, dev, max(4, args.steps // 4))
         comparisons["paper_shape"] = ([(1 % n_render, j) for j in range(1, WINDOW)], st_p["init"][:nc],
                                       st_p["T"][:nc], CAM, wins, N_POINTS, 6,
                                       {"gauss": True, "pattern": synth.square_pattern(7)})
         out["paper_shape"] = ps
         print("# paper-shape leg done", file=sys.stderr, flush=True)
+    tween_run = None
+    if "tween" in legs:
+        out["tween"], tw_frames, tw_dec = bench_tween(dpt, synth, 200)
+        tween_run = (tw_frames, tw_dec)
+        print("# tween leg done", file=sys.stderr, flush=True)
     if "batched" in legs:
         out["batched"] = {
             "sequences": bench_batched_sequences(dpt, synth, args.batch_streams, max(2, args.steps // 4), 1),
@@ -710,7 +751,8 @@ def main():
         out["learned_init"] = bench_learned_init(dpt, args.batch_streams, 30)
         print("# initialiser leg done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"], out["pose_diff_vs_oracle"] = cpu_baseline(wins, args.cpu_seconds, comparisons)
+        out["cpu_baseline"], out["pose_diff_vs_oracle"] = cpu_baseline(wins, args.cpu_seconds, comparisons,
+                                                                        tween_run)
     print(json.dumps(out), flush=True)
 
 

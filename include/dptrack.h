@@ -69,8 +69,7 @@ enum { DPT_FLAG_FIXED_H = 1 };
  *                     2y+2, clamped to the level) and keeps every second sample,
  *                     so pixel centres and per-level intrinsics are those of the
  *                     box pyramid.  Point selection still reads the uint8 frame.
- *                     FP32 precision, one-workgroup launch (DPT_LAUNCH_COOP is
- *                     rejected). */
+ *                     FP32 precision only. */
 enum { DPT_FLAG_GAUSS_F32 = 2 };
 
 /* pyramid slots */
@@ -186,7 +185,7 @@ enum { DPT_INIT_GIVEN = 0, DPT_INIT_CONST_VELOCITY = 1 };
  * (DPT_INIT_CONST_VELOCITY, computed on the GPU in FP64; T_cw_init may be NULL).
  * The history holds the last two poses: dpt_set_pose_history sets it, and every
  * track on the cooperative path appends its result.  The constant-velocity
- * start needs that path (K = 8, launch mode AUTO or COOP; DPT_E_ARG
+ * start needs that path (launch mode AUTO or COOP; DPT_E_ARG
  * otherwise); on the one-workgroup path a DPT_INIT_GIVEN enqueue runs
  * synchronously.  *out is written by the next dpt_synchronize (or any call
  * that synchronises the context) and must stay valid until then.  At most 64
@@ -288,7 +287,10 @@ int dpt_get_fixed_hessian(dpt_ctx* ctx, int32_t level, double H36[36], int32_t* 
  *                         launches and the map fits, else one workgroup per frame
  *   DPT_LAUNCH_WORKGROUP  one 512-thread workgroup runs the whole frame
  *   DPT_LAUNCH_COOP       the map is split into chunks of `chunk` points (64, 128
- *                         or 256), one workgroup each, synchronised per iteration
+ *                         or 256), one workgroup each, synchronised per iteration.
+ *                         Patterns other than the 8-pixel one and the Gaussian
+ *                         float pyramid use chunks of 64 points, four threads per
+ *                         point, whatever `chunk` says
  * Results agree with each other to rounding (the summation order differs). */
 enum { DPT_LAUNCH_AUTO = 0, DPT_LAUNCH_WORKGROUP = 1, DPT_LAUNCH_COOP = 2 };
 int dpt_set_launch_config(dpt_ctx* ctx, int32_t mode, int32_t chunk);

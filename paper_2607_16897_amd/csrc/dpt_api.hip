@@ -730,28 +730,41 @@ int dpt_tween_frame(dpt_ctx* c, const uint8_t* img, int64_t pitch, int32_t img_o
 
 namespace {
 
+// Patterns other than the 8-pixel one, and the floating-point pyramid, run on
+// the generic cooperative variant (four lanes per point, fixed 256-thread chunks).
+bool generic_track(const dpt_params& p) { return p.n_pattern != 8 || (p.flags & DPT_FLAG_GAUSS_F32); }
+
 int coop_variant(const dpt_params& p) {
   if (p.precision == DPT_PREC_MIXED) return kCoopMixed;
-  return (p.flags & DPT_FLAG_FIXED_H) ? kCoopFixedH : kCoopFP32;
+  int v = (p.flags & DPT_FLAG_FIXED_H) ? kCoopFixedH : kCoopFP32;
+  if (generic_track(p)) v |= kCoopGeneric | ((p.flags & DPT_FLAG_GAUSS_F32) ? kCoopFloatPyr : 0);
+  return v;
+}
+
+// Threads and points per chunk of a cooperative launch.
+int coop_threads(const dpt_params& p, int chunk) { return generic_track(p) ? kGenericThreads : chunk; }
+int coop_ppc(const dpt_params& p, int chunk) {
+  return generic_track(p) ? kGenericThreads / kLanesPerPoint : chunk;
 }
 
 // Whether this frame runs on the cooperative chunked kernel.
 bool use_coop(dpt_ctx* c) {
   if (c->prm.precision == DPT_PREC_MIXED) return true;  // only the cooperative kernel has the mixed variant
-  if (c->prm.flags & DPT_FLAG_GAUSS_F32) return false;  // float levels: the one-workgroup kernel
-  if (c->launch_mode == DPT_LAUNCH_WORKGROUP || c->prm.n_pattern != 8) return false;
-  const int nch = c->n_points > 0 ? (c->n_points + c->chunk - 1) / c->chunk : 1;
-  return nch <= coop_max_blocks(c->chunk) / 8;  // the XCD-packed grid may hold up to 8x padding
+  if (c->launch_mode == DPT_LAUNCH_WORKGROUP) return false;
+  const int ppc = coop_ppc(c->prm, c->chunk);
+  const int nch = c->n_points > 0 ? (c->n_points + ppc - 1) / ppc : 1;
+  return nch <= coop_max_blocks(coop_threads(c->prm, c->chunk)) / 8;  // the XCD-packed grid may hold up to 8x padding
 }
 
 // The context's single-stream cooperative engine, built on first use and
 // refreshed when the map changed size.
 int ensure_engine(dpt_ctx* c) {
-  const int nch = c->n_points > 0 ? (c->n_points + c->chunk - 1) / c->chunk : 1;
-  if (8 * nch > coop_max_blocks(c->chunk))
-    return fail(DPT_E_ARG, "%d points exceed the cooperative capacity at chunk %d", c->n_points, c->chunk);
+  const int threads = coop_threads(c->prm, c->chunk), ppc = coop_ppc(c->prm, c->chunk);
+  const int nch = c->n_points > 0 ? (c->n_points + ppc - 1) / ppc : 1;
+  if (8 * nch > coop_max_blocks(threads))
+    return fail(DPT_E_ARG, "%d points exceed the cooperative capacity at %d points per chunk", c->n_points, ppc);
   if (!c->eng_ready) {
-    HIP_TRY(c->eng.init(1, &c->cap, c->chunk, true, c->stream));
+    HIP_TRY(c->eng.init(1, &c->cap, threads, ppc, true, c->stream));
     c->eng.variant = coop_variant(c->prm);
     c->eng_ready = true;
   }
@@ -887,7 +900,7 @@ int dpt_track_enqueue(dpt_ctx* c, int32_t init_mode, const double T_cw_init[16],
   if (e != DPT_OK) return e;
   if (!use_coop(c)) {
     if (init_mode == DPT_INIT_CONST_VELOCITY)
-      return fail(DPT_E_ARG, "a constant-velocity start needs the cooperative track (K = 8, launch mode AUTO or COOP)");
+      return fail(DPT_E_ARG, "a constant-velocity start needs the cooperative track (launch mode AUTO or COOP)");
     return dpt_track_frame(c, T_cw_init, out);
   }
   return enqueue_coop(c, init_mode == DPT_INIT_GIVEN ? kStartGiven : kStartConstVelocity, T_cw_init, out);
@@ -912,9 +925,6 @@ int dpt_set_launch_config(dpt_ctx* c, int32_t mode, int32_t chunk) {
   if (!c) return fail(DPT_E_ARG, "NULL context");
   if (mode < DPT_LAUNCH_AUTO || mode > DPT_LAUNCH_COOP) return fail(DPT_E_ARG, "mode %d", mode);
   if (chunk != 64 && chunk != 128 && chunk != 256) return fail(DPT_E_ARG, "chunk %d not in {64, 128, 256}", chunk);
-  if (mode == DPT_LAUNCH_COOP && c->prm.n_pattern != 8) return fail(DPT_E_ARG, "cooperative track needs K = 8");
-  if (mode == DPT_LAUNCH_COOP && (c->prm.flags & DPT_FLAG_GAUSS_F32))
-    return fail(DPT_E_ARG, "the Gaussian float pyramid runs on the one-workgroup launch");
   if (mode == DPT_LAUNCH_WORKGROUP && c->prm.precision == DPT_PREC_MIXED)
     return fail(DPT_E_ARG, "mixed precision runs on the cooperative launch only");
   if (chunk != c->chunk && c->eng_ready) {
@@ -1093,14 +1103,15 @@ namespace {
 
 int batch_chunks(const dpt_batch* b, int s) {
   const int n = b->ctx[s]->n_points;
-  return n > 0 ? (n + b->chunk - 1) / b->chunk : 1;
+  const int ppc = coop_ppc(b->ctx[0]->prm, b->chunk);
+  return n > 0 ? (n + ppc - 1) / ppc : 1;
 }
 
 // Partition streams into groups that each fit one cooperative launch: a group's
 // XCD-packed grid is at most its chunk total plus 8 slots per largest stream.
 int build_groups(dpt_batch* b) {
   b->clear_groups();
-  const int cap = coop_max_blocks(b->chunk);
+  const int cap = coop_max_blocks(coop_threads(b->ctx[0]->prm, b->chunk));
   std::vector<int> order(b->n);
   for (int s = 0; s < b->n; ++s) order[s] = s;
   std::sort(order.begin(), order.end(), [&](int p, int q) { return batch_chunks(b, p) > batch_chunks(b, q); });
@@ -1113,7 +1124,8 @@ int build_groups(dpt_batch* b) {
     if (!g) return fail(DPT_E_OOM, "host allocation failed");
     std::vector<int> maxp(cur.size());
     for (size_t k = 0; k < cur.size(); ++k) maxp[k] = b->ctx[cur[k]]->cap;
-    hipError_t e = g->init((int)cur.size(), maxp.data(), b->chunk, true, b->stream);
+    hipError_t e = g->init((int)cur.size(), maxp.data(), coop_threads(b->ctx[0]->prm, b->chunk),
+                           coop_ppc(b->ctx[0]->prm, b->chunk), true, b->stream);
     if (e != hipSuccess) {
       delete g;
       return fail(DPT_E_HIP, "cooperative group init: %s", hipGetErrorString(e));
@@ -1149,8 +1161,7 @@ int build_groups(dpt_batch* b) {
 
 bool batch_use_coop(const dpt_batch* b) {
   if (b->ctx[0]->prm.precision == DPT_PREC_MIXED) return true;
-  if (b->ctx[0]->prm.flags & DPT_FLAG_GAUSS_F32) return false;
-  return b->launch_mode != DPT_LAUNCH_WORKGROUP && b->ctx[0]->prm.n_pattern == 8 && coop_max_blocks(b->chunk) > 0;
+  return b->launch_mode != DPT_LAUNCH_WORKGROUP && coop_max_blocks(coop_threads(b->ctx[0]->prm, b->chunk)) > 0;
 }
 
 // Wait for the stream and fill the results of every batched track in flight.
@@ -1482,7 +1493,7 @@ int dpt_batch_track_enqueue(dpt_batch* b, int32_t init_mode, const double* T_cw_
   if (e != DPT_OK) return e;
   if (!batch_use_coop(b)) {
     if (init_mode == DPT_INIT_CONST_VELOCITY)
-      return fail(DPT_E_ARG, "a constant-velocity start needs the cooperative track (K = 8, launch mode AUTO or COOP)");
+      return fail(DPT_E_ARG, "a constant-velocity start needs the cooperative track (launch mode AUTO or COOP)");
     return dpt_batch_track(b, T_cw_init, out);
   }
   std::vector<int> modes(b->n, init_mode == DPT_INIT_GIVEN ? kStartGiven : kStartConstVelocity);
@@ -1506,9 +1517,6 @@ int dpt_batch_set_launch_config(dpt_batch* b, int32_t mode, int32_t chunk) {
   if (!b) return fail(DPT_E_ARG, "NULL batch");
   if (mode < DPT_LAUNCH_AUTO || mode > DPT_LAUNCH_COOP) return fail(DPT_E_ARG, "mode %d", mode);
   if (chunk != 64 && chunk != 128 && chunk != 256) return fail(DPT_E_ARG, "chunk %d not in {64, 128, 256}", chunk);
-  if (mode == DPT_LAUNCH_COOP && b->ctx[0]->prm.n_pattern != 8) return fail(DPT_E_ARG, "cooperative track needs K = 8");
-  if (mode == DPT_LAUNCH_COOP && (b->ctx[0]->prm.flags & DPT_FLAG_GAUSS_F32))
-    return fail(DPT_E_ARG, "the Gaussian float pyramid runs on the one-workgroup launch");
   if (mode == DPT_LAUNCH_WORKGROUP && b->ctx[0]->prm.precision == DPT_PREC_MIXED)
     return fail(DPT_E_ARG, "mixed precision runs on the cooperative launch only");
   const int e = batch_synchronize(b);

@@ -167,14 +167,20 @@ __device__ __forceinline__ void start_pose(const StartSlot* __restrict__ st, con
 // FIXED: fixed-H mode (FP32): unweighted residuals, only b, the cost and the
 // counts are reduced and exchanged (16 slots), and each level's constant H
 // comes factored from the precompute.
-template <int CH, bool MIXED, bool FIXED>
+// GENERIC: any pattern K (four lanes per point, CH / 4 points per chunk) on
+// uint8 levels or (PIX = float) the floating-point Gaussian pyramid.
+template <int CH, bool MIXED, bool FIXED, bool GENERIC = false, class PIX = uint8_t>
 __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __restrict__ streams,
                                                            const int2* __restrict__ work,
                                                            const StartSlot* __restrict__ start,
                                                            TrackOut* __restrict__ outs, uint32_t tag_base,
                                                            int spin_limit) {
   static_assert(!(MIXED && FIXED), "the fixed-H mode computes in FP32");
-  using PR = typename std::conditional<MIXED, PointRegsH, PointRegs>::type;
+  static_assert(!(MIXED && GENERIC) && (GENERIC || std::is_same<PIX, uint8_t>::value), "variant");
+  using PR = typename std::conditional<GENERIC, PointGeo,
+                                       typename std::conditional<MIXED, PointRegsH, PointRegs>::type>::type;
+  constexpr bool FLOAT_PYR = std::is_same<PIX, float>::value;
+  constexpr int PPC = GENERIC ? CH / kLanesPerPoint : CH;  // points per chunk
   constexpr int NV = FIXED ? kFixSlots : 32;
   constexpr int sE = FIXED ? kFixE : kSlotE, sN = FIXED ? kFixN : kSlotN, sP = FIXED ? kFixPts : kSlotPts;
   __shared__ CoopStream ss;
@@ -195,7 +201,9 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
   const TrackArgs& a = ss.a;
   const PatRegs pregs = pattern_regs(a.pat);
   const int chunk = w.y, nch = ss.n_chunks;
-  const int i = chunk * CH + threadIdx.x;
+  const int i = chunk * PPC + (GENERIC ? (int)threadIdx.x / kLanesPerPoint : (int)threadIdx.x);
+  const int sub = GENERIC ? (int)threadIdx.x % kLanesPerPoint : 0;
+  const PIX* cur = FLOAT_PYR ? reinterpret_cast<const PIX*>(a.curf) : reinterpret_cast<const PIX*>(a.cur);
   // pose state, identical in every thread of every chunk of the stream
   float T[12];
   double Td[MIXED ? 12 : 1];
@@ -214,8 +222,11 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
   PR pr;
   for (int l = a.levels - 1; l >= 0 && !stop; --l) {
     const LevelGeom g = a.lv[l];
-    const uint8_t* img = a.cur + g.off;
-    load_point(a, l, i, pr);
+    const PIX* img = cur + g.off;
+    if constexpr (GENERIC)
+      load_point_geo(a, l, i, pr);
+    else
+      load_point(a, l, i, pr);
     if constexpr (FIXED) {
       // read by every thread after the next exchange's barrier; the other
       // parity's copy may still be in use by a previous level's solve
@@ -229,7 +240,10 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
       float acc[NV];
 #pragma unroll
       for (int j = 0; j < NV; ++j) acc[j] = 0.f;
-      accumulate_point<false, true, PR, NV>(a, pregs, g, img, T, pr, acc);
+      if constexpr (GENERIC)
+        accumulate_point_generic<false, PIX, NV>(a, a.pat, g, img, T, pr, sub, acc);
+      else
+        accumulate_point<false, true, PR, NV>(a, pregs, g, img, T, pr, acc);
       if (!stream_total<MIXED, NV>(acc, sh_red, sh_tot, &sh_ok, ss.partials, chunk, nch, tag, spin_limit)) {
         timed_out = stop = true;
         break;
@@ -279,8 +293,13 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
 #pragma unroll
     for (int j = 0; j < NV; ++j) acc[j] = 0.f;
     const LevelGeom g = a.lv[0];
-    load_point(a, 0, i, pr);
-    accumulate_point<true, true, PR, NV>(a, pregs, g, a.cur + g.off, T, pr, acc);
+    if constexpr (GENERIC) {
+      load_point_geo(a, 0, i, pr);
+      accumulate_point_generic<true, PIX, NV>(a, a.pat, g, cur + g.off, T, pr, sub, acc);
+    } else {
+      load_point(a, 0, i, pr);
+      accumulate_point<true, true, PR, NV>(a, pregs, g, a.cur + g.off, T, pr, acc);
+    }
     if (!stream_total<MIXED, NV>(acc, sh_red, sh_tot, &sh_ok, ss.partials, chunk, nch, tag, spin_limit))
       timed_out = true;
   }
@@ -321,6 +340,20 @@ static int coop_blocks_per_cu() {
       v = v2 = v3 = 0;
     }
     nb = std::min(v, std::min(v2, v3));
+    if (CH == kGenericThreads) {
+      const void* gk[] = {reinterpret_cast<const void*>(&coop_track_kernel<kGenericThreads, false, false, true>),
+                          reinterpret_cast<const void*>(&coop_track_kernel<kGenericThreads, false, true, true>),
+                          reinterpret_cast<const void*>(&coop_track_kernel<kGenericThreads, false, false, true, float>),
+                          reinterpret_cast<const void*>(&coop_track_kernel<kGenericThreads, false, true, true, float>)};
+      for (const void* f : gk) {
+        int vg = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&vg, f, CH, 0) != hipSuccess) {
+          (void)hipGetLastError();
+          vg = 0;
+        }
+        nb = std::min(nb, vg);
+      }
+    }
   }
   return nb;
 }
@@ -362,9 +395,21 @@ static hipError_t coop_launch_k(const CoopStream* d_streams, const int2* d_work,
                                 TrackOut* out, uint32_t tag_base, int variant, int spin_limit, hipStream_t s) {
   void* args[] = {(void*)&d_streams, (void*)&d_work, (void*)&start, (void*)&out, (void*)&tag_base,
                   (void*)&spin_limit};
-  const void* fn = variant == kCoopMixed    ? reinterpret_cast<const void*>(&coop_track_kernel<CH, true, false>)
-                   : variant == kCoopFixedH ? reinterpret_cast<const void*>(&coop_track_kernel<CH, false, true>)
-                                            : reinterpret_cast<const void*>(&coop_track_kernel<CH, false, false>);
+  const void* fn = nullptr;
+  if (variant & kCoopGeneric) {
+    if (CH != kGenericThreads) return hipErrorInvalidValue;
+    constexpr int G = kGenericThreads;
+    switch (variant & (kCoopFixedH | kCoopFloatPyr)) {
+      case 0: fn = reinterpret_cast<const void*>(&coop_track_kernel<G, false, false, true>); break;
+      case kCoopFixedH: fn = reinterpret_cast<const void*>(&coop_track_kernel<G, false, true, true>); break;
+      case kCoopFloatPyr: fn = reinterpret_cast<const void*>(&coop_track_kernel<G, false, false, true, float>); break;
+      default: fn = reinterpret_cast<const void*>(&coop_track_kernel<G, false, true, true, float>); break;
+    }
+  } else {
+    fn = variant == kCoopMixed    ? reinterpret_cast<const void*>(&coop_track_kernel<CH, true, false>)
+         : variant == kCoopFixedH ? reinterpret_cast<const void*>(&coop_track_kernel<CH, false, true>)
+                                  : reinterpret_cast<const void*>(&coop_track_kernel<CH, false, false>);
+  }
   if (4 * n_work <= coop_max_blocks(CH)) return hipLaunchKernel(fn, dim3(n_work), dim3(CH), args, 0, s);
   return hipLaunchCooperativeKernel(fn, dim3(n_work), dim3(CH), args, 0, s);
 }
@@ -381,17 +426,18 @@ hipError_t launch_coop_track(const CoopStream* d_streams, const int2* d_work, in
 
 // ---------------------------------------------------------------- engine (host)
 
-hipError_t CoopEngine::init(int n_streams, const int* max_points, int chunk_, bool xcd, hipStream_t s) {
+hipError_t CoopEngine::init(int n_streams, const int* max_points, int chunk_, int ppc_, bool xcd, hipStream_t s) {
   release();
   n = n_streams;
   chunk = chunk_;
+  ppc = ppc_;
   xcd_pack = xcd;
   stream = s;
   h_streams.assign(n, CoopStream{});
   max_chunks.resize(n);
   partial_words = 0;
   for (int k = 0; k < n; ++k) {
-    max_chunks[k] = (max_points[k] + chunk - 1) / chunk;
+    max_chunks[k] = (max_points[k] + ppc - 1) / ppc;
     partial_words += (size_t)2 * max_chunks[k] * 32;
   }
   if (partial_words == 0) partial_words = 64;
@@ -434,7 +480,7 @@ void CoopEngine::set_stream(int k, const TrackArgs& a, double* hist) {
   c.a = a;
   c.a.out = nullptr;  // results go to the launch's slot of h_out
   c.hist = hist;
-  c.n_chunks = a.ref.n > 0 ? (a.ref.n + chunk - 1) / chunk : 1;
+  c.n_chunks = a.ref.n > 0 ? (a.ref.n + ppc - 1) / ppc : 1;
   dirty = true;
 }
 

@@ -686,4 +686,120 @@ __device__ __forceinline__ void accumulate_point(const TrackArgs& a, const PatRe
   }
 }
 
+// ---------------------------------------------------------------- generic-K cooperative accumulation
+
+// Patterns other than the 8-pixel one (p x p patches) and the floating-point
+// pyramid: four lanes share a point, lane `sub` of the quad taking samples
+// sub, sub + 4, ... < K, so a 49-sample patch costs each lane 13 samples.  The
+// quad's partial sums are combined with DPP quad permutations and lane 0 of the
+// quad adds the point's normal-equation terms.
+struct PointGeo {
+  float X0, Y0, Z0;
+  float iz, xp, yp;
+  int64_t s0;  // cache index of the point's sample 0 at the level
+  bool ok;
+};
+
+__device__ __forceinline__ void load_point_geo(const TrackArgs& a, int l, int i, PointGeo& pg) {
+  float4 p;
+  int64_t e;
+  const bool ok = load_geometry(a, l, i, p, e);
+  set_geometry(pg, ok, p);
+  pg.s0 = e * a.pat.K;
+}
+
+// DPP quad permutation (quad_perm selector), a VALU operand modifier.
+template <int SEL>
+__device__ __forceinline__ float dpp_quad(float v) {
+  return __uint_as_float(__builtin_amdgcn_update_dpp(0u, __float_as_uint(v), SEL, 0xf, 0xf, false));
+}
+
+// Sum over the four lanes of a quad, the same in every lane of it.
+__device__ __forceinline__ float quad_sum(float v) {
+  v += dpp_quad<0xB1>(v);  // lanes [1, 0, 3, 2]
+  v += dpp_quad<0x4E>(v);  // lanes [2, 3, 0, 1]
+  return v;
+}
+
+// NV = 32: robust mode; NV = kFixSlots: fixed-H mode (no weights, b only), as
+// accumulate_point.  PIX: uint8 levels or the floating-point Gaussian pyramid.
+template <bool COST_ONLY, class PIX, int NV>
+__device__ __forceinline__ void accumulate_point_generic(const TrackArgs& a, const Pattern& pat, const LevelGeom& g,
+                                                         const PIX* __restrict__ img, const float* T,
+                                                         const PointGeo& pg, int sub, float (&acc)[NV]) {
+  constexpr bool FIXED = NV == kFixSlots;
+  constexpr int sE = FIXED ? kFixE : kSlotE, sN = FIXED ? kFixN : kSlotN, sP = FIXED ? kFixPts : kSlotPts;
+  const float kH = FIXED ? 0.0f : a.huber_k;
+  float X, Y, Z;
+  transform(T, pg.X0, pg.Y0, pg.Z0, X, Y, Z);
+  float u, v;
+  project(g, X, Y, Z, u, v);
+  const bool ok = pg.ok & (Z > a.z_min) & inside(g, pat, u, v);
+  u = ok ? u : 0.0f;
+  v = ok ? v : 0.0f;
+  const int K = pat.K, W = g.W;
+  const __attribute__((address_space(1))) PIX* gimg = (const __attribute__((address_space(1))) PIX*)img;
+  float m00 = 0.f, m01 = 0.f, m11 = 0.f, v0 = 0.f, v1 = 0.f, E = 0.f;
+  for (int k = sub; k < K; k += kLanesPerPoint) {
+    const float x = u + (float)pat.dx[k], y = v + (float)pat.dy[k];
+    const float fx = floorf(x), fy = floorf(y);
+    const float ta = x - fx, tc = y - fy;
+    const int off = ((int)fy * W + (int)fx) & -(int)ok;  // an unusable point reads the level's first taps
+    const float t00 = gimg[off], t10 = gimg[off + 1], t01 = gimg[off + W], t11 = gimg[off + W + 1];
+    const float top = fmaf(ta, t10 - t00, t00);
+    const float bot = fmaf(ta, t11 - t01, t01);
+    const float Ic = fmaf(tc, bot - top, top);
+    const float r = a.ref.I0[pg.s0 + k] - Ic;
+    const float ar = fabsf(r);
+    const bool hub = (kH > 0.f) & (ar > kH);
+    const float w = hub ? kH * __builtin_amdgcn_rcpf(ar) : 1.0f;
+    const float rho = hub ? kH * (ar - 0.5f * kH) : 0.5f * r * r;
+    E += rho;
+    if (!COST_ONLY) {
+      const float gx = a.ref.gx[pg.s0 + k], gy = a.ref.gy[pg.s0 + k];
+      const float wgx = w * gx, wgy = w * gy;
+      if (!FIXED) {
+        m00 = fmaf(wgx, gx, m00);
+        m01 = fmaf(wgx, gy, m01);
+        m11 = fmaf(wgy, gy, m11);
+      }
+      v0 = fmaf(wgx, r, v0);
+      v1 = fmaf(wgy, r, v1);
+    }
+  }
+  const bool use = ok & (sub == 0);
+  E = quad_sum(E);
+  acc[sE] += use ? E : 0.0f;
+  acc[sN] += use ? (float)K : 0.0f;
+  acc[sP] += use ? 1.0f : 0.0f;
+  if (COST_ONLY) return;
+  v0 = quad_sum(v0);
+  v1 = quad_sum(v1);
+  v0 = use ? v0 : 0.0f, v1 = use ? v1 : 0.0f;
+  const float iz = pg.iz, xp = pg.xp, yp = pg.yp;
+  const float au[6] = {-g.fx * xp * yp, g.fx * fmaf(xp, xp, 1.0f), -g.fx * yp, g.fx * iz, 0.0f, -g.fx * xp * iz};
+  const float av[6] = {-g.fy * fmaf(yp, yp, 1.0f), g.fy * xp * yp, g.fy * xp, 0.0f, g.fy * iz, -g.fy * yp * iz};
+  if constexpr (FIXED) {
+#pragma unroll
+    for (int r = 0; r < 6; ++r) acc[kFixB + r] -= fmaf(au[r], v0, av[r] * v1);
+  } else {
+    m00 = quad_sum(m00);
+    m01 = quad_sum(m01);
+    m11 = quad_sum(m11);
+    m00 = use ? m00 : 0.0f, m01 = use ? m01 : 0.0f, m11 = use ? m11 : 0.0f;
+    int q = 0;
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+      const float ma = fmaf(m00, au[r], m01 * av[r]);
+      const float mc = fmaf(m01, au[r], m11 * av[r]);
+#pragma unroll
+      for (int c = r; c < 6; ++c) {
+        acc[q] = fmaf(ma, au[c], fmaf(mc, av[c], acc[q]));
+        ++q;
+      }
+      acc[kSlotB + r] -= fmaf(au[r], v0, av[r] * v1);
+    }
+  }
+}
+
 }  // namespace dpt

@@ -197,14 +197,19 @@ struct PyrJob {
 };
 
 // Variants of the cooperative track kernel.
-enum { kCoopFP32 = 0, kCoopMixed = 1, kCoopFixedH = 2 };
+// Bits: kCoopMixed and kCoopFixedH as named; kCoopGeneric: any pattern K, four
+// lanes per point, kGenericThreads-thread chunks of kGenericThreads / 4 points;
+// kCoopFloatPyr (with kCoopGeneric): the floating-point Gaussian pyramid.
+enum { kCoopFP32 = 0, kCoopMixed = 1, kCoopFixedH = 2, kCoopGeneric = 4, kCoopFloatPyr = 8 };
+constexpr int kGenericThreads = 256;
+constexpr int kLanesPerPoint = 4;
 
 // Host-side owner of a cooperative track launch over n streams.  Start slots
 // and results live in host-mapped pinned memory that the kernel reads and
 // writes directly, in rings of kRing launches, so a launch needs no copy
 // commands and up to kRing launches can be in flight.
 struct CoopEngine {
-  int n = 0, chunk = 256, work_cap = 0;
+  int n = 0, chunk = 256, ppc = 256, work_cap = 0;  // threads and points per chunk
   bool xcd_pack = true, dirty = true;
   hipStream_t stream = nullptr;
   std::vector<CoopStream> h_streams;
@@ -217,10 +222,10 @@ struct CoopEngine {
   uint32_t tag_base = 1;       // epoch tags of the next launch start here; 0 marks a cleared word
   StartSlot* h_start = nullptr;   // [kRing][n], host-mapped
   StartSlot* dv_start = nullptr;  // device view of h_start
-  int variant = kCoopFP32;        // kernel variant (kCoopFP32, kCoopMixed, kCoopFixedH)
+  int variant = kCoopFP32;        // kernel variant (kCoop* bits)
   TrackOut* h_out = nullptr;      // [kRing][n] results, host-mapped
   TrackOut* dv_out = nullptr;     // device view of h_out
-  hipError_t init(int n_streams, const int* max_points, int chunk, bool xcd_pack, hipStream_t s);
+  hipError_t init(int n_streams, const int* max_points, int chunk, int ppc, bool xcd_pack, hipStream_t s);
   void release();
   void set_stream(int k, const TrackArgs& a, double* hist);
   hipError_t upload();

@@ -117,9 +117,10 @@ def test_fixed_h_identity_and_statuses(gpu_lib, launch):
     assert trk.track(behind)["status"] == dpt.TRACK_TOO_FEW_POINTS
 
 
-def test_fixed_h_square_patch(gpu_lib):
-    """7x7 patches (49 samples per point) through the generic-K path."""
-    d, P, trk, ref = _setup(gpu_lib, seed=6, n=300, pattern=synth.square_pattern(7))
+@pytest.mark.parametrize("launch", [(1, 256), (2, 256)])
+def test_fixed_h_square_patch(gpu_lib, launch):
+    """7x7 patches (49 samples per point) through the generic-K paths."""
+    d, P, trk, ref = _setup(gpu_lib, seed=6, n=300, pattern=synth.square_pattern(7), launch=launch)
     g = trk.track(np.eye(4))
     o = ref.track(d["cur"], np.eye(4))
     rot, tr, rel = _compare(g, o)

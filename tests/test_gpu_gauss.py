@@ -18,12 +18,17 @@ def _oparams(p, fixed_h=False):
                               min_points=p.min_points, pattern=pat, z_min=p.z_min, fixed_h=fixed_h, gauss=True)
 
 
-def _setup(dpt, seed=0, n=500, levels=3, cam=synth.CAM_640, fixed_h=False, **kw):
+LAUNCHES = [(1, 256), (2, 256)]  # one workgroup; cooperative (64-point chunks, four lanes per point)
+
+
+def _setup(dpt, seed=0, n=500, levels=3, cam=synth.CAM_640, fixed_h=False, launch=None, **kw):
     d = synth.pair(seed, cam)
     idx = oracle.select_points(d["ref"], n, 8)
     P = synth.backproject(cam, d["depth"], idx, d["T_rw"])
     prm = dpt.make_params(levels=levels, gauss=True, fixed_h=fixed_h, **kw)
     trk = dpt.Tracker(cam, prm, max_points=max(n, 1))
+    if launch is not None:
+        trk.set_launch_config(*launch)
     trk.build_pyramid(dpt.SLOT_REF, d["ref"])
     trk.set_reference_points(P, d["T_rw"])
     trk.build_pyramid(dpt.SLOT_CUR, d["cur"])
@@ -85,9 +90,10 @@ def _compare(g, o):
     return rot, tr, rel
 
 
+@pytest.mark.parametrize("launch", LAUNCHES)
 @pytest.mark.parametrize("seed", [0, 5, 21, 42])
-def test_gauss_track_matches_oracle(gpu_lib, seed):
-    d, P, trk, ref = _setup(gpu_lib, seed=seed, n=1500)
+def test_gauss_track_matches_oracle(gpu_lib, seed, launch):
+    d, P, trk, ref = _setup(gpu_lib, seed=seed, n=1500, launch=launch)
     g, o = trk.track(np.eye(4)), ref.track(d["cur"], np.eye(4))
     rot, tr, rel = _compare(g, o)
     print(f"seed {seed}: rot {rot:.2e} tr {tr:.2e} cost {rel:.2e} iters {g['iterations']}/{o['iterations']}")
@@ -95,12 +101,13 @@ def test_gauss_track_matches_oracle(gpu_lib, seed):
     assert rot < ROT_TOL and tr < TR_TOL and rel < COST_TOL
 
 
+@pytest.mark.parametrize("launch", LAUNCHES)
 @pytest.mark.parametrize("patch,levels,fixed_h", [(7, 6, False), (11, 5, False), (7, 6, True), (11, 5, True)])
-def test_gauss_paper_shape(gpu_lib, patch, levels, fixed_h):
+def test_gauss_paper_shape(gpu_lib, patch, levels, fixed_h, launch):
     """The paper's per-point shape: 752x480, p x p patches, 6 levels (5 for
     11x11, whose patch leaves too few valid positions in the 23x15 sixth level)."""
     d, P, trk, ref = _setup(gpu_lib, seed=3, n=600, levels=levels, cam=synth.CAM_752,
-                            pattern=synth.square_pattern(patch), fixed_h=fixed_h)
+                            pattern=synth.square_pattern(patch), fixed_h=fixed_h, launch=launch)
     g, o = trk.track(np.eye(4)), ref.track(d["cur"], np.eye(4))
     rot, tr, rel = _compare(g, o)
     print(f"p={patch} fixed_h={fixed_h}: rot {rot:.2e} tr {tr:.2e} cost {rel:.2e} "
@@ -110,26 +117,27 @@ def test_gauss_paper_shape(gpu_lib, patch, levels, fixed_h):
     assert rot < ROT_TOL and tr < TR_TOL and rel < COST_TOL
 
 
-def test_gauss_paper_shape_too_few_points_at_coarsest(gpu_lib):
+@pytest.mark.parametrize("launch", LAUNCHES)
+def test_gauss_paper_shape_too_few_points_at_coarsest(gpu_lib, launch):
     """A 7x7 patch fits few points into the 23x15 sixth level: with this map
     only 4 are valid there, so both sides stop with TOO_FEW_POINTS."""
     dpt = gpu_lib
-    d, P, trk, ref = _setup(dpt, seed=6, n=600, levels=6, cam=synth.CAM_752, pattern=synth.square_pattern(7))
+    d, P, trk, ref = _setup(dpt, seed=6, n=600, levels=6, cam=synth.CAM_752, pattern=synth.square_pattern(7),
+                            launch=launch)
     assert int(trk.reference_cache(5)["valid"].sum()) == int(ref.cache(5)["refvalid"].sum()) == 4
     g, o = trk.track(np.eye(4)), ref.track(d["cur"], np.eye(4))
     assert g["status"] == o["status"] == dpt.TRACK_TOO_FEW_POINTS
     assert g["iterations"] == o["iterations"] == 0
 
 
-def test_gauss_identity_and_rejections(gpu_lib):
+@pytest.mark.parametrize("launch", LAUNCHES)
+def test_gauss_identity_and_rejections(gpu_lib, launch):
     dpt = gpu_lib
-    d, P, trk, ref = _setup(dpt, seed=4)
+    d, P, trk, ref = _setup(dpt, seed=4, launch=launch)
     trk.build_pyramid(dpt.SLOT_CUR, d["ref"])
     g = trk.track(np.eye(4))
     np.testing.assert_array_equal(g["T_cw"], np.eye(4))
     assert g["final_cost"] == 0.0 and g["status"] == 0
-    with pytest.raises(dpt.DptError):
-        trk.set_launch_config(dpt.LAUNCH_COOP, 256)
     with pytest.raises(dpt.DptError):
         dpt.Tracker(synth.CAM_640, dpt.make_params(gauss=True, precision=dpt.PREC_MIXED), max_points=10)
 

@@ -195,10 +195,13 @@ def test_failure_statuses(gpu_lib, launch):
     assert trk1.track(np.eye(4))["status"] == dpt.TRACK_TOO_FEW_POINTS
 
 
-@pytest.mark.parametrize("patch", [7, 11])
-def test_track_square_patches(gpu_lib, patch):
-    """Paper-shaped p x p patches (7x7 and 11x11) through the generic-K path."""
-    d, P, trk, ref = _pair_setup(gpu_lib, seed=6, n=300, pattern=synth.square_pattern(patch))
+@pytest.mark.parametrize("launch", [(1, 256), (2, 256)])
+@pytest.mark.parametrize("patch", [3, 7, 11])
+def test_track_square_patches(gpu_lib, patch, launch):
+    """Paper-shaped p x p patches (and a 3x3 one, K = 9, not a multiple of the
+    four lanes per point) through the generic-K paths: one workgroup, and the
+    cooperative variant with four lanes per point."""
+    d, P, trk, ref = _pair_setup(gpu_lib, seed=6, n=300, pattern=synth.square_pattern(patch), launch=launch)
     g = trk.track(np.eye(4))
     o = ref.track(d["cur"], np.eye(4))
     rot, tr, rel = _compare(g, o)
