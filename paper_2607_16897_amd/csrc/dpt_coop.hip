@@ -21,6 +21,9 @@
 
 namespace dpt {
 
+// Chunk words read per round trip while polling (one load each in flight).
+constexpr int kPollBatch = 8;
+
 // Wave 0 only.  Publish this chunk's column sums (`mine`, lanes < NV) under
 // `tag`, wait until all nch chunks of the stream published theirs, and return
 // the stream totals in chunk order (lanes < NV).  False on timeout.  A chunk's
@@ -38,15 +41,15 @@ __device__ __forceinline__ bool exchange_partials(uint64_t* partials, int chunk,
     float s = 0.0f, comp = 0.0f;
     int ok = 1;
     if (lane < NV) {
-      for (int c0 = 0; c0 < nch; c0 += 8) {
-        uint64_t v[8];
+      for (int c0 = 0; c0 < nch; c0 += kPollBatch) {
+        uint64_t v[kPollBatch];
 #pragma unroll
-        for (int j = 0; j < 8; ++j)  // eight loads in flight, then the checks
+        for (int j = 0; j < kPollBatch; ++j)  // a batch of loads in flight, then the checks
           v[j] = c0 + j < nch ? __hip_atomic_load(&buf[(c0 + j) * 32 + lane], __ATOMIC_RELAXED,
                                                   __HIP_MEMORY_SCOPE_AGENT)
                               : hi;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
+        for (int j = 0; j < kPollBatch; ++j) {
           if (c0 + j >= nch) break;
           ok &= (uint32_t)(v[j] >> 32) == tag;
           const float x = __uint_as_float((uint32_t)v[j]);

@@ -740,31 +740,48 @@ __device__ __forceinline__ void accumulate_point_generic(const TrackArgs& a, con
   const int K = pat.K, W = g.W;
   const __attribute__((address_space(1))) PIX* gimg = (const __attribute__((address_space(1))) PIX*)img;
   float m00 = 0.f, m01 = 0.f, m11 = 0.f, v0 = 0.f, v1 = 0.f, E = 0.f;
-  for (int k = sub; k < K; k += kLanesPerPoint) {
-    const float x = u + (float)pat.dx[k], y = v + (float)pat.dy[k];
-    const float fx = floorf(x), fy = floorf(y);
-    const float ta = x - fx, tc = y - fy;
-    const int off = ((int)fy * W + (int)fx) & -(int)ok;  // an unusable point reads the level's first taps
-    const float t00 = gimg[off], t10 = gimg[off + 1], t01 = gimg[off + W], t11 = gimg[off + W + 1];
-    const float top = fmaf(ta, t10 - t00, t00);
-    const float bot = fmaf(ta, t11 - t01, t01);
-    const float Ic = fmaf(tc, bot - top, top);
-    const float r = a.ref.I0[pg.s0 + k] - Ic;
-    const float ar = fabsf(r);
-    const bool hub = (kH > 0.f) & (ar > kH);
-    const float w = hub ? kH * __builtin_amdgcn_rcpf(ar) : 1.0f;
-    const float rho = hub ? kH * (ar - 0.5f * kH) : 0.5f * r * r;
-    E += rho;
-    if (!COST_ONLY) {
-      const float gx = a.ref.gx[pg.s0 + k], gy = a.ref.gy[pg.s0 + k];
-      const float wgx = w * gx, wgy = w * gy;
-      if (!FIXED) {
-        m00 = fmaf(wgx, gx, m00);
-        m01 = fmaf(wgx, gy, m01);
-        m11 = fmaf(wgy, gy, m11);
+  // Batches of four samples per lane: all their taps and cache entries are
+  // issued before any is used.  A slot past the pattern reads sample 0 (always
+  // in range) and is weighted by zero.
+  constexpr int B = 4;
+  for (int k0 = sub; k0 < K; k0 += B * kLanesPerPoint) {
+    float ta[B], tc[B], t00[B], t10[B], t01[B], t11[B], i0[B], gxs[B], gys[B], msk[B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      const int k = k0 + j * kLanesPerPoint;
+      const bool has = k < K;
+      const int kk = has ? k : 0;
+      msk[j] = has ? 1.0f : 0.0f;
+      const float x = u + (float)pat.dx[kk], y = v + (float)pat.dy[kk];
+      const float fx = floorf(x), fy = floorf(y);
+      ta[j] = x - fx;
+      tc[j] = y - fy;
+      const int off = ((int)fy * W + (int)fx) & -(int)ok;  // an unusable point reads the level's first taps
+      t00[j] = gimg[off], t10[j] = gimg[off + 1], t01[j] = gimg[off + W], t11[j] = gimg[off + W + 1];
+      i0[j] = a.ref.I0[pg.s0 + kk];
+      if (!COST_ONLY) gxs[j] = a.ref.gx[pg.s0 + kk], gys[j] = a.ref.gy[pg.s0 + kk];
+    }
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      const float top = fmaf(ta[j], t10[j] - t00[j], t00[j]);
+      const float bot = fmaf(ta[j], t11[j] - t01[j], t01[j]);
+      const float Ic = fmaf(tc[j], bot - top, top);
+      const float r = i0[j] - Ic;
+      const float ar = fabsf(r);
+      const bool hub = (kH > 0.f) & (ar > kH);
+      const float w = (hub ? kH * __builtin_amdgcn_rcpf(ar) : 1.0f) * msk[j];
+      const float rho = hub ? kH * (ar - 0.5f * kH) : 0.5f * r * r;
+      E = fmaf(msk[j], rho, E);
+      if (!COST_ONLY) {
+        const float wgx = w * gxs[j], wgy = w * gys[j];
+        if (!FIXED) {
+          m00 = fmaf(wgx, gxs[j], m00);
+          m01 = fmaf(wgx, gys[j], m01);
+          m11 = fmaf(wgy, gys[j], m11);
+        }
+        v0 = fmaf(wgx, r, v0);
+        v1 = fmaf(wgy, r, v1);
       }
-      v0 = fmaf(wgx, r, v0);
-      v1 = fmaf(wgy, r, v1);
     }
   }
   const bool use = ok & (sub == 0);
