@@ -528,6 +528,32 @@ def cpu_baseline(wins, seconds: float, comparisons, tween_run=None):
     out = {"value": round((WINDOW - 1) * n / el, 2), "unit": "frames/s", "cores": 1, "kind": "oracle",
            "sample": f"{n} keyframe windows ({(WINDOW - 1) * n} tracked frames) of the headline sequence in "
                      f"{el:.1f} s, FP64 C oracle (gcc -O2) on one host thread"}
+    # the same windows on every host core the process may use (one window per thread at a time; the
+    # oracle's C calls release the interpreter lock), capped at 16 threads, about a third as long
+    from concurrent.futures import ThreadPoolExecutor
+
+    threads = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()))
+
+    def one_window(w):
+        win = wins[w % len(wins)]
+        idx = oracle.select_points(win["imgs"][0], N_POINTS, 8)
+        ref = oracle.Reference(CAM, prm, win["imgs"][0], synth.backproject(CAM, win["depth"], idx, win["gts"][0]),
+                               win["gts"][0])
+        prev2, prev1 = win["T_prev"], win["gts"][0]
+        for j in range(1, WINDOW):
+            r = ref.track(win["imgs"][j], cv_init(prev2, prev1))
+            prev2, prev1 = prev1, r["T_cw"]
+        return WINDOW - 1
+
+    t0 = time.perf_counter()
+    done, w = 0, 0
+    with ThreadPoolExecutor(threads) as ex:
+        while time.perf_counter() - t0 < seconds / 3:
+            done += sum(ex.map(one_window, range(w, w + threads)))
+            w += threads
+    el_all = time.perf_counter() - t0
+    out["all_cores"] = {"value": round(done / el_all, 2), "unit": "frames/s", "cores": threads,
+                        "sample": f"{done // (WINDOW - 1)} keyframe windows in {el_all:.1f} s, {threads} threads"}
     diffs = {}
     for name, (frames, starts, poses, cam, wset, npts, levels, *extra) in comparisons.items():
         p = oracle.make_params(levels=levels, **(extra[0] if extra else {}))
