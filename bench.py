@@ -192,10 +192,9 @@ def timed_plain(dpt, synth, wins, dev, steps, warmup, prm, launch, chunk, n_poin
 def bench_batched_sequences(dpt, synth, n_streams: int, steps: int, warmup: int, n_win: int = 2):
     """n_streams independent sequences of the headline shape, stream s on its own
     scene and trajectory (seed 2607 + s), tracked together: a step is one
-    keyframe window of every stream."""
+    keyframe window of every stream.  Returns the FP32 result, and the same
+    frames through the mixed-precision variant under "mixed_precision"."""
     import torch
-
-    from paper_2607_16897_amd import autotune
 
     t_r = time.perf_counter()
     wins = [make_windows(n_win, seed=2607 + s) for s in range(n_streams)]
@@ -207,12 +206,24 @@ def bench_batched_sequences(dpt, synth, n_streams: int, steps: int, warmup: int,
     depths = [torch.from_numpy(np.stack([wins[s][w]["depth"] for s in range(n_streams)])).cuda()
               for w in range(n_win)]
     torch.cuda.synchronize()
-    prm = dpt.make_params(levels=LEVELS, max_iters=10, huber_k=9.0, step_eps=1e-5)
-    bt = dpt.BatchTracker([CAM] * n_streams, prm, [N_POINTS] * n_streams)
-    stats = {"samples": [], "iters": [], "status": []}
-
     T_rw = [np.stack([wins[s][w]["gts"][0] for s in range(n_streams)]) for w in range(n_win)]
     T_prev = [np.stack([wins[s][w]["T_prev"] for s in range(n_streams)]) for w in range(n_win)]
+    out = _batched_run(dpt, wins, frames, depths, T_rw, T_prev, n_streams, steps, warmup, n_win, dpt.PREC_FP32)
+    out["mixed_precision"] = _batched_run(dpt, wins, frames, depths, T_rw, T_prev, n_streams, steps, warmup, n_win,
+                                          dpt.PREC_MIXED)
+    out["setup_render_s"] = round(render_s, 2)
+    return out
+
+
+def _batched_run(dpt, wins, frames, depths, T_rw, T_prev, n_streams, steps, warmup, n_win, precision):
+    import torch
+
+    from paper_2607_16897_amd import autotune
+
+    mixed = precision == dpt.PREC_MIXED
+    prm = dpt.make_params(levels=LEVELS, max_iters=10, huber_k=9.0, step_eps=1e-5, precision=precision)
+    bt = dpt.BatchTracker([CAM] * n_streams, prm, [N_POINTS] * n_streams)
+    stats = {"samples": [], "iters": [], "status": []}
 
     def enqueue(w):
         bt.build_pyramids(dpt.SLOT_REF, frames[w][0])
@@ -246,15 +257,19 @@ def bench_batched_sequences(dpt, synth, n_streams: int, steps: int, warmup: int,
     bt.set_profiling(False)
     bt.close()
     res = np.concatenate(results)  # (launches, streams)
+    gts = np.stack([np.stack([wins[s][(warmup + st) % n_win]["gts"][j] for s in range(n_streams)])
+                    for st in range(steps) for j in range(1, WINDOW)])
+    errs = [pose_error(np.asarray(T).reshape(4, 4), G) for T, G in
+            zip(res["T_cw"].reshape(-1, 16), gts.reshape(-1, 4, 4))]
     stats["samples"] = list(res["samples"].sum(axis=1))
     stats["iters"] = list(res["iterations"].reshape(-1))
     stats["status"] = list(res["status"].reshape(-1))
     tracked = n_streams * (WINDOW - 1) * steps
     track_ms = prof["track_ms"] / prof["n_track"]
     samp_launch = float(np.mean(stats["samples"]))
-    achieved = samp_launch * BYTES_PER_SAMPLE_F32 / (track_ms * 1e-3) / 1e9
+    achieved = samp_launch * (BYTES_PER_SAMPLE_MIXED if mixed else BYTES_PER_SAMPLE_F32) / (track_ms * 1e-3) / 1e9
     return {"workload": f"{n_streams} independent 752x480 sequences, 2000 points each, 4 levels, sigma=2, "
-                        "keyframe every 10 frames, FP32, tracked together",
+                        f"keyframe every 10 frames, {'mixed precision' if mixed else 'FP32'}, tracked together",
             "value": round(tracked / el, 1), "unit": "frames/s", "samples_per_s": round(sum(stats["samples"]) / el, 1),
             "ms_per_step": round(el * 1e3 / steps, 4), "steps": steps,
             "track_launch_ms": round(track_ms, 5),
@@ -262,9 +277,9 @@ def bench_batched_sequences(dpt, synth, n_streams: int, steps: int, warmup: int,
             "launch": {"mode": mode, "chunk": chunk, "autotune_ms": timings},
             "iterations_per_frame": round(float(np.mean(stats["iters"])), 3),
             "status_counts": {str(k): int(v) for k, v in zip(*np.unique(stats["status"], return_counts=True))},
+            "pose_error_vs_gt": err_summary(errs),
             "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(achieved / HBM_PEAK_GBS, 5), "samples_per_launch": round(samp_launch, 1)},
-            "setup_render_s": round(render_s, 2)}
+                         "frac": round(achieved / HBM_PEAK_GBS, 5), "samples_per_launch": round(samp_launch, 1)}}
 
 
 def bench_batched_mixed(dpt, synth, n_streams: int, n_frames: int, reps: int):
