@@ -73,13 +73,78 @@ __device__ __forceinline__ bool exchange_partials(uint64_t* partials, int chunk,
   return false;
 }
 
+// Polling by the whole workgroup, for streams of more than kPollBatch chunks:
+// thread t reads value t % 32 of chunks c = t / 32 (mod blockDim / 32 groups),
+// four loads in flight, and sums them in chunk order; the groups' sums meet in
+// LDS (sh_grp, blockDim floats) and are added in group order, a fixed order
+// shared by every chunk of the stream.  All threads; false on timeout.
+template <bool KAHAN, int NV>
+__device__ __forceinline__ bool exchange_wide(const uint64_t* partials, int nch, uint32_t tag, int spin_limit,
+                                              float* sh_grp, float* sh_tot) {
+  const int t = threadIdx.x, v = t & 31, q = t >> 5, G = blockDim.x >> 5;
+  const uint64_t* buf = partials + (size_t)(tag & 1u) * nch * 32;
+  const uint64_t hi = (uint64_t)tag << 32;
+  float s = 0.0f, comp = 0.0f;
+  bool ok = true;
+  if (v < NV) {
+    ok = false;
+    for (int it = 0; it < spin_limit && !ok; ++it) {
+      s = 0.0f, comp = 0.0f;
+      ok = true;
+      for (int c0 = q; c0 < nch; c0 += 4 * G) {
+        uint64_t w[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int c = c0 + j * G;
+          w[j] = c < nch ? __hip_atomic_load(&buf[c * 32 + v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : hi;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (c0 + j * G >= nch) break;
+          ok &= (uint32_t)(w[j] >> 32) == tag;
+          const float x = __uint_as_float((uint32_t)w[j]);
+          if (KAHAN) {
+            const float y = x - comp;
+            const float u = s + y;
+            comp = (u - s) - y;
+            s = u;
+          } else {
+            s += x;
+          }
+        }
+      }
+      if (!ok) __builtin_amdgcn_s_sleep(1);
+    }
+    sh_grp[q * NV + v] = s;
+  }
+  const int bad = __syncthreads_or(!ok);
+  if (t < NV) {
+    float tot = 0.0f, c2 = 0.0f;
+    for (int g = 0; g < G; ++g) {
+      const float x = sh_grp[g * NV + t];
+      if (KAHAN) {
+        const float y = x - c2;
+        const float u = tot + y;
+        c2 = (u - tot) - y;
+        tot = u;
+      } else {
+        tot += x;
+      }
+    }
+    sh_tot[t] = tot;
+  }
+  return bad == 0;
+}
+
 // Block sum of acc[NV] (after each thread accumulated its point), exchanged
 // across the stream's chunks; the totals land in sh_tot.  Returns false on
-// timeout (same value in every thread).  NV = 32 or 16.
-template <bool KAHAN, int NV>
+// timeout (same value in every thread).  NV = 32 or 16.  WIDE: streams of
+// more than kPollBatch chunks are polled by the whole workgroup (exchange_wide,
+// sh_grp: blockDim floats of LDS); otherwise wave 0 polls alone.
+template <bool KAHAN, int NV, bool WIDE>
 __device__ __forceinline__ bool stream_total(float (&acc)[NV], float* sh_red, float* sh_tot, int* sh_ok,
                                              uint64_t* partials, int chunk, int nch, uint32_t tag,
-                                             int spin_limit) {
+                                             int spin_limit, float* sh_grp) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   constexpr int PER_ROW = NV / 4;  // values per 16-lane row after the wave reduction
   if constexpr (NV == 32)
@@ -106,11 +171,22 @@ __device__ __forceinline__ bool stream_total(float (&acc)[NV], float* sh_red, fl
         }
       }
     }
-    float tot = s;
-    bool ok = true;
-    if (nch > 1) ok = exchange_partials<KAHAN, NV>(partials, chunk, nch, tag, s, spin_limit, &tot);
-    if (lane < NV) sh_tot[lane] = tot;
-    if (lane == 0) *sh_ok = ok ? 1 : 0;
+    if (WIDE && nch > kPollBatch) {  // publish; the whole workgroup polls below
+      if (lane < NV)
+        __hip_atomic_store(&partials[(size_t)(tag & 1u) * nch * 32 + chunk * 32 + lane],
+                           ((uint64_t)tag << 32) | __float_as_uint(s), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      float tot = s;
+      bool ok = true;
+      if (nch > 1) ok = exchange_partials<KAHAN, NV>(partials, chunk, nch, tag, s, spin_limit, &tot);
+      if (lane < NV) sh_tot[lane] = tot;
+      if (lane == 0) *sh_ok = ok ? 1 : 0;
+    }
+  }
+  if (WIDE && nch > kPollBatch) {
+    const bool ok = exchange_wide<KAHAN, NV>(partials, nch, tag, spin_limit, sh_grp, sh_tot);
+    __syncthreads();
+    return ok;
   }
   __syncthreads();
   return *sh_ok != 0;
@@ -191,6 +267,7 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
   __shared__ double sh_T0[12], sh_rw[12], sh_h0[12], sh_h1[12], sh_m1[12], sh_m2[12];
   __shared__ float sh_tot[32];
   __shared__ float sh_red[(CH / 64) * 32];
+  __shared__ float sh_grp[GENERIC ? CH : 1];  // the whole-workgroup exchange of many-chunk streams
   __shared__ int sh_ok;
   const int2 w = work[blockIdx.x];
   if (w.x < 0) return;  // padding slot of the XCD-aware work list
@@ -247,7 +324,7 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
         accumulate_point_generic<false, PIX, NV>(a, a.pat, g, img, T, pr, sub, acc);
       else
         accumulate_point<false, true, PR, NV>(a, pregs, g, img, T, pr, acc);
-      if (!stream_total<MIXED, NV>(acc, sh_red, sh_tot, &sh_ok, ss.partials, chunk, nch, tag, spin_limit)) {
+      if (!stream_total<MIXED, NV, GENERIC>(acc, sh_red, sh_tot, &sh_ok, ss.partials, chunk, nch, tag, spin_limit, sh_grp)) {
         timed_out = stop = true;
         break;
       }
@@ -303,7 +380,7 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
       load_point(a, 0, i, pr);
       accumulate_point<true, true, PR, NV>(a, pregs, g, a.cur + g.off, T, pr, acc);
     }
-    if (!stream_total<MIXED, NV>(acc, sh_red, sh_tot, &sh_ok, ss.partials, chunk, nch, tag, spin_limit))
+    if (!stream_total<MIXED, NV, GENERIC>(acc, sh_red, sh_tot, &sh_ok, ss.partials, chunk, nch, tag, spin_limit, sh_grp))
       timed_out = true;
   }
   if (chunk == 0 && threadIdx.x == 0) {
