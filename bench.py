@@ -639,6 +639,29 @@ def pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, kernel="co
 COPY_MIB = 256
 
 
+def attainable_copy_gbs(mib: int = 1024, reps: int = 10) -> float:
+    """Measured attainable HBM bandwidth: a plain device-to-device copy of `mib`
+    MiB timed with events, bytes read plus bytes written per second (GB/s)."""
+    import torch
+
+    n = mib << 20
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def calibrate_copy(mib: int):
     """A plain device copy of known size, for scaling FETCH_SIZE / WRITE_SIZE."""
     import torch
@@ -715,6 +738,7 @@ def main():
     alg_bytes = samp_launch * BYTES_PER_SAMPLE_F32
     achieved = alg_bytes / (track_ms * 1e-3) / 1e9
     kname = f"coop_track_kernel<{args.chunk}, false, false, false, unsigned char>"
+    att_gbs = attainable_copy_gbs()  # after the timed region
     out = {
         "metric": METRIC,
         "value": round(tracked / elapsed, 2),
@@ -737,6 +761,7 @@ def main():
         "roofline": {"kernel": kname, "bound": "hbm", "achieved": round(achieved, 3),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
                      "traffic": traffic_from_profile(),
+                     "attainable_copy": round(att_gbs, 1), "frac_of_attainable": round(achieved / att_gbs, 6),
                      "bytes_per_launch_algorithmic": round(alg_bytes, 1), "samples_per_launch": round(samp_launch, 1),
                      "avg_launch_ms": round(track_ms, 5),
                      "note": "one launch tracks one frame; a single stream is latency-bound by its ~16 dependent "
