@@ -17,8 +17,9 @@
  *     Pixel centres sit at integer coordinates.
  *   - The caller owns every input buffer; it is only borrowed for the duration
  *     of the call.  A context copies what it keeps into device memory it owns.
- *   - "on_device" flags say whether a pointer is device memory (HIP) or host
- *     memory.  Device inputs must stay valid until the call returns.
+ *   - "on_device" flags say whether a pointer is device memory (1, HIP) or host
+ *     memory (0); any other value is DPT_E_ARG.  Device inputs must stay valid
+ *     until the call returns.
  *   - All GPU work of a context is ordered on the HIP stream given at creation
  *     (NULL = the null stream).  Calls that return host results synchronise that
  *     stream before returning.

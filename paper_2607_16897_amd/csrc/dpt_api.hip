@@ -460,6 +460,7 @@ void dpt_destroy(dpt_ctx* ctx) {
 int dpt_build_pyramid(dpt_ctx* c, int32_t slot, const uint8_t* img, int64_t pitch, int32_t img_on_device) {
   g_err.clear();
   if (!c || !img) return fail(DPT_E_ARG, "NULL argument");
+  if (img_on_device != 0 && img_on_device != 1) return fail(DPT_E_ARG, "img_on_device %d is neither 0 nor 1", img_on_device);
   if (slot != DPT_SLOT_REF && slot != DPT_SLOT_CUR) return fail(DPT_E_ARG, "slot %d", slot);
   if (pitch < c->cam.width) return fail(DPT_E_ARG, "pitch %lld < width %d", (long long)pitch, c->cam.width);
   const uint8_t* src = img;
@@ -582,6 +583,7 @@ extern "C" {
 
 int dpt_set_reference_points(dpt_ctx* c, const float* xyz, int32_t n, const double T_rw[16], int32_t on_device) {
   g_err.clear();
+  if (on_device != 0 && on_device != 1) return fail(DPT_E_ARG, "xyz_on_device %d is neither 0 nor 1", on_device);
   if (!c || !T_rw || (n > 0 && !xyz)) return fail(DPT_E_ARG, "NULL argument");
   if (n < 0 || n > c->cap) return fail(DPT_E_ARG, "n %d outside [0, %d]", n, c->cap);
   if (!finite16(T_rw)) return fail(DPT_E_ARG, "T_rw not finite");
@@ -603,6 +605,8 @@ int dpt_set_reference_points(dpt_ctx* c, const float* xyz, int32_t n, const doub
 int dpt_set_reference_from_depth(dpt_ctx* c, int32_t n, int32_t margin, const float* depth, int64_t depth_pitch,
                                  int32_t depth_on_device, const double T_rw[16]) {
   g_err.clear();
+  if (depth_on_device != 0 && depth_on_device != 1)
+    return fail(DPT_E_ARG, "depth_on_device %d is neither 0 nor 1", depth_on_device);
   if (!c || !depth || !T_rw) return fail(DPT_E_ARG, "NULL argument");
   if (n < 1 || n > c->cap) return fail(DPT_E_ARG, "n %d outside [1, %d]", n, c->cap);
   if (margin < 1 || 2 * margin >= c->cam.width || 2 * margin >= c->cam.height) return fail(DPT_E_ARG, "margin %d", margin);
@@ -1310,6 +1314,7 @@ void dpt_batch_destroy(dpt_batch* b) { delete b; }
 int dpt_batch_build_pyramids(dpt_batch* b, int32_t slot, const uint8_t* const* imgs, const int64_t* pitches,
                              int32_t on_device) {
   g_err.clear();
+  if (on_device != 0 && on_device != 1) return fail(DPT_E_ARG, "on_device %d is neither 0 nor 1", on_device);
   if (!b || !imgs || !pitches) return fail(DPT_E_ARG, "NULL argument");
   if (slot != DPT_SLOT_REF && slot != DPT_SLOT_CUR) return fail(DPT_E_ARG, "slot %d", slot);
   // alternate job tables: the one written now was uploaded two calls ago
@@ -1644,6 +1649,7 @@ int dpt_cnn_predict_batch(dpt_cnn* cnn, dpt_batch* b, double* T_cw_out) {
 }  // extern "C"
 
 extern "C" int dpt_batch_get_level(dpt_batch* b, int32_t slot, int32_t level, uint8_t* dst, int32_t dst_on_device) {
+  if (dst_on_device != 0 && dst_on_device != 1) return fail(DPT_E_ARG, "dst_on_device %d is neither 0 nor 1", dst_on_device);
   g_err.clear();
   if (!b || !dst) return fail(DPT_E_ARG, "NULL argument");
   if (slot != DPT_SLOT_REF && slot != DPT_SLOT_CUR) return fail(DPT_E_ARG, "slot %d", slot);
