@@ -1342,7 +1342,10 @@ int dpt_batch_build_pyramids(dpt_batch* b, int32_t slot, const uint8_t* const* i
     j.dst = c->pyr[slot];
     j.g = c->pg;
     j.vec4 = ((sp % 4) == 0 && (reinterpret_cast<uintptr_t>(src) % 4) == 0 && (c->pg.W[0] % 4) == 0) ? 1 : 0;
-    j.pad = 0;
+    j.vec16 = ((sp % 16) == 0 && (reinterpret_cast<uintptr_t>(src) % 16) == 0 && (c->pg.W[0] % 16) == 0 &&
+               (reinterpret_cast<uintptr_t>(c->pyr[slot]) % 16) == 0)
+                  ? 1
+                  : 0;
     max_w = std::max(max_w, c->cam.width);
     max_h = std::max(max_h, c->cam.height);
   }

@@ -668,14 +668,14 @@ template <int TILE>
 __global__ __launch_bounds__(256) void pyramid_batch_kernel(const PyrJob* __restrict__ jobs) {
   const PyrJob& j = jobs[blockIdx.z];
   if ((int)blockIdx.x * TILE >= j.g.W[0] || (int)blockIdx.y * TILE >= j.g.H[0]) return;
-  pyramid_tile<TILE>(j.src, j.pitch, j.dst, j.g, j.vec4);
+  if (TILE == 64 && j.vec16)
+    pyramid_tile64v(j.src, j.pitch, j.dst, j.g);
+  else
+    pyramid_tile<TILE>(j.src, j.pitch, j.dst, j.g, j.vec4);
 }
 
 hipError_t launch_pyramid_batch(const PyrJob* d_jobs, int n_jobs, int max_w, int max_h, int levels, hipStream_t s) {
-  if (levels <= 6)
-    hipLaunchKernelGGL(pyramid_batch_kernel<32>, dim3((max_w + 31) / 32, (max_h + 31) / 32, n_jobs), dim3(256), 0, s,
-                       d_jobs);
-  else if (levels == 7)
+  if (levels <= 7)
     hipLaunchKernelGGL(pyramid_batch_kernel<64>, dim3((max_w + 63) / 64, (max_h + 63) / 64, n_jobs), dim3(256), 0, s,
                        d_jobs);
   else

@@ -147,6 +147,72 @@ __device__ __forceinline__ void pyramid_tile(const uint8_t* __restrict__ src, in
   }
 }
 
+// pyramid_tile for 64x64 tiles of frames whose width, pitch and base address
+// are multiples of 16: one 16-byte load and store per thread for level 0 (256
+// threads), four level-1 pixels per thread from two 8-byte LDS reads with one
+// 4-byte store, then the coarser levels as pyramid_tile.  Up to 7 levels.
+__device__ __forceinline__ void pyramid_tile64v(const uint8_t* __restrict__ src, int64_t pitch,
+                                                uint8_t* __restrict__ dst, const PyrGeom& g) {
+  __shared__ __align__(16) uint8_t buf0[64 * 64];
+  __shared__ __align__(16) uint8_t buf1[32 * 32];
+  const int ox = blockIdx.x * 64, oy = blockIdx.y * 64;
+  const int W0 = g.W[0], H0 = g.H[0];
+  {
+    const int r = threadIdx.x >> 2, c = (threadIdx.x & 3) * 16;
+    const int gx = ox + c, gy = oy + r;
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (gy < H0 && gx < W0) {  // W0 % 16 == 0: the 16 bytes lie inside the row
+      v = *reinterpret_cast<const uint4*>(src + gy * pitch + gx);
+      *reinterpret_cast<uint4*>(dst + g.off[0] + (int64_t)gy * W0 + gx) = v;
+    }
+    *reinterpret_cast<uint4*>(buf0 + r * 64 + c) = v;
+  }
+  __syncthreads();
+  if (g.levels < 2) return;
+  {
+    const int r = threadIdx.x >> 3, c = (threadIdx.x & 7) * 4;
+    const uint2 a = *reinterpret_cast<const uint2*>(buf0 + (2 * r) * 64 + 2 * c);
+    const uint2 b = *reinterpret_cast<const uint2*>(buf0 + (2 * r + 1) * 64 + 2 * c);
+    const uint32_t top[2] = {a.x, a.y}, bot[2] = {b.x, b.y};
+    uint32_t out = 0u;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t t = top[j >> 1] >> (16 * (j & 1)), u = bot[j >> 1] >> (16 * (j & 1));
+      const uint32_t s4 = (t & 0xffu) + ((t >> 8) & 0xffu) + (u & 0xffu) + ((u >> 8) & 0xffu);
+      out |= ((s4 + 2u) >> 2) << (8 * j);
+    }
+    *reinterpret_cast<uint32_t*>(buf1 + r * 32 + c) = out;
+    const int W1 = g.W[1], H1 = g.H[1];
+    const int gx = (ox >> 1) + c, gy = (oy >> 1) + r;
+    if (gy < H1 && gx < W1)  // W1 % 8 == 0 and gx % 4 == 0: all four pixels are inside
+      *reinterpret_cast<uint32_t*>(dst + g.off[1] + (int64_t)gy * W1 + gx) = out;
+  }
+  __syncthreads();
+  uint8_t* prev = buf1;
+  uint8_t* next = buf0;
+  for (int l = 2; l < g.levels; ++l) {
+    const int T = 64 >> l, Tp = 64 >> (l - 1);
+    const int Wl = g.W[l], Hl = g.H[l];
+    const int oxl = ox >> l, oyl = oy >> l;
+    for (int q = threadIdx.x; q < T * T; q += blockDim.x) {
+      const int ly = q / T, lx = q % T;
+      const int gx = oxl + lx, gy = oyl + ly;
+      uint8_t v = 0;
+      if (gx < Wl && gy < Hl) {
+        const uint8_t* p = prev + (2 * ly) * Tp + 2 * lx;
+        const int s4 = (int)p[0] + (int)p[1] + (int)p[Tp] + (int)p[Tp + 1];
+        v = (uint8_t)((s4 + 2) >> 2);
+        dst[g.off[l] + (int64_t)gy * Wl + gx] = v;
+      }
+      next[q] = v;
+    }
+    __syncthreads();
+    uint8_t* t = prev;
+    prev = next;
+    next = t;
+  }
+}
+
 // ---------------------------------------------------------------- block scans / reductions
 
 // Exclusive prefix sum of one int per thread over a 1024-thread workgroup.

@@ -192,8 +192,8 @@ struct PyrJob {
   int64_t pitch;
   uint8_t* dst;
   PyrGeom g;
-  int32_t vec4;
-  int32_t pad;
+  int32_t vec4;   // width, pitch and addresses multiples of 4
+  int32_t vec16;  // ... of 16 (pyramid_tile64v)
 };
 
 // Variants of the cooperative track kernel.

@@ -20,12 +20,22 @@ __global__ __launch_bounds__(256) void pyramid_kernel(const uint8_t* __restrict_
   pyramid_tile<TILE>(src, pitch, dst, g, vec4);
 }
 
+__global__ __launch_bounds__(256) void pyramid64v_kernel(const uint8_t* __restrict__ src, int64_t pitch,
+                                                         uint8_t* __restrict__ dst, PyrGeom g) {
+  pyramid_tile64v(src, pitch, dst, g);
+}
+
 hipError_t launch_pyramid(const uint8_t* src, int64_t pitch, uint8_t* dst, const PyrGeom& g, hipStream_t s) {
   int vec4 = ((pitch % 4) == 0 && (reinterpret_cast<uintptr_t>(src) % 4) == 0 && (g.W[0] % 4) == 0 &&
               (reinterpret_cast<uintptr_t>(dst) % 4) == 0)
                  ? 1
                  : 0;
-  if (g.levels <= 6) {
+  const bool vec16 = (pitch % 16) == 0 && (reinterpret_cast<uintptr_t>(src) % 16) == 0 && (g.W[0] % 16) == 0 &&
+                     (reinterpret_cast<uintptr_t>(dst) % 16) == 0;
+  if (vec16 && g.levels <= 7) {
+    dim3 grid((g.W[0] + 63) / 64, (g.H[0] + 63) / 64);
+    hipLaunchKernelGGL(pyramid64v_kernel, grid, dim3(256), 0, s, src, pitch, dst, g);
+  } else if (g.levels <= 6) {
     dim3 grid((g.W[0] + 31) / 32, (g.H[0] + 31) / 32);
     hipLaunchKernelGGL(pyramid_kernel<32>, grid, dim3(256), 0, s, src, pitch, dst, g, vec4);
   } else if (g.levels == 7) {
