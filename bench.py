@@ -117,6 +117,10 @@ def new_stats():
 
 
 SYNC_EVERY = 6  # windows in flight between synchronisations (6 x 9 tracks fit the 64-slot ring)
+# Launches between two timed ones in the timed region: each HIP event record is a
+# queue marker that holds the next kernel for several microseconds, so timing
+# every launch would slow the stream by ~20 us per frame.
+PROFILE_EVERY = 8
 
 
 def enqueue_window(dpt, trk, win, dev, n_points):
@@ -167,7 +171,7 @@ def timed_plain(dpt, synth, wins, dev, steps, warmup, prm, launch, chunk, n_poin
     for w in range(warmup):
         enqueue_window(dpt, trk, wins[w % n], dev[w % n], n_points)
     trk.synchronize()
-    trk.set_profiling(True)
+    trk.set_profiling(True, every=PROFILE_EVERY)
     stats = new_stats()
     done, results = [], []
     torch.cuda.synchronize()
@@ -242,7 +246,7 @@ def _batched_run(dpt, wins, frames, depths, T_rw, T_prev, n_streams, steps, warm
     for w in range(warmup):
         enqueue(w % n_win)
     bt.synchronize()
-    bt.set_profiling(True)
+    bt.set_profiling(True, every=PROFILE_EVERY)
     results = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -312,7 +316,7 @@ def bench_batched_mixed(dpt, synth, n_streams: int, n_frames: int, reps: int):
     key = autotune.shape_key(cams, npts, 3, 8)
     mode, chunk, timings = autotune.tune(bt, I, key, cache=None)
     batched_T, samples, ms = [], 0, []
-    bt.set_profiling(True)
+    bt.set_profiling(True, every=PROFILE_EVERY)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for r in range(reps):

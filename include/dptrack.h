@@ -296,13 +296,15 @@ int dpt_get_fixed_hessian(dpt_ctx* ctx, int32_t level, double H36[36], int32_t* 
 enum { DPT_LAUNCH_AUTO = 0, DPT_LAUNCH_WORKGROUP = 1, DPT_LAUNCH_COOP = 2 };
 int dpt_set_launch_config(dpt_ctx* ctx, int32_t mode, int32_t chunk);
 
-/* Profiling hook: when enabled, pyramid builds and tracks bracket their
- * kernels with HIP events on the context's stream.  dpt_last_kernel_ms
- * returns the durations (ms) of the most recent pyramid and track kernels (-1
- * if none was timed); dpt_get_profile the totals (ms) and counts since
- * profiling was enabled.  Both synchronise the context.  Off by default;
- * enabling it (which also synchronises and resets the totals) adds two event
- * records per launch. */
+/* Profiling hook: with enable = N > 0, every N-th pyramid build and every
+ * N-th track brackets its kernel with HIP events on the context's stream
+ * (each event record is a queue marker of a few microseconds, so N > 1 keeps
+ * the measurement from slowing the stream much); 0 switches it off (the
+ * default), < 0 is DPT_E_ARG.  dpt_last_kernel_ms returns the durations (ms)
+ * of the most recent timed pyramid and track kernels (-1 if none was timed);
+ * dpt_get_profile the totals (ms) and counts of the timed launches since
+ * profiling was enabled.  Both synchronise the context; so does enabling,
+ * which also resets the totals. */
 int dpt_set_profiling(dpt_ctx* ctx, int32_t enable);
 int dpt_last_kernel_ms(dpt_ctx* ctx, float* pyramid_ms, float* track_ms);
 int dpt_get_profile(dpt_ctx* ctx, double* pyramid_ms, int64_t* n_pyramid, double* track_ms, int64_t* n_track);

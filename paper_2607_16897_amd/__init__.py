@@ -338,8 +338,9 @@ class Tracker:
     def set_launch_config(self, mode: int, chunk: int = 256):
         _check(self._lib.dpt_set_launch_config(self._h, mode, chunk))
 
-    def set_profiling(self, enable: bool = True):
-        _check(self._lib.dpt_set_profiling(self._h, int(enable)))
+    def set_profiling(self, enable: bool = True, every: int = 1):
+        """Time every `every`-th pyramid and track launch with HIP events (off: enable=False)."""
+        _check(self._lib.dpt_set_profiling(self._h, int(every) if enable else 0))
 
     def last_kernel_ms(self):
         """(pyramid_ms, track_ms) of the most recent timed kernels (-1 if none)."""
@@ -530,8 +531,9 @@ class BatchTracker:
         _check(self._lib.dpt_batch_get_level(self._h, slot, level, dst.data_ptr(), 1))
         return dst
 
-    def set_profiling(self, enable: bool = True):
-        _check(self._lib.dpt_batch_set_profiling(self._h, int(enable)))
+    def set_profiling(self, enable: bool = True, every: int = 1):
+        """Time every `every`-th batched pyramid and track launch (off: enable=False)."""
+        _check(self._lib.dpt_batch_set_profiling(self._h, int(every) if enable else 0))
 
     def last_kernel_ms(self):
         a, b = ctypes.c_float(), ctypes.c_float()

@@ -129,6 +129,11 @@ struct ProfRing {
   static constexpr int kN = 2 * kRing;
   hipEvent_t ev[kN][2] = {};
   bool created = false;
+  // Only every `every`-th launch is bracketed: each event record is a marker
+  // the queue processes between kernels (several microseconds), so timing
+  // every launch would slow the stream it measures.
+  int every = 1;
+  int64_t tick = 0;
   int next = 0, n_pending = 0;  // pending pairs: the n_pending slots before `next`
   double total_ms = 0.0;
   int64_t count = 0;
@@ -163,6 +168,8 @@ struct ProfRing {
     return hipSuccess;
   }
   hipError_t begin(hipStream_t st, int* slot) {
+    *slot = -1;
+    if (tick++ % every != 0) return hipSuccess;
     if (n_pending == kN) {
       const hipError_t e = drain_one();
       if (e != hipSuccess) return e;
@@ -172,6 +179,7 @@ struct ProfRing {
     return hipEventRecord(ev[*slot][0], st);
   }
   hipError_t end(hipStream_t st, int slot) {
+    if (slot < 0) return hipSuccess;
     ++n_pending;
     return hipEventRecord(ev[slot][1], st);
   }
@@ -182,7 +190,9 @@ struct ProfRing {
     }
     return hipSuccess;
   }
-  void reset() {
+  void reset(int every_ = 1) {
+    every = every_ > 0 ? every_ : 1;
+    tick = 0;
     total_ms = 0.0;
     count = 0;
     last_ms = -1.0f;
@@ -1007,14 +1017,15 @@ int dpt_get_fixed_hessian(dpt_ctx* c, int32_t level, double* H36, int32_t* not_p
 int dpt_set_profiling(dpt_ctx* c, int32_t enable) {
   g_err.clear();
   if (!c) return fail(DPT_E_ARG, "NULL context");
+  if (enable < 0) return fail(DPT_E_ARG, "enable %d < 0", enable);
   int e = synchronize(c);
   if (e != DPT_OK) return e;
   if (enable) {
     HIP_TRY(c->prof_pyr.create());
     HIP_TRY(c->prof_trk.create());
   }
-  c->prof_pyr.reset();
-  c->prof_trk.reset();
+  c->prof_pyr.reset(enable);
+  c->prof_trk.reset(enable);
   c->prof = enable != 0;
   return DPT_OK;
 }
@@ -1538,14 +1549,15 @@ int dpt_batch_set_launch_config(dpt_batch* b, int32_t mode, int32_t chunk) {
 int dpt_batch_set_profiling(dpt_batch* b, int32_t enable) {
   g_err.clear();
   if (!b) return fail(DPT_E_ARG, "NULL batch");
+  if (enable < 0) return fail(DPT_E_ARG, "enable %d < 0", enable);
   int e = batch_synchronize(b);
   if (e != DPT_OK) return e;
   if (enable) {
     HIP_TRY(b->prof_pyr.create());
     HIP_TRY(b->prof_trk.create());
   }
-  b->prof_pyr.reset();
-  b->prof_trk.reset();
+  b->prof_pyr.reset(enable);
+  b->prof_trk.reset(enable);
   b->prof = enable != 0;
   return DPT_OK;
 }

@@ -210,6 +210,16 @@ def test_workgroup_path_and_profile_counts(gpu_lib):
     p = trk.profile()
     assert p["n_track"] == 3 and p["n_pyramid"] == 3
     assert p["track_ms"] > 0 and p["pyramid_ms"] > 0
+    trk.set_profiling(True, every=4)  # launches 0, 4, 8 of the next 10 are timed
+    for _ in range(10):
+        trk.build_pyramid(dpt.SLOT_CUR, d["cur"])
+        trk.track_enqueue(np.eye(4))
+    trk.synchronize()
+    p = trk.profile()
+    assert p["n_track"] == 3 and p["n_pyramid"] == 3
+    assert p["track_ms"] > 0
+    with pytest.raises(dpt.DptError):
+        trk.set_profiling(True, every=-1)
 
 
 def test_batch_reference_update_all_equals_per_stream(gpu_lib):
