@@ -1070,6 +1070,7 @@ struct dpt_batch {
   PyrJob* h_jobs = nullptr;  // pinned, two tables
   hipEvent_t ev_jobs[2] = {nullptr, nullptr};  // each table's last upload
   int jobs_next = 0;
+  PyrJob* d_static[2] = {nullptr, nullptr};  // per slot: destinations and geometry (n <= kPyrArgJobs)
   // one-workgroup-per-stream launch
   TrackArgs* d_args = nullptr;
   TrackArgs* h_args = nullptr;  // pinned
@@ -1106,6 +1107,8 @@ struct dpt_batch {
     for (hipEvent_t e : ev_jobs)
       if (e) (void)hipEventDestroy(e);
     if (d_jobs) (void)hipFree(d_jobs);
+    for (PyrJob* p : d_static)
+      if (p) (void)hipFree(p);
     if (d_args) (void)hipFree(d_args);
     if (d_outs) (void)hipFree(d_outs);
     if (h_jobs) (void)hipHostFree(h_jobs);
@@ -1307,6 +1310,22 @@ int dpt_batch_create(int32_t n_streams, const dpt_camera* cams, const dpt_params
     delete b;
     return fail(DPT_E_OOM, "batch allocation failed");
   }
+  if (n_streams <= kPyrArgJobs) {  // the static pyramid tables: sources go in the kernel arguments
+    std::vector<PyrJob> t(n_streams);
+    for (int slot = 0; slot < 2; ++slot) {
+      for (int s = 0; s < n_streams; ++s) {
+        std::memset(&t[s], 0, sizeof t[s]);
+        t[s].dst = b->ctx[s]->pyr[slot];
+        t[s].g = b->ctx[s]->pg;
+      }
+      if (hipMalloc(&b->d_static[slot], sizeof(PyrJob) * n_streams) != hipSuccess ||
+          hipMemcpy(b->d_static[slot], t.data(), sizeof(PyrJob) * n_streams, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        delete b;
+        return fail(DPT_E_OOM, "batch allocation failed");
+      }
+    }
+  }
   {
     std::vector<double*> hp(n_streams);
     for (int s = 0; s < n_streams; ++s) hp[s] = b->ctx[s]->d_hist;
@@ -1328,6 +1347,36 @@ int dpt_batch_build_pyramids(dpt_batch* b, int32_t slot, const uint8_t* const* i
   if (on_device != 0 && on_device != 1) return fail(DPT_E_ARG, "on_device %d is neither 0 nor 1", on_device);
   if (!b || !imgs || !pitches) return fail(DPT_E_ARG, "NULL argument");
   if (slot != DPT_SLOT_REF && slot != DPT_SLOT_CUR) return fail(DPT_E_ARG, "slot %d", slot);
+  if (b->d_static[slot] && !b->ctx[0]->pyrf[slot]) {  // sources by value: no table upload
+    PyrSrcArgs srcs;
+    std::memset(&srcs, 0, sizeof srcs);
+    int max_w = 0, max_h = 0;
+    for (int s = 0; s < b->n; ++s) {
+      dpt_ctx* c = b->ctx[s];
+      if (!imgs[s]) return fail(DPT_E_ARG, "image %d is NULL", s);
+      if (pitches[s] < c->cam.width) return fail(DPT_E_ARG, "stream %d: pitch < width", s);
+      srcs.src[s] = imgs[s];
+      srcs.pitch[s] = pitches[s];
+      if (!on_device) {
+        HIP_TRY(hipMemcpy2DAsync(c->staging, c->cam.width, imgs[s], pitches[s], c->cam.width, c->cam.height,
+                                 hipMemcpyHostToDevice, b->stream));
+        srcs.src[s] = c->staging;
+        srcs.pitch[s] = c->cam.width;
+      }
+      max_w = std::max(max_w, c->cam.width);
+      max_h = std::max(max_h, c->cam.height);
+    }
+    int ps = -1;
+    if (b->prof) HIP_TRY(b->prof_pyr.begin(b->stream, &ps));
+    HIP_TRY(launch_pyramid_batch_args(b->d_static[slot], srcs, b->n, max_w, max_h, b->ctx[0]->prm.levels, b->stream));
+    if (b->prof) HIP_TRY(b->prof_pyr.end(b->stream, ps));
+    if (!on_device) HIP_TRY(hipStreamSynchronize(b->stream));  // the host images are only borrowed
+    for (int s = 0; s < b->n; ++s) {
+      b->ctx[s]->have_pyr[slot] = true;
+      if (slot == DPT_SLOT_REF) b->ctx[s]->have_ref = false;
+    }
+    return DPT_OK;
+  }
   // alternate job tables: the one written now was uploaded two calls ago
   const int jt = b->jobs_next;
   b->jobs_next ^= 1;

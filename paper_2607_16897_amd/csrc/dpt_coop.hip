@@ -674,6 +674,36 @@ __global__ __launch_bounds__(256) void pyramid_batch_kernel(const PyrJob* __rest
     pyramid_tile<TILE>(j.src, j.pitch, j.dst, j.g, j.vec4);
 }
 
+// As pyramid_batch_kernel, with job z's source and pitch taken from the kernel
+// arguments (no table upload per call) and the vector paths chosen here.
+template <int TILE>
+__global__ __launch_bounds__(256) void pyramid_batch_args_kernel(const PyrJob* __restrict__ jobs, PyrSrcArgs srcs) {
+  const int z = blockIdx.z;
+  const PyrJob& j = jobs[z];
+  if ((int)blockIdx.x * TILE >= j.g.W[0] || (int)blockIdx.y * TILE >= j.g.H[0]) return;
+  const uint8_t* src = srcs.src[z];
+  const int64_t pitch = srcs.pitch[z];
+  const uintptr_t sa = reinterpret_cast<uintptr_t>(src), da = reinterpret_cast<uintptr_t>(j.dst);
+  const int W0 = j.g.W[0];
+  if (TILE == 64 && (pitch % 16) == 0 && (sa % 16) == 0 && (W0 % 16) == 0 && (da % 16) == 0)
+    pyramid_tile64v(src, pitch, j.dst, j.g);
+  else
+    pyramid_tile<TILE>(src, pitch, j.dst, j.g,
+                       ((pitch % 4) == 0 && (sa % 4) == 0 && (W0 % 4) == 0 && (da % 4) == 0) ? 1 : 0);
+}
+
+hipError_t launch_pyramid_batch_args(const PyrJob* d_static, const PyrSrcArgs& srcs, int n_jobs, int max_w,
+                                     int max_h, int levels, hipStream_t s) {
+  if (n_jobs > kPyrArgJobs) return hipErrorInvalidValue;
+  if (levels <= 7)
+    hipLaunchKernelGGL(pyramid_batch_args_kernel<64>, dim3((max_w + 63) / 64, (max_h + 63) / 64, n_jobs), dim3(256),
+                       0, s, d_static, srcs);
+  else
+    hipLaunchKernelGGL(pyramid_batch_args_kernel<128>, dim3((max_w + 127) / 128, (max_h + 127) / 128, n_jobs),
+                       dim3(256), 0, s, d_static, srcs);
+  return hipGetLastError();
+}
+
 hipError_t launch_pyramid_batch(const PyrJob* d_jobs, int n_jobs, int max_w, int max_h, int levels, hipStream_t s) {
   if (levels <= 7)
     hipLaunchKernelGGL(pyramid_batch_kernel<64>, dim3((max_w + 63) / 64, (max_h + 63) / 64, n_jobs), dim3(256), 0, s,

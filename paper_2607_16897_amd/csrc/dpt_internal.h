@@ -285,5 +285,14 @@ hipError_t launch_set_history(double* hist, const double* T0, const double* T1, 
 hipError_t launch_set_history_batch(double* const* d_hists, const double* d_vals, int n, hipStream_t s);
 int coop_max_blocks(int chunk);  // co-resident workgroups of a cooperative launch (0 if unsupported)
 hipError_t launch_pyramid_batch(const PyrJob* d_jobs, int n_jobs, int max_w, int max_h, int levels, hipStream_t s);
+// Up to kPyrArgJobs images whose sources travel in the kernel arguments; the
+// device table holds each job's destination and geometry (src, pitch unused).
+constexpr int kPyrArgJobs = 64;
+struct PyrSrcArgs {
+  const uint8_t* src[kPyrArgJobs];
+  int64_t pitch[kPyrArgJobs];
+};
+hipError_t launch_pyramid_batch_args(const PyrJob* d_static, const PyrSrcArgs& srcs, int n_jobs, int max_w,
+                                     int max_h, int levels, hipStream_t s);
 
 }  // namespace dpt
