@@ -101,10 +101,15 @@ def make_windows(n_windows: int, seed: int = 2607, cam=None):
 
 
 def to_device(wins):
-    """Frames and keyframe depth of every window as device tensors."""
+    """Frames and keyframe depth of every window as device tensors: the frames of
+    a window in one [10, H, W] tensor (keyframe first), handed out as views."""
     import torch
 
-    return [([torch.from_numpy(im).cuda() for im in w["imgs"]], torch.from_numpy(w["depth"]).cuda()) for w in wins]
+    out = []
+    for w in wins:
+        stack = torch.from_numpy(np.stack(w["imgs"])).cuda()
+        out.append(([stack[j] for j in range(len(w["imgs"]))], torch.from_numpy(w["depth"]).cuda(), stack))
+    return out
 
 
 def cv_init(prev2, prev1):
@@ -116,24 +121,31 @@ def new_stats():
     return {k: [] for k in ("samples", "iters", "status", "T", "init", "gt")}
 
 
-SYNC_EVERY = 6  # windows in flight between synchronisations (6 x 9 tracks fit the 64-slot ring)
+SYNC_EVERY = 24  # windows enqueued between synchronisations (24 x 9 tracks fit the 256-slot ring)
 # Launches between two timed ones in the timed region: each HIP event record is a
 # queue marker that holds the next kernel for several microseconds, so timing
 # every launch would slow the stream by ~20 us per frame.
 PROFILE_EVERY = 8
+PROFILE_EVERY_WINDOW = 4  # window tracks: one launch per 9 frames
 
 
-def enqueue_window(dpt, trk, win, dev, n_points):
+def enqueue_window(dpt, trk, win, dev, n_points, window=True):
     """One keyframe window, enqueued without waiting: the reference refresh
     (pyramid, selection, back-projection from the keyframe's depth and IC
     precompute, all on the device), the pose history (the frame before the
-    keyframe and the keyframe, true poses), then 9 frames each with its
-    pyramid and a track from the constant-velocity prediction, which the GPU
-    computes from the two previous poses.  dev = (device frames, device depth)."""
-    dev_imgs, dev_depth = dev
+    keyframe and the keyframe, true poses), then the 9 tween frames, each
+    tracked from the constant-velocity prediction of the two poses before it
+    (computed on the GPU): window=True in one window track (one pyramid launch
+    for the 9 frames, one track launch), else frame by frame (a pyramid and a
+    track launch per frame).  Both give bitwise the same poses.
+    dev = (device frames, device depth, the window's [10, H, W] frame stack)."""
+    dev_imgs, dev_depth, stack = dev
     trk.build_pyramid(dpt.SLOT_REF, dev_imgs[0])
     trk.set_reference_from_depth(n_points, dev_depth, win["gts"][0])
     trk.set_pose_history(win["T_prev"], win["gts"][0])
+    if window:
+        trk.track_window_enqueue(stack[1:])
+        return
     for j in range(1, WINDOW):
         trk.build_pyramid(dpt.SLOT_CUR, dev_imgs[j])
         trk.track_enqueue(None)
@@ -158,27 +170,29 @@ def collect(results, wins_done, stats):
             stats["gt"].append(win["gts"][j])
 
 
-def timed_plain(dpt, synth, wins, dev, steps, warmup, prm, launch, chunk, n_points=N_POINTS, cam=None):
+def timed_plain(dpt, synth, wins, dev, steps, warmup, prm, launch, chunk, n_points=N_POINTS, cam=None, window=True):
     """warmup + steps keyframe windows through one context, enqueued
-    asynchronously; the first timed window is wins[warmup % len(wins)].  Returns
-    (elapsed s, stats, profile totals of the timed region)."""
+    asynchronously (window tracks, or frame by frame); the first timed window is
+    wins[warmup % len(wins)].  Returns (elapsed s, stats, profile totals of the
+    timed region)."""
     import torch
 
     cam = cam or CAM
     trk = dpt.Tracker(cam, prm, max_points=n_points)
     trk.set_launch_config(launch, chunk)
     n = len(wins)
+    every = PROFILE_EVERY if not window else PROFILE_EVERY_WINDOW
     for w in range(warmup):
-        enqueue_window(dpt, trk, wins[w % n], dev[w % n], n_points)
+        enqueue_window(dpt, trk, wins[w % n], dev[w % n], n_points, window)
     trk.synchronize()
-    trk.set_profiling(True, every=PROFILE_EVERY)
+    trk.set_profiling(True, every=every)
     stats = new_stats()
     done, results = [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(steps):
         w = (warmup + s) % n
-        enqueue_window(dpt, trk, wins[w], dev[w], n_points)
+        enqueue_window(dpt, trk, wins[w], dev[w], n_points, window)
         done.append(wins[w])
         if len(done) % SYNC_EVERY == 0:
             results.append(trk.synchronize(arrays=True))
@@ -186,10 +200,16 @@ def timed_plain(dpt, synth, wins, dev, steps, warmup, prm, launch, chunk, n_poin
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     prof = trk.profile()
+    prof["frames_per_launch"] = WINDOW - 1 if window else 1
     trk.set_profiling(False)
     trk.close()
     collect(np.concatenate(results), done, stats)
     return el, stats, prof
+
+
+def frame_track_ms(prof):
+    """Track kernel time per frame: the average launch over the frames one launch tracks."""
+    return prof["track_ms"] / prof["n_track"] / prof.get("frames_per_launch", 1)
 
 
 # ---------------------------------------------------------------- batched legs
@@ -205,21 +225,35 @@ def bench_batched_sequences(dpt, synth, n_streams: int, steps: int, warmup: int,
     render_s = time.perf_counter() - t_r
     # device layout: per window, one [streams, H, W] uint8 tensor per frame index and
     # one [streams, H, W] float32 depth tensor of the keyframes
-    frames = [[torch.from_numpy(np.stack([wins[s][w]["imgs"][j] for s in range(n_streams)])).cuda()
-               for j in range(WINDOW)] for w in range(n_win)]
+    # [frame index, stream, H, W] per window: a frame index's images are one
+    # [streams, H, W] block, and a stream's frames sit at a constant stride
+    stacks = [torch.from_numpy(np.stack([np.stack([wins[s][w]["imgs"][j] for s in range(n_streams)])
+                                         for j in range(WINDOW)])).cuda() for w in range(n_win)]
+    frames = [[stacks[w][j] for j in range(WINDOW)] for w in range(n_win)]
     depths = [torch.from_numpy(np.stack([wins[s][w]["depth"] for s in range(n_streams)])).cuda()
               for w in range(n_win)]
     torch.cuda.synchronize()
     T_rw = [np.stack([wins[s][w]["gts"][0] for s in range(n_streams)]) for w in range(n_win)]
     T_prev = [np.stack([wins[s][w]["T_prev"] for s in range(n_streams)]) for w in range(n_win)]
-    out = _batched_run(dpt, wins, frames, depths, T_rw, T_prev, n_streams, steps, warmup, n_win, dpt.PREC_FP32)
-    out["mixed_precision"] = _batched_run(dpt, wins, frames, depths, T_rw, T_prev, n_streams, steps, warmup, n_win,
-                                          dpt.PREC_MIXED)
+    wframes = [[stacks[w][1:, s] for s in range(n_streams)] for w in range(n_win)]
+    args = (dpt, wins, frames, wframes, depths, T_rw, T_prev, n_streams, steps, warmup, n_win)
+    out = _batched_run(*args, dpt.PREC_FP32, True)
+    out["frame_by_frame"] = _batched_run(*args, dpt.PREC_FP32, False, out["launch"])
+    out["mixed_precision"] = _batched_run(*args, dpt.PREC_MIXED, True)
+    out["mixed_precision"]["frame_by_frame"] = _batched_run(*args, dpt.PREC_MIXED, False,
+                                                            out["mixed_precision"]["launch"])
+    for o in (out, out["mixed_precision"]):  # the same tuned launch: bitwise the same poses
+        o["poses_bitwise_equal_frame_by_frame"] = bool(np.array_equal(o.pop("poses"), o["frame_by_frame"].pop("poses")))
     out["setup_render_s"] = round(render_s, 2)
     return out
 
 
-def _batched_run(dpt, wins, frames, depths, T_rw, T_prev, n_streams, steps, warmup, n_win, precision):
+def _batched_run(dpt, wins, frames, wframes, depths, T_rw, T_prev, n_streams, steps, warmup, n_win, precision,
+                 window, tuned=None):
+    """One batched leg: window=True tracks each keyframe window's 9 frames of
+    every stream in one window track, else frame by frame (one batched pyramid
+    and track launch per frame).  tuned: the launch an earlier leg's autotuner
+    chose (its "launch" entry), else tune here."""
     import torch
 
     from paper_2607_16897_amd import autotune
@@ -229,20 +263,26 @@ def _batched_run(dpt, wins, frames, depths, T_rw, T_prev, n_streams, steps, warm
     bt = dpt.BatchTracker([CAM] * n_streams, prm, [N_POINTS] * n_streams)
     stats = {"samples": [], "iters": [], "status": []}
 
-    def enqueue(w):
+    def enqueue(w, window=window):
         bt.build_pyramids(dpt.SLOT_REF, frames[w][0])
         bt.set_reference_from_depth_all(N_POINTS, depths[w], T_rw[w])
         bt.set_pose_history_all(T_prev[w], T_rw[w])
+        if window:
+            bt.track_window_enqueue(wframes[w])
+            return
         for j in range(1, WINDOW):
             bt.build_pyramids(dpt.SLOT_CUR, frames[w][j])
             bt.track_enqueue(None)
 
-    # tune on the last frame of the first window, started from the true poses
-    enqueue(0)
-    bt.synchronize()
-    key = autotune.shape_key([CAM] * n_streams, [N_POINTS] * n_streams, LEVELS, 8)
-    mode, chunk, timings = autotune.tune(bt, np.stack([wins[s][0]["gts"][WINDOW - 1] for s in range(n_streams)]),
-                                         key, cache=None, candidates=autotune.COOP_CANDIDATES)
+    if tuned is None:  # tune on the last frame of the first window, started from the true poses
+        enqueue(0, False)
+        bt.synchronize()
+        key = autotune.shape_key([CAM] * n_streams, [N_POINTS] * n_streams, LEVELS, 8)
+        mode, chunk, timings = autotune.tune(bt, np.stack([wins[s][0]["gts"][WINDOW - 1] for s in range(n_streams)]),
+                                             key, cache=None, candidates=autotune.COOP_CANDIDATES)
+    else:
+        mode, chunk, timings = tuned["mode"], tuned["chunk"], tuned["autotune_ms"]
+        bt.set_launch_config(mode, chunk)
     for w in range(warmup):
         enqueue(w % n_win)
     bt.synchronize()
@@ -269,15 +309,18 @@ def _batched_run(dpt, wins, frames, depths, T_rw, T_prev, n_streams, steps, warm
     stats["iters"] = list(res["iterations"].reshape(-1))
     stats["status"] = list(res["status"].reshape(-1))
     tracked = n_streams * (WINDOW - 1) * steps
+    fpl = WINDOW - 1 if window else 1
     track_ms = prof["track_ms"] / prof["n_track"]
-    samp_launch = float(np.mean(stats["samples"]))
+    samp_launch = float(np.mean(stats["samples"])) * fpl
     achieved = samp_launch * (BYTES_PER_SAMPLE_MIXED if mixed else BYTES_PER_SAMPLE_F32) / (track_ms * 1e-3) / 1e9
     return {"workload": f"{n_streams} independent 752x480 sequences, 2000 points each, 4 levels, sigma=2, "
-                        f"keyframe every 10 frames, {'mixed precision' if mixed else 'FP32'}, tracked together",
+                        f"keyframe every 10 frames, {'mixed precision' if mixed else 'FP32'}, tracked together, "
+                        f"{'one window track per keyframe window' if window else 'frame by frame'}",
             "value": round(tracked / el, 1), "unit": "frames/s", "samples_per_s": round(sum(stats["samples"]) / el, 1),
             "ms_per_step": round(el * 1e3 / steps, 4), "steps": steps,
-            "track_launch_ms": round(track_ms, 5),
-            "track_only_frames_per_s": round(n_streams / (track_ms * 1e-3), 1),
+            "track_launch_ms": round(track_ms, 5), "frames_per_launch_per_stream": fpl,
+            "track_only_frames_per_s": round(n_streams * fpl / (track_ms * 1e-3), 1),
+            "poses": res["T_cw"].copy(),
             "launch": {"mode": mode, "chunk": chunk, "autotune_ms": timings},
             "iterations_per_frame": round(float(np.mean(stats["iters"])), 3),
             "status_counts": {str(k): int(v) for k, v in zip(*np.unique(stats["status"], return_counts=True))},
@@ -370,10 +413,10 @@ def bench_mixed_precision(dpt, synth, wins, dev, steps):
     cache, Kahan-compensated FP32 sums, FP64 solve, exponential and pose)."""
     prm = dpt.make_params(levels=LEVELS, max_iters=10, huber_k=9.0, step_eps=1e-5, precision=dpt.PREC_MIXED)
     el, st, prof = timed_plain(dpt, synth, wins, dev, steps, 1, prm, dpt.LAUNCH_COOP, 256)
-    track_ms = prof["track_ms"] / prof["n_track"]
+    track_ms = frame_track_ms(prof)
     achieved = float(np.mean(st["samples"])) * BYTES_PER_SAMPLE_MIXED / (track_ms * 1e-3) / 1e9
     out = {"workload": "the headline workload, mixed precision", "frames_per_s": round(steps * (WINDOW - 1) / el, 2),
-           "track_launch_ms": round(track_ms, 5), "iterations_per_frame": round(float(np.mean(st["iters"])), 3),
+           "track_ms_per_frame": round(track_ms, 5), "iterations_per_frame": round(float(np.mean(st["iters"])), 3),
            "pose_error_vs_gt": err_summary([pose_error(T, G) for T, G in zip(st["T"], st["gt"])]),
            "roofline": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS, "achieved": round(achieved, 3),
                         "frac": round(achieved / HBM_PEAK_GBS, 6)}}
@@ -386,16 +429,16 @@ def bench_fixed_h(dpt, synth, wins, dev, steps):
     reduced per iteration, no robust weights."""
     prm = dpt.make_params(levels=LEVELS, max_iters=10, huber_k=9.0, step_eps=1e-5, fixed_h=True)
     el, st, prof = timed_plain(dpt, synth, wins, dev, steps, 1, prm, dpt.LAUNCH_COOP, 256)
-    track_ms = prof["track_ms"] / prof["n_track"]
+    track_ms = frame_track_ms(prof)
     iters = float(np.mean(st["iters"]))
     achieved = float(np.mean(st["samples"])) * BYTES_PER_SAMPLE_F32 / (track_ms * 1e-3) / 1e9
     out = {"workload": "the headline workload, fixed-H mode (constant H per level, b only, no weights)",
-           "frames_per_s": round(steps * (WINDOW - 1) / el, 2), "track_launch_ms": round(track_ms, 5),
+           "frames_per_s": round(steps * (WINDOW - 1) / el, 2), "track_ms_per_frame": round(track_ms, 5),
            "iterations_per_frame": round(iters, 3),
            "track_us_per_iteration": round(track_ms * 1e3 / (iters + 1), 3),
            "status_counts": {str(k): int(v) for k, v in zip(*np.unique(st["status"], return_counts=True))},
            "pose_error_vs_gt": err_summary([pose_error(T, G) for T, G in zip(st["T"], st["gt"])]),
-           "roofline": {"kernel": "coop_track_kernel<256, false, true, false, unsigned char>", "bound": "hbm", "unit": "GB/s",
+           "roofline": {"kernel": "coop_track_kernel<256, false, true, false, unsigned char, true>", "bound": "hbm", "unit": "GB/s",
                         "peak": HBM_PEAK_GBS, "achieved": round(achieved, 3),
                         "frac": round(achieved / HBM_PEAK_GBS, 6)}}
     return out, st
@@ -405,23 +448,23 @@ def bench_paper_shape(dpt, synth, wins, dev, steps):
     """The paper's per-point shape on the headline sequence: the floating-point
     Gaussian pyramid, 6 levels, 7x7 patches (49 samples per point), 2000 points;
     cooperative generic-pattern track (four lanes per point), windows enqueued
-    like the headline's."""
+    like the headline's but frame by frame (window tracks read box pyramids)."""
     prm = dpt.make_params(levels=6, max_iters=10, huber_k=9.0, step_eps=1e-5, gauss=True,
                           pattern=synth.square_pattern(7))
-    el, st, prof = timed_plain(dpt, synth, wins, dev, steps, 1, prm, dpt.LAUNCH_AUTO, 256)
-    track_ms = prof["track_ms"] / prof["n_track"]
+    el, st, prof = timed_plain(dpt, synth, wins, dev, steps, 1, prm, dpt.LAUNCH_AUTO, 256, window=False)
+    track_ms = frame_track_ms(prof)
     samp = float(np.mean(st["samples"]))
     # per sample: 12 B of template and gradient, x0 shared by 49 samples, four FP32 taps
     bps = 12.0 + 12.0 / 49 + 16.0
     achieved = samp * bps / (track_ms * 1e-3) / 1e9
     out = {"workload": "the headline sequence at the paper's shape: FP32 Gaussian pyramid, 6 levels, 7x7 patches, "
                        "2000 points",
-           "frames_per_s": round(steps * (WINDOW - 1) / el, 2), "track_launch_ms": round(track_ms, 5),
+           "frames_per_s": round(steps * (WINDOW - 1) / el, 2), "track_ms_per_frame": round(track_ms, 5),
            "iterations_per_frame": round(float(np.mean(st["iters"])), 3),
            "samples_per_frame": round(samp, 1),
            "status_counts": {str(k): int(v) for k, v in zip(*np.unique(st["status"], return_counts=True))},
            "pose_error_vs_gt": err_summary([pose_error(T, G) for T, G in zip(st["T"], st["gt"])]),
-           "roofline": {"kernel": "coop_track_kernel<256, false, false, true, float>", "bound": "hbm",
+           "roofline": {"kernel": "coop_track_kernel<256, false, false, true, float, false>", "bound": "hbm",
                         "unit": "GB/s", "peak": HBM_PEAK_GBS, "bytes_per_sample": round(bps, 3),
                         "achieved": round(achieved, 3), "frac": round(achieved / HBM_PEAK_GBS, 6)}}
     return out, st
@@ -495,7 +538,7 @@ def bench_stress(dpt, synth):
         prm = dpt.make_params(levels=4, max_iters=10, huber_k=9.0, step_eps=1e-5, precision=prec)
         el, st, prof = timed_plain(dpt, synth, wins, dev, 2, 1, prm, dpt.LAUNCH_COOP, 256, n_points=16000, cam=cam)
         out[name] = {"frames_per_s": round(2 * (WINDOW - 1) / el, 1),
-                     "track_launch_ms": round(prof["track_ms"] / prof["n_track"], 5),
+                     "track_ms_per_frame": round(frame_track_ms(prof), 5),
                      "iterations_per_frame": round(float(np.mean(st["iters"])), 3),
                      "pose_error_vs_gt": err_summary([pose_error(T, G) for T, G in zip(st["T"], st["gt"])])}
         raw[name] = st
@@ -599,18 +642,21 @@ def cpu_baseline(wins, seconds: float, comparisons, tween_run=None):
     return out, diffs
 
 
-def traffic_from_profile():
-    """HBM bytes per launch from the committed rocprofv3 PMC summary, or None if
-    the kernel sources changed since the counters were taken."""
+def traffic_from_profile(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC summary,
+    or None if the kernel sources changed since the counters were taken."""
     if not os.path.exists(PMC_FILE):
         return None
     d = json.load(open(PMC_FILE))
-    if d.get("kernel_source_sha") != kernel_source_hash():
+    if d.get("kernel_source_sha") != kernel_source_hash() or d.get("kernel") != kernel:
         return None
     return d.get("bytes_per_launch")
 
 
-def pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, kernel="coop_track_kernel"):
+HEADLINE_KERNEL = "coop_track_kernel<256, false, false, false, unsigned char, true>"
+
+
+def pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, kernel=HEADLINE_KERNEL):
     """HBM bytes per launch of `kernel` from two rocprofv3 --pmc runs (FETCH_SIZE,
     WRITE_SIZE; KiB per dispatch), each scaled by what the same counter reads for
     the plain copy of --calibrate-copy (bytes moved / counter bytes).  Writes the
@@ -693,6 +739,9 @@ def main():
     ap.add_argument("--launch", choices=["auto", "coop"], default="coop",
                     help="track launch (the GPU-side constant-velocity start needs the cooperative track)")
     ap.add_argument("--chunk", type=int, default=256)
+    ap.add_argument("--mode", choices=["window", "frame"], default="window",
+                    help="headline launch form: one window track per keyframe window (9 frames, bitwise the same "
+                         "poses) or frame by frame; the other form is measured beside it")
     ap.add_argument("--batch-streams", type=int, default=64)
     ap.add_argument("--only-headline", action="store_true", help="skip the batched, precision, fixed-H and initialiser legs")
     ap.add_argument("--legs", default="mixed,fixed,paper,tween,batched,init",
@@ -732,16 +781,35 @@ def main():
 
     launch = {"auto": dpt.LAUNCH_AUTO, "coop": dpt.LAUNCH_COOP}[args.launch]
     prm = dpt.make_params(levels=LEVELS, max_iters=10, huber_k=9.0, step_eps=1e-5)
-    elapsed, stats, prof = timed_plain(dpt, synth, wins, dev, args.steps, args.warmup, prm, launch, args.chunk)
+    window = args.mode == "window"
+    elapsed, stats, prof = timed_plain(dpt, synth, wins, dev, args.steps, args.warmup, prm, launch, args.chunk,
+                                       window=window)
     print(f"# headline leg done ({elapsed:.2f} s)", file=sys.stderr, flush=True)
+    # the same windows frame by frame (a pyramid and a track launch per frame): the
+    # rate of a live camera whose frames arrive one at a time
+    el_f, st_f, prof_f = timed_plain(dpt, synth, wins, dev, args.steps, args.warmup, prm, launch, args.chunk,
+                                     window=not window)
+    same = bool(np.array_equal(np.asarray(stats["T"]), np.asarray(st_f["T"])))
+    print(f"# other launch form done ({el_f:.2f} s)", file=sys.stderr, flush=True)
 
     tracked = args.steps * (WINDOW - 1)
     samples = float(np.sum(stats["samples"]))
-    track_ms = prof["track_ms"] / prof["n_track"]
-    samp_launch = float(np.mean(stats["samples"]))
+    fpl = prof["frames_per_launch"]
+    launch_ms = prof["track_ms"] / prof["n_track"]
+    track_ms = launch_ms / fpl
+    samp_launch = float(np.mean(stats["samples"])) * fpl
     alg_bytes = samp_launch * BYTES_PER_SAMPLE_F32
-    achieved = alg_bytes / (track_ms * 1e-3) / 1e9
-    kname = f"coop_track_kernel<{args.chunk}, false, false, false, unsigned char>"
+    achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
+    kname = f"coop_track_kernel<{args.chunk}, false, false, false, unsigned char, {'true' if window else 'false'}>"
+    iters = float(np.mean(stats["iters"]))
+
+    def form(el, st, pr, w):
+        lm = pr["track_ms"] / pr["n_track"]
+        return {"launch_form": "window" if w else "frame", "frames_per_s": round(tracked / el, 2),
+                "track_launch_ms": round(lm, 5), "track_ms_per_frame": round(lm / pr["frames_per_launch"], 5),
+                "pyramid_launch_ms": round(pr["pyramid_ms"] / max(pr["n_pyramid"], 1), 5),
+                "kernel": f"coop_track_kernel<{args.chunk}, false, false, false, unsigned char, {'true' if w else 'false'}>"}
+
     att_gbs = attainable_copy_gbs()  # after the timed region
     out = {
         "metric": METRIC,
@@ -760,23 +828,25 @@ def main():
                                "Huber 9, <=10 iters/level, sigma=2 noise, keyframe every 10 frames, "
                                "plain FP32, one stream",
                    "tracked_frames_per_step": WINDOW - 1, "frames_per_step": WINDOW, "parallelism": "none",
-                   "launch": args.launch, "chunk": args.chunk},
+                   "launch": args.launch, "chunk": args.chunk, "launch_form": args.mode},
         "samples_per_s": round(samples / elapsed, 1),
         "roofline": {"kernel": kname, "bound": "hbm", "achieved": round(achieved, 3),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
-                     "traffic": traffic_from_profile(),
+                     "traffic": traffic_from_profile(kname),
                      "attainable_copy": round(att_gbs, 1), "frac_of_attainable": round(achieved / att_gbs, 6),
                      "bytes_per_launch_algorithmic": round(alg_bytes, 1), "samples_per_launch": round(samp_launch, 1),
-                     "avg_launch_ms": round(track_ms, 5),
-                     "note": "one launch tracks one frame; a single stream is latency-bound by its ~16 dependent "
-                             "Gauss-Newton iterations, each a grid-wide reduction"},
-        "kernels_ms": {"track_kernel": round(track_ms, 5),
-                       "pyramid_kernel": round(prof["pyramid_ms"] / max(prof["n_pyramid"], 1), 5)},
+                     "frames_per_launch": fpl, "avg_launch_ms": round(launch_ms, 5),
+                     "note": f"one launch tracks {fpl} frame(s); a single stream is latency-bound by its ~16 "
+                             "dependent Gauss-Newton iterations per frame, each a grid-wide reduction"},
+        "kernels_ms": {"track_kernel_per_launch": round(launch_ms, 5),
+                       "pyramid_kernel_per_launch": round(prof["pyramid_ms"] / max(prof["n_pyramid"], 1), 5)},
         "track_only_frames_per_s": round(1.0 / (track_ms * 1e-3), 1),
-        "iterations_per_frame": round(float(np.mean(stats["iters"])), 3),
-        "track_us_per_iteration": round(track_ms * 1e3 / (float(np.mean(stats["iters"])) + 1), 3),
+        "iterations_per_frame": round(iters, 3),
+        "track_us_per_iteration": round(track_ms * 1e3 / (iters + 1), 3),
         "status_counts": {str(k): int(v) for k, v in zip(*np.unique(stats["status"], return_counts=True))},
         "pose_error_vs_gt": err_summary([pose_error(T, G) for T, G in zip(stats["T"], stats["gt"])]),
+        "launch_forms": {"this": form(elapsed, stats, prof, window), "other": form(el_f, st_f, prof_f, not window),
+                         "poses_bitwise_equal": same},
         "setup_render_s": round(render_s, 2),
     }
     nc = WINDOW - 1  # the first timed window of each leg is compared with the oracle

@@ -177,6 +177,9 @@ int dpt_track_frame(dpt_ctx* ctx, const double T_cw_init[16], dpt_result* out);
 /* Start pose of an enqueued track. */
 enum { DPT_INIT_GIVEN = 0, DPT_INIT_CONST_VELOCITY = 1 };
 
+/* Most tracks (frames) enqueued and not yet synchronised, per context or batch. */
+#define DPT_MAX_IN_FLIGHT 256
+
 /* Asynchronous form of dpt_track_frame (the same computation, Sec. IV-C
  * "Track"): enqueue the track of the CUR pyramid on the context's stream and
  * return at once, so frames can follow each other without the host waiting
@@ -189,8 +192,8 @@ enum { DPT_INIT_GIVEN = 0, DPT_INIT_CONST_VELOCITY = 1 };
  * start needs that path (launch mode AUTO or COOP; DPT_E_ARG
  * otherwise); on the one-workgroup path a DPT_INIT_GIVEN enqueue runs
  * synchronously.  *out is written by the next dpt_synchronize (or any call
- * that synchronises the context) and must stay valid until then.  At most 64
- * tracks may be in flight (DPT_E_STATE beyond).  Later pyramid builds and
+ * that synchronises the context) and must stay valid until then.  At most
+ * DPT_MAX_IN_FLIGHT tracks may be in flight (DPT_E_STATE beyond).  Later pyramid builds and
  * reference updates on the same stream are ordered after the enqueued track. */
 int dpt_track_enqueue(dpt_ctx* ctx, int32_t init_mode, const double T_cw_init[16], dpt_result* out);
 
@@ -201,6 +204,32 @@ int dpt_synchronize(dpt_ctx* ctx);
 /* Set the pose history used by DPT_INIT_CONST_VELOCITY (row-major 4x4 T_cw,
  * older first), ordered on the stream with the tracks.  Initially identity. */
 int dpt_set_pose_history(dpt_ctx* ctx, const double T_older[16], const double T_newer[16]);
+
+/* Most frames one window track may cover. */
+#define DPT_MAX_WINDOW 32
+
+/* Window tracking: the tween frames of one reference (Sec. III: the frames the
+ * direct tracker handles between two references), n_frames consecutive frames
+ * tracked in order against the current reference by one pyramid launch for
+ * all of them and one cooperative track launch, the same computation as
+ * n_frames dpt_build_pyramid(CUR) + dpt_track_enqueue calls: frame 0 starts
+ * from T_cw_init (DPT_INIT_GIVEN) or the constant-velocity prediction of the
+ * pose history (DPT_INIT_CONST_VELOCITY), every later frame from the
+ * constant-velocity prediction of the two poses before it, and the history
+ * ends with the window's last two poses.  The poses are bitwise those of the
+ * frame-by-frame calls.  frames: n_frames uint8 W x H images, rows `pitch`
+ * bytes apart, frame f at frames + f * frame_stride, in device memory if
+ * frames_on_device (1), else host memory (0; copied, and the call then waits
+ * for the stream).  out: n_frames results, written by the next
+ * dpt_synchronize.  1 <= n_frames <= DPT_MAX_WINDOW; the frames count towards
+ * the DPT_MAX_IN_FLIGHT tracks in flight.  The window pyramids are the context's own (the
+ * CUR slot is left as it was), allocated on the first call and grown when a
+ * longer window comes (the call then first waits for the tracks in flight).
+ * DPT_E_ARG for a frame_stride smaller than a frame, the one-workgroup launch
+ * mode, or DPT_FLAG_GAUSS_F32; DPT_E_STATE without reference points. */
+int dpt_track_window_enqueue(dpt_ctx* ctx, const uint8_t* frames, int64_t pitch, int64_t frame_stride,
+                             int32_t n_frames, int32_t frames_on_device, int32_t init_mode,
+                             const double T_cw_init[16], dpt_result* out);
 
 /* ------------------------------------------------------------------ tween-window schedule
  * The schedule of Sec. III and Sec. IV-D: direct tracking handles the tween
@@ -363,6 +392,17 @@ int dpt_batch_synchronize(dpt_batch* b);
 int dpt_batch_set_pose_history(dpt_batch* b, int32_t s, const double T_older[16], const double T_newer[16]);
 /* Pose histories of every stream at once (n_streams row-major 4x4 each), one launch. */
 int dpt_batch_set_pose_history_all(dpt_batch* b, const double* T_older, const double* T_newer);
+
+/* dpt_track_window_enqueue for every stream of the batch: stream s's frames at
+ * frames[s] (pitches[s], frame_strides[s]), all streams n_frames frames, one
+ * pyramid launch per 64 streams and one track launch per cooperative group.
+ * Each stream advances through its window at its own pace: a stream that needs
+ * more iterations on one frame does not hold the others back at every frame.
+ * T_cw_init: n_streams row-major 4x4 (DPT_INIT_GIVEN) or NULL; out:
+ * n_frames x n_streams results, frame-major (out[f * n_streams + s]). */
+int dpt_batch_track_window_enqueue(dpt_batch* b, const uint8_t* const* frames, const int64_t* pitches,
+                                   const int64_t* frame_strides, int32_t n_frames, int32_t frames_on_device,
+                                   int32_t init_mode, const double* T_cw_init, dpt_result* out);
 
 /* Launch configuration as dpt_set_launch_config, for the whole batch. */
 int dpt_batch_set_launch_config(dpt_batch* b, int32_t mode, int32_t chunk);

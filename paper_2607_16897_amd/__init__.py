@@ -25,6 +25,8 @@ FLAG_GAUSS_F32 = 2  # dpt_params.flags: track on the floating-point Gaussian pyr
 SLOT_REF, SLOT_CUR = 0, 1
 LAUNCH_AUTO, LAUNCH_WORKGROUP, LAUNCH_COOP = 0, 1, 2
 INIT_GIVEN, INIT_CONST_VELOCITY = 0, 1
+MAX_WINDOW = 32  # most frames one window track covers
+MAX_IN_FLIGHT = 256  # most tracks enqueued and not yet synchronised
 DEFAULT_PATTERN = ((-2, 0), (2, 0), (0, -2), (0, 2), (-1, -1), (1, -1), (-1, 1), (1, 1))
 
 
@@ -101,6 +103,8 @@ SIGNATURES = {
                                                           ctypes.POINTER(ctypes.c_double)]),
     "dpt_track_frame": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(Result)]),
     "dpt_track_enqueue": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ctypes.c_double), _vp]),
+    "dpt_track_window_enqueue": (ctypes.c_int, [_vp, _vp, _i64, _i64, _i32, _i32, _i32,
+                                                ctypes.POINTER(ctypes.c_double), _vp]),
     "dpt_synchronize": (ctypes.c_int, [_vp]),
     "dpt_set_pose_history": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "dpt_get_profile": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64),
@@ -119,6 +123,7 @@ SIGNATURES = {
     "dpt_batch_set_reference_points": (ctypes.c_int, [_vp, _i32, _vp, _i32, ctypes.POINTER(ctypes.c_double), _i32]),
     "dpt_batch_track": (ctypes.c_int, [_vp, _vp, _vp]),
     "dpt_batch_track_enqueue": (ctypes.c_int, [_vp, _i32, _vp, _vp]),
+    "dpt_batch_track_window_enqueue": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _i32, _i32, _vp, _vp]),
     "dpt_batch_synchronize": (ctypes.c_int, [_vp]),
     "dpt_batch_set_reference_from_depth_all": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp, ctypes.POINTER(ctypes.c_double)]),
     "dpt_batch_set_pose_history_all": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double),
@@ -186,6 +191,26 @@ def _ptr(x):
         if not x.is_contiguous():
             x = x.contiguous()
         return x.data_ptr(), int(x.is_cuda), x
+    raise TypeError(f"unsupported buffer type {type(x)}")
+
+
+def _frames(x):
+    """(n_frames, pointer, row pitch, frame stride, on_device, keepalive) of a
+    [F, H, W] uint8 NumPy array or torch tensor (device tensors at their own
+    strides; rows must be contiguous)."""
+    if isinstance(x, np.ndarray):
+        x = np.ascontiguousarray(x, dtype=np.uint8)
+        if x.ndim != 3:
+            raise ValueError("frames must be [F, H, W]")
+        return x.shape[0], x.ctypes.data, x.strides[1], x.strides[0], 0, x
+    import torch
+
+    if isinstance(x, torch.Tensor):
+        if x.dim() != 3 or x.dtype != torch.uint8:
+            raise ValueError("frames must be a [F, H, W] uint8 tensor")
+        if x.stride(2) != 1:
+            x = x.contiguous()
+        return x.shape[0], x.data_ptr(), x.stride(1), x.stride(0), int(x.is_cuda), x
     raise TypeError(f"unsupported buffer type {type(x)}")
 
 
@@ -319,6 +344,20 @@ class Tracker:
         else:
             _check(self._lib.dpt_track_enqueue(self._h, INIT_GIVEN, _mat(T_cw_init), ctypes.byref(r)))
         self._pending.append(r)
+
+    def track_window_enqueue(self, frames, T_cw_init=None):
+        """Enqueue the track of consecutive frames (a [F, H, W] uint8 NumPy array on
+        the host or torch CUDA tensor, rows and frames at any stride) in one pyramid
+        and one track launch: frame 0 from T_cw_init or (None) the constant-velocity
+        prediction of the pose history, every later frame from the prediction of
+        the two before it.  Results come back, in order, from synchronize()."""
+        F, p, pitch, fstride, dev, keep = _frames(frames)
+        res = (Result * F)()
+        T = None if T_cw_init is None else _mat(T_cw_init)
+        _check(self._lib.dpt_track_window_enqueue(self._h, p, pitch, fstride, F, dev,
+                                                  INIT_CONST_VELOCITY if T is None else INIT_GIVEN, T,
+                                                  ctypes.cast(res, _vp)))
+        self._pending.extend(res[f] for f in range(F))
 
     def synchronize(self, arrays: bool = False):
         """Results of the enqueued tracks, in order: a list of dicts, or (arrays=True)
@@ -467,6 +506,34 @@ class BatchTracker:
             T = np.ascontiguousarray(np.asarray(T_cw_init, np.float64).reshape(self.n, 16))
             _check(self._lib.dpt_batch_track_enqueue(self._h, INIT_GIVEN, T.ctypes.data, ctypes.cast(res, _vp)))
         self._pending.append(res)
+
+    def track_window_enqueue(self, frames, T_cw_init=None):
+        """Window tracking of every stream (Tracker.track_window_enqueue): frames is
+        one [F, H_s, W_s] array or tensor per stream, all with the same F, or one
+        [n, F, H, W] CUDA tensor.  synchronize() returns one list of n results per
+        frame."""
+        if hasattr(frames, "dim") and frames.dim() == 4:
+            frames = [frames[s] for s in range(frames.shape[0])]
+        if len(frames) != self.n:
+            raise ValueError(f"{len(frames)} frame stacks for {self.n} streams")
+        parts = [_frames(x) for x in frames]
+        F = parts[0][0]
+        if any(q[0] != F for q in parts) or len({q[4] for q in parts}) != 1:
+            raise ValueError("every stream needs the same number of frames, all on one side (host or device)")
+        ptrs = (ctypes.c_void_p * self.n)(*[q[1] for q in parts])
+        pitches = (_i64 * self.n)(*[q[2] for q in parts])
+        strides = (_i64 * self.n)(*[q[3] for q in parts])
+        res = (Result * (F * self.n))()
+        if T_cw_init is None:
+            mode, T = INIT_CONST_VELOCITY, None
+        else:
+            mode = INIT_GIVEN
+            T = np.ascontiguousarray(np.asarray(T_cw_init, np.float64).reshape(self.n, 16))
+        _check(self._lib.dpt_batch_track_window_enqueue(
+            self._h, ctypes.cast(ptrs, _vp), ctypes.cast(pitches, _vp), ctypes.cast(strides, _vp), F, parts[0][4],
+            mode, None if T is None else T.ctypes.data, ctypes.cast(res, _vp)))
+        size = ctypes.sizeof(Result) * self.n
+        self._pending.extend((Result * self.n).from_buffer(res, f * size) for f in range(F))
 
     def synchronize(self, arrays: bool = False):
         """Results of the enqueued tracks, in order: one list of n per enqueue, or

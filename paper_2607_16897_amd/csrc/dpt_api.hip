@@ -126,7 +126,7 @@ namespace dpt {
 // stream around each launch; a pair is drained into the totals once its end
 // event has completed.
 struct ProfRing {
-  static constexpr int kN = 2 * kRing;
+  static constexpr int kN = 128;  // pairs recorded and not yet read back
   hipEvent_t ev[kN][2] = {};
   bool created = false;
   // Only every `every`-th launch is bracketed: each event record is a marker
@@ -288,6 +288,12 @@ struct dpt_ctx {
   double* d_hist = nullptr;  // pose history: the last two T_cw, 2 x 3x4 FP64 (device)
   std::vector<std::pair<int, dpt_result*>> pending;  // tracks in flight: (ring slot, caller's result)
   int slot_next = 0;
+  // window tracking: box pyramids of up to win_cap consecutive frames
+  uint8_t* win = nullptr;
+  int64_t win_stride = 0;  // bytes per frame pyramid, a multiple of 256
+  int32_t win_cap = 0;
+  uint8_t* win_staging = nullptr;  // level 0 of host frames, win_cap frames of W x H
+  WinJob* d_winjob = nullptr;      // this context's window pyramid job (device)
   // tween-window schedule (host state)
   dpt_tween_policy tween{};
   bool tween_policy = false, tween_anchored = false, tween_needs_anchor = false;
@@ -304,7 +310,8 @@ struct dpt_ctx {
     if (depth_stage) (void)hipFree(depth_stage);
     for (void* p : {(void*)pyr[0], (void*)pyr[1], (void*)staging, (void*)x0, (void*)valid, (void*)I0, (void*)gx,
                     (void*)gy, (void*)I0h, (void*)gh, (void*)pts, (void*)sel_idx, (void*)sel_count, (void*)sel_scratch, (void*)d_out,
-                    (void*)d_tot, (void*)d_fixed, (void*)d_hpart, (void*)pyrf[0], (void*)pyrf[1]})
+                    (void*)d_tot, (void*)d_fixed, (void*)d_hpart, (void*)pyrf[0], (void*)pyrf[1], (void*)win,
+                    (void*)win_staging, (void*)d_winjob})
       if (p) (void)hipFree(p);
     if (h_out) (void)hipHostFree(h_out);
     if (h_tot) (void)hipHostFree(h_tot);
@@ -785,7 +792,7 @@ int ensure_engine(dpt_ctx* c) {
   if (c->eng.dirty || c->eng.h_streams[0].a.ref.n != c->n_points) {
     TrackArgs a;
     fill_track_args(c, a);
-    c->eng.set_stream(0, a, c->d_hist);
+    c->eng.set_stream(0, a, c->d_hist, c->win, c->win_stride);
   }
   if (c->eng.dirty) HIP_TRY(c->eng.upload());
   return DPT_OK;
@@ -885,6 +892,61 @@ int check_track_state(const dpt_ctx* c) {
   return DPT_OK;
 }
 
+// Window pyramids for n_frames frames (grown on demand; nothing may be in
+// flight).  *grown tells the caller that the engines must see the new buffer.
+int ensure_window(dpt_ctx* c, int n_frames, bool* grown) {
+  *grown = false;
+  if (n_frames <= c->win_cap) return DPT_OK;
+  for (void** p : {(void**)&c->win, (void**)&c->win_staging}) {
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+  }
+  c->win_cap = 0;
+  const int64_t stride = (c->pyr_bytes + 255) / 256 * 256;
+  int e;
+  if ((e = dev_alloc((void**)&c->win, (size_t)stride * n_frames)) != DPT_OK) return e;
+  if (!c->d_winjob && (e = dev_alloc((void**)&c->d_winjob, sizeof(WinJob))) != DPT_OK) return e;
+  WinJob j;
+  std::memset(&j, 0, sizeof j);
+  j.dst = c->win;
+  j.dst_stride = stride;
+  j.g = c->pg;
+  HIP_TRY(hipMemcpy(c->d_winjob, &j, sizeof j, hipMemcpyHostToDevice));
+  c->win_stride = stride;
+  c->win_cap = n_frames;
+  *grown = true;
+  return DPT_OK;
+}
+
+// Level 0 of n_frames host frames into the context's device staging.
+int stage_window(dpt_ctx* c, const uint8_t* frames, int64_t pitch, int64_t frame_stride, int n_frames,
+                 hipStream_t s) {
+  const int W = c->cam.width, H = c->cam.height;
+  int e;
+  if (!c->win_staging && (e = dev_alloc((void**)&c->win_staging, (size_t)W * H * c->win_cap)) != DPT_OK) return e;
+  for (int f = 0; f < n_frames; ++f)
+    HIP_TRY(hipMemcpy2DAsync(c->win_staging + (size_t)f * W * H, W, frames + f * frame_stride, pitch, W, H,
+                             hipMemcpyHostToDevice, s));
+  return DPT_OK;
+}
+
+int check_window_args(const dpt_ctx* c, const uint8_t* frames, int64_t pitch, int64_t frame_stride, int n_frames,
+                      int on_device, int init_mode) {
+  if (!frames) return fail(DPT_E_ARG, "frames is NULL");
+  if (on_device != 0 && on_device != 1) return fail(DPT_E_ARG, "frames_on_device %d is neither 0 nor 1", on_device);
+  if (n_frames < 1 || n_frames > DPT_MAX_WINDOW)
+    return fail(DPT_E_ARG, "n_frames %d outside [1, %d]", n_frames, DPT_MAX_WINDOW);
+  if (init_mode != DPT_INIT_GIVEN && init_mode != DPT_INIT_CONST_VELOCITY)
+    return fail(DPT_E_ARG, "init_mode %d", init_mode);
+  if (pitch < c->cam.width) return fail(DPT_E_ARG, "pitch %lld < width %d", (long long)pitch, c->cam.width);
+  if (n_frames > 1 && frame_stride < pitch * (c->cam.height - 1) + c->cam.width)
+    return fail(DPT_E_ARG, "frame_stride %lld smaller than one frame", (long long)frame_stride);
+  if (c->prm.flags & DPT_FLAG_GAUSS_F32)
+    return fail(DPT_E_ARG, "window tracking reads box pyramids (DPT_FLAG_GAUSS_F32 is set)");
+  if (!c->have_ref) return fail(DPT_E_STATE, "no reference points");
+  return DPT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -931,6 +993,59 @@ int dpt_set_pose_history(dpt_ctx* c, const double T_older[16], const double T_ne
   if (!c || !T_older || !T_newer) return fail(DPT_E_ARG, "NULL argument");
   if (!finite16(T_older) || !finite16(T_newer)) return fail(DPT_E_ARG, "pose not finite");
   HIP_TRY(launch_set_history(c->d_hist, T_older, T_newer, c->stream));
+  return DPT_OK;
+}
+
+int dpt_track_window_enqueue(dpt_ctx* c, const uint8_t* frames, int64_t pitch, int64_t frame_stride,
+                             int32_t n_frames, int32_t frames_on_device, int32_t init_mode, const double T_cw_init[16],
+                             dpt_result* out) {
+  g_err.clear();
+  if (!c || !out) return fail(DPT_E_ARG, "NULL argument");
+  int e = check_window_args(c, frames, pitch, frame_stride, n_frames, frames_on_device, init_mode);
+  if (e != DPT_OK) return e;
+  if (init_mode == DPT_INIT_GIVEN && (!T_cw_init || !finite16(T_cw_init)))
+    return fail(DPT_E_ARG, "T_cw_init missing or not finite");
+  if (!use_coop(c)) return fail(DPT_E_ARG, "window tracking needs the cooperative track (launch mode AUTO or COOP)");
+  if ((int)c->pending.size() + n_frames > kRing)
+    return fail(DPT_E_STATE, "%d tracks in flight and %d more exceed %d: synchronise first", (int)c->pending.size(),
+                n_frames, kRing);
+  if (n_frames > c->win_cap) {  // the buffers in use by tracks in flight are replaced
+    if (!c->pending.empty() && (e = synchronize(c)) != DPT_OK) return e;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    bool grown = false;
+    if ((e = ensure_window(c, n_frames, &grown)) != DPT_OK) return e;
+    if (grown && c->eng_ready) c->eng.dirty = true;
+  }
+  if ((e = ensure_engine(c)) != DPT_OK) return e;
+  const uint8_t* src = frames;
+  int64_t sp = pitch, sst = frame_stride;
+  if (!frames_on_device) {
+    if ((e = stage_window(c, frames, pitch, frame_stride, n_frames, c->stream)) != DPT_OK) return e;
+    src = c->win_staging;
+    sp = c->cam.width;
+    sst = (int64_t)c->cam.width * c->cam.height;
+  }
+  PyrWinSrc srcs;
+  std::memset(&srcs, 0, sizeof srcs);
+  srcs.src[0] = src;
+  srcs.pitch[0] = sp;
+  srcs.stride[0] = sst;
+  int ps = -1;
+  if (c->prof) HIP_TRY(c->prof_pyr.begin(c->stream, &ps));
+  HIP_TRY(launch_pyramid_window(c->d_winjob, srcs, 1, n_frames, c->cam.width, c->cam.height, c->prm.levels,
+                                c->stream));
+  if (c->prof) HIP_TRY(c->prof_pyr.end(c->stream, ps));
+  const int slot = c->slot_next;
+  for (int f = 0; f < n_frames; ++f) {
+    const int mode = f == 0 && init_mode == DPT_INIT_GIVEN ? kStartGiven : kStartConstVelocity;
+    fill_start(c, mode, T_cw_init, c->eng.start((slot + f) % kRing));
+  }
+  if (c->prof) HIP_TRY(c->prof_trk.begin(c->stream, &ps));
+  HIP_TRY(c->eng.launch(kSpinLimit, slot, n_frames));
+  if (c->prof) HIP_TRY(c->prof_trk.end(c->stream, ps));
+  for (int f = 0; f < n_frames; ++f) c->pending.emplace_back((slot + f) % kRing, out + f);
+  c->slot_next = (slot + n_frames) % kRing;
+  if (!frames_on_device) HIP_TRY(hipStreamSynchronize(c->stream));  // the host frames are only borrowed
   return DPT_OK;
 }
 
@@ -1086,6 +1201,7 @@ struct dpt_batch {
   StagedTable<PrecomputeArgs> pre_args;
   StagedTable<double> hist_vals;  // 24 per stream
   double** d_hist_ptrs = nullptr;  // device array of the streams' history pointers
+  WinJob* d_winjobs = nullptr;     // the streams' window pyramid jobs (device)
 
   void clear_groups() {
     for (CoopEngine* g : groups) delete g;
@@ -1104,6 +1220,7 @@ struct dpt_batch {
     pre_args.release();
     hist_vals.release();
     if (d_hist_ptrs) (void)hipFree(d_hist_ptrs);
+    if (d_winjobs) (void)hipFree(d_winjobs);
     for (hipEvent_t e : ev_jobs)
       if (e) (void)hipEventDestroy(e);
     if (d_jobs) (void)hipFree(d_jobs);
@@ -1152,7 +1269,7 @@ int build_groups(dpt_batch* b) {
     for (size_t k = 0; k < cur.size(); ++k) {
       TrackArgs a;
       fill_track_args(b->ctx[cur[k]], a);
-      g->set_stream((int)k, a, b->ctx[cur[k]]->d_hist);
+      g->set_stream((int)k, a, b->ctx[cur[k]]->d_hist, b->ctx[cur[k]]->win, b->ctx[cur[k]]->win_stride);
     }
     b->groups.push_back(g);
     b->group_streams.push_back(cur);
@@ -1572,6 +1689,92 @@ int dpt_batch_synchronize(dpt_batch* b) {
   g_err.clear();
   if (!b) return fail(DPT_E_ARG, "NULL batch");
   return batch_synchronize(b);
+}
+
+int dpt_batch_track_window_enqueue(dpt_batch* b, const uint8_t* const* frames, const int64_t* pitches,
+                                   const int64_t* frame_strides, int32_t n_frames, int32_t frames_on_device,
+                                   int32_t init_mode, const double* T_cw_init, dpt_result* out) {
+  g_err.clear();
+  if (!b || !frames || !pitches || !frame_strides || !out) return fail(DPT_E_ARG, "NULL argument");
+  int e;
+  for (int s = 0; s < b->n; ++s)
+    if ((e = check_window_args(b->ctx[s], frames[s], pitches[s], frame_strides[s], n_frames, frames_on_device,
+                               init_mode)) != DPT_OK)
+      return e;
+  if (init_mode == DPT_INIT_GIVEN) {
+    if (!T_cw_init) return fail(DPT_E_ARG, "T_cw_init is NULL");
+    for (int s = 0; s < b->n; ++s)
+      if (!finite16(T_cw_init + 16 * s)) return fail(DPT_E_ARG, "T_cw_init %d not finite", s);
+  }
+  if (!batch_use_coop(b)) return fail(DPT_E_ARG, "window tracking needs the cooperative track (launch mode AUTO or COOP)");
+  if ((int)b->pending.size() + n_frames > kRing)
+    return fail(DPT_E_STATE, "%d batched tracks in flight and %d more exceed %d: synchronise first",
+                (int)b->pending.size(), n_frames, kRing);
+  bool need = false;
+  for (int s = 0; s < b->n; ++s) need |= n_frames > b->ctx[s]->win_cap;
+  if (need) {  // new buffers: finish what is in flight, then regroup with them
+    if ((e = batch_synchronize(b)) != DPT_OK) return e;
+    for (int s = 0; s < b->n; ++s) {
+      bool grown = false;
+      if ((e = ensure_window(b->ctx[s], n_frames, &grown)) != DPT_OK) return e;
+    }
+    if (!b->d_winjobs && hipMalloc(&b->d_winjobs, sizeof(WinJob) * b->n) != hipSuccess) {
+      (void)hipGetLastError();
+      b->d_winjobs = nullptr;
+      return fail(DPT_E_OOM, "window job table allocation failed");
+    }
+    for (int s = 0; s < b->n; ++s)
+      HIP_TRY(hipMemcpy(b->d_winjobs + s, b->ctx[s]->d_winjob, sizeof(WinJob), hipMemcpyDeviceToDevice));
+    b->clear_groups();
+  }
+  if (b->groups_dirty && (e = build_groups(b)) != DPT_OK) return e;
+  for (CoopEngine* g : b->groups)
+    if (g->dirty) HIP_TRY(g->upload());
+  // pyramids of every stream's frames, up to kPyrArgJobs streams per launch
+  int ps = -1;
+  if (b->prof) HIP_TRY(b->prof_pyr.begin(b->stream, &ps));
+  for (int s0 = 0; s0 < b->n; s0 += kPyrArgJobs) {
+    const int m = std::min(kPyrArgJobs, b->n - s0);
+    PyrWinSrc srcs;
+    std::memset(&srcs, 0, sizeof srcs);
+    int max_w = 0, max_h = 0;
+    for (int k = 0; k < m; ++k) {
+      dpt_ctx* c = b->ctx[s0 + k];
+      srcs.src[k] = frames[s0 + k];
+      srcs.pitch[k] = pitches[s0 + k];
+      srcs.stride[k] = frame_strides[s0 + k];
+      if (!frames_on_device) {
+        if ((e = stage_window(c, frames[s0 + k], pitches[s0 + k], frame_strides[s0 + k], n_frames, b->stream)) !=
+            DPT_OK)
+          return e;
+        srcs.src[k] = c->win_staging;
+        srcs.pitch[k] = c->cam.width;
+        srcs.stride[k] = (int64_t)c->cam.width * c->cam.height;
+      }
+      max_w = std::max(max_w, c->cam.width);
+      max_h = std::max(max_h, c->cam.height);
+    }
+    HIP_TRY(launch_pyramid_window(b->d_winjobs + s0, srcs, m, n_frames, max_w, max_h, b->ctx[0]->prm.levels,
+                                  b->stream));
+  }
+  if (b->prof) HIP_TRY(b->prof_pyr.end(b->stream, ps));
+  const int slot = b->slot_next;
+  for (int f = 0; f < n_frames; ++f) {
+    const int mode = f == 0 && init_mode == DPT_INIT_GIVEN ? kStartGiven : kStartConstVelocity;
+    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+      const std::vector<int>& ss = b->group_streams[gi];
+      StartSlot* st = b->groups[gi]->start((slot + f) % kRing);
+      for (size_t k = 0; k < ss.size(); ++k)
+        fill_start(b->ctx[ss[k]], mode, T_cw_init ? T_cw_init + 16 * ss[k] : nullptr, &st[k]);
+    }
+  }
+  if (b->prof) HIP_TRY(b->prof_trk.begin(b->stream, &ps));
+  for (CoopEngine* g : b->groups) HIP_TRY(g->launch(kSpinLimit, slot, n_frames));
+  if (b->prof) HIP_TRY(b->prof_trk.end(b->stream, ps));
+  for (int f = 0; f < n_frames; ++f) b->pending.emplace_back((slot + f) % kRing, out + (size_t)f * b->n);
+  b->slot_next = (slot + n_frames) % kRing;
+  if (!frames_on_device) HIP_TRY(hipStreamSynchronize(b->stream));  // the host frames are only borrowed
+  return DPT_OK;
 }
 
 int dpt_batch_set_pose_history(dpt_batch* b, int32_t s, const double T_older[16], const double T_newer[16]) {

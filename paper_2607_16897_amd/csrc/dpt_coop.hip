@@ -206,23 +206,11 @@ __device__ __forceinline__ double invert34_elem(const double* A, int t) {
   return -(A[r] * A[3] + A[4 + r] * A[7] + A[8 + r] * A[11]);
 }
 
-// Start pose relative to the reference for this launch: the given one, or the
-// constant-velocity prediction P1 P0^-1 P1 from the stream's pose history,
-// taken relative to the reference (P T_rw^-1).  Block-wide; the result and the
-// history's latest pose land in LDS.
-__device__ __forceinline__ void start_pose(const StartSlot* __restrict__ st, const double* __restrict__ hist,
-                                           double* T0, double* rw, double* h0, double* h1, double* m1, double* m2) {
+// Constant-velocity start P1 P0^-1 P1 from the pose history (h0 = P0, h1 = P1
+// in LDS), taken relative to the reference (P T_rw^-1), into T0.  Block-wide.
+__device__ __forceinline__ void const_velocity_start(double* T0, const double* rw, const double* h0,
+                                                     const double* h1, double* m1, double* m2) {
   const int t = threadIdx.x;
-  __shared__ int sh_mode;
-  if (t < 12) {
-    T0[t] = st->T_rel[t];
-    rw[t] = st->T_rw[t];
-    h0[t] = hist[t];
-    h1[t] = hist[12 + t];
-  }
-  if (t == 0) sh_mode = st->mode > 0.5 ? kStartConstVelocity : kStartGiven;
-  __syncthreads();
-  if (sh_mode != kStartConstVelocity) return;
   if (t < 12) m1[t] = invert34_elem(h0, t);
   if (t >= 16 && t < 28) m2[t - 16] = invert34_elem(rw, t - 16);
   __syncthreads();
@@ -241,6 +229,24 @@ __device__ __forceinline__ void start_pose(const StartSlot* __restrict__ st, con
   __syncthreads();
 }
 
+// Start pose relative to the reference for this launch: the given one, or the
+// constant-velocity prediction from the stream's pose history.  Block-wide;
+// the result, the reference pose and the history land in LDS.
+__device__ __forceinline__ void start_pose(const StartSlot* __restrict__ st, const double* __restrict__ hist,
+                                           double* T0, double* rw, double* h0, double* h1, double* m1, double* m2) {
+  const int t = threadIdx.x;
+  __shared__ int sh_mode;
+  if (t < 12) {
+    T0[t] = st->T_rel[t];
+    rw[t] = st->T_rw[t];
+    h0[t] = hist[t];
+    h1[t] = hist[12 + t];
+  }
+  if (t == 0) sh_mode = st->mode > 0.5 ? kStartConstVelocity : kStartGiven;
+  __syncthreads();
+  if (sh_mode == kStartConstVelocity) const_velocity_start(T0, rw, h0, h1, m1, m2);
+}
+
 // MIXED: FP16 reference cache, Kahan-compensated FP32 sums across waves and
 // chunks, FP64 solve, exponential and pose state.
 // FIXED: fixed-H mode (FP32): unweighted residuals, only b, the cost and the
@@ -248,12 +254,12 @@ __device__ __forceinline__ void start_pose(const StartSlot* __restrict__ st, con
 // comes factored from the precompute.
 // GENERIC: any pattern K (four lanes per point, CH / 4 points per chunk) on
 // uint8 levels or (PIX = float) the floating-point Gaussian pyramid.
-template <int CH, bool MIXED, bool FIXED, bool GENERIC = false, class PIX = uint8_t>
+template <int CH, bool MIXED, bool FIXED, bool GENERIC = false, class PIX = uint8_t, bool WIN = false>
 __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __restrict__ streams,
                                                            const int2* __restrict__ work,
                                                            const StartSlot* __restrict__ start,
-                                                           TrackOut* __restrict__ outs, uint32_t tag_base,
-                                                           int spin_limit) {
+                                                           TrackOut* __restrict__ out_ring, int slot, int n_out,
+                                                           int n_frames, uint32_t tag_base, int spin_limit) {
   static_assert(!(MIXED && FIXED), "the fixed-H mode computes in FP32");
   static_assert(!(MIXED && GENERIC) && (GENERIC || std::is_same<PIX, uint8_t>::value), "variant");
   using PR = typename std::conditional<GENERIC, PointGeo,
@@ -283,157 +289,228 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
   const int chunk = w.y, nch = ss.n_chunks;
   const int i = chunk * PPC + (GENERIC ? (int)threadIdx.x / kLanesPerPoint : (int)threadIdx.x);
   const int sub = GENERIC ? (int)threadIdx.x % kLanesPerPoint : 0;
-  const PIX* cur = FLOAT_PYR ? reinterpret_cast<const PIX*>(a.curf) : reinterpret_cast<const PIX*>(a.cur);
-  // pose state, identical in every thread of every chunk of the stream
-  float T[12];
-  double Td[MIXED ? 12 : 1];
-#pragma unroll
-  for (int j = 0; j < 12; ++j) {
-    T[j] = (float)sh_T0[j];
-    if (MIXED) Td[j] = sh_T0[j];
-  }
-  int status = 0, iterations = 0;
-  int ipl[kMaxLevels];
-#pragma unroll
-  for (int j = 0; j < kMaxLevels; ++j) ipl[j] = 0;
+  const int nf = WIN ? n_frames : 1;
   uint32_t tag = tag_base;
-  int64_t samples = 0;
-  bool stop = false, timed_out = false;
-  PR pr;
-  for (int l = a.levels - 1; l >= 0 && !stop; --l) {
-    const LevelGeom g = a.lv[l];
-    const PIX* img = cur + g.off;
-    if constexpr (GENERIC)
-      load_point_geo(a, l, i, pr);
-    else
-      load_point(a, l, i, pr);
-    if constexpr (FIXED) {
-      // read by every thread after the next exchange's barrier; the other
-      // parity's copy may still be in use by a previous level's solve
-      const FixedH& f = a.ref.fixed[l];
-      if (threadIdx.x < 21) sh_fac[l & 1][threadIdx.x] = f.L[threadIdx.x];
-      if (threadIdx.x >= 32 && threadIdx.x < 38) sh_fac[l & 1][21 + threadIdx.x - 32] = f.invd[threadIdx.x - 32];
-      if (threadIdx.x == 40) sh_fac[l & 1][27] = f.bad ? 1.0f : 0.0f;
+  // WIN: the frames of the launch in order, each from the constant-velocity
+  // prediction of the history the previous one extended.  Every chunk keeps its
+  // own copy of the history in LDS: the poses are bitwise identical in all
+  // chunks of a stream, so no exchange is needed between frames.
+  for (int f = 0; f < nf; ++f) {
+    if (WIN && f > 0) const_velocity_start(sh_T0, sh_rw, sh_h0, sh_h1, sh_m1, sh_m2);
+    const PIX* cur = WIN        ? reinterpret_cast<const PIX*>(ss.win + f * ss.win_stride)
+                     : FLOAT_PYR ? reinterpret_cast<const PIX*>(a.curf)
+                                 : reinterpret_cast<const PIX*>(a.cur);
+    // pose state, identical in every thread of every chunk of the stream
+    float T[12];
+    double Td[MIXED ? 12 : 1];
+#pragma unroll
+    for (int j = 0; j < 12; ++j) {
+      T[j] = (float)sh_T0[j];
+      if (MIXED) Td[j] = sh_T0[j];
     }
-    bool converged = false;
-    for (int it = 0; it < a.max_iters; ++it) {
+    int status = 0, iterations = 0;
+    int ipl[kMaxLevels];
+#pragma unroll
+    for (int j = 0; j < kMaxLevels; ++j) ipl[j] = 0;
+    int64_t samples = 0;
+    bool stop = false, timed_out = false;
+    PR pr;
+    for (int l = a.levels - 1; l >= 0 && !stop; --l) {
+      const LevelGeom g = a.lv[l];
+      const PIX* img = cur + g.off;
+      if constexpr (GENERIC)
+        load_point_geo(a, l, i, pr);
+      else
+        load_point(a, l, i, pr);
+      if constexpr (FIXED) {
+        // read by every thread after the next exchange's barrier; the other
+        // parity's copy may still be in use by a previous level's solve
+        const FixedH& fh = a.ref.fixed[l];
+        if (threadIdx.x < 21) sh_fac[l & 1][threadIdx.x] = fh.L[threadIdx.x];
+        if (threadIdx.x >= 32 && threadIdx.x < 38) sh_fac[l & 1][21 + threadIdx.x - 32] = fh.invd[threadIdx.x - 32];
+        if (threadIdx.x == 40) sh_fac[l & 1][27] = fh.bad ? 1.0f : 0.0f;
+      }
+      bool converged = false;
+      for (int it = 0; it < a.max_iters; ++it) {
+        float acc[NV];
+#pragma unroll
+        for (int j = 0; j < NV; ++j) acc[j] = 0.f;
+        if constexpr (GENERIC)
+          accumulate_point_generic<false, PIX, NV>(a, a.pat, g, img, T, pr, sub, acc);
+        else
+          accumulate_point<false, true, PR, NV>(a, pregs, g, img, T, pr, acc);
+        if (!stream_total<MIXED, NV, GENERIC>(acc, sh_red, sh_tot, &sh_ok, ss.partials, chunk, nch, tag, spin_limit,
+                                              sh_grp)) {
+          timed_out = stop = true;
+          break;
+        }
+        ++tag;
+        samples += (int64_t)sh_tot[sN];
+        if ((int)sh_tot[sP] < a.min_points) {
+          status = 2;  // too few points
+          stop = true;
+          break;
+        }
+        int bad;
+        double step;
+        if (FIXED) {
+          const float* fac = sh_fac[FIXED ? (l & 1) : 0];
+          bad = fac[27] != 0.0f;
+          float stepf = 0.0f;
+          if (!bad) solve_fixed(fac, fac + 21, sh_tot + kFixB, T, &stepf);
+          step = stepf;
+        } else if (MIXED) {
+          bad = solve_update_d(sh_tot, Td, &step);
+          if (!bad)
+#pragma unroll
+            for (int j = 0; j < 12; ++j) T[j] = (float)Td[j];
+        } else {
+          float stepf;
+          bad = solve_update(sh_tot, T, &stepf);
+          step = stepf;
+        }
+        if (bad) {
+          status = 3;  // not positive definite
+          stop = true;
+          break;
+        }
+        ++iterations;
+#pragma unroll
+        for (int j = 0; j < kMaxLevels; ++j) ipl[j] += j == l;
+        if (step < (double)a.step_eps) {
+          converged = true;
+          break;
+        }
+      }
+      if (!stop && l == 0 && !converged) status = 1;  // iteration cap at level 0
+    }
+    if (!timed_out) {  // final cost-only pass at level 0
       float acc[NV];
 #pragma unroll
       for (int j = 0; j < NV; ++j) acc[j] = 0.f;
-      if constexpr (GENERIC)
-        accumulate_point_generic<false, PIX, NV>(a, a.pat, g, img, T, pr, sub, acc);
-      else
-        accumulate_point<false, true, PR, NV>(a, pregs, g, img, T, pr, acc);
-      if (!stream_total<MIXED, NV, GENERIC>(acc, sh_red, sh_tot, &sh_ok, ss.partials, chunk, nch, tag, spin_limit, sh_grp)) {
-        timed_out = stop = true;
-        break;
-      }
-      ++tag;
-      samples += (int64_t)sh_tot[sN];
-      if ((int)sh_tot[sP] < a.min_points) {
-        status = 2;  // too few points
-        stop = true;
-        break;
-      }
-      int bad;
-      double step;
-      if (FIXED) {
-        const float* fac = sh_fac[FIXED ? (l & 1) : 0];
-        bad = fac[27] != 0.0f;
-        float stepf = 0.0f;
-        if (!bad) solve_fixed(fac, fac + 21, sh_tot + kFixB, T, &stepf);
-        step = stepf;
-      } else if (MIXED) {
-        bad = solve_update_d(sh_tot, Td, &step);
-        if (!bad)
-#pragma unroll
-          for (int j = 0; j < 12; ++j) T[j] = (float)Td[j];
+      const LevelGeom g = a.lv[0];
+      if constexpr (GENERIC) {
+        load_point_geo(a, 0, i, pr);
+        accumulate_point_generic<true, PIX, NV>(a, a.pat, g, cur + g.off, T, pr, sub, acc);
       } else {
-        float stepf;
-        bad = solve_update(sh_tot, T, &stepf);
-        step = stepf;
+        load_point(a, 0, i, pr);
+        accumulate_point<true, true, PR, NV>(a, pregs, g, cur + g.off, T, pr, acc);
       }
-      if (bad) {
-        status = 3;  // not positive definite
-        stop = true;
-        break;
+      if (!stream_total<MIXED, NV, GENERIC>(acc, sh_red, sh_tot, &sh_ok, ss.partials, chunk, nch, tag, spin_limit,
+                                            sh_grp))
+        timed_out = true;
+      ++tag;
+    }
+    if constexpr (!WIN) {
+      if (chunk == 0 && threadIdx.x == 0) {
+        TrackOut* o = out_ring + (size_t)slot * n_out + w.x;
+        double Tf[12];
+        for (int j = 0; j < 12; ++j) Tf[j] = MIXED ? Td[j] : (double)T[j];
+        orthonormalize34(Tf);
+        for (int j = 0; j < 12; ++j) {
+          o->T[j] = T[j];
+          o->Td[j] = Tf[j];
+        }
+        // the pose history gains this track's estimate T_cw = T_rel T_rw (every
+        // chunk read the history at its start, before its first exchange)
+        for (int j = 0; j < 12; ++j) {
+          ss.hist[j] = sh_h1[j];
+          ss.hist[12 + j] = compose34_elem(Tf, sh_rw, j);
+        }
+        o->E = sh_tot[sE];
+        o->n = sh_tot[sN];
+        o->iterations = iterations;
+        for (int j = 0; j < kMaxLevels; ++j) o->iters_per_level[j] = ipl[j];
+        o->n_valid_points = (int)sh_tot[sP];
+        o->status = timed_out ? kStatusTimeout : status;
+        o->samples = samples + (int64_t)sh_tot[sN];
       }
-      ++iterations;
-#pragma unroll
-      for (int j = 0; j < kMaxLevels; ++j) ipl[j] += j == l;
-      if (step < (double)a.step_eps) {
-        converged = true;
-        break;
+      return;
+    }
+    if (threadIdx.x == 0) {
+      double Tf[12];
+      for (int j = 0; j < 12; ++j) Tf[j] = MIXED ? Td[j] : (double)T[j];
+      orthonormalize34(Tf);
+      for (int j = 0; j < 12; ++j) sh_m1[j] = Tf[j];
+      if (chunk == 0) {
+        TrackOut* o = out_ring + (size_t)((slot + f) % kRing) * n_out + w.x;
+        for (int j = 0; j < 12; ++j) {
+          o->T[j] = T[j];
+          o->Td[j] = Tf[j];
+        }
+        o->E = sh_tot[sE];
+        o->n = sh_tot[sN];
+        o->iterations = iterations;
+        for (int j = 0; j < kMaxLevels; ++j) o->iters_per_level[j] = ipl[j];
+        o->n_valid_points = (int)sh_tot[sP];
+        o->status = timed_out ? kStatusTimeout : status;
+        o->samples = samples + (int64_t)sh_tot[sN];
+        // a chunk gave up: so do the frames after this one
+        if (timed_out)
+          for (int q = f + 1; q < nf; ++q) out_ring[(size_t)((slot + q) % kRing) * n_out + w.x].status = kStatusTimeout;
       }
     }
-    if (!stop && l == 0 && !converged) status = 1;  // iteration cap at level 0
+    __syncthreads();
+    // the history gains this frame's estimate T_cw = T_rel T_rw
+    if (threadIdx.x < 12) {
+      const double v = compose34_elem(sh_m1, sh_rw, threadIdx.x);
+      sh_h0[threadIdx.x] = sh_h1[threadIdx.x];
+      sh_h1[threadIdx.x] = v;
+    }
+    __syncthreads();
+    if (timed_out) break;
   }
-  if (!timed_out) {  // final cost-only pass at level 0
-    float acc[NV];
-#pragma unroll
-    for (int j = 0; j < NV; ++j) acc[j] = 0.f;
-    const LevelGeom g = a.lv[0];
-    if constexpr (GENERIC) {
-      load_point_geo(a, 0, i, pr);
-      accumulate_point_generic<true, PIX, NV>(a, a.pat, g, cur + g.off, T, pr, sub, acc);
-    } else {
-      load_point(a, 0, i, pr);
-      accumulate_point<true, true, PR, NV>(a, pregs, g, a.cur + g.off, T, pr, acc);
-    }
-    if (!stream_total<MIXED, NV, GENERIC>(acc, sh_red, sh_tot, &sh_ok, ss.partials, chunk, nch, tag, spin_limit, sh_grp))
-      timed_out = true;
-  }
-  if (chunk == 0 && threadIdx.x == 0) {
-    TrackOut* o = outs + w.x;
-    double Tf[12];
-    for (int j = 0; j < 12; ++j) Tf[j] = MIXED ? Td[j] : (double)T[j];
-    orthonormalize34(Tf);
-    for (int j = 0; j < 12; ++j) {
-      o->T[j] = T[j];
-      o->Td[j] = Tf[j];
-    }
-    // the pose history gains this track's estimate T_cw = T_rel T_rw (every
-    // chunk read the history at its start, before its first exchange)
-    for (int j = 0; j < 12; ++j) {
-      ss.hist[j] = sh_h1[j];
-      ss.hist[12 + j] = compose34_elem(Tf, sh_rw, j);
-    }
-    o->E = sh_tot[sE];
-    o->n = sh_tot[sN];
-    o->iterations = iterations;
-    for (int j = 0; j < kMaxLevels; ++j) o->iters_per_level[j] = ipl[j];
-    o->n_valid_points = (int)sh_tot[sP];
-    o->status = timed_out ? kStatusTimeout : status;
-    o->samples = samples + (int64_t)sh_tot[sN];
+  // the stream's history for the next launch (every chunk read it at its start,
+  // before its first exchange)
+  if (WIN && chunk == 0 && threadIdx.x < 12) {
+    ss.hist[threadIdx.x] = sh_h0[threadIdx.x];
+    ss.hist[12 + threadIdx.x] = sh_h1[threadIdx.x];
   }
 }
 
+// The kernel of a variant (kCoop* bits); WIN: the window form.  Null for a
+// combination that does not exist (a generic variant at another chunk size,
+// window tracking of the floating-point pyramid).
+template <int CH, bool WIN>
+static const void* coop_fn(int variant) {
+  if (variant & kCoopGeneric) {
+    if (CH != kGenericThreads) return nullptr;
+    constexpr int G = kGenericThreads;
+    switch (variant & (kCoopFixedH | kCoopFloatPyr)) {
+      case 0: return reinterpret_cast<const void*>(&coop_track_kernel<G, false, false, true, uint8_t, WIN>);
+      case kCoopFixedH: return reinterpret_cast<const void*>(&coop_track_kernel<G, false, true, true, uint8_t, WIN>);
+      case kCoopFloatPyr:
+        return WIN ? nullptr : reinterpret_cast<const void*>(&coop_track_kernel<G, false, false, true, float>);
+      default: return WIN ? nullptr : reinterpret_cast<const void*>(&coop_track_kernel<G, false, true, true, float>);
+    }
+  }
+  switch (variant) {
+    case kCoopFP32: return reinterpret_cast<const void*>(&coop_track_kernel<CH, false, false, false, uint8_t, WIN>);
+    case kCoopMixed: return reinterpret_cast<const void*>(&coop_track_kernel<CH, true, false, false, uint8_t, WIN>);
+    case kCoopFixedH: return reinterpret_cast<const void*>(&coop_track_kernel<CH, false, true, false, uint8_t, WIN>);
+    default: return nullptr;
+  }
+}
+
+// Co-resident workgroups per CU: the least over every variant at this chunk size.
 template <int CH>
 static int coop_blocks_per_cu() {
   static int nb = -1;
   if (nb < 0) {
-    int v = 0, v2 = 0, v3 = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, coop_track_kernel<CH, false, false>, CH, 0) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&v2, coop_track_kernel<CH, true, false>, CH, 0) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&v3, coop_track_kernel<CH, false, true>, CH, 0) != hipSuccess) {
-      (void)hipGetLastError();
-      v = v2 = v3 = 0;
-    }
-    nb = std::min(v, std::min(v2, v3));
-    if (CH == kGenericThreads) {
-      const void* gk[] = {reinterpret_cast<const void*>(&coop_track_kernel<kGenericThreads, false, false, true>),
-                          reinterpret_cast<const void*>(&coop_track_kernel<kGenericThreads, false, true, true>),
-                          reinterpret_cast<const void*>(&coop_track_kernel<kGenericThreads, false, false, true, float>),
-                          reinterpret_cast<const void*>(&coop_track_kernel<kGenericThreads, false, true, true, float>)};
-      for (const void* f : gk) {
-        int vg = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&vg, f, CH, 0) != hipSuccess) {
+    const int vs[] = {kCoopFP32, kCoopMixed, kCoopFixedH, kCoopGeneric, kCoopGeneric | kCoopFixedH,
+                      kCoopGeneric | kCoopFloatPyr, kCoopGeneric | kCoopFixedH | kCoopFloatPyr};
+    int best = 1 << 30;
+    for (int v : vs)
+      for (const void* f : {coop_fn<CH, false>(v), coop_fn<CH, true>(v)}) {
+        if (!f) continue;
+        int k = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&k, f, CH, 0) != hipSuccess) {
           (void)hipGetLastError();
-          vg = 0;
+          k = 0;
         }
-        nb = std::min(nb, vg);
+        best = std::min(best, k);
       }
-    }
+    nb = best;
   }
   return nb;
 }
@@ -472,34 +549,30 @@ int coop_max_blocks(int chunk) {
 // into a reported timeout, not a hang.
 template <int CH>
 static hipError_t coop_launch_k(const CoopStream* d_streams, const int2* d_work, int n_work, const StartSlot* start,
-                                TrackOut* out, uint32_t tag_base, int variant, int spin_limit, hipStream_t s) {
-  void* args[] = {(void*)&d_streams, (void*)&d_work, (void*)&start, (void*)&out, (void*)&tag_base,
-                  (void*)&spin_limit};
-  const void* fn = nullptr;
-  if (variant & kCoopGeneric) {
-    if (CH != kGenericThreads) return hipErrorInvalidValue;
-    constexpr int G = kGenericThreads;
-    switch (variant & (kCoopFixedH | kCoopFloatPyr)) {
-      case 0: fn = reinterpret_cast<const void*>(&coop_track_kernel<G, false, false, true>); break;
-      case kCoopFixedH: fn = reinterpret_cast<const void*>(&coop_track_kernel<G, false, true, true>); break;
-      case kCoopFloatPyr: fn = reinterpret_cast<const void*>(&coop_track_kernel<G, false, false, true, float>); break;
-      default: fn = reinterpret_cast<const void*>(&coop_track_kernel<G, false, true, true, float>); break;
-    }
-  } else {
-    fn = variant == kCoopMixed    ? reinterpret_cast<const void*>(&coop_track_kernel<CH, true, false>)
-         : variant == kCoopFixedH ? reinterpret_cast<const void*>(&coop_track_kernel<CH, false, true>)
-                                  : reinterpret_cast<const void*>(&coop_track_kernel<CH, false, false>);
-  }
+                                TrackOut* out_ring, int slot, int n_out, int n_frames, uint32_t tag_base, int variant,
+                                int spin_limit, hipStream_t s) {
+  void* args[] = {(void*)&d_streams, (void*)&d_work,   (void*)&start,    (void*)&out_ring, (void*)&slot,
+                  (void*)&n_out,     (void*)&n_frames, (void*)&tag_base, (void*)&spin_limit};
+  const void* fn = n_frames > 0 ? coop_fn<CH, true>(variant) : coop_fn<CH, false>(variant);
+  if (!fn) return hipErrorInvalidValue;
   if (4 * n_work <= coop_max_blocks(CH)) return hipLaunchKernel(fn, dim3(n_work), dim3(CH), args, 0, s);
   return hipLaunchCooperativeKernel(fn, dim3(n_work), dim3(CH), args, 0, s);
 }
 
 hipError_t launch_coop_track(const CoopStream* d_streams, const int2* d_work, int n_work, const StartSlot* start,
-                             TrackOut* out, uint32_t tag_base, int chunk, int variant, int spin_limit, hipStream_t s) {
+                             TrackOut* out_ring, int slot, int n_out, int n_frames, uint32_t tag_base, int chunk,
+                             int variant, int spin_limit, hipStream_t s) {
+  if (slot < 0 || slot >= kRing || n_frames < 0 || n_frames > kRing) return hipErrorInvalidValue;
   switch (chunk) {
-    case 64: return coop_launch_k<64>(d_streams, d_work, n_work, start, out, tag_base, variant, spin_limit, s);
-    case 128: return coop_launch_k<128>(d_streams, d_work, n_work, start, out, tag_base, variant, spin_limit, s);
-    case 256: return coop_launch_k<256>(d_streams, d_work, n_work, start, out, tag_base, variant, spin_limit, s);
+    case 64:
+      return coop_launch_k<64>(d_streams, d_work, n_work, start, out_ring, slot, n_out, n_frames, tag_base, variant,
+                               spin_limit, s);
+    case 128:
+      return coop_launch_k<128>(d_streams, d_work, n_work, start, out_ring, slot, n_out, n_frames, tag_base, variant,
+                                spin_limit, s);
+    case 256:
+      return coop_launch_k<256>(d_streams, d_work, n_work, start, out_ring, slot, n_out, n_frames, tag_base, variant,
+                                spin_limit, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -555,11 +628,13 @@ void CoopEngine::release() {
   partial_words = 0;
 }
 
-void CoopEngine::set_stream(int k, const TrackArgs& a, double* hist) {
+void CoopEngine::set_stream(int k, const TrackArgs& a, double* hist, const uint8_t* win, int64_t win_stride) {
   CoopStream& c = h_streams[k];
   c.a = a;
   c.a.out = nullptr;  // results go to the launch's slot of h_out
   c.hist = hist;
+  c.win = win;
+  c.win_stride = win_stride;
   c.n_chunks = a.ref.n > 0 ? (a.ref.n + ppc - 1) / ppc : 1;
   dirty = true;
 }
@@ -611,17 +686,18 @@ hipError_t CoopEngine::upload() {
 
 int CoopEngine::grid() const { return (int)h_work.size(); }
 
-hipError_t CoopEngine::launch(int spin_limit, int slot) {
+hipError_t CoopEngine::launch(int spin_limit, int slot, int n_frames) {
   hipError_t e;
-  if (slot < 0 || slot >= kRing) return hipErrorInvalidValue;
+  if (slot < 0 || slot >= kRing || n_frames < 0 || n_frames > kRing) return hipErrorInvalidValue;
   if (dirty && (e = upload()) != hipSuccess) return e;
-  // tags used by this launch: at most levels * max_iters + 1 epochs per stream
+  // tags used by this launch: at most levels * max_iters + 1 epochs per stream and frame
   uint32_t span = 1;
   for (const CoopStream& c : h_streams) span = std::max(span, (uint32_t)(c.a.levels * c.a.max_iters + 1));
+  span *= (uint32_t)std::max(n_frames, 1);
   if (tag_base > 0xFFFFFFFFu - span) {  // wrap: restart the tags on cleared words
     if ((e = clear_partials()) != hipSuccess) return e;
   }
-  e = launch_coop_track(d_streams, d_work, grid(), dv_start + (size_t)slot * n, dv_out + (size_t)slot * n, tag_base,
+  e = launch_coop_track(d_streams, d_work, grid(), dv_start + (size_t)slot * n, dv_out, slot, n, n_frames, tag_base,
                         chunk, variant, spin_limit, stream);
   tag_base += span;
   return e;
@@ -701,6 +777,37 @@ hipError_t launch_pyramid_batch_args(const PyrJob* d_static, const PyrSrcArgs& s
   else
     hipLaunchKernelGGL(pyramid_batch_args_kernel<128>, dim3((max_w + 127) / 128, (max_h + 127) / 128, n_jobs),
                        dim3(256), 0, s, d_static, srcs);
+  return hipGetLastError();
+}
+
+// Window pyramids: blockIdx.z = stream * n_frames + frame.
+template <int TILE>
+__global__ __launch_bounds__(256) void pyramid_window_kernel(const WinJob* __restrict__ jobs, PyrWinSrc srcs,
+                                                             int n_frames) {
+  const int z = blockIdx.z, js = z / n_frames, f = z - js * n_frames;
+  const WinJob& j = jobs[js];
+  if ((int)blockIdx.x * TILE >= j.g.W[0] || (int)blockIdx.y * TILE >= j.g.H[0]) return;
+  const uint8_t* src = srcs.src[js] + f * srcs.stride[js];
+  uint8_t* dst = j.dst + f * j.dst_stride;
+  const int64_t pitch = srcs.pitch[js];
+  const uintptr_t sa = reinterpret_cast<uintptr_t>(src), da = reinterpret_cast<uintptr_t>(dst);
+  const int W0 = j.g.W[0];
+  if (TILE == 64 && (pitch % 16) == 0 && (sa % 16) == 0 && (W0 % 16) == 0 && (da % 16) == 0)
+    pyramid_tile64v(src, pitch, dst, j.g);
+  else
+    pyramid_tile<TILE>(src, pitch, dst, j.g, ((pitch % 4) == 0 && (sa % 4) == 0 && (W0 % 4) == 0 && (da % 4) == 0) ? 1 : 0);
+}
+
+hipError_t launch_pyramid_window(const WinJob* d_jobs, const PyrWinSrc& srcs, int n_streams, int n_frames, int max_w,
+                                 int max_h, int levels, hipStream_t s) {
+  if (n_streams < 1 || n_streams > kPyrArgJobs || n_frames < 1 || (int64_t)n_streams * n_frames > 65535)
+    return hipErrorInvalidValue;
+  if (levels <= 7)
+    hipLaunchKernelGGL(pyramid_window_kernel<64>, dim3((max_w + 63) / 64, (max_h + 63) / 64, n_streams * n_frames),
+                       dim3(256), 0, s, d_jobs, srcs, n_frames);
+  else
+    hipLaunchKernelGGL(pyramid_window_kernel<128>, dim3((max_w + 127) / 128, (max_h + 127) / 128, n_streams * n_frames),
+                       dim3(256), 0, s, d_jobs, srcs, n_frames);
   return hipGetLastError();
 }
 

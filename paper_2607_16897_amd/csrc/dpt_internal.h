@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/dptrack.h"
+
 #include <algorithm>
 #include <vector>
 
@@ -150,6 +152,8 @@ struct CoopStream {
   TrackArgs a;
   uint64_t* partials;  // [2][n_chunks][32] chunk sums, each word = (tag << 32) | float bits
   double* hist;        // the stream's last two poses T_cw, 2 x 3x4 row-major FP64 (device)
+  const uint8_t* win;  // window tracking: the pyramids of consecutive frames, win_stride bytes apart
+  int64_t win_stride;
   int32_t n_chunks;
   int32_t pad;
 };
@@ -184,7 +188,7 @@ struct StartSlot {
   double pad1[4];
 };
 constexpr int kStartGiven = 0, kStartConstVelocity = 1;
-constexpr int kRing = 64;  // tracks that may be in flight per context or batch
+constexpr int kRing = DPT_MAX_IN_FLIGHT;  // tracks that may be in flight per context or batch
 
 // One image of a batched pyramid launch.
 struct PyrJob {
@@ -227,14 +231,16 @@ struct CoopEngine {
   TrackOut* dv_out = nullptr;     // device view of h_out
   hipError_t init(int n_streams, const int* max_points, int chunk, int ppc, bool xcd_pack, hipStream_t s);
   void release();
-  void set_stream(int k, const TrackArgs& a, double* hist);
+  void set_stream(int k, const TrackArgs& a, double* hist, const uint8_t* win, int64_t win_stride);
   hipError_t upload();
   int grid() const;
   StartSlot* start(int slot) { return h_start + (size_t)slot * n; }
   TrackOut* out(int slot) { return h_out + (size_t)slot * n; }
   // Enqueue the track of every stream from start slot `slot`; its results land
-  // in out(slot) once the stream reaches this point.
-  hipError_t launch(int spin_limit, int slot);
+  // in out(slot) once the stream reaches this point.  n_frames > 0: track that
+  // many consecutive frames of each stream's window pyramids in one launch,
+  // frame f's results in out((slot + f) % kRing).
+  hipError_t launch(int spin_limit, int slot, int n_frames = 0);
   hipError_t clear_partials();
   ~CoopEngine() { release(); }
 };
@@ -277,8 +283,13 @@ hipError_t launch_track_batch(const TrackArgs& any, const TrackArgs* batch, int 
                               int max_points, hipStream_t s);
 int track_lds_bytes(const LevelGeom* lv, int levels, int pixel_bytes);  // pixel_bytes: 1 uint8, 4 float
 hipError_t launch_normal_equations(const TrackArgs& a, hipStream_t s);
+// start: the start slots of `slot` (one per stream); out_ring: the kRing x n_out
+// result ring (frame f of the launch writes slot (slot + f) % kRing);
+// n_frames = 0: one frame from each stream's current pyramid (a.cur / a.curf),
+// n_frames > 0: that many frames from the streams' window pyramids.
 hipError_t launch_coop_track(const CoopStream* d_streams, const int2* d_work, int n_work, const StartSlot* start,
-                             TrackOut* out, uint32_t tag_base, int chunk, int variant, int spin_limit, hipStream_t s);
+                             TrackOut* out_ring, int slot, int n_out, int n_frames, uint32_t tag_base, int chunk,
+                             int variant, int spin_limit, hipStream_t s);
 // Set a pose history (two row-major 4x4 T_cw) on the stream.
 hipError_t launch_set_history(double* hist, const double* T0, const double* T1, hipStream_t s);
 // Pose histories of n streams: d_vals[24 s ..] = (older, newer) 3x4 into d_hists[s] (device arrays).
@@ -294,5 +305,21 @@ struct PyrSrcArgs {
 };
 hipError_t launch_pyramid_batch_args(const PyrJob* d_static, const PyrSrcArgs& srcs, int n_jobs, int max_w,
                                      int max_h, int levels, hipStream_t s);
+// Window tracking: the box pyramids of n_frames consecutive frames of up to
+// kPyrArgJobs streams in one launch.  Frame f of stream s is read from
+// src[s] + f * stride[s] (rows pitch[s] apart) and its pyramid written to
+// jobs[s].dst + f * jobs[s].dst_stride.
+struct WinJob {
+  uint8_t* dst;
+  int64_t dst_stride;
+  PyrGeom g;
+};
+struct PyrWinSrc {
+  const uint8_t* src[kPyrArgJobs];
+  int64_t pitch[kPyrArgJobs];
+  int64_t stride[kPyrArgJobs];
+};
+hipError_t launch_pyramid_window(const WinJob* d_jobs, const PyrWinSrc& srcs, int n_streams, int n_frames, int max_w,
+                                 int max_h, int levels, hipStream_t s);
 
 }  // namespace dpt

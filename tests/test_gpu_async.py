@@ -121,14 +121,14 @@ def test_given_enqueue_equals_track_frame_and_ring_limit(gpu_lib):
     trk.build_pyramid(dpt.SLOT_REF, d["ref"])
     trk.set_reference_points(P, d["T_rw"])
     trk.build_pyramid(dpt.SLOT_CUR, d["cur"])
-    starts = [synth.random_perturbation(np.random.default_rng([4, i]), 0.5, 0.01) for i in range(64)]
+    starts = [synth.random_perturbation(np.random.default_rng([4, i]), 0.5, 0.01) for i in range(dpt.MAX_IN_FLIGHT)]
     want = [trk.track(T) for T in starts[:5]]
     for T in starts:
         trk.track_enqueue(T)
-    with pytest.raises(dpt.DptError):  # a 65th track in flight
+    with pytest.raises(dpt.DptError):  # one track more than the ring holds
         trk.track_enqueue(starts[0])
     got = trk.synchronize()
-    assert len(got) == 64
+    assert len(got) == dpt.MAX_IN_FLIGHT
     for g, s in zip(got, want):
         np.testing.assert_array_equal(g["T_cw"], s["T_cw"])
         assert g["iterations"] == s["iterations"] and g["final_cost"] == s["final_cost"]

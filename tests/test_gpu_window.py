@@ -1,0 +1,182 @@
+"""Window tracking (dpt_track_window_enqueue, dpt_batch_track_window_enqueue):
+the tween frames of one reference (Sec. III) tracked in order by one pyramid
+launch and one cooperative track launch.  The poses, costs, iteration counts
+and statuses must be bitwise those of the frame-by-frame calls (pyramid build +
+track from the constant-velocity prediction), the pose history must end in the
+same state, and each frame must match the oracle started from the same
+prediction."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import tween
+
+pytestmark = pytest.mark.gpu
+
+ROT_TOL, TR_TOL, COST_TOL = 1e-4, 1e-4, 1e-3
+FIELDS = ("T_cw", "final_cost", "iterations", "iters_per_level", "n_valid_points", "status", "samples")
+
+
+def _sequence(seed, cam, n_frames):
+    """Keyframe (image, depth, pose), the pose before it, and n_frames tween frames."""
+    traj, scene = synth.Trajectory(seed), synth.Scene(seed)
+    k0 = 40
+    img0, depth = scene.render(cam, traj.T_cw(k0), synth.pixel_noise(seed, k0, cam, 2.0), want_depth=True)
+    frames = np.stack([scene.render(cam, traj.T_cw(k0 + j), synth.pixel_noise(seed, k0 + j, cam, 2.0),
+                                    want_depth=False)[0] for j in range(1, n_frames + 1)])
+    return dict(img0=img0, depth=depth.astype(np.float32), T0=traj.T_cw(k0), T_prev=traj.T_cw(k0 - 1),
+                frames=frames, gts=[traj.T_cw(k0 + j) for j in range(1, n_frames + 1)])
+
+
+def _tracker(dpt, cam, seq, n, prm, launch=(0, 256)):
+    trk = dpt.Tracker(cam, prm, max_points=n)
+    trk.set_launch_config(*launch)
+    trk.build_pyramid(dpt.SLOT_REF, seq["img0"])
+    trk.set_reference_from_depth(n, seq["depth"], seq["T0"])
+    trk.set_pose_history(seq["T_prev"], seq["T0"])
+    return trk
+
+
+def _per_frame(dpt, trk, frames, T_first=None):
+    for j, im in enumerate(frames):
+        trk.build_pyramid(dpt.SLOT_CUR, im)
+        trk.track_enqueue(T_first if j == 0 else None)
+    return trk.synchronize()
+
+
+def _assert_same(a, b):
+    for f, (x, y) in enumerate(zip(a, b)):
+        for k in FIELDS:
+            np.testing.assert_array_equal(np.asarray(x[k]), np.asarray(y[k]), err_msg=f"frame {f} field {k}")
+
+
+VARIANTS = {
+    "fp32": dict(levels=4),
+    "mixed": dict(levels=4, precision=1),
+    "fixed_h": dict(levels=4, fixed_h=True),
+    "square5": dict(levels=4, pattern=synth.square_pattern(5)),
+}
+
+
+@pytest.mark.parametrize("variant", list(VARIANTS))
+def test_window_equals_frame_by_frame(gpu_lib, variant):
+    import torch
+
+    dpt = gpu_lib
+    cam, n = synth.CAM_752, 2000
+    seq = _sequence(11, cam, 9)
+    prm = dpt.make_params(**VARIANTS[variant])
+    a = _tracker(dpt, cam, seq, n, prm)
+    ra = _per_frame(dpt, a, seq["frames"])
+    b = _tracker(dpt, cam, seq, n, prm)
+    b.track_window_enqueue(torch.from_numpy(seq["frames"]).cuda())
+    rb = b.synchronize()
+    assert len(rb) == 9
+    _assert_same(ra, rb)
+    assert all(r["status"] in (0, 1) for r in ra)
+    # both histories end at the window's last two poses: one more frame agrees
+    nxt = _sequence(11, cam, 10)["frames"][9:]
+    _assert_same(_per_frame(dpt, a, nxt), _per_frame(dpt, b, nxt))
+
+
+def test_window_host_frames_given_start_and_oracle(gpu_lib):
+    """Host frames, a given start for frame 0; every frame against the oracle
+    started from the constant-velocity prediction of the GPU's previous poses."""
+    dpt = gpu_lib
+    cam, n = synth.CAM_640, 800
+    seq = _sequence(5, cam, 6)
+    prm = dpt.make_params(levels=3)
+    T_first = seq["gts"][0] @ oracle.se3_exp(np.array([0.002, -0.001, 0.001, 0.004, -0.002, 0.003]))
+    a = _tracker(dpt, cam, seq, n, prm)
+    ra = _per_frame(dpt, a, seq["frames"], T_first)
+    b = _tracker(dpt, cam, seq, n, prm)
+    b.track_window_enqueue(seq["frames"], T_cw_init=T_first)
+    rb = b.synchronize()
+    _assert_same(ra, rb)
+    # the oracle: the same map (selected and back-projected by the oracle's own code)
+    idx = oracle.select_points(seq["img0"], n, 8)
+    P = tween.backproject(cam, seq["depth"], idx, seq["T0"])
+    ref = oracle.Reference(cam, oracle.make_params(levels=3), seq["img0"], P, seq["T0"])
+    prev2, prev1 = seq["T_prev"], seq["T0"]
+    for f, r in enumerate(rb):
+        start = T_first if f == 0 else tween.cv_start(prev2, prev1)
+        o = ref.track(seq["frames"][f], start)
+        rot, tr = oracle.pose_error(np.asarray(r["T_cw"]).reshape(4, 4), o["T_cw"])
+        rel = abs(r["final_cost"] - o["final_cost"]) / max(o["final_cost"], 1e-12)
+        print(f"frame {f}: rot {rot:.2e} tr {tr:.2e} cost {rel:.2e} iters {r['iterations']}/{o['iterations']}")
+        assert r["status"] == o["status"] and r["status"] in (0, 1)
+        assert rot < ROT_TOL and tr < TR_TOL and rel < COST_TOL
+        prev2, prev1 = prev1, np.asarray(r["T_cw"]).reshape(4, 4)
+
+
+def test_batch_window_equals_frame_by_frame(gpu_lib):
+    """Three streams of different resolutions and map sizes; the window results
+    equal the batched frame-by-frame ones stream by stream, frame by frame."""
+    import torch
+
+    dpt = gpu_lib
+    cams = [synth.CAM_640, synth.CAM_752, synth.CAM_640]
+    ns = [500, 2000, 1300]
+    seqs = [_sequence(20 + s, cams[s], 7) for s in range(3)]
+    prm = dpt.make_params(levels=4)
+
+    def make():
+        bt = dpt.BatchTracker(cams, prm, ns)
+        bt.build_pyramids(dpt.SLOT_REF, [q["img0"] for q in seqs])
+        for s, q in enumerate(seqs):
+            bt.set_reference_from_depth(s, ns[s], q["depth"], q["T0"])
+            bt.set_pose_history(s, q["T_prev"], q["T0"])
+        return bt
+
+    a = make()
+    for j in range(7):
+        a.build_pyramids(dpt.SLOT_CUR, [q["frames"][j] for q in seqs])
+        a.track_enqueue(None)
+    ra = a.synchronize()
+    b = make()
+    b.track_window_enqueue([torch.from_numpy(q["frames"]).cuda() for q in seqs])
+    rb = b.synchronize()
+    assert len(rb) == 7 and all(len(x) == 3 for x in rb)
+    for j in range(7):
+        _assert_same(ra[j], rb[j])
+    assert all(r["status"] in (0, 1) for x in rb for r in x)
+
+
+def test_window_errors(gpu_lib):
+    import torch
+
+    dpt = gpu_lib
+    cam = synth.CAM_640
+    seq = _sequence(3, cam, 2)
+    frames = torch.from_numpy(seq["frames"]).cuda()
+    trk = dpt.Tracker(cam, dpt.make_params(levels=3), max_points=300)
+    with pytest.raises(dpt.DptError):  # no reference yet
+        trk.track_window_enqueue(frames)
+    trk.build_pyramid(dpt.SLOT_REF, seq["img0"])
+    trk.set_reference_from_depth(300, seq["depth"], seq["T0"])
+    with pytest.raises(dpt.DptError):  # no frames
+        trk.track_window_enqueue(frames[:0])
+    big = frames[:1].expand(dpt.MAX_WINDOW + 1, -1, -1)  # stride 0 between frames, and too many
+    with pytest.raises(dpt.DptError):
+        trk.track_window_enqueue(big)
+    overlap = torch.empty(cam.height * cam.width + cam.width, dtype=torch.uint8, device="cuda")
+    over = overlap.as_strided((2, cam.height, cam.width), (cam.width, cam.width, 1))  # frames overlap
+    with pytest.raises(dpt.DptError):
+        trk.track_window_enqueue(over)
+    trk.set_launch_config(dpt.LAUNCH_WORKGROUP, 256)
+    with pytest.raises(dpt.DptError):  # needs the cooperative track
+        trk.track_window_enqueue(frames)
+    trk.set_launch_config(dpt.LAUNCH_AUTO, 256)
+    many = frames[:1].expand(dpt.MAX_WINDOW, -1, -1)
+    many = many.contiguous()
+    for _ in range(dpt.MAX_IN_FLIGHT // dpt.MAX_WINDOW):  # the ring full
+        trk.track_window_enqueue(many)
+    with pytest.raises(dpt.DptError):
+        trk.track_window_enqueue(frames)
+    assert len(trk.synchronize()) == dpt.MAX_IN_FLIGHT  # the refused window left no results behind
+    g = dpt.Tracker(cam, dpt.make_params(levels=3, gauss=True), max_points=300)
+    g.build_pyramid(dpt.SLOT_REF, seq["img0"])
+    g.set_reference_from_depth(300, seq["depth"], seq["T0"])
+    with pytest.raises(dpt.DptError):  # box pyramids only
+        g.track_window_enqueue(frames)
