@@ -1242,16 +1242,30 @@ int batch_chunks(const dpt_batch* b, int s) {
   return n > 0 ? (n + ppc - 1) / ppc : 1;
 }
 
-// Partition streams into groups that each fit one cooperative launch: a group's
-// XCD-packed grid is at most its chunk total plus 8 slots per largest stream.
+// Grid of the XCD-packed work list (CoopEngine::upload) of streams with these
+// chunk counts, given largest first: each stream goes to the least-loaded of
+// the eight XCDs, block j of XCD x is grid slot 8 j + x, trailing padding cut.
+int packed_grid(const std::vector<int>& chunks_desc) {
+  int load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int c : chunks_desc) *std::min_element(load, load + 8) += c;
+  const int depth = *std::max_element(load, load + 8);
+  if (depth == 0) return 0;
+  int last = 0;
+  for (int x = 0; x < 8; ++x)
+    if (load[x] == depth) last = x;
+  return 8 * (depth - 1) + last + 1;
+}
+
+// Partition streams into groups that each fit one cooperative launch: streams
+// largest first, a group closed when its packed grid would exceed the
+// co-resident capacity.
 int build_groups(dpt_batch* b) {
   b->clear_groups();
   const int cap = coop_max_blocks(coop_threads(b->ctx[0]->prm, b->chunk));
   std::vector<int> order(b->n);
   for (int s = 0; s < b->n; ++s) order[s] = s;
   std::sort(order.begin(), order.end(), [&](int p, int q) { return batch_chunks(b, p) > batch_chunks(b, q); });
-  std::vector<int> cur;
-  int total = 0, largest = 0;
+  std::vector<int> cur, cur_chunks;
   auto flush = [&]() -> int {
     if (cur.empty()) return DPT_OK;
     std::sort(cur.begin(), cur.end());
@@ -1274,19 +1288,21 @@ int build_groups(dpt_batch* b) {
     b->groups.push_back(g);
     b->group_streams.push_back(cur);
     cur.clear();
-    total = largest = 0;
+    cur_chunks.clear();
     return DPT_OK;
   };
   for (int s : order) {
     const int c = batch_chunks(b, s);
-    if (c + 8 * c > cap) return fail(DPT_E_ARG, "stream %d: %d chunks exceed the co-resident capacity %d", s, c, cap);
-    if (!cur.empty() && total + c + 8 * std::max(largest, c) > cap) {
+    if (packed_grid({c}) > cap)
+      return fail(DPT_E_ARG, "stream %d: %d chunks exceed the co-resident capacity %d", s, c, cap);
+    cur_chunks.push_back(c);
+    if (cur.size() > 0 && packed_grid(cur_chunks) > cap) {
+      cur_chunks.pop_back();
       int e = flush();
       if (e != DPT_OK) return e;
+      cur_chunks.push_back(c);
     }
     cur.push_back(s);
-    total += c;
-    largest = std::max(largest, c);
   }
   int e = flush();
   if (e != DPT_OK) return e;

@@ -90,3 +90,58 @@ def test_batch_deterministic_and_reusable(gpu_lib, streams):
     e = bt.track(np.stack([np.eye(4)] * len(streams)))
     assert e[3]["status"] == dpt.TRACK_TOO_FEW_POINTS
     np.testing.assert_array_equal(e[0]["T_cw"], a[0]["T_cw"])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_full_capacity_batch_equals_plain(gpu_lib, precision):
+    """64 streams of 2000 points (8 chunks of 256 each, 512 workgroups: every
+    co-resident slot of the device in one cooperative launch when the XCD
+    packing balances) give, stream by stream, the poses of 64 plain contexts,
+    frame by frame and as window tracks."""
+    import torch
+
+    dpt = gpu_lib
+    cam, n, S = synth.CAM_752, 2000, 64
+    traj, scene = [synth.Trajectory(7000 + s) for s in range(4)], [synth.Scene(7000 + s) for s in range(4)]
+    seqs = []
+    for s in range(4):
+        img0, depth = scene[s].render(cam, traj[s].T_cw(30), synth.pixel_noise(s, 30, cam, 2.0), want_depth=True)
+        frames = np.stack([scene[s].render(cam, traj[s].T_cw(30 + j), synth.pixel_noise(s, 30 + j, cam, 2.0),
+                                           want_depth=False)[0] for j in (1, 2, 3)])
+        seqs.append((img0, depth.astype(np.float32), frames, traj[s].T_cw(29), traj[s].T_cw(30)))
+    prm = dpt.make_params(levels=4, precision=precision)
+    bt = dpt.BatchTracker([cam] * S, prm, [n] * S)
+    bt.set_launch_config(dpt.LAUNCH_COOP, 256)
+    T_rw = np.stack([seqs[s % 4][4] for s in range(S)])
+    T_prev = np.stack([seqs[s % 4][3] for s in range(S)])
+
+    def refresh():
+        bt.build_pyramids(dpt.SLOT_REF, [torch.from_numpy(seqs[s % 4][0]).cuda() for s in range(S)])
+        bt.set_reference_from_depth_all([n] * S, [torch.from_numpy(seqs[s % 4][1]).cuda() for s in range(S)], T_rw)
+        bt.set_pose_history_all(T_prev, T_rw)
+
+    refresh()
+    for j in range(3):
+        bt.build_pyramids(dpt.SLOT_CUR, [torch.from_numpy(seqs[s % 4][2][j]).cuda() for s in range(S)])
+        bt.track_enqueue(None)
+    per_frame = bt.synchronize()
+    refresh()
+    bt.track_window_enqueue([torch.from_numpy(seqs[s % 4][2]).cuda() for s in range(S)])
+    window = bt.synchronize()
+    for j in range(3):
+        for s in range(S):
+            np.testing.assert_array_equal(per_frame[j][s]["T_cw"], window[j][s]["T_cw"])
+    for q in range(4):  # streams q, q + 4, ... saw the same frames: one plain context per sequence
+        t = dpt.Tracker(cam, prm, max_points=n)
+        t.build_pyramid(dpt.SLOT_REF, seqs[q][0])
+        t.set_reference_from_depth(n, seqs[q][1], seqs[q][4])
+        t.set_pose_history(seqs[q][3], seqs[q][4])
+        for j in range(3):
+            t.build_pyramid(dpt.SLOT_CUR, seqs[q][2][j])
+            t.track_enqueue(None)
+        plain = t.synchronize()
+        for j in range(3):
+            assert plain[j]["status"] in (0, 1)
+            for s in range(q, S, 4):
+                np.testing.assert_array_equal(per_frame[j][s]["T_cw"], plain[j]["T_cw"])
+                assert per_frame[j][s]["iterations"] == plain[j]["iterations"]
