@@ -47,7 +47,8 @@ enum {
   DPT_TRACK_OK = 0,             /* converged at level 0 */
   DPT_TRACK_MAX_ITERS = 1,      /* level 0 used all max_iters iterations (pose still returned) */
   DPT_TRACK_TOO_FEW_POINTS = 2, /* fewer than min_points valid points at some iteration */
-  DPT_TRACK_NOT_PD = 3          /* normal matrix not positive definite (Cholesky pivot too small) */
+  DPT_TRACK_NOT_PD = 3,         /* normal matrix not positive definite (Cholesky pivot too small) */
+  DPT_TRACK_TIMEOUT = 4         /* a cooperative wait gave up (dpt_set_spin_limit); the pose is not valid */
 };
 
 /* dpt_params.precision */
@@ -325,6 +326,17 @@ int dpt_get_fixed_hessian(dpt_ctx* ctx, int32_t level, double H36[36], int32_t* 
 enum { DPT_LAUNCH_AUTO = 0, DPT_LAUNCH_WORKGROUP = 1, DPT_LAUNCH_COOP = 2 };
 int dpt_set_launch_config(dpt_ctx* ctx, int32_t mode, int32_t chunk);
 
+/* Bound of the cooperative track's waits: a chunk that polls the other chunks'
+ * partial sums `polls` times without seeing them all gives up, and its frame
+ * (and, in a window track, the frames after it) ends with status
+ * DPT_TRACK_TIMEOUT; the next synchronisation then reports DPT_E_HIP and resets
+ * the exchange, so later tracks start clean.  Default 4194304 (seconds of
+ * polling; reached only if the chunks were not co-resident).  polls = 0 makes
+ * every cross-chunk wait give up at once, which exercises that path; a map of
+ * one chunk never waits.  DPT_E_ARG for polls < 0. */
+#define DPT_DEFAULT_SPIN_LIMIT 4194304
+int dpt_set_spin_limit(dpt_ctx* ctx, int32_t polls);
+
 /* Profiling hook: with enable = N > 0, every N-th pyramid build and every
  * N-th track brackets its kernel with HIP events on the context's stream
  * (each event record is a queue marker of a few microseconds, so N > 1 keeps
@@ -406,6 +418,8 @@ int dpt_batch_track_window_enqueue(dpt_batch* b, const uint8_t* const* frames, c
 
 /* Launch configuration as dpt_set_launch_config, for the whole batch. */
 int dpt_batch_set_launch_config(dpt_batch* b, int32_t mode, int32_t chunk);
+/* Wait bound as dpt_set_spin_limit, for the whole batch. */
+int dpt_batch_set_spin_limit(dpt_batch* b, int32_t polls);
 
 /* Profiling as dpt_set_profiling / dpt_last_kernel_ms / dpt_get_profile: a
  * batched track launch sequence and a batched pyramid launch each count once. */

@@ -18,7 +18,7 @@ LIB_PATH = os.environ.get("DPT_LIBRARY") or os.path.join(_HERE, "libdptrack.so")
 _lib = None
 
 DPT_OK, DPT_E_ARG, DPT_E_HIP, DPT_E_STATE, DPT_E_OOM = 0, -1, -2, -3, -4
-TRACK_OK, TRACK_MAX_ITERS, TRACK_TOO_FEW_POINTS, TRACK_NOT_PD = 0, 1, 2, 3
+TRACK_OK, TRACK_MAX_ITERS, TRACK_TOO_FEW_POINTS, TRACK_NOT_PD, TRACK_TIMEOUT = 0, 1, 2, 3, 4
 PREC_FP32, PREC_MIXED = 0, 1
 FLAG_FIXED_H = 1  # dpt_params.flags: the paper's constant-H track
 FLAG_GAUSS_F32 = 2  # dpt_params.flags: track on the floating-point Gaussian pyramid
@@ -116,6 +116,7 @@ SIGNATURES = {
     "dpt_get_fixed_hessian": (ctypes.c_int, [_vp, _i32, _vp, ctypes.POINTER(_i32)]),
     "dpt_set_profiling": (ctypes.c_int, [_vp, _i32]),
     "dpt_set_launch_config": (ctypes.c_int, [_vp, _i32, _i32]),
+    "dpt_set_spin_limit": (ctypes.c_int, [_vp, _i32]),
     "dpt_batch_create": (ctypes.c_int, [_i32, _vp, ctypes.POINTER(Params), _vp, _vp, ctypes.POINTER(_vp)]),
     "dpt_batch_destroy": (None, [_vp]),
     "dpt_batch_build_pyramids": (ctypes.c_int, [_vp, _i32, _vp, _vp, _i32]),
@@ -133,6 +134,7 @@ SIGNATURES = {
     "dpt_batch_get_profile": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64),
                                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]),
     "dpt_batch_set_launch_config": (ctypes.c_int, [_vp, _i32, _i32]),
+    "dpt_batch_set_spin_limit": (ctypes.c_int, [_vp, _i32]),
     "dpt_batch_set_profiling": (ctypes.c_int, [_vp, _i32]),
     "dpt_batch_last_kernel_ms": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
     "dpt_batch_get_level": (ctypes.c_int, [_vp, _i32, _i32, _vp, _i32]),
@@ -362,7 +364,12 @@ class Tracker:
     def synchronize(self, arrays: bool = False):
         """Results of the enqueued tracks, in order: a list of dicts, or (arrays=True)
         one structured array with the fields of RESULT_DTYPE."""
-        _check(self._lib.dpt_synchronize(self._h))
+        try:
+            _check(self._lib.dpt_synchronize(self._h))
+        except DptError as err:  # the results travel with the error (err.results)
+            err.results = [r.as_dict() for r in self._pending]
+            self._pending = []
+            raise
         if arrays:
             out = np.concatenate([np.frombuffer(r, dtype=RESULT_DTYPE) for r in self._pending]) if self._pending \
                 else np.empty(0, RESULT_DTYPE)
@@ -376,6 +383,10 @@ class Tracker:
 
     def set_launch_config(self, mode: int, chunk: int = 256):
         _check(self._lib.dpt_set_launch_config(self._h, mode, chunk))
+
+    def set_spin_limit(self, polls: int = 4194304):
+        """Polls before a cooperative wait gives up (0: at once; the default restores it)."""
+        _check(self._lib.dpt_set_spin_limit(self._h, polls))
 
     def set_profiling(self, enable: bool = True, every: int = 1):
         """Time every `every`-th pyramid and track launch with HIP events (off: enable=False)."""
@@ -539,7 +550,12 @@ class BatchTracker:
         """Results of the enqueued tracks, in order: one list of n per enqueue, or
         (arrays=True) one structured array of shape (enqueues, n) with the fields of
         RESULT_DTYPE."""
-        _check(self._lib.dpt_batch_synchronize(self._h))
+        try:
+            _check(self._lib.dpt_batch_synchronize(self._h))
+        except DptError as err:  # the results travel with the error (err.results)
+            err.results = [[r.as_dict() for r in res] for res in self._pending]
+            self._pending = []
+            raise
         if arrays:
             out = np.stack([np.frombuffer(res, dtype=RESULT_DTYPE) for res in self._pending]) if self._pending \
                 else np.empty((0, self.n), RESULT_DTYPE)
@@ -585,6 +601,10 @@ class BatchTracker:
 
     def set_launch_config(self, mode: int, chunk: int = 256):
         _check(self._lib.dpt_batch_set_launch_config(self._h, mode, chunk))
+
+    def set_spin_limit(self, polls: int = 4194304):
+        """Polls before a cooperative wait gives up, for every stream."""
+        _check(self._lib.dpt_batch_set_spin_limit(self._h, polls))
 
     def get_level(self, slot: int, level: int, dst=None):
         """Pyramid level of every stream, packed [n][H_l][W_l]: into `dst` (a torch CUDA

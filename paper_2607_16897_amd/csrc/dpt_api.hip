@@ -283,6 +283,7 @@ struct dpt_ctx {
   bool prof = false;
   ProfRing prof_pyr, prof_trk;  // pyramid and track launch timings
   int32_t launch_mode = DPT_LAUNCH_AUTO, chunk = 256;
+  int32_t spin_limit = kSpinLimit;
   CoopEngine eng;
   bool eng_ready = false;
   double* d_hist = nullptr;  // pose history: the last two T_cw, 2 x 3x4 FP64 (device)
@@ -839,7 +840,7 @@ int enqueue_coop(dpt_ctx* c, int mode, const double* T_cw_init, dpt_result* out)
   fill_start(c, mode, T_cw_init, c->eng.start(slot));
   int ps = -1;
   if (c->prof) HIP_TRY(c->prof_trk.begin(c->stream, &ps));
-  HIP_TRY(c->eng.launch(kSpinLimit, slot));
+  HIP_TRY(c->eng.launch(c->spin_limit, slot));
   if (c->prof) HIP_TRY(c->prof_trk.end(c->stream, ps));
   c->pending.emplace_back(slot, out);
   return DPT_OK;
@@ -1041,11 +1042,19 @@ int dpt_track_window_enqueue(dpt_ctx* c, const uint8_t* frames, int64_t pitch, i
     fill_start(c, mode, T_cw_init, c->eng.start((slot + f) % kRing));
   }
   if (c->prof) HIP_TRY(c->prof_trk.begin(c->stream, &ps));
-  HIP_TRY(c->eng.launch(kSpinLimit, slot, n_frames));
+  HIP_TRY(c->eng.launch(c->spin_limit, slot, n_frames));
   if (c->prof) HIP_TRY(c->prof_trk.end(c->stream, ps));
   for (int f = 0; f < n_frames; ++f) c->pending.emplace_back((slot + f) % kRing, out + f);
   c->slot_next = (slot + n_frames) % kRing;
   if (!frames_on_device) HIP_TRY(hipStreamSynchronize(c->stream));  // the host frames are only borrowed
+  return DPT_OK;
+}
+
+int dpt_set_spin_limit(dpt_ctx* c, int32_t polls) {
+  g_err.clear();
+  if (!c) return fail(DPT_E_ARG, "NULL context");
+  if (polls < 0) return fail(DPT_E_ARG, "polls %d < 0", polls);
+  c->spin_limit = polls;
   return DPT_OK;
 }
 
@@ -1176,6 +1185,7 @@ struct dpt_batch {
   hipStream_t stream = nullptr;
   std::vector<dpt_ctx*> ctx;
   int32_t launch_mode = DPT_LAUNCH_AUTO, chunk = 256;
+  int32_t spin_limit = kSpinLimit;
   // cooperative groups of streams (each fits one co-resident launch)
   std::vector<CoopEngine*> groups;
   std::vector<std::vector<int>> group_streams;
@@ -1364,7 +1374,7 @@ int batch_enqueue_coop(dpt_batch* b, const int* modes, const double* T_cw_init, 
   }
   int ps = -1;
   if (b->prof) HIP_TRY(b->prof_trk.begin(b->stream, &ps));
-  for (CoopEngine* g : b->groups) HIP_TRY(g->launch(kSpinLimit, slot));
+  for (CoopEngine* g : b->groups) HIP_TRY(g->launch(b->spin_limit, slot));
   if (b->prof) HIP_TRY(b->prof_trk.end(b->stream, ps));
   b->pending.emplace_back(slot, out);
   return DPT_OK;
@@ -1785,7 +1795,7 @@ int dpt_batch_track_window_enqueue(dpt_batch* b, const uint8_t* const* frames, c
     }
   }
   if (b->prof) HIP_TRY(b->prof_trk.begin(b->stream, &ps));
-  for (CoopEngine* g : b->groups) HIP_TRY(g->launch(kSpinLimit, slot, n_frames));
+  for (CoopEngine* g : b->groups) HIP_TRY(g->launch(b->spin_limit, slot, n_frames));
   if (b->prof) HIP_TRY(b->prof_trk.end(b->stream, ps));
   for (int f = 0; f < n_frames; ++f) b->pending.emplace_back((slot + f) % kRing, out + (size_t)f * b->n);
   b->slot_next = (slot + n_frames) % kRing;
@@ -1797,6 +1807,14 @@ int dpt_batch_set_pose_history(dpt_batch* b, int32_t s, const double T_older[16]
   g_err.clear();
   if (!b || s < 0 || s >= b->n) return fail(DPT_E_ARG, "stream %d", s);
   return dpt_set_pose_history(b->ctx[s], T_older, T_newer);
+}
+
+int dpt_batch_set_spin_limit(dpt_batch* b, int32_t polls) {
+  g_err.clear();
+  if (!b) return fail(DPT_E_ARG, "NULL batch");
+  if (polls < 0) return fail(DPT_E_ARG, "polls %d < 0", polls);
+  b->spin_limit = polls;
+  return DPT_OK;
 }
 
 int dpt_batch_set_launch_config(dpt_batch* b, int32_t mode, int32_t chunk) {

@@ -245,8 +245,8 @@ struct CoopEngine {
   ~CoopEngine() { release(); }
 };
 
-constexpr int kStatusTimeout = 4;  // a cooperative wait gave up (dpt_result.status)
-constexpr int kSpinLimit = 1 << 22;  // polls (one round trip to memory each) before a chunk reports a timeout
+constexpr int kStatusTimeout = DPT_TRACK_TIMEOUT;  // a cooperative wait gave up (dpt_result.status)
+constexpr int kSpinLimit = DPT_DEFAULT_SPIN_LIMIT;  // polls (one round trip to memory each) before a chunk reports a timeout
 
 // Record an error message for dpt_last_error() and return `code`.
 int set_error(int code, const char* msg);

@@ -180,3 +180,71 @@ def test_window_errors(gpu_lib):
     g.set_reference_from_depth(300, seq["depth"], seq["T0"])
     with pytest.raises(dpt.DptError):  # box pyramids only
         g.track_window_enqueue(frames)
+
+
+def test_timeout_path_and_recovery(gpu_lib):
+    """A zero spin limit makes every cross-chunk wait give up at once (forced
+    from the host: every kernel still runs to its end).  The frames report
+    TIMEOUT, the synchronisation DPT_E_HIP, and with the default limit back the
+    context tracks the same frames bitwise like a fresh one."""
+    import torch
+
+    dpt = gpu_lib
+    cam, n = synth.CAM_752, 2000  # 8 chunks: every iteration waits
+    seq = _sequence(17, cam, 4)
+    prm = dpt.make_params(levels=4)
+    frames = torch.from_numpy(seq["frames"]).cuda()
+    want = _per_frame(dpt, _tracker(dpt, cam, seq, n, prm), seq["frames"])
+    trk = _tracker(dpt, cam, seq, n, prm, launch=(dpt.LAUNCH_COOP, 256))
+    trk.set_spin_limit(0)
+    trk.track_window_enqueue(frames)
+    trk.build_pyramid(dpt.SLOT_CUR, seq["frames"][0])
+    trk.track_enqueue(None)
+    with pytest.raises(dpt.DptError) as ei:
+        trk.synchronize()
+    assert [r["status"] for r in ei.value.results] == [dpt.TRACK_TIMEOUT] * 5
+    with pytest.raises(dpt.DptError):
+        trk.set_spin_limit(-1)
+    trk.set_spin_limit()
+    trk.set_pose_history(seq["T_prev"], seq["T0"])
+    _assert_same(want, _per_frame(dpt, trk, seq["frames"]))
+    trk.set_pose_history(seq["T_prev"], seq["T0"])
+    trk.track_window_enqueue(frames)
+    _assert_same(want, trk.synchronize())
+
+
+def test_batch_timeout_only_where_chunks_wait(gpu_lib):
+    """In a batch, a one-chunk stream never waits and tracks normally while a
+    many-chunk stream times out; both recover."""
+    import torch
+
+    dpt = gpu_lib
+    cam = synth.CAM_640
+    seqs = [_sequence(30 + s, cam, 3) for s in range(2)]
+    ns = [200, 1500]
+    prm = dpt.make_params(levels=3)
+    bt = dpt.BatchTracker([cam, cam], prm, ns)
+    bt.set_launch_config(dpt.LAUNCH_COOP, 256)
+
+    def refresh():
+        bt.build_pyramids(dpt.SLOT_REF, [q["img0"] for q in seqs])
+        for s, q in enumerate(seqs):
+            bt.set_reference_from_depth(s, ns[s], q["depth"], q["T0"])
+            bt.set_pose_history(s, q["T_prev"], q["T0"])
+
+    refresh()
+    bt.set_spin_limit(0)
+    bt.track_window_enqueue([torch.from_numpy(q["frames"]).cuda() for q in seqs])
+    with pytest.raises(dpt.DptError) as ei:
+        bt.synchronize()
+    res = ei.value.results
+    assert len(res) == 3
+    assert all(r[0]["status"] in (dpt.TRACK_OK, dpt.TRACK_MAX_ITERS) for r in res)
+    assert all(r[1]["status"] == dpt.TRACK_TIMEOUT for r in res)
+    bt.set_spin_limit()
+    refresh()
+    bt.track_window_enqueue([torch.from_numpy(q["frames"]).cuda() for q in seqs])
+    again = bt.synchronize()
+    for j in range(3):
+        np.testing.assert_array_equal(again[j][0]["T_cw"], res[j][0]["T_cw"])
+        assert again[j][1]["status"] in (dpt.TRACK_OK, dpt.TRACK_MAX_ITERS)
