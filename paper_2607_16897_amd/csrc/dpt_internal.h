@@ -123,6 +123,7 @@ struct PrecomputeArgs {
 struct SelGeom {
   const uint8_t* img;
   int32_t W, m, Wc, C, n;
+  float inv_wc;  // 1 / Wc, for the candidate's row
 };
 
 // One image's selection: geometry, its scratch (select_scratch_ints ints), the

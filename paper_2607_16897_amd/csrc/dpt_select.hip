@@ -39,8 +39,26 @@ __device__ __forceinline__ int sel_score(const uint8_t* img, int W, int x, int y
 }
 
 
+// Row and column of candidate c: the float quotient (c < 2^24 is exact, and
+// the product's error is far below one row) corrected by at most one row.
+__device__ __forceinline__ void cand_xy(const SelGeom& g, int c, int* x, int* y) {
+  int r = (int)((float)c * g.inv_wc);
+  int q = c - r * g.Wc;
+  if (q < 0) {
+    --r;
+    q += g.Wc;
+  } else if (q >= g.Wc) {
+    ++r;
+    q -= g.Wc;
+  }
+  *x = q;
+  *y = r;
+}
+
 __device__ __forceinline__ int cand_score(const SelGeom& g, int c) {
-  return sel_score(g.img, g.W, g.m + c % g.Wc, g.m + c / g.Wc);
+  int x, y;
+  cand_xy(g, c, &x, &y);
+  return sel_score(g.img, g.W, g.m + x, g.m + y);
 }
 
 // The selection of one image (`one`), or of image blockIdx.y of a batch (`many`
@@ -65,25 +83,40 @@ __global__ __launch_bounds__(kSelThreads) void sel_hist_coarse(SelJob one, const
   for (int b = threadIdx.x; b < 256; b += blockDim.x) h[b] = 0;
   __syncthreads();
   const int c0 = blockIdx.x * kSelChunk;
+  // bin 0 (scores below 512, most of a frame) is not counted: it is the
+  // candidate total minus the other bins, which spares its atomics
   for (int q = threadIdx.x; q < kSelChunk; q += blockDim.x) {
     const int c = c0 + q;
-    if (c < g.C) atomicAdd(&h[cand_score(g, c) >> 9], 1);
+    if (c < g.C) {
+      const int b = cand_score(g, c) >> 9;
+      if (b) atomicAdd(&h[b], 1);
+    }
   }
   __syncthreads();
-  for (int b = threadIdx.x; b < 256; b += blockDim.x)
+  for (int b = threadIdx.x + 1; b < 256; b += blockDim.x)
     if (h[b]) atomicAdd(&sc[SelScratch::kHist1 + b], h[b]);
 }
 
 // One wave: the largest bin b with sum_{b' >= b} h[b'] >= n over NB bins
 // (NB / 64 per lane), given `above` candidates already counted in higher bins.
+// total >= 0: bin 0 is not stored and holds total minus the other bins.
 // Returns b (or -1 if the total is short of n) and the count above b.
 template <int NB>
-__device__ __forceinline__ int2 wave_find_bin(const int* __restrict__ h, int n, int above) {
+__device__ __forceinline__ int2 wave_find_bin(const int* __restrict__ h, int n, int above, int total = -1) {
   constexpr int PB = NB / 64;
   const int lane = threadIdx.x & 63;
   int v[PB], t = 0;
 #pragma unroll
   for (int j = 0; j < PB; ++j) t += (v[j] = h[lane * PB + j]);
+  if (total >= 0) {
+    int rest = t;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) rest += __shfl_xor(rest, d, 64);
+    if (lane == 0) {
+      v[0] = total - rest;
+      t += v[0];
+    }
+  }
   // suffix sum over the lanes above this one
   int suf = t;
 #pragma unroll
@@ -109,7 +142,7 @@ __device__ __forceinline__ int2 wave_find_bin(const int* __restrict__ h, int n, 
 // Coarse bucket B and the count above it (B = -1: take every candidate).
 __device__ __forceinline__ int2 coarse_bucket(const SelGeom& g, const int* sc) {
   if (g.C <= g.n) return make_int2(-1, 0);
-  return wave_find_bin<256>(sc + SelScratch::kHist1, g.n, 0);
+  return wave_find_bin<256>(sc + SelScratch::kHist1, g.n, 0, g.C);
 }
 
 __global__ __launch_bounds__(kSelThreads) void sel_hist_fine(SelJob one, const SelJob* many) {
@@ -254,8 +287,9 @@ __global__ __launch_bounds__(kSelThreads) void sel_write(SelJob one, const SelJo
 #pragma unroll
   for (int j = 0; j < kSelPPT; ++j)
     if (sel[j]) {
-      const int c = c0 + j;
-      idx[pos++] = (g.m + c / g.Wc) * g.W + (g.m + c % g.Wc);
+      int x, y;
+      cand_xy(g, c0 + j, &x, &y);
+      idx[pos++] = (g.m + y) * g.W + (g.m + x);
     }
   if (blockIdx.x == G - 1 && threadIdx.x == 0) *count = base.x + tot;
 }
@@ -270,6 +304,7 @@ SelJob make_sel_job(const uint8_t* img, int32_t W, int32_t H, int32_t margin, in
   const int Hc = H - 2 * margin;
   j.g.C = (j.g.Wc > 0 && Hc > 0) ? j.g.Wc * Hc : 0;
   j.g.n = n;
+  j.g.inv_wc = j.g.Wc > 0 ? 1.0f / (float)j.g.Wc : 0.0f;
   j.sc = scratch;
   j.idx = idx;
   j.count = count;
