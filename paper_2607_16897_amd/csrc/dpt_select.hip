@@ -256,9 +256,17 @@ __global__ __launch_bounds__(kSelThreads) void sel_write(SelJob one, const SelJo
   __shared__ int wsum[16];
   __shared__ int red[8];
   __shared__ int sT, sNeed;
+  __shared__ int4 s_score[kSelChunk / 4];  // the chunk's scores, candidate order
   if (threadIdx.x < 64) {
     const int2 r = threshold(g, sc);
     if (threadIdx.x == 0) sT = r.x, sNeed = r.y;
+  }
+  // scores computed with consecutive threads on consecutive candidates (the
+  // image reads coalesce), then each thread takes kSelPPT consecutive ones
+  {
+    int* sv = reinterpret_cast<int*>(s_score);
+    const int cb = blockIdx.x * kSelChunk;
+    for (int q = threadIdx.x; q < kSelChunk; q += blockDim.x) sv[q] = cb + q < g.C ? cand_score(g, cb + q) : -2;
   }
   __syncthreads();
   const int T = sT, need = sNeed;
@@ -267,11 +275,12 @@ __global__ __launch_bounds__(kSelThreads) void sel_write(SelJob one, const SelJo
   int s[kSelPPT];
   int eq_local = 0;
 #pragma unroll
-  for (int j = 0; j < kSelPPT; ++j) {
-    const int c = c0 + j;
-    s[j] = c < g.C ? cand_score(g, c) : -2;
-    eq_local += s[j] == T;
+  for (int j = 0; j < kSelPPT / 4; ++j) {
+    const int4 v = s_score[threadIdx.x * (kSelPPT / 4) + j];
+    s[4 * j] = v.x, s[4 * j + 1] = v.y, s[4 * j + 2] = v.z, s[4 * j + 3] = v.w;
   }
+#pragma unroll
+  for (int j = 0; j < kSelPPT; ++j) eq_local += s[j] == T;
   int tot;
   int tie = block_exclusive_scan(eq_local, wsum, &tot) + base.y;
   bool sel[kSelPPT];
