@@ -226,6 +226,10 @@ int dpt_set_pose_history(dpt_ctx* ctx, const double T_older[16], const double T_
  * the DPT_MAX_IN_FLIGHT tracks in flight.  The window pyramids are the context's own (the
  * CUR slot is left as it was), allocated on the first call and grown when a
  * longer window comes (the call then first waits for the tracks in flight).
+ * Device frames whose rows are W bytes apart (pitch == width) are level 0 of
+ * their pyramids as they are: the track launch reads them too, so they must
+ * stay unchanged until it has run (work enqueued later on the same stream is
+ * ordered after it).
  * DPT_E_ARG for a frame_stride smaller than a frame, the one-workgroup launch
  * mode, or DPT_FLAG_GAUSS_F32; DPT_E_STATE without reference points. */
 int dpt_track_window_enqueue(dpt_ctx* ctx, const uint8_t* frames, int64_t pitch, int64_t frame_stride,

@@ -1026,11 +1026,15 @@ int dpt_track_window_enqueue(dpt_ctx* c, const uint8_t* frames, int64_t pitch, i
     sp = c->cam.width;
     sst = (int64_t)c->cam.width * c->cam.height;
   }
+  // frames with rows W bytes apart serve as level 0 themselves: the pyramid
+  // launch then writes the coarser levels only
+  const bool l0_direct = sp == c->cam.width;
   PyrWinSrc srcs;
   std::memset(&srcs, 0, sizeof srcs);
   srcs.src[0] = src;
   srcs.pitch[0] = sp;
   srcs.stride[0] = sst;
+  srcs.write_l0[0] = l0_direct ? 0 : 1;
   int ps = -1;
   if (c->prof) HIP_TRY(c->prof_pyr.begin(c->stream, &ps));
   HIP_TRY(launch_pyramid_window(c->d_winjob, srcs, 1, n_frames, c->cam.width, c->cam.height, c->prm.levels,
@@ -1040,6 +1044,11 @@ int dpt_track_window_enqueue(dpt_ctx* c, const uint8_t* frames, int64_t pitch, i
   for (int f = 0; f < n_frames; ++f) {
     const int mode = f == 0 && init_mode == DPT_INIT_GIVEN ? kStartGiven : kStartConstVelocity;
     fill_start(c, mode, T_cw_init, c->eng.start((slot + f) % kRing));
+  }
+  if (l0_direct) {
+    StartSlot* st = c->eng.start(slot);
+    st->l0 = src;
+    st->l0_stride = sst;
   }
   if (c->prof) HIP_TRY(c->prof_trk.begin(c->stream, &ps));
   HIP_TRY(c->eng.launch(c->spin_limit, slot, n_frames));
@@ -1756,6 +1765,18 @@ int dpt_batch_track_window_enqueue(dpt_batch* b, const uint8_t* const* frames, c
   if (b->groups_dirty && (e = build_groups(b)) != DPT_OK) return e;
   for (CoopEngine* g : b->groups)
     if (g->dirty) HIP_TRY(g->upload());
+  // the frames as the pyramid launch and the track read them (host frames
+  // through each stream's staging); rows W bytes apart serve as level 0
+  std::vector<const uint8_t*> src(b->n);
+  std::vector<int64_t> sp(b->n), sst(b->n);
+  for (int s = 0; s < b->n; ++s) {
+    dpt_ctx* c = b->ctx[s];
+    src[s] = frames[s], sp[s] = pitches[s], sst[s] = frame_strides[s];
+    if (!frames_on_device) {
+      if ((e = stage_window(c, frames[s], pitches[s], frame_strides[s], n_frames, b->stream)) != DPT_OK) return e;
+      src[s] = c->win_staging, sp[s] = c->cam.width, sst[s] = (int64_t)c->cam.width * c->cam.height;
+    }
+  }
   // pyramids of every stream's frames, up to kPyrArgJobs streams per launch
   int ps = -1;
   if (b->prof) HIP_TRY(b->prof_pyr.begin(b->stream, &ps));
@@ -1766,17 +1787,10 @@ int dpt_batch_track_window_enqueue(dpt_batch* b, const uint8_t* const* frames, c
     int max_w = 0, max_h = 0;
     for (int k = 0; k < m; ++k) {
       dpt_ctx* c = b->ctx[s0 + k];
-      srcs.src[k] = frames[s0 + k];
-      srcs.pitch[k] = pitches[s0 + k];
-      srcs.stride[k] = frame_strides[s0 + k];
-      if (!frames_on_device) {
-        if ((e = stage_window(c, frames[s0 + k], pitches[s0 + k], frame_strides[s0 + k], n_frames, b->stream)) !=
-            DPT_OK)
-          return e;
-        srcs.src[k] = c->win_staging;
-        srcs.pitch[k] = c->cam.width;
-        srcs.stride[k] = (int64_t)c->cam.width * c->cam.height;
-      }
+      srcs.src[k] = src[s0 + k];
+      srcs.pitch[k] = sp[s0 + k];
+      srcs.stride[k] = sst[s0 + k];
+      srcs.write_l0[k] = sp[s0 + k] == c->cam.width ? 0 : 1;
       max_w = std::max(max_w, c->cam.width);
       max_h = std::max(max_h, c->cam.height);
     }
@@ -1790,8 +1804,10 @@ int dpt_batch_track_window_enqueue(dpt_batch* b, const uint8_t* const* frames, c
     for (size_t gi = 0; gi < b->groups.size(); ++gi) {
       const std::vector<int>& ss = b->group_streams[gi];
       StartSlot* st = b->groups[gi]->start((slot + f) % kRing);
-      for (size_t k = 0; k < ss.size(); ++k)
+      for (size_t k = 0; k < ss.size(); ++k) {
         fill_start(b->ctx[ss[k]], mode, T_cw_init ? T_cw_init + 16 * ss[k] : nullptr, &st[k]);
+        if (f == 0 && sp[ss[k]] == b->ctx[ss[k]]->cam.width) st[k].l0 = src[ss[k]], st[k].l0_stride = sst[ss[k]];
+      }
     }
   }
   if (b->prof) HIP_TRY(b->prof_trk.begin(b->stream, &ps));

@@ -233,7 +233,8 @@ __device__ __forceinline__ void const_velocity_start(double* T0, const double* r
 // constant-velocity prediction from the stream's pose history.  Block-wide;
 // the result, the reference pose and the history land in LDS.
 __device__ __forceinline__ void start_pose(const StartSlot* __restrict__ st, const double* __restrict__ hist,
-                                           double* T0, double* rw, double* h0, double* h1, double* m1, double* m2) {
+                                           double* T0, double* rw, double* h0, double* h1, double* m1, double* m2,
+                                           const uint8_t** l0, int64_t* l0_stride) {
   const int t = threadIdx.x;
   __shared__ int sh_mode;
   if (t < 12) {
@@ -243,6 +244,7 @@ __device__ __forceinline__ void start_pose(const StartSlot* __restrict__ st, con
     h1[t] = hist[12 + t];
   }
   if (t == 0) sh_mode = st->mode > 0.5 ? kStartConstVelocity : kStartGiven;
+  if (t == 32) *l0 = st->l0, *l0_stride = st->l0_stride;
   __syncthreads();
   if (sh_mode == kStartConstVelocity) const_velocity_start(T0, rw, h0, h1, m1, m2);
 }
@@ -275,6 +277,8 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
   __shared__ float sh_red[(CH / 64) * 32];
   __shared__ float sh_grp[GENERIC ? CH : 1];  // the whole-workgroup exchange of many-chunk streams
   __shared__ int sh_ok;
+  __shared__ const uint8_t* sh_l0;
+  __shared__ int64_t sh_l0_stride;
   const int2 w = work[blockIdx.x];
   if (w.x < 0) return;  // padding slot of the XCD-aware work list
   {
@@ -283,7 +287,7 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
       reinterpret_cast<uint32_t*>(&ss)[j] = src[j];
   }
   __syncthreads();
-  start_pose(start + w.x, ss.hist, sh_T0, sh_rw, sh_h0, sh_h1, sh_m1, sh_m2);
+  start_pose(start + w.x, ss.hist, sh_T0, sh_rw, sh_h0, sh_h1, sh_m1, sh_m2, &sh_l0, &sh_l0_stride);
   const TrackArgs& a = ss.a;
   const PatRegs pregs = pattern_regs(a.pat);
   const int chunk = w.y, nch = ss.n_chunks;
@@ -300,6 +304,9 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
     const PIX* cur = WIN        ? reinterpret_cast<const PIX*>(ss.win + f * ss.win_stride)
                      : FLOAT_PYR ? reinterpret_cast<const PIX*>(a.curf)
                                  : reinterpret_cast<const PIX*>(a.cur);
+    // level 0 of the frame: from the source frames themselves when the window
+    // pyramids were built without it
+    const PIX* cur0 = WIN && sh_l0 ? reinterpret_cast<const PIX*>(sh_l0 + f * sh_l0_stride) : cur + a.lv[0].off;
     // pose state, identical in every thread of every chunk of the stream
     float T[12];
     double Td[MIXED ? 12 : 1];
@@ -317,7 +324,7 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
     PR pr;
     for (int l = a.levels - 1; l >= 0 && !stop; --l) {
       const LevelGeom g = a.lv[l];
-      const PIX* img = cur + g.off;
+      const PIX* img = WIN && l == 0 ? cur0 : cur + g.off;
       if constexpr (GENERIC)
         load_point_geo(a, l, i, pr);
       else
@@ -391,10 +398,10 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
       const LevelGeom g = a.lv[0];
       if constexpr (GENERIC) {
         load_point_geo(a, 0, i, pr);
-        accumulate_point_generic<true, PIX, NV>(a, a.pat, g, cur + g.off, T, pr, sub, acc);
+        accumulate_point_generic<true, PIX, NV>(a, a.pat, g, WIN ? cur0 : cur + g.off, T, pr, sub, acc);
       } else {
         load_point(a, 0, i, pr);
-        accumulate_point<true, true, PR, NV>(a, pregs, g, cur + g.off, T, pr, acc);
+        accumulate_point<true, true, PR, NV>(a, pregs, g, WIN ? cur0 : cur + g.off, T, pr, acc);
       }
       if (!stream_total<MIXED, NV, GENERIC>(acc, sh_red, sh_tot, &sh_ok, ss.partials, chunk, nch, tag, spin_limit,
                                             sh_grp))
@@ -780,34 +787,46 @@ hipError_t launch_pyramid_batch_args(const PyrJob* d_static, const PyrSrcArgs& s
   return hipGetLastError();
 }
 
-// Window pyramids: blockIdx.z = stream * n_frames + frame.
+// Window pyramids: blockIdx.z = stream * n_frames + frame; a workgroup builds
+// kWinTiles consecutive tiles of a tile row.
+constexpr int kWinTiles = 4;
 template <int TILE>
 __global__ __launch_bounds__(256) void pyramid_window_kernel(const WinJob* __restrict__ jobs, PyrWinSrc srcs,
                                                              int n_frames) {
   const int z = blockIdx.z, js = z / n_frames, f = z - js * n_frames;
   const WinJob& j = jobs[js];
-  if ((int)blockIdx.x * TILE >= j.g.W[0] || (int)blockIdx.y * TILE >= j.g.H[0]) return;
+  const int oy = blockIdx.y * TILE;
+  if (oy >= j.g.H[0]) return;
   const uint8_t* src = srcs.src[js] + f * srcs.stride[js];
   uint8_t* dst = j.dst + f * j.dst_stride;
   const int64_t pitch = srcs.pitch[js];
+  const bool write_l0 = srcs.write_l0[js] != 0;
   const uintptr_t sa = reinterpret_cast<uintptr_t>(src), da = reinterpret_cast<uintptr_t>(dst);
   const int W0 = j.g.W[0];
-  if (TILE == 64 && (pitch % 16) == 0 && (sa % 16) == 0 && (W0 % 16) == 0 && (da % 16) == 0)
-    pyramid_tile64v(src, pitch, dst, j.g);
-  else
-    pyramid_tile<TILE>(src, pitch, dst, j.g, ((pitch % 4) == 0 && (sa % 4) == 0 && (W0 % 4) == 0 && (da % 4) == 0) ? 1 : 0);
+  const bool v16 = TILE == 64 && (pitch % 16) == 0 && (sa % 16) == 0 && (W0 % 16) == 0 && (da % 16) == 0;
+  const int v4 = ((pitch % 4) == 0 && (sa % 4) == 0 && (W0 % 4) == 0 && (da % 4) == 0) ? 1 : 0;
+  for (int t = 0; t < kWinTiles; ++t) {  // the tile's LDS is free again when the previous call returns
+    const int ox = ((int)blockIdx.x * kWinTiles + t) * TILE;
+    if (ox >= W0) break;
+    if (v16)
+      pyramid_tile64v_at(src, pitch, dst, j.g, ox, oy, write_l0);
+    else
+      pyramid_tile_at<TILE>(src, pitch, dst, j.g, v4, ox, oy, write_l0);
+  }
 }
 
 hipError_t launch_pyramid_window(const WinJob* d_jobs, const PyrWinSrc& srcs, int n_streams, int n_frames, int max_w,
                                  int max_h, int levels, hipStream_t s) {
   if (n_streams < 1 || n_streams > kPyrArgJobs || n_frames < 1 || (int64_t)n_streams * n_frames > 65535)
     return hipErrorInvalidValue;
+  constexpr int T64 = 64 * kWinTiles, T128 = 128 * kWinTiles;
   if (levels <= 7)
-    hipLaunchKernelGGL(pyramid_window_kernel<64>, dim3((max_w + 63) / 64, (max_h + 63) / 64, n_streams * n_frames),
+    hipLaunchKernelGGL(pyramid_window_kernel<64>, dim3((max_w + T64 - 1) / T64, (max_h + 63) / 64, n_streams * n_frames),
                        dim3(256), 0, s, d_jobs, srcs, n_frames);
   else
-    hipLaunchKernelGGL(pyramid_window_kernel<128>, dim3((max_w + 127) / 128, (max_h + 127) / 128, n_streams * n_frames),
-                       dim3(256), 0, s, d_jobs, srcs, n_frames);
+    hipLaunchKernelGGL(pyramid_window_kernel<128>,
+                       dim3((max_w + T128 - 1) / T128, (max_h + 127) / 128, n_streams * n_frames), dim3(256), 0, s,
+                       d_jobs, srcs, n_frames);
   return hipGetLastError();
 }
 

@@ -90,12 +90,14 @@ __device__ __forceinline__ void gradient(const PIX* img, int W, float x, float y
 // One launch builds every level.  A workgroup owns a TILE x TILE block of
 // level 0 (TILE >= 2^(levels-1)), so each level's 2x2 parents stay inside the
 // tile; levels alternate between two LDS buffers.
+// The tile at level-0 origin (ox, oy); write_l0 = false leaves level 0 of dst
+// unwritten (a caller that reads level 0 from the source frame itself).
 template <int TILE>
-__device__ __forceinline__ void pyramid_tile(const uint8_t* __restrict__ src, int64_t pitch,
-                                             uint8_t* __restrict__ dst, const PyrGeom& g, int vec4) {
+__device__ __forceinline__ void pyramid_tile_at(const uint8_t* __restrict__ src, int64_t pitch,
+                                                uint8_t* __restrict__ dst, const PyrGeom& g, int vec4, int ox, int oy,
+                                                bool write_l0) {
   __shared__ uint8_t buf0[TILE * TILE];
   __shared__ uint8_t buf1[TILE * TILE / 4];
-  const int ox = blockIdx.x * TILE, oy = blockIdx.y * TILE;
   const int W0 = g.W[0], H0 = g.H[0];
   if (vec4) {
     // 4-byte loads: width, pitch and base are multiples of 4
@@ -105,7 +107,7 @@ __device__ __forceinline__ void pyramid_tile(const uint8_t* __restrict__ src, in
       uint32_t v = 0;
       if (gy < H0 && gx < W0) {
         v = *reinterpret_cast<const uint32_t*>(src + gy * pitch + gx);
-        *reinterpret_cast<uint32_t*>(dst + g.off[0] + (int64_t)gy * W0 + gx) = v;
+        if (write_l0) *reinterpret_cast<uint32_t*>(dst + g.off[0] + (int64_t)gy * W0 + gx) = v;
       }
       *reinterpret_cast<uint32_t*>(buf0 + ly * TILE + lx) = v;
     }
@@ -116,7 +118,7 @@ __device__ __forceinline__ void pyramid_tile(const uint8_t* __restrict__ src, in
       uint8_t v = 0;
       if (gy < H0 && gx < W0) {
         v = src[gy * pitch + gx];
-        dst[g.off[0] + (int64_t)gy * W0 + gx] = v;
+        if (write_l0) dst[g.off[0] + (int64_t)gy * W0 + gx] = v;
       }
       buf0[q] = v;
     }
@@ -147,15 +149,21 @@ __device__ __forceinline__ void pyramid_tile(const uint8_t* __restrict__ src, in
   }
 }
 
+template <int TILE>
+__device__ __forceinline__ void pyramid_tile(const uint8_t* __restrict__ src, int64_t pitch,
+                                             uint8_t* __restrict__ dst, const PyrGeom& g, int vec4) {
+  pyramid_tile_at<TILE>(src, pitch, dst, g, vec4, blockIdx.x * TILE, blockIdx.y * TILE, true);
+}
+
 // pyramid_tile for 64x64 tiles of frames whose width, pitch and base address
 // are multiples of 16: one 16-byte load and store per thread for level 0 (256
 // threads), four level-1 pixels per thread from two 8-byte LDS reads with one
 // 4-byte store, then the coarser levels as pyramid_tile.  Up to 7 levels.
-__device__ __forceinline__ void pyramid_tile64v(const uint8_t* __restrict__ src, int64_t pitch,
-                                                uint8_t* __restrict__ dst, const PyrGeom& g) {
+__device__ __forceinline__ void pyramid_tile64v_at(const uint8_t* __restrict__ src, int64_t pitch,
+                                                   uint8_t* __restrict__ dst, const PyrGeom& g, int ox, int oy,
+                                                   bool write_l0) {
   __shared__ __align__(16) uint8_t buf0[64 * 64];
   __shared__ __align__(16) uint8_t buf1[32 * 32];
-  const int ox = blockIdx.x * 64, oy = blockIdx.y * 64;
   const int W0 = g.W[0], H0 = g.H[0];
   {
     const int r = threadIdx.x >> 2, c = (threadIdx.x & 3) * 16;
@@ -163,7 +171,7 @@ __device__ __forceinline__ void pyramid_tile64v(const uint8_t* __restrict__ src,
     uint4 v = make_uint4(0u, 0u, 0u, 0u);
     if (gy < H0 && gx < W0) {  // W0 % 16 == 0: the 16 bytes lie inside the row
       v = *reinterpret_cast<const uint4*>(src + gy * pitch + gx);
-      *reinterpret_cast<uint4*>(dst + g.off[0] + (int64_t)gy * W0 + gx) = v;
+      if (write_l0) *reinterpret_cast<uint4*>(dst + g.off[0] + (int64_t)gy * W0 + gx) = v;
     }
     *reinterpret_cast<uint4*>(buf0 + r * 64 + c) = v;
   }
@@ -211,6 +219,11 @@ __device__ __forceinline__ void pyramid_tile64v(const uint8_t* __restrict__ src,
     prev = next;
     next = t;
   }
+}
+
+__device__ __forceinline__ void pyramid_tile64v(const uint8_t* __restrict__ src, int64_t pitch,
+                                                uint8_t* __restrict__ dst, const PyrGeom& g) {
+  pyramid_tile64v_at(src, pitch, dst, g, blockIdx.x * 64, blockIdx.y * 64, true);
 }
 
 // ---------------------------------------------------------------- block scans / reductions

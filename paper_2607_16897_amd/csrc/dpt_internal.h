@@ -184,10 +184,15 @@ __host__ __device__ inline void orthonormalize34(double* T) {
 struct StartSlot {
   double T_rel[12];  // given start pose relative to the reference (mode kStartGiven)
   double mode;       // kStartGiven, or kStartConstVelocity: P1 P0^-1 P1 from the history
-  double pad0[3];
+  // window tracks: level 0 of frame f read at l0 + f * l0_stride (rows W bytes
+  // apart) instead of from the window pyramids, or l0 = null
+  const uint8_t* l0;
+  int64_t l0_stride;
+  double pad0;
   double T_rw[12];   // reference pose (world -> reference camera), 3x4
   double pad1[4];
 };
+static_assert(sizeof(StartSlot) == 256, "StartSlot layout");
 constexpr int kStartGiven = 0, kStartConstVelocity = 1;
 constexpr int kRing = DPT_MAX_IN_FLIGHT;  // tracks that may be in flight per context or batch
 
@@ -319,6 +324,7 @@ struct PyrWinSrc {
   const uint8_t* src[kPyrArgJobs];
   int64_t pitch[kPyrArgJobs];
   int64_t stride[kPyrArgJobs];
+  int32_t write_l0[kPyrArgJobs];  // 0: the track reads level 0 from the source frames
 };
 hipError_t launch_pyramid_window(const WinJob* d_jobs, const PyrWinSrc& srcs, int n_streams, int n_frames, int max_w,
                                  int max_h, int levels, hipStream_t s);

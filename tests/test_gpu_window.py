@@ -248,3 +248,32 @@ def test_batch_timeout_only_where_chunks_wait(gpu_lib):
     for j in range(3):
         np.testing.assert_array_equal(again[j][0]["T_cw"], res[j][0]["T_cw"])
         assert again[j][1]["status"] in (dpt.TRACK_OK, dpt.TRACK_MAX_ITERS)
+
+
+def test_window_padded_rows_and_batch_of_both(gpu_lib):
+    """Frames whose rows are W bytes apart serve as level 0 directly; padded
+    rows go through the window pyramids' own level 0.  Both equal the
+    frame-by-frame track bitwise, alone and side by side in one batch."""
+    import torch
+
+    dpt = gpu_lib
+    cam, n = synth.CAM_640, 1200
+    seq = _sequence(23, cam, 5)
+    prm = dpt.make_params(levels=3)
+    want = _per_frame(dpt, _tracker(dpt, cam, seq, n, prm), seq["frames"])
+    padded = torch.zeros((5, cam.height, cam.width + 48), dtype=torch.uint8, device="cuda")
+    padded[:, :, :cam.width] = torch.from_numpy(seq["frames"]).cuda()
+    view = padded[:, :, :cam.width]  # rows W + 48 bytes apart
+    assert view.stride(1) == cam.width + 48
+    trk = _tracker(dpt, cam, seq, n, prm)
+    trk.track_window_enqueue(view)
+    _assert_same(want, trk.synchronize())
+    bt = dpt.BatchTracker([cam, cam], prm, [n, n])
+    bt.build_pyramids(dpt.SLOT_REF, [seq["img0"], seq["img0"]])
+    for s in range(2):
+        bt.set_reference_from_depth(s, n, seq["depth"], seq["T0"])
+        bt.set_pose_history(s, seq["T_prev"], seq["T0"])
+    bt.track_window_enqueue([view, torch.from_numpy(seq["frames"]).cuda()])
+    got = bt.synchronize()
+    for s in range(2):
+        _assert_same(want, [got[j][s] for j in range(5)])
