@@ -26,45 +26,59 @@ constexpr int kPollBatch = 8;
 
 // Wave 0 only.  Publish this chunk's column sums (`mine`, lanes < NV) under
 // `tag`, wait until all nch chunks of the stream published theirs, and return
-// the stream totals in chunk order (lanes < NV).  False on timeout.  A chunk's
-// words are 32 apart whatever NV is.
+// the stream totals (lanes < NV).  False on timeout.  A chunk's words are 32
+// apart whatever NV is.  The wave's 64 / NV lane groups poll consecutive
+// ranges of the chunks (group q the q-th range, lane v word v), so a poll
+// round has 64 loads in flight, and the group sums meet in a fixed tree, the
+// same in every chunk of the stream.
 template <bool KAHAN, int NV>
 __device__ __forceinline__ bool exchange_partials(uint64_t* partials, int chunk, int nch, uint32_t tag, float mine,
                                                   int spin_limit, float* total) {
-  const int lane = threadIdx.x & 63;
+  constexpr int G = 64 / NV;
+  static_assert(G == 2 || G == 4, "32 or 16 values per chunk");
+  static_assert(!(KAHAN && G != 2), "compensated sums use 32 values");
+  const int lane = threadIdx.x & 63, q = lane / NV, v = lane % NV;
   uint64_t* buf = partials + (size_t)(tag & 1u) * nch * 32;
   const uint64_t hi = (uint64_t)tag << 32;
   if (lane < NV)
     __hip_atomic_store(&buf[chunk * 32 + lane], hi | __float_as_uint(mine), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
+  const int per = (nch + G - 1) / G, cb = q * per, ce = cb + per < nch ? cb + per : nch;
   for (int t = 0; t < spin_limit; ++t) {
     float s = 0.0f, comp = 0.0f;
     int ok = 1;
-    if (lane < NV) {
-      for (int c0 = 0; c0 < nch; c0 += kPollBatch) {
-        uint64_t v[kPollBatch];
+    for (int c0 = cb; c0 < ce; c0 += kPollBatch) {
+      uint64_t w[kPollBatch];
 #pragma unroll
-        for (int j = 0; j < kPollBatch; ++j)  // a batch of loads in flight, then the checks
-          v[j] = c0 + j < nch ? __hip_atomic_load(&buf[(c0 + j) * 32 + lane], __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_AGENT)
-                              : hi;
+      for (int j = 0; j < kPollBatch; ++j)  // a batch of loads in flight, then the checks
+        w[j] = c0 + j < ce ? __hip_atomic_load(&buf[(c0 + j) * 32 + v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                           : hi;
 #pragma unroll
-        for (int j = 0; j < kPollBatch; ++j) {
-          if (c0 + j >= nch) break;
-          ok &= (uint32_t)(v[j] >> 32) == tag;
-          const float x = __uint_as_float((uint32_t)v[j]);
-          if (KAHAN) {
-            const float y = x - comp;
-            const float u = s + y;
-            comp = (u - s) - y;
-            s = u;
-          } else {
-            s += x;
-          }
+      for (int j = 0; j < kPollBatch; ++j) {
+        if (c0 + j >= ce) break;
+        ok &= (uint32_t)(w[j] >> 32) == tag;
+        const float x = __uint_as_float((uint32_t)w[j]);
+        if (KAHAN) {
+          const float y = x - comp;
+          const float u = s + y;
+          comp = (u - s) - y;
+          s = u;
+        } else {
+          s += x;
         }
       }
     }
     if (__all(ok)) {
+      if constexpr (G == 4) s += __shfl_xor(s, 16, 64);  // (g0 + g1), (g2 + g3)
+      if constexpr (KAHAN) {  // the two compensated sums: (s0 - c0) + (s1 - c1)
+        const float ps = __shfl_xor(s, 32, 64), pc = __shfl_xor(comp, 32, 64);
+        const float lo_s = q == 0 ? s : ps, lo_c = q == 0 ? comp : pc;
+        const float hi_s = q == 0 ? ps : s, hi_c = q == 0 ? pc : comp;
+        const float y = hi_s - (lo_c + hi_c);
+        s = lo_s + y;
+      } else {
+        s += __shfl_xor(s, 32, 64);
+      }
       *total = s;
       return true;
     }
