@@ -8,7 +8,7 @@
 // word holding an epoch tag above the float's bits, so a reader knows from the
 // word alone whether it is current: a chunk publishes its partials and polls
 // the stream's words until every chunk's carry the tag, with no counter, no
-// fence and no second read.  Every chunk then sums the partials in chunk order
+// fence and no second read.  Every chunk then sums the partials in one fixed order
 // and every thread solves the 6x6 system itself: all threads of all chunks of
 // a stream compute bitwise-identical poses, so one exchange per iteration
 // suffices and the result is reproducible.  Waits are bounded: a chunk that
