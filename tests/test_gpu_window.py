@@ -277,3 +277,22 @@ def test_window_padded_rows_and_batch_of_both(gpu_lib):
     got = bt.synchronize()
     for s in range(2):
         _assert_same(want, [got[j][s] for j in range(5)])
+
+
+def test_window_eight_levels_odd_width(gpu_lib):
+    """The 128-pixel tiles of an 8-level pyramid on a 2047 x 1535 frame (odd
+    width: no vector accesses; level 0 straight from the frames) and the
+    fixed-H window kernel: bitwise the frame-by-frame track."""
+    import torch
+
+    dpt = gpu_lib
+    cam = synth.Camera(2047, 1535, 900.0, 900.0, 1023.0, 767.0)
+    seq = _sequence(29, cam, 3)
+    for kw in (dict(levels=8), dict(levels=8, fixed_h=True)):
+        prm = dpt.make_params(**kw)
+        want = _per_frame(dpt, _tracker(dpt, cam, seq, 3000, prm), seq["frames"])
+        trk = _tracker(dpt, cam, seq, 3000, prm)
+        trk.track_window_enqueue(torch.from_numpy(seq["frames"]).cuda())
+        got = trk.synchronize()
+        _assert_same(want, got)
+        assert all(r["status"] in (0, 1) for r in got)
