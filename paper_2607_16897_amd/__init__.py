@@ -258,6 +258,7 @@ class Tracker:
         self._h = h
         self.n_points = 0
         self._pending = []
+        self._frames_keep = []  # window frames until their tracks are synchronised
 
     def close(self):
         if getattr(self, "_h", None):
@@ -360,6 +361,7 @@ class Tracker:
                                                   INIT_CONST_VELOCITY if T is None else INIT_GIVEN, T,
                                                   ctypes.cast(res, _vp)))
         self._pending.extend(res[f] for f in range(F))
+        self._frames_keep.append(keep)  # device frames are read by the track launch too
 
     def synchronize(self, arrays: bool = False):
         """Results of the enqueued tracks, in order: a list of dicts, or (arrays=True)
@@ -369,6 +371,7 @@ class Tracker:
         except DptError as err:  # the results travel with the error (err.results)
             err.results = [r.as_dict() for r in self._pending]
             self._pending = []
+            self._frames_keep = []
             raise
         if arrays:
             out = np.concatenate([np.frombuffer(r, dtype=RESULT_DTYPE) for r in self._pending]) if self._pending \
@@ -376,6 +379,7 @@ class Tracker:
         else:
             out = [r.as_dict() for r in self._pending]
         self._pending = []
+        self._frames_keep = []
         return out
 
     def set_pose_history(self, T_older, T_newer):
@@ -451,6 +455,7 @@ class BatchTracker:
                                           ctypes.cast(mp, _vp), self.stream, ctypes.byref(h)))
         self._h = h
         self._pending = []
+        self._frames_keep = []  # window frames until their tracks are synchronised
 
     def close(self):
         if getattr(self, "_h", None):
@@ -545,6 +550,7 @@ class BatchTracker:
             mode, None if T is None else T.ctypes.data, ctypes.cast(res, _vp)))
         size = ctypes.sizeof(Result) * self.n
         self._pending.extend((Result * self.n).from_buffer(res, f * size) for f in range(F))
+        self._frames_keep.append([q[5] for q in parts])  # device frames are read by the track launch too
 
     def synchronize(self, arrays: bool = False):
         """Results of the enqueued tracks, in order: one list of n per enqueue, or
@@ -555,6 +561,7 @@ class BatchTracker:
         except DptError as err:  # the results travel with the error (err.results)
             err.results = [[r.as_dict() for r in res] for res in self._pending]
             self._pending = []
+            self._frames_keep = []
             raise
         if arrays:
             out = np.stack([np.frombuffer(res, dtype=RESULT_DTYPE) for res in self._pending]) if self._pending \
@@ -562,6 +569,7 @@ class BatchTracker:
         else:
             out = [[r.as_dict() for r in res] for res in self._pending]
         self._pending = []
+        self._frames_keep = []
         return out
 
     def set_pose_history(self, s: int, T_older, T_newer):
