@@ -5,7 +5,8 @@
  *
  * Job file (native byte order): int32 W, H, levels, n; double fx, fy, cx, cy;
  * double T_rw[16], T_init[16]; uint8 ref[W*H], cur[W*H]; float xyz[n*3].
- * Output file: the dpt_result struct as returned.
+ * Output file: the dpt_result of dpt_track_frame, then that of a one-frame
+ * window track of the same host frame from the same start.
  *
  * usage: track_pair JOB OUT */
 #include <stdio.h>
@@ -68,15 +69,19 @@ int main(int argc, char** argv) {
   prm.flags = 0;
 
   dpt_ctx* ctx = NULL;
-  dpt_result res;
+  dpt_result res, win;
   int rc = 1;
   if (check(dpt_create(&cam, &prm, n > 0 ? n : 1, NULL, &ctx), "dpt_create")) goto done;
   if (check(dpt_build_pyramid(ctx, DPT_SLOT_REF, ref, W, 0), "dpt_build_pyramid(REF)")) goto done;
   if (check(dpt_set_reference_points(ctx, xyz, n, T_rw, 0), "dpt_set_reference_points")) goto done;
   if (check(dpt_build_pyramid(ctx, DPT_SLOT_CUR, cur, W, 0), "dpt_build_pyramid(CUR)")) goto done;
   if (check(dpt_track_frame(ctx, T_init, &res), "dpt_track_frame")) goto done;
+  if (check(dpt_track_window_enqueue(ctx, cur, W, (int64_t)W * H, 1, 0, DPT_INIT_GIVEN, T_init, &win),
+            "dpt_track_window_enqueue") ||
+      check(dpt_synchronize(ctx), "dpt_synchronize"))
+    goto done;
   f = fopen(argv[2], "wb");
-  if (!f || fwrite(&res, sizeof res, 1, f) != 1) {
+  if (!f || fwrite(&res, sizeof res, 1, f) != 1 || fwrite(&win, sizeof win, 1, f) != 1) {
     fprintf(stderr, "cannot write %s\n", argv[2]);
     if (f) fclose(f);
     goto done;

@@ -1,6 +1,8 @@
 """The C ABI from plain C: tests/c/track_pair.c includes include/dptrack.h as
-C99, links libdptrack.so and tracks one frame with no Python in its process.
-CPU: it compiles and links warning-free.  GPU: its pose matches the oracle's."""
+C99, links libdptrack.so and tracks one frame with no Python in its process,
+frame by frame and as a one-frame window track of the host image.  CPU: it
+compiles and links warning-free.  GPU: its pose matches the oracle's and the
+window track returns the same bytes."""
 import os
 import struct
 import subprocess
@@ -52,6 +54,7 @@ def test_c_client_tracks_like_the_oracle(tmp_path, seed):
     print(r.stdout, r.stderr)
     assert r.returncode == 0
     raw = out.read_bytes()
+    assert len(raw) % 2 == 0 and raw[:len(raw) // 2] == raw[len(raw) // 2:]  # the window track: bitwise the same
     T = np.frombuffer(raw[:128], np.float64).reshape(4, 4)
     final_cost = struct.unpack("d", raw[128:136])[0]
     iterations, status = struct.unpack("i", raw[136:140])[0], struct.unpack("i", raw[176:180])[0]
