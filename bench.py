@@ -121,7 +121,7 @@ def new_stats():
     return {k: [] for k in ("samples", "iters", "status", "T", "init", "gt")}
 
 
-SYNC_EVERY = 24  # windows enqueued between synchronisations (24 x 9 tracks fit the 256-slot ring)
+LOOKAHEAD = 8  # windows kept enqueued ahead: the oldest one's results are collected while the rest run
 # Launches between two timed ones in the timed region: each HIP event record is a
 # queue marker that holds the next kernel for several microseconds, so timing
 # every launch would slow the stream by ~20 us per frame.
@@ -194,8 +194,8 @@ def timed_plain(dpt, synth, wins, dev, steps, warmup, prm, launch, chunk, n_poin
         w = (warmup + s) % n
         enqueue_window(dpt, trk, wins[w], dev[w], n_points, window)
         done.append(wins[w])
-        if len(done) % SYNC_EVERY == 0:
-            results.append(trk.synchronize(arrays=True))
+        if s >= LOOKAHEAD:  # the GPU keeps LOOKAHEAD windows while the host takes the oldest one's results
+            results.append(trk.collect(WINDOW - 1, arrays=True))
     results.append(trk.synchronize(arrays=True))
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
@@ -292,8 +292,8 @@ def _batched_run(dpt, wins, frames, wframes, depths, T_rw, T_prev, n_streams, st
     t0 = time.perf_counter()
     for st in range(steps):
         enqueue((warmup + st) % n_win)
-        if (st + 1) % SYNC_EVERY == 0:
-            results.append(bt.synchronize(arrays=True))
+        if st >= LOOKAHEAD:  # as in timed_plain
+            results.append(bt.collect(WINDOW - 1, arrays=True))
     results.append(bt.synchronize(arrays=True))
     torch.cuda.synchronize()
     el = time.perf_counter() - t0

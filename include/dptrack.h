@@ -202,6 +202,21 @@ int dpt_track_enqueue(dpt_ctx* ctx, int32_t init_mode, const double T_cw_init[16
  * Returns DPT_E_HIP if one of them timed out (its result has status 4). */
 int dpt_synchronize(dpt_ctx* ctx);
 
+/* Fill the results of the oldest n enqueued tracks as soon as they have
+ * finished, while the tracks enqueued after them keep the GPU busy: a serving
+ * loop collects finished frames without draining the stream.  The host polls
+ * the results in host memory (each written last with its sequence number).
+ * DPT_E_ARG if fewer than n tracks are in flight; if one of the n timed out,
+ * behaves as dpt_synchronize (waits for everything, DPT_E_HIP); DPT_E_HIP if
+ * the stream ran dry without the results or none came within 60 s. */
+int dpt_collect(dpt_ctx* ctx, int32_t n);
+
+/* Number of enqueued tracks whose results no dpt_synchronize or dpt_collect
+ * has filled yet (calls that wait for the stream themselves, such as
+ * dpt_track_frame or a launch-configuration change, fill them too), or a
+ * negative error code. */
+int dpt_tracks_in_flight(dpt_ctx* ctx);
+
 /* Set the pose history used by DPT_INIT_CONST_VELOCITY (row-major 4x4 T_cw,
  * older first), ordered on the stream with the tracks.  Initially identity. */
 int dpt_set_pose_history(dpt_ctx* ctx, const double T_older[16], const double T_newer[16]);
@@ -405,6 +420,10 @@ int dpt_batch_track(dpt_batch* b, const double* T_cw_init, dpt_result* out);
  * with DPT_INIT_CONST_VELOCITY; out: n_streams results) or for stream `s`. */
 int dpt_batch_track_enqueue(dpt_batch* b, int32_t init_mode, const double* T_cw_init, dpt_result* out);
 int dpt_batch_synchronize(dpt_batch* b);
+/* As dpt_collect / dpt_tracks_in_flight: the oldest n batched tracks (each
+ * n_streams results), and how many are in flight. */
+int dpt_batch_collect(dpt_batch* b, int32_t n);
+int dpt_batch_tracks_in_flight(dpt_batch* b);
 int dpt_batch_set_pose_history(dpt_batch* b, int32_t s, const double T_older[16], const double T_newer[16]);
 /* Pose histories of every stream at once (n_streams row-major 4x4 each), one launch. */
 int dpt_batch_set_pose_history_all(dpt_batch* b, const double* T_older, const double* T_newer);

@@ -103,6 +103,8 @@ SIGNATURES = {
                                                           ctypes.POINTER(ctypes.c_double)]),
     "dpt_track_frame": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(Result)]),
     "dpt_track_enqueue": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ctypes.c_double), _vp]),
+    "dpt_collect": (ctypes.c_int, [_vp, _i32]),
+    "dpt_tracks_in_flight": (ctypes.c_int, [_vp]),
     "dpt_track_window_enqueue": (ctypes.c_int, [_vp, _vp, _i64, _i64, _i32, _i32, _i32,
                                                 ctypes.POINTER(ctypes.c_double), _vp]),
     "dpt_synchronize": (ctypes.c_int, [_vp]),
@@ -124,6 +126,8 @@ SIGNATURES = {
     "dpt_batch_set_reference_points": (ctypes.c_int, [_vp, _i32, _vp, _i32, ctypes.POINTER(ctypes.c_double), _i32]),
     "dpt_batch_track": (ctypes.c_int, [_vp, _vp, _vp]),
     "dpt_batch_track_enqueue": (ctypes.c_int, [_vp, _i32, _vp, _vp]),
+    "dpt_batch_collect": (ctypes.c_int, [_vp, _i32]),
+    "dpt_batch_tracks_in_flight": (ctypes.c_int, [_vp]),
     "dpt_batch_track_window_enqueue": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _i32, _i32, _vp, _vp]),
     "dpt_batch_synchronize": (ctypes.c_int, [_vp]),
     "dpt_batch_set_reference_from_depth_all": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp, ctypes.POINTER(ctypes.c_double)]),
@@ -347,6 +351,7 @@ class Tracker:
         else:
             _check(self._lib.dpt_track_enqueue(self._h, INIT_GIVEN, _mat(T_cw_init), ctypes.byref(r)))
         self._pending.append(r)
+        self._frames_keep.append(None)
 
     def track_window_enqueue(self, frames, T_cw_init=None):
         """Enqueue the track of consecutive frames (a [F, H, W] uint8 NumPy array on
@@ -361,7 +366,28 @@ class Tracker:
                                                   INIT_CONST_VELOCITY if T is None else INIT_GIVEN, T,
                                                   ctypes.cast(res, _vp)))
         self._pending.extend(res[f] for f in range(F))
-        self._frames_keep.append(keep)  # device frames are read by the track launch too
+        # device frames are read by the track launch too: kept with the window's last result
+        self._frames_keep.extend([None] * (F - 1) + [keep])
+
+    def collect(self, n: int, arrays: bool = False):
+        """Results of the oldest n enqueued tracks as soon as they have finished; the
+        later ones keep running.  Same forms as synchronize()."""
+        if not 0 <= n <= len(self._pending):
+            raise ValueError(f"{n} results asked, {len(self._pending)} enqueued")
+        ready = len(self._pending) - self._lib.dpt_tracks_in_flight(self._h)  # filled by an earlier wait
+        try:
+            if n > ready:
+                _check(self._lib.dpt_collect(self._h, n - ready))
+        except DptError as err:  # a timeout synchronised everything: all results travel with the error
+            err.results = [r.as_dict() for r in self._pending]
+            self._pending, self._frames_keep = [], []
+            raise
+        got, self._pending = self._pending[:n], self._pending[n:]
+        self._frames_keep = self._frames_keep[n:]
+        if arrays:
+            return np.concatenate([np.frombuffer(r, dtype=RESULT_DTYPE) for r in got]) if got \
+                else np.empty(0, RESULT_DTYPE)
+        return [r.as_dict() for r in got]
 
     def synchronize(self, arrays: bool = False):
         """Results of the enqueued tracks, in order: a list of dicts, or (arrays=True)
@@ -522,6 +548,7 @@ class BatchTracker:
             T = np.ascontiguousarray(np.asarray(T_cw_init, np.float64).reshape(self.n, 16))
             _check(self._lib.dpt_batch_track_enqueue(self._h, INIT_GIVEN, T.ctypes.data, ctypes.cast(res, _vp)))
         self._pending.append(res)
+        self._frames_keep.append(None)
 
     def track_window_enqueue(self, frames, T_cw_init=None):
         """Window tracking of every stream (Tracker.track_window_enqueue): frames is
@@ -550,7 +577,28 @@ class BatchTracker:
             mode, None if T is None else T.ctypes.data, ctypes.cast(res, _vp)))
         size = ctypes.sizeof(Result) * self.n
         self._pending.extend((Result * self.n).from_buffer(res, f * size) for f in range(F))
-        self._frames_keep.append([q[5] for q in parts])  # device frames are read by the track launch too
+        # device frames are read by the track launch too: kept with the window's last results
+        self._frames_keep.extend([None] * (F - 1) + [[q[5] for q in parts]])
+
+    def collect(self, k: int, arrays: bool = False):
+        """Results of the oldest k enqueued batched tracks as soon as they have
+        finished; the later ones keep running.  Same forms as synchronize()."""
+        if not 0 <= k <= len(self._pending):
+            raise ValueError(f"{k} results asked, {len(self._pending)} enqueued")
+        ready = len(self._pending) - self._lib.dpt_batch_tracks_in_flight(self._h)  # filled by an earlier wait
+        try:
+            if k > ready:
+                _check(self._lib.dpt_batch_collect(self._h, k - ready))
+        except DptError as err:  # a timeout synchronised everything: all results travel with the error
+            err.results = [[r.as_dict() for r in res] for res in self._pending]
+            self._pending, self._frames_keep = [], []
+            raise
+        got, self._pending = self._pending[:k], self._pending[k:]
+        self._frames_keep = self._frames_keep[k:]
+        if arrays:
+            return np.stack([np.frombuffer(res, dtype=RESULT_DTYPE) for res in got]) if got \
+                else np.empty((0, self.n), RESULT_DTYPE)
+        return [[r.as_dict() for r in res] for res in got]
 
     def synchronize(self, arrays: bool = False):
         """Results of the enqueued tracks, in order: one list of n per enqueue, or

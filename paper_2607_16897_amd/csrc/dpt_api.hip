@@ -4,9 +4,11 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <chrono>
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 
 #include "../../include/dptrack.h"
 #include "dpt_internal.h"
@@ -851,6 +853,7 @@ int synchronize(dpt_ctx* c) {
   HIP_TRY(hipStreamSynchronize(c->stream));
   bool timeout = false;
   for (const auto& p : c->pending) {
+    if (p.first < 0) continue;  // ran synchronously, result already filled
     const TrackOut& o = c->eng.out(p.first)[0];
     timeout |= o.status == kStatusTimeout;
     if (p.second) fill_result(c, o, c->eng.start(p.first)[0].T_rw, p.second);
@@ -865,6 +868,48 @@ int synchronize(dpt_ctx* c) {
     (void)hipStreamSynchronize(c->stream);
     return fail(DPT_E_HIP, "cooperative track: chunk synchronisation timed out");
   }
+  return DPT_OK;
+}
+
+// Wait until `done()` holds: the results of a launch in flight arrive through
+// host-mapped memory, each stream's last written after a system-scope fence.
+// Gives up if the stream has run dry without them, or after a minute.
+template <class Done>
+int wait_results(hipStream_t stream, Done done) {
+  const auto t0 = std::chrono::steady_clock::now();
+  for (int64_t k = 0; !done(); ++k) {
+    if ((k & 1023) == 1023) {
+      const hipError_t q = hipStreamQuery(stream);
+      if (q == hipSuccess && !done()) return fail(DPT_E_HIP, "the stream finished without a track's results");
+      if (q != hipSuccess && q != hipErrorNotReady) return fail(DPT_E_HIP, "stream: %s", hipGetErrorString(q));
+      if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(60))
+        return fail(DPT_E_HIP, "no track results after 60 s");
+      std::this_thread::yield();
+    }
+  }
+  return DPT_OK;
+}
+
+// The oldest n tracks in flight: wait for their results only, fill them, and
+// leave the later ones running.  A timeout among them falls back to synchronize().
+int collect(dpt_ctx* c, int n) {
+  if (n < 0 || n > (int)c->pending.size())
+    return fail(DPT_E_ARG, "%d results asked, %d tracks in flight", n, (int)c->pending.size());
+  bool timeout = false;
+  for (int i = 0; i < n; ++i) {
+    const int slot = c->pending[i].first;
+    if (slot < 0) continue;
+    const int e = wait_results(c->stream, [&] { return c->eng.done(slot); });
+    if (e != DPT_OK) return e;
+    const TrackOut& o = c->eng.out(slot)[0];
+    timeout |= o.status == kStatusTimeout;
+  }
+  if (timeout) return synchronize(c);
+  for (int i = 0; i < n; ++i) {
+    const auto& p = c->pending[i];
+    if (p.first >= 0 && p.second) fill_result(c, c->eng.out(p.first)[0], c->eng.start(p.first)[0].T_rw, p.second);
+  }
+  c->pending.erase(c->pending.begin(), c->pending.begin() + n);
   return DPT_OK;
 }
 
@@ -978,7 +1023,9 @@ int dpt_track_enqueue(dpt_ctx* c, int32_t init_mode, const double T_cw_init[16],
   if (!use_coop(c)) {
     if (init_mode == DPT_INIT_CONST_VELOCITY)
       return fail(DPT_E_ARG, "a constant-velocity start needs the cooperative track (launch mode AUTO or COOP)");
-    return dpt_track_frame(c, T_cw_init, out);
+    const int e2 = dpt_track_frame(c, T_cw_init, out);
+    if (e2 == DPT_OK) c->pending.emplace_back(-1, nullptr);  // in order with the tracks in flight, already done
+    return e2;
   }
   return enqueue_coop(c, init_mode == DPT_INIT_GIVEN ? kStartGiven : kStartConstVelocity, T_cw_init, out);
 }
@@ -987,6 +1034,18 @@ int dpt_synchronize(dpt_ctx* c) {
   g_err.clear();
   if (!c) return fail(DPT_E_ARG, "NULL context");
   return synchronize(c);
+}
+
+int dpt_collect(dpt_ctx* c, int32_t n) {
+  g_err.clear();
+  if (!c) return fail(DPT_E_ARG, "NULL context");
+  return collect(c, n);
+}
+
+int dpt_tracks_in_flight(dpt_ctx* c) {
+  g_err.clear();
+  if (!c) return fail(DPT_E_ARG, "NULL context");
+  return (int)c->pending.size();
 }
 
 int dpt_set_pose_history(dpt_ctx* c, const double T_older[16], const double T_newer[16]) {
@@ -1339,6 +1398,7 @@ int batch_synchronize(dpt_batch* b) {
   HIP_TRY(hipStreamSynchronize(b->stream));
   bool timeout = false;
   for (const auto& p : b->pending) {
+    if (p.first < 0) continue;  // ran synchronously, results already filled
     for (size_t gi = 0; gi < b->groups.size(); ++gi) {
       const std::vector<int>& ss = b->group_streams[gi];
       const TrackOut* o = b->groups[gi]->out(p.first);
@@ -1386,6 +1446,37 @@ int batch_enqueue_coop(dpt_batch* b, const int* modes, const double* T_cw_init, 
   for (CoopEngine* g : b->groups) HIP_TRY(g->launch(b->spin_limit, slot));
   if (b->prof) HIP_TRY(b->prof_trk.end(b->stream, ps));
   b->pending.emplace_back(slot, out);
+  return DPT_OK;
+}
+
+// As collect(), for the oldest n batched track launches (each of all streams).
+int batch_collect(dpt_batch* b, int n) {
+  if (n < 0 || n > (int)b->pending.size())
+    return fail(DPT_E_ARG, "%d results asked, %d batched tracks in flight", n, (int)b->pending.size());
+  bool timeout = false;
+  for (int i = 0; i < n; ++i) {
+    const int slot = b->pending[i].first;
+    if (slot < 0) continue;
+    for (CoopEngine* g : b->groups) {
+      const int e = wait_results(b->stream, [&] { return g->done(slot); });
+      if (e != DPT_OK) return e;
+      const TrackOut* o = g->out(slot);
+      for (int k = 0; k < g->n; ++k) timeout |= o[k].status == kStatusTimeout;
+    }
+  }
+  if (timeout) return batch_synchronize(b);
+  for (int i = 0; i < n; ++i) {
+    const auto& p = b->pending[i];
+    if (p.first < 0) continue;
+    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+      const std::vector<int>& ss = b->group_streams[gi];
+      const TrackOut* o = b->groups[gi]->out(p.first);
+      const StartSlot* st = b->groups[gi]->start(p.first);
+      for (size_t k = 0; k < ss.size(); ++k)
+        if (p.second) fill_result(b->ctx[ss[k]], o[k], st[k].T_rw, &p.second[ss[k]]);
+    }
+  }
+  b->pending.erase(b->pending.begin(), b->pending.begin() + n);
   return DPT_OK;
 }
 
@@ -1714,7 +1805,9 @@ int dpt_batch_track_enqueue(dpt_batch* b, int32_t init_mode, const double* T_cw_
   if (!batch_use_coop(b)) {
     if (init_mode == DPT_INIT_CONST_VELOCITY)
       return fail(DPT_E_ARG, "a constant-velocity start needs the cooperative track (launch mode AUTO or COOP)");
-    return dpt_batch_track(b, T_cw_init, out);
+    const int e2 = dpt_batch_track(b, T_cw_init, out);
+    if (e2 == DPT_OK) b->pending.emplace_back(-1, nullptr);  // in order with the tracks in flight, already done
+    return e2;
   }
   std::vector<int> modes(b->n, init_mode == DPT_INIT_GIVEN ? kStartGiven : kStartConstVelocity);
   return batch_enqueue_coop(b, modes.data(), T_cw_init, out);
@@ -1724,6 +1817,18 @@ int dpt_batch_synchronize(dpt_batch* b) {
   g_err.clear();
   if (!b) return fail(DPT_E_ARG, "NULL batch");
   return batch_synchronize(b);
+}
+
+int dpt_batch_collect(dpt_batch* b, int32_t n) {
+  g_err.clear();
+  if (!b) return fail(DPT_E_ARG, "NULL batch");
+  return batch_collect(b, n);
+}
+
+int dpt_batch_tracks_in_flight(dpt_batch* b) {
+  g_err.clear();
+  if (!b) return fail(DPT_E_ARG, "NULL batch");
+  return (int)b->pending.size();
 }
 
 int dpt_batch_track_window_enqueue(dpt_batch* b, const uint8_t* const* frames, const int64_t* pitches,

@@ -275,7 +275,8 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
                                                            const int2* __restrict__ work,
                                                            const StartSlot* __restrict__ start,
                                                            TrackOut* __restrict__ out_ring, int slot, int n_out,
-                                                           int n_frames, uint32_t tag_base, int spin_limit) {
+                                                           int n_frames, uint32_t seq0, uint32_t tag_base,
+                                                           int spin_limit) {
   static_assert(!(MIXED && FIXED), "the fixed-H mode computes in FP32");
   static_assert(!(MIXED && GENERIC) && (GENERIC || std::is_same<PIX, uint8_t>::value), "variant");
   using PR = typename std::conditional<GENERIC, PointGeo,
@@ -445,6 +446,8 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
         o->n_valid_points = (int)sh_tot[sP];
         o->status = timed_out ? kStatusTimeout : status;
         o->samples = samples + (int64_t)sh_tot[sN];
+        __threadfence_system();  // the fields reach the host before the sequence number
+        o->seq = seq0;
       }
       return;
     }
@@ -469,6 +472,10 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
         // a chunk gave up: so do the frames after this one
         if (timed_out)
           for (int q = f + 1; q < nf; ++q) out_ring[(size_t)((slot + q) % kRing) * n_out + w.x].status = kStatusTimeout;
+        __threadfence_system();  // the fields reach the host before the sequence numbers
+        o->seq = seq0 + f;
+        if (timed_out)
+          for (int q = f + 1; q < nf; ++q) out_ring[(size_t)((slot + q) % kRing) * n_out + w.x].seq = seq0 + q;
       }
     }
     __syncthreads();
@@ -570,10 +577,10 @@ int coop_max_blocks(int chunk) {
 // into a reported timeout, not a hang.
 template <int CH>
 static hipError_t coop_launch_k(const CoopStream* d_streams, const int2* d_work, int n_work, const StartSlot* start,
-                                TrackOut* out_ring, int slot, int n_out, int n_frames, uint32_t tag_base, int variant,
-                                int spin_limit, hipStream_t s) {
-  void* args[] = {(void*)&d_streams, (void*)&d_work,   (void*)&start,    (void*)&out_ring, (void*)&slot,
-                  (void*)&n_out,     (void*)&n_frames, (void*)&tag_base, (void*)&spin_limit};
+                                TrackOut* out_ring, int slot, int n_out, int n_frames, uint32_t seq0, uint32_t tag_base,
+                                int variant, int spin_limit, hipStream_t s) {
+  void* args[] = {(void*)&d_streams, (void*)&d_work,   (void*)&start, (void*)&out_ring, (void*)&slot,
+                  (void*)&n_out,     (void*)&n_frames, (void*)&seq0,  (void*)&tag_base, (void*)&spin_limit};
   const void* fn = n_frames > 0 ? coop_fn<CH, true>(variant) : coop_fn<CH, false>(variant);
   if (!fn) return hipErrorInvalidValue;
   if (4 * n_work <= coop_max_blocks(CH)) return hipLaunchKernel(fn, dim3(n_work), dim3(CH), args, 0, s);
@@ -581,19 +588,19 @@ static hipError_t coop_launch_k(const CoopStream* d_streams, const int2* d_work,
 }
 
 hipError_t launch_coop_track(const CoopStream* d_streams, const int2* d_work, int n_work, const StartSlot* start,
-                             TrackOut* out_ring, int slot, int n_out, int n_frames, uint32_t tag_base, int chunk,
-                             int variant, int spin_limit, hipStream_t s) {
+                             TrackOut* out_ring, int slot, int n_out, int n_frames, uint32_t seq0, uint32_t tag_base,
+                             int chunk, int variant, int spin_limit, hipStream_t s) {
   if (slot < 0 || slot >= kRing || n_frames < 0 || n_frames > kRing) return hipErrorInvalidValue;
   switch (chunk) {
     case 64:
-      return coop_launch_k<64>(d_streams, d_work, n_work, start, out_ring, slot, n_out, n_frames, tag_base, variant,
-                               spin_limit, s);
+      return coop_launch_k<64>(d_streams, d_work, n_work, start, out_ring, slot, n_out, n_frames, seq0, tag_base,
+                               variant, spin_limit, s);
     case 128:
-      return coop_launch_k<128>(d_streams, d_work, n_work, start, out_ring, slot, n_out, n_frames, tag_base, variant,
-                                spin_limit, s);
+      return coop_launch_k<128>(d_streams, d_work, n_work, start, out_ring, slot, n_out, n_frames, seq0, tag_base,
+                                variant, spin_limit, s);
     case 256:
-      return coop_launch_k<256>(d_streams, d_work, n_work, start, out_ring, slot, n_out, n_frames, tag_base, variant,
-                                spin_limit, s);
+      return coop_launch_k<256>(d_streams, d_work, n_work, start, out_ring, slot, n_out, n_frames, seq0, tag_base,
+                                variant, spin_limit, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -718,10 +725,22 @@ hipError_t CoopEngine::launch(int spin_limit, int slot, int n_frames) {
   if (tag_base > 0xFFFFFFFFu - span) {  // wrap: restart the tags on cleared words
     if ((e = clear_partials()) != hipSuccess) return e;
   }
-  e = launch_coop_track(d_streams, d_work, grid(), dv_start + (size_t)slot * n, dv_out, slot, n, n_frames, tag_base,
-                        chunk, variant, spin_limit, stream);
+  const int nf = std::max(n_frames, 1);
+  if (seq_next > 0xFFFFFFFFu - (uint32_t)nf) seq_next = 1;  // 0 never marks a result
+  const uint32_t seq0 = seq_next;
+  seq_next += (uint32_t)nf;
+  for (int f = 0; f < nf; ++f) slot_seq[(slot + f) % kRing] = seq0 + (uint32_t)f;
+  e = launch_coop_track(d_streams, d_work, grid(), dv_start + (size_t)slot * n, dv_out, slot, n, n_frames, seq0,
+                        tag_base, chunk, variant, spin_limit, stream);
   tag_base += span;
   return e;
+}
+
+bool CoopEngine::done(int slot) const {
+  const TrackOut* o = h_out + (size_t)slot * n;
+  for (int k = 0; k < n; ++k)
+    if (__atomic_load_n(&o[k].seq, __ATOMIC_ACQUIRE) != slot_seq[slot]) return false;
+  return true;
 }
 
 hipError_t CoopEngine::clear_partials() {

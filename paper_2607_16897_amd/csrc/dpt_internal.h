@@ -75,7 +75,7 @@ struct TrackOut {
   int32_t iters_per_level[kMaxLevels];
   int32_t n_valid_points;
   int32_t status;
-  int32_t pad;
+  uint32_t seq;  // written last, after a system-scope fence: the launch's sequence number + frame
   int64_t samples;
 };
 
@@ -230,6 +230,8 @@ struct CoopEngine {
   uint64_t* d_partials = nullptr;
   size_t partial_words = 0;
   uint32_t tag_base = 1;       // epoch tags of the next launch start here; 0 marks a cleared word
+  uint32_t seq_next = 1;       // sequence number of the next launch's first frame (never 0)
+  uint32_t slot_seq[kRing] = {};  // the sequence number each ring slot's results will carry
   StartSlot* h_start = nullptr;   // [kRing][n], host-mapped
   StartSlot* dv_start = nullptr;  // device view of h_start
   int variant = kCoopFP32;        // kernel variant (kCoop* bits)
@@ -247,6 +249,8 @@ struct CoopEngine {
   // many consecutive frames of each stream's window pyramids in one launch,
   // frame f's results in out((slot + f) % kRing).
   hipError_t launch(int spin_limit, int slot, int n_frames = 0);
+  // Whether every stream's results in ring slot `slot` have arrived (non-blocking).
+  bool done(int slot) const;
   hipError_t clear_partials();
   ~CoopEngine() { release(); }
 };
@@ -294,8 +298,8 @@ hipError_t launch_normal_equations(const TrackArgs& a, hipStream_t s);
 // n_frames = 0: one frame from each stream's current pyramid (a.cur / a.curf),
 // n_frames > 0: that many frames from the streams' window pyramids.
 hipError_t launch_coop_track(const CoopStream* d_streams, const int2* d_work, int n_work, const StartSlot* start,
-                             TrackOut* out_ring, int slot, int n_out, int n_frames, uint32_t tag_base, int chunk,
-                             int variant, int spin_limit, hipStream_t s);
+                             TrackOut* out_ring, int slot, int n_out, int n_frames, uint32_t seq0, uint32_t tag_base,
+                             int chunk, int variant, int spin_limit, hipStream_t s);
 // Set a pose history (two row-major 4x4 T_cw) on the stream.
 hipError_t launch_set_history(double* hist, const double* T0, const double* T1, hipStream_t s);
 // Pose histories of n streams: d_vals[24 s ..] = (older, newer) 3x4 into d_hists[s] (device arrays).

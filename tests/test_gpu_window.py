@@ -296,3 +296,76 @@ def test_window_eight_levels_odd_width(gpu_lib):
         got = trk.synchronize()
         _assert_same(want, got)
         assert all(r["status"] in (0, 1) for r in got)
+
+
+def test_collect_oldest_results_while_the_rest_runs(gpu_lib):
+    """collect(n) returns the oldest n results as they finish, in order, equal
+    to what synchronize() returns for the same work; results filled by a call
+    that waits for the stream itself come back at once; errors and the
+    timeout fallback."""
+    import torch
+
+    dpt = gpu_lib
+    cam, n = synth.CAM_640, 1000
+    seq = _sequence(41, cam, 6)
+    prm = dpt.make_params(levels=3)
+    frames = torch.from_numpy(seq["frames"]).cuda()
+
+    def run(take):
+        trk = _tracker(dpt, cam, seq, n, prm)
+        for _ in range(3):
+            trk.set_pose_history(seq["T_prev"], seq["T0"])
+            trk.track_window_enqueue(frames)
+        return take(trk)
+
+    want = run(lambda t: t.synchronize())
+    got = run(lambda t: t.collect(6) + t.collect(7) + t.synchronize())
+    assert len(want) == len(got) == 18
+    _assert_same(want, got)
+    arr = run(lambda t: np.concatenate([t.collect(6, arrays=True), t.synchronize(arrays=True)]))
+    np.testing.assert_array_equal(arr["T_cw"].reshape(-1, 16), np.stack([np.asarray(r["T_cw"]).reshape(16) for r in want]))
+    # results a waiting call filled already
+    trk = _tracker(dpt, cam, seq, n, prm)
+    trk.track_window_enqueue(frames)
+    trk.set_launch_config(dpt.LAUNCH_COOP, 128)  # waits for the stream
+    assert dpt.load().dpt_tracks_in_flight(trk._h) == 0
+    _assert_same(want[:6], trk.collect(6))
+    with pytest.raises(ValueError):
+        trk.collect(1)
+    assert dpt.load().dpt_collect(trk._h, 1) == dpt.DPT_E_ARG
+    # a timeout among the collected tracks: everything is synchronised, the results travel with the error
+    trk.set_spin_limit(0)
+    trk.track_window_enqueue(frames)
+    trk.track_window_enqueue(frames)
+    with pytest.raises(dpt.DptError) as ei:
+        trk.collect(3)
+    assert len(ei.value.results) == 12 and all(r["status"] == dpt.TRACK_TIMEOUT for r in ei.value.results)
+    assert trk.synchronize() == []
+
+
+def test_batch_collect(gpu_lib):
+    import torch
+
+    dpt = gpu_lib
+    cam = synth.CAM_640
+    seqs = [_sequence(50 + s, cam, 4) for s in range(3)]
+    ns = [400, 900, 1500]
+    prm = dpt.make_params(levels=3)
+
+    def run(take):
+        bt = dpt.BatchTracker([cam] * 3, prm, ns)
+        bt.build_pyramids(dpt.SLOT_REF, [q["img0"] for q in seqs])
+        for s, q in enumerate(seqs):
+            bt.set_reference_from_depth(s, ns[s], q["depth"], q["T0"])
+            bt.set_pose_history(s, q["T_prev"], q["T0"])
+        for j in range(2):
+            bt.build_pyramids(dpt.SLOT_CUR, [q["frames"][j] for q in seqs])
+            bt.track_enqueue(None)
+        bt.track_window_enqueue([torch.from_numpy(q["frames"][2:]).cuda() for q in seqs])
+        return take(bt)
+
+    want = run(lambda b: b.synchronize())
+    got = run(lambda b: b.collect(1) + b.collect(2) + b.collect(1))
+    assert len(want) == len(got) == 4
+    for j in range(4):
+        _assert_same(want[j], got[j])
