@@ -431,6 +431,12 @@ int dpt_create(const dpt_camera* cam, const dpt_params* prm, int32_t max_points,
     delete c;
     return e;
   }
+  // the selection passes leave their histograms cleared for the next run: start cleared
+  if (hipMemset(c->sel_scratch, 0, sizeof(int32_t) * select_scratch_ints(cam->width, cam->height)) != hipSuccess) {
+    (void)hipGetLastError();
+    delete c;
+    return fail(DPT_E_HIP, "selection scratch initialisation failed");
+  }
   if ((prm->flags & DPT_FLAG_GAUSS_F32) && ((e = dev_alloc((void**)&c->pyrf[0], (size_t)off * sizeof(float))) ||
                                             (e = dev_alloc((void**)&c->pyrf[1], (size_t)off * sizeof(float))))) {
     delete c;
@@ -1717,6 +1723,7 @@ int dpt_batch_set_reference_from_depth_all(dpt_batch* b, const int32_t* n_points
   HIP_TRY(b->bp_args.acquire(&hb, &wb));
   HIP_TRY(b->pre_args.acquire(&hp, &wp));
   int G_max = 0, max_n = 0, max_samples = 0, max_levels = 0;
+  bool any_empty = false;
   for (int s = 0; s < b->n; ++s) {
     dpt_ctx* c = b->ctx[s];
     const int n = n_points[s];
@@ -1734,6 +1741,7 @@ int dpt_batch_set_reference_from_depth_all(dpt_batch* b, const int32_t* n_points
     bp.P = c->pts;
     hp[s] = precompute_args(c, c->pts, n, T_rw + 16 * s);
     G_max = std::max(G_max, hs[s].G);
+    any_empty |= hs[s].G == 0;
     max_n = std::max(max_n, n);
     max_samples = std::max(max_samples, n * c->prm.n_pattern);
     max_levels = std::max(max_levels, c->prm.levels);
@@ -1744,7 +1752,7 @@ int dpt_batch_set_reference_from_depth_all(dpt_batch* b, const int32_t* n_points
   HIP_TRY(b->sel_jobs.upload(ws, b->n, b->stream, &ds));
   HIP_TRY(b->bp_args.upload(wb, b->n, b->stream, &db));
   HIP_TRY(b->pre_args.upload(wp, b->n, b->stream, &dp));
-  HIP_TRY(launch_select_batch(ds, b->n, G_max, b->stream));
+  HIP_TRY(launch_select_batch(ds, b->n, G_max, any_empty, b->stream));
   HIP_TRY(launch_backproject_batch(db, b->n, max_n, b->stream));
   HIP_TRY(launch_precompute_batch(dp, b->n, max_samples, max_levels, b->stream));
   if (b->ctx[0]->prm.flags & DPT_FLAG_FIXED_H) HIP_TRY(launch_fixed_h_batch(dp, b->n, max_n, max_levels, b->stream));

@@ -276,8 +276,9 @@ hipError_t launch_select(const uint8_t* img, int32_t W, int32_t H, int32_t margi
 SelJob make_sel_job(const uint8_t* img, int32_t W, int32_t H, int32_t margin, int32_t n, int32_t* idx,
                     int32_t* count, int32_t* scratch);
 // Selections of n_img images in one launch sequence; d_jobs in device memory,
-// G_max = the largest chunk count among them.
-hipError_t launch_select_batch(const SelJob* d_jobs, int n_img, int G_max, hipStream_t s);
+// G_max = the largest chunk count among them, any_empty: one has none.  The
+// scratch of every image must start zeroed (a fresh one: hipMemset).
+hipError_t launch_select_batch(const SelJob* d_jobs, int n_img, int G_max, bool any_empty, hipStream_t s);
 hipError_t launch_precompute(const PrecomputeArgs& a, hipStream_t s);
 hipError_t launch_backproject(const BackprojectArgs& a, hipStream_t s);
 // Batched forms: one launch over n references / maps (argument arrays in device memory).

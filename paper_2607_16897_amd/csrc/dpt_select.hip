@@ -22,8 +22,8 @@ namespace dpt {
 
 constexpr int kSelThreads = 256, kSelPPT = 16, kSelChunk = kSelThreads * kSelPPT;
 
-struct SelScratch {  // layout of the int32 scratch buffer
-  static constexpr int kHist1 = 0, kHist2 = 256, kChunks = 768;
+struct SelScratch {  // layout of the int32 scratch buffer (histograms and kDone zero between runs)
+  static constexpr int kHist1 = 0, kHist2 = 256, kDone = 768, kChunks = 772;
 };
 
 int64_t select_scratch_ints(int32_t W, int32_t H) {
@@ -249,13 +249,13 @@ __global__ __launch_bounds__(kSelThreads) void sel_write(SelJob one, const SelJo
   const SelJob j = sel_job(one, many);
   if ((int)blockIdx.x >= j.G) return;
   const SelGeom& g = j.g;
-  const int* __restrict__ sc = j.sc;
+  int* __restrict__ sc = j.sc;
   const int G = j.G;
   int32_t* __restrict__ idx = j.idx;
   int32_t* __restrict__ count = j.count;
   __shared__ int wsum[16];
   __shared__ int red[8];
-  __shared__ int sT, sNeed;
+  __shared__ int sT, sNeed, sLast;
   __shared__ int4 s_score[kSelChunk / 4];  // the chunk's scores, candidate order
   if (threadIdx.x < 64) {
     const int2 r = threshold(g, sc);
@@ -301,6 +301,18 @@ __global__ __launch_bounds__(kSelThreads) void sel_write(SelJob one, const SelJo
       idx[pos++] = (g.m + y) * g.W + (g.m + x);
     }
   if (blockIdx.x == G - 1 && threadIdx.x == 0) *count = base.x + tot;
+  // the last workgroup of the image to finish (every other one has read the
+  // histograms) leaves them cleared for the next selection
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    sLast = atomicAdd(&sc[SelScratch::kDone], 1) == G - 1;
+  }
+  __syncthreads();
+  if (sLast) {
+    for (int b = threadIdx.x; b < SelScratch::kDone; b += blockDim.x) sc[b] = 0;
+    if (threadIdx.x == 0) sc[SelScratch::kDone] = 0;
+  }
 }
 
 SelJob make_sel_job(const uint8_t* img, int32_t W, int32_t H, int32_t margin, int32_t n, int32_t* idx,
@@ -323,11 +335,13 @@ SelJob make_sel_job(const uint8_t* img, int32_t W, int32_t H, int32_t margin, in
 }
 
 // The pipeline for one image (many == nullptr) or for n_img images whose
-// chunk counts are at most G_max.  The histograms are cleared by a kernel, so
-// the sequence can be captured.
-static hipError_t run_select(const SelJob& one, const SelJob* many, int n_img, int G_max, hipStream_t s) {
+// chunk counts are at most G_max.  The write pass leaves the histograms
+// cleared, so sel_clear runs only where an image has no candidates (its count
+// must still be written); the scratch starts zeroed (select_scratch_init).
+static hipError_t run_select(const SelJob& one, const SelJob* many, int n_img, int G_max, bool any_empty,
+                             hipStream_t s) {
   const dim3 grid(G_max > 0 ? G_max : 1, n_img);
-  hipLaunchKernelGGL(sel_clear, dim3(1, n_img), dim3(kSelThreads), 0, s, one, many);
+  if (any_empty) hipLaunchKernelGGL(sel_clear, dim3(1, n_img), dim3(kSelThreads), 0, s, one, many);
   if (G_max > 0) {
     hipLaunchKernelGGL(sel_hist_coarse, grid, dim3(kSelThreads), 0, s, one, many);
     hipLaunchKernelGGL(sel_hist_fine, grid, dim3(kSelThreads), 0, s, one, many);
@@ -340,13 +354,13 @@ static hipError_t run_select(const SelJob& one, const SelJob* many, int n_img, i
 hipError_t launch_select(const uint8_t* img, int32_t W, int32_t H, int32_t margin, int32_t n, int32_t* idx,
                          int32_t* count, int32_t* scratch, hipStream_t s) {
   const SelJob j = make_sel_job(img, W, H, margin, n, idx, count, scratch);
-  return run_select(j, nullptr, 1, j.G, s);
+  return run_select(j, nullptr, 1, j.G, j.G == 0, s);
 }
 
-hipError_t launch_select_batch(const SelJob* d_jobs, int n_img, int G_max, hipStream_t s) {
+hipError_t launch_select_batch(const SelJob* d_jobs, int n_img, int G_max, bool any_empty, hipStream_t s) {
   SelJob none;
   std::memset(&none, 0, sizeof none);
-  return run_select(none, d_jobs, n_img, G_max, s);
+  return run_select(none, d_jobs, n_img, G_max, any_empty, s);
 }
 
 }  // namespace dpt
