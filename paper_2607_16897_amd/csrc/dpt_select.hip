@@ -301,13 +301,12 @@ __global__ __launch_bounds__(kSelThreads) void sel_write(SelJob one, const SelJo
       idx[pos++] = (g.m + y) * g.W + (g.m + x);
     }
   if (blockIdx.x == G - 1 && threadIdx.x == 0) *count = base.x + tot;
-  // the last workgroup of the image to finish (every other one has read the
-  // histograms) leaves them cleared for the next selection
+  // the last workgroup of the image to finish leaves the histograms cleared for
+  // the next selection: every other one used the values it read from them
+  // before its count went up (no fence: nothing written here is read in this
+  // launch, and a release fence would write back the whole L2)
   __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    sLast = atomicAdd(&sc[SelScratch::kDone], 1) == G - 1;
-  }
+  if (threadIdx.x == 0) sLast = atomicAdd(&sc[SelScratch::kDone], 1) == G - 1;
   __syncthreads();
   if (sLast) {
     for (int b = threadIdx.x; b < SelScratch::kDone; b += blockDim.x) sc[b] = 0;
