@@ -369,3 +369,33 @@ def test_batch_collect(gpu_lib):
     assert len(want) == len(got) == 4
     for j in range(4):
         _assert_same(want[j], got[j])
+
+
+def test_collect_after_synchronous_enqueues(gpu_lib):
+    """On the one-workgroup path an enqueue with a given start runs at once;
+    collect() still hands its results back in order with the cooperative ones
+    enqueued around it."""
+    dpt = gpu_lib
+    cam, n = synth.CAM_640, 700
+    seq = _sequence(61, cam, 3)
+    prm = dpt.make_params(levels=3)
+    T = seq["gts"][0]
+    trk = _tracker(dpt, cam, seq, n, prm, launch=(dpt.LAUNCH_WORKGROUP, 256))
+    trk.build_pyramid(dpt.SLOT_CUR, seq["frames"][0])
+    want = trk.track(T)
+    trk.track_enqueue(T)
+    trk.track_enqueue(T)
+    # each ran at once; the second waited for the stream first, which also
+    # filled the first: only the second still counts as in flight
+    assert dpt.load().dpt_tracks_in_flight(trk._h) == 1
+    got = trk.collect(2)
+    for g in got:
+        np.testing.assert_array_equal(g["T_cw"], want["T_cw"])
+    assert trk.synchronize() == []
+    trk.set_launch_config(dpt.LAUNCH_COOP, 256)
+    trk.track_enqueue(T)
+    trk.set_launch_config(dpt.LAUNCH_WORKGROUP, 256)  # no chunk change: nothing waits
+    trk.track_enqueue(T)
+    got = trk.collect(1) + trk.collect(1)
+    assert got[0]["status"] in (0, 1) and got[1]["status"] in (0, 1)
+    np.testing.assert_array_equal(got[1]["T_cw"], want["T_cw"])
