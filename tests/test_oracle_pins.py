@@ -291,6 +291,26 @@ def test_normal_equations_brute_force(k_huber):
         assert abs(ne["E"] - E) <= 1e-9 * max(1.0, E)
 
 
+@pytest.mark.parametrize("k_huber", [9.0, 0.0])
+def test_final_cost_brute_force(k_huber):
+    """The returned cost is the mean rho over the level-0 samples valid at the
+    returned pose, and the valid-point count is theirs (Sec. IV-C: the track
+    hands back a valid pose with its robust photometric error); checked against
+    the independent assembly above at that pose."""
+    d = synth.pair(14)
+    rng = np.random.default_rng(1)
+    idx = np.sort(rng.choice(oracle.select_points(d["ref"], 400, 8), 30, replace=False))
+    P = synth.backproject(d["cam"], d["depth"], idx, d["T_rw"])
+    prm = _params(levels=3, huber_k=k_huber)
+    ref = oracle.Reference(d["cam"], prm, d["ref"], P, np.eye(4))
+    r = ref.track(d["cur"], oracle.se3_exp(np.array([0.001, 0.0, -0.001, 0.002, 0.0, 0.001])))
+    assert r["status"] in (oracle.OK, oracle.MAX_ITERS)
+    assert r["iterations"] == sum(r["iters_per_level"][:3])
+    _, _, E, n, npts = _brute_normal_equations(d, P, 0, r["T_cw"], k_huber, prm)
+    assert r["n_valid_points"] == npts and n == 8 * npts and npts >= 10
+    assert abs(r["final_cost"] - E / n) <= 1e-9 * max(1.0, E / n)
+
+
 def test_fixed_h_equals_irls_without_weights():
     """Paper mode (H reduced once per reference, Sec. IV-B) equals the re-reduced H
     when no weights apply and every reference-valid point stays valid."""
