@@ -363,11 +363,17 @@ def test_perturbation_recovery(seed):
     g = ref.track(d["cur"], d["T_cw_gt"])
     rot, tr = oracle.pose_error(r["T_cw"], d["T_cw_gt"])
     assert r["status"] == oracle.OK
-    assert np.rad2deg(rot) < 0.1 and tr < 4e-3
+    # the floor left by rasterisation, quantisation and bilinear error is
+    # ~0.002-0.015 deg / 0.2-0.8 mm on these seeds
+    assert np.rad2deg(rot) < 0.05 and tr < 2e-3
+    rot0, tr0 = oracle.pose_error(np.eye(4), d["T_cw_gt"])
+    # where the start is well above that floor, the error shrinks at least 8x
+    if np.rad2deg(rot0) > 0.05:
+        assert rot < rot0 / 8
+    if tr0 > 4e-3:
+        assert tr < tr0 / 8
     rot2, tr2 = oracle.pose_error(r["T_cw"], g["T_cw"])
     assert rot2 < 1e-8 and tr2 < 1e-8
-    rot0, tr0 = oracle.pose_error(np.eye(4), d["T_cw_gt"])
-    assert rot < rot0 or rot0 < 2e-3
 
 
 def test_near_zero_residual_at_ground_truth():
@@ -389,7 +395,8 @@ def test_world_frame_equivariance():
     ref2 = oracle.Reference(d["cam"], ref.params, d["ref"], P2, d["T_rw"] @ Gi)
     r2 = ref2.track(d["cur"], Gi)
     rot, tr = oracle.pose_error(r2["T_cw"], r["T_cw"] @ Gi)
-    assert rot < 1e-6 and tr < 1e-6
+    # the moved points are rounded to float32 again (~2e-7 m), hence not 1e-12
+    assert rot < 1e-8 and tr < 1e-8
 
 
 def test_failure_statuses():
@@ -406,3 +413,124 @@ def test_failure_statuses():
     # iteration cap
     capped = oracle.Reference(d["cam"], _params(max_iters=1), d["ref"], P, np.eye(4))
     assert capped.track(d["cur"], np.eye(4))["status"] == oracle.MAX_ITERS
+
+
+# ------------------------------------------------------------------ fixed-H mode (Sec. IV-B, IV-C)
+def _brute_fixed_h(d, P, l, prm):
+    """Independent assembly of the constant H of one level: sum of J^T J over the
+    points whose every pattern position lies inside the reference level (the
+    precompute runs before any current frame exists), with J from np.gradient,
+    map_coordinates and finite differences of scipy's expm; T_rw = I."""
+    cam = d["cam"]
+    ref_l = oracle.pyramid(d["ref"], prm.levels)[l].astype(np.float64)
+    Hl, Wl = ref_l.shape
+    fx, fy, cx, cy = _level_camera(cam, l)
+    gyi, gxi = np.gradient(ref_l)
+    pat = np.array(oracle.DEFAULT_PATTERN, float)
+    H = np.zeros((6, 6))
+    for x0 in P.astype(np.float64):
+        u0, v0 = fx * x0[0] / x0[2] + cx + pat[:, 0], fy * x0[1] / x0[2] + cy + pat[:, 1]
+        if not np.all((u0 >= 1) & (u0 < Wl - 2) & (v0 >= 1) & (v0 < Hl - 2)):
+            continue
+
+        def proj(xi):
+            y = scipy.linalg.expm(_hat(xi)) @ np.append(x0, 1.0)
+            return np.array([fx * y[0] / y[2], fy * y[1] / y[2]])
+
+        h = 1e-7
+        Jw = np.column_stack([(proj(h * e) - proj(-h * e)) / (2 * h) for e in np.eye(6)])
+        g = np.column_stack([map_coordinates(gxi, [v0, u0], order=1), map_coordinates(gyi, [v0, u0], order=1)])
+        for kk in range(len(pat)):
+            J = g[kk] @ Jw
+            H += np.outer(J, J)
+    return H
+
+
+def test_fixed_h_normal_equations_brute_force():
+    """Fixed-H mode at a pose where some residuals exceed the Huber threshold and
+    some reference-valid points leave the current level: H is the constant H of
+    that level (over the reference-valid points), b and E are unweighted (w = 1,
+    rho = r^2 / 2) over the points valid in the current frame, whatever huber_k is."""
+    d = synth.pair(11)
+    rng = np.random.default_rng(5)
+    cand = oracle.select_points(d["ref"], 2000, 8)
+    # half the points from the border band, so a shift moves some out of the level
+    H0, W0 = d["ref"].shape
+    ys, xs = cand // W0, cand % W0
+    near = (xs < 40) | (xs > W0 - 41) | (ys < 40) | (ys > H0 - 41)
+    idx = np.sort(np.concatenate([rng.choice(cand[near], 10, replace=False),
+                                  rng.choice(cand[~near], 10, replace=False)]))
+    P = synth.backproject(d["cam"], d["depth"], idx, d["T_rw"])
+    prm = _params(levels=3, huber_k=9.0, fixed_h=True)
+    ref = oracle.Reference(d["cam"], prm, d["ref"], P, np.eye(4))
+    T_rel = oracle.se3_exp(np.array([0.01, -0.012, 0.004, 0.05, -0.03, 0.02]))
+    Hs = []
+    for l in range(3):
+        ne = ref.normal_equations(d["cur"], l, T_rel)
+        Hb = _brute_fixed_h(d, P, l, prm)
+        _, b0, E0, n, npts = _brute_normal_equations(d, P, l, T_rel, 0.0, prm)
+        _, b9, E9, _, _ = _brute_normal_equations(d, P, l, T_rel, 9.0, prm)
+        assert ne["npts"] == npts and ne["n"] == n and npts > 3
+        np.testing.assert_allclose(ne["H"], Hb, atol=2e-6 * np.abs(Hb).max())
+        np.testing.assert_allclose(ne["b"], b0, atol=2e-6 * np.abs(b0).max())
+        assert abs(ne["E"] - E0) <= 1e-9 * max(1.0, E0)
+        # the case distinguishes the modes: weights and the Huber cost would show
+        assert np.abs(b9 - b0).max() > 1e-3 * np.abs(b0).max() and E9 < 0.99 * E0
+        Hs.append(Hb)
+    # some reference-valid points are outside the current level 0, so the
+    # constant H is not the one of the current-valid points
+    assert ref.cache(0)["refvalid"].sum() > ref.normal_equations(d["cur"], 0, T_rel)["npts"]
+    # every level's H is its own: a wrong level index would fail above
+    for a in range(3):
+        for c in range(a + 1, 3):
+            assert np.abs(Hs[a] - Hs[c]).max() > 0.1 * np.abs(Hs[c]).max()
+
+
+def test_fixed_h_track_equals_irls_without_weights_when_all_points_stay_valid():
+    """With every reference-valid point valid in the current frame at every
+    iteration, the constant H equals the re-reduced unweighted H, so the paper's
+    track and the unweighted IRLS track take the same steps."""
+    d = synth.pair(21)
+    P = synth.backproject(d["cam"], d["depth"], oracle.select_points(d["ref"], 300, 60), d["T_rw"])
+    fixed = oracle.Reference(d["cam"], _params(huber_k=9.0, fixed_h=True), d["ref"], P, d["T_rw"])
+    irls = oracle.Reference(d["cam"], _params(huber_k=0.0), d["ref"], P, d["T_rw"])
+    a = fixed.track(d["cur"], np.eye(4))
+    b = irls.track(d["cur"], np.eye(4))
+    assert a["status"] == b["status"] == oracle.OK
+    assert a["iters_per_level"] == b["iters_per_level"]
+    np.testing.assert_allclose(a["T_cw"], b["T_cw"], rtol=0, atol=1e-12)
+    assert abs(a["final_cost"] - b["final_cost"]) <= 1e-12 * max(1.0, b["final_cost"])
+    assert a["n_valid_points"] == b["n_valid_points"] == len(P)
+
+
+@pytest.mark.parametrize("seed", [0, 17, 45, 80])
+def test_fixed_h_perturbation_recovery(seed):
+    """The paper's constant-H track recovers the rendered perturbation: from the
+    identity it reaches the fixed point it reaches from the true pose."""
+    d, P, ref = _setup(seed, fixed_h=True)
+    r = ref.track(d["cur"], np.eye(4))
+    g = ref.track(d["cur"], d["T_cw_gt"])
+    rot, tr = oracle.pose_error(r["T_cw"], d["T_cw_gt"])
+    rot0, tr0 = oracle.pose_error(np.eye(4), d["T_cw_gt"])
+    assert r["status"] in (oracle.OK, oracle.MAX_ITERS)
+    assert np.rad2deg(rot) < 0.1 and tr < 4e-3
+    assert tr < 0.5 * tr0 or tr0 < 2e-3
+    rot2, tr2 = oracle.pose_error(r["T_cw"], g["T_cw"])
+    assert rot2 < 1e-8 and tr2 < 1e-8
+
+
+def test_fixed_h_final_cost_brute_force():
+    """The fixed-H track returns the unweighted mean cost r^2 / 2 over the level-0
+    samples valid at the returned pose, whatever huber_k is."""
+    d = synth.pair(14)
+    rng = np.random.default_rng(1)
+    idx = np.sort(rng.choice(oracle.select_points(d["ref"], 400, 8), 30, replace=False))
+    P = synth.backproject(d["cam"], d["depth"], idx, d["T_rw"])
+    ref = oracle.Reference(d["cam"], _params(levels=3, huber_k=1.0, fixed_h=True), d["ref"], P, np.eye(4))
+    r = ref.track(d["cur"], oracle.se3_exp(np.array([0.001, 0.0, -0.001, 0.002, 0.0, 0.001])))
+    assert r["status"] in (oracle.OK, oracle.MAX_ITERS)
+    _, _, E0, n, npts = _brute_normal_equations(d, P, 0, r["T_cw"], 0.0, _params(levels=3))
+    _, _, E1, _, _ = _brute_normal_equations(d, P, 0, r["T_cw"], 1.0, _params(levels=3))
+    assert r["n_valid_points"] == npts and n == 8 * npts and npts >= 10
+    assert abs(r["final_cost"] - E0 / n) <= 1e-9 * max(1.0, E0 / n)
+    assert E1 < 0.99 * E0  # the Huber cost at k = 1 would differ
