@@ -564,6 +564,30 @@ def bench_learned_init(dpt, n_streams: int, n_frames: int):
 
 
 # ---------------------------------------------------------------- CPU baseline (the oracle)
+def host_cpu() -> dict:
+    """The host the oracle runs on: CPU model, logical CPUs of the machine
+    (nproc) and of this process's affinity mask, and the share of them the
+    multi-threaded baseline uses: OMP_NUM_THREADS where the environment sets the
+    process's CPU share that way, else every CPU of the affinity mask."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    affinity = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    share = affinity
+    try:
+        share = max(1, min(affinity, int(os.environ.get("OMP_NUM_THREADS", affinity))))
+    except ValueError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity": affinity, "share": share,
+            "share_from": "OMP_NUM_THREADS" if "OMP_NUM_THREADS" in os.environ else "affinity"}
+
+
 def cpu_baseline(wins, seconds: float, comparisons, tween_run=None):
     """The FP64 oracle on one host thread, on the headline windows until
     `seconds` elapse.  `comparisons` maps a leg name to (frames [(window, j)],
@@ -591,11 +615,12 @@ def cpu_baseline(wins, seconds: float, comparisons, tween_run=None):
     out = {"value": round((WINDOW - 1) * n / el, 2), "unit": "frames/s", "cores": 1, "kind": "oracle",
            "sample": f"{n} keyframe windows ({(WINDOW - 1) * n} tracked frames) of the headline sequence in "
                      f"{el:.1f} s, FP64 C oracle (gcc -O2) on one host thread"}
-    # the same windows on every host core the process may use (one window per thread at a time; the
-    # oracle's C calls release the interpreter lock), capped at 16 threads, about a third as long
+    # the same windows on the host cores this GPU's process is given (one window per thread at a time;
+    # the oracle's C calls release the interpreter lock), about a third as long
     from concurrent.futures import ThreadPoolExecutor
 
-    threads = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()))
+    host = host_cpu()
+    threads = host["share"]
 
     def one_window(w):
         win = wins[w % len(wins)]
@@ -617,6 +642,7 @@ def cpu_baseline(wins, seconds: float, comparisons, tween_run=None):
     el_all = time.perf_counter() - t0
     out["all_cores"] = {"value": round(done / el_all, 2), "unit": "frames/s", "cores": threads,
                         "sample": f"{done // (WINDOW - 1)} keyframe windows in {el_all:.1f} s, {threads} threads"}
+    out["host"] = host
     diffs = {}
     for name, (frames, starts, poses, cam, wset, npts, levels, *extra) in comparisons.items():
         p = oracle.make_params(levels=levels, **(extra[0] if extra else {}))

@@ -199,7 +199,11 @@ enum { DPT_INIT_GIVEN = 0, DPT_INIT_CONST_VELOCITY = 1 };
 int dpt_track_enqueue(dpt_ctx* ctx, int32_t init_mode, const double T_cw_init[16], dpt_result* out);
 
 /* Wait for the context's stream and fill the results of every enqueued track.
- * Returns DPT_E_HIP if one of them timed out (its result has status 4). */
+ * Returns DPT_E_HIP if one of them timed out (its result has status 4).
+ * Whatever it returns, no track is in flight afterwards: on a failure of the
+ * wait itself every result of a track that finished is filled, every other one
+ * gets status DPT_TRACK_TIMEOUT, and the library keeps no pointer to the
+ * results or the frames. */
 int dpt_synchronize(dpt_ctx* ctx);
 
 /* Fill the results of the oldest n enqueued tracks as soon as they have
@@ -208,7 +212,9 @@ int dpt_synchronize(dpt_ctx* ctx);
  * the results in host memory (each written last with its sequence number).
  * DPT_E_ARG if fewer than n tracks are in flight; if one of the n timed out,
  * behaves as dpt_synchronize (waits for everything, DPT_E_HIP); DPT_E_HIP if
- * the stream ran dry without the results or none came within 60 s. */
+ * the stream ran dry without the results or none came within 60 s, and then,
+ * as after a failed dpt_synchronize, nothing is in flight any more (finished
+ * tracks filled, the others DPT_TRACK_TIMEOUT). */
 int dpt_collect(dpt_ctx* ctx, int32_t n);
 
 /* Number of enqueued tracks whose results no dpt_synchronize or dpt_collect
@@ -341,7 +347,22 @@ int dpt_get_fixed_hessian(dpt_ctx* ctx, int32_t level, double H36[36], int32_t* 
  *                         Patterns other than the 8-pixel one and the Gaussian
  *                         float pyramid use chunks of 64 points, four threads per
  *                         point, whatever `chunk` says
- * Results agree with each other to rounding (the summation order differs). */
+ * Results agree with each other to rounding (the summation order differs).
+ *
+ * Co-residency.  The chunks of a stream wait for each other's partial sums,
+ * so all workgroups of a cooperative track must run at the same time.  A grid
+ * larger than a quarter of the device's co-resident capacity (two workgroups
+ * per compute unit) goes through the cooperative launch, which the runtime
+ * only starts once every workgroup fits.  A smaller grid (one stream of up to
+ * 16 chunks, or a small batch) is launched as an ordinary kernel to save the
+ * cooperative launch's extra cost; it is co-resident whenever the device has
+ * that much room, which holds while this process runs at most three such
+ * tracks concurrently and no other work fills the compute units.  If other
+ * streams or processes occupy the device so that a chunk cannot start, the
+ * waiting chunks give up after the spin limit (dpt_set_spin_limit) and the
+ * frame ends with DPT_TRACK_TIMEOUT instead of a pose; nothing hangs.  A caller
+ * that shares the device with heavy concurrent work and cannot accept that
+ * outcome uses DPT_LAUNCH_WORKGROUP, which never waits across workgroups. */
 enum { DPT_LAUNCH_AUTO = 0, DPT_LAUNCH_WORKGROUP = 1, DPT_LAUNCH_COOP = 2 };
 int dpt_set_launch_config(dpt_ctx* ctx, int32_t mode, int32_t chunk);
 

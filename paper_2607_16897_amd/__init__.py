@@ -8,8 +8,11 @@ the library is not built, :func:`load` raises.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import sys
+import weakref
 
 import numpy as np
 
@@ -176,6 +179,24 @@ def load():
     return _lib
 
 
+# Every open Tracker, BatchTracker and Cnn.  An interpreter exit closes the ones
+# still open from an atexit hook, which runs before module teardown while torch
+# and the HIP runtime are fully alive; a handle reached by __del__ during the
+# interpreter's own finalisation is left to the process exit instead of calling
+# into HIP at an undefined point of the teardown.
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live():
+    for obj in list(_live):
+        obj.close()
+
+
+def _finalising() -> bool:
+    return sys.is_finalizing()
+
+
 def _check(code: int):
     if code != DPT_OK:
         raise DptError(code, load().dpt_last_error().decode())
@@ -263,13 +284,24 @@ class Tracker:
         self.n_points = 0
         self._pending = []
         self._frames_keep = []  # window frames until their tracks are synchronised
+        _live.add(self)
 
     def close(self):
         if getattr(self, "_h", None):
             self._lib.dpt_destroy(self._h)
             self._h = None
+            self._pending, self._frames_keep = [], []
+        _live.discard(self)
 
-    __del__ = close
+    def __del__(self):
+        if not _finalising():
+            self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
     def build_pyramid(self, slot: int, img, pitch: int | None = None):
         p, dev, keep = _ptr(img)
@@ -378,9 +410,9 @@ class Tracker:
         try:
             if n > ready:
                 _check(self._lib.dpt_collect(self._h, n - ready))
-        except DptError as err:  # a timeout synchronised everything: all results travel with the error
+        except DptError as err:  # all results travel with the error
             err.results = [r.as_dict() for r in self._pending]
-            self._pending, self._frames_keep = [], []
+            self._drop_pending(self._lib.dpt_tracks_in_flight(self._h))
             raise
         got, self._pending = self._pending[:n], self._pending[n:]
         self._frames_keep = self._frames_keep[n:]
@@ -396,8 +428,7 @@ class Tracker:
             _check(self._lib.dpt_synchronize(self._h))
         except DptError as err:  # the results travel with the error (err.results)
             err.results = [r.as_dict() for r in self._pending]
-            self._pending = []
-            self._frames_keep = []
+            self._drop_pending(self._lib.dpt_tracks_in_flight(self._h))
             raise
         if arrays:
             out = np.concatenate([np.frombuffer(r, dtype=RESULT_DTYPE) for r in self._pending]) if self._pending \
@@ -407,6 +438,14 @@ class Tracker:
         self._pending = []
         self._frames_keep = []
         return out
+
+    def _drop_pending(self, in_flight: int):
+        """After a failed wait the library has filled or marked every result and
+        holds no pointer to them (dpt_tracks_in_flight() == 0): the result buffers
+        and the window frames are released.  Should it still report tracks in
+        flight, they stay referenced, since the library may still write them."""
+        if in_flight == 0:
+            self._pending, self._frames_keep = [], []
 
     def set_pose_history(self, T_older, T_newer):
         _check(self._lib.dpt_set_pose_history(self._h, _mat(T_older), _mat(T_newer)))
@@ -482,13 +521,24 @@ class BatchTracker:
         self._h = h
         self._pending = []
         self._frames_keep = []  # window frames until their tracks are synchronised
+        _live.add(self)
 
     def close(self):
         if getattr(self, "_h", None):
             self._lib.dpt_batch_destroy(self._h)
             self._h = None
+            self._pending, self._frames_keep = [], []
+        _live.discard(self)
 
-    __del__ = close
+    def __del__(self):
+        if not _finalising():
+            self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
     def _stacked(self, x):
         """(pointer array, row pitch in elements) of a contiguous [n, H, W] CUDA tensor."""
@@ -589,9 +639,9 @@ class BatchTracker:
         try:
             if k > ready:
                 _check(self._lib.dpt_batch_collect(self._h, k - ready))
-        except DptError as err:  # a timeout synchronised everything: all results travel with the error
+        except DptError as err:  # all results travel with the error
             err.results = [[r.as_dict() for r in res] for res in self._pending]
-            self._pending, self._frames_keep = [], []
+            self._drop_pending(self._lib.dpt_batch_tracks_in_flight(self._h))
             raise
         got, self._pending = self._pending[:k], self._pending[k:]
         self._frames_keep = self._frames_keep[k:]
@@ -608,8 +658,7 @@ class BatchTracker:
             _check(self._lib.dpt_batch_synchronize(self._h))
         except DptError as err:  # the results travel with the error (err.results)
             err.results = [[r.as_dict() for r in res] for res in self._pending]
-            self._pending = []
-            self._frames_keep = []
+            self._drop_pending(self._lib.dpt_batch_tracks_in_flight(self._h))
             raise
         if arrays:
             out = np.stack([np.frombuffer(res, dtype=RESULT_DTYPE) for res in self._pending]) if self._pending \
@@ -619,6 +668,8 @@ class BatchTracker:
         self._pending = []
         self._frames_keep = []
         return out
+
+    _drop_pending = Tracker._drop_pending
 
     def set_pose_history(self, s: int, T_older, T_newer):
         _check(self._lib.dpt_batch_set_pose_history(self._h, s, _mat(T_older), _mat(T_newer)))
@@ -714,13 +765,23 @@ class Cnn:
         _check(self._lib.dpt_cnn_create(max_batch, self.stream, ctypes.byref(h)))
         self._h = h
         self.max_batch = max_batch
+        _live.add(self)
 
     def close(self):
         if getattr(self, "_h", None):
             self._lib.dpt_cnn_destroy(self._h)
             self._h = None
+        _live.discard(self)
 
-    __del__ = close
+    def __del__(self):
+        if not _finalising():
+            self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
     def set_params(self, params):
         flat = cnn_flatten(params) if isinstance(params, dict) else np.ascontiguousarray(params, np.float32)

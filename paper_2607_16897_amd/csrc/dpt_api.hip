@@ -854,9 +854,34 @@ int enqueue_coop(dpt_ctx* c, int mode, const double* T_cw_init, dpt_result* out)
   return DPT_OK;
 }
 
+// After a failed wait: let the stream run out (every wait inside the kernels is
+// bounded, so it does unless the device itself failed), fill the results of
+// the tracks that finished, mark the others TIMEOUT, and forget them all, so no
+// entry of the pending list outlives the caller's result buffers and no kernel
+// still reads the caller's frames.  Leaves the failure's message in place.
+void abandon(dpt_ctx* c) {
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipGetLastError();
+  for (const auto& p : c->pending) {
+    if (p.first < 0 || !p.second) continue;
+    if (c->eng.done(p.first)) {
+      fill_result(c, c->eng.out(p.first)[0], c->eng.start(p.first)[0].T_rw, p.second);
+    } else {
+      std::memset(p.second, 0, sizeof *p.second);
+      p.second->status = kStatusTimeout;
+    }
+  }
+  c->pending.clear();
+}
+
 // Wait for the stream and fill the results of every track in flight.
 int synchronize(dpt_ctx* c) {
-  HIP_TRY(hipStreamSynchronize(c->stream));
+  const hipError_t es = hipStreamSynchronize(c->stream);
+  if (es != hipSuccess) {
+    const int r = fail(DPT_E_HIP, "hipStreamSynchronize: %s", hipGetErrorString(es));
+    abandon(c);
+    return r;
+  }
   bool timeout = false;
   for (const auto& p : c->pending) {
     if (p.first < 0) continue;  // ran synchronously, result already filled
@@ -906,7 +931,10 @@ int collect(dpt_ctx* c, int n) {
     const int slot = c->pending[i].first;
     if (slot < 0) continue;
     const int e = wait_results(c->stream, [&] { return c->eng.done(slot); });
-    if (e != DPT_OK) return e;
+    if (e != DPT_OK) {
+      abandon(c);
+      return e;
+    }
     const TrackOut& o = c->eng.out(slot)[0];
     timeout |= o.status == kStatusTimeout;
   }
@@ -1399,9 +1427,39 @@ bool batch_use_coop(const dpt_batch* b) {
   return b->launch_mode != DPT_LAUNCH_WORKGROUP && coop_max_blocks(coop_threads(b->ctx[0]->prm, b->chunk)) > 0;
 }
 
+// abandon() for a batch: every group's results of every launch in flight.
+void batch_abandon(dpt_batch* b) {
+  (void)hipStreamSynchronize(b->stream);
+  (void)hipGetLastError();
+  for (const auto& p : b->pending) {
+    if (p.first < 0 || !p.second) continue;
+    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+      const std::vector<int>& ss = b->group_streams[gi];
+      const bool fin = b->groups[gi]->done(p.first);
+      const TrackOut* o = b->groups[gi]->out(p.first);
+      const StartSlot* st = b->groups[gi]->start(p.first);
+      for (size_t k = 0; k < ss.size(); ++k) {
+        dpt_result* r = &p.second[ss[k]];
+        if (fin) {
+          fill_result(b->ctx[ss[k]], o[k], st[k].T_rw, r);
+        } else {
+          std::memset(r, 0, sizeof *r);
+          r->status = kStatusTimeout;
+        }
+      }
+    }
+  }
+  b->pending.clear();
+}
+
 // Wait for the stream and fill the results of every batched track in flight.
 int batch_synchronize(dpt_batch* b) {
-  HIP_TRY(hipStreamSynchronize(b->stream));
+  const hipError_t es = hipStreamSynchronize(b->stream);
+  if (es != hipSuccess) {
+    const int r = fail(DPT_E_HIP, "hipStreamSynchronize: %s", hipGetErrorString(es));
+    batch_abandon(b);
+    return r;
+  }
   bool timeout = false;
   for (const auto& p : b->pending) {
     if (p.first < 0) continue;  // ran synchronously, results already filled
@@ -1431,8 +1489,8 @@ int batch_synchronize(dpt_batch* b) {
 // Enqueue one cooperative track of every stream.  modes[s] is kStartGiven
 // (start from T_cw_init[s]) or kStartConstVelocity.
 int batch_enqueue_coop(dpt_batch* b, const int* modes, const double* T_cw_init, dpt_result* out) {
-  if (b->groups_dirty) {  // regrouping frees the rings: finish what is in flight first
-    int e = batch_synchronize(b);
+  if (b->groups_dirty) {  // regrouping frees the rings: finish and fill what is in flight first
+    int e = b->pending.empty() ? DPT_OK : batch_synchronize(b);
     if (e != DPT_OK) return e;
     if ((e = build_groups(b)) != DPT_OK) return e;
   }
@@ -1465,7 +1523,10 @@ int batch_collect(dpt_batch* b, int n) {
     if (slot < 0) continue;
     for (CoopEngine* g : b->groups) {
       const int e = wait_results(b->stream, [&] { return g->done(slot); });
-      if (e != DPT_OK) return e;
+      if (e != DPT_OK) {
+        batch_abandon(b);
+        return e;
+      }
       const TrackOut* o = g->out(slot);
       for (int k = 0; k < g->n; ++k) timeout |= o[k].status == kStatusTimeout;
     }
@@ -1875,7 +1936,10 @@ int dpt_batch_track_window_enqueue(dpt_batch* b, const uint8_t* const* frames, c
       HIP_TRY(hipMemcpy(b->d_winjobs + s, b->ctx[s]->d_winjob, sizeof(WinJob), hipMemcpyDeviceToDevice));
     b->clear_groups();
   }
-  if (b->groups_dirty && (e = build_groups(b)) != DPT_OK) return e;
+  if (b->groups_dirty) {  // regrouping frees the rings: finish and fill what is in flight first
+    if (!b->pending.empty() && (e = batch_synchronize(b)) != DPT_OK) return e;
+    if ((e = build_groups(b)) != DPT_OK) return e;
+  }
   for (CoopEngine* g : b->groups)
     if (g->dirty) HIP_TRY(g->upload());
   // the frames as the pyramid launch and the track read them (host frames

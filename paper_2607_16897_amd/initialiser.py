@@ -99,6 +99,7 @@ def make_dataset(n_refs: int, per_ref: int, seed: int, streams: int = 128, max_d
         if log and (g0 // S) % 10 == 0:
             log(f"dataset: {k}/{n} pairs, {time.perf_counter() - t0:.1f} s")
     torch.cuda.synchronize()
+    bt.close()
     return pairs, targets, {"pairs": n, "seconds": time.perf_counter() - t0, "label_failures": int(fails)}
 
 
@@ -204,6 +205,7 @@ def evaluate(net: Cnn | None, n_streams: int, n_frames: int, seed: int, jerk_deg
         out[mode] = {"iterations_mean": float(its.mean()), "failure_rate": fail / (S * n_frames),
                      "frames_per_s": round(fps, 1)}
     out["gt_start_iterations_mean"] = float(its_gt.mean())
+    bt.close()
     return out
 
 

@@ -238,7 +238,6 @@ def test_sequence_window_full_size(gpu_lib, launch):
 
 
 # ------------------------------------------------------------------ mixed precision
-MIXED_ROT_TOL, MIXED_TR_TOL = 2e-4, 2e-4  # FP16 template cache: stated per result
 
 
 @pytest.mark.parametrize("seed", [0, 3, 21, 77])
@@ -251,7 +250,7 @@ def test_mixed_precision_pair(gpu_lib, seed, chunk):
     rot, tr, rel = _compare(g, o)
     print(f"mixed seed {seed} chunk {chunk}: rot {rot:.2e} rad, trans {tr:.2e} m, cost {rel:.2e}")
     assert g["status"] == o["status"] == 0
-    assert rot < MIXED_ROT_TOL and tr < MIXED_TR_TOL and rel < 5e-3
+    assert rot < ROT_TOL and tr < TR_TOL and rel < COST_TOL
 
 
 def test_mixed_precision_identity(gpu_lib):
@@ -274,7 +273,7 @@ def test_mixed_precision_stress_16k(gpu_lib):
     rot, tr, rel = _compare(g, o)
     print(f"mixed 16k: rot {rot:.2e} rad, trans {tr:.2e} m, cost {rel:.2e}")
     assert g["status"] == o["status"] == 0
-    assert rot < MIXED_ROT_TOL and tr < MIXED_TR_TOL and rel < 5e-3
+    assert rot < ROT_TOL and tr < TR_TOL and rel < COST_TOL
     trk32, _ = _tracker(dpt, cam, 16000, levels=4)
     trk32.set_launch_config(2, 256)
     trk32.build_pyramid(dpt.SLOT_REF, d["ref"])

@@ -412,7 +412,6 @@ def test_window_full_size_against_oracle(gpu_lib, case):
     dpt = gpu_lib
     cam, n = (synth.CAM_752, 2000) if case.startswith("752") else (synth.CAM_1280, 16000)
     mixed = case.endswith("mixed")
-    rot_tol, tr_tol, cost_tol = (2e-4, 2e-4, 5e-3) if mixed else (ROT_TOL, TR_TOL, COST_TOL)
     seq = _sequence(19, cam, 9)
     prm = dpt.make_params(levels=4, precision=1 if mixed else 0)
     trk = _tracker(dpt, cam, seq, n, prm)
@@ -431,5 +430,5 @@ def test_window_full_size_against_oracle(gpu_lib, case):
         print(f"{case} frame {f}: rot {rot:.2e} tr {tr:.2e} cost {rel:.2e} iters {r['iterations']}/{o['iterations']}")
         assert r["status"] in (0, 1) and o["status"] in (0, 1)
         assert abs(r["n_valid_points"] - o["n_valid_points"]) <= 2  # FP32 vs FP64 at the image border
-        assert rot < rot_tol and tr < tr_tol and rel < cost_tol
+        assert rot < ROT_TOL and tr < TR_TOL and rel < COST_TOL
         prev2, prev1 = prev1, np.asarray(r["T_cw"]).reshape(4, 4)
