@@ -439,6 +439,12 @@ class Tracker:
         self._frames_keep = []
         return out
 
+    def tracks_in_flight(self) -> int:
+        """Enqueued tracks whose results the library has not filled yet."""
+        n = self._lib.dpt_tracks_in_flight(self._h)
+        _check(min(n, 0))
+        return n
+
     def _drop_pending(self, in_flight: int):
         """After a failed wait the library has filled or marked every result and
         holds no pointer to them (dpt_tracks_in_flight() == 0): the result buffers
@@ -670,6 +676,12 @@ class BatchTracker:
         return out
 
     _drop_pending = Tracker._drop_pending
+
+    def tracks_in_flight(self) -> int:
+        """Enqueued batched tracks (each of all streams) whose results are not filled yet."""
+        n = self._lib.dpt_batch_tracks_in_flight(self._h)
+        _check(min(n, 0))
+        return n
 
     def set_pose_history(self, s: int, T_older, T_newer):
         _check(self._lib.dpt_batch_set_pose_history(self._h, s, _mat(T_older), _mat(T_newer)))

@@ -143,6 +143,48 @@ def test_batch_window_equals_frame_by_frame(gpu_lib):
     assert all(r["status"] in (0, 1) for x in rb for r in x)
 
 
+def test_batch_window_regroup_with_tracks_in_flight(gpu_lib):
+    """A batched reference update that changes the map sizes (and so the launch
+    groups) while a window track is still in flight: the next window enqueue
+    must first finish and fill the results in flight, then regroup.  The
+    results equal those of the same sequence synchronised after each window."""
+    import torch
+
+    dpt = gpu_lib
+    cams = [synth.CAM_640, synth.CAM_752, synth.CAM_640]
+    sizes = ([1800, 700, 2000], [600, 2000, 1100])  # chunk counts change for every stream
+    seqs = [[_sequence(60 + 10 * w + s, cams[s], 5) for s in range(3)] for w in range(2)]
+    prm = dpt.make_params(levels=4)
+    dev = [[torch.from_numpy(q["frames"]).cuda() for q in seqs[w]] for w in range(2)]
+    depth = [[torch.from_numpy(q["depth"]).cuda() for q in seqs[w]] for w in range(2)]
+    out = {}
+    for mode in ("in_flight", "synchronised"):
+        bt = dpt.BatchTracker(cams, prm, [2000] * 3)
+        res = []
+        for w in range(2):
+            bt.build_pyramids(dpt.SLOT_REF, [q["img0"] for q in seqs[w]])
+            bt.set_reference_from_depth_all(sizes[w], depth[w], np.stack([q["T0"] for q in seqs[w]]))
+            bt.set_pose_history_all(np.stack([q["T_prev"] for q in seqs[w]]), np.stack([q["T0"] for q in seqs[w]]))
+            bt.track_window_enqueue(dev[w])
+            if mode == "synchronised":
+                res += bt.synchronize()
+        if mode == "in_flight":
+            assert bt.tracks_in_flight() == 10
+            res += bt.collect(3)
+            res += bt.synchronize()
+        out[mode] = res
+        bt.close()
+    assert len(out["in_flight"]) == len(out["synchronised"]) == 10
+    for j in range(10):
+        _assert_same(out["in_flight"][j], out["synchronised"][j])
+    for w in range(2):
+        for f in range(5):
+            for s in range(3):
+                r = out["in_flight"][5 * w + f][s]
+                assert r["status"] in (0, 1)
+                assert oracle.pose_error(r["T_cw"], seqs[w][s]["gts"][f])[0] < 2e-3
+
+
 def test_window_errors(gpu_lib):
     import torch
 
