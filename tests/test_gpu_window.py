@@ -169,7 +169,8 @@ def test_batch_window_regroup_with_tracks_in_flight(gpu_lib):
             if mode == "synchronised":
                 res += bt.synchronize()
         if mode == "in_flight":
-            assert bt.tracks_in_flight() == 10
+            # the second enqueue regrouped: it first filled the first window's results
+            assert bt.tracks_in_flight() == 5
             res += bt.collect(3)
             res += bt.synchronize()
         out[mode] = res
