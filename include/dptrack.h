@@ -143,6 +143,24 @@ int dpt_get_pyramid_f32(dpt_ctx* ctx, int32_t slot, int32_t level, float* host_d
  * order to host_idx (capacity n) and their count to *n_out. */
 int dpt_select_points(dpt_ctx* ctx, int32_t n, int32_t margin, int32_t* host_idx, int32_t* n_out);
 
+/* For callers that cannot allocate memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): the selection of
+ * dpt_select_points on a device image the caller passes, needing no context
+ * and allocating nothing.  Its histograms, completion counter and per-chunk
+ * counts live in a static device array of the library (about 36 KB per GPU,
+ * held until the process ends) instead of context memory; the call only
+ * enqueues kernels on hip_stream (a kernel clears the array first) and never
+ * waits.  img: device uint8 image width x height, rows `pitch` bytes apart
+ * (width <= pitch < 2^31); idx: device int32[n], receives min(n, candidates)
+ * indices y*width+x in ascending order; count: device int32, receives their
+ * number.  The outputs are complete once the stream has run the call.
+ * width * height <= 4096 * 4096 (DPT_E_ARG beyond, before any device work);
+ * n and margin as in dpt_select_points.  All calls on one GPU share the array:
+ * calls that overlap on one GPU (two streams, two threads) race and may return
+ * wrong selections; serialise them. */
+int dpt_select_points_noalloc(const uint8_t* img, int32_t width, int32_t height, int64_t pitch, int32_t n,
+                              int32_t margin, int32_t* idx, int32_t* count, void* hip_stream);
+
 /* Set the reference map and run the IC precompute on the REF pyramid (Sec.
  * IV-C "Precompute Inverse Compositional", Eq.(6)): for each level and point,
  * x0 = T_rw P, the patch intensities I0 and reference-side gradients are cached;

@@ -99,6 +99,7 @@ SIGNATURES = {
     "dpt_tween_anchor": (ctypes.c_int, [_vp, _vp, _i64, _i32, _vp, _i64, _i32, ctypes.POINTER(ctypes.c_double)]),
     "dpt_tween_frame": (ctypes.c_int, [_vp, _vp, _i64, _i32, ctypes.POINTER(TweenResult)]),
     "dpt_select_points": (ctypes.c_int, [_vp, _i32, _i32, _vp, ctypes.POINTER(_i32)]),
+    "dpt_select_points_noalloc": (ctypes.c_int, [_vp, _i32, _i32, _i64, _i32, _i32, _vp, _vp, _vp]),
     "dpt_set_reference_points": (ctypes.c_int, [_vp, _vp, _i32, ctypes.POINTER(ctypes.c_double), _i32]),
     "dpt_set_reference_from_depth": (ctypes.c_int, [_vp, _i32, _i32, _vp, _i64, _i32,
                                                     ctypes.POINTER(ctypes.c_double)]),
@@ -267,6 +268,22 @@ def current_stream() -> int:
     import torch
 
     return int(torch.cuda.current_stream().cuda_stream) if torch.cuda.is_available() else 0
+
+
+def select_points_noalloc(img, n: int, margin: int, idx, count, stream: int | None = None):
+    """dpt_select_points_noalloc: top-n gradient-score pixels of a uint8 CUDA
+    tensor img (H x W, rows at any stride) into the int32 CUDA tensors idx (>= n
+    entries) and count (>= 1 entry), enqueued on `stream` (torch's current one
+    by default); allocates nothing and does not wait."""
+    lib = load()
+    if not (img.is_cuda and idx.is_cuda and count.is_cuda):
+        raise ValueError("img, idx and count must be CUDA tensors")
+    if img.dim() != 2 or img.stride(1) != 1 or idx.numel() < n or count.numel() < 1:
+        raise ValueError("img must be H x W with unit column stride; idx needs n entries, count one")
+    H, W = int(img.shape[0]), int(img.shape[1])
+    s = current_stream() if stream is None else stream
+    _check(lib.dpt_select_points_noalloc(img.data_ptr(), W, H, int(img.stride(0)), n, margin, idx.data_ptr(),
+                                         count.data_ptr(), s))
 
 
 class Tracker:

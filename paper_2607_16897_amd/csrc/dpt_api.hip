@@ -3,6 +3,7 @@
 // arguments and turns HIP failures into negative return codes with a message.
 #include <cmath>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <chrono>
 #include <cstring>
@@ -17,15 +18,20 @@ using namespace dpt;
 
 namespace {
 
-thread_local std::string g_err;
+// The calling thread's last error message, in a fixed buffer: recording an
+// error allocates nothing.
+struct ErrMsg {
+  char text[512] = {0};
+  void clear() { text[0] = 0; }
+  const char* c_str() const { return text; }
+};
+thread_local ErrMsg g_err;
 
 int fail(int code, const char* fmt, ...) {
-  char buf[512];
   va_list ap;
   va_start(ap, fmt);
-  vsnprintf(buf, sizeof buf, fmt, ap);
+  vsnprintf(g_err.text, sizeof g_err.text, fmt, ap);
   va_end(ap);
-  g_err = buf;
   return code;
 }
 
@@ -118,7 +124,7 @@ Pattern make_pattern(const dpt_params* p) {
 }  // namespace
 
 int dpt::set_error(int code, const char* msg) {
-  g_err = msg;
+  snprintf(g_err.text, sizeof g_err.text, "%s", msg);
   return code;
 }
 
@@ -531,6 +537,22 @@ int dpt_get_pyramid_f32(dpt_ctx* c, int32_t slot, int32_t level, float* host_dst
   HIP_TRY(hipMemcpyAsync(host_dst, c->pyrf[slot] + g.off, (size_t)g.W * g.H * sizeof(float), hipMemcpyDeviceToHost,
                          c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
+  return DPT_OK;
+}
+
+int dpt_select_points_noalloc(const uint8_t* img, int32_t width, int32_t height, int64_t pitch, int32_t n,
+                              int32_t margin, int32_t* idx, int32_t* count, void* hip_stream) {
+  g_err.clear();
+  if (!img || !idx || !count) return fail(DPT_E_ARG, "NULL argument");
+  if (width < 3 || height < 3) return fail(DPT_E_ARG, "image %dx%d", width, height);
+  if ((int64_t)width * height > kNoAllocSelectPixels)
+    return fail(DPT_E_ARG, "image %dx%d exceeds the %lld pixels of the static scratch", width, height,
+                (long long)kNoAllocSelectPixels);
+  if (pitch < width || pitch > INT32_MAX) return fail(DPT_E_ARG, "pitch %lld", (long long)pitch);
+  if (n < 1 || (int64_t)n > (int64_t)width * height) return fail(DPT_E_ARG, "n %d", n);
+  if (margin < 1 || 2 * margin >= width || 2 * margin >= height) return fail(DPT_E_ARG, "margin %d", margin);
+  HIP_TRY(launch_select_noalloc(img, width, height, pitch, margin, n, idx, count,
+                                static_cast<hipStream_t>(hip_stream)));
   return DPT_OK;
 }
 

@@ -124,6 +124,7 @@ struct SelGeom {
   const uint8_t* img;
   int32_t W, m, Wc, C, n;
   float inv_wc;  // 1 / Wc, for the candidate's row
+  int32_t pitch, pad;  // bytes between image rows (>= W)
 };
 
 // One image's selection: geometry, its scratch (select_scratch_ints ints), the
@@ -279,6 +280,11 @@ SelJob make_sel_job(const uint8_t* img, int32_t W, int32_t H, int32_t margin, in
 // G_max = the largest chunk count among them, any_empty: one has none.  The
 // scratch of every image must start zeroed (a fresh one: hipMemset).
 hipError_t launch_select_batch(const SelJob* d_jobs, int n_img, int G_max, bool any_empty, hipStream_t s);
+// The selection of one device image with its scratch in the library's static
+// device array (nothing allocated): images of at most kNoAllocSelectPixels.
+constexpr int64_t kNoAllocSelectPixels = 4096 * 4096;
+hipError_t launch_select_noalloc(const uint8_t* img, int32_t W, int32_t H, int64_t pitch, int32_t margin, int32_t n,
+                                 int32_t* idx, int32_t* count, hipStream_t s);
 hipError_t launch_precompute(const PrecomputeArgs& a, hipStream_t s);
 hipError_t launch_backproject(const BackprojectArgs& a, hipStream_t s);
 // Batched forms: one launch over n references / maps (argument arrays in device memory).

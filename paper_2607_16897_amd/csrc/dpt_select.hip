@@ -14,7 +14,9 @@
 //   D  every workgroup scans the chunk counts before it for its output offset
 //      and tie base, then writes its selected indices with a block-wide prefix
 //      sum; the last chunk writes the count
+#include <cstdint>
 #include <cstring>
+#include <mutex>
 
 #include "dpt_device.h"
 
@@ -31,10 +33,10 @@ int64_t select_scratch_ints(int32_t W, int32_t H) {
   return SelScratch::kChunks + 2 * G;
 }
 
-__device__ __forceinline__ int sel_score(const uint8_t* img, int W, int x, int y) {
-  const uint8_t* p = img + y * W + x;
+__device__ __forceinline__ int sel_score(const uint8_t* img, int pitch, int x, int y) {
+  const uint8_t* p = img + (int64_t)y * pitch + x;
   const int dx = (int)p[1] - (int)p[-1];
-  const int dy = (int)p[W] - (int)p[-W];
+  const int dy = (int)p[pitch] - (int)p[-pitch];
   return dx * dx + dy * dy;
 }
 
@@ -58,7 +60,7 @@ __device__ __forceinline__ void cand_xy(const SelGeom& g, int c, int* x, int* y)
 __device__ __forceinline__ int cand_score(const SelGeom& g, int c) {
   int x, y;
   cand_xy(g, c, &x, &y);
-  return sel_score(g.img, g.W, g.m + x, g.m + y);
+  return sel_score(g.img, g.pitch, g.m + x, g.m + y);
 }
 
 // The selection of one image (`one`), or of image blockIdx.y of a batch (`many`
@@ -325,6 +327,8 @@ SelJob make_sel_job(const uint8_t* img, int32_t W, int32_t H, int32_t margin, in
   j.g.C = (j.g.Wc > 0 && Hc > 0) ? j.g.Wc * Hc : 0;
   j.g.n = n;
   j.g.inv_wc = j.g.Wc > 0 ? 1.0f / (float)j.g.Wc : 0.0f;
+  j.g.pitch = W;
+  j.g.pad = 0;
   j.sc = scratch;
   j.idx = idx;
   j.count = count;
@@ -360,6 +364,54 @@ hipError_t launch_select_batch(const SelJob* d_jobs, int n_img, int G_max, bool 
   SelJob none;
   std::memset(&none, 0, sizeof none);
   return run_select(none, d_jobs, n_img, G_max, any_empty, s);
+}
+
+// ---------------------------------------------------------------- selection without allocation
+
+// Histograms, completion counter and per-chunk counts of one selection of an
+// image of up to kNoAllocSelectPixels pixels, for callers that cannot allocate.
+// Every device holds its own copy for the life of the process; all calls on a
+// device share it (calls that overlap on one device race).
+constexpr int64_t kNoAllocSelectInts = SelScratch::kChunks + 2 * ((kNoAllocSelectPixels + kSelChunk - 1) / kSelChunk + 1);
+static __device__ __align__(256) int32_t g_select_scratch[kNoAllocSelectInts];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int32_t* g_scratch_ptr[kMaxDevices] = {};  // device address of g_select_scratch, per device
+
+// The device address of the current device's copy of g_select_scratch, looked
+// up once per device (the array's name in host code is not that address).
+hipError_t select_scratch_ptr(int32_t** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(g_select_scratch))) != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<int32_t*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+}  // namespace
+
+hipError_t launch_select_noalloc(const uint8_t* img, int32_t W, int32_t H, int64_t pitch, int32_t margin, int32_t n,
+                                 int32_t* idx, int32_t* count, hipStream_t s) {
+  if ((int64_t)W * H > kNoAllocSelectPixels || pitch < W || pitch > INT32_MAX) return hipErrorInvalidValue;
+  int32_t* sc = nullptr;
+  hipError_t e = select_scratch_ptr(&sc);
+  if (e != hipSuccess) return e;
+  SelJob j = make_sel_job(img, W, H, margin, n, idx, count, sc);
+  j.g.pitch = (int32_t)pitch;
+  // the histograms and the completion counter start at zero: cleared by a
+  // kernel (no memset node, so the call can also be captured into a graph);
+  // sel_clear also writes the count of an image without candidates
+  hipLaunchKernelGGL(sel_clear, dim3(1, 1), dim3(kSelThreads), 0, s, j, nullptr);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return run_select(j, nullptr, 1, j.G, false, s);
 }
 
 }  // namespace dpt
