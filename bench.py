@@ -755,6 +755,74 @@ def calibrate_copy(mib: int):
     print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 3}))
 
 
+def decode_place(v: int) -> dict:
+    """XCC id << 32 | HW_ID of gfx9: wave [3:0], SIMD [5:4], CU [11:8], SH [12], SE [15:13]."""
+    hw = v & 0xFFFFFFFF
+    return {"xcc": v >> 32, "se": (hw >> 13) & 7, "sh": (hw >> 12) & 1, "cu": (hw >> 8) & 15, "simd": (hw >> 4) & 3}
+
+
+def cycle_split(args, legs):
+    """Per-phase cycle split of the headline track (and, with the batched leg
+    named, of the 64-stream window batch) from the instrumented library: mean
+    cycles per Gauss-Newton iteration of thread 0 of each workgroup, over every
+    launch of `steps` keyframe windows, and where each workgroup ran.  Prints one
+    JSON line; the timings of an instrumented build are not the headline's."""
+    os.environ.setdefault("DPT_LIBRARY", os.path.join(ROOT, "paper_2607_16897_amd", "libdptrack_cycles.so"))
+    import torch
+
+    import paper_2607_16897_amd as dpt
+    import synth
+
+    global CAM
+    CAM = synth.CAM_752
+    dpt.load()
+    torch.cuda.set_device(0)
+    wins = make_windows(min(args.steps + args.warmup, 24))
+    dev = to_device(wins)
+    out = {"library": os.path.basename(dpt.LIB_PATH), "workload": "headline: 752x480, 2000 points, 4 levels, "
+           f"{'window' if args.mode == 'window' else 'frame-by-frame'} tracks of {args.steps} keyframe windows"}
+
+    def summarise(rows, n_slots):
+        used = rows[rows[:, 5] > 0]
+        it = used[:, 4].astype(np.float64)
+        per = {f: float(np.mean(used[:, k] / np.maximum(it, 1))) for k, f in enumerate(dpt.CYCLE_FIELDS[:4])}
+        per["total"] = float(sum(per.values()))
+        clock_mhz = float(np.mean(used[:, 6] / np.maximum(used[:, 7], 1)) * 100.0)
+        places = [decode_place(int(v)) for v in used[:, 8]]
+        cus = {(p["xcc"], p["se"], p["sh"], p["cu"]) for p in places}
+        return {"cycles_per_iteration": per, "per_slot": {f: [round(float(x), 1) for x in used[:, k] / np.maximum(it, 1)]
+                                                          for k, f in enumerate(dpt.CYCLE_FIELDS[:4])},
+                "us_per_iteration_at_shader_clock": per["total"] / clock_mhz if clock_mhz > 0 else None,
+                "shader_clock_mhz": round(clock_mhz, 1), "workgroups": int(len(used)),
+                "distinct_cus": len(cus), "xccs": sorted({p["xcc"] for p in places}), "places": places[:64]}
+
+    launch = {"auto": dpt.LAUNCH_AUTO, "coop": dpt.LAUNCH_COOP}[args.launch]
+    prm = dpt.make_params(levels=LEVELS, max_iters=10, huber_k=9.0, step_eps=1e-5)
+    dpt_slots = 1024
+    dpt.cycle_profile(dpt_slots, reset=True)
+    timed_plain(dpt, synth, wins, dev, args.steps, args.warmup, prm, launch, args.chunk, window=args.mode == "window")
+    out["headline"] = summarise(dpt.cycle_profile(dpt_slots, reset=True), dpt_slots)
+    if "batched" in legs:
+        cams = [CAM] * args.batch_streams
+        bt = dpt.BatchTracker(cams, prm, [N_POINTS] * args.batch_streams)
+        bt.set_launch_config(dpt.LAUNCH_COOP, args.chunk)
+        for w in range(args.steps):
+            win = wins[w % len(wins)]
+            stack = dev[w % len(wins)][2]
+            bt.build_pyramids(dpt.SLOT_REF, stack[0:1].expand(args.batch_streams, -1, -1).contiguous())
+            depth = dev[w % len(wins)][1].unsqueeze(0).expand(args.batch_streams, -1, -1).contiguous()
+            bt.set_reference_from_depth_all(N_POINTS, depth, np.stack([win["gts"][0]] * args.batch_streams))
+            bt.set_pose_history_all(np.stack([win["T_prev"]] * args.batch_streams),
+                                    np.stack([win["gts"][0]] * args.batch_streams))
+            bt.track_window_enqueue(stack[1:].unsqueeze(0).expand(args.batch_streams, -1, -1, -1).contiguous())
+            bt.synchronize()
+        bt.close()
+        out["batched_64_window"] = summarise(dpt.cycle_profile(dpt_slots, reset=True), dpt_slots)
+        for k in ("per_slot", "places"):
+            out["batched_64_window"].pop(k)
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -775,6 +843,10 @@ def main():
                     help="legs after the headline: any of mixed, fixed, paper, tween, batched, init (comma separated)")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="write the track kernel's HBM traffic per launch from rocprofv3 --pmc output and exit")
+    ap.add_argument("--cycle-split", action="store_true",
+                    help="per-phase cycles per Gauss-Newton iteration from the instrumented library "
+                         "(libdptrack_cycles.so) on the headline workload (and the batch with --legs batched); "
+                         "prints that instead of the benchmark line")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -788,6 +860,9 @@ def main():
         pmc_summary(*args.pmc_summary)
         return
     legs = set() if args.only_headline else set(x for x in args.legs.split(",") if x)
+    if args.cycle_split:
+        cycle_split(args, legs)
+        return
 
     import torch
 

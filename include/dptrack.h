@@ -395,6 +395,32 @@ int dpt_set_launch_config(dpt_ctx* ctx, int32_t mode, int32_t chunk);
 #define DPT_DEFAULT_SPIN_LIMIT 4194304
 int dpt_set_spin_limit(dpt_ctx* ctx, int32_t polls);
 
+/* Cycle split of the cooperative track kernels, for performance work: only a
+ * library compiled with -DDPT_CYCLE_PROFILE (paper_2607_16897_amd/build.py
+ * --cycles, libdptrack_cycles.so) records it; every other build returns
+ * DPT_E_STATE.  For each of the first n_slots workgroup slots of the launch
+ * grids, DPT_CYCLE_FIELDS int64 values summed over every launch since the last
+ * reset, as seen by thread 0 of the workgroup (shader-clock cycles):
+ *   DPT_CYCLE_ACCUMULATE  its own point's residuals and normal-equation terms
+ *   DPT_CYCLE_REDUCE      the wave reduction up to the workgroup barrier (waits
+ *                         there for the workgroup's slowest wave)
+ *   DPT_CYCLE_EXCHANGE    the cross-chunk exchange until the stream totals
+ *   DPT_CYCLE_SOLVE       the 6x6 solve and pose update
+ *   DPT_CYCLE_ITERATIONS  Gauss-Newton iterations and DPT_CYCLE_LAUNCHES launches
+ *   DPT_CYCLE_KERNEL      cycles from the workgroup's start to its end
+ *   DPT_CYCLE_REALTIME    the same span in ticks of the 100 MHz constant clock
+ *   DPT_CYCLE_PLACE       where the slot's last workgroup ran: XCC id << 32 |
+ *                         the HW_ID register (CU, SIMD, shader engine)
+ * out: n_slots * DPT_CYCLE_FIELDS int64, slot-major.  reset != 0 clears the
+ * sums after reading.  Waits for the device.  1 <= n_slots <= 1024. */
+#define DPT_CYCLE_FIELDS 10
+enum {
+  DPT_CYCLE_ACCUMULATE = 0, DPT_CYCLE_REDUCE = 1, DPT_CYCLE_EXCHANGE = 2, DPT_CYCLE_SOLVE = 3,
+  DPT_CYCLE_ITERATIONS = 4, DPT_CYCLE_LAUNCHES = 5, DPT_CYCLE_KERNEL = 6, DPT_CYCLE_REALTIME = 7,
+  DPT_CYCLE_PLACE = 8
+};
+int dpt_cycle_profile(int64_t* out, int32_t n_slots, int32_t reset);
+
 /* Profiling hook: with enable = N > 0, every N-th pyramid build and every
  * N-th track brackets its kernel with HIP events on the context's stream
  * (each event record is a queue marker of a few microseconds, so N > 1 keeps

@@ -122,6 +122,7 @@ SIGNATURES = {
     "dpt_get_fixed_hessian": (ctypes.c_int, [_vp, _i32, _vp, ctypes.POINTER(_i32)]),
     "dpt_set_profiling": (ctypes.c_int, [_vp, _i32]),
     "dpt_set_launch_config": (ctypes.c_int, [_vp, _i32, _i32]),
+    "dpt_cycle_profile": (ctypes.c_int, [_vp, _i32, _i32]),
     "dpt_set_spin_limit": (ctypes.c_int, [_vp, _i32]),
     "dpt_batch_create": (ctypes.c_int, [_i32, _vp, ctypes.POINTER(Params), _vp, _vp, ctypes.POINTER(_vp)]),
     "dpt_batch_destroy": (None, [_vp]),
@@ -192,10 +193,6 @@ _live = weakref.WeakSet()
 def _close_live():
     for obj in list(_live):
         obj.close()
-
-
-def _finalising() -> bool:
-    return sys.is_finalizing()
 
 
 def _check(code: int):
@@ -270,6 +267,18 @@ def current_stream() -> int:
     return int(torch.cuda.current_stream().cuda_stream) if torch.cuda.is_available() else 0
 
 
+CYCLE_FIELDS = ("accumulate", "reduce", "exchange", "solve", "iterations", "launches", "kernel", "realtime", "place")
+
+
+def cycle_profile(n_slots: int, reset: bool = True) -> np.ndarray:
+    """Per-slot cycle split of the cooperative track (dpt_cycle_profile): an
+    int64 array (n_slots, 10) with columns CYCLE_FIELDS (+1 spare).  Needs the
+    instrumented library (DPT_LIBRARY=.../libdptrack_cycles.so)."""
+    out = np.zeros((n_slots, 10), np.int64)
+    _check(load().dpt_cycle_profile(out.ctypes.data, n_slots, int(bool(reset))))
+    return out
+
+
 def select_points_noalloc(img, n: int, margin: int, idx, count, stream: int | None = None):
     """dpt_select_points_noalloc: top-n gradient-score pixels of a uint8 CUDA
     tensor img (H x W, rows at any stride) into the int32 CUDA tensors idx (>= n
@@ -310,7 +319,7 @@ class Tracker:
             self._pending, self._frames_keep = [], []
         _live.discard(self)
 
-    def __del__(self):
+    def __del__(self, _finalising=sys.is_finalizing):  # bound now: module globals are gone at shutdown
         if not _finalising():
             self.close()
 
@@ -553,7 +562,7 @@ class BatchTracker:
             self._pending, self._frames_keep = [], []
         _live.discard(self)
 
-    def __del__(self):
+    def __del__(self, _finalising=sys.is_finalizing):  # bound now: module globals are gone at shutdown
         if not _finalising():
             self.close()
 
@@ -802,7 +811,7 @@ class Cnn:
             self._h = None
         _live.discard(self)
 
-    def __del__(self):
+    def __del__(self, _finalising=sys.is_finalizing):  # bound now: module globals are gone at shutdown
         if not _finalising():
             self.close()
 

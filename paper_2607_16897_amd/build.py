@@ -1,6 +1,7 @@
 """Build step: compile the HIP sources for gfx950 into libdptrack.so (in-tree)."""
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import subprocess
 import sys
@@ -18,25 +19,36 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
+LIB_CYCLES = os.path.join(HERE, "libdptrack_cycles.so")
+
+
+def build(verbose: bool = False, cycles: bool = False) -> str:
+    """cycles=True: the instrumented library (libdptrack_cycles.so, -DDPT_CYCLE_PROFILE)
+    whose track kernels record the per-phase cycle split (dpt_cycle_profile)."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    objs = []
+    lib = LIB_CYCLES if cycles else LIB
+    tag = ".cyc" if cycles else ""
+    objs, cmds = [], []
     for src in SOURCES:
-        obj = os.path.join(CSRC, src.replace(".hip", ".o"))
-        cmd = [hipcc, *HIPCC_FLAGS, "-I", os.path.join(os.path.dirname(HERE), "include"), "-c",
-               os.path.join(CSRC, src), "-o", obj]
+        obj = os.path.join(CSRC, src.replace(".hip", f"{tag}.o"))
+        cmd = [hipcc, *HIPCC_FLAGS, *(["-DDPT_CYCLE_PROFILE"] if cycles else []),
+               "-I", os.path.join(os.path.dirname(HERE), "include"), "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
+        cmds.append(cmd)
         objs.append(obj)
-    tmp = LIB + ".tmp"
+    # the sources compile independently: a few at a time
+    with concurrent.futures.ThreadPoolExecutor(max_workers=min(len(cmds), os.cpu_count() or 1, 8)) as ex:
+        for _ in ex.map(subprocess.check_call, cmds):
+            pass
+    tmp = lib + ".tmp"
     cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     for o in objs:
         os.remove(o)
-    return LIB
+    return lib
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, cycles="--cycles" in sys.argv))

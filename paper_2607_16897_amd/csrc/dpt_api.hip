@@ -1174,6 +1174,15 @@ int dpt_track_window_enqueue(dpt_ctx* c, const uint8_t* frames, int64_t pitch, i
   return DPT_OK;
 }
 
+int dpt_cycle_profile(int64_t* out, int32_t n_slots, int32_t reset) {
+  g_err.clear();
+  if (!out) return fail(DPT_E_ARG, "NULL argument");
+  if (n_slots < 1 || n_slots > kCycleSlots) return fail(DPT_E_ARG, "n_slots %d", n_slots);
+  if (!kCycleProfile) return fail(DPT_E_STATE, "library built without DPT_CYCLE_PROFILE");
+  HIP_TRY(read_cycle_profile(reinterpret_cast<uint64_t*>(out), n_slots, reset != 0));
+  return DPT_OK;
+}
+
 int dpt_set_spin_limit(dpt_ctx* c, int32_t polls) {
   g_err.clear();
   if (!c) return fail(DPT_E_ARG, "NULL context");

@@ -14,6 +14,7 @@
 // suffices and the result is reproducible.  Waits are bounded: a chunk that
 // polls longer than `spin_limit` times gives up and reports a timeout instead
 // of hanging.
+#include <climits>
 #include <cstring>
 #include <type_traits>
 
@@ -158,7 +159,7 @@ __device__ __forceinline__ bool exchange_wide(const uint64_t* partials, int nch,
 template <bool KAHAN, int NV, bool WIDE>
 __device__ __forceinline__ bool stream_total(float (&acc)[NV], float* sh_red, float* sh_tot, int* sh_ok,
                                              uint64_t* partials, int chunk, int nch, uint32_t tag,
-                                             int spin_limit, float* sh_grp) {
+                                             int spin_limit, float* sh_grp, uint64_t* t_bar = nullptr) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   constexpr int PER_ROW = NV / 4;  // values per 16-lane row after the wave reduction
   if constexpr (NV == 32)
@@ -170,6 +171,7 @@ __device__ __forceinline__ bool stream_total(float (&acc)[NV], float* sh_red, fl
     for (int j = 0; j < PER_ROW; ++j) sh_red[wave * NV + PER_ROW * (lane >> 4) + j] = acc[j];
   }
   __syncthreads();
+  if (kCycleProfile && t_bar) *t_bar = clock64();
   if (wave == 0) {
     float s = 0.0f, comp = 0.0f;
     if (lane < NV) {
@@ -263,6 +265,143 @@ __device__ __forceinline__ void start_pose(const StartSlot* __restrict__ st, con
   if (sh_mode == kStartConstVelocity) const_velocity_start(T0, rw, h0, h1, m1, m2);
 }
 
+// ---------------------------------------------------------------- cycle split (DPT_CYCLE_PROFILE builds)
+
+#ifdef DPT_CYCLE_PROFILE
+constexpr int kCycFields = DPT_CYCLE_FIELDS;
+__device__ uint64_t g_cycles[kCycleSlots * kCycFields];
+#endif
+
+// Where this workgroup runs: XCC id << 32 | HW_ID (CU, SIMD, shader engine).
+__device__ __forceinline__ uint64_t hw_place() {
+#ifdef DPT_CYCLE_PROFILE
+  uint32_t xcc, hw;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_HW_ID)" : "=s"(hw));
+  return ((uint64_t)xcc << 32) | hw;
+#else
+  return 0;
+#endif
+}
+
+// Thread 0's phase sums of one launch into the slot's totals.
+__device__ __forceinline__ void cycles_flush(const uint64_t (&cy)[4], uint64_t iters, uint64_t t_start,
+                                             uint64_t rt_start) {
+#ifdef DPT_CYCLE_PROFILE
+  if (threadIdx.x != 0 || blockIdx.x >= (unsigned)kCycleSlots) return;
+  uint64_t* o = g_cycles + (size_t)blockIdx.x * kCycFields;
+  for (int k = 0; k < 4; ++k) atomicAdd((unsigned long long*)&o[k], (unsigned long long)cy[k]);
+  atomicAdd((unsigned long long*)&o[DPT_CYCLE_ITERATIONS], (unsigned long long)iters);
+  atomicAdd((unsigned long long*)&o[DPT_CYCLE_LAUNCHES], 1ull);
+  atomicAdd((unsigned long long*)&o[DPT_CYCLE_KERNEL], (unsigned long long)(clock64() - t_start));
+  atomicAdd((unsigned long long*)&o[DPT_CYCLE_REALTIME], (unsigned long long)(wall_clock64() - rt_start));
+  o[DPT_CYCLE_PLACE] = hw_place();
+#else
+  (void)cy, (void)iters, (void)t_start, (void)rt_start;
+#endif
+}
+
+hipError_t read_cycle_profile(uint64_t* host, int n_slots, bool reset) {
+#ifdef DPT_CYCLE_PROFILE
+  if (n_slots < 1 || n_slots > kCycleSlots) return hipErrorInvalidValue;
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return e;
+  if ((e = hipMemcpyFromSymbol(host, HIP_SYMBOL(g_cycles), sizeof(uint64_t) * kCycFields * n_slots)) != hipSuccess)
+    return e;
+  if (reset) {
+    static uint64_t zeros[kCycleSlots * kCycFields] = {};
+    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(g_cycles), zeros, sizeof zeros)) != hipSuccess) return e;
+  }
+  return hipDeviceSynchronize();
+#else
+  (void)host, (void)n_slots, (void)reset;
+  return hipErrorNotSupported;
+#endif
+}
+
+// ---------------------------------------------------------------- LDS tiles of the current level
+
+// Bytes of a level a workgroup of the 8-pixel kernels stages in LDS: levels of
+// up to this size whole, larger ones as the band of rows its points' taps span.
+// Launches of many workgroups (two per compute unit, 160 KB of LDS each) take
+// the small tile: with the kernel's own ~2 KB a workgroup stays within 64 KB.
+// A launch small enough to run one workgroup per compute unit (the plain-launch
+// path) takes the large one, which holds a 752x480 frame's second level whole
+// and ~190 rows of its first.
+constexpr int kTileBytesSmall = 60 * 1024;
+constexpr int kTileBytesLarge = 144 * 1024;
+constexpr int kTilePad = 16;  // the last pair of words read past the last byte
+// Rows kept around the band at the level's start pose: the pose moves during the
+// level's iterations.  Points whose taps leave the band are read from global
+// memory (their whole wave).
+constexpr int kBandMargin = 4;
+
+// Stage level g of the current frame (img = its first byte) in the workgroup's
+// LDS tile: the whole level if it fits, else the rows the taps of the usable
+// points span at pose T, widened by kBandMargin and cut to the tile's size.
+// Copies the 16-byte granules that overlap those rows (each holds at least one
+// byte of them, so none crosses into a page the level does not touch).
+// Block-wide; the caller has finished every read of the previous tile.
+template <class PR>
+__device__ __forceinline__ Tile8 stage_tile(const TrackArgs& a, const PatRegs& pat, const LevelGeom& g,
+                                            const uint8_t* img, const float* T, const PR& pr, uint8_t* tile_mem,
+                                            int tile_bytes, int* sh_band) {
+  const int W = g.W, H = g.H;
+  const int rows_fit = (tile_bytes - 32) / W;
+  int lo = 0, hi = H - 1;
+  if (rows_fit < H) {
+    float X, Y, Z;
+    transform(T, pr.X0, pr.Y0, pr.Z0, X, Y, Z);
+    const float iz = __builtin_amdgcn_rcpf(Z);
+    const float u = fmaf(g.fx * X, iz, g.cx), v = fmaf(g.fy * Y, iz, g.cy);
+    const bool ok = pr.ok & (Z > a.z_min) & inside(g, pat, u, v);
+    const int iv = (int)floorf(ok ? v : 0.0f);
+    int rlo = ok ? iv + (int)pat.dy_min : INT_MAX, rhi = ok ? iv + (int)pat.dy_max + 1 : INT_MIN;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+      rlo = min(rlo, __shfl_xor(rlo, d, 64));
+      rhi = max(rhi, __shfl_xor(rhi, d, 64));
+    }
+    const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if ((threadIdx.x & 63) == 0) sh_band[2 * wave] = rlo, sh_band[2 * wave + 1] = rhi;
+    __syncthreads();
+    rlo = INT_MAX, rhi = INT_MIN;
+    for (int w = 0; w < nw; ++w) rlo = min(rlo, sh_band[2 * w]), rhi = max(rhi, sh_band[2 * w + 1]);
+    if (rlo <= rhi) {
+      lo = max(0, rlo - kBandMargin);
+      hi = min(H - 1, rhi + kBandMargin);
+    }
+    if (hi - lo + 1 > rows_fit) hi = lo + rows_fit - 1;  // the rows below are read from global memory
+  }
+  const uintptr_t sa = reinterpret_cast<uintptr_t>(img + (int64_t)lo * W), s0 = sa & ~(uintptr_t)15;
+  const int delta = (int)(sa - s0);
+  const int ng = (delta + (hi - lo + 1) * W + 15) >> 4;
+  // Global memory straight into LDS (global_load_lds_dwordx4): each wave moves
+  // 64 consecutive granules per instruction, every load in flight at once and
+  // no registers held; one wait for all of them.
+  const int lane = threadIdx.x & 63;
+  for (int q0 = (int)(threadIdx.x & ~63u); q0 < ng; q0 += blockDim.x) {
+    const int q = q0 + lane;
+    if (q < ng)
+      __builtin_amdgcn_global_load_lds(reinterpret_cast<const uint32_t*>(s0 + 16 * (uintptr_t)q),
+                                       (__attribute__((address_space(3))) void*)(tile_mem + 16 * q0), 16, 0, 0);
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  Tile8 t;
+  t.lds = (const __attribute__((address_space(3))) uint8_t*)(tile_mem);
+  t.lo = lo, t.hi = hi, t.delta = delta, t.bytes = ng * 16;
+  return t;
+}
+
+// A tile that holds no row: every usable point reads global memory.
+__device__ __forceinline__ Tile8 no_tile(uint8_t* tile_mem) {
+  Tile8 t;
+  t.lds = (const __attribute__((address_space(3))) uint8_t*)(tile_mem);
+  t.lo = 1, t.hi = 0, t.delta = 0, t.bytes = 16;
+  return t;
+}
+
 // MIXED: FP16 reference cache, Kahan-compensated FP32 sums across waves and
 // chunks, FP64 solve, exponential and pose state.
 // FIXED: fixed-H mode (FP32): unweighted residuals, only b, the cost and the
@@ -276,7 +415,7 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
                                                            const StartSlot* __restrict__ start,
                                                            TrackOut* __restrict__ out_ring, int slot, int n_out,
                                                            int n_frames, uint32_t seq0, uint32_t tag_base,
-                                                           int spin_limit) {
+                                                           int spin_limit, int tile_bytes) {
   static_assert(!(MIXED && FIXED), "the fixed-H mode computes in FP32");
   static_assert(!(MIXED && GENERIC) && (GENERIC || std::is_same<PIX, uint8_t>::value), "variant");
   using PR = typename std::conditional<GENERIC, PointGeo,
@@ -292,6 +431,8 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
   __shared__ float sh_red[(CH / 64) * 32];
   __shared__ float sh_grp[GENERIC ? CH : 1];  // the whole-workgroup exchange of many-chunk streams
   __shared__ int sh_ok;
+  __shared__ int sh_band[2 * (CH / 64)];
+  extern __shared__ __align__(16) uint8_t sh_tile[];  // tile_bytes + kTilePad for the 8-pixel kernels, else none
   __shared__ const uint8_t* sh_l0;
   __shared__ int64_t sh_l0_stride;
   const int2 w = work[blockIdx.x];
@@ -310,6 +451,8 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
   const int sub = GENERIC ? (int)threadIdx.x % kLanesPerPoint : 0;
   const int nf = WIN ? n_frames : 1;
   uint32_t tag = tag_base;
+  uint64_t cy[4] = {0, 0, 0, 0}, cy_iters = 0, cy_t0 = 0, cy_rt0 = 0;
+  if constexpr (kCycleProfile) cy_t0 = clock64(), cy_rt0 = wall_clock64();
   // WIN: the frames of the launch in order, each from the constant-velocity
   // prediction of the history the previous one extended.  Every chunk keeps its
   // own copy of the history in LDS: the poses are bitwise identical in all
@@ -340,10 +483,15 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
     for (int l = a.levels - 1; l >= 0 && !stop; --l) {
       const LevelGeom g = a.lv[l];
       const PIX* img = WIN && l == 0 ? cur0 : cur + g.off;
-      if constexpr (GENERIC)
+      Tile8 tile;
+      int offs[8];
+      if constexpr (GENERIC) {
         load_point_geo(a, l, i, pr);
-      else
+      } else {
         load_point(a, l, i, pr);
+        pattern_offsets(pregs, g.W, offs);
+        tile = stage_tile(a, pregs, g, reinterpret_cast<const uint8_t*>(img), T, pr, sh_tile, tile_bytes, sh_band);
+      }
       if constexpr (FIXED) {
         // read by every thread after the next exchange's barrier; the other
         // parity's copy may still be in use by a previous level's solve
@@ -354,20 +502,27 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
       }
       bool converged = false;
       for (int it = 0; it < a.max_iters; ++it) {
+        uint64_t c0 = 0, c1 = 0, c2 = 0;
+        if constexpr (kCycleProfile) c0 = clock64();
         float acc[NV];
 #pragma unroll
         for (int j = 0; j < NV; ++j) acc[j] = 0.f;
         if constexpr (GENERIC)
           accumulate_point_generic<false, PIX, NV>(a, a.pat, g, img, T, pr, sub, acc);
         else
-          accumulate_point<false, true, PR, NV>(a, pregs, g, img, T, pr, acc);
+          accumulate_point8<false, PR, NV>(a, pregs, offs, g, reinterpret_cast<const uint8_t*>(img), tile, T, pr,
+                                           acc);
+        if constexpr (kCycleProfile) c1 = clock64();
         if (!stream_total<MIXED, NV, GENERIC>(acc, sh_red, sh_tot, &sh_ok, ss.partials, chunk, nch, tag, spin_limit,
-                                              sh_grp)) {
+                                              sh_grp, &c2)) {
           timed_out = stop = true;
           break;
         }
+        uint64_t c3 = 0;
+        if constexpr (kCycleProfile) c3 = clock64();
         ++tag;
-        samples += (int64_t)sh_tot[sN];
+        // the 8-pixel kernels count samples as 8 per point outside the final pass
+        samples += GENERIC ? (int64_t)sh_tot[sN] : 8 * (int64_t)sh_tot[sP];
         if ((int)sh_tot[sP] < a.min_points) {
           status = 2;  // too few points
           stop = true;
@@ -390,6 +545,10 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
           float stepf;
           bad = solve_update(sh_tot, T, &stepf);
           step = stepf;
+        }
+        if constexpr (kCycleProfile) {
+          const uint64_t c4 = clock64();
+          cy[0] += c1 - c0, cy[1] += c2 - c1, cy[2] += c3 - c2, cy[3] += c4 - c3, ++cy_iters;
         }
         if (bad) {
           status = 3;  // not positive definite
@@ -416,7 +575,9 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
         accumulate_point_generic<true, PIX, NV>(a, a.pat, g, WIN ? cur0 : cur + g.off, T, pr, sub, acc);
       } else {
         load_point(a, 0, i, pr);
-        accumulate_point<true, true, PR, NV>(a, pregs, g, WIN ? cur0 : cur + g.off, T, pr, acc);
+        int offs[8];
+        pattern_offsets(pregs, g.W, offs);
+        accumulate_point8<true, PR, NV>(a, pregs, offs, g, WIN ? cur0 : cur + g.off, no_tile(sh_tile), T, pr, acc);
       }
       if (!stream_total<MIXED, NV, GENERIC>(acc, sh_red, sh_tot, &sh_ok, ss.partials, chunk, nch, tag, spin_limit,
                                             sh_grp))
@@ -449,6 +610,7 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
         __threadfence_system();  // the fields reach the host before the sequence number
         o->seq = seq0;
       }
+      if constexpr (kCycleProfile) cycles_flush(cy, cy_iters, cy_t0, cy_rt0);
       return;
     }
     if (threadIdx.x == 0) {
@@ -494,6 +656,7 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
     ss.hist[threadIdx.x] = sh_h0[threadIdx.x];
     ss.hist[12 + threadIdx.x] = sh_h1[threadIdx.x];
   }
+  if constexpr (kCycleProfile) cycles_flush(cy, cy_iters, cy_t0, cy_rt0);
 }
 
 // The kernel of a variant (kCoop* bits); WIN: the window form.  Null for a
@@ -532,7 +695,8 @@ static int coop_blocks_per_cu() {
       for (const void* f : {coop_fn<CH, false>(v), coop_fn<CH, true>(v)}) {
         if (!f) continue;
         int k = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&k, f, CH, 0) != hipSuccess) {
+        const size_t dyn = (v & kCoopGeneric) ? 0 : kTileBytesSmall + kTilePad;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&k, f, CH, dyn) != hipSuccess) {
           (void)hipGetLastError();
           k = 0;
         }
@@ -579,12 +743,27 @@ template <int CH>
 static hipError_t coop_launch_k(const CoopStream* d_streams, const int2* d_work, int n_work, const StartSlot* start,
                                 TrackOut* out_ring, int slot, int n_out, int n_frames, uint32_t seq0, uint32_t tag_base,
                                 int variant, int spin_limit, hipStream_t s) {
-  void* args[] = {(void*)&d_streams, (void*)&d_work,   (void*)&start, (void*)&out_ring, (void*)&slot,
-                  (void*)&n_out,     (void*)&n_frames, (void*)&seq0,  (void*)&tag_base, (void*)&spin_limit};
   const void* fn = n_frames > 0 ? coop_fn<CH, true>(variant) : coop_fn<CH, false>(variant);
   if (!fn) return hipErrorInvalidValue;
-  if (4 * n_work <= coop_max_blocks(CH)) return hipLaunchKernel(fn, dim3(n_work), dim3(CH), args, 0, s);
-  return hipLaunchCooperativeKernel(fn, dim3(n_work), dim3(CH), args, 0, s);
+  const bool plain = 4 * n_work <= coop_max_blocks(CH);
+  // the 8-pixel kernels' level tile: large where the launch is small enough for
+  // one workgroup per compute unit, else small (two per compute unit)
+  int tile_bytes = (variant & kCoopGeneric) ? 0 : plain ? kTileBytesLarge : kTileBytesSmall;
+  const size_t dyn = tile_bytes ? (size_t)tile_bytes + kTilePad : 0;
+  if (dyn > 64 * 1024) {
+    static bool raised[2][8] = {};  // per window form and variant: the attribute is set once
+    bool& r = raised[n_frames > 0][variant & 7];
+    if (!r) {
+      const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+      if (e != hipSuccess) return e;
+      r = true;
+    }
+  }
+  void* args[] = {(void*)&d_streams, (void*)&d_work,   (void*)&start,    (void*)&out_ring,   (void*)&slot,
+                  (void*)&n_out,     (void*)&n_frames, (void*)&seq0,     (void*)&tag_base,   (void*)&spin_limit,
+                  (void*)&tile_bytes};
+  if (plain) return hipLaunchKernel(fn, dim3(n_work), dim3(CH), args, dyn, s);
+  return hipLaunchCooperativeKernel(fn, dim3(n_work), dim3(CH), args, dyn, s);
 }
 
 hipError_t launch_coop_track(const CoopStream* d_streams, const int2* d_work, int n_work, const StartSlot* start,

@@ -15,10 +15,14 @@ __device__ __forceinline__ void transform(const float* T, float X, float Y, floa
   z = fmaf(T[8], X, fmaf(T[9], Y, fmaf(T[10], Z, T[11])));
 }
 
-// Eq.(1): pinhole projection at one pyramid level.
+// Eq.(1): pinhole projection at one pyramid level, through one reciprocal of
+// z (v_rcp_f32, 1 ulp).  Every sampling site (the precompute and every track
+// path) projects with this same arithmetic, so a pose equal to the reference's
+// reproduces the template's sample positions bit for bit.
 __device__ __forceinline__ void project(const LevelGeom& g, float x, float y, float z, float& u, float& v) {
-  u = fmaf(g.fx, x / z, g.cx);
-  v = fmaf(g.fy, y / z, g.cy);
+  const float iz = __builtin_amdgcn_rcpf(z);
+  u = fmaf(g.fx * x, iz, g.cx);
+  v = fmaf(g.fy * y, iz, g.cy);
 }
 
 // A point is usable when it is in front of the camera and every pattern
@@ -51,38 +55,60 @@ __device__ __forceinline__ bool inside(const LevelGeom& g, const PatRegs& p, flo
          (v + p.dy_max < (float)(g.H - 2));
 }
 
-// Bilinear intensity of a level (uint8 or float pixels), pixel centres at
-// integer coordinates.
-template <class PIX>
-__device__ __forceinline__ float bilinear(const PIX* img, int W, float x, float y) {
-  float fx = floorf(x), fy = floorf(y);
-  float a = x - fx, c = y - fy;
-  const PIX* p = img + (int)fy * W + (int)fx;
-  float p00 = p[0], p10 = p[1], p01 = p[W], p11 = p[W + 1];
-  float top = fmaf(a, p10 - p00, p00);
-  float bot = fmaf(a, p11 - p01, p01);
-  return fmaf(c, bot - top, top);
+// Bilinear sampling, pixel centres at integer coordinates.  A point projected
+// to (u, v) lies in the cell with corner (iu, iv) = floor(u, v) at fractions
+// (a, c); the pattern's offsets are whole pixels, so every sample of the point
+// is the cell at (iu + dx_k, iv + dy_k) with the same fractions and weights.
+// The weights are formed once per point, the same way at every sampling site.
+struct Bilin {
+  float w00, w10, w01, w11;
+};
+
+struct Cell {
+  int iu, iv;
+  Bilin w;
+};
+
+__device__ __forceinline__ Cell cell_of(float u, float v) {
+  Cell q;
+  const float fu = floorf(u), fv = floorf(v);
+  const float a = u - fu, c = v - fv;  // exact: u and floor(u) are close
+  q.iu = (int)fu, q.iv = (int)fv;
+  q.w.w11 = a * c;
+  q.w.w10 = a - q.w.w11;
+  q.w.w01 = c - q.w.w11;
+  q.w.w00 = (1.0f - a) - q.w.w01;
+  return q;
 }
 
-// Reference-side gradient: central differences / 2 at the four bilinear taps,
-// blended with the same bilinear weights.
+// (1-a)(1-c) t00 + a(1-c) t10 + (1-a)c t01 + ac t11.
+__device__ __forceinline__ float bilin_mix(const Bilin& w, float t00, float t10, float t01, float t11) {
+  return fmaf(w.w11, t11, fmaf(w.w01, t01, fmaf(w.w10, t10, w.w00 * t00)));
+}
+
+// Intensity of a level (uint8 or float pixels) in the cell with corner (x, y).
 template <class PIX>
-__device__ __forceinline__ void gradient(const PIX* img, int W, float x, float y, float& gx, float& gy) {
-  float fx = floorf(x), fy = floorf(y);
-  float a = x - fx, c = y - fy;
-  const PIX* p = img + (int)fy * W + (int)fx;
-  float gx00 = 0.5f * ((float)p[1] - (float)p[-1]);
-  float gx10 = 0.5f * ((float)p[2] - (float)p[0]);
-  float gx01 = 0.5f * ((float)p[W + 1] - (float)p[W - 1]);
-  float gx11 = 0.5f * ((float)p[W + 2] - (float)p[W]);
-  float gy00 = 0.5f * ((float)p[W] - (float)p[-W]);
-  float gy10 = 0.5f * ((float)p[W + 1] - (float)p[1 - W]);
-  float gy01 = 0.5f * ((float)p[2 * W] - (float)p[0]);
-  float gy11 = 0.5f * ((float)p[2 * W + 1] - (float)p[1]);
-  float tx = fmaf(a, gx10 - gx00, gx00), bx = fmaf(a, gx11 - gx01, gx01);
-  float ty = fmaf(a, gy10 - gy00, gy00), by = fmaf(a, gy11 - gy01, gy01);
-  gx = fmaf(c, bx - tx, tx);
-  gy = fmaf(c, by - ty, ty);
+__device__ __forceinline__ float sample_cell(const PIX* img, int W, int x, int y, const Bilin& w) {
+  const PIX* p = img + y * W + x;
+  return bilin_mix(w, (float)p[0], (float)p[1], (float)p[W], (float)p[W + 1]);
+}
+
+// Reference-side gradient in the same cell: central differences / 2 at its
+// four corners, blended with the same weights.
+template <class PIX>
+__device__ __forceinline__ void gradient_cell(const PIX* img, int W, int x, int y, const Bilin& w, float& gx,
+                                              float& gy) {
+  const PIX* p = img + y * W + x;
+  const float gx00 = 0.5f * ((float)p[1] - (float)p[-1]);
+  const float gx10 = 0.5f * ((float)p[2] - (float)p[0]);
+  const float gx01 = 0.5f * ((float)p[W + 1] - (float)p[W - 1]);
+  const float gx11 = 0.5f * ((float)p[W + 2] - (float)p[W]);
+  const float gy00 = 0.5f * ((float)p[W] - (float)p[-W]);
+  const float gy10 = 0.5f * ((float)p[W + 1] - (float)p[1 - W]);
+  const float gy01 = 0.5f * ((float)p[2 * W] - (float)p[0]);
+  const float gy11 = 0.5f * ((float)p[2 * W + 1] - (float)p[1]);
+  gx = bilin_mix(w, gx00, gx10, gx01, gx11);
+  gy = bilin_mix(w, gy00, gy10, gy01, gy11);
 }
 
 // ---------------------------------------------------------------- pyramid
@@ -690,15 +716,12 @@ __device__ __forceinline__ void accumulate_point(const TrackArgs& a, const PatRe
   v = ok ? v : 0.0f;
   // Phase 1: all 32 bilinear taps of the point are issued before any is used
   // (one memory round trip per point instead of one per sample).
-  float ta[8], tc[8], t00[8], t10[8], t01[8], t11[8];
+  const Cell q0 = cell_of(u, v);
+  float t00[8], t10[8], t01[8], t11[8];
   const int W = g.W;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    const float x = u + pat.dx[k], y = v + pat.dy[k];
-    const float fx = floorf(x), fy = floorf(y);
-    ta[k] = x - fx;
-    tc[k] = y - fy;
-    const int off = ((int)fy * W + (int)fx) & -(int)ok;  // masked, not branched
+    const int off = ((q0.iv + (int)pat.dy[k]) * W + q0.iu + (int)pat.dx[k]) & -(int)ok;  // masked, not branched
     if constexpr (GLOBAL_IMG) {
       const __attribute__((address_space(1))) uint8_t* p =
           (const __attribute__((address_space(1))) uint8_t*)img + off;
@@ -709,13 +732,11 @@ __device__ __forceinline__ void accumulate_point(const TrackArgs& a, const PatRe
     }
   }
   // Phase 2: residuals, Huber weights and the point's sums.  The interpolation
-  // repeats bilinear()'s arithmetic exactly.
+  // repeats the precompute's arithmetic exactly.
   float m00 = 0.f, m01 = 0.f, m11 = 0.f, v0 = 0.f, v1 = 0.f, E = 0.f;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    const float top = fmaf(ta[k], t10[k] - t00[k], t00[k]);
-    const float bot = fmaf(ta[k], t11[k] - t01[k], t01[k]);
-    const float Ic = fmaf(tc[k], bot - top, top);
+    const float Ic = bilin_mix(q0.w, t00[k], t10[k], t01[k], t11[k]);
     const float r = pr.i0(k) - Ic;
     const float ar = fabsf(r);
     const bool hub = (kH > 0.f) & (ar > kH);
@@ -745,6 +766,143 @@ __device__ __forceinline__ void accumulate_point(const TrackArgs& a, const PatRe
   const float iz = pr.iz, xp = pr.xp, yp = pr.yp;
   const float au[6] = {-g.fx * xp * yp, g.fx * fmaf(xp, xp, 1.0f), -g.fx * yp, g.fx * iz, 0.0f, -g.fx * xp * iz};
   const float av[6] = {-g.fy * fmaf(yp, yp, 1.0f), g.fy * xp * yp, g.fy * xp, 0.0f, g.fy * iz, -g.fy * yp * iz};
+  if constexpr (FIXED) {
+#pragma unroll
+    for (int r = 0; r < 6; ++r) acc[kFixB + r] -= fmaf(au[r], v0, av[r] * v1);
+  } else {
+    m00 = ok ? m00 : 0.0f, m01 = ok ? m01 : 0.0f, m11 = ok ? m11 : 0.0f;
+    int q = 0;
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+      const float ma = fmaf(m00, au[r], m01 * av[r]);
+      const float mc = fmaf(m01, au[r], m11 * av[r]);
+#pragma unroll
+      for (int c = r; c < 6; ++c) {
+        acc[q] = fmaf(ma, au[c], fmaf(mc, av[c], acc[q]));
+        ++q;
+      }
+      acc[kSlotB + r] -= fmaf(au[r], v0, av[r] * v1);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- LDS-staged accumulation (K = 8)
+
+// The bytes of the current level a workgroup holds in LDS: rows lo..hi
+// (inclusive), each W bytes, byte (r, x) of the level at offset
+// delta + (r - lo) * W + x.  `bytes` is how many are valid from the start.
+struct Tile8 {
+  const __attribute__((address_space(3))) uint8_t* lds;
+  int lo, hi, delta, bytes;
+};
+
+// Byte offset in the level of the pattern's sample k relative to its base
+// pixel: dy_k * W + dx_k, the same for every point of the level.
+__device__ __forceinline__ void pattern_offsets(const PatRegs& pat, int W, int (&off)[8]) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k) off[k] = (int)pat.dy[k] * W + (int)pat.dx[k];
+}
+
+// accumulate_point for the 8-pixel pattern, with the taps read from the
+// workgroup's LDS copy of the level where every point of the wave lies inside
+// it (else from global memory, as accumulate_point).  The pattern offsets are
+// whole pixels, so all 8 samples share the point's bilinear fractions: the
+// weights are formed once per point.  COST_ONLY: only the cost and the counts
+// (the final pass).  Otherwise the Gauss-Newton terms and the point count, no
+// cost (it is read only after the final pass; the sample count is 8 per point).
+template <bool COST_ONLY, class PR, int NV = 32>
+__device__ __forceinline__ void accumulate_point8(const TrackArgs& a, const PatRegs& pat, const int (&off)[8],
+                                                  const LevelGeom& g, const uint8_t* __restrict__ img,
+                                                  const Tile8& tile, const float* T, const PR& pr,
+                                                  float (&acc)[NV]) {
+  constexpr bool FIXED = NV == kFixSlots;
+  static_assert(NV == 32 || FIXED, "slot layout");
+  constexpr int sE = FIXED ? kFixE : kSlotE, sN = FIXED ? kFixN : kSlotN, sP = FIXED ? kFixPts : kSlotPts;
+  const float kH = FIXED ? 0.0f : a.huber_k;
+  // Huber weight min(1, k / |r|); without a threshold every weight is 1
+  const float kHw = kH > 0.0f ? kH : __builtin_inff();
+  float X, Y, Z;
+  transform(T, pr.X0, pr.Y0, pr.Z0, X, Y, Z);
+  float u, v;
+  project(g, X, Y, Z, u, v);
+  const bool ok = pr.ok & (Z > a.z_min) & inside(g, pat, u, v);
+  u = ok ? u : 0.0f;
+  v = ok ? v : 0.0f;
+  const Cell q0 = cell_of(u, v);
+  const int iu = q0.iu, iv = q0.iv, W = g.W;
+  float t00[8], t10[8], t01[8], t11[8];
+  const bool in_tile = !ok | ((iv + (int)pat.dy_min >= tile.lo) & (iv + (int)pat.dy_max + 1 <= tile.hi));
+  if (__all(in_tile)) {
+    // Every usable point of the wave lies inside the tile.  An unusable one
+    // reads from the tile position of a pattern whose top-left sample sits at
+    // the tile's first byte: a few rows, inside the allocation whatever the
+    // level, and masked below.  All 16 pairs of words are requested before any
+    // is used (one LDS round trip per point).
+    const uint32_t lb = (uint32_t)(uintptr_t)tile.lds;
+    const int base = (int)lb + tile.delta +
+                     (ok ? (iv - tile.lo) * W + iu : -((int)pat.dy_min * W + (int)pat.dx_min));
+    uint32_t w[8][4];
+    int bt[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      bt[k] = base + off[k];
+      const __attribute__((address_space(3))) uint32_t* p =
+          (const __attribute__((address_space(3))) uint32_t*)(uintptr_t)(uint32_t)(bt[k] & ~3);
+      const __attribute__((address_space(3))) uint32_t* q =
+          (const __attribute__((address_space(3))) uint32_t*)(uintptr_t)(uint32_t)((bt[k] + W) & ~3);
+      w[k][0] = p[0], w[k][1] = p[1], w[k][2] = q[0], w[k][3] = q[1];
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const uint32_t top = __builtin_amdgcn_alignbyte(w[k][1], w[k][0], (uint32_t)bt[k]);
+      const uint32_t bot = __builtin_amdgcn_alignbyte(w[k][3], w[k][2], (uint32_t)(bt[k] + W));
+      t00[k] = (float)(top & 0xffu), t10[k] = (float)((top >> 8) & 0xffu);
+      t01[k] = (float)(bot & 0xffu), t11[k] = (float)((bot >> 8) & 0xffu);
+    }
+  } else {
+    const __attribute__((address_space(1))) uint8_t* gimg = (const __attribute__((address_space(1))) uint8_t*)img;
+    const int base = iv * W + iu;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int o = ok ? base + off[k] : 0;  // an unusable point reads the level's first pixels
+      t00[k] = gimg[o], t10[k] = gimg[o + 1], t01[k] = gimg[o + W], t11[k] = gimg[o + W + 1];
+    }
+  }
+  float m00 = 0.f, m01 = 0.f, m11 = 0.f, v0 = 0.f, v1 = 0.f, E = 0.f;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const float Ic = bilin_mix(q0.w, t00[k], t10[k], t01[k], t11[k]);
+    const float r = pr.i0(k) - Ic;
+    if constexpr (COST_ONLY) {
+      const float ar = fabsf(r);
+      const bool hub = (kH > 0.f) & (ar > kH);
+      E += hub ? kH * (ar - 0.5f * kH) : 0.5f * r * r;
+    } else {
+      const float gx = pr.gx(k), gy = pr.gy(k);
+      if constexpr (FIXED) {
+        v0 = fmaf(gx, r, v0);
+        v1 = fmaf(gy, r, v1);
+      } else {
+        const float w = fminf(1.0f, kHw * __builtin_amdgcn_rcpf(fabsf(r)));
+        const float wgx = w * gx, wgy = w * gy;
+        m00 = fmaf(wgx, gx, m00);
+        m01 = fmaf(wgx, gy, m01);
+        m11 = fmaf(wgy, gy, m11);
+        v0 = fmaf(wgx, r, v0);
+        v1 = fmaf(wgy, r, v1);
+      }
+    }
+  }
+  acc[sP] += ok ? 1.0f : 0.0f;
+  if constexpr (COST_ONLY) {
+    acc[sE] += ok ? E : 0.0f;
+    acc[sN] += ok ? 8.0f : 0.0f;
+    return;
+  }
+  v0 = ok ? v0 : 0.0f, v1 = ok ? v1 : 0.0f;
+  const float izr = pr.iz, xp = pr.xp, yp = pr.yp;
+  const float au[6] = {-g.fx * xp * yp, g.fx * fmaf(xp, xp, 1.0f), -g.fx * yp, g.fx * izr, 0.0f, -g.fx * xp * izr};
+  const float av[6] = {-g.fy * fmaf(yp, yp, 1.0f), g.fy * xp * yp, g.fy * xp, 0.0f, g.fy * izr, -g.fy * yp * izr};
   if constexpr (FIXED) {
 #pragma unroll
     for (int r = 0; r < 6; ++r) acc[kFixB + r] -= fmaf(au[r], v0, av[r] * v1);
@@ -816,6 +974,7 @@ __device__ __forceinline__ void accumulate_point_generic(const TrackArgs& a, con
   const bool ok = pg.ok & (Z > a.z_min) & inside(g, pat, u, v);
   u = ok ? u : 0.0f;
   v = ok ? v : 0.0f;
+  const Cell q0 = cell_of(u, v);
   const int K = pat.K, W = g.W;
   const __attribute__((address_space(1))) PIX* gimg = (const __attribute__((address_space(1))) PIX*)img;
   float m00 = 0.f, m01 = 0.f, m11 = 0.f, v0 = 0.f, v1 = 0.f, E = 0.f;
@@ -824,27 +983,22 @@ __device__ __forceinline__ void accumulate_point_generic(const TrackArgs& a, con
   // in range) and is weighted by zero.
   constexpr int B = 4;
   for (int k0 = sub; k0 < K; k0 += B * kLanesPerPoint) {
-    float ta[B], tc[B], t00[B], t10[B], t01[B], t11[B], i0[B], gxs[B], gys[B], msk[B];
+    float t00[B], t10[B], t01[B], t11[B], i0[B], gxs[B], gys[B], msk[B];
 #pragma unroll
     for (int j = 0; j < B; ++j) {
       const int k = k0 + j * kLanesPerPoint;
       const bool has = k < K;
       const int kk = has ? k : 0;
       msk[j] = has ? 1.0f : 0.0f;
-      const float x = u + (float)pat.dx[kk], y = v + (float)pat.dy[kk];
-      const float fx = floorf(x), fy = floorf(y);
-      ta[j] = x - fx;
-      tc[j] = y - fy;
-      const int off = ((int)fy * W + (int)fx) & -(int)ok;  // an unusable point reads the level's first taps
+      // an unusable point reads the level's first taps
+      const int off = ((q0.iv + (int)pat.dy[kk]) * W + q0.iu + (int)pat.dx[kk]) & -(int)ok;
       t00[j] = gimg[off], t10[j] = gimg[off + 1], t01[j] = gimg[off + W], t11[j] = gimg[off + W + 1];
       i0[j] = a.ref.I0[pg.s0 + kk];
       if (!COST_ONLY) gxs[j] = a.ref.gx[pg.s0 + kk], gys[j] = a.ref.gy[pg.s0 + kk];
     }
 #pragma unroll
     for (int j = 0; j < B; ++j) {
-      const float top = fmaf(ta[j], t10[j] - t00[j], t00[j]);
-      const float bot = fmaf(ta[j], t11[j] - t01[j], t01[j]);
-      const float Ic = fmaf(tc[j], bot - top, top);
+      const float Ic = bilin_mix(q0.w, t00[j], t10[j], t01[j], t11[j]);
       const float r = i0[j] - Ic;
       const float ar = fabsf(r);
       const bool hub = (kH > 0.f) & (ar > kH);

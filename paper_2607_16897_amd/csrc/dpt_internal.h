@@ -256,6 +256,18 @@ struct CoopEngine {
   ~CoopEngine() { release(); }
 };
 
+// Cycle split of the cooperative track, in builds compiled with
+// -DDPT_CYCLE_PROFILE only: per grid slot, summed over every iteration of
+// every launch since the last reset, the cycles thread 0 of the workgroup spends
+// in each phase of a Gauss-Newton iteration (DPT_CYCLE_* in dptrack.h).
+#ifdef DPT_CYCLE_PROFILE
+constexpr bool kCycleProfile = true;
+#else
+constexpr bool kCycleProfile = false;
+#endif
+constexpr int kCycleSlots = 1024;
+hipError_t read_cycle_profile(uint64_t* host, int n_slots, bool reset);  // hipErrorNotSupported without the flag
+
 constexpr int kStatusTimeout = DPT_TRACK_TIMEOUT;  // a cooperative wait gave up (dpt_result.status)
 constexpr int kSpinLimit = DPT_DEFAULT_SPIN_LIMIT;  // polls (one round trip to memory each) before a chunk reports a timeout
 

@@ -118,14 +118,15 @@ __global__ __launch_bounds__(256) void precompute_kernel(PrecomputeArgs one, con
   }
   if (k == 0) a.valid[(int64_t)l * a.cap + i] = ok ? 1 : 0;
   float I0 = 0.f, gx = 0.f, gy = 0.f;
-  if (ok) {
-    const float px = u + (float)a.pat.dx[k], py = v + (float)a.pat.dy[k];
+  if (ok) {  // sample k: the cell of the point's projection moved by the pattern offset
+    const Cell q = cell_of(u, v);
+    const int x = q.iu + (int)a.pat.dx[k], y = q.iv + (int)a.pat.dy[k];
     if (a.reff) {  // floating-point Gaussian pyramid
-      I0 = bilinear(a.reff + g.off, g.W, px, py);
-      gradient(a.reff + g.off, g.W, px, py, gx, gy);
+      I0 = sample_cell(a.reff + g.off, g.W, x, y, q.w);
+      gradient_cell(a.reff + g.off, g.W, x, y, q.w, gx, gy);
     } else {
-      I0 = bilinear(a.ref + g.off, g.W, px, py);
-      gradient(a.ref + g.off, g.W, px, py, gx, gy);
+      I0 = sample_cell(a.ref + g.off, g.W, x, y, q.w);
+      gradient_cell(a.ref + g.off, g.W, x, y, q.w, gx, gy);
     }
   }
   const int64_t o = (int64_t)l * a.cap * K + s;
@@ -348,9 +349,10 @@ __device__ __forceinline__ void accumulate(const TrackArgs& a, const Pattern& pa
       }
     }
     float m00 = 0.f, m01 = 0.f, m11 = 0.f, v0 = 0.f, v1 = 0.f, E = 0.f;
+    const Cell q0 = cell_of(u, v);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const float Ic = bilinear(img, g.W, u + (float)pat.dx[k], v + (float)pat.dy[k]);
+      const float Ic = sample_cell(img, g.W, q0.iu + (int)pat.dx[k], q0.iv + (int)pat.dy[k], q0.w);
       const float tmpl = KT ? i0[k] : I0[(int64_t)i * K + k];
       const float r = tmpl - Ic;
       const float ar = fabsf(r);
