@@ -50,7 +50,17 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2607_16897_amd", "csrc", f)
                   for f in ("dpt_coop.hip", "dpt_device.h", "dpt_internal.h")]
 
 CAM = None  # synth.CAM_752, set in main
+LAUNCH_NAME = {0: "auto", 2: "coop", 3: "pairs"}  # launch mode -> the --launch name
 LEVELS, N_POINTS, WINDOW = 4, 2000, 10
+
+
+def track_kernel_name(launch: str, chunk: int, window: bool, mixed: bool = False, fixed: bool = False) -> str:
+    """The cooperative 8-pixel track kernel a launch configuration runs (as rocprofv3 names it)."""
+    pairs = launch == "pairs"
+    threads = 2 * chunk if pairs else chunk
+    name = (f"coop_track_kernel<{threads}, {'true' if mixed else 'false'}, {'true' if fixed else 'false'}, false, "
+            f"unsigned char, {'true' if window else 'false'}")
+    return name + (", 2>" if pairs else ", 1>")
 
 
 def kernel_source_hash() -> str:
@@ -358,6 +368,9 @@ def bench_batched_mixed(dpt, synth, n_streams: int, n_frames: int, reps: int):
     bt.build_pyramids(dpt.SLOT_CUR, [f[0] for f in dev_frames])
     key = autotune.shape_key(cams, npts, 3, 8)
     mode, chunk, timings = autotune.tune(bt, I, key, cache=None)
+    # the chosen configuration's launch groups are built by its first track:
+    # outside the timed region
+    bt.track(I)
     # every frame is an independent pair tracked from the identity: all are
     # enqueued (each frame's pyramid build is ordered after the previous
     # frame's track), the results come back at the end
@@ -409,11 +422,11 @@ def bench_batched_mixed(dpt, synth, n_streams: int, n_frames: int, reps: int):
 
 
 # ---------------------------------------------------------------- precision legs
-def bench_mixed_precision(dpt, synth, wins, dev, steps):
+def bench_mixed_precision(dpt, synth, wins, dev, steps, launch, chunk):
     """The headline workload through the mixed-precision variant (FP16 template
     cache, Kahan-compensated FP32 sums, FP64 solve, exponential and pose)."""
     prm = dpt.make_params(levels=LEVELS, max_iters=10, huber_k=9.0, step_eps=1e-5, precision=dpt.PREC_MIXED)
-    el, st, prof = timed_plain(dpt, synth, wins, dev, steps, 1, prm, dpt.LAUNCH_COOP, 256)
+    el, st, prof = timed_plain(dpt, synth, wins, dev, steps, 1, prm, launch, chunk)
     track_ms = frame_track_ms(prof)
     achieved = float(np.mean(st["samples"])) * BYTES_PER_SAMPLE_MIXED / (track_ms * 1e-3) / 1e9
     out = {"workload": "the headline workload, mixed precision", "frames_per_s": round(steps * (WINDOW - 1) / el, 2),
@@ -424,12 +437,12 @@ def bench_mixed_precision(dpt, synth, wins, dev, steps):
     return out, st
 
 
-def bench_fixed_h(dpt, synth, wins, dev, steps):
+def bench_fixed_h(dpt, synth, wins, dev, steps, launch, chunk):
     """The headline workload through the paper's own inverse-compositional track:
     per level a constant H reduced once per reference, only b and the cost
     reduced per iteration, no robust weights."""
     prm = dpt.make_params(levels=LEVELS, max_iters=10, huber_k=9.0, step_eps=1e-5, fixed_h=True)
-    el, st, prof = timed_plain(dpt, synth, wins, dev, steps, 1, prm, dpt.LAUNCH_COOP, 256)
+    el, st, prof = timed_plain(dpt, synth, wins, dev, steps, 1, prm, launch, chunk)
     track_ms = frame_track_ms(prof)
     iters = float(np.mean(st["iters"]))
     achieved = float(np.mean(st["samples"])) * BYTES_PER_SAMPLE_F32 / (track_ms * 1e-3) / 1e9
@@ -439,7 +452,8 @@ def bench_fixed_h(dpt, synth, wins, dev, steps):
            "track_us_per_iteration": round(track_ms * 1e3 / (iters + 1), 3),
            "status_counts": {str(k): int(v) for k, v in zip(*np.unique(st["status"], return_counts=True))},
            "pose_error_vs_gt": err_summary([pose_error(T, G) for T, G in zip(st["T"], st["gt"])]),
-           "roofline": {"kernel": "coop_track_kernel<256, false, true, false, unsigned char, true>", "bound": "hbm", "unit": "GB/s",
+           "roofline": {"kernel": track_kernel_name(LAUNCH_NAME[launch], chunk, True, fixed=True), "bound": "hbm",
+                        "unit": "GB/s",
                         "peak": HBM_PEAK_GBS, "achieved": round(achieved, 3),
                         "frac": round(achieved / HBM_PEAK_GBS, 6)}}
     return out, st
@@ -796,7 +810,7 @@ def cycle_split(args, legs):
                 "shader_clock_mhz": round(clock_mhz, 1), "workgroups": int(len(used)),
                 "distinct_cus": len(cus), "xccs": sorted({p["xcc"] for p in places}), "places": places[:64]}
 
-    launch = {"auto": dpt.LAUNCH_AUTO, "coop": dpt.LAUNCH_COOP}[args.launch]
+    launch = {"auto": dpt.LAUNCH_AUTO, "coop": dpt.LAUNCH_COOP, "pairs": dpt.LAUNCH_COOP_PAIRS}[args.launch]
     prm = dpt.make_params(levels=LEVELS, max_iters=10, huber_k=9.0, step_eps=1e-5)
     dpt_slots = 1024
     dpt.cycle_profile(dpt_slots, reset=True)
@@ -805,7 +819,7 @@ def cycle_split(args, legs):
     if "batched" in legs:
         cams = [CAM] * args.batch_streams
         bt = dpt.BatchTracker(cams, prm, [N_POINTS] * args.batch_streams)
-        bt.set_launch_config(dpt.LAUNCH_COOP, args.chunk)
+        bt.set_launch_config(dpt.LAUNCH_COOP, 256)
         for w in range(args.steps):
             win = wins[w % len(wins)]
             stack = dev[w % len(wins)][2]
@@ -831,9 +845,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB")
-    ap.add_argument("--launch", choices=["auto", "coop"], default="coop",
-                    help="track launch (the GPU-side constant-velocity start needs the cooperative track)")
-    ap.add_argument("--chunk", type=int, default=256)
+    ap.add_argument("--launch", choices=["auto", "coop", "pairs"], default="pairs",
+                    help="track launch (the GPU-side constant-velocity start needs the cooperative track); "
+                         "pairs: cooperative with two threads per point (--chunk 64 or 128)")
+    ap.add_argument("--chunk", type=int, default=128, help="points per chunk (pairs: 64 or 128)")
     ap.add_argument("--mode", choices=["window", "frame"], default="window",
                     help="headline launch form: one window track per keyframe window (9 frames, bitwise the same "
                          "poses) or frame by frame; the other form is measured beside it")
@@ -881,7 +896,7 @@ def main():
     torch.cuda.synchronize()
     print(f"# rendered {n_render} windows in {render_s:.1f} s", file=sys.stderr, flush=True)
 
-    launch = {"auto": dpt.LAUNCH_AUTO, "coop": dpt.LAUNCH_COOP}[args.launch]
+    launch = {"auto": dpt.LAUNCH_AUTO, "coop": dpt.LAUNCH_COOP, "pairs": dpt.LAUNCH_COOP_PAIRS}[args.launch]
     prm = dpt.make_params(levels=LEVELS, max_iters=10, huber_k=9.0, step_eps=1e-5)
     window = args.mode == "window"
     elapsed, stats, prof = timed_plain(dpt, synth, wins, dev, args.steps, args.warmup, prm, launch, args.chunk,
@@ -902,7 +917,7 @@ def main():
     samp_launch = float(np.mean(stats["samples"])) * fpl
     alg_bytes = samp_launch * BYTES_PER_SAMPLE_F32
     achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
-    kname = f"coop_track_kernel<{args.chunk}, false, false, false, unsigned char, {'true' if window else 'false'}>"
+    kname = track_kernel_name(args.launch, args.chunk, window)
     iters = float(np.mean(stats["iters"]))
 
     def form(el, st, pr, w):
@@ -910,7 +925,7 @@ def main():
         return {"launch_form": "window" if w else "frame", "frames_per_s": round(tracked / el, 2),
                 "track_launch_ms": round(lm, 5), "track_ms_per_frame": round(lm / pr["frames_per_launch"], 5),
                 "pyramid_launch_ms": round(pr["pyramid_ms"] / max(pr["n_pyramid"], 1), 5),
-                "kernel": f"coop_track_kernel<{args.chunk}, false, false, false, unsigned char, {'true' if w else 'false'}>"}
+                "kernel": track_kernel_name(args.launch, args.chunk, w)}
 
     att_gbs = attainable_copy_gbs()  # after the timed region
     out = {
@@ -955,7 +970,7 @@ def main():
     comparisons = {"headline_fp32": ([(args.warmup % n_render, j) for j in range(1, WINDOW)], stats["init"][:nc],
                                      stats["T"][:nc], CAM, wins, N_POINTS, LEVELS)}
     if "mixed" in legs:
-        mp, st_m = bench_mixed_precision(dpt, synth, wins, dev, max(4, args.steps // 2))
+        mp, st_m = bench_mixed_precision(dpt, synth, wins, dev, max(4, args.steps // 2), launch, args.chunk)
         comparisons["headline_mixed"] = ([(1 % n_render, j) for j in range(1, WINDOW)], st_m["init"][:nc],
                                          st_m["T"][:nc], CAM, wins, N_POINTS, LEVELS)
         sw, so, sraw = bench_stress(dpt, synth)
@@ -966,7 +981,7 @@ def main():
         out["mixed_precision"] = mp
         print("# precision legs done", file=sys.stderr, flush=True)
     if "fixed" in legs:
-        fh, st_f = bench_fixed_h(dpt, synth, wins, dev, max(4, args.steps // 2))
+        fh, st_f = bench_fixed_h(dpt, synth, wins, dev, max(4, args.steps // 2), launch, args.chunk)
         comparisons["headline_fixed_h"] = ([(1 % n_render, j) for j in range(1, WINDOW)], st_f["init"][:nc],
                                            st_f["T"][:nc], CAM, wins, N_POINTS, LEVELS, {"fixed_h": True})
         out["fixed_h"] = fh

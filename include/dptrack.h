@@ -365,6 +365,13 @@ int dpt_get_fixed_hessian(dpt_ctx* ctx, int32_t level, double H36[36], int32_t* 
  *                         Patterns other than the 8-pixel one and the Gaussian
  *                         float pyramid use chunks of 64 points, four threads per
  *                         point, whatever `chunk` says
+ *   DPT_LAUNCH_COOP_PAIRS as DPT_LAUNCH_COOP with two threads per point, each
+ *                         taking four of the 8-pixel pattern's samples: chunks
+ *                         of `chunk` points (64 or 128) in 2 x chunk threads.
+ *                         Half the work per thread on twice the compute units:
+ *                         the faster form for a stream or a small batch that
+ *                         leaves most of the GPU idle.  Other patterns and the
+ *                         Gaussian float pyramid run as DPT_LAUNCH_COOP
  * Results agree with each other to rounding (the summation order differs).
  *
  * Co-residency.  The chunks of a stream wait for each other's partial sums,
@@ -381,7 +388,7 @@ int dpt_get_fixed_hessian(dpt_ctx* ctx, int32_t level, double H36[36], int32_t* 
  * frame ends with DPT_TRACK_TIMEOUT instead of a pose; nothing hangs.  A caller
  * that shares the device with heavy concurrent work and cannot accept that
  * outcome uses DPT_LAUNCH_WORKGROUP, which never waits across workgroups. */
-enum { DPT_LAUNCH_AUTO = 0, DPT_LAUNCH_WORKGROUP = 1, DPT_LAUNCH_COOP = 2 };
+enum { DPT_LAUNCH_AUTO = 0, DPT_LAUNCH_WORKGROUP = 1, DPT_LAUNCH_COOP = 2, DPT_LAUNCH_COOP_PAIRS = 3 };
 int dpt_set_launch_config(dpt_ctx* ctx, int32_t mode, int32_t chunk);
 
 /* Bound of the cooperative track's waits: a chunk that polls the other chunks'

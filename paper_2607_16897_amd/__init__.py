@@ -26,7 +26,7 @@ PREC_FP32, PREC_MIXED = 0, 1
 FLAG_FIXED_H = 1  # dpt_params.flags: the paper's constant-H track
 FLAG_GAUSS_F32 = 2  # dpt_params.flags: track on the floating-point Gaussian pyramid
 SLOT_REF, SLOT_CUR = 0, 1
-LAUNCH_AUTO, LAUNCH_WORKGROUP, LAUNCH_COOP = 0, 1, 2
+LAUNCH_AUTO, LAUNCH_WORKGROUP, LAUNCH_COOP, LAUNCH_COOP_PAIRS = 0, 1, 2, 3
 INIT_GIVEN, INIT_CONST_VELOCITY = 0, 1
 MAX_WINDOW = 32  # most frames one window track covers
 MAX_IN_FLIGHT = 256  # most tracks enqueued and not yet synchronised

@@ -2,7 +2,8 @@
 
 For a tracker or batch whose reference maps and current pyramids are loaded,
 time every candidate launch configuration (one workgroup per frame; cooperative
-chunks of 64, 128 or 256 points per workgroup) with the library's own HIP
+chunks of 64, 128 or 256 points per workgroup, one thread per point; chunks of 64
+or 128 points with two threads per point) with the library's own HIP
 event timing, check that the candidates agree on the poses, and keep the
 fastest.  Choices are cached in a JSON file keyed by GPU architecture and a
 shape bucket (streams, resolution mix, map-size bucket, levels, pattern size).
@@ -15,12 +16,13 @@ import os
 
 import numpy as np
 
-from . import LAUNCH_COOP, LAUNCH_WORKGROUP
+from . import LAUNCH_COOP, LAUNCH_COOP_PAIRS, LAUNCH_WORKGROUP
 
-CANDIDATES = ((LAUNCH_WORKGROUP, 256), (LAUNCH_COOP, 64), (LAUNCH_COOP, 128), (LAUNCH_COOP, 256))
+CANDIDATES = ((LAUNCH_WORKGROUP, 256), (LAUNCH_COOP, 64), (LAUNCH_COOP, 128), (LAUNCH_COOP, 256),
+              (LAUNCH_COOP_PAIRS, 64), (LAUNCH_COOP_PAIRS, 128))
 # the cooperative configurations only (the constant-velocity start computed on
 # the GPU needs the cooperative track)
-COOP_CANDIDATES = tuple(c for c in CANDIDATES if c[0] == LAUNCH_COOP)
+COOP_CANDIDATES = tuple(c for c in CANDIDATES if c[0] in (LAUNCH_COOP, LAUNCH_COOP_PAIRS))
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "dptrack", "autotune.json")
 
 

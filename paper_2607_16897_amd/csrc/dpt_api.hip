@@ -786,15 +786,21 @@ namespace {
 // the generic cooperative variant (four lanes per point, fixed 256-thread chunks).
 bool generic_track(const dpt_params& p) { return p.n_pattern != 8 || (p.flags & DPT_FLAG_GAUSS_F32); }
 
-int coop_variant(const dpt_params& p) {
-  if (p.precision == DPT_PREC_MIXED) return kCoopMixed;
+// Two threads per point: the pair launch mode, for the 8-pixel kernels.
+bool pair_track(const dpt_params& p, int mode) { return mode == DPT_LAUNCH_COOP_PAIRS && !generic_track(p); }
+
+int coop_variant(const dpt_params& p, int mode) {
+  const int pairs = pair_track(p, mode) ? kCoopPairs : 0;
+  if (p.precision == DPT_PREC_MIXED) return kCoopMixed | pairs;
   int v = (p.flags & DPT_FLAG_FIXED_H) ? kCoopFixedH : kCoopFP32;
   if (generic_track(p)) v |= kCoopGeneric | ((p.flags & DPT_FLAG_GAUSS_F32) ? kCoopFloatPyr : 0);
-  return v;
+  return v | pairs;
 }
 
-// Threads and points per chunk of a cooperative launch.
-int coop_threads(const dpt_params& p, int chunk) { return generic_track(p) ? kGenericThreads : chunk; }
+// Threads and points per chunk of a cooperative launch (`chunk` as configured).
+int coop_threads(const dpt_params& p, int chunk, int mode) {
+  return generic_track(p) ? kGenericThreads : pair_track(p, mode) ? 2 * chunk : chunk;
+}
 int coop_ppc(const dpt_params& p, int chunk) {
   return generic_track(p) ? kGenericThreads / kLanesPerPoint : chunk;
 }
@@ -805,19 +811,19 @@ bool use_coop(dpt_ctx* c) {
   if (c->launch_mode == DPT_LAUNCH_WORKGROUP) return false;
   const int ppc = coop_ppc(c->prm, c->chunk);
   const int nch = c->n_points > 0 ? (c->n_points + ppc - 1) / ppc : 1;
-  return nch <= coop_max_blocks(coop_threads(c->prm, c->chunk)) / 8;  // the XCD-packed grid may hold up to 8x padding
+  return nch <= coop_max_blocks(coop_threads(c->prm, c->chunk, c->launch_mode)) / 8;  // the XCD-packed grid may hold up to 8x padding
 }
 
 // The context's single-stream cooperative engine, built on first use and
 // refreshed when the map changed size.
 int ensure_engine(dpt_ctx* c) {
-  const int threads = coop_threads(c->prm, c->chunk), ppc = coop_ppc(c->prm, c->chunk);
+  const int threads = coop_threads(c->prm, c->chunk, c->launch_mode), ppc = coop_ppc(c->prm, c->chunk);
   const int nch = c->n_points > 0 ? (c->n_points + ppc - 1) / ppc : 1;
   if (8 * nch > coop_max_blocks(threads))
     return fail(DPT_E_ARG, "%d points exceed the cooperative capacity at %d points per chunk", c->n_points, ppc);
   if (!c->eng_ready) {
     HIP_TRY(c->eng.init(1, &c->cap, threads, ppc, true, c->stream));
-    c->eng.variant = coop_variant(c->prm);
+    c->eng.variant = coop_variant(c->prm, c->launch_mode);
     c->eng_ready = true;
   }
   if (c->eng.dirty || c->eng.h_streams[0].a.ref.n != c->n_points) {
@@ -1194,11 +1200,13 @@ int dpt_set_spin_limit(dpt_ctx* c, int32_t polls) {
 int dpt_set_launch_config(dpt_ctx* c, int32_t mode, int32_t chunk) {
   g_err.clear();
   if (!c) return fail(DPT_E_ARG, "NULL context");
-  if (mode < DPT_LAUNCH_AUTO || mode > DPT_LAUNCH_COOP) return fail(DPT_E_ARG, "mode %d", mode);
+  if (mode < DPT_LAUNCH_AUTO || mode > DPT_LAUNCH_COOP_PAIRS) return fail(DPT_E_ARG, "mode %d", mode);
   if (chunk != 64 && chunk != 128 && chunk != 256) return fail(DPT_E_ARG, "chunk %d not in {64, 128, 256}", chunk);
+  if (mode == DPT_LAUNCH_COOP_PAIRS && chunk == 256)
+    return fail(DPT_E_ARG, "chunk %d: two threads per point take 64 or 128 points per chunk", chunk);
   if (mode == DPT_LAUNCH_WORKGROUP && c->prm.precision == DPT_PREC_MIXED)
     return fail(DPT_E_ARG, "mixed precision runs on the cooperative launch only");
-  if (chunk != c->chunk && c->eng_ready) {
+  if ((chunk != c->chunk || pair_track(c->prm, mode) != pair_track(c->prm, c->launch_mode)) && c->eng_ready) {
     const int e = synchronize(c);
     if (e != DPT_OK) return e;
     c->eng.release();
@@ -1404,7 +1412,7 @@ int packed_grid(const std::vector<int>& chunks_desc) {
 // co-resident capacity.
 int build_groups(dpt_batch* b) {
   b->clear_groups();
-  const int cap = coop_max_blocks(coop_threads(b->ctx[0]->prm, b->chunk));
+  const int cap = coop_max_blocks(coop_threads(b->ctx[0]->prm, b->chunk, b->launch_mode));
   std::vector<int> order(b->n);
   for (int s = 0; s < b->n; ++s) order[s] = s;
   std::sort(order.begin(), order.end(), [&](int p, int q) { return batch_chunks(b, p) > batch_chunks(b, q); });
@@ -1416,13 +1424,13 @@ int build_groups(dpt_batch* b) {
     if (!g) return fail(DPT_E_OOM, "host allocation failed");
     std::vector<int> maxp(cur.size());
     for (size_t k = 0; k < cur.size(); ++k) maxp[k] = b->ctx[cur[k]]->cap;
-    hipError_t e = g->init((int)cur.size(), maxp.data(), coop_threads(b->ctx[0]->prm, b->chunk),
+    hipError_t e = g->init((int)cur.size(), maxp.data(), coop_threads(b->ctx[0]->prm, b->chunk, b->launch_mode),
                            coop_ppc(b->ctx[0]->prm, b->chunk), true, b->stream);
     if (e != hipSuccess) {
       delete g;
       return fail(DPT_E_HIP, "cooperative group init: %s", hipGetErrorString(e));
     }
-    g->variant = coop_variant(b->ctx[0]->prm);
+    g->variant = coop_variant(b->ctx[0]->prm, b->launch_mode);
     for (size_t k = 0; k < cur.size(); ++k) {
       TrackArgs a;
       fill_track_args(b->ctx[cur[k]], a);
@@ -1455,7 +1463,8 @@ int build_groups(dpt_batch* b) {
 
 bool batch_use_coop(const dpt_batch* b) {
   if (b->ctx[0]->prm.precision == DPT_PREC_MIXED) return true;
-  return b->launch_mode != DPT_LAUNCH_WORKGROUP && coop_max_blocks(coop_threads(b->ctx[0]->prm, b->chunk)) > 0;
+  return b->launch_mode != DPT_LAUNCH_WORKGROUP &&
+         coop_max_blocks(coop_threads(b->ctx[0]->prm, b->chunk, b->launch_mode)) > 0;
 }
 
 // abandon() for a batch: every group's results of every launch in flight.
@@ -2044,13 +2053,16 @@ int dpt_batch_set_spin_limit(dpt_batch* b, int32_t polls) {
 int dpt_batch_set_launch_config(dpt_batch* b, int32_t mode, int32_t chunk) {
   g_err.clear();
   if (!b) return fail(DPT_E_ARG, "NULL batch");
-  if (mode < DPT_LAUNCH_AUTO || mode > DPT_LAUNCH_COOP) return fail(DPT_E_ARG, "mode %d", mode);
+  if (mode < DPT_LAUNCH_AUTO || mode > DPT_LAUNCH_COOP_PAIRS) return fail(DPT_E_ARG, "mode %d", mode);
   if (chunk != 64 && chunk != 128 && chunk != 256) return fail(DPT_E_ARG, "chunk %d not in {64, 128, 256}", chunk);
+  if (mode == DPT_LAUNCH_COOP_PAIRS && chunk == 256)
+    return fail(DPT_E_ARG, "chunk %d: two threads per point take 64 or 128 points per chunk", chunk);
   if (mode == DPT_LAUNCH_WORKGROUP && b->ctx[0]->prm.precision == DPT_PREC_MIXED)
     return fail(DPT_E_ARG, "mixed precision runs on the cooperative launch only");
   const int e = batch_synchronize(b);
   if (e != DPT_OK) return e;
-  if (chunk != b->chunk) b->clear_groups();
+  if (chunk != b->chunk || pair_track(b->ctx[0]->prm, mode) != pair_track(b->ctx[0]->prm, b->launch_mode))
+    b->clear_groups();
   b->launch_mode = mode;
   b->chunk = chunk;
   return DPT_OK;

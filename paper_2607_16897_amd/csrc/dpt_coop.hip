@@ -394,6 +394,16 @@ __device__ __forceinline__ Tile8 stage_tile(const TrackArgs& a, const PatRegs& p
   return t;
 }
 
+// The pattern offsets of this thread's samples: all 8, or (NS = 4) the half
+// `sub` of a point's pair takes.
+template <int NS>
+__device__ __forceinline__ void lane_offsets(const PatRegs& pat, int W, int sub, int (&off)[NS]) {
+  int all[8];
+  pattern_offsets(pat, W, all);
+#pragma unroll
+  for (int k = 0; k < NS; ++k) off[k] = NS == 8 ? all[k] : (sub ? all[NS + k] : all[k]);
+}
+
 // A tile that holds no row: every usable point reads global memory.
 __device__ __forceinline__ Tile8 no_tile(uint8_t* tile_mem) {
   Tile8 t;
@@ -409,7 +419,10 @@ __device__ __forceinline__ Tile8 no_tile(uint8_t* tile_mem) {
 // comes factored from the precompute.
 // GENERIC: any pattern K (four lanes per point, CH / 4 points per chunk) on
 // uint8 levels or (PIX = float) the floating-point Gaussian pyramid.
-template <int CH, bool MIXED, bool FIXED, bool GENERIC = false, class PIX = uint8_t, bool WIN = false>
+//
+// LPP = 2 (8-pixel pattern only): two threads per point, four samples each;
+// a chunk of CH threads holds CH / 2 points.
+template <int CH, bool MIXED, bool FIXED, bool GENERIC = false, class PIX = uint8_t, bool WIN = false, int LPP = 1>
 __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __restrict__ streams,
                                                            const int2* __restrict__ work,
                                                            const StartSlot* __restrict__ start,
@@ -418,10 +431,14 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
                                                            int spin_limit, int tile_bytes) {
   static_assert(!(MIXED && FIXED), "the fixed-H mode computes in FP32");
   static_assert(!(MIXED && GENERIC) && (GENERIC || std::is_same<PIX, uint8_t>::value), "variant");
-  using PR = typename std::conditional<GENERIC, PointGeo,
-                                       typename std::conditional<MIXED, PointRegsH, PointRegs>::type>::type;
+  static_assert(LPP == 1 || (LPP == 2 && !GENERIC), "two threads per point: the 8-pixel kernels");
+  using PR8 = typename std::conditional<MIXED, PointRegsH, PointRegs>::type;
+  using PR4 = typename std::conditional<MIXED, PointRegsH4, PointRegs4>::type;
+  using PR = typename std::conditional<GENERIC, PointGeo, typename std::conditional<LPP == 2, PR4, PR8>::type>::type;
   constexpr bool FLOAT_PYR = std::is_same<PIX, float>::value;
-  constexpr int PPC = GENERIC ? CH / kLanesPerPoint : CH;  // points per chunk
+  constexpr int TPP = GENERIC ? kLanesPerPoint : LPP;  // threads per point
+  constexpr int PPC = CH / TPP;                        // points per chunk
+  constexpr int NS = 8 / LPP;                          // samples per thread (8-pixel kernels)
   constexpr int NV = FIXED ? kFixSlots : 32;
   constexpr int sE = FIXED ? kFixE : kSlotE, sN = FIXED ? kFixN : kSlotN, sP = FIXED ? kFixPts : kSlotPts;
   __shared__ CoopStream ss;
@@ -447,8 +464,8 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
   const TrackArgs& a = ss.a;
   const PatRegs pregs = pattern_regs(a.pat);
   const int chunk = w.y, nch = ss.n_chunks;
-  const int i = chunk * PPC + (GENERIC ? (int)threadIdx.x / kLanesPerPoint : (int)threadIdx.x);
-  const int sub = GENERIC ? (int)threadIdx.x % kLanesPerPoint : 0;
+  const int i = chunk * PPC + (int)threadIdx.x / TPP;
+  const int sub = (int)threadIdx.x % TPP;
   const int nf = WIN ? n_frames : 1;
   uint32_t tag = tag_base;
   uint64_t cy[4] = {0, 0, 0, 0}, cy_iters = 0, cy_t0 = 0, cy_rt0 = 0;
@@ -484,12 +501,15 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
       const LevelGeom g = a.lv[l];
       const PIX* img = WIN && l == 0 ? cur0 : cur + g.off;
       Tile8 tile;
-      int offs[8];
+      int offs[NS];
       if constexpr (GENERIC) {
         load_point_geo(a, l, i, pr);
       } else {
-        load_point(a, l, i, pr);
-        pattern_offsets(pregs, g.W, offs);
+        if constexpr (LPP == 2)
+          load_point(a, l, i, sub, pr);
+        else
+          load_point(a, l, i, pr);
+        lane_offsets<NS>(pregs, g.W, sub, offs);
         tile = stage_tile(a, pregs, g, reinterpret_cast<const uint8_t*>(img), T, pr, sh_tile, tile_bytes, sh_band);
       }
       if constexpr (FIXED) {
@@ -510,8 +530,8 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
         if constexpr (GENERIC)
           accumulate_point_generic<false, PIX, NV>(a, a.pat, g, img, T, pr, sub, acc);
         else
-          accumulate_point8<false, PR, NV>(a, pregs, offs, g, reinterpret_cast<const uint8_t*>(img), tile, T, pr,
-                                           acc);
+          accumulate_point8<false, PR, NV, NS>(a, pregs, offs, g, reinterpret_cast<const uint8_t*>(img), tile, T,
+                                               pr, acc, sub == 0);
         if constexpr (kCycleProfile) c1 = clock64();
         if (!stream_total<MIXED, NV, GENERIC>(acc, sh_red, sh_tot, &sh_ok, ss.partials, chunk, nch, tag, spin_limit,
                                               sh_grp, &c2)) {
@@ -574,10 +594,14 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
         load_point_geo(a, 0, i, pr);
         accumulate_point_generic<true, PIX, NV>(a, a.pat, g, WIN ? cur0 : cur + g.off, T, pr, sub, acc);
       } else {
-        load_point(a, 0, i, pr);
-        int offs[8];
-        pattern_offsets(pregs, g.W, offs);
-        accumulate_point8<true, PR, NV>(a, pregs, offs, g, WIN ? cur0 : cur + g.off, no_tile(sh_tile), T, pr, acc);
+        if constexpr (LPP == 2)
+          load_point(a, 0, i, sub, pr);
+        else
+          load_point(a, 0, i, pr);
+        int offs[NS];
+        lane_offsets<NS>(pregs, g.W, sub, offs);
+        accumulate_point8<true, PR, NV, NS>(a, pregs, offs, g, WIN ? cur0 : cur + g.off, no_tile(sh_tile), T, pr,
+                                            acc, sub == 0);
       }
       if (!stream_total<MIXED, NV, GENERIC>(acc, sh_red, sh_tot, &sh_ok, ss.partials, chunk, nch, tag, spin_limit,
                                             sh_grp))
@@ -675,6 +699,18 @@ static const void* coop_fn(int variant) {
       default: return WIN ? nullptr : reinterpret_cast<const void*>(&coop_track_kernel<G, false, true, true, float>);
     }
   }
+  if (variant & kCoopPairs) {
+    if (CH == 64) return nullptr;  // a pair chunk holds 64 or 128 points
+    switch (variant & ~kCoopPairs) {
+      case kCoopFP32:
+        return reinterpret_cast<const void*>(&coop_track_kernel<CH, false, false, false, uint8_t, WIN, 2>);
+      case kCoopMixed:
+        return reinterpret_cast<const void*>(&coop_track_kernel<CH, true, false, false, uint8_t, WIN, 2>);
+      case kCoopFixedH:
+        return reinterpret_cast<const void*>(&coop_track_kernel<CH, false, true, false, uint8_t, WIN, 2>);
+      default: return nullptr;
+    }
+  }
   switch (variant) {
     case kCoopFP32: return reinterpret_cast<const void*>(&coop_track_kernel<CH, false, false, false, uint8_t, WIN>);
     case kCoopMixed: return reinterpret_cast<const void*>(&coop_track_kernel<CH, true, false, false, uint8_t, WIN>);
@@ -688,8 +724,16 @@ template <int CH>
 static int coop_blocks_per_cu() {
   static int nb = -1;
   if (nb < 0) {
-    const int vs[] = {kCoopFP32, kCoopMixed, kCoopFixedH, kCoopGeneric, kCoopGeneric | kCoopFixedH,
-                      kCoopGeneric | kCoopFloatPyr, kCoopGeneric | kCoopFixedH | kCoopFloatPyr};
+    const int vs[] = {kCoopFP32,
+                      kCoopMixed,
+                      kCoopFixedH,
+                      kCoopPairs,
+                      kCoopPairs | kCoopMixed,
+                      kCoopPairs | kCoopFixedH,
+                      kCoopGeneric,
+                      kCoopGeneric | kCoopFixedH,
+                      kCoopGeneric | kCoopFloatPyr,
+                      kCoopGeneric | kCoopFixedH | kCoopFloatPyr};
     int best = 1 << 30;
     for (int v : vs)
       for (const void* f : {coop_fn<CH, false>(v), coop_fn<CH, true>(v)}) {
@@ -751,8 +795,8 @@ static hipError_t coop_launch_k(const CoopStream* d_streams, const int2* d_work,
   int tile_bytes = (variant & kCoopGeneric) ? 0 : plain ? kTileBytesLarge : kTileBytesSmall;
   const size_t dyn = tile_bytes ? (size_t)tile_bytes + kTilePad : 0;
   if (dyn > 64 * 1024) {
-    static bool raised[2][8] = {};  // per window form and variant: the attribute is set once
-    bool& r = raised[n_frames > 0][variant & 7];
+    static bool raised[2][32] = {};  // per window form and variant: the attribute is set once
+    bool& r = raised[n_frames > 0][variant & 31];
     if (!r) {
       const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
       if (e != hipSuccess) return e;

@@ -618,6 +618,29 @@ struct PointRegsH {
   __device__ __forceinline__ float gy(int k) const { return __high2float(g_[k]); }
 };
 
+// Half of a point's 8-sample cache, for kernels that give each point two
+// threads: samples 4 sub .. 4 sub + 3 of thread `sub` of the pair.
+struct PointRegs4 {
+  float X0, Y0, Z0;
+  float iz, xp, yp;
+  float i0_[4], gx_[4], gy_[4];
+  bool ok;
+  __device__ __forceinline__ float i0(int k) const { return i0_[k]; }
+  __device__ __forceinline__ float gx(int k) const { return gx_[k]; }
+  __device__ __forceinline__ float gy(int k) const { return gy_[k]; }
+};
+
+struct PointRegsH4 {
+  float X0, Y0, Z0;
+  float iz, xp, yp;
+  __half i0_[4];
+  __half2 g_[4];
+  bool ok;
+  __device__ __forceinline__ float i0(int k) const { return __half2float(i0_[k]) + 128.0f; }
+  __device__ __forceinline__ float gx(int k) const { return __low2float(g_[k]); }
+  __device__ __forceinline__ float gy(int k) const { return __high2float(g_[k]); }
+};
+
 // Load point i's registers for level l.  Branch-free: a point past the map
 // (i >= n) reads entry 0 instead, and the geometry of an unusable point is
 // selected to finite values (its warp Jacobian multiplies masked zeros); the
@@ -658,6 +681,42 @@ __device__ __forceinline__ void load_point(const TrackArgs& a, int l, int i, Poi
   const float t2[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
 #pragma unroll
   for (int k = 0; k < 8; ++k) pr.i0_[k] = t0[k], pr.gx_[k] = t1[k], pr.gy_[k] = t2[k];
+}
+
+// Thread `sub` (0 or 1) of point i's pair: its four samples of the cache.
+__device__ __forceinline__ void load_point(const TrackArgs& a, int l, int i, int sub, PointRegs4& pr) {
+  float4 p;
+  int64_t e;
+  const bool ok = load_geometry(a, l, i, p, e);
+  set_geometry(pr, ok, p);
+  const float4 a0 = reinterpret_cast<const float4*>(a.ref.I0 + e * 8)[sub];
+  const float4 b0 = reinterpret_cast<const float4*>(a.ref.gx + e * 8)[sub];
+  const float4 c0 = reinterpret_cast<const float4*>(a.ref.gy + e * 8)[sub];
+  pr.i0_[0] = a0.x, pr.i0_[1] = a0.y, pr.i0_[2] = a0.z, pr.i0_[3] = a0.w;
+  pr.gx_[0] = b0.x, pr.gx_[1] = b0.y, pr.gx_[2] = b0.z, pr.gx_[3] = b0.w;
+  pr.gy_[0] = c0.x, pr.gy_[1] = c0.y, pr.gy_[2] = c0.z, pr.gy_[3] = c0.w;
+}
+
+__device__ __forceinline__ void load_point(const TrackArgs& a, int l, int i, int sub, PointRegsH4& pr) {
+  float4 p;
+  int64_t e;
+  const bool ok = load_geometry(a, l, i, p, e);
+  set_geometry(pr, ok, p);
+  const uint2 h = reinterpret_cast<const uint2*>(a.ref.I0h + e * 8)[sub];
+  const uint4 g = reinterpret_cast<const uint4*>(a.ref.gh + e * 8)[sub];
+  const uint32_t hw[2] = {h.x, h.y};
+  const uint32_t gw[4] = {g.x, g.y, g.z, g.w};
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    pr.i0_[2 * k] = __ushort_as_half((unsigned short)(hw[k] & 0xffffu));
+    pr.i0_[2 * k + 1] = __ushort_as_half((unsigned short)(hw[k] >> 16));
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    __half2 v;
+    __builtin_memcpy(&v, &gw[k], 4);
+    pr.g_[k] = v;
+  }
 }
 
 __device__ __forceinline__ void load_point(const TrackArgs& a, int l, int i, PointRegsH& pr) {
@@ -810,11 +869,16 @@ __device__ __forceinline__ void pattern_offsets(const PatRegs& pat, int W, int (
 // weights are formed once per point.  COST_ONLY: only the cost and the counts
 // (the final pass).  Otherwise the Gauss-Newton terms and the point count, no
 // cost (it is read only after the final pass; the sample count is 8 per point).
-template <bool COST_ONLY, class PR, int NV = 32>
-__device__ __forceinline__ void accumulate_point8(const TrackArgs& a, const PatRegs& pat, const int (&off)[8],
+//
+// NS = 4: the point has two threads, this one (first = false for the second of
+// the pair) taking four of its samples with their offsets `off`.  Each adds its
+// own samples' normal-equation terms, which sum to the point's (the terms are
+// linear in m and v); the first thread counts the point.
+template <bool COST_ONLY, class PR, int NV = 32, int NS = 8>
+__device__ __forceinline__ void accumulate_point8(const TrackArgs& a, const PatRegs& pat, const int (&off)[NS],
                                                   const LevelGeom& g, const uint8_t* __restrict__ img,
                                                   const Tile8& tile, const float* T, const PR& pr,
-                                                  float (&acc)[NV]) {
+                                                  float (&acc)[NV], bool first = true) {
   constexpr bool FIXED = NV == kFixSlots;
   static_assert(NV == 32 || FIXED, "slot layout");
   constexpr int sE = FIXED ? kFixE : kSlotE, sN = FIXED ? kFixN : kSlotN, sP = FIXED ? kFixPts : kSlotPts;
@@ -830,7 +894,7 @@ __device__ __forceinline__ void accumulate_point8(const TrackArgs& a, const PatR
   v = ok ? v : 0.0f;
   const Cell q0 = cell_of(u, v);
   const int iu = q0.iu, iv = q0.iv, W = g.W;
-  float t00[8], t10[8], t01[8], t11[8];
+  float t00[NS], t10[NS], t01[NS], t11[NS];
   const bool in_tile = !ok | ((iv + (int)pat.dy_min >= tile.lo) & (iv + (int)pat.dy_max + 1 <= tile.hi));
   if (__all(in_tile)) {
     // Every usable point of the wave lies inside the tile.  An unusable one
@@ -841,10 +905,10 @@ __device__ __forceinline__ void accumulate_point8(const TrackArgs& a, const PatR
     const uint32_t lb = (uint32_t)(uintptr_t)tile.lds;
     const int base = (int)lb + tile.delta +
                      (ok ? (iv - tile.lo) * W + iu : -((int)pat.dy_min * W + (int)pat.dx_min));
-    uint32_t w[8][4];
-    int bt[8];
+    uint32_t w[NS][4];
+    int bt[NS];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < NS; ++k) {
       bt[k] = base + off[k];
       const __attribute__((address_space(3))) uint32_t* p =
           (const __attribute__((address_space(3))) uint32_t*)(uintptr_t)(uint32_t)(bt[k] & ~3);
@@ -853,7 +917,7 @@ __device__ __forceinline__ void accumulate_point8(const TrackArgs& a, const PatR
       w[k][0] = p[0], w[k][1] = p[1], w[k][2] = q[0], w[k][3] = q[1];
     }
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < NS; ++k) {
       const uint32_t top = __builtin_amdgcn_alignbyte(w[k][1], w[k][0], (uint32_t)bt[k]);
       const uint32_t bot = __builtin_amdgcn_alignbyte(w[k][3], w[k][2], (uint32_t)(bt[k] + W));
       t00[k] = (float)(top & 0xffu), t10[k] = (float)((top >> 8) & 0xffu);
@@ -863,14 +927,14 @@ __device__ __forceinline__ void accumulate_point8(const TrackArgs& a, const PatR
     const __attribute__((address_space(1))) uint8_t* gimg = (const __attribute__((address_space(1))) uint8_t*)img;
     const int base = iv * W + iu;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < NS; ++k) {
       const int o = ok ? base + off[k] : 0;  // an unusable point reads the level's first pixels
       t00[k] = gimg[o], t10[k] = gimg[o + 1], t01[k] = gimg[o + W], t11[k] = gimg[o + W + 1];
     }
   }
   float m00 = 0.f, m01 = 0.f, m11 = 0.f, v0 = 0.f, v1 = 0.f, E = 0.f;
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
+  for (int k = 0; k < NS; ++k) {
     const float Ic = bilin_mix(q0.w, t00[k], t10[k], t01[k], t11[k]);
     const float r = pr.i0(k) - Ic;
     if constexpr (COST_ONLY) {
@@ -893,10 +957,10 @@ __device__ __forceinline__ void accumulate_point8(const TrackArgs& a, const PatR
       }
     }
   }
-  acc[sP] += ok ? 1.0f : 0.0f;
+  acc[sP] += (ok & first) ? 1.0f : 0.0f;
   if constexpr (COST_ONLY) {
     acc[sE] += ok ? E : 0.0f;
-    acc[sN] += ok ? 8.0f : 0.0f;
+    acc[sN] += ok ? (float)NS : 0.0f;
     return;
   }
   v0 = ok ? v0 : 0.0f, v1 = ok ? v1 : 0.0f;

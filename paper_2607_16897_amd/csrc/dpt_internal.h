@@ -210,8 +210,9 @@ struct PyrJob {
 // Variants of the cooperative track kernel.
 // Bits: kCoopMixed and kCoopFixedH as named; kCoopGeneric: any pattern K, four
 // lanes per point, kGenericThreads-thread chunks of kGenericThreads / 4 points;
-// kCoopFloatPyr (with kCoopGeneric): the floating-point Gaussian pyramid.
-enum { kCoopFP32 = 0, kCoopMixed = 1, kCoopFixedH = 2, kCoopGeneric = 4, kCoopFloatPyr = 8 };
+// kCoopFloatPyr (with kCoopGeneric): the floating-point Gaussian pyramid;
+// kCoopPairs (8-pixel pattern): two threads per point, chunks of threads / 2 points.
+enum { kCoopFP32 = 0, kCoopMixed = 1, kCoopFixedH = 2, kCoopGeneric = 4, kCoopFloatPyr = 8, kCoopPairs = 16 };
 constexpr int kGenericThreads = 256;
 constexpr int kLanesPerPoint = 4;
 

@@ -34,7 +34,7 @@ def _cmp(g, o):
     return rot, tr, rel
 
 
-@pytest.mark.parametrize("launch", [(2, 256), (2, 64), (1, 256)])
+@pytest.mark.parametrize("launch", [(2, 256), (2, 64), (1, 256), (3, 128)])
 @pytest.mark.parametrize("on_device", [True, False])
 def test_batch_matches_oracle_and_plain(gpu_lib, streams, launch, on_device):
     import torch

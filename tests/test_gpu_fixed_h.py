@@ -11,7 +11,7 @@ import synth
 pytestmark = pytest.mark.gpu
 
 ROT_TOL, TR_TOL, COST_TOL = 1e-4, 1e-4, 1e-3
-LAUNCHES = [(1, 256), (2, 64), (2, 256)]  # one workgroup; cooperative chunks
+LAUNCHES = [(1, 256), (2, 64), (2, 256), (3, 128)]  # one workgroup; cooperative chunks; two threads per point
 
 
 def _oparams(p):

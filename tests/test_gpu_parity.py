@@ -142,7 +142,9 @@ def test_track_single_pair(gpu_lib, seed):
     assert abs(g["n_valid_points"] - o["n_valid_points"]) <= 2
 
 
-LAUNCHES = [(1, 256), (2, 64), (2, 128), (2, 256)]  # one workgroup; cooperative chunks
+# one workgroup; cooperative chunks of one thread per point; cooperative chunks
+# of two threads per point
+LAUNCHES = [(1, 256), (2, 64), (2, 128), (2, 256), (3, 64), (3, 128)]
 
 
 @pytest.mark.parametrize("launch", LAUNCHES)
@@ -209,7 +211,7 @@ def test_track_square_patches(gpu_lib, patch, launch):
     assert rot < ROT_TOL and tr < TR_TOL and rel < COST_TOL
 
 
-@pytest.mark.parametrize("launch", [(1, 256), (2, 256)])
+@pytest.mark.parametrize("launch", [(1, 256), (2, 256), (3, 128)])
 def test_sequence_window_full_size(gpu_lib, launch):
     """752x480, 2000 points, 4 levels, sigma=2 noise: one keyframe window with the
     constant-velocity start, every frame compared with the oracle."""
@@ -241,14 +243,14 @@ def test_sequence_window_full_size(gpu_lib, launch):
 
 
 @pytest.mark.parametrize("seed", [0, 3, 21, 77])
-@pytest.mark.parametrize("chunk", [64, 256])
-def test_mixed_precision_pair(gpu_lib, seed, chunk):
+@pytest.mark.parametrize("mode,chunk", [(2, 64), (2, 256), (3, 128)])
+def test_mixed_precision_pair(gpu_lib, seed, mode, chunk):
     dpt = gpu_lib
-    d, P, trk, ref = _pair_setup(dpt, seed=seed, n=1500, precision=dpt.PREC_MIXED, launch=(2, chunk))
+    d, P, trk, ref = _pair_setup(dpt, seed=seed, n=1500, precision=dpt.PREC_MIXED, launch=(mode, chunk))
     g = trk.track(np.eye(4))
     o = ref.track(d["cur"], np.eye(4))
     rot, tr, rel = _compare(g, o)
-    print(f"mixed seed {seed} chunk {chunk}: rot {rot:.2e} rad, trans {tr:.2e} m, cost {rel:.2e}")
+    print(f"mixed seed {seed} mode {mode} chunk {chunk}: rot {rot:.2e} rad, trans {tr:.2e} m, cost {rel:.2e}")
     assert g["status"] == o["status"] == 0
     assert rot < ROT_TOL and tr < TR_TOL and rel < COST_TOL
 

@@ -59,17 +59,18 @@ VARIANTS = {
 }
 
 
-@pytest.mark.parametrize("variant", list(VARIANTS))
-def test_window_equals_frame_by_frame(gpu_lib, variant):
+@pytest.mark.parametrize("variant,launch", [(v, (0, 256)) for v in VARIANTS] +
+                         [(v, (3, 128)) for v in ("fp32", "mixed", "fixed_h")])
+def test_window_equals_frame_by_frame(gpu_lib, variant, launch):
     import torch
 
     dpt = gpu_lib
     cam, n = synth.CAM_752, 2000
     seq = _sequence(11, cam, 9)
     prm = dpt.make_params(**VARIANTS[variant])
-    a = _tracker(dpt, cam, seq, n, prm)
+    a = _tracker(dpt, cam, seq, n, prm, launch)
     ra = _per_frame(dpt, a, seq["frames"])
-    b = _tracker(dpt, cam, seq, n, prm)
+    b = _tracker(dpt, cam, seq, n, prm, launch)
     b.track_window_enqueue(torch.from_numpy(seq["frames"]).cuda())
     rb = b.synchronize()
     assert len(rb) == 9
@@ -444,7 +445,8 @@ def test_collect_after_synchronous_enqueues(gpu_lib):
     np.testing.assert_array_equal(got[1]["T_cw"], want["T_cw"])
 
 
-@pytest.mark.parametrize("case", ["752x480_2k_fp32", "1280x720_16k_fp32", "1280x720_16k_mixed"])
+@pytest.mark.parametrize("case", ["752x480_2k_fp32", "752x480_2k_fp32_pairs", "752x480_2k_mixed_pairs",
+                                  "1280x720_16k_fp32", "1280x720_16k_mixed"])
 def test_window_full_size_against_oracle(gpu_lib, case):
     """Device frames of a whole keyframe window, every start predicted on the
     GPU, at the full sizes (the 16000-point map spans 63 chunks over several
@@ -454,10 +456,11 @@ def test_window_full_size_against_oracle(gpu_lib, case):
 
     dpt = gpu_lib
     cam, n = (synth.CAM_752, 2000) if case.startswith("752") else (synth.CAM_1280, 16000)
-    mixed = case.endswith("mixed")
+    mixed = "mixed" in case
+    launch = (3, 128) if case.endswith("pairs") else (0, 256)
     seq = _sequence(19, cam, 9)
     prm = dpt.make_params(levels=4, precision=1 if mixed else 0)
-    trk = _tracker(dpt, cam, seq, n, prm)
+    trk = _tracker(dpt, cam, seq, n, prm, launch)
     print(f"{case}: enqueue", flush=True)
     trk.track_window_enqueue(torch.from_numpy(seq["frames"]).cuda())
     rw = trk.synchronize()
