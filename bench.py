@@ -45,7 +45,7 @@ HBM_PEAK_GBS = 8000.0
 # shared by its 8 samples (12 B / 8) and four uint8 bilinear taps
 BYTES_PER_SAMPLE_F32 = 12.0 + 12.0 / 8 + 4.0
 BYTES_PER_SAMPLE_MIXED = 6.0 + 12.0 / 8 + 4.0
-PMC_FILE = os.path.join(ROOT, "profiles", "coop_track_kernel_pmc.json")
+PMC_FILE = os.path.join(ROOT, "profiles", "track_kernels_pmc.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2607_16897_amd", "csrc", f)
                   for f in ("dpt_coop.hip", "dpt_device.h", "dpt_internal.h")]
 
@@ -223,20 +223,18 @@ def frame_track_ms(prof):
 
 
 # ---------------------------------------------------------------- batched legs
-def bench_batched_sequences(dpt, synth, n_streams: int, steps: int, warmup: int, n_win: int = 2):
+def batched_inputs(n_streams: int, n_win: int):
     """n_streams independent sequences of the headline shape, stream s on its own
-    scene and trajectory (seed 2607 + s), tracked together: a step is one
-    keyframe window of every stream.  Returns the FP32 result, and the same
-    frames through the mixed-precision variant under "mixed_precision"."""
+    scene and trajectory (seed 2607 + s), n_win keyframe windows each, resident on
+    the device.  Returns (wins, frames, wframes, depths, T_rw, T_prev, render s)."""
     import torch
 
     t_r = time.perf_counter()
     wins = [make_windows(n_win, seed=2607 + s) for s in range(n_streams)]
     render_s = time.perf_counter() - t_r
-    # device layout: per window, one [streams, H, W] uint8 tensor per frame index and
-    # one [streams, H, W] float32 depth tensor of the keyframes
     # [frame index, stream, H, W] per window: a frame index's images are one
-    # [streams, H, W] block, and a stream's frames sit at a constant stride
+    # [streams, H, W] block, and a stream's frames sit at a constant stride;
+    # one [streams, H, W] float32 depth tensor of the keyframes per window
     stacks = [torch.from_numpy(np.stack([np.stack([wins[s][w]["imgs"][j] for s in range(n_streams)])
                                          for j in range(WINDOW)])).cuda() for w in range(n_win)]
     frames = [[stacks[w][j] for j in range(WINDOW)] for w in range(n_win)]
@@ -246,6 +244,14 @@ def bench_batched_sequences(dpt, synth, n_streams: int, steps: int, warmup: int,
     T_rw = [np.stack([wins[s][w]["gts"][0] for s in range(n_streams)]) for w in range(n_win)]
     T_prev = [np.stack([wins[s][w]["T_prev"] for s in range(n_streams)]) for w in range(n_win)]
     wframes = [[stacks[w][1:, s] for s in range(n_streams)] for w in range(n_win)]
+    return wins, frames, wframes, depths, T_rw, T_prev, render_s
+
+
+def bench_batched_sequences(dpt, synth, n_streams: int, steps: int, warmup: int, n_win: int = 2):
+    """The sequences of batched_inputs tracked together: a step is one keyframe
+    window of every stream.  Returns the FP32 result, and the same frames through
+    the mixed-precision variant under "mixed_precision"."""
+    wins, frames, wframes, depths, T_rw, T_prev, render_s = batched_inputs(n_streams, n_win)
     args = (dpt, wins, frames, wframes, depths, T_rw, T_prev, n_streams, steps, warmup, n_win)
     out = _batched_run(*args, dpt.PREC_FP32, True)
     out["frame_by_frame"] = _batched_run(*args, dpt.PREC_FP32, False, out["launch"])
@@ -335,8 +341,11 @@ def _batched_run(dpt, wins, frames, wframes, depths, T_rw, T_prev, n_streams, st
             "iterations_per_frame": round(float(np.mean(stats["iters"])), 3),
             "status_counts": {str(k): int(v) for k, v in zip(*np.unique(stats["status"], return_counts=True))},
             "pose_error_vs_gt": err_summary(errs),
-            "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(achieved / HBM_PEAK_GBS, 5), "samples_per_launch": round(samp_launch, 1)}}
+            "roofline": {"kernel": track_kernel_name(LAUNCH_NAME.get(mode, "coop"), chunk, window, mixed),
+                         "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 5), "samples_per_launch": round(samp_launch, 1),
+                         "traffic": (traffic_from_profile("batched_mixed" if mixed else "batched_fp32",
+                                                          {"mode": mode, "chunk": chunk}) if window else None)}}
 
 
 def bench_batched_mixed(dpt, synth, n_streams: int, n_frames: int, reps: int):
@@ -432,8 +441,10 @@ def bench_mixed_precision(dpt, synth, wins, dev, steps, launch, chunk):
     out = {"workload": "the headline workload, mixed precision", "frames_per_s": round(steps * (WINDOW - 1) / el, 2),
            "track_ms_per_frame": round(track_ms, 5), "iterations_per_frame": round(float(np.mean(st["iters"])), 3),
            "pose_error_vs_gt": err_summary([pose_error(T, G) for T, G in zip(st["T"], st["gt"])]),
-           "roofline": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS, "achieved": round(achieved, 3),
-                        "frac": round(achieved / HBM_PEAK_GBS, 6)}}
+           "roofline": {"kernel": track_kernel_name(LAUNCH_NAME[launch], chunk, True, mixed=True), "bound": "hbm",
+                        "unit": "GB/s", "peak": HBM_PEAK_GBS, "achieved": round(achieved, 3),
+                        "frac": round(achieved / HBM_PEAK_GBS, 6),
+                        "traffic": traffic_from_profile("mixed", {"mode": launch, "chunk": chunk})}}
     return out, st
 
 
@@ -455,7 +466,8 @@ def bench_fixed_h(dpt, synth, wins, dev, steps, launch, chunk):
            "roofline": {"kernel": track_kernel_name(LAUNCH_NAME[launch], chunk, True, fixed=True), "bound": "hbm",
                         "unit": "GB/s",
                         "peak": HBM_PEAK_GBS, "achieved": round(achieved, 3),
-                        "frac": round(achieved / HBM_PEAK_GBS, 6)}}
+                        "frac": round(achieved / HBM_PEAK_GBS, 6),
+                        "traffic": traffic_from_profile("fixed", {"mode": launch, "chunk": chunk})}}
     return out, st
 
 
@@ -479,9 +491,10 @@ def bench_paper_shape(dpt, synth, wins, dev, steps):
            "samples_per_frame": round(samp, 1),
            "status_counts": {str(k): int(v) for k, v in zip(*np.unique(st["status"], return_counts=True))},
            "pose_error_vs_gt": err_summary([pose_error(T, G) for T, G in zip(st["T"], st["gt"])]),
-           "roofline": {"kernel": "coop_track_kernel<256, false, false, true, float, false>", "bound": "hbm",
+           "roofline": {"kernel": "coop_track_kernel<256, false, false, true, float, false, 1>", "bound": "hbm",
                         "unit": "GB/s", "peak": HBM_PEAK_GBS, "bytes_per_sample": round(bps, 3),
-                        "achieved": round(achieved, 3), "frac": round(achieved / HBM_PEAK_GBS, 6)}}
+                        "achieved": round(achieved, 3), "frac": round(achieved / HBM_PEAK_GBS, 6),
+                        "traffic": traffic_from_profile("paper", {"mode": dpt.LAUNCH_AUTO, "chunk": 256})}}
     return out, st
 
 
@@ -683,47 +696,120 @@ def cpu_baseline(wins, seconds: float, comparisons, tween_run=None):
     return out, diffs
 
 
-def traffic_from_profile(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC summary,
-    or None if the kernel sources changed since the counters were taken."""
+def traffic_from_profile(leg, launch=None):
+    """HBM bytes per track launch of a leg from the committed rocprofv3 PMC summary
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None if there is none for the
+    leg, the kernel sources changed since the counters were taken, or the leg now
+    runs another launch configuration than the profiled one."""
     if not os.path.exists(PMC_FILE):
         return None
-    d = json.load(open(PMC_FILE))
-    if d.get("kernel_source_sha") != kernel_source_hash() or d.get("kernel") != kernel:
+    e = json.load(open(PMC_FILE)).get("legs", {}).get(leg)
+    if not e or e.get("kernel_source_sha") != kernel_source_hash():
         return None
-    return d.get("bytes_per_launch")
+    if launch is not None and e.get("launch") != launch:
+        return None
+    return e.get("bytes_per_launch")
 
 
-HEADLINE_KERNEL = "coop_track_kernel<256, false, false, false, unsigned char, true>"
+# legs a --pmc-leg run can isolate: their track launches and nothing else of the bench
+PMC_LEGS = ("headline", "headline_frame", "mixed", "fixed", "paper", "batched_fp32", "batched_mixed")
 
 
-def pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, kernel=HEADLINE_KERNEL):
-    """HBM bytes per launch of `kernel` from two rocprofv3 --pmc runs (FETCH_SIZE,
-    WRITE_SIZE; KiB per dispatch), each scaled by what the same counter reads for
-    the plain copy of --calibrate-copy (bytes moved / counter bytes).  Writes the
+def pmc_leg(args, leg, meta_path):
+    """Runs only `leg`'s track launches (warmup + steps keyframe windows, the
+    launch configuration the bench measures the leg with), for rocprofv3 --pmc
+    runs, and writes how many track launches it made to meta_path."""
+    import torch
+
+    import paper_2607_16897_amd as dpt
+    import synth
+
+    global CAM
+    CAM = synth.CAM_752
+    dpt.load()
+    torch.cuda.set_device(0)
+    launch = {"auto": dpt.LAUNCH_AUTO, "coop": dpt.LAUNCH_COOP, "pairs": dpt.LAUNCH_COOP_PAIRS}[args.launch]
+    n_win = args.steps + args.warmup
+    if leg.startswith("batched"):
+        mode, chunk = args.batch_launch
+        wins, frames, wframes, depths, T_rw, T_prev, _ = batched_inputs(args.batch_streams, 2)
+        prec = dpt.PREC_MIXED if leg == "batched_mixed" else dpt.PREC_FP32
+        _batched_run(dpt, wins, frames, wframes, depths, T_rw, T_prev, args.batch_streams, args.steps, args.warmup,
+                     2, prec, True, {"mode": mode, "chunk": chunk, "autotune_ms": None})
+        launches = n_win
+    else:
+        wins = make_windows(min(n_win, 24))
+        dev = to_device(wins)
+        kw = dict(levels=LEVELS, max_iters=10, huber_k=9.0, step_eps=1e-5)
+        window, mode, chunk = leg != "headline_frame", launch, args.chunk
+        if leg == "mixed":
+            kw["precision"] = dpt.PREC_MIXED
+        elif leg == "fixed":
+            kw["fixed_h"] = True
+        elif leg == "paper":
+            kw.update(levels=6, gauss=True, pattern=synth.square_pattern(7))
+            window, mode, chunk = False, dpt.LAUNCH_AUTO, 256
+        timed_plain(dpt, synth, wins, dev, args.steps, args.warmup, dpt.make_params(**kw), mode, chunk,
+                    window=window)
+        launches = n_win * (1 if window else WINDOW - 1)
+    torch.cuda.synchronize()
+    with open(meta_path, "w") as f:
+        json.dump({"leg": leg, "launches": launches, "launch": {"mode": mode, "chunk": chunk},
+                   "steps": args.steps, "warmup": args.warmup}, f)
+    print(f"# pmc leg {leg}: {launches} track launches", file=sys.stderr, flush=True)
+
+
+def pmc_summary(leg, meta_path, copy_fetch_dir, copy_write_dir, *dirs):
+    """Per track launch of `leg`: every counter that the rocprofv3 --pmc runs in
+    `dirs` took on the track kernels (summed over the launch's dispatches: a batch
+    track is one dispatch per launch group), with FETCH_SIZE and WRITE_SIZE (KiB)
+    turned into HBM bytes by the factor the same counter reads for the plain copy
+    of --calibrate-copy (bytes moved / counter bytes).  Adds the leg to the
     summary the roofline's `traffic` field reads and prints it."""
     import csv
     import glob
 
-    def rows(d, counter):
+    meta = json.load(open(meta_path))
+    if meta["leg"] != leg:
+        raise SystemExit(f"{meta_path} describes leg {meta['leg']}, not {leg}")
+
+    def rows(d):
         f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
-        return [r for r in csv.DictReader(open(f)) if r["Counter_Name"] == counter]
+        return list(csv.DictReader(open(f)))
 
     def copy_factor(d, counter):
-        rs = [r for r in rows(d, counter) if "copyBuffer" in r["Kernel_Name"]]
-        nbytes = float(np.median([float(r["Counter_Value"]) for r in rs])) * 1024.0
-        return COPY_MIB * (1 << 20) / nbytes
+        v = [float(r["Counter_Value"]) for r in rows(d) if r["Counter_Name"] == counter and "copyBuffer" in
+             r["Kernel_Name"]]
+        return COPY_MIB * (1 << 20) / (float(np.median(v)) * 1024.0)
 
-    ff, wf = copy_factor(copy_fetch_dir, "FETCH_SIZE"), copy_factor(copy_write_dir, "WRITE_SIZE")
-    fk = [float(r["Counter_Value"]) for r in rows(fetch_dir, "FETCH_SIZE") if kernel in r["Kernel_Name"]]
-    wk = [float(r["Counter_Value"]) for r in rows(write_dir, "WRITE_SIZE") if kernel in r["Kernel_Name"]]
-    fetch_b, write_b = float(np.mean(fk)) * 1024.0 * ff, float(np.mean(wk)) * 1024.0 * wf
-    out = {"kernel": kernel, "dispatches": [len(fk), len(wk)], "fetch_kib_per_dispatch_raw": float(np.mean(fk)),
-           "write_kib_per_dispatch_raw": float(np.mean(wk)), "copy_scale": {"fetch": ff, "write": wf},
-           "fetch_bytes_per_launch": fetch_b, "write_bytes_per_launch": write_b,
-           "bytes_per_launch": fetch_b + write_b, "kernel_source_sha": kernel_source_hash()}
+    launches = meta["launches"]
+    per_launch, kernels = {}, {}
+    for d in dirs:
+        for r in rows(d):
+            if "track" not in r["Kernel_Name"]:
+                continue
+            c = r["Counter_Name"]
+            per_launch[c] = per_launch.get(c, 0.0) + float(r["Counter_Value"]) / launches
+            k = kernels.setdefault(r["Kernel_Name"], {})
+            k.setdefault(c, set()).add((r["Dispatch_Id"], r["Grid_Size"]))
+    disp = {name: {"dispatches": max(len(v) for v in k.values()),
+                   "grid_sizes": sorted({int(g) for v in k.values() for _, g in v})} for name, k in kernels.items()}
+    out = {"leg": leg, "launch": meta["launch"], "launches": launches, "kernels": disp,
+           "counters_per_launch": {c: round(v, 3) for c, v in sorted(per_launch.items())},
+           "kernel_source_sha": kernel_source_hash()}
+    if "FETCH_SIZE" in per_launch and "WRITE_SIZE" in per_launch:
+        ff, wf = copy_factor(copy_fetch_dir, "FETCH_SIZE"), copy_factor(copy_write_dir, "WRITE_SIZE")
+        out["copy_scale"] = {"fetch": ff, "write": wf}
+        out["fetch_bytes_per_launch"] = per_launch["FETCH_SIZE"] * 1024.0 * ff
+        out["write_bytes_per_launch"] = per_launch["WRITE_SIZE"] * 1024.0 * wf
+        out["bytes_per_launch"] = out["fetch_bytes_per_launch"] + out["write_bytes_per_launch"]
+    hit, miss = per_launch.get("TCC_HIT_sum"), per_launch.get("TCC_MISS_sum")
+    if hit is not None and miss is not None and hit + miss > 0:
+        out["l2_hit_rate"] = round(hit / (hit + miss), 5)
+    summary = json.load(open(PMC_FILE)) if os.path.exists(PMC_FILE) else {}
+    summary.setdefault("legs", {})[leg] = out
     with open(PMC_FILE, "w") as f:
-        json.dump(out, f, indent=1)
+        json.dump(summary, f, indent=1)
     print(json.dumps(out))
 
 
@@ -856,8 +942,14 @@ def main():
     ap.add_argument("--only-headline", action="store_true", help="skip the batched, precision, fixed-H and initialiser legs")
     ap.add_argument("--legs", default="mixed,fixed,paper,tween,batched,init",
                     help="legs after the headline: any of mixed, fixed, paper, tween, batched, init (comma separated)")
-    ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
-                    help="write the track kernel's HBM traffic per launch from rocprofv3 --pmc output and exit")
+    ap.add_argument("--batch-launch", nargs=2, type=int, default=[2, 256], metavar=("MODE", "CHUNK"),
+                    help="launch configuration of the batched legs under --pmc-leg (the bench tunes it)")
+    ap.add_argument("--pmc-leg", choices=PMC_LEGS,
+                    help="run only this leg's track launches (for rocprofv3 --pmc) and exit")
+    ap.add_argument("--pmc-meta", default="pmc_meta.json", help="where --pmc-leg writes its launch count")
+    ap.add_argument("--pmc-summary", nargs="+", metavar="ARG",
+                    help="LEG META COPY_FETCH_DIR COPY_WRITE_DIR DIR...: add the leg's per-launch counters (HBM "
+                         "traffic from FETCH_SIZE / WRITE_SIZE) from rocprofv3 --pmc output to the summary and exit")
     ap.add_argument("--cycle-split", action="store_true",
                     help="per-phase cycles per Gauss-Newton iteration from the instrumented library "
                          "(libdptrack_cycles.so) on the headline workload (and the batch with --legs batched); "
@@ -872,7 +964,12 @@ def main():
         calibrate_copy(args.calibrate_copy)
         return
     if args.pmc_summary:
+        if len(args.pmc_summary) < 5:
+            ap.error("--pmc-summary takes LEG META COPY_FETCH_DIR COPY_WRITE_DIR and at least one DIR")
         pmc_summary(*args.pmc_summary)
+        return
+    if args.pmc_leg:
+        pmc_leg(args, args.pmc_leg, args.pmc_meta)
         return
     legs = set() if args.only_headline else set(x for x in args.legs.split(",") if x)
     if args.cycle_split:
@@ -949,7 +1046,8 @@ def main():
         "samples_per_s": round(samples / elapsed, 1),
         "roofline": {"kernel": kname, "bound": "hbm", "achieved": round(achieved, 3),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
-                     "traffic": traffic_from_profile(kname),
+                     "traffic": traffic_from_profile("headline" if window else "headline_frame",
+                                                     {"mode": launch, "chunk": args.chunk}),
                      "attainable_copy": round(att_gbs, 1), "frac_of_attainable": round(achieved / att_gbs, 6),
                      "bytes_per_launch_algorithmic": round(alg_bytes, 1), "samples_per_launch": round(samp_launch, 1),
                      "frames_per_launch": fpl, "avg_launch_ms": round(launch_ms, 5),
