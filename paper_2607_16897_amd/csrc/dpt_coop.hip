@@ -521,6 +521,7 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
         if (threadIdx.x == 40) sh_fac[l & 1][27] = fh.bad ? 1.0f : 0.0f;
       }
       bool converged = false;
+      const int it0 = iterations;
       for (int it = 0; it < a.max_iters; ++it) {
         uint64_t c0 = 0, c1 = 0, c2 = 0;
         if constexpr (kCycleProfile) c0 = clock64();
@@ -542,7 +543,7 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
         if constexpr (kCycleProfile) c3 = clock64();
         ++tag;
         // the 8-pixel kernels count samples as 8 per point outside the final pass
-        samples += GENERIC ? (int64_t)sh_tot[sN] : 8 * (int64_t)sh_tot[sP];
+        samples += GENERIC ? (int64_t)(int)sh_tot[sN] : 8 * (int64_t)(int)sh_tot[sP];  // counts < 2^24: exact
         if ((int)sh_tot[sP] < a.min_points) {
           status = 2;  // too few points
           stop = true;
@@ -576,13 +577,13 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
           break;
         }
         ++iterations;
-#pragma unroll
-        for (int j = 0; j < kMaxLevels; ++j) ipl[j] += j == l;
         if (step < (double)a.step_eps) {
           converged = true;
           break;
         }
       }
+#pragma unroll
+      for (int j = 0; j < kMaxLevels; ++j) ipl[j] = j == l ? iterations - it0 : ipl[j];
       if (!stop && l == 0 && !converged) status = 1;  // iteration cap at level 0
     }
     if (!timed_out) {  // final cost-only pass at level 0

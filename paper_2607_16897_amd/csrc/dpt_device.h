@@ -379,6 +379,36 @@ __device__ __forceinline__ void block_reduce32_kahan(float (&a)[32], float* scra
 // Index of H(i, j), i <= j, in the row-major upper-triangle order of the sums.
 __host__ __device__ constexpr int tri(int i, int j) { return i * 6 - (i * (i - 1)) / 2 + (j - i); }
 
+// T <- T exp(xi) for the twist xi = (w, v) (rotation part first) of squared
+// angle th2 = |w|^2, given the coefficients A = sin(th) / th,
+// B = (1 - cos th) / th^2 and C = (th - sin th) / th^3 of the SE(3) exponential:
+// R = I + A [w]x + B [w]x^2 and t = (I + B [w]x + C [w]x^2) v.  With
+// [w]x^2 = w w^T - th2 I and [w]x v = w x v these are written out entry by
+// entry: R = (1 - B th2) I + A [w]x + B w w^T, t = (1 - C th2) v + B (w x v)
+// + C (w.v) w.  F = float or double; every product is an explicit FMA.
+template <class F>
+__device__ __forceinline__ void compose_exp(F* T, F w0, F w1, F w2, F v0, F v1, F v2, F th2, F A, F B, F C) {
+  const F Bw0 = B * w0, Bw1 = B * w1, Bw2 = B * w2, Aw0 = A * w0, Aw1 = A * w1, Aw2 = A * w2;
+  const F dg = fma(-B, th2, F(1));
+  const F E[3][4] = {
+      {fma(Bw0, w0, dg), fma(Bw0, w1, -Aw2), fma(Bw0, w2, Aw1), F(0)},
+      {fma(Bw0, w1, Aw2), fma(Bw1, w1, dg), fma(Bw1, w2, -Aw0), F(0)},
+      {fma(Bw0, w2, -Aw1), fma(Bw1, w2, Aw0), fma(Bw2, w2, dg), F(0)}};
+  const F c0 = fma(w1, v2, -(w2 * v1)), c1 = fma(w2, v0, -(w0 * v2)), c2 = fma(w0, v1, -(w1 * v0));
+  const F Cwv = C * fma(w0, v0, fma(w1, v1, w2 * v2)), Cv = fma(-C, th2, F(1));
+  const F t[3] = {fma(B, c0, fma(Cwv, w0, Cv * v0)), fma(B, c1, fma(Cwv, w1, Cv * v1)),
+                  fma(B, c2, fma(Cwv, w2, Cv * v2))};
+  F N[12];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) N[4 * r + c] = fma(T[4 * r], E[0][c], fma(T[4 * r + 1], E[1][c], T[4 * r + 2] * E[2][c]));
+    N[4 * r + 3] = fma(T[4 * r], t[0], fma(T[4 * r + 1], t[1], fma(T[4 * r + 2], t[2], T[4 * r + 3])));
+  }
+#pragma unroll
+  for (int j = 0; j < 12; ++j) T[j] = N[j];
+}
+
 // With H = L L^T given by its factor (L(i, j), i >= j, at tri(j, i), and
 // invd = 1 / diag(L)), solve H delta = b by forward and back substitution and
 // apply T <- T exp(-delta) in FP32; *max_step = max_j |delta_j|.
@@ -458,10 +488,8 @@ __device__ __forceinline__ void substitute_update(const float (&L)[21], const fl
 #pragma unroll
   for (int j = 0; j < 6; ++j) m = fmaxf(m, fabsf(d[j]));
   *max_step = m;
-  // exp(xi), xi = -delta = (w, v): R = I + A[w] + B[w]^2, t = (I + B[w] + C[w]^2) v
   const float w0 = -d[0], w1 = -d[1], w2 = -d[2];
-  const float vv[3] = {-d[3], -d[4], -d[5]};
-  const float th2 = w0 * w0 + w1 * w1 + w2 * w2;
+  const float th2 = fmaf(w0, w0, fmaf(w1, w1, w2 * w2));
   float A, B, C;
   if (th2 < 0.0025f) {  // |w| < 0.05
     A = 1.0f - th2 * (1.0f / 6.0f) * (1.0f - th2 * (1.0f / 20.0f));
@@ -474,30 +502,7 @@ __device__ __forceinline__ void substitute_update(const float (&L)[21], const fl
     B = 2.0f * sh * sh / th2;
     C = (th - sn) / (th2 * th);
   }
-  const float W[3][3] = {{0.f, -w2, w1}, {w2, 0.f, -w0}, {-w1, w0, 0.f}};
-  float E[3][4];
-#pragma unroll
-  for (int r = 0; r < 3; ++r) {
-    float tv = 0.f;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const float W2 = W[r][0] * W[0][c] + W[r][1] * W[1][c] + W[r][2] * W[2][c];
-      const float id = (r == c) ? 1.0f : 0.0f;
-      E[r][c] = id + A * W[r][c] + B * W2;
-      tv += (id + B * W[r][c] + C * W2) * vv[c];
-    }
-    E[r][3] = tv;
-  }
-  float N[12];
-#pragma unroll
-  for (int r = 0; r < 3; ++r) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-      N[4 * r + c] = fmaf(T[4 * r], E[0][c], fmaf(T[4 * r + 1], E[1][c], T[4 * r + 2] * E[2][c]));
-    N[4 * r + 3] = fmaf(T[4 * r], E[0][3], fmaf(T[4 * r + 1], E[1][3], fmaf(T[4 * r + 2], E[2][3], T[4 * r + 3])));
-  }
-#pragma unroll
-  for (int j = 0; j < 12; ++j) T[j] = N[j];
+  compose_exp(T, w0, w1, w2, -d[3], -d[4], -d[5], th2, A, B, C);
 }
 
 // FP64 variant of solve_update: Cholesky solve (pivot <= 1e-12 of the largest
@@ -553,13 +558,16 @@ __device__ __forceinline__ int solve_update_d(const float* tot_lds, double* T, d
   for (int j = 0; j < 6; ++j) m = fmax(m, fabs(d[j]));
   *max_step = m;
   const double w0 = -d[0], w1 = -d[1], w2 = -d[2];
-  const double vv[3] = {-d[3], -d[4], -d[5]};
-  const double th2 = w0 * w0 + w1 * w1 + w2 * w2;
+  const double th2 = fma(w0, w0, fma(w1, w1, w2 * w2));
   double A, B, C;
   if (th2 < 0.0025) {  // |w| < 0.05: series through th^8, truncation below 1e-20
-    A = 1.0 - th2 / 6.0 * (1.0 - th2 / 20.0 * (1.0 - th2 / 42.0 * (1.0 - th2 / 72.0)));
-    B = 0.5 * (1.0 - th2 / 12.0 * (1.0 - th2 / 30.0 * (1.0 - th2 / 56.0 * (1.0 - th2 / 90.0))));
-    C = (1.0 - th2 / 20.0 * (1.0 - th2 / 42.0 * (1.0 - th2 / 72.0 * (1.0 - th2 / 110.0)))) / 6.0;
+    A = fma(-th2 * (1.0 / 6.0), fma(-th2 * (1.0 / 20.0), fma(-th2 * (1.0 / 42.0), fma(-th2, 1.0 / 72.0, 1.0), 1.0), 1.0),
+            1.0);
+    B = 0.5 * fma(-th2 * (1.0 / 12.0),
+                  fma(-th2 * (1.0 / 30.0), fma(-th2 * (1.0 / 56.0), fma(-th2, 1.0 / 90.0, 1.0), 1.0), 1.0), 1.0);
+    C = (1.0 / 6.0) * fma(-th2 * (1.0 / 20.0),
+                          fma(-th2 * (1.0 / 42.0), fma(-th2 * (1.0 / 72.0), fma(-th2, 1.0 / 110.0, 1.0), 1.0), 1.0),
+                          1.0);
   } else {
     const double th = sqrt(th2);
     const double sn = sin(th), sh = sin(0.5 * th);
@@ -567,29 +575,7 @@ __device__ __forceinline__ int solve_update_d(const float* tot_lds, double* T, d
     B = 2.0 * sh * sh / th2;
     C = (th - sn) / (th2 * th);
   }
-  const double W[3][3] = {{0.0, -w2, w1}, {w2, 0.0, -w0}, {-w1, w0, 0.0}};
-  double E[3][4];
-#pragma unroll
-  for (int r = 0; r < 3; ++r) {
-    double tv = 0.0;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const double W2 = W[r][0] * W[0][c] + W[r][1] * W[1][c] + W[r][2] * W[2][c];
-      const double id = (r == c) ? 1.0 : 0.0;
-      E[r][c] = id + A * W[r][c] + B * W2;
-      tv += (id + B * W[r][c] + C * W2) * vv[c];
-    }
-    E[r][3] = tv;
-  }
-  double N[12];
-#pragma unroll
-  for (int r = 0; r < 3; ++r) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) N[4 * r + c] = T[4 * r] * E[0][c] + T[4 * r + 1] * E[1][c] + T[4 * r + 2] * E[2][c];
-    N[4 * r + 3] = T[4 * r] * E[0][3] + T[4 * r + 1] * E[1][3] + T[4 * r + 2] * E[2][3] + T[4 * r + 3];
-  }
-#pragma unroll
-  for (int j = 0; j < 12; ++j) T[j] = N[j];
+  compose_exp(T, w0, w1, w2, -d[3], -d[4], -d[5], th2, A, B, C);
   return 0;
 }
 
