@@ -194,7 +194,7 @@ int dpt_set_reference_from_depth(dpt_ctx* ctx, int32_t n, int32_t margin, const 
 int dpt_track_frame(dpt_ctx* ctx, const double T_cw_init[16], dpt_result* out);
 
 /* Start pose of an enqueued track. */
-enum { DPT_INIT_GIVEN = 0, DPT_INIT_CONST_VELOCITY = 1 };
+enum { DPT_INIT_GIVEN = 0, DPT_INIT_CONST_VELOCITY = 1, DPT_INIT_PROPOSED = 2 };
 
 /* Most tracks (frames) enqueued and not yet synchronised, per context or batch. */
 #define DPT_MAX_IN_FLIGHT 256
@@ -205,10 +205,12 @@ enum { DPT_INIT_GIVEN = 0, DPT_INIT_CONST_VELOCITY = 1 };
  * between them (the paper keeps the tracker on the GPU to avoid CPU-GPU
  * exchange, Sec. IV-C).  The start pose is T_cw_init (DPT_INIT_GIVEN) or the
  * constant-velocity prediction T1 T0^-1 T1 from the context's pose history
- * (DPT_INIT_CONST_VELOCITY, computed on the GPU in FP64; T_cw_init may be NULL).
+ * (DPT_INIT_CONST_VELOCITY, computed on the GPU in FP64; T_cw_init may be NULL),
+ * or the learned initialiser's proposal that the last dpt_cnn_propose on this
+ * context left in device memory (DPT_INIT_PROPOSED; DPT_E_STATE if none).
  * The history holds the last two poses: dpt_set_pose_history sets it, and every
  * track on the cooperative path appends its result.  The constant-velocity
- * start needs that path (launch mode AUTO or COOP; DPT_E_ARG
+ * start and the proposed one need that path (launch mode AUTO or COOP; DPT_E_ARG
  * otherwise); on the one-workgroup path a DPT_INIT_GIVEN enqueue runs
  * synchronously.  *out is written by the next dpt_synchronize (or any call
  * that synchronises the context) and must stay valid until then.  At most
@@ -489,7 +491,9 @@ int dpt_batch_track(dpt_batch* b, const double* T_cw_init, dpt_result* out);
 
 /* As dpt_track_enqueue / dpt_synchronize / dpt_set_pose_history, for every
  * stream of the batch (T_cw_init: n_streams row-major 4x4 doubles, may be NULL
- * with DPT_INIT_CONST_VELOCITY; out: n_streams results) or for stream `s`. */
+ * with DPT_INIT_CONST_VELOCITY or DPT_INIT_PROPOSED, the latter starting every
+ * stream from the last dpt_cnn_propose_batch; out: n_streams results) or for
+ * stream `s`. */
 int dpt_batch_track_enqueue(dpt_batch* b, int32_t init_mode, const double* T_cw_init, dpt_result* out);
 int dpt_batch_synchronize(dpt_batch* b);
 /* As dpt_collect / dpt_tracks_in_flight: the oldest n batched tracks (each
@@ -530,7 +534,8 @@ int dpt_batch_get_profile(dpt_batch* b, double* pyramid_ms, int64_t* n_pyramid, 
  * Network: conv 3x3 stride 2 pad 1 + ReLU, 2-16-32-64-64 channels; global
  * average pool; FC 64-64 + ReLU; FC 64-6.  Output: the twist (omega, v) divided
  * by (5 deg x3, 0.1 m x3).  BF16 activations and conv weights, FP32 master
- * weights, matrix-core (MFMA) forward convolutions with FP32 accumulation.
+ * weights; the forward and backward convolutions run on the matrix cores
+ * (MFMA, FP32 accumulation), the gradients between layers are BF16.
  * Parameters (dpt_cnn_num_params() floats) in tensor order w1 b1 w2 b2 w3 b3 w4
  * b4 fw1 fb1 fw2 fb2, conv weights [co][ci][ky][kx], FC weights [out][in]. */
 typedef struct dpt_cnn dpt_cnn;
@@ -560,6 +565,19 @@ int dpt_cnn_get_activation(dpt_cnn* c, int32_t l, int32_t B, float* host_out);
  * T_cw = exp(xi) T_rw (4x4 row-major doubles per stream). */
 int dpt_cnn_predict(dpt_cnn* c, dpt_ctx* ctx, double T_cw_out[16]);
 int dpt_cnn_predict_batch(dpt_cnn* c, dpt_batch* b, double* T_cw_out);
+/* The same proposal without a host round trip: enqueued on the context's (the
+ * batch's) stream, the forward pass on the coarsest REF and CUR levels and the
+ * exponential of each twist (FP64), kept in device memory as the start of the
+ * next dpt_track_enqueue / dpt_batch_track_enqueue with DPT_INIT_PROPOSED.  The
+ * levels are read when the stream reaches the call, so a CUR pyramid built
+ * before it on the same stream is the one proposed from.  The network's
+ * buffers are used on that stream: the CNN must not run concurrently on
+ * another one.  The first call on a context or batch allocates its proposal
+ * buffer and uploads its level pointer table (a synchronous copy); later calls
+ * neither allocate nor wait.  DPT_E_STATE if a pyramid or the reference is
+ * missing, DPT_E_ARG if the coarsest level is not 94 x 60. */
+int dpt_cnn_propose(dpt_cnn* c, dpt_ctx* ctx);
+int dpt_cnn_propose_batch(dpt_cnn* c, dpt_batch* b);
 
 #ifdef __cplusplus
 }

@@ -27,7 +27,7 @@ FLAG_FIXED_H = 1  # dpt_params.flags: the paper's constant-H track
 FLAG_GAUSS_F32 = 2  # dpt_params.flags: track on the floating-point Gaussian pyramid
 SLOT_REF, SLOT_CUR = 0, 1
 LAUNCH_AUTO, LAUNCH_WORKGROUP, LAUNCH_COOP, LAUNCH_COOP_PAIRS = 0, 1, 2, 3
-INIT_GIVEN, INIT_CONST_VELOCITY = 0, 1
+INIT_GIVEN, INIT_CONST_VELOCITY, INIT_PROPOSED = 0, 1, 2
 MAX_WINDOW = 32  # most frames one window track covers
 MAX_IN_FLIGHT = 256  # most tracks enqueued and not yet synchronised
 DEFAULT_PATTERN = ((-2, 0), (2, 0), (0, -2), (0, 2), (-1, -1), (1, -1), (-1, 1), (1, 1))
@@ -158,6 +158,8 @@ SIGNATURES = {
     "dpt_cnn_get_activation": (ctypes.c_int, [_vp, _i32, _i32, _vp]),
     "dpt_cnn_predict": (ctypes.c_int, [_vp, _vp, _vp]),
     "dpt_cnn_predict_batch": (ctypes.c_int, [_vp, _vp, _vp]),
+    "dpt_cnn_propose": (ctypes.c_int, [_vp, _vp]),
+    "dpt_cnn_propose_batch": (ctypes.c_int, [_vp, _vp]),
     "dpt_last_kernel_ms": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
 }
 
@@ -399,12 +401,15 @@ class Tracker:
         return dict(decision=r.decision, direct_since_ref=r.direct_since_ref, tracked=bool(r.tracked),
                     baseline=r.baseline, track=r.track.as_dict() if r.tracked else None)
 
-    def track_enqueue(self, T_cw_init=None):
-        """Enqueue a track without waiting: from T_cw_init, or (None) from the
-        constant-velocity prediction of the pose history.  Results come back, in
+    def track_enqueue(self, T_cw_init=None, proposed: bool = False):
+        """Enqueue a track without waiting: from T_cw_init, (None) from the
+        constant-velocity prediction of the pose history, or (proposed=True) from
+        the learned proposal of the last Cnn.propose(self).  Results come back, in
         order, from synchronize()."""
         r = Result()
-        if T_cw_init is None:
+        if proposed:
+            _check(self._lib.dpt_track_enqueue(self._h, INIT_PROPOSED, None, ctypes.byref(r)))
+        elif T_cw_init is None:
             _check(self._lib.dpt_track_enqueue(self._h, INIT_CONST_VELOCITY, None, ctypes.byref(r)))
         else:
             _check(self._lib.dpt_track_enqueue(self._h, INIT_GIVEN, _mat(T_cw_init), ctypes.byref(r)))
@@ -620,11 +625,14 @@ class BatchTracker:
         _check(self._lib.dpt_batch_track(self._h, T.ctypes.data, ctypes.cast(res, _vp)))
         return [r.as_dict() for r in res]
 
-    def track_enqueue(self, T_cw_init=None):
+    def track_enqueue(self, T_cw_init=None, proposed: bool = False):
         """Enqueue a track of every stream without waiting: from T_cw_init (n x 4 x 4),
-        or (None) from each stream's constant-velocity prediction."""
+        (None) from each stream's constant-velocity prediction, or (proposed=True)
+        from the learned proposals of the last Cnn.propose(self)."""
         res = (Result * self.n)()
-        if T_cw_init is None:
+        if proposed:
+            _check(self._lib.dpt_batch_track_enqueue(self._h, INIT_PROPOSED, None, ctypes.cast(res, _vp)))
+        elif T_cw_init is None:
             _check(self._lib.dpt_batch_track_enqueue(self._h, INIT_CONST_VELOCITY, None, ctypes.cast(res, _vp)))
         else:
             T = np.ascontiguousarray(np.asarray(T_cw_init, np.float64).reshape(self.n, 16))
@@ -863,6 +871,14 @@ class Cnn:
         out = np.empty((B,) + shapes[layer], np.float32)
         _check(self._lib.dpt_cnn_get_activation(self._h, layer, B, out.ctypes.data))
         return out
+
+    def propose(self, tracker):
+        """Enqueue the learned start of a Tracker or every stream of a BatchTracker
+        on its stream, kept on the device for track_enqueue(proposed=True)."""
+        if isinstance(tracker, BatchTracker):
+            _check(self._lib.dpt_cnn_propose_batch(self._h, tracker._h))
+        else:
+            _check(self._lib.dpt_cnn_propose(self._h, tracker._h))
 
     def predict(self, tracker) -> np.ndarray:
         """Start pose(s) T_cw from a Tracker (4x4) or a BatchTracker (n x 4 x 4)."""

@@ -295,6 +295,9 @@ struct dpt_ctx {
   CoopEngine eng;
   bool eng_ready = false;
   double* d_hist = nullptr;  // pose history: the last two T_cw, 2 x 3x4 FP64 (device)
+  double* d_prop = nullptr;  // learned start proposal relative to the reference, 3x4 FP64 (device)
+  const uint8_t** d_cnn_lv = nullptr;  // the coarsest reference and current levels, for the proposal
+  bool have_prop = false;
   std::vector<std::pair<int, dpt_result*>> pending;  // tracks in flight: (ring slot, caller's result)
   int slot_next = 0;
   // window tracking: box pyramids of up to win_cap consecutive frames
@@ -313,6 +316,8 @@ struct dpt_ctx {
     prof_pyr.destroy();
     prof_trk.destroy();
     if (d_hist) (void)hipFree(d_hist);
+    if (d_prop) (void)hipFree(d_prop);
+    if (d_cnn_lv) (void)hipFree(d_cnn_lv);
     if (ev_pts) (void)hipEventDestroy(ev_pts);
     if (h_pts) (void)hipHostFree(h_pts);
     if (h_sel) (void)hipHostFree(h_sel);
@@ -836,10 +841,11 @@ int ensure_engine(dpt_ctx* c) {
 }
 
 // Start slot of one stream for the context's current reference.
-void fill_start(const dpt_ctx* c, int mode, const double* T_cw_init, StartSlot* st) {
+void fill_start(const dpt_ctx* c, int mode, const double* T_cw_init, StartSlot* st, const double* dev_rel = nullptr) {
   std::memset(st, 0, sizeof *st);
   st->mode = mode;
   if (mode == kStartGiven) rel_pose_f32(c, T_cw_init, st->T_rel);
+  st->dev_rel = dev_rel;
   for (int j = 0; j < 12; ++j) st->T_rw[j] = c->T_rw[j];
 }
 
@@ -873,7 +879,7 @@ int enqueue_coop(dpt_ctx* c, int mode, const double* T_cw_init, dpt_result* out)
   if (e != DPT_OK) return e;
   const int slot = c->slot_next;
   c->slot_next = (slot + 1) % kRing;
-  fill_start(c, mode, T_cw_init, c->eng.start(slot));
+  fill_start(c, mode, T_cw_init, c->eng.start(slot), c->d_prop);
   int ps = -1;
   if (c->prof) HIP_TRY(c->prof_trk.begin(c->stream, &ps));
   HIP_TRY(c->eng.launch(c->spin_limit, slot));
@@ -1076,20 +1082,25 @@ int dpt_track_frame(dpt_ctx* c, const double T_cw_init[16], dpt_result* out) {
 int dpt_track_enqueue(dpt_ctx* c, int32_t init_mode, const double T_cw_init[16], dpt_result* out) {
   g_err.clear();
   if (!c || !out) return fail(DPT_E_ARG, "NULL argument");
-  if (init_mode != DPT_INIT_GIVEN && init_mode != DPT_INIT_CONST_VELOCITY)
+  if (init_mode != DPT_INIT_GIVEN && init_mode != DPT_INIT_CONST_VELOCITY && init_mode != DPT_INIT_PROPOSED)
     return fail(DPT_E_ARG, "init_mode %d", init_mode);
   if (init_mode == DPT_INIT_GIVEN && (!T_cw_init || !finite16(T_cw_init)))
     return fail(DPT_E_ARG, "T_cw_init missing or not finite");
+  if (init_mode == DPT_INIT_PROPOSED && !c->have_prop)
+    return fail(DPT_E_STATE, "no learned proposal: call dpt_cnn_propose first");
   int e = check_track_state(c);
   if (e != DPT_OK) return e;
   if (!use_coop(c)) {
-    if (init_mode == DPT_INIT_CONST_VELOCITY)
-      return fail(DPT_E_ARG, "a constant-velocity start needs the cooperative track (launch mode AUTO or COOP)");
+    if (init_mode != DPT_INIT_GIVEN)
+      return fail(DPT_E_ARG, "a constant-velocity or proposed start needs the cooperative track (launch mode AUTO or COOP)");
     const int e2 = dpt_track_frame(c, T_cw_init, out);
     if (e2 == DPT_OK) c->pending.emplace_back(-1, nullptr);  // in order with the tracks in flight, already done
     return e2;
   }
-  return enqueue_coop(c, init_mode == DPT_INIT_GIVEN ? kStartGiven : kStartConstVelocity, T_cw_init, out);
+  const int mode = init_mode == DPT_INIT_GIVEN ? kStartGiven
+                   : init_mode == DPT_INIT_PROPOSED ? kStartDevice
+                                                    : kStartConstVelocity;
+  return enqueue_coop(c, mode, T_cw_init, out);
 }
 
 int dpt_synchronize(dpt_ctx* c) {
@@ -1353,6 +1364,9 @@ struct dpt_batch {
   StagedTable<double> hist_vals;  // 24 per stream
   double** d_hist_ptrs = nullptr;  // device array of the streams' history pointers
   WinJob* d_winjobs = nullptr;     // the streams' window pyramid jobs (device)
+  double* d_prop = nullptr;        // learned start proposals, n x 3x4 FP64 (device)
+  const uint8_t** d_cnn_lv = nullptr;  // the streams' coarsest reference then current levels
+  bool have_prop = false;
 
   void clear_groups() {
     for (CoopEngine* g : groups) delete g;
@@ -1372,6 +1386,8 @@ struct dpt_batch {
     hist_vals.release();
     if (d_hist_ptrs) (void)hipFree(d_hist_ptrs);
     if (d_winjobs) (void)hipFree(d_winjobs);
+    if (d_prop) (void)hipFree(d_prop);
+    if (d_cnn_lv) (void)hipFree(d_cnn_lv);
     for (hipEvent_t e : ev_jobs)
       if (e) (void)hipEventDestroy(e);
     if (d_jobs) (void)hipFree(d_jobs);
@@ -1527,7 +1543,8 @@ int batch_synchronize(dpt_batch* b) {
 }
 
 // Enqueue one cooperative track of every stream.  modes[s] is kStartGiven
-// (start from T_cw_init[s]) or kStartConstVelocity.
+// (start from T_cw_init[s]), kStartConstVelocity or kStartDevice (the proposal
+// in d_prop).
 int batch_enqueue_coop(dpt_batch* b, const int* modes, const double* T_cw_init, dpt_result* out) {
   if (b->groups_dirty) {  // regrouping frees the rings: finish and fill what is in flight first
     int e = b->pending.empty() ? DPT_OK : batch_synchronize(b);
@@ -1543,7 +1560,8 @@ int batch_enqueue_coop(dpt_batch* b, const int* modes, const double* T_cw_init, 
     const std::vector<int>& ss = b->group_streams[gi];
     StartSlot* st = b->groups[gi]->start(slot);
     for (size_t k = 0; k < ss.size(); ++k)
-      fill_start(b->ctx[ss[k]], modes[ss[k]], T_cw_init ? T_cw_init + 16 * ss[k] : nullptr, &st[k]);
+      fill_start(b->ctx[ss[k]], modes[ss[k]], T_cw_init ? T_cw_init + 16 * ss[k] : nullptr, &st[k],
+                 b->d_prop ? b->d_prop + 12 * ss[k] : nullptr);
   }
   int ps = -1;
   if (b->prof) HIP_TRY(b->prof_trk.begin(b->stream, &ps));
@@ -1902,23 +1920,27 @@ int dpt_batch_track(dpt_batch* b, const double* T_cw_init, dpt_result* out) {
 int dpt_batch_track_enqueue(dpt_batch* b, int32_t init_mode, const double* T_cw_init, dpt_result* out) {
   g_err.clear();
   if (!b || !out) return fail(DPT_E_ARG, "NULL argument");
-  if (init_mode != DPT_INIT_GIVEN && init_mode != DPT_INIT_CONST_VELOCITY)
+  if (init_mode != DPT_INIT_GIVEN && init_mode != DPT_INIT_CONST_VELOCITY && init_mode != DPT_INIT_PROPOSED)
     return fail(DPT_E_ARG, "init_mode %d", init_mode);
   if (init_mode == DPT_INIT_GIVEN) {
     if (!T_cw_init) return fail(DPT_E_ARG, "T_cw_init is NULL");
     for (int s = 0; s < b->n; ++s)
       if (!finite16(T_cw_init + 16 * s)) return fail(DPT_E_ARG, "T_cw_init %d not finite", s);
   }
+  if (init_mode == DPT_INIT_PROPOSED && !b->have_prop)
+    return fail(DPT_E_STATE, "no learned proposal: call dpt_cnn_propose_batch first");
   int e = batch_check_state(b);
   if (e != DPT_OK) return e;
   if (!batch_use_coop(b)) {
-    if (init_mode == DPT_INIT_CONST_VELOCITY)
-      return fail(DPT_E_ARG, "a constant-velocity start needs the cooperative track (launch mode AUTO or COOP)");
+    if (init_mode != DPT_INIT_GIVEN)
+      return fail(DPT_E_ARG, "a constant-velocity or proposed start needs the cooperative track (launch mode AUTO or COOP)");
     const int e2 = dpt_batch_track(b, T_cw_init, out);
     if (e2 == DPT_OK) b->pending.emplace_back(-1, nullptr);  // in order with the tracks in flight, already done
     return e2;
   }
-  std::vector<int> modes(b->n, init_mode == DPT_INIT_GIVEN ? kStartGiven : kStartConstVelocity);
+  std::vector<int> modes(b->n, init_mode == DPT_INIT_GIVEN ? kStartGiven
+                               : init_mode == DPT_INIT_PROPOSED ? kStartDevice
+                                                                : kStartConstVelocity);
   return batch_enqueue_coop(b, modes.data(), T_cw_init, out);
 }
 
@@ -2167,9 +2189,48 @@ int predict_streams(dpt_cnn* cnn, dpt_ctx* const* ctxs, int n, double* T_out) {
   return DPT_OK;
 }
 
+// Enqueue the learned proposal of n streams on stream s: the forward pass on
+// their coarsest reference and current levels, then each start relative to
+// its reference into prop (n x 3x4 FP64, device).  The level pointer table is
+// uploaded at the first call (the pyramids never move).
+int propose_streams(dpt_cnn* cnn, dpt_ctx* const* ctxs, int n, hipStream_t s, const uint8_t*** d_lv, double** prop) {
+  std::vector<const uint8_t*> h(2 * (size_t)n);
+  for (int k = 0; k < n; ++k) {
+    dpt_ctx* c = ctxs[k];
+    const int L = c->prm.levels - 1;
+    if (c->lv[L].W != 94 || c->lv[L].H != 60) return fail(DPT_E_ARG, "stream %d: coarsest level is not 94 x 60", k);
+    if (!c->have_pyr[DPT_SLOT_REF] || !c->have_pyr[DPT_SLOT_CUR] || !c->have_ref)
+      return fail(DPT_E_STATE, "stream %d: pyramids or reference missing", k);
+    h[k] = c->pyr[DPT_SLOT_REF] + c->lv[L].off;
+    h[n + k] = c->pyr[DPT_SLOT_CUR] + c->lv[L].off;
+  }
+  if (!*d_lv) {
+    HIP_TRY(hipMalloc((void**)d_lv, sizeof(void*) * 2 * n));
+    HIP_TRY(hipMemcpy((void*)*d_lv, h.data(), sizeof(void*) * 2 * n, hipMemcpyHostToDevice));
+  }
+  if (!*prop) HIP_TRY(hipMalloc((void**)prop, sizeof(double) * 12 * n));
+  return cnn_propose(cnn, *d_lv, n, s, *prop);
+}
+
 }  // namespace
 
 extern "C" {
+
+int dpt_cnn_propose(dpt_cnn* cnn, dpt_ctx* c) {
+  g_err.clear();
+  if (!cnn || !c) return fail(DPT_E_ARG, "NULL argument");
+  const int e = propose_streams(cnn, &c, 1, c->stream, &c->d_cnn_lv, &c->d_prop);
+  if (e == DPT_OK) c->have_prop = true;
+  return e;
+}
+
+int dpt_cnn_propose_batch(dpt_cnn* cnn, dpt_batch* b) {
+  g_err.clear();
+  if (!cnn || !b) return fail(DPT_E_ARG, "NULL argument");
+  const int e = propose_streams(cnn, b->ctx.data(), b->n, b->stream, &b->d_cnn_lv, &b->d_prop);
+  if (e == DPT_OK) b->have_prop = true;
+  return e;
+}
 
 int dpt_cnn_predict(dpt_cnn* cnn, dpt_ctx* c, double T_cw_out[16]) {
   g_err.clear();

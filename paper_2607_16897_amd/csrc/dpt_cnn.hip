@@ -7,15 +7,19 @@
 // convolution weights are BF16 in NHWC / [co][ky][kx][ci] layouts; the
 // forward convolutions are implicit GEMMs on the matrix cores
 // (v_mfma_f32_16x16x16bf16_1k, FP32 accumulation) with bias and ReLU fused in
-// the epilogue.  Pooling, the FC layers, the loss, the backward pass (FP32
-// accumulation from the BF16 operands, split reductions summed in a fixed
-// order) and Adam run on the vector units; master weights and Adam moments
-// are FP32.
+// the epilogue.  The backward convolutions are implicit GEMMs on the same
+// instruction: the data gradient per stride-parity class of the input pixels
+// (only the taps that reach a class), the weight gradient as dZ^T Xcol split
+// over output pixels, with the bias gradient as a column of ones; gradients
+// flowing between layers are stored in BF16, split reductions are summed in a
+// fixed order.  Pooling, the FC layers, the loss and Adam run on the vector
+// units; master weights and Adam moments are FP32.
 #include <cmath>
 #include <cstring>
 #include <vector>
 
 #include "../../include/dptrack.h"
+#include "dpt_device.h"
 #include "dpt_internal.h"
 
 struct dpt_cnn;
@@ -172,7 +176,7 @@ __global__ __launch_bounds__(256) void conv_fwd_mfma(const uint16_t* __restrict_
 __global__ __launch_bounds__(64) void head_kernel(const uint16_t* __restrict__ a4, const float* __restrict__ P,
                                                   const float* __restrict__ targets, int B, float* __restrict__ out,
                                                   float* __restrict__ sqerr, float* __restrict__ fcg,
-                                                  float* __restrict__ dz4) {
+                                                  uint16_t* __restrict__ dz4) {
   const Offsets o = offsets();
   const int b = blockIdx.x, t = threadIdx.x;
   __shared__ float g[64], h1[64], dout[kOut], dz1[64];
@@ -211,82 +215,146 @@ __global__ __launch_bounds__(64) void head_kernel(const uint16_t* __restrict__ a
   float dg = 0.f;
   for (int q = 0; q < kHidden; ++q) dg = fmaf(P[o.fw1 + q * 64 + t], dz1[q], dg);
   dg *= (1.0f / HW);
-  for (int p = 0; p < HW; ++p) dz4[((size_t)b * HW + p) * 64 + t] = bf2f(a[p * 64 + t]) > 0.f ? dg : 0.f;
+  const uint16_t dgb = f2bf(dg);
+  for (int p = 0; p < HW; ++p) dz4[((size_t)b * HW + p) * 64 + t] = bf2f(a[p * 64 + t]) > 0.f ? dgb : (uint16_t)0;
 }
 
 // ---------------------------------------------------------------- backward convolution
 
-// dX for one layer, fused with the ReLU mask of the layer below:
-// dZprev[b][y][x][c] = (a_prev > 0) * sum_{ky,kx,o} W[o][ky][kx][c] dZ[b][i][j][o],
-// with 2i + ky - 1 = y, 2j + kx - 1 = x.  One thread per (b, y, x, c).
-template <int CI, int CO>
-__global__ void conv_bwd_data(const float* __restrict__ dz, int Ho, int Wo, const uint16_t* __restrict__ w,
-                              const uint16_t* __restrict__ aprev, int H, int W, int B, float* __restrict__ dzprev) {
-  const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= (size_t)B * H * W * CI) return;
-  const int c = id % CI;
-  const size_t pix = id / CI;
-  const int xx = pix % W, yy = (pix / W) % H, b = pix / ((size_t)W * H);
-  if (!(bf2f(aprev[id]) > 0.f)) {
-    dzprev[id] = 0.f;
-    return;
-  }
-  float s = 0.f;
-  for (int ky = 0; ky < 3; ++ky) {
-    const int ty = yy + 1 - ky;
-    if (ty < 0 || (ty & 1) || (ty >> 1) >= Ho) continue;
-    const int i = ty >> 1;
-    for (int kx = 0; kx < 3; ++kx) {
-      const int tx = xx + 1 - kx;
-      if (tx < 0 || (tx & 1) || (tx >> 1) >= Wo) continue;
-      const int j = tx >> 1;
-      const float* d = dz + (((size_t)b * Ho + i) * Wo + j) * CO;
-      const uint16_t* wk = w + (ky * 3 + kx) * CI + c;
-      for (int o = 0; o < CO; ++o) s = fmaf(bf2f(wk[(size_t)o * 9 * CI]), d[o], s);
-    }
-  }
-  dzprev[id] = s;
+__device__ __forceinline__ short4_t bf16x4(uint2 v) {
+  return short4_t{(short)(v.x & 0xffff), (short)(v.x >> 16), (short)(v.y & 0xffff), (short)(v.y >> 16)};
 }
 
-// dW and db, split over the batch: partial[split][co][ky][kx][ci] (then bias [co])
-// = sum over samples b in the split and output pixels (i, j) of dZ * x_pad.
-template <int CI, int CO>
-__global__ void conv_bwd_weight(const float* __restrict__ dz, int Ho, int Wo, const uint16_t* __restrict__ x, int H,
-                                int W, int B, int per_split, float* __restrict__ partial) {
-  constexpr int NW = CO * 9 * CI, NP = NW + CO;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  const int split = blockIdx.y;
-  if (e >= NP) return;
-  const int b0 = split * per_split, b1 = min(B, b0 + per_split);
-  float s = 0.f;
-  if (e < NW) {
-    const int c = e % CI, tap = (e / CI) % 9, o = e / (9 * CI);
-    const int ky = tap / 3, kx = tap % 3;
-    for (int b = b0; b < b1; ++b)
-      for (int i = 0; i < Ho; ++i) {
-        const int yy = 2 * i + ky - 1;
-        if (yy < 0 || yy >= H) continue;
-        for (int j = 0; j < Wo; ++j) {
-          const int xx = 2 * j + kx - 1;
-          if (xx < 0 || xx >= W) continue;
-          s = fmaf(dz[(((size_t)b * Ho + i) * Wo + j) * CO + o], bf2f(x[(((size_t)b * H + yy) * W + xx) * CI + c]), s);
+// Data gradient of layer L >= 1, fused with the ReLU mask of its input:
+// dZprev[b][y][x][c] = (a_prev > 0) * sum over taps (ky, kx) and channels o of
+// W[o][ky][kx][c] dZ[b][i][j][o], where 2i + ky - 1 = y and 2j + kx - 1 = x.
+// Stride 2 makes the reaching taps depend only on the parities of (y, x): an
+// even row is reached by ky = 1 alone, an odd one by ky = 0 and 2 (columns
+// likewise), so the rows of the implicit GEMM are the input pixels of one
+// parity class (blockIdx.y) and k = (reaching tap, o).  wT: the layer's BF16
+// weights as [tap][ci][co].  A wave computes 16 pixels x CI channels.
+template <int L>
+__global__ __launch_bounds__(256) void conv_bwd_data_mfma(const uint16_t* __restrict__ dz,
+                                                          const uint16_t* __restrict__ wT,
+                                                          const uint16_t* __restrict__ aprev, int B,
+                                                          uint16_t* __restrict__ dzprev) {
+  constexpr int CI = kC[L], CO = kC[L + 1], H = kHs[L], W = kWs[L], Ho = kHs[L + 1], Wo = kWs[L + 1];
+  constexpr int NT = CI / 16;
+  static_assert(CI % 16 == 0 && CO % 16 == 0, "16-channel tiles");
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, q = lane >> 4;
+  const int py = blockIdx.y >> 1, px = blockIdx.y & 1;
+  const int Hc = (H - py + 1) / 2, Wc = (W - px + 1) / 2;
+  const int M = B * Hc * Wc;
+  const int m0 = (blockIdx.x * 4 + wave) * 16;
+  if (m0 >= M) return;
+  const int m = m0 + (lane & 15);
+  const bool mvalid = m < M;
+  const int b = mvalid ? m / (Hc * Wc) : 0, r = mvalid ? m % (Hc * Wc) : 0;
+  const int y = 2 * (r / Wc) + py, x = 2 * (r % Wc) + px;
+  float4_t acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = float4_t{0.f, 0.f, 0.f, 0.f};
+  for (int ta = 0; ta < (py ? 2 : 1); ++ta)
+    for (int tb = 0; tb < (px ? 2 : 1); ++tb) {
+      const int ky = py ? 2 * ta : 1, kx = px ? 2 * tb : 1, tap = ky * 3 + kx;
+      const int i = (y + 1 - ky) >> 1, j = (x + 1 - kx) >> 1;  // y + 1 - ky >= 0 and even
+      const bool ok = mvalid && i < Ho && j < Wo;
+      // a row the tap does not reach reads pixel 0 and discards it
+      const uint16_t* drow = dz + (ok ? (((size_t)b * Ho + i) * Wo + j) * CO : 0);
+#pragma unroll
+      for (int o0 = 0; o0 < CO; o0 += 16) {
+        const int k0 = o0 + 4 * q;
+        uint2 dv = *reinterpret_cast<const uint2*>(drow + k0);
+        if (!ok) dv = make_uint2(0u, 0u);
+        const short4_t av = bf16x4(dv);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const int n = t * 16 + (lane & 15);
+          const short4_t bv = bf16x4(*reinterpret_cast<const uint2*>(wT + ((size_t)tap * CI + n) * CO + k0));
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[t], 0, 0, 0);
         }
       }
-  } else {
-    const int o = e - NW;
-    for (int b = b0; b < b1; ++b)
-      for (int p = 0; p < Ho * Wo; ++p) s += dz[((size_t)b * Ho * Wo + p) * CO + o];
+    }
+  // D[4q + j][lane % 16]: pixel row m0 + 4q + j, channel t * 16 + lane % 16
+#pragma unroll
+  for (int jq = 0; jq < 4; ++jq) {
+    const int mo = m0 + 4 * q + jq;
+    if (mo >= M) continue;
+    const int bo = mo / (Hc * Wc), ro = mo % (Hc * Wc);
+    const int yo = 2 * (ro / Wc) + py, xo = 2 * (ro % Wc) + px;
+    const size_t base = (((size_t)bo * H + yo) * W + xo) * CI;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const size_t id = base + t * 16 + (lane & 15);
+      dzprev[id] = bf2f(aprev[id]) > 0.f ? f2bf(acc[t][jq]) : (uint16_t)0;
+    }
   }
-  partial[(size_t)split * NP + e] = s;
 }
 
-// grad[off + e] = sum_s partial[s][e], fixed order
-__global__ void reduce_splits(const float* __restrict__ partial, int splits, int n, float* __restrict__ grad) {
+// Weight and bias gradient of layer L over the output pixels p = (b, i, j) of
+// split blockIdx.y: partial[split][o][n] = sum_p dZ[p][o] Xcol[p][n], where
+// Xcol[p][tap * CI + c] = X[b][2i + ky - 1][2j + kx - 1][c] (zero outside the
+// image) and column n = 9 CI is all ones (the bias); columns up to the next
+// multiple of 16 are zero.  One wave per 16 x 16 output tile (blockIdx.x * 4 +
+// wave over CO / 16 x NPAD / 16 tiles), 16 pixels per MFMA step.
+template <int L>
+__global__ __launch_bounds__(256) void conv_bwd_weight_mfma(const uint16_t* __restrict__ dz,
+                                                            const uint16_t* __restrict__ x, int P, int per_split,
+                                                            float* __restrict__ partial) {
+  constexpr int CI = kC[L], CO = kC[L + 1], H = kHs[L], W = kWs[L], Ho = kHs[L + 1], Wo = kWs[L + 1];
+  constexpr int NPAD = (9 * CI + 1 + 15) / 16 * 16, MT = CO / 16, NT = NPAD / 16;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, q = lane >> 4;
+  const int tile = blockIdx.x * 4 + wave;
+  if (tile >= MT * NT) return;
+  const int mt = tile / NT, nt = tile % NT, split = blockIdx.y;
+  const int p0 = split * per_split, p1 = min(P, p0 + per_split);
+  const int o = mt * 16 + (lane & 15), n = nt * 16 + (lane & 15);
+  const bool real = n < 9 * CI, ones = n == 9 * CI;
+  const int tap = real ? n / CI : 0, c = real ? n % CI : 0, ky = tap / 3, kx = tap % 3;
+  float4_t acc = float4_t{0.f, 0.f, 0.f, 0.f};
+  for (int pb = p0; pb < p1; pb += 16) {
+    short a[4], bb[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int p = pb + 4 * q + t;
+      uint16_t av = 0, bv = 0;
+      if (p < p1) {
+        av = dz[(size_t)p * CO + o];
+        if (ones) {
+          bv = 0x3f80;  // 1.0
+        } else if (real) {
+          const int b = p / (Ho * Wo), ij = p % (Ho * Wo);
+          const int yy = 2 * (ij / Wo) + ky - 1, xx = 2 * (ij % Wo) + kx - 1;
+          if (yy >= 0 && yy < H && xx >= 0 && xx < W) bv = x[(((size_t)b * H + yy) * W + xx) * CI + c];
+        }
+      }
+      a[t] = (short)av;
+      bb[t] = (short)bv;
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(short4_t{a[0], a[1], a[2], a[3]},
+                                                     short4_t{bb[0], bb[1], bb[2], bb[3]}, acc, 0, 0, 0);
+  }
+  float* out = partial + (size_t)split * CO * NPAD;
+#pragma unroll
+  for (int jq = 0; jq < 4; ++jq) out[(size_t)(mt * 16 + 4 * q + jq) * NPAD + n] = acc[jq];
+}
+
+// Sum of the splits of conv_bwd_weight_mfma in split order, into the gradient
+// vector: weights at w_off + o * 9 CI + n ([co][ky][kx][ci]), bias at b_off + o.
+template <int L>
+__global__ void reduce_wgrad(const float* __restrict__ partial, int splits, float* __restrict__ gw,
+                             float* __restrict__ gb) {
+  constexpr int CI = kC[L], CO = kC[L + 1], NPAD = (9 * CI + 1 + 15) / 16 * 16;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
+  if (e >= CO * NPAD) return;
+  const int o = e / NPAD, n = e % NPAD;
+  if (n > 9 * CI) return;
   float s = 0.f;
-  for (int q = 0; q < splits; ++q) s += partial[(size_t)q * n + e];
-  grad[e] = s;
+  for (int k = 0; k < splits; ++k) s += partial[(size_t)k * CO * NPAD + e];
+  if (n < 9 * CI)
+    gw[o * 9 * CI + n] = s;
+  else
+    gb[o] = s;
 }
 
 // sum over batch of the per-sample FC gradients (fixed order), and of the squared errors
@@ -302,9 +370,26 @@ __global__ void reduce_batch(const float* __restrict__ v, int B, int n, float* _
 
 // Adam (Kingma & Ba 2015) on the FP32 master weights with bias correction c1 =
 // 1 - b1^t, c2 = 1 - b2^t; refreshes the BF16 conv weight copies.
+// BF16 copies of parameter e: Pb[e]; a convolution weight ([co][ky][kx][ci])
+// also into PbT as [tap][ci][co], the operand layout of the data gradient.
+__device__ __forceinline__ void store_bf16_param(int e, float p, uint16_t* __restrict__ Pb,
+                                                 uint16_t* __restrict__ PbT) {
+  const uint16_t h = f2bf(p);
+  Pb[e] = h;
+  const Offsets o = offsets();
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    const int CI = kC[l], CO = kC[l + 1], r = e - o.w[l];
+    if (r >= 0 && r < CO * 9 * CI) {
+      const int co = r / (9 * CI), tap = (r / CI) % 9, ci = r % CI;
+      PbT[o.w[l] + (tap * CI + ci) * CO + co] = h;
+    }
+  }
+}
+
 __global__ void adam_kernel(float* __restrict__ P, const float* __restrict__ G, float* __restrict__ M,
                             float* __restrict__ V, int n, float lr, float b1, float b2, float eps, float c1, float c2,
-                            int conv_end, uint16_t* __restrict__ Pb) {
+                            int conv_end, uint16_t* __restrict__ Pb, uint16_t* __restrict__ PbT) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
   const float g = G[e];
@@ -314,12 +399,12 @@ __global__ void adam_kernel(float* __restrict__ P, const float* __restrict__ G, 
   V[e] = v;
   const float p = P[e] - lr * (m / c1) / (sqrtf(v / c2) + eps);
   P[e] = p;
-  if (e < conv_end) Pb[e] = f2bf(p);
+  if (e < conv_end) store_bf16_param(e, p, Pb, PbT);
 }
 
-__global__ void to_bf16(const float* __restrict__ P, int n, uint16_t* __restrict__ Pb) {
+__global__ void to_bf16(const float* __restrict__ P, int n, uint16_t* __restrict__ Pb, uint16_t* __restrict__ PbT) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < n) Pb[e] = f2bf(P[e]);
+  if (e < n) store_bf16_param(e, P[e], Pb, PbT);
 }
 
 __global__ void bf16_to_f32(const uint16_t* __restrict__ a, size_t n, float* __restrict__ out) {
@@ -341,8 +426,11 @@ struct dpt_cnn {
   Offsets o;
   float *P = nullptr, *G = nullptr, *M = nullptr, *V = nullptr;  // FP32 master, gradient, Adam moments
   uint16_t* Pb = nullptr;                                          // BF16 copy (conv weights used)
+  uint16_t* PbT = nullptr;                                         // BF16 conv weights as [tap][ci][co]
   uint16_t* act[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-  float *dz[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // dz[l]: gradient at layer l's output (pre-ReLU)
+  // dz[l]: gradient at layer l's output (pre-ReLU), BF16 NHWC; sized for FP32
+  // so that the activation test hook can stage an FP32 copy there
+  uint16_t* dz[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   float *out = nullptr, *tgt = nullptr, *sqerr = nullptr, *fcg = nullptr, *partial = nullptr, *scal = nullptr;
   uint8_t* pairs = nullptr;
   const uint8_t** d_lv = nullptr;  // [2][max_batch] level pointers
@@ -350,7 +438,7 @@ struct dpt_cnn {
   float* h_buf = nullptr;  // pinned
   size_t partial_floats = 0;
   ~dpt_cnn() {
-    for (void* p : {(void*)P, (void*)G, (void*)M, (void*)V, (void*)Pb, (void*)out, (void*)tgt, (void*)sqerr,
+    for (void* p : {(void*)P, (void*)G, (void*)M, (void*)V, (void*)Pb, (void*)PbT, (void*)out, (void*)tgt, (void*)sqerr,
                     (void*)fcg, (void*)partial, (void*)scal, (void*)pairs, (void*)d_lv})
       if (p) (void)hipFree(p);
     for (int l = 0; l < 5; ++l) {
@@ -371,57 +459,52 @@ int cfail(int code, const char* msg) { return set_error(code, msg); }
     if (e_ != hipSuccess) return cfail(DPT_E_HIP, #expr);      \
   } while (0)
 
-constexpr int kSplitsMax = 256;
+// Output pixels per split of the weight gradient: a few hundred MFMA steps per wave.
+constexpr int kPixPerSplit = 2048;
 
-int splits_for(int l, int B) {
-  // samples per split so that each thread loops over a few thousand terms
-  const int per_sample = kHs[l + 1] * kWs[l + 1];
-  int per = std::max(1, 4096 / per_sample);
-  return (B + per - 1) / per;
-}
+int splits_for(int l, int B) { return (B * kHs[l + 1] * kWs[l + 1] + kPixPerSplit - 1) / kPixPerSplit; }
 
-int per_split_for(int l, int B) {
-  const int per_sample = kHs[l + 1] * kWs[l + 1];
-  return std::max(1, 4096 / per_sample);
-}
+constexpr int npad(int l) { return (9 * kC[l] + 1 + 15) / 16 * 16; }
 
-hipError_t forward(dpt_cnn* c, int B) {
+hipError_t forward(dpt_cnn* c, int B, hipStream_t s) {
   const int M1 = B * kHs[1] * kWs[1], M2 = B * kHs[2] * kWs[2], M3 = B * kHs[3] * kWs[3], M4 = B * kHs[4] * kWs[4];
   auto grid = [](int M) { return dim3((M + 63) / 64); };
-  hipLaunchKernelGGL((conv_fwd_mfma<2, 16>), grid(M1), dim3(256), 0, c->stream, c->act[0], kHs[0], kWs[0], kHs[1],
+  hipLaunchKernelGGL((conv_fwd_mfma<2, 16>), grid(M1), dim3(256), 0, s, c->act[0], kHs[0], kWs[0], kHs[1],
                      kWs[1], B, c->Pb + c->o.w[0], c->P + c->o.b[0], c->act[1]);
-  hipLaunchKernelGGL((conv_fwd_mfma<16, 32>), grid(M2), dim3(256), 0, c->stream, c->act[1], kHs[1], kWs[1], kHs[2],
+  hipLaunchKernelGGL((conv_fwd_mfma<16, 32>), grid(M2), dim3(256), 0, s, c->act[1], kHs[1], kWs[1], kHs[2],
                      kWs[2], B, c->Pb + c->o.w[1], c->P + c->o.b[1], c->act[2]);
-  hipLaunchKernelGGL((conv_fwd_mfma<32, 64>), grid(M3), dim3(256), 0, c->stream, c->act[2], kHs[2], kWs[2], kHs[3],
+  hipLaunchKernelGGL((conv_fwd_mfma<32, 64>), grid(M3), dim3(256), 0, s, c->act[2], kHs[2], kWs[2], kHs[3],
                      kWs[3], B, c->Pb + c->o.w[2], c->P + c->o.b[2], c->act[3]);
-  hipLaunchKernelGGL((conv_fwd_mfma<64, 64>), grid(M4), dim3(256), 0, c->stream, c->act[3], kHs[3], kWs[3], kHs[4],
+  hipLaunchKernelGGL((conv_fwd_mfma<64, 64>), grid(M4), dim3(256), 0, s, c->act[3], kHs[3], kWs[3], kHs[4],
                      kWs[4], B, c->Pb + c->o.w[3], c->P + c->o.b[3], c->act[4]);
   return hipGetLastError();
 }
 
-template <int CI, int CO>
-hipError_t bwd_layer(dpt_cnn* c, int l, int B) {
-  const int Ho = kHs[l + 1], Wo = kWs[l + 1], H = kHs[l], W = kWs[l];
-  const int NP = CO * 9 * CI + CO;
-  const int per = per_split_for(l, B), splits = splits_for(l, B);
-  hipLaunchKernelGGL((conv_bwd_weight<CI, CO>), dim3((NP + 255) / 256, splits), dim3(256), 0, c->stream, c->dz[l + 1],
-                     Ho, Wo, c->act[l], H, W, B, per, c->partial);
-  hipLaunchKernelGGL(reduce_splits, dim3((NP + 255) / 256), dim3(256), 0, c->stream, c->partial, splits, NP,
-                     c->G + c->o.w[l]);
-  if (l > 0) {
-    const size_t n = (size_t)B * H * W * CI;
-    hipLaunchKernelGGL((conv_bwd_data<CI, CO>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
-                       c->dz[l + 1], Ho, Wo, c->Pb + c->o.w[l], c->act[l], H, W, B, c->dz[l]);
+template <int L>
+hipError_t bwd_layer(dpt_cnn* c, int B) {
+  constexpr int CO = kC[L + 1];
+  const int P = B * kHs[L + 1] * kWs[L + 1], splits = splits_for(L, B);
+  const int tiles = (CO / 16) * (npad(L) / 16);
+  hipLaunchKernelGGL((conv_bwd_weight_mfma<L>), dim3((tiles + 3) / 4, splits), dim3(256), 0, c->stream, c->dz[L + 1],
+                     c->act[L], P, kPixPerSplit, c->partial);
+  hipLaunchKernelGGL((reduce_wgrad<L>), dim3((CO * npad(L) + 255) / 256), dim3(256), 0, c->stream, c->partial, splits,
+                     c->G + c->o.w[L], c->G + c->o.b[L]);
+  if constexpr (L > 0) {
+    int rows = 0;  // the largest parity class
+    for (int cls = 0; cls < 4; ++cls)
+      rows = std::max(rows, B * ((kHs[L] - (cls >> 1) + 1) / 2) * ((kWs[L] - (cls & 1) + 1) / 2));
+    hipLaunchKernelGGL((conv_bwd_data_mfma<L>), dim3((rows + 63) / 64, 4), dim3(256), 0, c->stream, c->dz[L + 1],
+                       c->PbT + c->o.w[L], c->act[L], B, c->dz[L]);
   }
   return hipGetLastError();
 }
 
 hipError_t backward(dpt_cnn* c, int B) {
   hipError_t e;
-  if ((e = bwd_layer<64, 64>(c, 3, B)) != hipSuccess) return e;
-  if ((e = bwd_layer<32, 64>(c, 2, B)) != hipSuccess) return e;
-  if ((e = bwd_layer<16, 32>(c, 1, B)) != hipSuccess) return e;
-  return bwd_layer<2, 16>(c, 0, B);
+  if ((e = bwd_layer<3>(c, B)) != hipSuccess) return e;
+  if ((e = bwd_layer<2>(c, B)) != hipSuccess) return e;
+  if ((e = bwd_layer<1>(c, B)) != hipSuccess) return e;
+  return bwd_layer<0>(c, B);
 }
 
 int load_input(dpt_cnn* c, const uint8_t* pairs, int B, int on_device) {
@@ -452,15 +535,14 @@ int dpt_cnn_create(int32_t max_batch, void* hip_stream, dpt_cnn** out) {
   const size_t n = (size_t)c->o.total, B = (size_t)max_batch;
   bool ok = hipMalloc(&c->P, n * 4) == hipSuccess && hipMalloc(&c->G, n * 4) == hipSuccess &&
             hipMalloc(&c->M, n * 4) == hipSuccess && hipMalloc(&c->V, n * 4) == hipSuccess &&
-            hipMalloc(&c->Pb, n * 2) == hipSuccess;
+            hipMalloc(&c->Pb, n * 2) == hipSuccess && hipMalloc(&c->PbT, n * 2) == hipSuccess;
   for (int l = 0; l < 5 && ok; ++l) {
     const size_t e = B * kHs[l] * kWs[l] * kC[l];
     ok = hipMalloc(&c->act[l], e * 2) == hipSuccess && hipMalloc(&c->dz[l], e * 4) == hipSuccess;
   }
-  c->partial_floats = (size_t)kSplitsMax * (64 * 9 * 64 + 64);
   size_t maxsplit = 0;
   for (int l = 0; l < 4; ++l)
-    maxsplit = std::max(maxsplit, (size_t)splits_for(l, max_batch) * (kC[l + 1] * 9 * kC[l] + kC[l + 1]));
+    maxsplit = std::max(maxsplit, (size_t)splits_for(l, max_batch) * kC[l + 1] * npad(l));
   c->partial_floats = maxsplit;
   ok = ok && hipMalloc(&c->out, B * kOut * 4) == hipSuccess && hipMalloc(&c->tgt, B * kOut * 4) == hipSuccess &&
        hipMalloc(&c->sqerr, B * kOut * 4) == hipSuccess &&
@@ -477,6 +559,7 @@ int dpt_cnn_create(int32_t max_batch, void* hip_stream, dpt_cnn** out) {
   (void)hipMemsetAsync(c->V, 0, n * 4, c->stream);
   (void)hipMemsetAsync(c->P, 0, n * 4, c->stream);
   (void)hipMemsetAsync(c->Pb, 0, n * 2, c->stream);
+  (void)hipMemsetAsync(c->PbT, 0, n * 2, c->stream);
   if (hipStreamSynchronize(c->stream) != hipSuccess) {
     delete c;
     return cfail(DPT_E_HIP, "stream synchronize");
@@ -506,7 +589,7 @@ int dpt_cnn_set_params(dpt_cnn* c, const float* params) {
         for (int t = 0; t < 9; ++t) h[o.w[l] + (co * 9 + t) * CI + ci] = params[o.w[l] + (co * CI + ci) * 9 + t];
   }
   CNN_TRY(hipMemcpyAsync(c->P, h, sizeof(float) * o.total, hipMemcpyHostToDevice, c->stream));
-  hipLaunchKernelGGL(to_bf16, dim3((o.total + 255) / 256), dim3(256), 0, c->stream, c->P, o.total, c->Pb);
+  hipLaunchKernelGGL(to_bf16, dim3((o.total + 255) / 256), dim3(256), 0, c->stream, c->P, o.total, c->Pb, c->PbT);
   CNN_TRY(hipGetLastError());
   CNN_TRY(hipMemsetAsync(c->M, 0, sizeof(float) * o.total, c->stream));
   CNN_TRY(hipMemsetAsync(c->V, 0, sizeof(float) * o.total, c->stream));
@@ -546,7 +629,7 @@ int dpt_cnn_forward(dpt_cnn* c, const uint8_t* pairs, int32_t B, int32_t on_devi
   if (B < 1 || B > c->max_batch) return cfail(DPT_E_ARG, "batch size");
   int e = load_input(c, pairs, B, on_device);
   if (e != DPT_OK) return e;
-  CNN_TRY(forward(c, B));
+  CNN_TRY(forward(c, B, c->stream));
   hipLaunchKernelGGL(head_kernel, dim3(B), dim3(64), 0, c->stream, c->act[4], c->P, nullptr, B, c->out, nullptr,
                      nullptr, nullptr);
   CNN_TRY(hipGetLastError());
@@ -571,7 +654,7 @@ int dpt_cnn_train_step(dpt_cnn* c, const uint8_t* pairs, const float* targets, i
     tg = c->tgt;
   }
   const Offsets& o = c->o;
-  CNN_TRY(forward(c, B));
+  CNN_TRY(forward(c, B, c->stream));
   hipLaunchKernelGGL(head_kernel, dim3(B), dim3(64), 0, c->stream, c->act[4], c->P, tg, B, c->out, c->sqerr, c->fcg,
                      c->dz[4]);
   const int nfc = o.total - o.fw1;
@@ -583,7 +666,7 @@ int dpt_cnn_train_step(dpt_cnn* c, const uint8_t* pairs, const float* targets, i
     c->step += 1;
     const float c1 = 1.0f - std::pow(0.9f, (float)c->step), c2 = 1.0f - std::pow(0.999f, (float)c->step);
     hipLaunchKernelGGL(adam_kernel, dim3((o.total + 255) / 256), dim3(256), 0, c->stream, c->P, c->G, c->M, c->V,
-                       o.total, lr, 0.9f, 0.999f, 1e-8f, c1, c2, o.fw1, c->Pb);
+                       o.total, lr, 0.9f, 0.999f, 1e-8f, c1, c2, o.fw1, c->Pb, c->PbT);
     CNN_TRY(hipGetLastError());
   }
   CNN_TRY(hipMemcpyAsync(c->h_buf, c->scal, sizeof(float) * kOut, hipMemcpyDeviceToHost, c->stream));
@@ -602,9 +685,10 @@ int dpt_cnn_get_activation(dpt_cnn* c, int32_t l, int32_t B, float* host_out) {
     CNN_TRY(hipMemcpyAsync(host_out, c->out, sizeof(float) * B * kOut, hipMemcpyDeviceToHost, c->stream));
   } else {
     const size_t n = (size_t)B * kHs[l] * kWs[l] * kC[l];  // dz[l] has exactly this size
-    hipLaunchKernelGGL(bf16_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, c->act[l], n, c->dz[l]);
+    float* tmp = reinterpret_cast<float*>(c->dz[l]);
+    hipLaunchKernelGGL(bf16_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, c->act[l], n, tmp);
     CNN_TRY(hipGetLastError());
-    CNN_TRY(hipMemcpyAsync(host_out, c->dz[l], sizeof(float) * n, hipMemcpyDeviceToHost, c->stream));
+    CNN_TRY(hipMemcpyAsync(host_out, tmp, sizeof(float) * n, hipMemcpyDeviceToHost, c->stream));
   }
   CNN_TRY(hipStreamSynchronize(c->stream));
   return DPT_OK;
@@ -625,12 +709,57 @@ int cnn_forward_levels(dpt_cnn* c, const uint8_t* const* refs, const uint8_t* co
   hipLaunchKernelGGL(input_from_levels, dim3((n + 255) / 256), dim3(256), 0, c->stream, c->d_lv, c->d_lv + B, B,
                      c->act[0]);
   CNN_TRY(hipGetLastError());
-  CNN_TRY(forward(c, B));
+  CNN_TRY(forward(c, B, c->stream));
   hipLaunchKernelGGL(head_kernel, dim3(B), dim3(64), 0, c->stream, c->act[4], c->P, nullptr, B, c->out, nullptr,
                      nullptr, nullptr);
   CNN_TRY(hipGetLastError());
   CNN_TRY(hipMemcpyAsync(out_host, c->out, sizeof(float) * B * kOut, hipMemcpyDeviceToHost, c->stream));
   CNN_TRY(hipStreamSynchronize(c->stream));
+  return DPT_OK;
+}
+
+namespace cnn {
+
+// The network's outputs are twists scaled to unit range: 5 degrees (in
+// radians) for the rotation part, 0.1 m for the translation part.
+__constant__ double kTwistScaleDev[6] = {0.08726646259971647, 0.08726646259971647, 0.08726646259971647,
+                                         0.1, 0.1, 0.1};
+
+// rel[b] = exp(xi_b) as 3x4 FP64, xi_b = the scaled output b (rotation first).
+__global__ void propose_kernel(const float* __restrict__ out, int B, double* __restrict__ rel) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  double xi[6];
+  for (int j = 0; j < 6; ++j) xi[j] = (double)out[kOut * b + j] * kTwistScaleDev[j];
+  const double th2 = fma(xi[0], xi[0], fma(xi[1], xi[1], xi[2] * xi[2]));
+  double A, Bc, C;
+  if (th2 < 1e-8) {  // |w| < 1e-4: series, truncation below 1e-17
+    A = 1.0 - th2 * (1.0 / 6.0);
+    Bc = 0.5 - th2 * (1.0 / 24.0);
+    C = (1.0 / 6.0) - th2 * (1.0 / 120.0);
+  } else {
+    const double th = sqrt(th2), sn = sin(th), sh = sin(0.5 * th);
+    A = sn / th;
+    Bc = 2.0 * sh * sh / th2;
+    C = (th - sn) / (th2 * th);
+  }
+  double T[12] = {1.0, 0.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 0.0, 1.0, 0.0};
+  compose_exp(T, xi[0], xi[1], xi[2], xi[3], xi[4], xi[5], th2, A, Bc, C);
+  for (int j = 0; j < 12; ++j) rel[12 * b + j] = T[j];
+}
+
+}  // namespace cnn
+
+int cnn_propose(dpt_cnn* c, const uint8_t* const* d_lv, int B, hipStream_t s, double* rel) {
+  if (B < 1 || B > c->max_batch) return cfail(DPT_E_ARG, "batch size");
+  const int n = B * kH0 * kW0;
+  hipLaunchKernelGGL(input_from_levels, dim3((n + 255) / 256), dim3(256), 0, s, d_lv, d_lv + B, B, c->act[0]);
+  CNN_TRY(hipGetLastError());
+  CNN_TRY(forward(c, B, s));
+  hipLaunchKernelGGL(head_kernel, dim3(B), dim3(64), 0, s, c->act[4], c->P, nullptr, B, c->out, nullptr, nullptr,
+                     nullptr);
+  hipLaunchKernelGGL(propose_kernel, dim3((B + 63) / 64), dim3(64), 0, s, c->out, B, rel);
+  CNN_TRY(hipGetLastError());
   return DPT_OK;
 }
 

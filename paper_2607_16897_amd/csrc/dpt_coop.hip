@@ -245,8 +245,9 @@ __device__ __forceinline__ void const_velocity_start(double* T0, const double* r
   __syncthreads();
 }
 
-// Start pose relative to the reference for this launch: the given one, or the
-// constant-velocity prediction from the stream's pose history.  Block-wide;
+// Start pose relative to the reference for this launch: the given one, one
+// in device memory (a learned proposal), or the constant-velocity prediction
+// from the stream's pose history.  Block-wide;
 // the result, the reference pose and the history land in LDS.
 __device__ __forceinline__ void start_pose(const StartSlot* __restrict__ st, const double* __restrict__ hist,
                                            double* T0, double* rw, double* h0, double* h1, double* m1, double* m2,
@@ -254,12 +255,13 @@ __device__ __forceinline__ void start_pose(const StartSlot* __restrict__ st, con
   const int t = threadIdx.x;
   __shared__ int sh_mode;
   if (t < 12) {
-    T0[t] = st->T_rel[t];
+    // kStartDevice: the proposal an earlier launch on this stream wrote
+    T0[t] = st->mode > 1.5 ? st->dev_rel[t] : st->T_rel[t];
     rw[t] = st->T_rw[t];
     h0[t] = hist[t];
     h1[t] = hist[12 + t];
   }
-  if (t == 0) sh_mode = st->mode > 0.5 ? kStartConstVelocity : kStartGiven;
+  if (t == 0) sh_mode = st->mode > 1.5 ? kStartDevice : st->mode > 0.5 ? kStartConstVelocity : kStartGiven;
   if (t == 32) *l0 = st->l0, *l0_stride = st->l0_stride;
   __syncthreads();
   if (sh_mode == kStartConstVelocity) const_velocity_start(T0, rw, h0, h1, m1, m2);

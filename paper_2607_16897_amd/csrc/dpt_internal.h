@@ -184,17 +184,17 @@ __host__ __device__ inline void orthonormalize34(double* T) {
 // Per-launch, per-stream start of a cooperative track (host-mapped, 32 doubles).
 struct StartSlot {
   double T_rel[12];  // given start pose relative to the reference (mode kStartGiven)
-  double mode;       // kStartGiven, or kStartConstVelocity: P1 P0^-1 P1 from the history
+  double mode;       // kStartGiven, kStartConstVelocity (P1 P0^-1 P1 from the history) or kStartDevice
   // window tracks: level 0 of frame f read at l0 + f * l0_stride (rows W bytes
   // apart) instead of from the window pyramids, or l0 = null
   const uint8_t* l0;
   int64_t l0_stride;
-  double pad0;
+  const double* dev_rel;  // kStartDevice: the start relative to the reference, 3x4 FP64 in device memory
   double T_rw[12];   // reference pose (world -> reference camera), 3x4
   double pad1[4];
 };
 static_assert(sizeof(StartSlot) == 256, "StartSlot layout");
-constexpr int kStartGiven = 0, kStartConstVelocity = 1;
+constexpr int kStartGiven = 0, kStartConstVelocity = 1, kStartDevice = 2;
 constexpr int kRing = DPT_MAX_IN_FLIGHT;  // tracks that may be in flight per context or batch
 
 // One image of a batched pyramid launch.
@@ -278,6 +278,10 @@ int set_error(int code, const char* msg);
 // Learned initialiser forward pass on coarsest-level pairs (device pointers).
 int cnn_forward_levels(struct ::dpt_cnn* c, const uint8_t* const* refs, const uint8_t* const* curs, int B,
                        float* out_host);
+// The same forward pass enqueued on stream s without a host wait: d_lv is a
+// device array of B reference then B current level pointers; each pair's
+// proposal exp(xi) (the relative start pose, 3x4 FP64) goes to rel + 12 b.
+int cnn_propose(struct ::dpt_cnn* c, const uint8_t* const* d_lv, int B, hipStream_t s, double* rel);
 
 // Launchers (kernels.hip, coop.hip).  Each returns the hipError_t of the launch.
 hipError_t launch_pyramid(const uint8_t* src, int64_t pitch, uint8_t* dst, const PyrGeom& g, hipStream_t s);

@@ -1,13 +1,14 @@
-"""Learned initialiser on the GPU (BF16 MFMA forward, FP32-accumulated backward,
-Adam) against the FP64 oracle.
+"""Learned initialiser on the GPU (BF16 MFMA forward and backward with FP32
+accumulation, Adam) against the FP64 oracle.
 
 Two references: the FP64 oracle itself (per layer and per gradient tensor:
 cosine > 0.999 / relative error < 2e-2 for activations; for gradients the
 bound BF16 activation storage allows, cosine > 0.998 / relative error < 6e-2,
 measured on this data as 4.6e-2 for the first layer by the FP64 emulation
 below), and the oracle's own layers evaluated in FP64 with every stored
-activation rounded to BF16 as the GPU stores them, which must agree to
-FP32 accumulation rounding (cosine > 0.99999, relative error < 2e-3)."""
+activation and every gradient passed between convolution layers rounded to
+BF16 as the GPU stores them, which must agree to FP32 accumulation rounding
+(cosine > 0.99999, relative error < 2e-3)."""
 import numpy as np
 import pytest
 
@@ -72,7 +73,8 @@ def test_forward_matches_oracle(setup):
 
 
 def _bf16_storage_grads(q, x, tgt):
-    """Oracle layers in FP64, activations rounded to BF16 where the GPU stores them."""
+    """Oracle layers in FP64, with activations and the gradients flowing
+    between convolution layers rounded to BF16 where the GPU stores them."""
     acts, h = [x], x
     for i in range(4):
         h = _bf16(np.maximum(ocnn.conv_forward(h, q[f"w{i + 1}"], q[f"b{i + 1}"]), 0.0))
@@ -81,12 +83,20 @@ def _bf16_storage_grads(q, x, tgt):
     h1 = np.maximum(g @ q["fw1"].T + q["fb1"], 0.0)
     out = h1 @ q["fw2"].T + q["fb2"]
     loss, dout = ocnn.mse(out, tgt)
-    return loss, ocnn.backward(q, {"acts": acts, "g": g, "h1": h1}, dout)
+    grads = {"fw2": dout.T @ h1, "fb2": dout.sum(axis=0)}
+    dz1 = (dout @ q["fw2"]) * (h1 > 0)
+    grads["fw1"], grads["fb1"] = dz1.T @ g, dz1.sum(axis=0)
+    dh = np.broadcast_to((dz1 @ q["fw1"])[:, :, None, None] / (h.shape[2] * h.shape[3]), h.shape)
+    for i in range(3, -1, -1):
+        dz = _bf16(dh * (acts[i + 1] > 0))
+        dh, grads[f"w{i + 1}"], grads[f"b{i + 1}"] = ocnn.conv_backward(acts[i], q[f"w{i + 1}"], dz)
+    return loss, grads
 
 
-def test_gradients_match_oracle(setup):
+@pytest.mark.parametrize("B", [32, 5])
+def test_gradients_match_oracle(setup, B):
     dpt, net, p = setup
-    pairs, tgt = _data(32, seed=1)
+    pairs, tgt = _data(B, seed=1)
     loss = net.train_step(pairs, tgt, lr=0.0)
     g = dpt.cnn_unflatten(net.get_grads())
     q = {k: (_bf16(v) if k.startswith("w") else v) for k, v in p.items()}
@@ -100,7 +110,10 @@ def test_gradients_match_oracle(setup):
         print(f"{k}: vs oracle cos {_cos(g[k], og[k]):.6f} rel {_rel(g[k], og[k]):.2e}; "
               f"vs BF16-storage cos {_cos(g[k], eg[k]):.7f} rel {_rel(g[k], eg[k]):.2e}")
         assert _cos(g[k], eg[k]) > 0.99999 and _rel(g[k], eg[k]) < 2e-3, k
-        assert _cos(g[k], og[k]) > 0.998 and _rel(g[k], og[k]) < 6e-2, k
+        # the distance from the oracle is the one BF16 storage explains
+        assert _rel(g[k], og[k]) <= _rel(eg[k], og[k]) + 2e-3, k
+        if B == 32:  # the data the fixed bound was measured on
+            assert _cos(g[k], og[k]) > 0.998 and _rel(g[k], og[k]) < 6e-2, k
 
 
 def test_adam_step_matches_oracle(setup):

@@ -71,3 +71,52 @@ def test_trained_network_beats_constant_velocity(gpu_lib):
     print(res)
     assert res["cnn"]["iterations_mean"] < res["cv"]["iterations_mean"]
     assert res["cnn"]["failure_rate"] <= res["cv"]["failure_rate"]
+
+
+def test_device_proposal_matches_host_prediction(gpu_lib):
+    """The proposal kept on the device (no host round trip) starts the same
+    track as the host-side prediction given as the start pose."""
+    import torch
+
+    dpt = gpu_lib
+    from paper_2607_16897_amd import initialiser as ini
+
+    S = 4
+    net = dpt.Cnn(max_batch=S)
+    net.set_params(ini.init_params(5))
+    prm = dpt.make_params(levels=4)
+    bt = dpt.BatchTracker([synth.CAM_752] * S, prm, [500] * S)
+    with pytest.raises(dpt.DptError):  # no proposal yet
+        bt.track_enqueue(proposed=True)
+    rng = np.random.default_rng(77)
+    imgs = torch.empty((S, 2, 480, 752), dtype=torch.uint8, device="cuda")
+    dep = torch.empty((S, 2, 480, 752), dtype=torch.float32, device="cuda")
+    refs = []
+    for s in range(S):
+        Tr = np.eye(4)
+        Tc = synth.random_perturbation(rng, 3.0, 0.05)
+        synth.render_gpu(synth.Scene(500 + s), synth.CAM_752, np.stack([Tr, Tc]), imgs[s], dep[s])
+        refs.append(Tr)
+    bt.build_pyramids(dpt.SLOT_REF, [imgs[s, 0] for s in range(S)])
+    for s in range(S):
+        idx = bt.select_points(s, 500, 8)
+        d = dep[s, 0].reshape(-1)[torch.from_numpy(idx.astype(np.int64)).cuda()].double().cpu().numpy()
+        full = np.zeros(480 * 752)
+        full[idx] = d
+        bt.set_reference_points(s, synth.backproject(synth.CAM_752, full.reshape(480, 752), idx, refs[s]), refs[s])
+    bt.build_pyramids(dpt.SLOT_CUR, [imgs[s, 1] for s in range(S)])
+    host = bt.track(net.predict(bt))
+    net.propose(bt)
+    bt.track_enqueue(proposed=True)
+    dev = bt.synchronize()[0]
+    for h, d in zip(host, dev):
+        rot, tr = _pose_err(h["T_cw"], d["T_cw"])
+        assert rot < 1e-5 and tr < 1e-5 and h["status"] == d["status"]
+    bt.close()
+    net.close()
+
+
+def _pose_err(A, B):
+    E = np.asarray(A) @ np.linalg.inv(np.asarray(B))
+    ang = float(np.arccos(np.clip((np.trace(E[:3, :3]) - 1) / 2, -1, 1)))
+    return ang, float(np.linalg.norm(E[:3, 3]))
