@@ -348,7 +348,7 @@ def _batched_run(dpt, wins, frames, wframes, depths, T_rw, T_prev, n_streams, st
                                                           {"mode": mode, "chunk": chunk}) if window else None)}}
 
 
-def bench_batched_mixed(dpt, synth, n_streams: int, n_frames: int, reps: int):
+def bench_batched_mixed(dpt, synth, n_streams: int, n_frames: int, reps: int, keep=None):
     """Mixed batch: stream s draws its resolution from {640x480, 752x480,
     1280x720} and its map size log-uniformly in [300, 8000]; one reference and
     n_frames perturbed views (<= 1 deg, <= 2 cm) each, identity start.  Batched
@@ -358,9 +358,14 @@ def bench_batched_mixed(dpt, synth, n_streams: int, n_frames: int, reps: int):
 
     from paper_2607_16897_amd import autotune
 
+    from concurrent.futures import ThreadPoolExecutor
+
     t_r = time.perf_counter()
-    streams = [synth.stream_frames(s, n_frames=n_frames) for s in range(n_streams)]
+    with ThreadPoolExecutor(max(1, host_cpu()["share"])) as ex:  # the renderer's C calls release the GIL
+        streams = list(ex.map(lambda s: synth.stream_frames(s, n_frames=n_frames), range(n_streams)))
     render_s = time.perf_counter() - t_r
+    if keep is not None:  # the host baseline tracks the same streams
+        keep.extend(streams)
     prm = dpt.make_params(levels=3, max_iters=10, huber_k=9.0, step_eps=1e-5)
     cams = [d["cam"] for d in streams]
     npts = [d["n_points"] for d in streams]
@@ -655,11 +660,13 @@ def host_cpu() -> dict:
             "share_from": "OMP_NUM_THREADS" if "OMP_NUM_THREADS" in os.environ else "affinity"}
 
 
-def cpu_baseline(wins, seconds: float, comparisons, tween_run=None):
+def cpu_baseline(wins, seconds: float, comparisons, tween_run=None, c3_streams=None):
     """The FP64 oracle on one host thread, on the headline windows until
     `seconds` elapse.  `comparisons` maps a leg name to (frames [(window, j)],
     starts, GPU poses, camera, windows, points, levels): the oracle tracks each
-    of those frames from the same start for the pose differences."""
+    of those frames from the same start for the pose differences.  With
+    c3_streams (the mixed-resolution batch's streams), also that batch on every
+    host core of the share, one stream per thread."""
     import oracle
     import synth
 
@@ -709,6 +716,31 @@ def cpu_baseline(wins, seconds: float, comparisons, tween_run=None):
     el_all = time.perf_counter() - t0
     out["all_cores"] = {"value": round(done / el_all, 2), "unit": "frames/s", "cores": threads,
                         "sample": f"{done // (WINDOW - 1)} keyframe windows in {el_all:.1f} s, {threads} threads"}
+    if c3_streams:
+        p3 = oracle.make_params(levels=3)
+
+        def one_stream(k):  # the stream's reference, then its frames from the identity, until the budget ends
+            d = c3_streams[k % len(c3_streams)]
+            idx = oracle.select_points(d["ref"], d["n_points"], 8)
+            ref = oracle.Reference(d["cam"], p3, d["ref"], synth.backproject(d["cam"], d["depth"], idx, np.eye(4)),
+                                   np.eye(4))
+            n = 0
+            for f in d["frames"]:
+                if time.perf_counter() - t0 >= seconds / 3:
+                    break
+                ref.track(f, np.eye(4))
+                n += 1
+            return n
+
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(threads) as ex:
+            done3 = sum(ex.map(one_stream, range(threads)))
+        el3 = time.perf_counter() - t0
+        out["c3_batch_all_cores"] = {
+            "value": round(done3 / el3, 2), "unit": "frames/s", "cores": threads,
+            "per_core": round(done3 / el3 / threads, 3),
+            "sample": f"{done3} frames of the first {threads} mixed-resolution streams (one stream per thread, each "
+                      f"its reference and then its frames from the identity) in {el3:.1f} s"}
     out["host"] = host
     diffs = {}
     for name, (frames, starts, poses, cam, wset, npts, levels, *extra) in comparisons.items():
@@ -877,6 +909,19 @@ def attainable_copy_gbs(mib: int = 1024, reps: int = 10) -> float:
     del a, b
     torch.cuda.empty_cache()
     return gbs
+
+
+def attainable_peaks(dpt) -> dict:
+    """Measured roofs beside the published ones: HBM (a 1 GiB device copy), the
+    L2 (every workgroup rereading one 2 MiB buffer that every XCD's L2 holds),
+    the last-level cache (each of 8 workgroups per CU rereading its own 64 KiB,
+    128 MiB in all: above the L2s, inside the 256 MB cache) and the FP32 FMA
+    rate of the vector units as the library compiles (no packed FP32)."""
+    n_wg = 8 * 256
+    return {"hbm_copy_gbs": round(attainable_copy_gbs(), 1),
+            "l2_read_gbs": round(dpt.probe_read_bandwidth(2 << 20, 1, 1), 1),
+            "mall_read_gbs": round(dpt.probe_read_bandwidth(64 << 10, n_wg, 16), 1),
+            "fp32_fma_tflops": round(dpt.probe_fp32_fma(4096), 2)}
 
 
 def calibrate_copy(mib: int):
@@ -1064,7 +1109,8 @@ def main():
                 "pyramid_launch_ms": round(pr["pyramid_ms"] / max(pr["n_pyramid"], 1), 5),
                 "kernel": track_kernel_name(args.launch, args.chunk, w)}
 
-    att_gbs = attainable_copy_gbs()  # after the timed region
+    att = attainable_peaks(dpt)  # after the timed region
+    att_gbs = att["hbm_copy_gbs"]
     out = {
         "metric": METRIC,
         "value": round(tracked / elapsed, 2),
@@ -1103,6 +1149,7 @@ def main():
         "launch_forms": {"this": form(elapsed, stats, prof, window), "other": form(el_f, st_f, prof_f, not window),
                          "poses_bitwise_equal": same},
         "setup_render_s": round(render_s, 2),
+        "attainable": att,
     }
     nc = WINDOW - 1  # the first timed window of each leg is compared with the oracle
     comparisons = {"headline_fp32": ([(args.warmup % n_render, j) for j in range(1, WINDOW)], stats["init"][:nc],
@@ -1136,18 +1183,23 @@ def main():
         out["tween"], tw_frames, tw_dec = bench_tween(dpt, synth, 200)
         tween_run = (tw_frames, tw_dec)
         print("# tween leg done", file=sys.stderr, flush=True)
+    c3_keep = []
     if "batched" in legs:
         out["batched"] = {
             "sequences": bench_batched_sequences(dpt, synth, args.batch_streams, max(2, args.steps // 4), 1),
-            "mixed": bench_batched_mixed(dpt, synth, args.batch_streams, 4, 4),
+            "mixed": bench_batched_mixed(dpt, synth, args.batch_streams, 32, 1, keep=c3_keep),
         }
+        for o in (out["batched"]["sequences"], out["batched"]["sequences"]["mixed_precision"]):
+            r = o["roofline"]  # the window launches' working set lives in L2 and the last-level cache
+            r["frac_of_l2_read"] = round(r["achieved"] / att["l2_read_gbs"], 5)
+            r["frac_of_mall_read"] = round(r["achieved"] / att["mall_read_gbs"], 5)
         print("# batched legs done", file=sys.stderr, flush=True)
     if "init" in legs:
         out["learned_init"] = bench_learned_init(dpt, args.batch_streams, 100)
         print("# initialiser leg done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"], out["pose_diff_vs_oracle"] = cpu_baseline(wins, args.cpu_seconds, comparisons,
-                                                                        tween_run)
+                                                                        tween_run, c3_keep)
     print(json.dumps(out), flush=True)
 
 

@@ -579,6 +579,24 @@ int dpt_cnn_predict_batch(dpt_cnn* c, dpt_batch* b, double* T_cw_out);
 int dpt_cnn_propose(dpt_cnn* c, dpt_ctx* ctx);
 int dpt_cnn_propose_batch(dpt_cnn* c, dpt_batch* b);
 
+/* ------------------------------------------------------------------ device characterisation
+ * Attainable peaks for the roofline figures, measured on the current device
+ * (not part of the method).  Each call allocates, runs two launches on a
+ * private stream, times the second with events and frees; it synchronises.
+ *
+ * dpt_probe_read_bandwidth: 8 workgroups per compute unit, workgroup w reading
+ * slice w % n_slices of a zeroed buffer of n_slices x slice_bytes bytes
+ * (slice_bytes a positive multiple of 4096, the buffer at most 16 GiB) `reps`
+ * times; *gbs = bytes read / time.  One 2 MiB slice stays in every XCD's L2
+ * (the L2 read roof); one small slice per workgroup with a footprint between
+ * the L2s and the last-level cache gives that cache's roof.
+ * dpt_probe_fp32_fma: 8 workgroups per compute unit of 256 threads, each
+ * thread 8 independent FP32 FMA chains of `iters` steps, compiled like the
+ * library (no packed FP32); *tflops = 2 x FMAs / time.
+ * DPT_E_ARG on bad sizes, DPT_E_OOM, DPT_E_HIP. */
+int dpt_probe_read_bandwidth(int64_t slice_bytes, int32_t n_slices, int32_t reps, double* gbs);
+int dpt_probe_fp32_fma(int32_t iters, double* tflops);
+
 #ifdef __cplusplus
 }
 #endif

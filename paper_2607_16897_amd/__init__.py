@@ -159,6 +159,8 @@ SIGNATURES = {
     "dpt_cnn_predict": (ctypes.c_int, [_vp, _vp, _vp]),
     "dpt_cnn_predict_batch": (ctypes.c_int, [_vp, _vp, _vp]),
     "dpt_cnn_propose": (ctypes.c_int, [_vp, _vp]),
+    "dpt_probe_read_bandwidth": (ctypes.c_int, [_i64, _i32, _i32, ctypes.POINTER(ctypes.c_double)]),
+    "dpt_probe_fp32_fma": (ctypes.c_int, [_i32, ctypes.POINTER(ctypes.c_double)]),
     "dpt_cnn_propose_batch": (ctypes.c_int, [_vp, _vp]),
     "dpt_last_kernel_ms": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
 }
@@ -279,6 +281,21 @@ def cycle_profile(n_slots: int, reset: bool = True) -> np.ndarray:
     out = np.zeros((n_slots, 10), np.int64)
     _check(load().dpt_cycle_profile(out.ctypes.data, n_slots, int(bool(reset))))
     return out
+
+
+def probe_read_bandwidth(slice_bytes: int, n_slices: int, reps: int) -> float:
+    """dpt_probe_read_bandwidth: attainable read GB/s of a buffer of n_slices
+    slices of slice_bytes, each workgroup rereading one slice reps times."""
+    gbs = ctypes.c_double()
+    _check(load().dpt_probe_read_bandwidth(int(slice_bytes), int(n_slices), int(reps), ctypes.byref(gbs)))
+    return gbs.value
+
+
+def probe_fp32_fma(iters: int = 4096) -> float:
+    """dpt_probe_fp32_fma: attainable FP32 FMA TFLOP/s of the vector units."""
+    tf = ctypes.c_double()
+    _check(load().dpt_probe_fp32_fma(int(iters), ctypes.byref(tf)))
+    return tf.value
 
 
 def select_points_noalloc(img, n: int, margin: int, idx, count, stream: int | None = None):

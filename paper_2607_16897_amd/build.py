@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdptrack.so")
-SOURCES = ["dpt_kernels.hip", "dpt_select.hip", "dpt_coop.hip", "dpt_cnn.hip", "dpt_api.hip"]
+SOURCES = ["dpt_kernels.hip", "dpt_select.hip", "dpt_coop.hip", "dpt_cnn.hip", "dpt_probe.hip", "dpt_api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
