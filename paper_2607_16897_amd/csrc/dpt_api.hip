@@ -207,12 +207,19 @@ struct ProfRing {
   }
 };
 
+// n 4-byte words from host-mapped memory to device memory.
+__global__ void copy_host_words(uint32_t* __restrict__ dst, const uint32_t* __restrict__ src, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) dst[i] = src[i];
+}
+
 // A per-call argument table uploaded through pinned memory: two alternating
 // (host, device) buffers, a buffer's host side rewritten only after its
 // previous upload has run, so calls never wait for the stream otherwise.
 template <class T>
 struct StagedTable {
+  static_assert(sizeof(T) % 4 == 0, "copied in 4-byte words");
   T* h[2] = {nullptr, nullptr};
+  const T* hd[2] = {nullptr, nullptr};  // the host buffers' device addresses
   T* d[2] = {nullptr, nullptr};
   hipEvent_t ev[2] = {nullptr, nullptr};
   int cap = 0, next = 0;
@@ -220,8 +227,11 @@ struct StagedTable {
   hipError_t init(int n) {
     cap = n;
     hipError_t e;
+    // mapped and coherent: the upload is a kernel reading them over the host link
+    const unsigned fl = hipHostMallocMapped | hipHostMallocCoherent;
     for (int i = 0; i < 2; ++i) {
-      if ((e = hipHostMalloc((void**)&h[i], sizeof(T) * n)) != hipSuccess) return e;
+      if ((e = hipHostMalloc((void**)&h[i], sizeof(T) * n, fl)) != hipSuccess) return e;
+      if ((e = hipHostGetDevicePointer((void**)&hd[i], h[i], 0)) != hipSuccess) return e;
       if ((e = hipMalloc((void**)&d[i], sizeof(T) * n)) != hipSuccess) return e;
       if ((e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming)) != hipSuccess) return e;
     }
@@ -243,9 +253,16 @@ struct StagedTable {
     *host = h[*which];
     return hipEventSynchronize(ev[*which]);
   }
+  // A kernel on stream s copies the first n entries to the device (a launch
+  // in the stream's order, where a copy command would cost an engine switch).
   hipError_t upload(int which, int n, hipStream_t s, const T** dev) {
-    hipError_t e = hipMemcpyAsync(d[which], h[which], sizeof(T) * n, hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return e;
+    const int words = (int)(sizeof(T) / 4) * n;
+    if (words > 0) {
+      hipLaunchKernelGGL(copy_host_words, dim3(std::min((words + 255) / 256, 64)), dim3(256), 0, s,
+                         reinterpret_cast<uint32_t*>(d[which]), reinterpret_cast<const uint32_t*>(hd[which]), words);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
     *dev = d[which];
     return hipEventRecord(ev[which], s);
   }
@@ -1169,7 +1186,8 @@ int dpt_track_window_enqueue(dpt_ctx* c, const uint8_t* frames, int64_t pitch, i
   srcs.write_l0[0] = l0_direct ? 0 : 1;
   int ps = -1;
   if (c->prof) HIP_TRY(c->prof_pyr.begin(c->stream, &ps));
-  HIP_TRY(launch_pyramid_window(c->d_winjob, srcs, 1, n_frames, c->cam.width, c->cam.height, c->prm.levels,
+  const bool block = sst % 8 == 0 && c->win_stride % 8 == 0 && pyramid_block_ok(c->pg, src, sp, c->win);
+  HIP_TRY(launch_pyramid_window(c->d_winjob, srcs, 1, n_frames, c->cam.width, c->cam.height, c->prm.levels, block,
                                 c->stream));
   if (c->prof) HIP_TRY(c->prof_pyr.end(c->stream, ps));
   const int slot = c->slot_next;
@@ -1734,9 +1752,13 @@ int dpt_batch_build_pyramids(dpt_batch* b, int32_t slot, const uint8_t* const* i
       max_w = std::max(max_w, c->cam.width);
       max_h = std::max(max_h, c->cam.height);
     }
+    bool block = true;
+    for (int s = 0; s < b->n; ++s)
+      block = block && pyramid_block_ok(b->ctx[s]->pg, srcs.src[s], srcs.pitch[s], b->ctx[s]->pyr[slot]);
     int ps = -1;
     if (b->prof) HIP_TRY(b->prof_pyr.begin(b->stream, &ps));
-    HIP_TRY(launch_pyramid_batch_args(b->d_static[slot], srcs, b->n, max_w, max_h, b->ctx[0]->prm.levels, b->stream));
+    HIP_TRY(launch_pyramid_batch_args(b->d_static[slot], srcs, b->n, max_w, max_h, b->ctx[0]->prm.levels, block,
+                                      b->stream));
     if (b->prof) HIP_TRY(b->prof_pyr.end(b->stream, ps));
     if (!on_device) HIP_TRY(hipStreamSynchronize(b->stream));  // the host images are only borrowed
     for (int s = 0; s < b->n; ++s) {
@@ -2024,6 +2046,7 @@ int dpt_batch_track_window_enqueue(dpt_batch* b, const uint8_t* const* frames, c
     PyrWinSrc srcs;
     std::memset(&srcs, 0, sizeof srcs);
     int max_w = 0, max_h = 0;
+    bool block = true;
     for (int k = 0; k < m; ++k) {
       dpt_ctx* c = b->ctx[s0 + k];
       srcs.src[k] = src[s0 + k];
@@ -2032,8 +2055,11 @@ int dpt_batch_track_window_enqueue(dpt_batch* b, const uint8_t* const* frames, c
       srcs.write_l0[k] = sp[s0 + k] == c->cam.width ? 0 : 1;
       max_w = std::max(max_w, c->cam.width);
       max_h = std::max(max_h, c->cam.height);
+      // every frame's source rows and window pyramid aligned like the first's
+      block = block && sst[s0 + k] % 8 == 0 && c->win_stride % 8 == 0 &&
+              pyramid_block_ok(c->pg, src[s0 + k], sp[s0 + k], c->win);
     }
-    HIP_TRY(launch_pyramid_window(b->d_winjobs + s0, srcs, m, n_frames, max_w, max_h, b->ctx[0]->prm.levels,
+    HIP_TRY(launch_pyramid_window(b->d_winjobs + s0, srcs, m, n_frames, max_w, max_h, b->ctx[0]->prm.levels, block,
                                   b->stream));
   }
   if (b->prof) HIP_TRY(b->prof_pyr.end(b->stream, ps));

@@ -1034,9 +1034,28 @@ __global__ __launch_bounds__(256) void pyramid_batch_args_kernel(const PyrJob* _
                        ((pitch % 4) == 0 && (sa % 4) == 0 && (W0 % 4) == 0 && (da % 4) == 0) ? 1 : 0);
 }
 
+// pyramid_block over a batch: blockIdx.y = image, one thread per block.
+template <int LV>
+__global__ __launch_bounds__(256) void pyramid_batch_block_kernel(const PyrJob* __restrict__ jobs, PyrSrcArgs srcs) {
+  constexpr int B = 1 << (LV - 1);
+  const int z = blockIdx.y;
+  const PyrJob& j = jobs[z];
+  const int nbx = j.g.W[0] / B, t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nbx * (j.g.H[0] / B)) return;
+  pyramid_block<LV>(srcs.src[z], srcs.pitch[z], j.dst, j.g, t % nbx, t / nbx, true);
+}
+
 hipError_t launch_pyramid_batch_args(const PyrJob* d_static, const PyrSrcArgs& srcs, int n_jobs, int max_w,
-                                     int max_h, int levels, hipStream_t s) {
+                                     int max_h, int levels, bool block, hipStream_t s) {
   if (n_jobs > kPyrArgJobs) return hipErrorInvalidValue;
+  if (block) {  // every image passed pyramid_block_ok
+    const int B = 1 << (levels - 1), n = (max_w / B) * (max_h / B);
+    if (levels == 4)
+      hipLaunchKernelGGL(pyramid_batch_block_kernel<4>, dim3((n + 255) / 256, n_jobs), dim3(256), 0, s, d_static, srcs);
+    else
+      hipLaunchKernelGGL(pyramid_batch_block_kernel<3>, dim3((n + 255) / 256, n_jobs), dim3(256), 0, s, d_static, srcs);
+    return hipGetLastError();
+  }
   if (levels <= 7)
     hipLaunchKernelGGL(pyramid_batch_args_kernel<64>, dim3((max_w + 63) / 64, (max_h + 63) / 64, n_jobs), dim3(256),
                        0, s, d_static, srcs);
@@ -1074,10 +1093,33 @@ __global__ __launch_bounds__(256) void pyramid_window_kernel(const WinJob* __res
   }
 }
 
+// pyramid_block over the frames of a window: blockIdx.y = stream * n_frames + frame.
+template <int LV>
+__global__ __launch_bounds__(256) void pyramid_window_block_kernel(const WinJob* __restrict__ jobs, PyrWinSrc srcs,
+                                                                   int n_frames) {
+  constexpr int B = 1 << (LV - 1);
+  const int z = blockIdx.y, js = z / n_frames, f = z - js * n_frames;
+  const WinJob& j = jobs[js];
+  const int nbx = j.g.W[0] / B, t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nbx * (j.g.H[0] / B)) return;
+  pyramid_block<LV>(srcs.src[js] + f * srcs.stride[js], srcs.pitch[js], j.dst + f * j.dst_stride, j.g, t % nbx, t / nbx,
+                    srcs.write_l0[js] != 0);
+}
+
 hipError_t launch_pyramid_window(const WinJob* d_jobs, const PyrWinSrc& srcs, int n_streams, int n_frames, int max_w,
-                                 int max_h, int levels, hipStream_t s) {
+                                 int max_h, int levels, bool block, hipStream_t s) {
   if (n_streams < 1 || n_streams > kPyrArgJobs || n_frames < 1 || (int64_t)n_streams * n_frames > 65535)
     return hipErrorInvalidValue;
+  if (block) {  // every stream passed pyramid_block_ok for every frame
+    const int B = 1 << (levels - 1), n = (max_w / B) * (max_h / B);
+    if (levels == 4)
+      hipLaunchKernelGGL(pyramid_window_block_kernel<4>, dim3((n + 255) / 256, n_streams * n_frames), dim3(256), 0, s,
+                         d_jobs, srcs, n_frames);
+    else
+      hipLaunchKernelGGL(pyramid_window_block_kernel<3>, dim3((n + 255) / 256, n_streams * n_frames), dim3(256), 0, s,
+                         d_jobs, srcs, n_frames);
+    return hipGetLastError();
+  }
   constexpr int T64 = 64 * kWinTiles, T128 = 128 * kWinTiles;
   if (levels <= 7)
     hipLaunchKernelGGL(pyramid_window_kernel<64>, dim3((max_w + T64 - 1) / T64, (max_h + 63) / 64, n_streams * n_frames),

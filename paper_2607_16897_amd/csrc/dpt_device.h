@@ -247,6 +247,66 @@ __device__ __forceinline__ void pyramid_tile64v_at(const uint8_t* __restrict__ s
   }
 }
 
+// Rounded 2x2 box means of two rows of four bytes: bytes 0 and 1 of the
+// result hold (t0 + t1 + b0 + b1 + 2) >> 2 and (t2 + t3 + b2 + b3 + 2) >> 2.
+// The pair sums travel in two 16-bit lanes (at most 1022 each).
+__device__ __forceinline__ uint32_t box_pairs(uint32_t top, uint32_t bot) {
+  const uint32_t s = (top & 0x00ff00ffu) + ((top >> 8) & 0x00ff00ffu) + (bot & 0x00ff00ffu) + ((bot >> 8) & 0x00ff00ffu);
+  const uint32_t r = ((s + 0x00020002u) >> 2) & 0x00ff00ffu;
+  return (r & 0xffu) | ((r >> 8) & 0xff00u);
+}
+
+// The pyramid of one B x B block of level 0 (B = 2^(LV-1), LV = 3 or 4
+// levels) in one thread's registers: block (bx, by) of a level 0 whose sizes
+// are multiples of B, so every level's share of the block is whole and
+// (levels' sizes halving exactly) each level is written with one aligned
+// store per row.  Needs 8-byte aligned rows of src and dst.
+template <int LV>
+__device__ __forceinline__ void pyramid_block(const uint8_t* __restrict__ src, int64_t pitch,
+                                              uint8_t* __restrict__ dst, const PyrGeom& g, int bx, int by,
+                                              bool write_l0) {
+  static_assert(LV == 3 || LV == 4, "three or four levels");
+  constexpr int B = 1 << (LV - 1);
+  const int W0 = g.W[0];
+  if constexpr (LV == 4) {
+    uint2 r0[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) r0[r] = *reinterpret_cast<const uint2*>(src + (int64_t)(8 * by + r) * pitch + 8 * bx);
+    if (write_l0)
+#pragma unroll
+      for (int r = 0; r < 8; ++r) *reinterpret_cast<uint2*>(dst + g.off[0] + (int64_t)(8 * by + r) * W0 + 8 * bx) = r0[r];
+    uint32_t r1[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      r1[i] = box_pairs(r0[2 * i].x, r0[2 * i + 1].x) | (box_pairs(r0[2 * i].y, r0[2 * i + 1].y) << 16);
+      *reinterpret_cast<uint32_t*>(dst + g.off[1] + (int64_t)(4 * by + i) * g.W[1] + 4 * bx) = r1[i];
+    }
+    uint32_t r2[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      r2[i] = box_pairs(r1[2 * i], r1[2 * i + 1]);
+      *reinterpret_cast<uint16_t*>(dst + g.off[2] + (int64_t)(2 * by + i) * g.W[2] + 2 * bx) = (uint16_t)r2[i];
+    }
+    dst[g.off[3] + (int64_t)by * g.W[3] + bx] = (uint8_t)box_pairs(r2[0], r2[1]);
+  } else {
+    uint32_t r0[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) r0[r] = *reinterpret_cast<const uint32_t*>(src + (int64_t)(4 * by + r) * pitch + 4 * bx);
+    if (write_l0)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        *reinterpret_cast<uint32_t*>(dst + g.off[0] + (int64_t)(4 * by + r) * W0 + 4 * bx) = r0[r];
+    uint32_t r1[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      r1[i] = box_pairs(r0[2 * i], r0[2 * i + 1]);
+      *reinterpret_cast<uint16_t*>(dst + g.off[1] + (int64_t)(2 * by + i) * g.W[1] + 2 * bx) = (uint16_t)r1[i];
+    }
+    dst[g.off[2] + (int64_t)by * g.W[2] + bx] = (uint8_t)box_pairs(r1[0], r1[1]);
+  }
+  (void)B;
+}
+
 __device__ __forceinline__ void pyramid_tile64v(const uint8_t* __restrict__ src, int64_t pitch,
                                                 uint8_t* __restrict__ dst, const PyrGeom& g) {
   pyramid_tile64v_at(src, pitch, dst, g, blockIdx.x * 64, blockIdx.y * 64, true);

@@ -100,6 +100,16 @@ struct PyrGeom {
   int64_t off[kMaxLevels];
 };
 
+// Whether the one-thread-per-block pyramid applies: 3 or 4 levels, level-0
+// sizes multiples of the block (2^(levels-1)), 8-byte aligned source rows and
+// destination.
+inline bool pyramid_block_ok(const PyrGeom& g, const void* src, int64_t pitch, const void* dst) {
+  if (g.levels != 3 && g.levels != 4) return false;
+  const int B = 1 << (g.levels - 1);
+  return g.W[0] % B == 0 && g.H[0] % B == 0 && pitch % 8 == 0 && (reinterpret_cast<uintptr_t>(src) & 7) == 0 &&
+         (reinterpret_cast<uintptr_t>(dst) & 7) == 0;
+}
+
 struct PrecomputeArgs {
   const uint8_t* ref;  // reference pyramid base
   const float* reff;   // floating-point Gaussian pyramid of the reference (same offsets), or null
@@ -337,8 +347,10 @@ struct PyrSrcArgs {
   const uint8_t* src[kPyrArgJobs];
   int64_t pitch[kPyrArgJobs];
 };
+// block: every image passes pyramid_block_ok (3 or 4 levels, sizes multiples
+// of the block, 8-byte aligned rows): one thread per block of level 0.
 hipError_t launch_pyramid_batch_args(const PyrJob* d_static, const PyrSrcArgs& srcs, int n_jobs, int max_w,
-                                     int max_h, int levels, hipStream_t s);
+                                     int max_h, int levels, bool block, hipStream_t s);
 // Window tracking: the box pyramids of n_frames consecutive frames of up to
 // kPyrArgJobs streams in one launch.  Frame f of stream s is read from
 // src[s] + f * stride[s] (rows pitch[s] apart) and its pyramid written to
@@ -355,6 +367,6 @@ struct PyrWinSrc {
   int32_t write_l0[kPyrArgJobs];  // 0: the track reads level 0 from the source frames
 };
 hipError_t launch_pyramid_window(const WinJob* d_jobs, const PyrWinSrc& srcs, int n_streams, int n_frames, int max_w,
-                                 int max_h, int levels, hipStream_t s);
+                                 int max_h, int levels, bool block, hipStream_t s);
 
 }  // namespace dpt

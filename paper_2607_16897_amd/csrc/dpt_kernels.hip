@@ -25,7 +25,25 @@ __global__ __launch_bounds__(256) void pyramid64v_kernel(const uint8_t* __restri
   pyramid_tile64v(src, pitch, dst, g);
 }
 
+// One thread per block of level 0 (pyramid_block), blocks in row-major order.
+template <int LV>
+__global__ __launch_bounds__(256) void pyramid_block_kernel(const uint8_t* __restrict__ src, int64_t pitch,
+                                                            uint8_t* __restrict__ dst, PyrGeom g) {
+  constexpr int B = 1 << (LV - 1);
+  const int nbx = g.W[0] / B, t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nbx * (g.H[0] / B)) return;
+  pyramid_block<LV>(src, pitch, dst, g, t % nbx, t / nbx, true);
+}
+
 hipError_t launch_pyramid(const uint8_t* src, int64_t pitch, uint8_t* dst, const PyrGeom& g, hipStream_t s) {
+  if (pyramid_block_ok(g, src, pitch, dst)) {
+    const int B = 1 << (g.levels - 1), n = (g.W[0] / B) * (g.H[0] / B);
+    if (g.levels == 4)
+      hipLaunchKernelGGL(pyramid_block_kernel<4>, dim3((n + 255) / 256), dim3(256), 0, s, src, pitch, dst, g);
+    else
+      hipLaunchKernelGGL(pyramid_block_kernel<3>, dim3((n + 255) / 256), dim3(256), 0, s, src, pitch, dst, g);
+    return hipGetLastError();
+  }
   int vec4 = ((pitch % 4) == 0 && (reinterpret_cast<uintptr_t>(src) % 4) == 0 && (g.W[0] % 4) == 0 &&
               (reinterpret_cast<uintptr_t>(dst) % 4) == 0)
                  ? 1

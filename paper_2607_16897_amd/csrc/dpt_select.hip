@@ -63,6 +63,57 @@ __device__ __forceinline__ int cand_score(const SelGeom& g, int c) {
   return sel_score(g.img, g.pitch, g.m + x, g.m + y);
 }
 
+// Four candidates of a row at once from 4-byte loads: possible when the
+// candidate rows start 4-byte aligned (image and pitch multiples of 4, margin
+// a multiple of 4 and at least 4, so the words left and right of a group stay
+// in the row) and every row holds a multiple of 4 candidates (a group never
+// spans two rows, and the candidate total is a multiple of 4).
+__device__ __forceinline__ bool sel_vec4(const SelGeom& g) {
+  return ((uintptr_t)g.img & 3) == 0 && (g.pitch & 3) == 0 && (g.m & 3) == 0 && g.m >= 4 && (g.Wc & 3) == 0;
+}
+
+__device__ __forceinline__ int byte_of(uint32_t w, int i) { return (int)((w >> (8 * i)) & 255u); }
+
+// Scores of candidates c .. c + 3 (c a multiple of 4, sel_vec4): five aligned
+// words, the row above and below the four pixels and the row from one pixel
+// left of them to one right.
+__device__ __forceinline__ int4 cand_score4(const SelGeom& g, int c) {
+  int x, y;
+  cand_xy(g, c, &x, &y);
+  const uint8_t* p = g.img + (int64_t)(g.m + y) * g.pitch + (g.m + x);
+  const uint32_t lw = *reinterpret_cast<const uint32_t*>(p - 4), mw = *reinterpret_cast<const uint32_t*>(p),
+                 rw = *reinterpret_cast<const uint32_t*>(p + 4);
+  const uint32_t up = *reinterpret_cast<const uint32_t*>(p - g.pitch),
+                 dn = *reinterpret_cast<const uint32_t*>(p + g.pitch);
+  const int left[4] = {byte_of(lw, 3), byte_of(mw, 0), byte_of(mw, 1), byte_of(mw, 2)};
+  const int right[4] = {byte_of(mw, 1), byte_of(mw, 2), byte_of(mw, 3), byte_of(rw, 0)};
+  int sc[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int dx = right[k] - left[k], dy = byte_of(dn, k) - byte_of(up, k);
+    sc[k] = dx * dx + dy * dy;
+  }
+  return make_int4(sc[0], sc[1], sc[2], sc[3]);
+}
+
+// f(q, score) for every candidate c0 + q < C of the chunk at c0, the
+// workgroup's threads on consecutive candidates (or groups of four).
+template <class F>
+__device__ __forceinline__ void for_chunk_scores(const SelGeom& g, int c0, F&& f) {
+  if (sel_vec4(g)) {
+    for (int q = 4 * (int)threadIdx.x; q < kSelChunk; q += 4 * (int)blockDim.x) {
+      if (c0 + q >= g.C) break;
+      const int4 v = cand_score4(g, c0 + q);
+      f(q, v.x), f(q + 1, v.y), f(q + 2, v.z), f(q + 3, v.w);
+    }
+  } else {
+    for (int q = threadIdx.x; q < kSelChunk; q += blockDim.x) {
+      if (c0 + q >= g.C) break;
+      f(q, cand_score(g, c0 + q));
+    }
+  }
+}
+
 // The selection of one image (`one`), or of image blockIdx.y of a batch (`many`
 // non-null): every kernel below runs over (chunks, images) and a workgroup past
 // its image's chunk count returns at once.
@@ -84,16 +135,12 @@ __global__ __launch_bounds__(kSelThreads) void sel_hist_coarse(SelJob one, const
   __shared__ int h[256];
   for (int b = threadIdx.x; b < 256; b += blockDim.x) h[b] = 0;
   __syncthreads();
-  const int c0 = blockIdx.x * kSelChunk;
   // bin 0 (scores below 512, most of a frame) is not counted: it is the
   // candidate total minus the other bins, which spares its atomics
-  for (int q = threadIdx.x; q < kSelChunk; q += blockDim.x) {
-    const int c = c0 + q;
-    if (c < g.C) {
-      const int b = cand_score(g, c) >> 9;
-      if (b) atomicAdd(&h[b], 1);
-    }
-  }
+  for_chunk_scores(g, blockIdx.x * kSelChunk, [&](int, int sv) {
+    const int b = sv >> 9;
+    if (b) atomicAdd(&h[b], 1);
+  });
   __syncthreads();
   for (int b = threadIdx.x + 1; b < 256; b += blockDim.x)
     if (h[b]) atomicAdd(&sc[SelScratch::kHist1 + b], h[b]);
@@ -162,14 +209,9 @@ __global__ __launch_bounds__(kSelThreads) void sel_hist_fine(SelJob one, const S
   __syncthreads();
   const int B = sB;
   if (B < 0) return;
-  const int c0 = blockIdx.x * kSelChunk;
-  for (int q = threadIdx.x; q < kSelChunk; q += blockDim.x) {
-    const int c = c0 + q;
-    if (c < g.C) {
-      const int s = cand_score(g, c);
-      if ((s >> 9) == B) atomicAdd(&h[s & 511], 1);
-    }
-  }
+  for_chunk_scores(g, blockIdx.x * kSelChunk, [&](int, int sv) {
+    if ((sv >> 9) == B) atomicAdd(&h[sv & 511], 1);
+  });
   __syncthreads();
   for (int b = threadIdx.x; b < 512; b += blockDim.x)
     if (h[b]) atomicAdd(&sc[SelScratch::kHist2 + b], h[b]);
@@ -196,16 +238,11 @@ __global__ __launch_bounds__(kSelThreads) void sel_count(SelJob one, const SelJo
   }
   __syncthreads();
   const int T = sT;
-  const int c0 = blockIdx.x * kSelChunk;
   int gt = 0, eq = 0;
-  for (int q = threadIdx.x; q < kSelChunk; q += blockDim.x) {
-    const int c = c0 + q;
-    if (c < g.C) {
-      const int s = cand_score(g, c);
-      gt += s > T;
-      eq += s == T;
-    }
-  }
+  for_chunk_scores(g, blockIdx.x * kSelChunk, [&](int, int sv) {
+    gt += sv > T;
+    eq += sv == T;
+  });
 #pragma unroll
   for (int d = 32; d > 0; d >>= 1) {
     gt += __shfl_xor(gt, d, 64);
@@ -268,7 +305,9 @@ __global__ __launch_bounds__(kSelThreads) void sel_write(SelJob one, const SelJo
   {
     int* sv = reinterpret_cast<int*>(s_score);
     const int cb = blockIdx.x * kSelChunk;
-    for (int q = threadIdx.x; q < kSelChunk; q += blockDim.x) sv[q] = cb + q < g.C ? cand_score(g, cb + q) : -2;
+    for (int q = threadIdx.x; q < kSelChunk; q += blockDim.x)
+      if (cb + q >= g.C) sv[q] = -2;  // past the last candidate
+    for_chunk_scores(g, cb, [&](int q, int v) { sv[q] = v; });
   }
   __syncthreads();
   const int T = sT, need = sNeed;

@@ -53,8 +53,12 @@ def test_pyramid_bit_exact(gpu_lib, cam, levels):
 
 
 # ------------------------------------------------------------------ selection
-@pytest.mark.parametrize("case", ["c1", "c2", "hd16k", "ties", "all"])
+@pytest.mark.parametrize("case", ["c1", "c2", "hd16k", "ties", "all", "odd", "m4"])
 def test_selection_bit_exact(gpu_lib, case):
+    """c1, c2, hd16k and m4 take the four-candidate reads (aligned rows, a
+    margin that is a multiple of 4, candidate rows a multiple of 4 long; m4 at
+    the smallest such margin, whose left word starts at column 0); ties, all
+    and odd (45 candidates per row) the one-candidate reads."""
     dpt = gpu_lib
     if case == "c1":
         img, cam, n, m = synth.pair(0)["ref"], synth.CAM_640, 500, 8
@@ -69,6 +73,14 @@ def test_selection_bit_exact(gpu_lib, case):
         cam = synth.Camera(200, 100, 100, 100, 100, 50)
         img = (np.random.default_rng(1).integers(0, 3, (100, 200)) * 40).astype(np.uint8)
         n, m = 3000, 3
+    elif case == "odd":
+        cam = synth.Camera(61, 50, 50, 50, 30, 25)
+        img = np.random.default_rng(3).integers(0, 256, (50, 61), dtype=np.uint8)
+        n, m = 700, 8
+    elif case == "m4":
+        cam = synth.Camera(68, 44, 50, 50, 34, 22)
+        img = np.random.default_rng(4).integers(0, 256, (44, 68), dtype=np.uint8)
+        n, m = 900, 4
     else:
         cam = synth.Camera(64, 40, 50, 50, 32, 20)
         img = np.random.default_rng(2).integers(0, 256, (40, 64), dtype=np.uint8)
