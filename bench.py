@@ -180,16 +180,22 @@ def collect(results, wins_done, stats):
             stats["gt"].append(win["gts"][j])
 
 
+REF_STREAM = True  # reference updates on a second stream (the --single-stream flag turns it off)
+
+
 def timed_plain(dpt, synth, wins, dev, steps, warmup, prm, launch, chunk, n_points=N_POINTS, cam=None, window=True):
     """warmup + steps keyframe windows through one context, enqueued
     asynchronously (window tracks, or frame by frame); the first timed window is
-    wins[warmup % len(wins)].  Returns (elapsed s, stats, profile totals of the
-    timed region)."""
+    wins[warmup % len(wins)].  With REF_STREAM each keyframe's reference update
+    runs on a second stream beside the previous window's tracks.  Returns
+    (elapsed s, stats, profile totals of the timed region)."""
     import torch
 
     cam = cam or CAM
     trk = dpt.Tracker(cam, prm, max_points=n_points)
     trk.set_launch_config(launch, chunk)
+    if REF_STREAM:
+        trk.set_reference_stream(torch.cuda.Stream())
     n = len(wins)
     every = PROFILE_EVERY if not window else PROFILE_EVERY_WINDOW
     for w in range(warmup):
@@ -1024,6 +1030,8 @@ def main():
                     help="headline launch form: one window track per keyframe window (9 frames, bitwise the same "
                          "poses) or frame by frame; the other form is measured beside it")
     ap.add_argument("--batch-streams", type=int, default=64)
+    ap.add_argument("--single-stream", action="store_true",
+                    help="reference updates on the context's own stream instead of a second one")
     ap.add_argument("--only-headline", action="store_true", help="skip the batched, precision, fixed-H and initialiser legs")
     ap.add_argument("--legs", default="mixed,fixed,paper,tween,batched,init",
                     help="legs after the headline: any of mixed, fixed, paper, tween, batched, init (comma separated)")
@@ -1057,6 +1065,8 @@ def main():
         pmc_leg(args, args.pmc_leg, args.pmc_meta)
         return
     legs = set() if args.only_headline else set(x for x in args.legs.split(",") if x)
+    global REF_STREAM
+    REF_STREAM = not args.single_stream
     if args.cycle_split:
         cycle_split(args, legs)
         return

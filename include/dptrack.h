@@ -199,6 +199,21 @@ enum { DPT_INIT_GIVEN = 0, DPT_INIT_CONST_VELOCITY = 1, DPT_INIT_PROPOSED = 2 };
 /* Most tracks (frames) enqueued and not yet synchronised, per context or batch. */
 #define DPT_MAX_IN_FLIGHT 256
 
+/* Run reference updates on a second stream (hip_stream; NULL or the context's
+ * own stream: back to one stream), so that a keyframe's reference update (the
+ * reference pyramid, selection, back-projection and IC precompute of
+ * Sec. IV-C) overlaps the tracks of the previous keyframe's frames.  The
+ * context then holds two reference banks: an update starts with
+ * dpt_build_pyramid(DPT_SLOT_REF) (dpt_set_reference_points and
+ * dpt_set_reference_from_depth without one return DPT_E_STATE), writes the bank
+ * the tracks do not read once the tracks that read it last have run, and the
+ * first track or test hook after it waits (on the context's stream) for the
+ * update.  Results are those of the single-stream form.  Inputs of an update
+ * (images, depth maps) are read on the reference stream: the caller orders
+ * their producers before it.  The first call allocates the second bank; the
+ * call waits for both streams.  DPT_E_STATE while an update is open. */
+int dpt_set_reference_stream(dpt_ctx* ctx, void* hip_stream);
+
 /* Asynchronous form of dpt_track_frame (the same computation, Sec. IV-C
  * "Track"): enqueue the track of the CUR pyramid on the context's stream and
  * return at once, so frames can follow each other without the host waiting

@@ -159,6 +159,7 @@ SIGNATURES = {
     "dpt_cnn_predict": (ctypes.c_int, [_vp, _vp, _vp]),
     "dpt_cnn_predict_batch": (ctypes.c_int, [_vp, _vp, _vp]),
     "dpt_cnn_propose": (ctypes.c_int, [_vp, _vp]),
+    "dpt_set_reference_stream": (ctypes.c_int, [_vp, _vp]),
     "dpt_probe_read_bandwidth": (ctypes.c_int, [_i64, _i32, _i32, ctypes.POINTER(ctypes.c_double)]),
     "dpt_probe_fp32_fma": (ctypes.c_int, [_i32, ctypes.POINTER(ctypes.c_double)]),
     "dpt_cnn_propose_batch": (ctypes.c_int, [_vp, _vp]),
@@ -417,6 +418,14 @@ class Tracker:
         _check(self._lib.dpt_tween_frame(self._h, p, self.cam.width, dev, ctypes.byref(r)))
         return dict(decision=r.decision, direct_since_ref=r.direct_since_ref, tracked=bool(r.tracked),
                     baseline=r.baseline, track=r.track.as_dict() if r.tracked else None)
+
+    def set_reference_stream(self, stream=None):
+        """Reference updates on a second stream (a torch.cuda.Stream or a raw
+        handle; None: back to the context's stream), overlapping the tracks of
+        the previous reference; an update then starts with build_pyramid(SLOT_REF)."""
+        handle = getattr(stream, "cuda_stream", stream)
+        _check(self._lib.dpt_set_reference_stream(self._h, handle))
+        self.ref_stream = stream
 
     def track_enqueue(self, T_cw_init=None, proposed: bool = False):
         """Enqueue a track without waiting: from T_cw_init, (None) from the

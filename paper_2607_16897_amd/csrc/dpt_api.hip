@@ -268,6 +268,21 @@ struct StagedTable {
   }
 };
 
+// The reference state that a reference update writes and the tracks read:
+// one bank.  With a reference stream a context holds two and alternates.
+struct RefBank {
+  uint8_t* pyr_ref = nullptr;
+  float* pyrf_ref = nullptr;
+  float4* x0 = nullptr;
+  uint8_t* valid = nullptr;
+  float *I0 = nullptr, *gx = nullptr, *gy = nullptr;
+  __half* I0h = nullptr;
+  __half2* gh = nullptr;
+  float* pts = nullptr;
+  FixedH* d_fixed = nullptr;
+  float* d_hpart = nullptr;
+};
+
 }  // namespace dpt
 
 struct dpt_ctx {
@@ -323,6 +338,18 @@ struct dpt_ctx {
   int32_t win_cap = 0;
   uint8_t* win_staging = nullptr;  // level 0 of host frames, win_cap frames of W x H
   WinJob* d_winjob = nullptr;      // this context's window pyramid job (device)
+  // reference stream (dpt_set_reference_stream): reference updates run there,
+  // into the bank the tracks in flight do not read; the fields above hold the
+  // bank last written (committed once have_ref is set)
+  hipStream_t rstream = nullptr;
+  RefBank alt;                 // the other bank
+  RefBank phys[2];             // the banks' buffers by identity (bank 0: allocated at creation)
+  int32_t bank = 0;            // which of phys[] the fields hold
+  int32_t bank_n[2] = {0, 0};  // points committed to each bank
+  hipEvent_t ev_read[2] = {nullptr, nullptr};  // context stream: past the last track that read bank b
+  hipEvent_t ev_ready = nullptr;               // reference stream: the last committed update done
+  bool update_open = false;    // a reference update has started writing the fields' bank
+  bool commit_pending = false;  // committed, the context's stream not yet ordered after it
   // tween-window schedule (host state)
   dpt_tween_policy tween{};
   bool tween_policy = false, tween_anchored = false, tween_needs_anchor = false;
@@ -335,6 +362,12 @@ struct dpt_ctx {
     if (d_hist) (void)hipFree(d_hist);
     if (d_prop) (void)hipFree(d_prop);
     if (d_cnn_lv) (void)hipFree(d_cnn_lv);
+    for (void* p : {(void*)alt.pyr_ref, (void*)alt.pyrf_ref, (void*)alt.x0, (void*)alt.valid, (void*)alt.I0,
+                    (void*)alt.gx, (void*)alt.gy, (void*)alt.I0h, (void*)alt.gh, (void*)alt.pts, (void*)alt.d_fixed,
+                    (void*)alt.d_hpart})
+      if (p) (void)hipFree(p);
+    for (hipEvent_t e : {ev_read[0], ev_read[1], ev_ready})
+      if (e) (void)hipEventDestroy(e);
     if (ev_pts) (void)hipEventDestroy(ev_pts);
     if (h_pts) (void)hipHostFree(h_pts);
     if (h_sel) (void)hipHostFree(h_sel);
@@ -385,6 +418,65 @@ void fill_track_args(const dpt_ctx* c, TrackArgs& a) {
   a.ref.cap = c->cap;
   a.out = c->d_out;
   a.totals = c->d_tot;
+}
+
+RefBank fields_bank(const dpt_ctx* c) {
+  RefBank b;
+  b.pyr_ref = c->pyr[DPT_SLOT_REF];
+  b.pyrf_ref = c->pyrf[DPT_SLOT_REF];
+  b.x0 = c->x0, b.valid = c->valid, b.I0 = c->I0, b.gx = c->gx, b.gy = c->gy, b.I0h = c->I0h, b.gh = c->gh;
+  b.pts = c->pts, b.d_fixed = c->d_fixed, b.d_hpart = c->d_hpart;
+  return b;
+}
+
+void set_fields(dpt_ctx* c, const RefBank& b) {
+  c->pyr[DPT_SLOT_REF] = b.pyr_ref;
+  c->pyrf[DPT_SLOT_REF] = b.pyrf_ref;
+  c->x0 = b.x0, c->valid = b.valid, c->I0 = b.I0, c->gx = b.gx, c->gy = b.gy, c->I0h = b.I0h, c->gh = b.gh;
+  c->pts = b.pts, c->d_fixed = b.d_fixed, c->d_hpart = b.d_hpart;
+}
+
+// The reference cache of bank b as the cooperative engine's descriptor holds it.
+RefCache refcache_of(const dpt_ctx* c, int b) {
+  const RefBank& k = c->phys[b].x0 ? c->phys[b] : c->phys[0];
+  const bool fixed = (c->prm.flags & DPT_FLAG_FIXED_H) != 0;
+  RefCache r;
+  std::memset(&r, 0, sizeof r);
+  r.x0 = k.x0, r.valid = k.valid, r.I0 = k.I0, r.gx = k.gx, r.gy = k.gy, r.I0h = k.I0h, r.gh = k.gh;
+  r.fixed = fixed ? k.d_fixed : nullptr;
+  r.n = c->phys[b].x0 ? c->bank_n[b] : c->bank_n[0];
+  r.cap = c->cap;
+  return r;
+}
+
+// The stream reference updates run on.
+hipStream_t ref_stream(const dpt_ctx* c) { return c->rstream ? c->rstream : c->stream; }
+
+// Before the context's stream reads the reference (a track, a test hook):
+// after an update committed on the reference stream, mark the end of the
+// other bank's readers and order the context's stream after the update.
+int consume_commit(dpt_ctx* c) {
+  if (!c->commit_pending) return DPT_OK;
+  HIP_TRY(hipEventRecord(c->ev_read[c->bank ^ 1], c->stream));
+  HIP_TRY(hipStreamWaitEvent(c->stream, c->ev_ready, 0));
+  c->commit_pending = false;
+  return DPT_OK;
+}
+
+// A reference update starts (a reference pyramid build).  With a reference
+// stream the fields switch to the bank the tracks do not read, and the
+// reference stream waits for the tracks that read that bank last.
+int open_update(dpt_ctx* c) {
+  if (!c->rstream || c->update_open) return DPT_OK;
+  int e = consume_commit(c);  // an update without tracks since the last one: its readers are ordered here
+  if (e != DPT_OK) return e;
+  const RefBank cur = fields_bank(c);
+  set_fields(c, c->alt);
+  c->alt = cur;
+  c->bank ^= 1;
+  HIP_TRY(hipStreamWaitEvent(c->rstream, c->ev_read[c->bank], 0));
+  c->update_open = true;
+  return DPT_OK;
 }
 
 void rel_pose_f32(const dpt_ctx* c, const double* T_cw, float* out12) {
@@ -495,6 +587,7 @@ int dpt_create(const dpt_camera* cam, const dpt_params* prm, int32_t max_points,
     delete c;
     return e;
   }
+  c->phys[0] = fields_bank(c);
   static const double kIdentity[12] = {1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0};
   if (launch_set_history(c->d_hist, kIdentity, kIdentity, c->stream) != hipSuccess) {
     (void)hipGetLastError();
@@ -508,6 +601,7 @@ int dpt_create(const dpt_camera* cam, const dpt_params* prm, int32_t max_points,
 void dpt_destroy(dpt_ctx* ctx) {
   if (!ctx) return;
   (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->rstream) (void)hipStreamSynchronize(ctx->rstream);
   delete ctx;
 }
 
@@ -517,22 +611,29 @@ int dpt_build_pyramid(dpt_ctx* c, int32_t slot, const uint8_t* img, int64_t pitc
   if (img_on_device != 0 && img_on_device != 1) return fail(DPT_E_ARG, "img_on_device %d is neither 0 nor 1", img_on_device);
   if (slot != DPT_SLOT_REF && slot != DPT_SLOT_CUR) return fail(DPT_E_ARG, "slot %d", slot);
   if (pitch < c->cam.width) return fail(DPT_E_ARG, "pitch %lld < width %d", (long long)pitch, c->cam.width);
+  if (slot == DPT_SLOT_REF) {
+    const int e = open_update(c);
+    if (e != DPT_OK) return e;
+  }
+  // a reference pyramid belongs to the reference stream (the context's own without one)
+  const hipStream_t st = slot == DPT_SLOT_REF ? ref_stream(c) : c->stream;
   const uint8_t* src = img;
   int64_t sp = pitch;
+  uint8_t* stage = c->staging;
   if (!img_on_device) {
-    HIP_TRY(hipMemcpy2DAsync(c->staging, c->cam.width, img, pitch, c->cam.width, c->cam.height,
-                             hipMemcpyHostToDevice, c->stream));
-    src = c->staging;
+    HIP_TRY(hipMemcpy2DAsync(stage, c->cam.width, img, pitch, c->cam.width, c->cam.height, hipMemcpyHostToDevice, st));
+    src = stage;
     sp = c->cam.width;
   }
   int ps = -1;
-  if (c->prof) HIP_TRY(c->prof_pyr.begin(c->stream, &ps));
-  HIP_TRY(launch_pyramid(src, sp, c->pyr[slot], c->pg, c->stream));
-  if (c->pyrf[slot]) HIP_TRY(launch_pyramid_gauss(src, sp, c->pyrf[slot], c->pg, c->stream));
-  if (c->prof) HIP_TRY(c->prof_pyr.end(c->stream, ps));
+  const bool prof = c->prof && st == c->stream;  // the profile ring times the context's stream
+  if (prof) HIP_TRY(c->prof_pyr.begin(c->stream, &ps));
+  HIP_TRY(launch_pyramid(src, sp, c->pyr[slot], c->pg, st));
+  if (c->pyrf[slot]) HIP_TRY(launch_pyramid_gauss(src, sp, c->pyrf[slot], c->pg, st));
+  if (prof) HIP_TRY(c->prof_pyr.end(c->stream, ps));
   c->have_pyr[slot] = true;
   if (slot == DPT_SLOT_REF) c->have_ref = false;
-  if (!img_on_device) HIP_TRY(hipStreamSynchronize(c->stream));  // the host buffer is only borrowed
+  if (!img_on_device) HIP_TRY(hipStreamSynchronize(st));  // the host buffer is only borrowed
   return DPT_OK;
 }
 
@@ -584,13 +685,14 @@ int dpt_select_points(dpt_ctx* c, int32_t n, int32_t margin, int32_t* host_idx, 
   if (n < 1 || (int64_t)n > (int64_t)c->cam.width * c->cam.height) return fail(DPT_E_ARG, "n %d", n);
   if (margin < 1 || 2 * margin >= c->cam.width || 2 * margin >= c->cam.height) return fail(DPT_E_ARG, "margin %d", margin);
   if (!c->have_pyr[DPT_SLOT_REF]) return fail(DPT_E_STATE, "no reference pyramid");
+  const hipStream_t rs = ref_stream(c);  // the reference pyramid belongs to the reference stream
   HIP_TRY(launch_select(c->pyr[DPT_SLOT_REF], c->cam.width, c->cam.height, margin, n, c->sel_idx, c->sel_count,
-                        c->sel_scratch, c->stream));
+                        c->sel_scratch, rs));
   // count and the first min(n, cap) indices come back with one synchronisation
   const int32_t first = n < c->cap ? n : c->cap;
-  HIP_TRY(hipMemcpyAsync(c->h_sel, c->sel_count, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(hipMemcpyAsync(c->h_sel + 1, c->sel_idx, (size_t)first * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(hipStreamSynchronize(c->stream));
+  HIP_TRY(hipMemcpyAsync(c->h_sel, c->sel_count, sizeof(int32_t), hipMemcpyDeviceToHost, rs));
+  HIP_TRY(hipMemcpyAsync(c->h_sel + 1, c->sel_idx, (size_t)first * sizeof(int32_t), hipMemcpyDeviceToHost, rs));
+  HIP_TRY(hipStreamSynchronize(rs));
   const int32_t cnt = c->h_sel[0];
   if (cnt < 0 || cnt > n) return fail(DPT_E_HIP, "selection returned %d of %d", cnt, n);
   std::memcpy(host_idx, c->h_sel + 1, (size_t)std::min(cnt, first) * sizeof(int32_t));
@@ -632,19 +734,33 @@ PrecomputeArgs precompute_args(const dpt_ctx* c, const float* P, int32_t n, cons
   return a;
 }
 
-void commit_reference(dpt_ctx* c, int32_t n, const double T_rw[16]) {
+int commit_reference(dpt_ctx* c, int32_t n, const double T_rw[16], bool record = true) {
   std::memcpy(c->T_rw, T_rw, sizeof c->T_rw);
   c->n_points = n;
   c->have_ref = true;
+  c->bank_n[c->bank] = n;
+  if (c->rstream) {
+    if (record) HIP_TRY(hipEventRecord(c->ev_ready, c->rstream));
+    c->commit_pending = true;
+    c->update_open = false;
+  }
+  return DPT_OK;
+}
+
+// With a reference stream, a reference update starts with a new reference
+// pyramid (which selects the bank it writes).
+int check_update_open(const dpt_ctx* c) {
+  if (c->rstream && !c->update_open)
+    return fail(DPT_E_STATE, "with a reference stream, a reference update starts with dpt_build_pyramid(DPT_SLOT_REF)");
+  return DPT_OK;
 }
 
 // IC precompute of the reference cache from n device points P at T_rw.
 int precompute_reference(dpt_ctx* c, const float* P, int32_t n, const double T_rw[16]) {
   const PrecomputeArgs a = precompute_args(c, P, n, T_rw);
-  HIP_TRY(launch_precompute(a, c->stream));
-  if (c->prm.flags & DPT_FLAG_FIXED_H) HIP_TRY(launch_fixed_h(a, c->stream));
-  commit_reference(c, n, T_rw);
-  return DPT_OK;
+  HIP_TRY(launch_precompute(a, ref_stream(c)));
+  if (c->prm.flags & DPT_FLAG_FIXED_H) HIP_TRY(launch_fixed_h(a, ref_stream(c)));
+  return commit_reference(c, n, T_rw);
 }
 
 }  // namespace
@@ -658,6 +774,8 @@ int dpt_set_reference_points(dpt_ctx* c, const float* xyz, int32_t n, const doub
   if (n < 0 || n > c->cap) return fail(DPT_E_ARG, "n %d outside [0, %d]", n, c->cap);
   if (!finite16(T_rw)) return fail(DPT_E_ARG, "T_rw not finite");
   if (!c->have_pyr[DPT_SLOT_REF]) return fail(DPT_E_STATE, "no reference pyramid");
+  int e = check_update_open(c);
+  if (e != DPT_OK) return e;
   const float* P = xyz;
   if (n > 0 && !on_device) {
     // staged through pinned memory: the caller's buffer is free on return and
@@ -665,8 +783,8 @@ int dpt_set_reference_points(dpt_ctx* c, const float* xyz, int32_t n, const doub
     // previous upload out of it has run
     HIP_TRY(hipEventSynchronize(c->ev_pts));
     std::memcpy(c->h_pts, xyz, (size_t)n * 3 * sizeof(float));
-    HIP_TRY(hipMemcpyAsync(c->pts, c->h_pts, (size_t)n * 3 * sizeof(float), hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipEventRecord(c->ev_pts, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->pts, c->h_pts, (size_t)n * 3 * sizeof(float), hipMemcpyHostToDevice, ref_stream(c)));
+    HIP_TRY(hipEventRecord(c->ev_pts, ref_stream(c)));
     P = c->pts;
   }
   return precompute_reference(c, P, n, T_rw);
@@ -683,21 +801,24 @@ int dpt_set_reference_from_depth(dpt_ctx* c, int32_t n, int32_t margin, const fl
   if (depth_pitch < c->cam.width) return fail(DPT_E_ARG, "depth pitch %lld < width %d", (long long)depth_pitch, c->cam.width);
   if (!finite16(T_rw)) return fail(DPT_E_ARG, "T_rw not finite");
   if (!c->have_pyr[DPT_SLOT_REF]) return fail(DPT_E_STATE, "no reference pyramid");
+  int e = check_update_open(c);
+  if (e != DPT_OK) return e;
+  const hipStream_t rs = ref_stream(c);
   const float* D = depth;
   int64_t pitch = depth_pitch;
   if (!depth_on_device) {
     if (!c->depth_stage) {
-      const int e = dev_alloc((void**)&c->depth_stage, (size_t)c->cam.width * c->cam.height * sizeof(float));
-      if (e) return e;
+      const int e2 = dev_alloc((void**)&c->depth_stage, (size_t)c->cam.width * c->cam.height * sizeof(float));
+      if (e2) return e2;
     }
     HIP_TRY(hipMemcpy2DAsync(c->depth_stage, c->cam.width * sizeof(float), depth, depth_pitch * sizeof(float),
-                             c->cam.width * sizeof(float), c->cam.height, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));  // pageable source
+                             c->cam.width * sizeof(float), c->cam.height, hipMemcpyHostToDevice, rs));
+    HIP_TRY(hipStreamSynchronize(rs));  // pageable source
     D = c->depth_stage;
     pitch = c->cam.width;
   }
   HIP_TRY(launch_select(c->pyr[DPT_SLOT_REF], c->cam.width, c->cam.height, margin, n, c->sel_idx, c->sel_count,
-                        c->sel_scratch, c->stream));
+                        c->sel_scratch, rs));
   BackprojectArgs b;
   b.idx = c->sel_idx;
   b.count = c->sel_count;
@@ -708,9 +829,72 @@ int dpt_set_reference_from_depth(dpt_ctx* c, int32_t n, int32_t margin, const fl
   b.fx = c->cam.fx, b.fy = c->cam.fy, b.cx = c->cam.cx, b.cy = c->cam.cy;
   for (int j = 0; j < 12; ++j) b.T_rw[j] = T_rw[j];
   b.P = c->pts;
-  HIP_TRY(launch_backproject(b, c->stream));
+  HIP_TRY(launch_backproject(b, rs));
   return precompute_reference(c, c->pts, n, T_rw);
 }
+
+}  // extern "C"
+
+namespace {
+
+int synchronize(dpt_ctx* c);
+
+// Allocate the second reference bank of a context (the buffers a reference
+// update writes: reference pyramid, cache, points, fixed-H state).
+int alloc_alt_bank(dpt_ctx* c) {
+  if (c->phys[1].x0) return DPT_OK;
+  const size_t L = (size_t)c->prm.levels, cap = (size_t)c->cap, K = (size_t)c->prm.n_pattern;
+  RefBank& b = c->phys[1];
+  int e;
+  if ((e = dev_alloc((void**)&b.pyr_ref, (size_t)c->pyr_bytes)) || (e = dev_alloc((void**)&b.x0, cap * sizeof(float4))) ||
+      (e = dev_alloc((void**)&b.valid, L * cap)) || (e = dev_alloc((void**)&b.I0, L * cap * K * sizeof(float))) ||
+      (e = dev_alloc((void**)&b.gx, L * cap * K * sizeof(float))) ||
+      (e = dev_alloc((void**)&b.gy, L * cap * K * sizeof(float))) || (e = dev_alloc((void**)&b.pts, cap * 3 * sizeof(float))))
+    return e;
+  if (c->pyrf[DPT_SLOT_REF] && (e = dev_alloc((void**)&b.pyrf_ref, (size_t)c->pyr_bytes * sizeof(float)))) return e;
+  if (c->d_fixed && ((e = dev_alloc((void**)&b.d_fixed, L * sizeof(FixedH))) ||
+                     (e = dev_alloc((void**)&b.d_hpart, L * ((cap + 255) / 256) * 21 * sizeof(float)))))
+    return e;
+  if (c->I0h && ((e = dev_alloc((void**)&b.I0h, L * cap * K * sizeof(__half))) ||
+                 (e = dev_alloc((void**)&b.gh, L * cap * K * sizeof(__half2)))))
+    return e;
+  for (hipEvent_t* ev : {&c->ev_read[0], &c->ev_read[1], &c->ev_ready})
+    if (!*ev) HIP_TRY(hipEventCreateWithFlags(ev, hipEventDisableTiming));
+  return DPT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dpt_set_reference_stream(dpt_ctx* c, void* hip_stream) {
+  g_err.clear();
+  if (!c) return fail(DPT_E_ARG, "NULL context");
+  if (c->update_open) return fail(DPT_E_STATE, "a reference update is open: finish it first");
+  hipStream_t rs = static_cast<hipStream_t>(hip_stream);
+  if (rs == c->stream) rs = nullptr;  // the context's own stream: no separate reference stream
+  // everything in flight on either stream finishes first
+  int e;
+  if (!c->pending.empty() && (e = synchronize(c)) != DPT_OK) return e;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (c->rstream) HIP_TRY(hipStreamSynchronize(c->rstream));
+  c->commit_pending = false;
+  if (rs) {
+    const bool fresh = !c->phys[1].x0;
+    if ((e = alloc_alt_bank(c)) != DPT_OK) return e;
+    if (fresh) {  // the fields hold bank 0: the other one is bank 1
+      c->alt = c->phys[1];
+      c->bank_n[1] = 0;
+    }
+    if (c->eng_ready) c->eng.dirty = true;  // the descriptors gain the second bank
+  }
+  c->rstream = rs;
+  return DPT_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
 
 int dpt_tween_set_policy(dpt_ctx* c, const dpt_tween_policy* p) {
   g_err.clear();
@@ -840,7 +1024,8 @@ bool use_coop(dpt_ctx* c) {
 // refreshed when the map changed size.
 int ensure_engine(dpt_ctx* c) {
   const int threads = coop_threads(c->prm, c->chunk, c->launch_mode), ppc = coop_ppc(c->prm, c->chunk);
-  const int nch = c->n_points > 0 ? (c->n_points + ppc - 1) / ppc : 1;
+  const int nmax = std::max(c->n_points, std::max(c->bank_n[0], c->bank_n[1]));
+  const int nch = nmax > 0 ? (nmax + ppc - 1) / ppc : 1;
   if (8 * nch > coop_max_blocks(threads))
     return fail(DPT_E_ARG, "%d points exceed the cooperative capacity at %d points per chunk", c->n_points, ppc);
   if (!c->eng_ready) {
@@ -848,10 +1033,13 @@ int ensure_engine(dpt_ctx* c) {
     c->eng.variant = coop_variant(c->prm, c->launch_mode);
     c->eng_ready = true;
   }
-  if (c->eng.dirty || c->eng.h_streams[0].a.ref.n != c->n_points) {
+  const RefCache r0 = refcache_of(c, 0), r1 = refcache_of(c, 1);
+  if (c->eng.dirty || c->eng.h_streams[0].a.ref.n != r0.n || c->eng.h_streams[0].ref_alt.n != r1.n ||
+      c->eng.h_streams[0].ref_alt.x0 != r1.x0) {
     TrackArgs a;
     fill_track_args(c, a);
-    c->eng.set_stream(0, a, c->d_hist, c->win, c->win_stride);
+    a.ref = r0;
+    c->eng.set_stream(0, a, r1, c->d_hist, c->win, c->win_stride);
   }
   if (c->eng.dirty) HIP_TRY(c->eng.upload());
   return DPT_OK;
@@ -863,6 +1051,7 @@ void fill_start(const dpt_ctx* c, int mode, const double* T_cw_init, StartSlot* 
   st->mode = mode;
   if (mode == kStartGiven) rel_pose_f32(c, T_cw_init, st->T_rel);
   st->dev_rel = dev_rel;
+  st->bank = c->bank;  // the committed reference (the fields' bank)
   for (int j = 0; j < 12; ++j) st->T_rw[j] = c->T_rw[j];
 }
 
@@ -1017,10 +1206,12 @@ int track_workgroup(dpt_ctx* c, const double T_cw_init[16], dpt_result* out) {
   return DPT_OK;
 }
 
-int check_track_state(const dpt_ctx* c) {
+// Every track passes here: the reference must be committed, and the
+// context's stream is ordered after an update on the reference stream.
+int check_track_state(dpt_ctx* c) {
   if (!c->have_ref) return fail(DPT_E_STATE, "no reference points");
   if (!c->have_pyr[DPT_SLOT_CUR]) return fail(DPT_E_STATE, "no current pyramid");
-  return DPT_OK;
+  return consume_commit(c);
 }
 
 // Window pyramids for n_frames frames (grown on demand; nothing may be in
@@ -1156,6 +1347,7 @@ int dpt_track_window_enqueue(dpt_ctx* c, const uint8_t* frames, int64_t pitch, i
   if (init_mode == DPT_INIT_GIVEN && (!T_cw_init || !finite16(T_cw_init)))
     return fail(DPT_E_ARG, "T_cw_init missing or not finite");
   if (!use_coop(c)) return fail(DPT_E_ARG, "window tracking needs the cooperative track (launch mode AUTO or COOP)");
+  if ((e = consume_commit(c)) != DPT_OK) return e;
   if ((int)c->pending.size() + n_frames > kRing)
     return fail(DPT_E_STATE, "%d tracks in flight and %d more exceed %d: synchronise first", (int)c->pending.size(),
                 n_frames, kRing);
@@ -1249,6 +1441,10 @@ int dpt_set_launch_config(dpt_ctx* c, int32_t mode, int32_t chunk) {
 int dpt_get_reference_cache(dpt_ctx* c, int32_t level, uint8_t* valid, float* I0, float* gx, float* gy, float* x0) {
   g_err.clear();
   if (!c) return fail(DPT_E_ARG, "NULL context");
+  {
+    const int e0 = consume_commit(c);  // ordered after a reference update in flight
+    if (e0 != DPT_OK) return e0;
+  }
   if (level < 0 || level >= c->prm.levels) return fail(DPT_E_ARG, "level %d", level);
   if (!c->have_ref) return fail(DPT_E_STATE, "no reference points");
   const size_t n = (size_t)c->n_points, K = (size_t)c->prm.n_pattern, cap = (size_t)c->cap;
@@ -1268,6 +1464,10 @@ int dpt_normal_equations(dpt_ctx* c, int32_t level, const double T_rel[16], floa
                          int64_t* n, int32_t* npts) {
   g_err.clear();
   if (!c || !T_rel || !H21 || !b6 || !E || !n || !npts) return fail(DPT_E_ARG, "NULL argument");
+  {
+    const int e0 = consume_commit(c);  // ordered after a reference update in flight
+    if (e0 != DPT_OK) return e0;
+  }
   if (level < 0 || level >= c->prm.levels) return fail(DPT_E_ARG, "level %d", level);
   if (!finite16(T_rel)) return fail(DPT_E_ARG, "T_rel not finite");
   if (!c->have_ref) return fail(DPT_E_STATE, "no reference points");
@@ -1296,9 +1496,14 @@ int dpt_normal_equations(dpt_ctx* c, int32_t level, const double T_rel[16], floa
 int dpt_get_fixed_hessian(dpt_ctx* c, int32_t level, double* H36, int32_t* not_pd) {
   g_err.clear();
   if (!c || !H36 || !not_pd) return fail(DPT_E_ARG, "NULL argument");
+  {
+    const int e0 = consume_commit(c);  // ordered after a reference update in flight
+    if (e0 != DPT_OK) return e0;
+  }
   if (!(c->prm.flags & DPT_FLAG_FIXED_H)) return fail(DPT_E_STATE, "the context is not in the fixed-H mode");
   if (level < 0 || level >= c->prm.levels) return fail(DPT_E_ARG, "level %d", level);
   if (!c->have_ref) return fail(DPT_E_STATE, "no reference points");
+  HIP_TRY(hipStreamSynchronize(c->stream));  // the factor is written on the context's (or reference) stream
   FixedH f;
   HIP_TRY(hipStreamSynchronize(c->stream));
   HIP_TRY(hipMemcpy(&f, c->d_fixed + level, sizeof f, hipMemcpyDeviceToHost));
@@ -1422,7 +1627,8 @@ struct dpt_batch {
 namespace {
 
 int batch_chunks(const dpt_batch* b, int s) {
-  const int n = b->ctx[s]->n_points;
+  const dpt_ctx* c = b->ctx[s];
+  const int n = std::max(c->n_points, std::max(c->bank_n[0], c->bank_n[1]));  // the chunks cover both banks
   const int ppc = coop_ppc(b->ctx[0]->prm, b->chunk);
   return n > 0 ? (n + ppc - 1) / ppc : 1;
 }
@@ -1468,7 +1674,9 @@ int build_groups(dpt_batch* b) {
     for (size_t k = 0; k < cur.size(); ++k) {
       TrackArgs a;
       fill_track_args(b->ctx[cur[k]], a);
-      g->set_stream((int)k, a, b->ctx[cur[k]]->d_hist, b->ctx[cur[k]]->win, b->ctx[cur[k]]->win_stride);
+      a.ref = refcache_of(b->ctx[cur[k]], 0);
+      g->set_stream((int)k, a, refcache_of(b->ctx[cur[k]], 1), b->ctx[cur[k]]->d_hist, b->ctx[cur[k]]->win,
+                    b->ctx[cur[k]]->win_stride);
     }
     b->groups.push_back(g);
     b->group_streams.push_back(cur);
@@ -2200,6 +2408,8 @@ int predict_streams(dpt_cnn* cnn, dpt_ctx* const* ctxs, int n, double* T_out) {
     if (c->lv[L].W != 94 || c->lv[L].H != 60) return fail(DPT_E_ARG, "stream %d: coarsest level is not 94 x 60", s);
     if (!c->have_pyr[DPT_SLOT_REF] || !c->have_pyr[DPT_SLOT_CUR] || !c->have_ref)
       return fail(DPT_E_STATE, "stream %d: pyramids or reference missing", s);
+    const int e0 = consume_commit(c);
+    if (e0 != DPT_OK) return e0;
     refs[s] = c->pyr[DPT_SLOT_REF] + c->lv[L].off;
     curs[s] = c->pyr[DPT_SLOT_CUR] + c->lv[L].off;
   }
@@ -2227,6 +2437,8 @@ int propose_streams(dpt_cnn* cnn, dpt_ctx* const* ctxs, int n, hipStream_t s, co
     if (c->lv[L].W != 94 || c->lv[L].H != 60) return fail(DPT_E_ARG, "stream %d: coarsest level is not 94 x 60", k);
     if (!c->have_pyr[DPT_SLOT_REF] || !c->have_pyr[DPT_SLOT_CUR] || !c->have_ref)
       return fail(DPT_E_STATE, "stream %d: pyramids or reference missing", k);
+    const int e0 = consume_commit(c);
+    if (e0 != DPT_OK) return e0;
     h[k] = c->pyr[DPT_SLOT_REF] + c->lv[L].off;
     h[n + k] = c->pyr[DPT_SLOT_CUR] + c->lv[L].off;
   }

@@ -462,6 +462,11 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
       reinterpret_cast<uint32_t*>(&ss)[j] = src[j];
   }
   __syncthreads();
+  if (start[w.x].bank) {  // the stream's second reference bank
+    for (int j = threadIdx.x; j < (int)(sizeof(RefCache) / 4); j += blockDim.x)
+      reinterpret_cast<uint32_t*>(&ss.a.ref)[j] = reinterpret_cast<const uint32_t*>(&ss.ref_alt)[j];
+    __syncthreads();
+  }
   start_pose(start + w.x, ss.hist, sh_T0, sh_rw, sh_h0, sh_h1, sh_m1, sh_m2, &sh_l0, &sh_l0_stride);
   const TrackArgs& a = ss.a;
   const PatRegs pregs = pattern_regs(a.pat);
@@ -882,14 +887,17 @@ void CoopEngine::release() {
   partial_words = 0;
 }
 
-void CoopEngine::set_stream(int k, const TrackArgs& a, double* hist, const uint8_t* win, int64_t win_stride) {
+void CoopEngine::set_stream(int k, const TrackArgs& a, const RefCache& alt, double* hist, const uint8_t* win,
+                            int64_t win_stride) {
   CoopStream& c = h_streams[k];
   c.a = a;
   c.a.out = nullptr;  // results go to the launch's slot of h_out
+  c.ref_alt = alt;
   c.hist = hist;
   c.win = win;
   c.win_stride = win_stride;
-  c.n_chunks = a.ref.n > 0 ? (a.ref.n + ppc - 1) / ppc : 1;
+  const int n = std::max(a.ref.n, alt.n);  // the chunks cover the larger bank; the other leaves some idle
+  c.n_chunks = n > 0 ? (n + ppc - 1) / ppc : 1;
   dirty = true;
 }
 

@@ -161,7 +161,8 @@ struct BackprojectArgs {
 
 // One stream of a cooperative track launch (device array, one entry per stream).
 struct CoopStream {
-  TrackArgs a;
+  TrackArgs a;         // a.ref: the reference cache of bank 0
+  RefCache ref_alt;    // bank 1 (a reference stream in use), read when the launch's start slot says so
   uint64_t* partials;  // [2][n_chunks][32] chunk sums, each word = (tag << 32) | float bits
   double* hist;        // the stream's last two poses T_cw, 2 x 3x4 row-major FP64 (device)
   const uint8_t* win;  // window tracking: the pyramids of consecutive frames, win_stride bytes apart
@@ -201,7 +202,9 @@ struct StartSlot {
   int64_t l0_stride;
   const double* dev_rel;  // kStartDevice: the start relative to the reference, 3x4 FP64 in device memory
   double T_rw[12];   // reference pose (world -> reference camera), 3x4
-  double pad1[4];
+  int32_t bank;      // which reference bank of the stream the launch reads (0 or 1)
+  int32_t pad2;
+  double pad1[3];
 };
 static_assert(sizeof(StartSlot) == 256, "StartSlot layout");
 constexpr int kStartGiven = 0, kStartConstVelocity = 1, kStartDevice = 2;
@@ -251,7 +254,8 @@ struct CoopEngine {
   TrackOut* dv_out = nullptr;     // device view of h_out
   hipError_t init(int n_streams, const int* max_points, int chunk, int ppc, bool xcd_pack, hipStream_t s);
   void release();
-  void set_stream(int k, const TrackArgs& a, double* hist, const uint8_t* win, int64_t win_stride);
+  // a.ref: the stream's reference bank 0, alt: bank 1 (the same as bank 0 without a reference stream)
+  void set_stream(int k, const TrackArgs& a, const RefCache& alt, double* hist, const uint8_t* win, int64_t win_stride);
   hipError_t upload();
   int grid() const;
   StartSlot* start(int slot) { return h_start + (size_t)slot * n; }

@@ -1,0 +1,111 @@
+"""Reference updates on a second stream (dpt_set_reference_stream): the
+keyframe's reference pyramid, selection, back-projection and IC precompute
+(Sec. IV-C) run on their own stream into the reference bank the tracks in
+flight do not read.  Every track must return bitwise what the single-stream
+context returns on the same enqueue sequence (several keyframe windows
+enqueued back to back without host waits, window and frame-by-frame forms,
+FP32, mixed precision, fixed H, two threads per point), the test hooks must
+read the committed reference, and an update without a new reference pyramid
+must be refused."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("T_cw", "final_cost", "iterations", "iters_per_level", "n_valid_points", "status", "samples")
+N = 2000
+
+
+def _windows(n_win, cam=synth.CAM_752, seed=2607):
+    """Keyframe windows of the headline sequence: keyframe image and depth,
+    the pose before the keyframe and the keyframe's pose, nine tween frames."""
+    import torch
+
+    traj, scene = synth.Trajectory(seed), synth.Scene(seed)
+    out = []
+    for w in range(n_win):
+        k0 = 40 + 10 * w
+        img0, depth = scene.render(cam, traj.T_cw(k0), synth.pixel_noise(seed, k0, cam, 2.0), want_depth=True)
+        frames = np.stack([scene.render(cam, traj.T_cw(k0 + j), synth.pixel_noise(seed, k0 + j, cam, 2.0),
+                                        want_depth=False)[0] for j in range(1, 10)])
+        out.append(dict(img0=torch.from_numpy(img0).cuda(), depth=torch.from_numpy(depth.astype(np.float32)).cuda(),
+                        frames=torch.from_numpy(frames).cuda(), T0=traj.T_cw(k0), T_prev=traj.T_cw(k0 - 1)))
+    torch.cuda.synchronize()
+    return out
+
+
+def _run(dpt, wins, prm, launch, window, ref_stream):
+    import torch
+
+    trk = dpt.Tracker(synth.CAM_752, prm, max_points=N)
+    trk.set_launch_config(*launch)
+    if ref_stream:
+        trk.set_reference_stream(torch.cuda.Stream())
+    for w in wins:  # everything enqueued, one synchronisation at the end
+        trk.build_pyramid(dpt.SLOT_REF, w["img0"])
+        trk.set_reference_from_depth(N, w["depth"], w["T0"])
+        trk.set_pose_history(w["T_prev"], w["T0"])
+        if window:
+            trk.track_window_enqueue(w["frames"])
+        else:
+            for j in range(9):
+                trk.build_pyramid(dpt.SLOT_CUR, w["frames"][j])
+                trk.track_enqueue(None)
+    res = trk.synchronize()
+    cache = trk.reference_cache(0)
+    trk.close()
+    return res, cache
+
+
+def _assert_same(a, b):
+    assert len(a) == len(b)
+    for f, (x, y) in enumerate(zip(a, b)):
+        for k in FIELDS:
+            np.testing.assert_array_equal(np.asarray(x[k]), np.asarray(y[k]), err_msg=f"frame {f} field {k}")
+
+
+@pytest.fixture(scope="module")
+def wins(gpu_lib):
+    return _windows(5)
+
+
+@pytest.mark.parametrize("variant,launch,window", [
+    ("fp32", (3, 128), True), ("fp32", (2, 256), True), ("fp32", (3, 128), False),
+    ("mixed", (3, 128), True), ("fixed_h", (2, 256), True), ("fixed_h", (3, 128), False)])
+def test_reference_stream_equals_single_stream(gpu_lib, wins, variant, launch, window):
+    dpt = gpu_lib
+    kw = dict(levels=4)
+    if variant == "mixed":
+        kw["precision"] = dpt.PREC_MIXED
+    elif variant == "fixed_h":
+        kw["fixed_h"] = True
+    prm = dpt.make_params(**kw)
+    print(f"reference stream {variant} launch {launch} window {window}", flush=True)
+    base, cache0 = _run(dpt, wins, prm, launch, window, False)
+    piped, cache1 = _run(dpt, wins, prm, launch, window, True)
+    _assert_same(base, piped)
+    assert all(r["status"] == 0 for r in base)
+    for k in ("valid", "I0", "gx", "gy", "x0"):  # the hook reads the last committed reference
+        np.testing.assert_array_equal(cache0[k], cache1[k], err_msg=k)
+
+
+def test_reference_stream_needs_a_new_reference_pyramid(gpu_lib, wins):
+    import torch
+
+    dpt = gpu_lib
+    trk = dpt.Tracker(synth.CAM_752, dpt.make_params(levels=4), max_points=N)
+    trk.set_reference_stream(torch.cuda.Stream())
+    w = wins[0]
+    trk.build_pyramid(dpt.SLOT_REF, w["img0"])
+    trk.set_reference_from_depth(N, w["depth"], w["T0"])
+    with pytest.raises(dpt.DptError):  # a second update on the same pyramid
+        trk.set_reference_from_depth(N, w["depth"], w["T0"])
+    # back to one stream: the same update is accepted again
+    trk.set_reference_stream(None)
+    trk.set_reference_from_depth(N, w["depth"], w["T0"])
+    trk.set_pose_history(w["T_prev"], w["T0"])
+    trk.track_window_enqueue(w["frames"])
+    assert all(r["status"] == 0 for r in trk.synchronize())
+    trk.close()
