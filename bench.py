@@ -181,6 +181,17 @@ def collect(results, wins_done, stats):
 
 
 REF_STREAM = True  # reference updates on a second stream (the --single-stream flag turns it off)
+_REF_STREAM_OBJ = []
+
+
+def reference_stream(dpt):
+    """The one stream every leg's reference updates run on.  A process that
+    used more streams than the GPU has hardware queues (4 here) ran all later
+    kernels slower (the batched track 0.19 -> 0.28 ms after eight streams had
+    each been used once), so the legs share one instead of taking a new one."""
+    if not _REF_STREAM_OBJ:
+        _REF_STREAM_OBJ.append(dpt.Stream())
+    return _REF_STREAM_OBJ[0]
 
 
 def timed_plain(dpt, synth, wins, dev, steps, warmup, prm, launch, chunk, n_points=N_POINTS, cam=None, window=True):
@@ -195,7 +206,7 @@ def timed_plain(dpt, synth, wins, dev, steps, warmup, prm, launch, chunk, n_poin
     trk = dpt.Tracker(cam, prm, max_points=n_points)
     trk.set_launch_config(launch, chunk)
     if REF_STREAM:
-        trk.set_reference_stream(torch.cuda.Stream())
+        trk.set_reference_stream(reference_stream(dpt))
     n = len(wins)
     every = PROFILE_EVERY if not window else PROFILE_EVERY_WINDOW
     for w in range(warmup):
@@ -283,6 +294,8 @@ def _batched_run(dpt, wins, frames, wframes, depths, T_rw, T_prev, n_streams, st
     mixed = precision == dpt.PREC_MIXED
     prm = dpt.make_params(levels=LEVELS, max_iters=10, huber_k=9.0, step_eps=1e-5, precision=precision)
     bt = dpt.BatchTracker([CAM] * n_streams, prm, [N_POINTS] * n_streams)
+    if REF_STREAM:  # each keyframe's reference updates overlap the previous window's tracks
+        bt.set_reference_stream(reference_stream(dpt))
     stats = {"samples": [], "iters": [], "status": []}
 
     def enqueue(w, window=window):

@@ -214,6 +214,14 @@ enum { DPT_INIT_GIVEN = 0, DPT_INIT_CONST_VELOCITY = 1, DPT_INIT_PROPOSED = 2 };
  * call waits for both streams.  DPT_E_STATE while an update is open. */
 int dpt_set_reference_stream(dpt_ctx* ctx, void* hip_stream);
 
+/* A HIP stream for the reference updates: default priority, not ordered with
+ * the null stream.  *out receives the stream; the caller destroys it with
+ * dpt_stream_destroy (which waits for its work) after every context or batch
+ * using it has been destroyed or switched back to one stream.  A process that
+ * only needs this one extra stream avoids creating a pool of them. */
+int dpt_stream_create(void** out);
+int dpt_stream_destroy(void* stream);
+
 /* Asynchronous form of dpt_track_frame (the same computation, Sec. IV-C
  * "Track"): enqueue the track of the CUR pyramid on the context's stream and
  * return at once, so frames can follow each other without the host waiting
@@ -503,6 +511,13 @@ int dpt_batch_get_level(dpt_batch* b, int32_t slot, int32_t level, uint8_t* dst,
 /* Track every stream's CUR pyramid.  T_cw_init: n_streams row-major 4x4
  * doubles; out: n_streams results.  Synchronises the stream. */
 int dpt_batch_track(dpt_batch* b, const double* T_cw_init, dpt_result* out);
+
+/* As dpt_set_reference_stream, for every stream of the batch: reference
+ * updates (dpt_batch_build_pyramids with DPT_SLOT_REF, which starts one, the
+ * per-stream and all-stream reference setters) run on hip_stream into the
+ * banks the tracks in flight do not read; the next track orders the batch's
+ * stream after the update.  NULL or the batch's stream: one stream again. */
+int dpt_batch_set_reference_stream(dpt_batch* b, void* hip_stream);
 
 /* As dpt_track_enqueue / dpt_synchronize / dpt_set_pose_history, for every
  * stream of the batch (T_cw_init: n_streams row-major 4x4 doubles, may be NULL

@@ -160,6 +160,9 @@ SIGNATURES = {
     "dpt_cnn_predict_batch": (ctypes.c_int, [_vp, _vp, _vp]),
     "dpt_cnn_propose": (ctypes.c_int, [_vp, _vp]),
     "dpt_set_reference_stream": (ctypes.c_int, [_vp, _vp]),
+    "dpt_stream_create": (ctypes.c_int, [_vp]),
+    "dpt_stream_destroy": (ctypes.c_int, [_vp]),
+    "dpt_batch_set_reference_stream": (ctypes.c_int, [_vp, _vp]),
     "dpt_probe_read_bandwidth": (ctypes.c_int, [_i64, _i32, _i32, ctypes.POINTER(ctypes.c_double)]),
     "dpt_probe_fp32_fma": (ctypes.c_int, [_i32, ctypes.POINTER(ctypes.c_double)]),
     "dpt_cnn_propose_batch": (ctypes.c_int, [_vp, _vp]),
@@ -270,6 +273,27 @@ def current_stream() -> int:
     import torch
 
     return int(torch.cuda.current_stream().cuda_stream) if torch.cuda.is_available() else 0
+
+
+class Stream:
+    """A HIP stream the library creates (dpt_stream_create) for reference
+    updates: default priority, not ordered with the null stream.  Pass it to
+    Tracker/BatchTracker.set_reference_stream; it is destroyed by close() or
+    when the last holder lets it go."""
+
+    def __init__(self):
+        h = _vp()
+        _check(load().dpt_stream_create(ctypes.byref(h)))
+        self.cuda_stream = int(h.value)
+
+    def close(self):
+        if getattr(self, "cuda_stream", 0):
+            _check(load().dpt_stream_destroy(self.cuda_stream))
+            self.cuda_stream = 0
+
+    def __del__(self, _finalising=sys.is_finalizing):
+        if not _finalising():
+            self.close()
 
 
 CYCLE_FIELDS = ("accumulate", "reduce", "exchange", "solve", "iterations", "launches", "kernel", "realtime", "place")
@@ -420,9 +444,9 @@ class Tracker:
                     baseline=r.baseline, track=r.track.as_dict() if r.tracked else None)
 
     def set_reference_stream(self, stream=None):
-        """Reference updates on a second stream (a torch.cuda.Stream or a raw
-        handle; None: back to the context's stream), overlapping the tracks of
-        the previous reference; an update then starts with build_pyramid(SLOT_REF)."""
+        """Reference updates on a second stream (a Stream, a torch.cuda.Stream or
+        a raw handle; None: back to the context's stream), overlapping the tracks
+        of the previous reference; an update then starts with build_pyramid(SLOT_REF)."""
         handle = getattr(stream, "cuda_stream", stream)
         _check(self._lib.dpt_set_reference_stream(self._h, handle))
         self.ref_stream = stream
@@ -777,6 +801,12 @@ class BatchTracker:
         _check(self._lib.dpt_batch_get_profile(self._h, ctypes.byref(pm), ctypes.byref(pn), ctypes.byref(tm),
                                                ctypes.byref(tn)))
         return dict(pyramid_ms=pm.value, n_pyramid=pn.value, track_ms=tm.value, n_track=tn.value)
+
+    def set_reference_stream(self, stream=None):
+        """Reference updates of every stream on a second stream (Tracker.set_reference_stream)."""
+        handle = getattr(stream, "cuda_stream", stream)
+        _check(self._lib.dpt_batch_set_reference_stream(self._h, handle))
+        self.ref_stream = stream
 
     def set_launch_config(self, mode: int, chunk: int = 256):
         _check(self._lib.dpt_batch_set_launch_config(self._h, mode, chunk))

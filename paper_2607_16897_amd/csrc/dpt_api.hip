@@ -328,7 +328,10 @@ struct dpt_ctx {
   bool eng_ready = false;
   double* d_hist = nullptr;  // pose history: the last two T_cw, 2 x 3x4 FP64 (device)
   double* d_prop = nullptr;  // learned start proposal relative to the reference, 3x4 FP64 (device)
-  const uint8_t** d_cnn_lv = nullptr;  // the coarsest reference and current levels, for the proposal
+  // the coarsest reference and current levels, for the proposal: one table
+  // per reference bank, each uploaded the first time that bank is read
+  const uint8_t** d_cnn_lv = nullptr;
+  bool cnn_lv_ok[2] = {false, false};
   bool have_prop = false;
   std::vector<std::pair<int, dpt_result*>> pending;  // tracks in flight: (ring slot, caller's result)
   int slot_next = 0;
@@ -350,6 +353,7 @@ struct dpt_ctx {
   hipEvent_t ev_ready = nullptr;               // reference stream: the last committed update done
   bool update_open = false;    // a reference update has started writing the fields' bank
   bool commit_pending = false;  // committed, the context's stream not yet ordered after it
+  bool batch_owned = false;     // a batch stream: the batch orders its updates and tracks
   // tween-window schedule (host state)
   dpt_tween_policy tween{};
   bool tween_policy = false, tween_anchored = false, tween_needs_anchor = false;
@@ -643,6 +647,7 @@ int dpt_get_pyramid(dpt_ctx* c, int32_t slot, int32_t level, uint8_t* host_dst) 
   if (slot != DPT_SLOT_REF && slot != DPT_SLOT_CUR) return fail(DPT_E_ARG, "slot %d", slot);
   if (level < 0 || level >= c->prm.levels) return fail(DPT_E_ARG, "level %d", level);
   if (!c->have_pyr[slot]) return fail(DPT_E_STATE, "slot %d has no pyramid", slot);
+  if (slot == DPT_SLOT_REF && c->rstream) HIP_TRY(hipStreamSynchronize(c->rstream));  // built on the reference stream
   const LevelGeom& g = c->lv[level];
   HIP_TRY(hipMemcpyAsync(host_dst, c->pyr[slot] + g.off, (size_t)g.W * g.H, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
@@ -656,6 +661,7 @@ int dpt_get_pyramid_f32(dpt_ctx* c, int32_t slot, int32_t level, float* host_dst
   if (slot != DPT_SLOT_REF && slot != DPT_SLOT_CUR) return fail(DPT_E_ARG, "slot %d", slot);
   if (level < 0 || level >= c->prm.levels) return fail(DPT_E_ARG, "level %d", level);
   if (!c->have_pyr[slot]) return fail(DPT_E_STATE, "slot %d has no pyramid", slot);
+  if (slot == DPT_SLOT_REF && c->rstream) HIP_TRY(hipStreamSynchronize(c->rstream));
   const LevelGeom& g = c->lv[level];
   HIP_TRY(hipMemcpyAsync(host_dst, c->pyrf[slot] + g.off, (size_t)g.W * g.H * sizeof(float), hipMemcpyDeviceToHost,
                          c->stream));
@@ -739,7 +745,7 @@ int commit_reference(dpt_ctx* c, int32_t n, const double T_rw[16], bool record =
   c->n_points = n;
   c->have_ref = true;
   c->bank_n[c->bank] = n;
-  if (c->rstream) {
+  if (c->rstream && !c->batch_owned) {
     if (record) HIP_TRY(hipEventRecord(c->ev_ready, c->rstream));
     c->commit_pending = true;
     c->update_open = false;
@@ -866,6 +872,23 @@ int alloc_alt_bank(dpt_ctx* c) {
 }  // namespace
 
 extern "C" {
+
+int dpt_stream_create(void** out) {
+  g_err.clear();
+  if (!out) return fail(DPT_E_ARG, "NULL argument");
+  hipStream_t s = nullptr;
+  HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  *out = s;
+  return DPT_OK;
+}
+
+int dpt_stream_destroy(void* s) {
+  g_err.clear();
+  if (!s) return DPT_OK;
+  HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(s)));
+  HIP_TRY(hipStreamDestroy(static_cast<hipStream_t>(s)));
+  return DPT_OK;
+}
 
 int dpt_set_reference_stream(dpt_ctx* c, void* hip_stream) {
   g_err.clear();
@@ -1559,6 +1582,13 @@ struct dpt_batch {
   int32_t n = 0;
   hipStream_t stream = nullptr;
   std::vector<dpt_ctx*> ctx;
+  // reference stream (dpt_batch_set_reference_stream): every stream's reference
+  // banks switch together; the events order the batch's two streams
+  hipStream_t rstream = nullptr;
+  hipEvent_t ev_read[2] = {nullptr, nullptr};  // batch stream: past the last track that read bank b
+  hipEvent_t ev_ready = nullptr;               // reference stream: the last update done
+  int32_t bank = 0;
+  bool update_open = false, commit_pending = false;
   int32_t launch_mode = DPT_LAUNCH_AUTO, chunk = 256;
   int32_t spin_limit = kSpinLimit;
   // cooperative groups of streams (each fits one co-resident launch)
@@ -1570,7 +1600,9 @@ struct dpt_batch {
   PyrJob* h_jobs = nullptr;  // pinned, two tables
   hipEvent_t ev_jobs[2] = {nullptr, nullptr};  // each table's last upload
   int jobs_next = 0;
-  PyrJob* d_static[2] = {nullptr, nullptr};  // per slot: destinations and geometry (n <= kPyrArgJobs)
+  // destinations and geometry (n <= kPyrArgJobs) per slot (the reference in
+  // bank 0, current frames), then the reference in bank 1 (reference stream)
+  PyrJob* d_static[3] = {nullptr, nullptr, nullptr};
   // one-workgroup-per-stream launch
   TrackArgs* d_args = nullptr;
   TrackArgs* h_args = nullptr;  // pinned
@@ -1588,7 +1620,8 @@ struct dpt_batch {
   double** d_hist_ptrs = nullptr;  // device array of the streams' history pointers
   WinJob* d_winjobs = nullptr;     // the streams' window pyramid jobs (device)
   double* d_prop = nullptr;        // learned start proposals, n x 3x4 FP64 (device)
-  const uint8_t** d_cnn_lv = nullptr;  // the streams' coarsest reference then current levels
+  const uint8_t** d_cnn_lv = nullptr;  // the streams' coarsest reference then current levels, per bank
+  bool cnn_lv_ok[2] = {false, false};
   bool have_prop = false;
 
   void clear_groups() {
@@ -1599,6 +1632,9 @@ struct dpt_batch {
   }
   ~dpt_batch() {
     (void)hipStreamSynchronize(stream);
+    if (rstream) (void)hipStreamSynchronize(rstream);
+    for (hipEvent_t e : {ev_read[0], ev_read[1], ev_ready})
+      if (e) (void)hipEventDestroy(e);
     clear_groups();
     for (dpt_ctx* c : ctx) delete c;
     prof_pyr.destroy();
@@ -1625,6 +1661,46 @@ struct dpt_batch {
 };
 
 namespace {
+
+// The batch's counterparts of open_update / consume_commit: every stream's
+// fields switch bank together at a reference pyramid build, the update closes
+// (one event on the reference stream) when the last reference is set or at
+// the next track, and the batch stream is ordered after it before tracking.
+int batch_consume(dpt_batch* b) {
+  if (!b->commit_pending) return DPT_OK;
+  HIP_TRY(hipEventRecord(b->ev_read[b->bank ^ 1], b->stream));
+  HIP_TRY(hipStreamWaitEvent(b->stream, b->ev_ready, 0));
+  b->commit_pending = false;
+  return DPT_OK;
+}
+
+int batch_close_update(dpt_batch* b) {
+  if (!b->update_open) return DPT_OK;
+  HIP_TRY(hipEventRecord(b->ev_ready, b->rstream));
+  b->update_open = false;
+  b->commit_pending = true;
+  for (dpt_ctx* c : b->ctx) c->update_open = false;
+  return DPT_OK;
+}
+
+int batch_open_update(dpt_batch* b) {
+  if (!b->rstream || b->update_open) return DPT_OK;
+  int e = batch_consume(b);
+  if (e != DPT_OK) return e;
+  for (dpt_ctx* c : b->ctx) {
+    const RefBank cur = fields_bank(c);
+    set_fields(c, c->alt);
+    c->alt = cur;
+    c->bank ^= 1;
+    c->update_open = true;
+  }
+  b->bank ^= 1;
+  HIP_TRY(hipStreamWaitEvent(b->rstream, b->ev_read[b->bank], 0));
+  b->update_open = true;
+  return DPT_OK;
+}
+
+hipStream_t batch_ref_stream(const dpt_batch* b) { return b->rstream ? b->rstream : b->stream; }
 
 int batch_chunks(const dpt_batch* b, int s) {
   const dpt_ctx* c = b->ctx[s];
@@ -1768,10 +1844,34 @@ int batch_synchronize(dpt_batch* b) {
   return DPT_OK;
 }
 
+// A reference committed to a bank since the launch descriptors were written:
+// refresh them in place, or regroup when a stream now needs more chunks.
+void refresh_groups(dpt_batch* b) {
+  for (size_t gi = 0; gi < b->groups.size() && !b->groups_dirty; ++gi) {
+    CoopEngine* g = b->groups[gi];
+    const std::vector<int>& ss = b->group_streams[gi];
+    for (size_t k = 0; k < ss.size(); ++k) {
+      const dpt_ctx* c = b->ctx[ss[k]];
+      const RefCache r0 = refcache_of(c, 0), r1 = refcache_of(c, 1);
+      const CoopStream& hs = g->h_streams[k];
+      if (hs.a.ref.n == r0.n && hs.ref_alt.n == r1.n && hs.ref_alt.x0 == r1.x0) continue;
+      if (batch_chunks(b, ss[k]) > hs.n_chunks) {
+        b->groups_dirty = true;
+        break;
+      }
+      TrackArgs a;
+      fill_track_args(c, a);
+      a.ref = r0;
+      g->set_stream((int)k, a, r1, c->d_hist, c->win, c->win_stride);
+    }
+  }
+}
+
 // Enqueue one cooperative track of every stream.  modes[s] is kStartGiven
 // (start from T_cw_init[s]), kStartConstVelocity or kStartDevice (the proposal
 // in d_prop).
 int batch_enqueue_coop(dpt_batch* b, const int* modes, const double* T_cw_init, dpt_result* out) {
+  refresh_groups(b);
   if (b->groups_dirty) {  // regrouping frees the rings: finish and fill what is in flight first
     int e = b->pending.empty() ? DPT_OK : batch_synchronize(b);
     if (e != DPT_OK) return e;
@@ -1831,12 +1931,13 @@ int batch_collect(dpt_batch* b, int n) {
   return DPT_OK;
 }
 
-int batch_check_state(const dpt_batch* b) {
+int batch_check_state(dpt_batch* b) {
   for (int s = 0; s < b->n; ++s) {
     if (!b->ctx[s]->have_ref) return fail(DPT_E_STATE, "stream %d has no reference points", s);
     if (!b->ctx[s]->have_pyr[DPT_SLOT_CUR]) return fail(DPT_E_STATE, "stream %d has no current pyramid", s);
   }
-  return DPT_OK;
+  int e = batch_close_update(b);
+  return e != DPT_OK ? e : batch_consume(b);
 }
 
 // One workgroup per stream, synchronous.
@@ -1935,13 +2036,59 @@ int dpt_batch_create(int32_t n_streams, const dpt_camera* cams, const dpt_params
 
 void dpt_batch_destroy(dpt_batch* b) { delete b; }
 
+int dpt_batch_set_reference_stream(dpt_batch* b, void* hip_stream) {
+  g_err.clear();
+  if (!b) return fail(DPT_E_ARG, "NULL batch");
+  if (b->update_open) return fail(DPT_E_STATE, "a reference update is open: finish it first");
+  hipStream_t rs = static_cast<hipStream_t>(hip_stream);
+  if (rs == b->stream) rs = nullptr;
+  int e;
+  if (!b->pending.empty() && (e = batch_synchronize(b)) != DPT_OK) return e;
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  if (b->rstream) HIP_TRY(hipStreamSynchronize(b->rstream));
+  b->commit_pending = false;
+  if (rs) {
+    for (hipEvent_t* ev : {&b->ev_read[0], &b->ev_read[1], &b->ev_ready})
+      if (!*ev) HIP_TRY(hipEventCreateWithFlags(ev, hipEventDisableTiming));
+    for (dpt_ctx* c : b->ctx) {
+      if (c->bank != b->bank) return fail(DPT_E_STATE, "stream banks out of step");
+      const bool fresh = !c->phys[1].x0;
+      if ((e = alloc_alt_bank(c)) != DPT_OK) return e;
+      if (fresh) c->alt = c->phys[1], c->bank_n[1] = 0;
+    }
+    if (b->d_static[DPT_SLOT_REF] && !b->d_static[2]) {  // the second bank's reference pyramid table
+      std::vector<PyrJob> t(b->n);
+      for (int s = 0; s < b->n; ++s) {
+        std::memset(&t[s], 0, sizeof t[s]);
+        t[s].dst = b->ctx[s]->phys[1].pyr_ref;
+        t[s].g = b->ctx[s]->pg;
+      }
+      if ((e = dev_alloc((void**)&b->d_static[2], sizeof(PyrJob) * b->n)) != DPT_OK) return e;
+      HIP_TRY(hipMemcpy(b->d_static[2], t.data(), sizeof(PyrJob) * b->n, hipMemcpyHostToDevice));
+    }
+    b->groups_dirty = true;  // the launch descriptors gain the second banks
+  }
+  for (dpt_ctx* c : b->ctx) c->rstream = rs, c->batch_owned = true, c->commit_pending = false;
+  b->rstream = rs;
+  return DPT_OK;
+}
+
 int dpt_batch_build_pyramids(dpt_batch* b, int32_t slot, const uint8_t* const* imgs, const int64_t* pitches,
                              int32_t on_device) {
   g_err.clear();
   if (on_device != 0 && on_device != 1) return fail(DPT_E_ARG, "on_device %d is neither 0 nor 1", on_device);
   if (!b || !imgs || !pitches) return fail(DPT_E_ARG, "NULL argument");
   if (slot != DPT_SLOT_REF && slot != DPT_SLOT_CUR) return fail(DPT_E_ARG, "slot %d", slot);
-  if (b->d_static[slot] && !b->ctx[0]->pyrf[slot]) {  // sources by value: no table upload
+  if (slot == DPT_SLOT_REF) {
+    const int e0 = batch_open_update(b);
+    if (e0 != DPT_OK) return e0;
+  }
+  // reference pyramids belong to the reference stream (the batch's own without one)
+  const hipStream_t st = slot == DPT_SLOT_REF ? batch_ref_stream(b) : b->stream;
+  const bool prof = b->prof && st == b->stream;
+  // the static table of the bank the fields now hold (the reference's switches with it)
+  const PyrJob* d_static = slot == DPT_SLOT_REF && b->bank == 1 ? b->d_static[2] : b->d_static[slot];
+  if (d_static && !b->ctx[0]->pyrf[slot]) {  // sources by value: no table upload
     PyrSrcArgs srcs;
     std::memset(&srcs, 0, sizeof srcs);
     int max_w = 0, max_h = 0;
@@ -1953,7 +2100,7 @@ int dpt_batch_build_pyramids(dpt_batch* b, int32_t slot, const uint8_t* const* i
       srcs.pitch[s] = pitches[s];
       if (!on_device) {
         HIP_TRY(hipMemcpy2DAsync(c->staging, c->cam.width, imgs[s], pitches[s], c->cam.width, c->cam.height,
-                                 hipMemcpyHostToDevice, b->stream));
+                                 hipMemcpyHostToDevice, st));
         srcs.src[s] = c->staging;
         srcs.pitch[s] = c->cam.width;
       }
@@ -1964,11 +2111,11 @@ int dpt_batch_build_pyramids(dpt_batch* b, int32_t slot, const uint8_t* const* i
     for (int s = 0; s < b->n; ++s)
       block = block && pyramid_block_ok(b->ctx[s]->pg, srcs.src[s], srcs.pitch[s], b->ctx[s]->pyr[slot]);
     int ps = -1;
-    if (b->prof) HIP_TRY(b->prof_pyr.begin(b->stream, &ps));
-    HIP_TRY(launch_pyramid_batch_args(b->d_static[slot], srcs, b->n, max_w, max_h, b->ctx[0]->prm.levels, block,
-                                      b->stream));
-    if (b->prof) HIP_TRY(b->prof_pyr.end(b->stream, ps));
-    if (!on_device) HIP_TRY(hipStreamSynchronize(b->stream));  // the host images are only borrowed
+    if (prof) HIP_TRY(b->prof_pyr.begin(b->stream, &ps));
+    HIP_TRY(launch_pyramid_batch_args(d_static, srcs, b->n, max_w, max_h, b->ctx[0]->prm.levels, block,
+                                      st));
+    if (prof) HIP_TRY(b->prof_pyr.end(b->stream, ps));
+    if (!on_device) HIP_TRY(hipStreamSynchronize(st));  // the host images are only borrowed
     for (int s = 0; s < b->n; ++s) {
       b->ctx[s]->have_pyr[slot] = true;
       if (slot == DPT_SLOT_REF) b->ctx[s]->have_ref = false;
@@ -1990,7 +2137,7 @@ int dpt_batch_build_pyramids(dpt_batch* b, int32_t slot, const uint8_t* const* i
     int64_t sp = pitches[s];
     if (!on_device) {
       HIP_TRY(hipMemcpy2DAsync(c->staging, c->cam.width, imgs[s], pitches[s], c->cam.width, c->cam.height,
-                               hipMemcpyHostToDevice, b->stream));
+                               hipMemcpyHostToDevice, st));
       src = c->staging;
       sp = c->cam.width;
     }
@@ -2007,16 +2154,17 @@ int dpt_batch_build_pyramids(dpt_batch* b, int32_t slot, const uint8_t* const* i
     max_w = std::max(max_w, c->cam.width);
     max_h = std::max(max_h, c->cam.height);
   }
-  HIP_TRY(hipMemcpyAsync(d_jobs, h_jobs, sizeof(PyrJob) * b->n, hipMemcpyHostToDevice, b->stream));
-  HIP_TRY(hipEventRecord(b->ev_jobs[jt], b->stream));
+  HIP_TRY(hipMemcpyAsync(d_jobs, h_jobs, sizeof(PyrJob) * b->n, hipMemcpyHostToDevice, st));
   int ps = -1;
-  if (b->prof) HIP_TRY(b->prof_pyr.begin(b->stream, &ps));
-  HIP_TRY(launch_pyramid_batch(d_jobs, b->n, max_w, max_h, b->ctx[0]->prm.levels, b->stream));
+  if (prof) HIP_TRY(b->prof_pyr.begin(b->stream, &ps));
+  HIP_TRY(launch_pyramid_batch(d_jobs, b->n, max_w, max_h, b->ctx[0]->prm.levels, st));
   for (int s = 0; s < b->n; ++s)
     if (b->ctx[s]->pyrf[slot])
-      HIP_TRY(launch_pyramid_gauss(h_jobs[s].src, h_jobs[s].pitch, b->ctx[s]->pyrf[slot], b->ctx[s]->pg, b->stream));
-  if (b->prof) HIP_TRY(b->prof_pyr.end(b->stream, ps));
-  if (!on_device) HIP_TRY(hipStreamSynchronize(b->stream));  // the host images are only borrowed
+      HIP_TRY(launch_pyramid_gauss(h_jobs[s].src, h_jobs[s].pitch, b->ctx[s]->pyrf[slot], b->ctx[s]->pg, st));
+  // after the launches that read the table: the tables alternate between the two streams' builds
+  HIP_TRY(hipEventRecord(b->ev_jobs[jt], st));
+  if (prof) HIP_TRY(b->prof_pyr.end(b->stream, ps));
+  if (!on_device) HIP_TRY(hipStreamSynchronize(st));  // the host images are only borrowed
   for (int s = 0; s < b->n; ++s) {
     b->ctx[s]->have_pyr[slot] = true;
     if (slot == DPT_SLOT_REF) b->ctx[s]->have_ref = false;
@@ -2063,7 +2211,10 @@ int dpt_batch_set_reference_from_depth_all(dpt_batch* b, const int32_t* n_points
     if (depth_pitches[s] < c->cam.width) return fail(DPT_E_ARG, "stream %d: depth pitch < width", s);
     if (!finite16(T_rw + 16 * s)) return fail(DPT_E_ARG, "T_rw %d not finite", s);
     if (!c->have_pyr[DPT_SLOT_REF]) return fail(DPT_E_STATE, "stream %d has no reference pyramid", s);
+    if (b->rstream && !c->update_open)
+      return fail(DPT_E_STATE, "with a reference stream, a reference update starts with dpt_batch_build_pyramids(DPT_SLOT_REF)");
   }
+  const hipStream_t rs = batch_ref_stream(b);
   SelJob* hs;
   BackprojectArgs* hb;
   PrecomputeArgs* hp;
@@ -2098,18 +2249,19 @@ int dpt_batch_set_reference_from_depth_all(dpt_batch* b, const int32_t* n_points
   const SelJob* ds;
   const BackprojectArgs* db;
   const PrecomputeArgs* dp;
-  HIP_TRY(b->sel_jobs.upload(ws, b->n, b->stream, &ds));
-  HIP_TRY(b->bp_args.upload(wb, b->n, b->stream, &db));
-  HIP_TRY(b->pre_args.upload(wp, b->n, b->stream, &dp));
-  HIP_TRY(launch_select_batch(ds, b->n, G_max, any_empty, b->stream));
-  HIP_TRY(launch_backproject_batch(db, b->n, max_n, b->stream));
-  HIP_TRY(launch_precompute_batch(dp, b->n, max_samples, max_levels, b->stream));
-  if (b->ctx[0]->prm.flags & DPT_FLAG_FIXED_H) HIP_TRY(launch_fixed_h_batch(dp, b->n, max_n, max_levels, b->stream));
+  HIP_TRY(b->sel_jobs.upload(ws, b->n, rs, &ds));
+  HIP_TRY(b->bp_args.upload(wb, b->n, rs, &db));
+  HIP_TRY(b->pre_args.upload(wp, b->n, rs, &dp));
+  HIP_TRY(launch_select_batch(ds, b->n, G_max, any_empty, rs));
+  HIP_TRY(launch_backproject_batch(db, b->n, max_n, rs));
+  HIP_TRY(launch_precompute_batch(dp, b->n, max_samples, max_levels, rs));
+  if (b->ctx[0]->prm.flags & DPT_FLAG_FIXED_H) HIP_TRY(launch_fixed_h_batch(dp, b->n, max_n, max_levels, rs));
   for (int s = 0; s < b->n; ++s) {
     if (b->ctx[s]->n_points != n_points[s]) b->groups_dirty = true;
-    commit_reference(b->ctx[s], n_points[s], T_rw + 16 * s);
+    const int e = commit_reference(b->ctx[s], n_points[s], T_rw + 16 * s);
+    if (e != DPT_OK) return e;
   }
-  return DPT_OK;
+  return batch_close_update(b);
 }
 
 int dpt_batch_set_pose_history_all(dpt_batch* b, const double* T_older, const double* T_newer) {
@@ -2208,6 +2360,7 @@ int dpt_batch_track_window_enqueue(dpt_batch* b, const uint8_t* const* frames, c
       if (!finite16(T_cw_init + 16 * s)) return fail(DPT_E_ARG, "T_cw_init %d not finite", s);
   }
   if (!batch_use_coop(b)) return fail(DPT_E_ARG, "window tracking needs the cooperative track (launch mode AUTO or COOP)");
+  if ((e = batch_close_update(b)) != DPT_OK || (e = batch_consume(b)) != DPT_OK) return e;
   if ((int)b->pending.size() + n_frames > kRing)
     return fail(DPT_E_STATE, "%d batched tracks in flight and %d more exceed %d: synchronise first",
                 (int)b->pending.size(), n_frames, kRing);
@@ -2228,6 +2381,7 @@ int dpt_batch_track_window_enqueue(dpt_batch* b, const uint8_t* const* frames, c
       HIP_TRY(hipMemcpy(b->d_winjobs + s, b->ctx[s]->d_winjob, sizeof(WinJob), hipMemcpyDeviceToDevice));
     b->clear_groups();
   }
+  refresh_groups(b);
   if (b->groups_dirty) {  // regrouping frees the rings: finish and fill what is in flight first
     if (!b->pending.empty() && (e = batch_synchronize(b)) != DPT_OK) return e;
     if ((e = build_groups(b)) != DPT_OK) return e;
@@ -2429,8 +2583,10 @@ int predict_streams(dpt_cnn* cnn, dpt_ctx* const* ctxs, int n, double* T_out) {
 // their coarsest reference and current levels, then each start relative to
 // its reference into prop (n x 3x4 FP64, device).  The level pointer table is
 // uploaded at the first call (the pyramids never move).
-int propose_streams(dpt_cnn* cnn, dpt_ctx* const* ctxs, int n, hipStream_t s, const uint8_t*** d_lv, double** prop) {
+int propose_streams(dpt_cnn* cnn, dpt_ctx* const* ctxs, int n, hipStream_t s, const uint8_t*** d_lv, bool* lv_ok,
+                    double** prop) {
   std::vector<const uint8_t*> h(2 * (size_t)n);
+  const int bank = ctxs[0]->bank;  // a batch's streams switch banks together
   for (int k = 0; k < n; ++k) {
     dpt_ctx* c = ctxs[k];
     const int L = c->prm.levels - 1;
@@ -2439,15 +2595,19 @@ int propose_streams(dpt_cnn* cnn, dpt_ctx* const* ctxs, int n, hipStream_t s, co
       return fail(DPT_E_STATE, "stream %d: pyramids or reference missing", k);
     const int e0 = consume_commit(c);
     if (e0 != DPT_OK) return e0;
+    if (c->bank != bank) return fail(DPT_E_STATE, "stream banks out of step");
     h[k] = c->pyr[DPT_SLOT_REF] + c->lv[L].off;
     h[n + k] = c->pyr[DPT_SLOT_CUR] + c->lv[L].off;
   }
-  if (!*d_lv) {
-    HIP_TRY(hipMalloc((void**)d_lv, sizeof(void*) * 2 * n));
-    HIP_TRY(hipMemcpy((void*)*d_lv, h.data(), sizeof(void*) * 2 * n, hipMemcpyHostToDevice));
+  if (!*d_lv) HIP_TRY(hipMalloc((void**)d_lv, sizeof(void*) * 4 * n));
+  const uint8_t** tab = *d_lv + (size_t)bank * 2 * n;
+  if (!lv_ok[bank]) {  // the bank's buffers are fixed for the context's life: one upload
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipMemcpy((void*)tab, h.data(), sizeof(void*) * 2 * n, hipMemcpyHostToDevice));
+    lv_ok[bank] = true;
   }
   if (!*prop) HIP_TRY(hipMalloc((void**)prop, sizeof(double) * 12 * n));
-  return cnn_propose(cnn, *d_lv, n, s, *prop);
+  return cnn_propose(cnn, tab, n, s, *prop);
 }
 
 }  // namespace
@@ -2457,7 +2617,7 @@ extern "C" {
 int dpt_cnn_propose(dpt_cnn* cnn, dpt_ctx* c) {
   g_err.clear();
   if (!cnn || !c) return fail(DPT_E_ARG, "NULL argument");
-  const int e = propose_streams(cnn, &c, 1, c->stream, &c->d_cnn_lv, &c->d_prop);
+  const int e = propose_streams(cnn, &c, 1, c->stream, &c->d_cnn_lv, c->cnn_lv_ok, &c->d_prop);
   if (e == DPT_OK) c->have_prop = true;
   return e;
 }
@@ -2465,7 +2625,11 @@ int dpt_cnn_propose(dpt_cnn* cnn, dpt_ctx* c) {
 int dpt_cnn_propose_batch(dpt_cnn* cnn, dpt_batch* b) {
   g_err.clear();
   if (!cnn || !b) return fail(DPT_E_ARG, "NULL argument");
-  const int e = propose_streams(cnn, b->ctx.data(), b->n, b->stream, &b->d_cnn_lv, &b->d_prop);
+  {
+    int e0 = batch_close_update(b);
+    if (e0 != DPT_OK || (e0 = batch_consume(b)) != DPT_OK) return e0;
+  }
+  const int e = propose_streams(cnn, b->ctx.data(), b->n, b->stream, &b->d_cnn_lv, b->cnn_lv_ok, &b->d_prop);
   if (e == DPT_OK) b->have_prop = true;
   return e;
 }
@@ -2479,6 +2643,10 @@ int dpt_cnn_predict(dpt_cnn* cnn, dpt_ctx* c, double T_cw_out[16]) {
 int dpt_cnn_predict_batch(dpt_cnn* cnn, dpt_batch* b, double* T_cw_out) {
   g_err.clear();
   if (!cnn || !b || !T_cw_out) return fail(DPT_E_ARG, "NULL argument");
+  {
+    int e0 = batch_close_update(b);
+    if (e0 != DPT_OK || (e0 = batch_consume(b)) != DPT_OK) return e0;
+  }
   return predict_streams(cnn, b->ctx.data(), b->n, T_cw_out);
 }
 
@@ -2497,6 +2665,7 @@ extern "C" int dpt_batch_get_level(dpt_batch* b, int32_t slot, int32_t level, ui
     if (c->lv[level].W != g0.W || c->lv[level].H != g0.H) return fail(DPT_E_ARG, "level sizes differ across streams");
     if (!c->have_pyr[slot]) return fail(DPT_E_STATE, "stream %d has no pyramid in slot %d", s, slot);
   }
+  if (slot == DPT_SLOT_REF && b->rstream) HIP_TRY(hipStreamSynchronize(b->rstream));  // built on the reference stream
   for (int s = 0; s < b->n; ++s)
     HIP_TRY(hipMemcpyAsync(dst + s * bytes, b->ctx[s]->pyr[slot] + g0.off, bytes,
                            dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, b->stream));

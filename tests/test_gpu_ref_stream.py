@@ -37,12 +37,10 @@ def _windows(n_win, cam=synth.CAM_752, seed=2607):
 
 
 def _run(dpt, wins, prm, launch, window, ref_stream):
-    import torch
-
     trk = dpt.Tracker(synth.CAM_752, prm, max_points=N)
     trk.set_launch_config(*launch)
     if ref_stream:
-        trk.set_reference_stream(torch.cuda.Stream())
+        trk.set_reference_stream(ref_stream)
     for w in wins:  # everything enqueued, one synchronisation at the end
         trk.build_pyramid(dpt.SLOT_REF, w["img0"])
         trk.set_reference_from_depth(N, w["depth"], w["T0"])
@@ -71,10 +69,19 @@ def wins(gpu_lib):
     return _windows(5)
 
 
+@pytest.fixture(scope="module")
+def rstream(gpu_lib):
+    """One library-made stream for every case (a process that uses more streams
+    than the GPU has hardware queues runs later kernels slower)."""
+    s = gpu_lib.Stream()
+    yield s
+    s.close()
+
+
 @pytest.mark.parametrize("variant,launch,window", [
     ("fp32", (3, 128), True), ("fp32", (2, 256), True), ("fp32", (3, 128), False),
     ("mixed", (3, 128), True), ("fixed_h", (2, 256), True), ("fixed_h", (3, 128), False)])
-def test_reference_stream_equals_single_stream(gpu_lib, wins, variant, launch, window):
+def test_reference_stream_equals_single_stream(gpu_lib, wins, rstream, variant, launch, window):
     dpt = gpu_lib
     kw = dict(levels=4)
     if variant == "mixed":
@@ -83,20 +90,18 @@ def test_reference_stream_equals_single_stream(gpu_lib, wins, variant, launch, w
         kw["fixed_h"] = True
     prm = dpt.make_params(**kw)
     print(f"reference stream {variant} launch {launch} window {window}", flush=True)
-    base, cache0 = _run(dpt, wins, prm, launch, window, False)
-    piped, cache1 = _run(dpt, wins, prm, launch, window, True)
+    base, cache0 = _run(dpt, wins, prm, launch, window, None)
+    piped, cache1 = _run(dpt, wins, prm, launch, window, rstream)
     _assert_same(base, piped)
     assert all(r["status"] == 0 for r in base)
     for k in ("valid", "I0", "gx", "gy", "x0"):  # the hook reads the last committed reference
         np.testing.assert_array_equal(cache0[k], cache1[k], err_msg=k)
 
 
-def test_reference_stream_needs_a_new_reference_pyramid(gpu_lib, wins):
-    import torch
-
+def test_reference_stream_needs_a_new_reference_pyramid(gpu_lib, wins, rstream):
     dpt = gpu_lib
     trk = dpt.Tracker(synth.CAM_752, dpt.make_params(levels=4), max_points=N)
-    trk.set_reference_stream(torch.cuda.Stream())
+    trk.set_reference_stream(rstream)
     w = wins[0]
     trk.build_pyramid(dpt.SLOT_REF, w["img0"])
     trk.set_reference_from_depth(N, w["depth"], w["T0"])
@@ -109,3 +114,87 @@ def test_reference_stream_needs_a_new_reference_pyramid(gpu_lib, wins):
     trk.track_window_enqueue(w["frames"])
     assert all(r["status"] == 0 for r in trk.synchronize())
     trk.close()
+
+
+S = 4  # streams of the batch cases
+
+
+@pytest.fixture(scope="module")
+def bwins(gpu_lib):
+    """Four keyframe windows of each of S streams, each stream its own scene and trajectory."""
+    return [_windows(4, seed=2607 + 13 * s) for s in range(S)]
+
+
+def _run_batch(dpt, bw, prm, launch, window, ref_stream, cnn=None):
+    """Every window of every stream enqueued back to back; odd windows set the
+    references stream by stream, even ones in one launch sequence."""
+    bt = dpt.BatchTracker([synth.CAM_752] * S, prm, [N] * S)
+    bt.set_launch_config(*launch)
+    if ref_stream:
+        bt.set_reference_stream(ref_stream)
+    for w in range(len(bw[0])):
+        ws = [bw[s][w] for s in range(S)]
+        bt.build_pyramids(dpt.SLOT_REF, [x["img0"] for x in ws])
+        if w % 2 == 0:
+            bt.set_reference_from_depth_all(N, [x["depth"] for x in ws], np.stack([x["T0"] for x in ws]))
+        else:
+            for s, x in enumerate(ws):
+                bt.set_reference_from_depth(s, N, x["depth"], x["T0"])
+        bt.set_pose_history_all(np.stack([x["T_prev"] for x in ws]), np.stack([x["T0"] for x in ws]))
+        if window:
+            bt.track_window_enqueue([x["frames"] for x in ws])
+            continue
+        for j in range(9):
+            bt.build_pyramids(dpt.SLOT_CUR, [x["frames"][j] for x in ws])
+            if cnn is not None:
+                cnn.propose(bt)
+                bt.track_enqueue(proposed=True)
+            else:
+                bt.track_enqueue(None)
+    res = bt.synchronize()
+    ref_level = bt.get_level(dpt.SLOT_REF, 1)
+    bt.close()
+    return res, ref_level
+
+
+def _assert_same_batch(a, b):
+    assert len(a) == len(b)
+    for f, (x, y) in enumerate(zip(a, b)):
+        assert len(x) == len(y) == S
+        for s, (p, q) in enumerate(zip(x, y)):
+            for k in FIELDS:
+                np.testing.assert_array_equal(np.asarray(p[k]), np.asarray(q[k]), err_msg=f"frame {f} stream {s} field {k}")
+
+
+@pytest.mark.parametrize("variant,launch,window", [
+    ("fp32", (3, 128), True), ("fp32", (2, 256), False), ("mixed", (3, 128), True), ("fixed_h", (3, 128), False)])
+def test_batch_reference_stream_equals_single_stream(gpu_lib, bwins, rstream, variant, launch, window):
+    dpt = gpu_lib
+    kw = dict(levels=4)
+    if variant == "mixed":
+        kw["precision"] = dpt.PREC_MIXED
+    elif variant == "fixed_h":
+        kw["fixed_h"] = True
+    prm = dpt.make_params(**kw)
+    print(f"batch reference stream {variant} launch {launch} window {window}", flush=True)
+    base, lv0 = _run_batch(dpt, bwins, prm, launch, window, None)
+    piped, lv1 = _run_batch(dpt, bwins, prm, launch, window, rstream)
+    _assert_same_batch(base, piped)
+    assert all(r["status"] == 0 for f in base for r in f)
+    np.testing.assert_array_equal(lv0, lv1)  # the last reference pyramid, read after its update
+
+
+def test_learned_start_with_reference_stream(gpu_lib, bwins, rstream):
+    """Proposals read the coarsest reference level of the committed bank: the
+    proposed starts, and so the tracks, equal the single-stream ones."""
+    dpt = gpu_lib
+    from paper_2607_16897_amd import initialiser as ini
+
+    net = dpt.Cnn(max_batch=S)
+    net.set_params(ini.init_params(5))
+    prm = dpt.make_params(levels=4)
+    print("batch reference stream with learned starts", flush=True)
+    base, _ = _run_batch(dpt, bwins, prm, (3, 128), False, None, cnn=net)
+    piped, _ = _run_batch(dpt, bwins, prm, (3, 128), False, rstream, cnn=net)
+    net.close()
+    _assert_same_batch(base, piped)
