@@ -997,6 +997,7 @@ def cycle_split(args, legs):
         return {"cycles_per_iteration": per, "per_slot": {f: [round(float(x), 1) for x in used[:, k] / np.maximum(it, 1)]
                                                           for k, f in enumerate(dpt.CYCLE_FIELDS[:4])},
                 "us_per_iteration_at_shader_clock": per["total"] / clock_mhz if clock_mhz > 0 else None,
+                "polls_per_exchange": float(np.mean(used[:, 9] / np.maximum(it, 1))),
                 "shader_clock_mhz": round(clock_mhz, 1), "workgroups": int(len(used)),
                 "distinct_cus": len(cus), "xccs": sorted({p["xcc"] for p in places}), "places": places[:64]}
 

@@ -443,13 +443,15 @@ int dpt_set_spin_limit(dpt_ctx* ctx, int32_t polls);
  *   DPT_CYCLE_REALTIME    the same span in ticks of the 100 MHz constant clock
  *   DPT_CYCLE_PLACE       where the slot's last workgroup ran: XCC id << 32 |
  *                         the HW_ID register (CU, SIMD, shader engine)
+ *   DPT_CYCLE_POLLS       poll rounds of the exchanges (one round reads every
+ *                         chunk's words once)
  * out: n_slots * DPT_CYCLE_FIELDS int64, slot-major.  reset != 0 clears the
  * sums after reading.  Waits for the device.  1 <= n_slots <= 1024. */
 #define DPT_CYCLE_FIELDS 10
 enum {
   DPT_CYCLE_ACCUMULATE = 0, DPT_CYCLE_REDUCE = 1, DPT_CYCLE_EXCHANGE = 2, DPT_CYCLE_SOLVE = 3,
   DPT_CYCLE_ITERATIONS = 4, DPT_CYCLE_LAUNCHES = 5, DPT_CYCLE_KERNEL = 6, DPT_CYCLE_REALTIME = 7,
-  DPT_CYCLE_PLACE = 8
+  DPT_CYCLE_PLACE = 8, DPT_CYCLE_POLLS = 9
 };
 int dpt_cycle_profile(int64_t* out, int32_t n_slots, int32_t reset);
 

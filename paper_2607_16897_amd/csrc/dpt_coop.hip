@@ -8,7 +8,13 @@
 // word holding an epoch tag above the float's bits, so a reader knows from the
 // word alone whether it is current: a chunk publishes its partials and polls
 // the stream's words until every chunk's carry the tag, with no counter, no
-// fence and no second read.  Every chunk then sums the partials in one fixed order
+// fence and no second read.  Every word is stored twice: a group-scope copy,
+// which stays in the L2 of the chunk's XCD, and a device-scope copy, written
+// through to memory.  A stream's chunks share one XCD (the work list places
+// them so), where a device-scope poll finds the first copy in the shared L2 in
+// about half the round trip of the second; every eighth poll reads the second
+// copies instead, so a chunk that the dispatcher placed on another XCD is still
+// seen.  Every chunk then sums the partials in one fixed order
 // and every thread solves the 6x6 system itself: all threads of all chunks of
 // a stream compute bitwise-identical poses, so one exchange per iteration
 // suffices and the result is reproducible.  Waits are bounded: a chunk that
@@ -25,6 +31,16 @@ namespace dpt {
 // Chunk words read per round trip while polling (one load each in flight).
 constexpr int kPollBatch = 8;
 
+// Polls of the L2 copies between two polls of the device-scope copies, minus one.
+constexpr int kSlowPollMask = 7;
+
+// Publish one partial word: the group-scope store (kept in the XCD's L2, no
+// write-through) to `fast`, the device-scope one to `slow`.
+__device__ __forceinline__ void publish_word(uint64_t* fast, uint64_t* slow, uint64_t w) {
+  asm volatile("global_store_dwordx2 %0, %1, off sc0" : : "v"(fast), "v"(w) : "memory");
+  __hip_atomic_store(slow, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Wave 0 only.  Publish this chunk's column sums (`mine`, lanes < NV) under
 // `tag`, wait until all nch chunks of the stream published theirs, and return
 // the stream totals (lanes < NV).  False on timeout.  A chunk's words are 32
@@ -34,25 +50,25 @@ constexpr int kPollBatch = 8;
 // same in every chunk of the stream.
 template <bool KAHAN, int NV>
 __device__ __forceinline__ bool exchange_partials(uint64_t* partials, int chunk, int nch, uint32_t tag, float mine,
-                                                  int spin_limit, float* total) {
+                                                  int spin_limit, float* total, int* polls = nullptr) {
   constexpr int G = 64 / NV;
   static_assert(G == 2 || G == 4, "32 or 16 values per chunk");
   static_assert(!(KAHAN && G != 2), "compensated sums use 32 values");
   const int lane = threadIdx.x & 63, q = lane / NV, v = lane % NV;
   uint64_t* buf = partials + (size_t)(tag & 1u) * nch * 32;
+  uint64_t* slow = partials + (size_t)(2 + (tag & 1u)) * nch * 32;
   const uint64_t hi = (uint64_t)tag << 32;
-  if (lane < NV)
-    __hip_atomic_store(&buf[chunk * 32 + lane], hi | __float_as_uint(mine), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
+  if (lane < NV) publish_word(&buf[chunk * 32 + lane], &slow[chunk * 32 + lane], hi | __float_as_uint(mine));
   const int per = (nch + G - 1) / G, cb = q * per, ce = cb + per < nch ? cb + per : nch;
   for (int t = 0; t < spin_limit; ++t) {
+    const uint64_t* rb = (t & kSlowPollMask) == kSlowPollMask ? slow : buf;
     float s = 0.0f, comp = 0.0f;
     int ok = 1;
     for (int c0 = cb; c0 < ce; c0 += kPollBatch) {
       uint64_t w[kPollBatch];
 #pragma unroll
       for (int j = 0; j < kPollBatch; ++j)  // a batch of loads in flight, then the checks
-        w[j] = c0 + j < ce ? __hip_atomic_load(&buf[(c0 + j) * 32 + v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+        w[j] = c0 + j < ce ? __hip_atomic_load(&rb[(c0 + j) * 32 + v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                            : hi;
 #pragma unroll
       for (int j = 0; j < kPollBatch; ++j) {
@@ -81,6 +97,7 @@ __device__ __forceinline__ bool exchange_partials(uint64_t* partials, int chunk,
         s += __shfl_xor(s, 32, 64);
       }
       *total = s;
+      if (kCycleProfile && polls) *polls = t + 1;
       return true;
     }
     __builtin_amdgcn_s_sleep(1);
@@ -98,12 +115,14 @@ __device__ __forceinline__ bool exchange_wide(const uint64_t* partials, int nch,
                                               float* sh_grp, float* sh_tot) {
   const int t = threadIdx.x, v = t & 31, q = t >> 5, G = blockDim.x >> 5;
   const uint64_t* buf = partials + (size_t)(tag & 1u) * nch * 32;
+  const uint64_t* slow = partials + (size_t)(2 + (tag & 1u)) * nch * 32;
   const uint64_t hi = (uint64_t)tag << 32;
   float s = 0.0f, comp = 0.0f;
   bool ok = true;
   if (v < NV) {
     ok = false;
     for (int it = 0; it < spin_limit && !ok; ++it) {
+      const uint64_t* rb = (it & kSlowPollMask) == kSlowPollMask ? slow : buf;
       s = 0.0f, comp = 0.0f;
       ok = true;
       for (int c0 = q; c0 < nch; c0 += 4 * G) {
@@ -111,7 +130,7 @@ __device__ __forceinline__ bool exchange_wide(const uint64_t* partials, int nch,
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int c = c0 + j * G;
-          w[j] = c < nch ? __hip_atomic_load(&buf[c * 32 + v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : hi;
+          w[j] = c < nch ? __hip_atomic_load(&rb[c * 32 + v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : hi;
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -159,7 +178,8 @@ __device__ __forceinline__ bool exchange_wide(const uint64_t* partials, int nch,
 template <bool KAHAN, int NV, bool WIDE>
 __device__ __forceinline__ bool stream_total(float (&acc)[NV], float* sh_red, float* sh_tot, int* sh_ok,
                                              uint64_t* partials, int chunk, int nch, uint32_t tag,
-                                             int spin_limit, float* sh_grp, uint64_t* t_bar = nullptr) {
+                                             int spin_limit, float* sh_grp, uint64_t* t_bar = nullptr,
+                                             int* polls = nullptr) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   constexpr int PER_ROW = NV / 4;  // values per 16-lane row after the wave reduction
   if constexpr (NV == 32)
@@ -189,12 +209,13 @@ __device__ __forceinline__ bool stream_total(float (&acc)[NV], float* sh_red, fl
     }
     if (WIDE && nch > kPollBatch) {  // publish; the whole workgroup polls below
       if (lane < NV)
-        __hip_atomic_store(&partials[(size_t)(tag & 1u) * nch * 32 + chunk * 32 + lane],
-                           ((uint64_t)tag << 32) | __float_as_uint(s), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        publish_word(&partials[(size_t)(tag & 1u) * nch * 32 + chunk * 32 + lane],
+                     &partials[(size_t)(2 + (tag & 1u)) * nch * 32 + chunk * 32 + lane],
+                     ((uint64_t)tag << 32) | __float_as_uint(s));
     } else {
       float tot = s;
       bool ok = true;
-      if (nch > 1) ok = exchange_partials<KAHAN, NV>(partials, chunk, nch, tag, s, spin_limit, &tot);
+      if (nch > 1) ok = exchange_partials<KAHAN, NV>(partials, chunk, nch, tag, s, spin_limit, &tot, polls);
       if (lane < NV) sh_tot[lane] = tot;
       if (lane == 0) *sh_ok = ok ? 1 : 0;
     }
@@ -288,7 +309,7 @@ __device__ __forceinline__ uint64_t hw_place() {
 
 // Thread 0's phase sums of one launch into the slot's totals.
 __device__ __forceinline__ void cycles_flush(const uint64_t (&cy)[4], uint64_t iters, uint64_t t_start,
-                                             uint64_t rt_start) {
+                                             uint64_t rt_start, uint64_t polls) {
 #ifdef DPT_CYCLE_PROFILE
   if (threadIdx.x != 0 || blockIdx.x >= (unsigned)kCycleSlots) return;
   uint64_t* o = g_cycles + (size_t)blockIdx.x * kCycFields;
@@ -297,9 +318,10 @@ __device__ __forceinline__ void cycles_flush(const uint64_t (&cy)[4], uint64_t i
   atomicAdd((unsigned long long*)&o[DPT_CYCLE_LAUNCHES], 1ull);
   atomicAdd((unsigned long long*)&o[DPT_CYCLE_KERNEL], (unsigned long long)(clock64() - t_start));
   atomicAdd((unsigned long long*)&o[DPT_CYCLE_REALTIME], (unsigned long long)(wall_clock64() - rt_start));
+  atomicAdd((unsigned long long*)&o[DPT_CYCLE_POLLS], (unsigned long long)polls);
   o[DPT_CYCLE_PLACE] = hw_place();
 #else
-  (void)cy, (void)iters, (void)t_start, (void)rt_start;
+  (void)cy, (void)iters, (void)t_start, (void)rt_start, (void)polls;
 #endif
 }
 
@@ -475,7 +497,7 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
   const int sub = (int)threadIdx.x % TPP;
   const int nf = WIN ? n_frames : 1;
   uint32_t tag = tag_base;
-  uint64_t cy[4] = {0, 0, 0, 0}, cy_iters = 0, cy_t0 = 0, cy_rt0 = 0;
+  uint64_t cy[4] = {0, 0, 0, 0}, cy_iters = 0, cy_t0 = 0, cy_rt0 = 0, cy_polls = 0;
   if constexpr (kCycleProfile) cy_t0 = clock64(), cy_rt0 = wall_clock64();
   // WIN: the frames of the launch in order, each from the constant-velocity
   // prediction of the history the previous one extended.  Every chunk keeps its
@@ -541,8 +563,9 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
           accumulate_point8<false, PR, NV, NS>(a, pregs, offs, g, reinterpret_cast<const uint8_t*>(img), tile, T,
                                                pr, acc, sub == 0);
         if constexpr (kCycleProfile) c1 = clock64();
+        int polls = 0;
         if (!stream_total<MIXED, NV, GENERIC>(acc, sh_red, sh_tot, &sh_ok, ss.partials, chunk, nch, tag, spin_limit,
-                                              sh_grp, &c2)) {
+                                              sh_grp, &c2, &polls)) {
           timed_out = stop = true;
           break;
         }
@@ -576,7 +599,7 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
         }
         if constexpr (kCycleProfile) {
           const uint64_t c4 = clock64();
-          cy[0] += c1 - c0, cy[1] += c2 - c1, cy[2] += c3 - c2, cy[3] += c4 - c3, ++cy_iters;
+          cy[0] += c1 - c0, cy[1] += c2 - c1, cy[2] += c3 - c2, cy[3] += c4 - c3, ++cy_iters, cy_polls += polls;
         }
         if (bad) {
           status = 3;  // not positive definite
@@ -642,7 +665,7 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
         __threadfence_system();  // the fields reach the host before the sequence number
         o->seq = seq0;
       }
-      if constexpr (kCycleProfile) cycles_flush(cy, cy_iters, cy_t0, cy_rt0);
+      if constexpr (kCycleProfile) cycles_flush(cy, cy_iters, cy_t0, cy_rt0, cy_polls);
       return;
     }
     if (threadIdx.x == 0) {
@@ -688,7 +711,7 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
     ss.hist[threadIdx.x] = sh_h0[threadIdx.x];
     ss.hist[12 + threadIdx.x] = sh_h1[threadIdx.x];
   }
-  if constexpr (kCycleProfile) cycles_flush(cy, cy_iters, cy_t0, cy_rt0);
+  if constexpr (kCycleProfile) cycles_flush(cy, cy_iters, cy_t0, cy_rt0, cy_polls);
 }
 
 // The kernel of a variant (kCoop* bits); WIN: the window form.  Null for a
@@ -850,7 +873,7 @@ hipError_t CoopEngine::init(int n_streams, const int* max_points, int chunk_, in
   partial_words = 0;
   for (int k = 0; k < n; ++k) {
     max_chunks[k] = (max_points[k] + ppc - 1) / ppc;
-    partial_words += (size_t)2 * max_chunks[k] * 32;
+    partial_words += (size_t)4 * max_chunks[k] * 32;  // two parities, each an L2 and a device-scope copy
   }
   if (partial_words == 0) partial_words = 64;
   hipError_t e;
@@ -870,7 +893,7 @@ hipError_t CoopEngine::init(int n_streams, const int* max_points, int chunk_, in
   size_t off = 0;
   for (int k = 0; k < n; ++k) {
     h_streams[k].partials = d_partials + off;
-    off += (size_t)2 * max_chunks[k] * 32;
+    off += (size_t)4 * max_chunks[k] * 32;
   }
   dirty = true;
   return hipSuccess;

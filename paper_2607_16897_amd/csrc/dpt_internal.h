@@ -163,7 +163,7 @@ struct BackprojectArgs {
 struct CoopStream {
   TrackArgs a;         // a.ref: the reference cache of bank 0
   RefCache ref_alt;    // bank 1 (a reference stream in use), read when the launch's start slot says so
-  uint64_t* partials;  // [2][n_chunks][32] chunk sums, each word = (tag << 32) | float bits
+  uint64_t* partials;  // [2][2][n_chunks][32] chunk sums (copy: L2, device scope; parity), word = (tag << 32) | float bits
   double* hist;        // the stream's last two poses T_cw, 2 x 3x4 row-major FP64 (device)
   const uint8_t* win;  // window tracking: the pyramids of consecutive frames, win_stride bytes apart
   int64_t win_stride;
