@@ -998,6 +998,11 @@ def cycle_split(args, legs):
                                                           for k, f in enumerate(dpt.CYCLE_FIELDS[:4])},
                 "us_per_iteration_at_shader_clock": per["total"] / clock_mhz if clock_mhz > 0 else None,
                 "polls_per_exchange": float(np.mean(used[:, 9] / np.maximum(it, 1))),
+                "cycles_per_frame": {f: float(np.mean(used[:, k] / np.maximum(used[:, 13], 1)))
+                                     for k, f in ((10, "frame_start"), (11, "level_starts"), (12, "final_pass"),
+                                                  (14, "frame_end"))}
+                | {"iterations": float(np.mean(used[:, 4] / np.maximum(used[:, 13], 1))),
+                   "kernel": float(np.mean(used[:, 6] / np.maximum(used[:, 13], 1)))},
                 "shader_clock_mhz": round(clock_mhz, 1), "workgroups": int(len(used)),
                 "distinct_cus": len(cus), "xccs": sorted({p["xcc"] for p in places}), "places": places[:64]}
 

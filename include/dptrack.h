@@ -445,13 +445,21 @@ int dpt_set_spin_limit(dpt_ctx* ctx, int32_t polls);
  *                         the HW_ID register (CU, SIMD, shader engine)
  *   DPT_CYCLE_POLLS       poll rounds of the exchanges (one round reads every
  *                         chunk's words once)
+ *   DPT_CYCLE_FRAME_START each frame's start (start pose) before its first level
+ *   DPT_CYCLE_LEVEL_START each level's start (its points' registers and the
+ *                         LDS tile) before its first iteration
+ *   DPT_CYCLE_FINAL       the final cost pass with its exchange
+ *   DPT_CYCLE_FRAMES      frames tracked
+ *   DPT_CYCLE_FRAME_END   window tracks: each frame's end (its pose refined,
+ *                         its result written, the history extended)
  * out: n_slots * DPT_CYCLE_FIELDS int64, slot-major.  reset != 0 clears the
  * sums after reading.  Waits for the device.  1 <= n_slots <= 1024. */
-#define DPT_CYCLE_FIELDS 10
+#define DPT_CYCLE_FIELDS 16
 enum {
   DPT_CYCLE_ACCUMULATE = 0, DPT_CYCLE_REDUCE = 1, DPT_CYCLE_EXCHANGE = 2, DPT_CYCLE_SOLVE = 3,
   DPT_CYCLE_ITERATIONS = 4, DPT_CYCLE_LAUNCHES = 5, DPT_CYCLE_KERNEL = 6, DPT_CYCLE_REALTIME = 7,
-  DPT_CYCLE_PLACE = 8, DPT_CYCLE_POLLS = 9
+  DPT_CYCLE_PLACE = 8, DPT_CYCLE_POLLS = 9, DPT_CYCLE_FRAME_START = 10, DPT_CYCLE_LEVEL_START = 11,
+  DPT_CYCLE_FINAL = 12, DPT_CYCLE_FRAMES = 13, DPT_CYCLE_FRAME_END = 14
 };
 int dpt_cycle_profile(int64_t* out, int32_t n_slots, int32_t reset);
 

@@ -297,14 +297,14 @@ class Stream:
 
 
 CYCLE_FIELDS = ("accumulate", "reduce", "exchange", "solve", "iterations", "launches", "kernel", "realtime", "place",
-                "polls")
+                "polls", "frame_start", "level_start", "final", "frames", "frame_end", "spare")
 
 
 def cycle_profile(n_slots: int, reset: bool = True) -> np.ndarray:
     """Per-slot cycle split of the cooperative track (dpt_cycle_profile): an
-    int64 array (n_slots, 10) with columns CYCLE_FIELDS.  Needs the
+    int64 array (n_slots, 16) with columns CYCLE_FIELDS.  Needs the
     instrumented library (DPT_LIBRARY=.../libdptrack_cycles.so)."""
-    out = np.zeros((n_slots, 10), np.int64)
+    out = np.zeros((n_slots, len(CYCLE_FIELDS)), np.int64)
     _check(load().dpt_cycle_profile(out.ctypes.data, n_slots, int(bool(reset))))
     return out
 

@@ -309,7 +309,7 @@ __device__ __forceinline__ uint64_t hw_place() {
 
 // Thread 0's phase sums of one launch into the slot's totals.
 __device__ __forceinline__ void cycles_flush(const uint64_t (&cy)[4], uint64_t iters, uint64_t t_start,
-                                             uint64_t rt_start, uint64_t polls) {
+                                             uint64_t rt_start, uint64_t polls, const uint64_t (&fr)[5]) {
 #ifdef DPT_CYCLE_PROFILE
   if (threadIdx.x != 0 || blockIdx.x >= (unsigned)kCycleSlots) return;
   uint64_t* o = g_cycles + (size_t)blockIdx.x * kCycFields;
@@ -319,9 +319,10 @@ __device__ __forceinline__ void cycles_flush(const uint64_t (&cy)[4], uint64_t i
   atomicAdd((unsigned long long*)&o[DPT_CYCLE_KERNEL], (unsigned long long)(clock64() - t_start));
   atomicAdd((unsigned long long*)&o[DPT_CYCLE_REALTIME], (unsigned long long)(wall_clock64() - rt_start));
   atomicAdd((unsigned long long*)&o[DPT_CYCLE_POLLS], (unsigned long long)polls);
+  for (int k = 0; k < 5; ++k) atomicAdd((unsigned long long*)&o[DPT_CYCLE_FRAME_START + k], (unsigned long long)fr[k]);
   o[DPT_CYCLE_PLACE] = hw_place();
 #else
-  (void)cy, (void)iters, (void)t_start, (void)rt_start, (void)polls;
+  (void)cy, (void)iters, (void)t_start, (void)rt_start, (void)polls, (void)fr;
 #endif
 }
 
@@ -402,7 +403,8 @@ __device__ __forceinline__ Tile8 stage_tile(const TrackArgs& a, const PatRegs& p
   const int ng = (delta + (hi - lo + 1) * W + 15) >> 4;
   // Global memory straight into LDS (global_load_lds_dwordx4): each wave moves
   // 64 consecutive granules per instruction, every load in flight at once and
-  // no registers held; one wait for all of them.
+  // no registers held.  The caller waits for all of them (s_waitcnt 0, then a
+  // workgroup barrier) before the tile is read.
   const int lane = threadIdx.x & 63;
   for (int q0 = (int)(threadIdx.x & ~63u); q0 < ng; q0 += blockDim.x) {
     const int q = q0 + lane;
@@ -410,8 +412,6 @@ __device__ __forceinline__ Tile8 stage_tile(const TrackArgs& a, const PatRegs& p
       __builtin_amdgcn_global_load_lds(reinterpret_cast<const uint32_t*>(s0 + 16 * (uintptr_t)q),
                                        (__attribute__((address_space(3))) void*)(tile_mem + 16 * q0), 16, 0, 0);
   }
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
   Tile8 t;
   t.lds = (const __attribute__((address_space(3))) uint8_t*)(tile_mem);
   t.lo = lo, t.hi = hi, t.delta = delta, t.bytes = ng * 16;
@@ -498,12 +498,15 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
   const int nf = WIN ? n_frames : 1;
   uint32_t tag = tag_base;
   uint64_t cy[4] = {0, 0, 0, 0}, cy_iters = 0, cy_t0 = 0, cy_rt0 = 0, cy_polls = 0;
+  uint64_t cy_fr[5] = {0, 0, 0, 0, 0};  // frame start, level starts, final pass, frames, frame end
   if constexpr (kCycleProfile) cy_t0 = clock64(), cy_rt0 = wall_clock64();
   // WIN: the frames of the launch in order, each from the constant-velocity
   // prediction of the history the previous one extended.  Every chunk keeps its
   // own copy of the history in LDS: the poses are bitwise identical in all
   // chunks of a stream, so no exchange is needed between frames.
   for (int f = 0; f < nf; ++f) {
+    uint64_t cf0 = 0;
+    if constexpr (kCycleProfile) cf0 = clock64();
     if (WIN && f > 0) const_velocity_start(sh_T0, sh_rw, sh_h0, sh_h1, sh_m1, sh_m2);
     const PIX* cur = WIN        ? reinterpret_cast<const PIX*>(ss.win + f * ss.win_stride)
                      : FLOAT_PYR ? reinterpret_cast<const PIX*>(a.curf)
@@ -526,7 +529,14 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
     int64_t samples = 0;
     bool stop = false, timed_out = false;
     PR pr;
+    // the level-0 tile and point registers, reused by the final pass when the
+    // levels ran down to 0
+    Tile8 tile0 = no_tile(sh_tile);
+    bool at0 = false;
+    if constexpr (kCycleProfile) cy_fr[0] += clock64() - cf0, ++cy_fr[3];
     for (int l = a.levels - 1; l >= 0 && !stop; --l) {
+      uint64_t cl0 = 0;
+      if constexpr (kCycleProfile) cl0 = clock64();
       const LevelGeom g = a.lv[l];
       const PIX* img = WIN && l == 0 ? cur0 : cur + g.off;
       Tile8 tile;
@@ -540,6 +550,9 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
           load_point(a, l, i, pr);
         lane_offsets<NS>(pregs, g.W, sub, offs);
         tile = stage_tile(a, pregs, g, reinterpret_cast<const uint8_t*>(img), T, pr, sh_tile, tile_bytes, sh_band);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (l == 0) tile0 = tile, at0 = true;
       }
       if constexpr (FIXED) {
         // read by every thread after the next exchange's barrier; the other
@@ -551,6 +564,7 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
       }
       bool converged = false;
       const int it0 = iterations;
+      if constexpr (kCycleProfile) cy_fr[1] += clock64() - cl0;
       for (int it = 0; it < a.max_iters; ++it) {
         uint64_t c0 = 0, c1 = 0, c2 = 0;
         if constexpr (kCycleProfile) c0 = clock64();
@@ -616,6 +630,8 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
       for (int j = 0; j < kMaxLevels; ++j) ipl[j] = j == l ? iterations - it0 : ipl[j];
       if (!stop && l == 0 && !converged) status = 1;  // iteration cap at level 0
     }
+    uint64_t cp0 = 0;
+    if constexpr (kCycleProfile) cp0 = clock64();
     if (!timed_out) {  // final cost-only pass at level 0
       float acc[NV];
 #pragma unroll
@@ -625,20 +641,22 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
         load_point_geo(a, 0, i, pr);
         accumulate_point_generic<true, PIX, NV>(a, a.pat, g, WIN ? cur0 : cur + g.off, T, pr, sub, acc);
       } else {
-        if constexpr (LPP == 2)
-          load_point(a, 0, i, sub, pr);
-        else
-          load_point(a, 0, i, pr);
+        if (!at0) {  // the levels stopped above 0: level 0's registers, taps from global memory
+          if constexpr (LPP == 2)
+            load_point(a, 0, i, sub, pr);
+          else
+            load_point(a, 0, i, pr);
+        }
         int offs[NS];
         lane_offsets<NS>(pregs, g.W, sub, offs);
-        accumulate_point8<true, PR, NV, NS>(a, pregs, offs, g, WIN ? cur0 : cur + g.off, no_tile(sh_tile), T, pr,
-                                            acc, sub == 0);
+        accumulate_point8<true, PR, NV, NS>(a, pregs, offs, g, WIN ? cur0 : cur + g.off, tile0, T, pr, acc, sub == 0);
       }
       if (!stream_total<MIXED, NV, GENERIC>(acc, sh_red, sh_tot, &sh_ok, ss.partials, chunk, nch, tag, spin_limit,
                                             sh_grp))
         timed_out = true;
       ++tag;
     }
+    if constexpr (kCycleProfile) cy_fr[2] += clock64() - cp0;
     if constexpr (!WIN) {
       if (chunk == 0 && threadIdx.x == 0) {
         TrackOut* o = out_ring + (size_t)slot * n_out + w.x;
@@ -662,12 +680,16 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
         o->n_valid_points = (int)sh_tot[sP];
         o->status = timed_out ? kStatusTimeout : status;
         o->samples = samples + (int64_t)sh_tot[sN];
-        __threadfence_system();  // the fields reach the host before the sequence number
+        // the fields reach the host before the sequence number: a system-scope
+        // release (no acquire, so the L2 keeps the reference data it holds)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
         o->seq = seq0;
       }
-      if constexpr (kCycleProfile) cycles_flush(cy, cy_iters, cy_t0, cy_rt0, cy_polls);
+      if constexpr (kCycleProfile) cycles_flush(cy, cy_iters, cy_t0, cy_rt0, cy_polls, cy_fr);
       return;
     }
+    uint64_t ct0 = 0;
+    if constexpr (kCycleProfile) ct0 = clock64();
     if (threadIdx.x == 0) {
       double Tf[12];
       for (int j = 0; j < 12; ++j) Tf[j] = MIXED ? Td[j] : (double)T[j];
@@ -689,7 +711,7 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
         // a chunk gave up: so do the frames after this one
         if (timed_out)
           for (int q = f + 1; q < nf; ++q) out_ring[(size_t)((slot + q) % kRing) * n_out + w.x].status = kStatusTimeout;
-        __threadfence_system();  // the fields reach the host before the sequence numbers
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");  // the fields reach the host before the sequence numbers
         o->seq = seq0 + f;
         if (timed_out)
           for (int q = f + 1; q < nf; ++q) out_ring[(size_t)((slot + q) % kRing) * n_out + w.x].seq = seq0 + q;
@@ -703,6 +725,7 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
       sh_h1[threadIdx.x] = v;
     }
     __syncthreads();
+    if constexpr (kCycleProfile) cy_fr[4] += clock64() - ct0;
     if (timed_out) break;
   }
   // the stream's history for the next launch (every chunk read it at its start,
@@ -711,7 +734,7 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
     ss.hist[threadIdx.x] = sh_h0[threadIdx.x];
     ss.hist[12 + threadIdx.x] = sh_h1[threadIdx.x];
   }
-  if constexpr (kCycleProfile) cycles_flush(cy, cy_iters, cy_t0, cy_rt0, cy_polls);
+  if constexpr (kCycleProfile) cycles_flush(cy, cy_iters, cy_t0, cy_rt0, cy_polls, cy_fr);
 }
 
 // The kernel of a variant (kCoop* bits); WIN: the window form.  Null for a
