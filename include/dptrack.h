@@ -621,8 +621,8 @@ int dpt_cnn_propose_batch(dpt_cnn* c, dpt_batch* b);
 
 /* ------------------------------------------------------------------ device characterisation
  * Attainable peaks for the roofline figures, measured on the current device
- * (not part of the method).  Each call allocates, runs two launches on a
- * private stream, times the second with events and frees; it synchronises.
+ * (not part of the method).  Each call allocates, runs two launches on the
+ * null stream, times the second with events and frees; it synchronises.
  *
  * dpt_probe_read_bandwidth: 8 workgroups per compute unit, workgroup w reading
  * slice w % n_slices of a zeroed buffer of n_slices x slice_bytes bytes

@@ -51,15 +51,16 @@ int cus() {
   return n;
 }
 
-// Milliseconds of the second of two launches of `launch` on a private stream.
+// Milliseconds of the second of two launches of `launch` on the null stream
+// (no stream of its own: a process that has used more streams than the GPU
+// has hardware queues runs its later kernels slower).
 template <class F>
 int time_ms(F launch, float* ms) {
-  hipStream_t st = nullptr;
+  const hipStream_t st = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   int rc = DPT_OK;
-  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
-      hipEventCreate(&e1) != hipSuccess) {
-    rc = set_error(DPT_E_HIP, "probe: stream or event creation failed");
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    rc = set_error(DPT_E_HIP, "probe: event creation failed");
   } else {
     launch(st);  // warm-up: first touch of the buffer, code load
     if (hipEventRecord(e0, st) != hipSuccess) rc = set_error(DPT_E_HIP, "probe: event record");
@@ -70,7 +71,6 @@ int time_ms(F launch, float* ms) {
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
-  if (st) (void)hipStreamDestroy(st);
   return rc;
 }
 
