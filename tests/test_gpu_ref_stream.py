@@ -198,3 +198,61 @@ def test_learned_start_with_reference_stream(gpu_lib, bwins, rstream):
     piped, _ = _run_batch(dpt, bwins, prm, (3, 128), False, rstream, cnn=net)
     net.close()
     _assert_same_batch(base, piped)
+
+
+def test_reference_reads_follow_the_update(gpu_lib, wins, rstream):
+    """Reading the reference pyramid back right after an update on the second
+    stream (tracks of the previous reference still in flight) returns the new
+    reference, level by level, as the one-stream context does; so do the
+    template cache and a batch's packed levels."""
+    dpt = gpu_lib
+    prm = dpt.make_params(levels=4)
+    one = dpt.Tracker(synth.CAM_752, prm, max_points=N)
+    two = dpt.Tracker(synth.CAM_752, prm, max_points=N)
+    two.set_reference_stream(rstream)
+    for w in wins[:4]:
+        for t in (one, two):
+            t.build_pyramid(dpt.SLOT_REF, w["img0"])
+            t.set_reference_from_depth(N, w["depth"], w["T0"])
+        for l in range(4):
+            np.testing.assert_array_equal(one.get_pyramid(dpt.SLOT_REF, l), two.get_pyramid(dpt.SLOT_REF, l),
+                                          err_msg=f"level {l}")
+        c1, c2 = one.reference_cache(1), two.reference_cache(1)
+        for k in ("valid", "I0", "gx", "gy", "x0"):
+            np.testing.assert_array_equal(c1[k], c2[k], err_msg=k)
+        for t in (one, two):  # tracks in flight while the next reference is built
+            t.set_pose_history(w["T_prev"], w["T0"])
+            t.track_window_enqueue(w["frames"])
+    _assert_same(one.synchronize(), two.synchronize())
+    one.close()
+    two.close()
+
+
+def test_batch_levels_follow_the_update(gpu_lib, bwins, rstream):
+    dpt = gpu_lib
+    prm = dpt.make_params(levels=4)
+    bts = [dpt.BatchTracker([synth.CAM_752] * S, prm, [N] * S) for _ in range(2)]
+    bts[1].set_reference_stream(rstream)
+    for w in range(len(bwins[0])):
+        ws = [bwins[s][w] for s in range(S)]
+        for bt in bts:
+            bt.build_pyramids(dpt.SLOT_REF, [x["img0"] for x in ws])
+            bt.set_reference_from_depth_all(N, [x["depth"] for x in ws], np.stack([x["T0"] for x in ws]))
+        for l in range(4):
+            np.testing.assert_array_equal(bts[0].get_level(dpt.SLOT_REF, l), bts[1].get_level(dpt.SLOT_REF, l))
+        for bt in bts:
+            bt.set_pose_history_all(np.stack([x["T_prev"] for x in ws]), np.stack([x["T0"] for x in ws]))
+            bt.track_window_enqueue([x["frames"] for x in ws])
+    _assert_same_batch(bts[0].synchronize(), bts[1].synchronize())
+    for bt in bts:
+        bt.close()
+
+
+def test_library_streams_can_be_made_and_released(gpu_lib):
+    dpt = gpu_lib
+    streams = [dpt.Stream() for _ in range(3)]
+    assert len({s.cuda_stream for s in streams}) == 3 and all(s.cuda_stream for s in streams)
+    for s in streams:
+        s.close()
+        assert s.cuda_stream == 0
+        s.close()  # a second close is a no-op
