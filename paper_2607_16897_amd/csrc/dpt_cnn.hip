@@ -311,9 +311,8 @@ __global__ __launch_bounds__(256) void conv_bwd_weight_mfma(const uint16_t* __re
   const int o = mt * 16 + (lane & 15), n = nt * 16 + (lane & 15);
   const bool real = n < 9 * CI, ones = n == 9 * CI;
   const int tap = real ? n / CI : 0, c = real ? n % CI : 0, ky = tap / 3, kx = tap % 3;
-  float4_t acc = float4_t{0.f, 0.f, 0.f, 0.f};
-  for (int pb = p0; pb < p1; pb += 16) {
-    short a[4], bb[4];
+  // the lane's four rows of the step at pb: dZ and the im2col column
+  auto operands = [&](int pb, short (&a)[4], short (&bb)[4]) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int p = pb + 4 * q + t;
@@ -331,39 +330,69 @@ __global__ __launch_bounds__(256) void conv_bwd_weight_mfma(const uint16_t* __re
       a[t] = (short)av;
       bb[t] = (short)bv;
     }
+  };
+  float4_t acc = float4_t{0.f, 0.f, 0.f, 0.f};
+  short a[4], bb[4];
+  operands(p0, a, bb);
+  for (int pb = p0; pb < p1; pb += 16) {  // the next step's loads in flight during this step's product
+    short a2[4], b2[4];
+    operands(pb + 16, a2, b2);
     acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(short4_t{a[0], a[1], a[2], a[3]},
                                                      short4_t{bb[0], bb[1], bb[2], bb[3]}, acc, 0, 0, 0);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) a[t] = a2[t], bb[t] = b2[t];
   }
   float* out = partial + (size_t)split * CO * NPAD;
 #pragma unroll
   for (int jq = 0; jq < 4; ++jq) out[(size_t)(mt * 16 + 4 * q + jq) * NPAD + n] = acc[jq];
 }
 
-// Sum of the splits of conv_bwd_weight_mfma in split order, into the gradient
-// vector: weights at w_off + o * 9 CI + n ([co][ky][kx][ci]), bias at b_off + o.
-template <int L>
-__global__ void reduce_wgrad(const float* __restrict__ partial, int splits, float* __restrict__ gw,
-                             float* __restrict__ gb) {
-  constexpr int CI = kC[L], CO = kC[L + 1], NPAD = (9 * CI + 1 + 15) / 16 * 16;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= CO * NPAD) return;
-  const int o = e / NPAD, n = e % NPAD;
-  if (n > 9 * CI) return;
+// sum_k v[k * n + e] for the n elements e of a block's share, in a fixed
+// order: the PARTS threads of an element (threads el, el + 256 / PARTS, ...)
+// sum k = part, part + PARTS, ... in order, and the parts meet in a fixed
+// pairwise tree in LDS.  The result goes to out(e, sum) (part 0's thread).
+template <int PARTS, class Out>
+__device__ __forceinline__ void sum_slices(const float* __restrict__ v, int K, int n, Out out) {
+  constexpr int EPB = 256 / PARTS;  // elements per block
+  __shared__ float sh[256];
+  const int el = (int)threadIdx.x % EPB, part = (int)threadIdx.x / EPB;
+  const int e = (int)blockIdx.x * EPB + el;
   float s = 0.f;
-  for (int k = 0; k < splits; ++k) s += partial[(size_t)k * CO * NPAD + e];
-  if (n < 9 * CI)
-    gw[o * 9 * CI + n] = s;
-  else
-    gb[o] = s;
+  if (e < n)
+    for (int k = part; k < K; k += PARTS) s += v[(size_t)k * n + e];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+#pragma unroll
+  for (int w = PARTS / 2; w > 0; w >>= 1) {
+    if (part < w) sh[threadIdx.x] += sh[threadIdx.x + w * EPB];
+    __syncthreads();
+  }
+  if (part == 0 && e < n) out(e, sh[el]);
 }
 
-// sum over batch of the per-sample FC gradients (fixed order), and of the squared errors
-__global__ void reduce_batch(const float* __restrict__ v, int B, int n, float* __restrict__ out) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  float s = 0.f;
-  for (int b = 0; b < B; ++b) s += v[(size_t)b * n + e];
-  out[e] = s;
+// Threads per element for a sum over K slices: about sixteen slices each.
+inline int parts_for(int K) { return K > 1024 ? 256 : K > 256 ? 64 : K > 64 ? 16 : K > 16 ? 4 : 1; }
+
+// Sum of the splits of conv_bwd_weight_mfma into the gradient vector: weights
+// at w_off + o * 9 CI + n ([co][ky][kx][ci]), bias at b_off + o.
+template <int L, int PARTS>
+__global__ __launch_bounds__(256) void reduce_wgrad(const float* __restrict__ partial, int splits,
+                                                    float* __restrict__ gw, float* __restrict__ gb) {
+  constexpr int CI = kC[L], CO = kC[L + 1], NPAD = (9 * CI + 1 + 15) / 16 * 16;
+  sum_slices<PARTS>(partial, splits, CO * NPAD, [&](int e, float s) {
+    const int o = e / NPAD, n = e % NPAD;
+    if (n < 9 * CI)
+      gw[o * 9 * CI + n] = s;
+    else if (n == 9 * CI)
+      gb[o] = s;
+  });
+}
+
+// Sum over the batch of the per-sample FC gradients, and of the squared errors.
+template <int PARTS>
+__global__ __launch_bounds__(256) void reduce_batch(const float* __restrict__ v, int B, int n,
+                                                    float* __restrict__ out) {
+  sum_slices<PARTS>(v, B, n, [&](int e, float s) { out[e] = s; });
 }
 
 // ---------------------------------------------------------------- Adam
@@ -459,10 +488,36 @@ int cfail(int code, const char* msg) { return set_error(code, msg); }
     if (e_ != hipSuccess) return cfail(DPT_E_HIP, #expr);      \
   } while (0)
 
-// Output pixels per split of the weight gradient: a few hundred MFMA steps per wave.
-constexpr int kPixPerSplit = 2048;
+// Output pixels per split of the weight gradient, per layer: 8-16 MFMA steps
+// per wave and a few thousand waves, so the loads of many waves overlap (the
+// first and last layers have the fewest tiles, so the shortest splits).
+constexpr int kPixPerSplit[4] = {128, 256, 256, 128};
 
-int splits_for(int l, int B) { return (B * kHs[l + 1] * kWs[l + 1] + kPixPerSplit - 1) / kPixPerSplit; }
+int splits_for(int l, int B) { return (B * kHs[l + 1] * kWs[l + 1] + kPixPerSplit[l] - 1) / kPixPerSplit[l]; }
+
+// Launch of a sum over K slices with the PARTS that parts_for(K) picks.
+template <template <int> class Kernel, class... Args>
+void launch_sum(int K, int n, hipStream_t s, Args... args) {
+  switch (parts_for(K)) {
+    case 256: hipLaunchKernelGGL(Kernel<256>::fn, dim3(n), dim3(256), 0, s, args...); break;
+    case 64: hipLaunchKernelGGL(Kernel<64>::fn, dim3((n + 3) / 4), dim3(256), 0, s, args...); break;
+    case 16: hipLaunchKernelGGL(Kernel<16>::fn, dim3((n + 15) / 16), dim3(256), 0, s, args...); break;
+    case 4: hipLaunchKernelGGL(Kernel<4>::fn, dim3((n + 63) / 64), dim3(256), 0, s, args...); break;
+    default: hipLaunchKernelGGL(Kernel<1>::fn, dim3((n + 255) / 256), dim3(256), 0, s, args...); break;
+  }
+}
+
+template <int L>
+struct WgradSum {
+  template <int PARTS>
+  struct K {
+    static constexpr auto fn = reduce_wgrad<L, PARTS>;
+  };
+};
+template <int PARTS>
+struct BatchSum {
+  static constexpr auto fn = reduce_batch<PARTS>;
+};
 
 constexpr int npad(int l) { return (9 * kC[l] + 1 + 15) / 16 * 16; }
 
@@ -486,9 +541,9 @@ hipError_t bwd_layer(dpt_cnn* c, int B) {
   const int P = B * kHs[L + 1] * kWs[L + 1], splits = splits_for(L, B);
   const int tiles = (CO / 16) * (npad(L) / 16);
   hipLaunchKernelGGL((conv_bwd_weight_mfma<L>), dim3((tiles + 3) / 4, splits), dim3(256), 0, c->stream, c->dz[L + 1],
-                     c->act[L], P, kPixPerSplit, c->partial);
-  hipLaunchKernelGGL((reduce_wgrad<L>), dim3((CO * npad(L) + 255) / 256), dim3(256), 0, c->stream, c->partial, splits,
-                     c->G + c->o.w[L], c->G + c->o.b[L]);
+                     c->act[L], P, kPixPerSplit[L], c->partial);
+  launch_sum<WgradSum<L>::template K>(splits, CO * npad(L), c->stream, (const float*)c->partial, splits,
+                                      c->G + c->o.w[L], c->G + c->o.b[L]);
   if constexpr (L > 0) {
     int rows = 0;  // the largest parity class
     for (int cls = 0; cls < 4; ++cls)
@@ -658,8 +713,8 @@ int dpt_cnn_train_step(dpt_cnn* c, const uint8_t* pairs, const float* targets, i
   hipLaunchKernelGGL(head_kernel, dim3(B), dim3(64), 0, c->stream, c->act[4], c->P, tg, B, c->out, c->sqerr, c->fcg,
                      c->dz[4]);
   const int nfc = o.total - o.fw1;
-  hipLaunchKernelGGL(reduce_batch, dim3((nfc + 255) / 256), dim3(256), 0, c->stream, c->fcg, B, nfc, c->G + o.fw1);
-  hipLaunchKernelGGL(reduce_batch, dim3(1), dim3(64), 0, c->stream, c->sqerr, B, kOut, c->scal);
+  launch_sum<BatchSum>(B, nfc, c->stream, (const float*)c->fcg, B, nfc, c->G + o.fw1);
+  launch_sum<BatchSum>(B, kOut, c->stream, (const float*)c->sqerr, B, (int)kOut, c->scal);
   CNN_TRY(hipGetLastError());
   CNN_TRY(backward(c, B));
   if (lr > 0.f) {
