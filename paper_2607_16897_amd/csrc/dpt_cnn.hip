@@ -82,16 +82,6 @@ __global__ void input_from_pairs(const uint8_t* __restrict__ pairs, int B, uint1
     x[2 * p + c] = f2bf(((float)pairs[((size_t)b * 2 + c) * kH0 * kW0 + r] - 128.0f) * (1.0f / 64.0f));
 }
 
-// coarsest pyramid levels of stream pairs (ref[b], cur[b] device pointers) -> BF16 NHWC
-__global__ void input_from_levels(const uint8_t* const* __restrict__ refs, const uint8_t* const* __restrict__ curs,
-                                  int B, uint16_t* __restrict__ x) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= B * kH0 * kW0) return;
-  const int b = p / (kH0 * kW0), r = p % (kH0 * kW0);
-  x[2 * p] = f2bf(((float)refs[b][r] - 128.0f) * (1.0f / 64.0f));
-  x[2 * p + 1] = f2bf(((float)curs[b][r] - 128.0f) * (1.0f / 64.0f));
-}
-
 // ---------------------------------------------------------------- forward convolution (MFMA)
 
 // Implicit GEMM: rows m = output pixels (b, i, j), columns n = output channels,
@@ -167,6 +157,196 @@ __global__ __launch_bounds__(256) void conv_fwd_mfma(const uint16_t* __restrict_
   }
 }
 
+// ---------------------------------------------------------------- head forward and proposal (device parts)
+
+// The network's outputs are twists scaled to unit range: 5 degrees (in
+// radians) for the rotation part, 0.1 m for the translation part.
+__constant__ double kTwistScaleDev[6] = {0.08726646259971647, 0.08726646259971647, 0.08726646259971647,
+                                         0.1, 0.1, 0.1};
+
+// rel = exp(xi) as 3x4 FP64, xi = the six scaled outputs o6 (rotation first).
+__device__ __forceinline__ void propose_twist(const float* o6, double* rel) {
+  double xi[6];
+  for (int j = 0; j < 6; ++j) xi[j] = (double)o6[j] * kTwistScaleDev[j];
+  const double th2 = fma(xi[0], xi[0], fma(xi[1], xi[1], xi[2] * xi[2]));
+  double A, Bc, C;
+  if (th2 < 1e-8) {  // |w| < 1e-4: series, truncation below 1e-17
+    A = 1.0 - th2 * (1.0 / 6.0);
+    Bc = 0.5 - th2 * (1.0 / 24.0);
+    C = (1.0 / 6.0) - th2 * (1.0 / 120.0);
+  } else {
+    const double th = sqrt(th2), sn = sin(th), sh = sin(0.5 * th);
+    A = sn / th;
+    Bc = 2.0 * sh * sh / th2;
+    C = (th - sn) / (th2 * th);
+  }
+  double T[12] = {1.0, 0.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 0.0, 1.0, 0.0};
+  compose_exp(T, xi[0], xi[1], xi[2], xi[3], xi[4], xi[5], th2, A, Bc, C);
+  for (int j = 0; j < 12; ++j) rel[j] = T[j];
+}
+
+// The head's forward pass on one sample's layer-4 activations a (4 x 6 x 64,
+// LDS or global): g = their mean, h1 = relu(fw1 g + fb1), and for threads
+// t < kOut the return value out[t] = fw2 h1 + fb2.  Threads t < 64 do the
+// work; every thread of the workgroup calls it (two barriers); g and h1 are
+// 64-float LDS vectors.
+__device__ __forceinline__ float head_forward(const uint16_t* __restrict__ a, const float* __restrict__ P,
+                                              const Offsets& o, float* g, float* h1) {
+  constexpr int HW = 4 * 6;
+  const int t = threadIdx.x;
+  if (t < 64) {
+    float s = 0.f;
+    for (int p = 0; p < HW; ++p) s += bf2f(a[p * 64 + t]);
+    g[t] = s * (1.0f / HW);
+  }
+  __syncthreads();
+  if (t < 64) {
+    float z = P[o.fb1 + t];
+    for (int q = 0; q < 64; ++q) z = fmaf(P[o.fw1 + t * 64 + q], g[q], z);
+    h1[t] = fmaxf(z, 0.f);
+  }
+  __syncthreads();
+  float v = 0.f;
+  if (t < kOut) {
+    v = P[o.fb2 + t];
+    for (int q = 0; q < kHidden; ++q) v = fmaf(P[o.fw2 + t * kHidden + q], h1[q], v);
+  }
+  return v;
+}
+
+// ---------------------------------------------------------------- fused inference convolutions
+
+// One layer of one sample inside a workgroup: conv_fwd_mfma's implicit GEMM
+// (the same k order, lane layout and epilogue, so bitwise the same outputs)
+// with the sample's activations and the layer's weights in LDS.  The waves
+// take the (16-row tile, 16-channel tile) pairs in turn.
+template <int CI, int CO>
+__device__ __forceinline__ void conv_sample(const uint16_t* __restrict__ x, int H, int W, int Ho, int Wo,
+                                            const uint16_t* __restrict__ w, const float* __restrict__ bias,
+                                            uint16_t* __restrict__ y) {
+  constexpr int K = 9 * CI, KP = (K + 15) / 16 * 16, NT = CO / 16;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6, kq = lane >> 4;
+  const int M = Ho * Wo, items = (M + 15) / 16 * NT;
+  for (int it = wave; it < items; it += nw) {
+    const int m0 = it / NT * 16, t = it % NT, n = t * 16 + (lane & 15);
+    const int m = m0 + (lane & 15);
+    const bool mvalid = m < M;
+    const int i = mvalid ? m / Wo : 0, j = mvalid ? m % Wo : 0;
+    float4_t acc = float4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < KP / 16; ++ks) {
+      const int k0 = ks * 16 + 4 * kq;
+      short4_t a, bv;
+      if constexpr (CI % 4 == 0) {
+        const int tap = k0 / CI, c = k0 % CI;
+        const int yy = 2 * i + tap / 3 - 1, xx = 2 * j + tap % 3 - 1;
+        uint2 v = make_uint2(0u, 0u);
+        if (mvalid && yy >= 0 && yy < H && xx >= 0 && xx < W)
+          v = *reinterpret_cast<const uint2*>(x + (yy * W + xx) * CI + c);
+        a = short4_t{(short)(v.x & 0xffff), (short)(v.x >> 16), (short)(v.y & 0xffff), (short)(v.y >> 16)};
+        const uint2 u = *reinterpret_cast<const uint2*>(w + n * K + k0);
+        bv = short4_t{(short)(u.x & 0xffff), (short)(u.x >> 16), (short)(u.y & 0xffff), (short)(u.y >> 16)};
+      } else {
+        short e[4], f[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int k = k0 + q;
+          uint16_t v = 0;
+          if (k < K && mvalid) {
+            const int tap = k / CI, c = k % CI;
+            const int yy = 2 * i + tap / 3 - 1, xx = 2 * j + tap % 3 - 1;
+            if (yy >= 0 && yy < H && xx >= 0 && xx < W) v = x[(yy * W + xx) * CI + c];
+          }
+          e[q] = (short)v;
+          f[q] = k < K ? (short)w[n * K + k] : (short)0;
+        }
+        a = short4_t{e[0], e[1], e[2], e[3]};
+        bv = short4_t{f[0], f[1], f[2], f[3]};
+      }
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int mo = m0 + 4 * kq + q;
+      if (mo < M) y[mo * CO + n] = f2bf(fmaxf(acc[q] + bias[n], 0.0f));
+    }
+  }
+}
+
+// A layer's BF16 weights ([co][tap][ci], `bytes` a multiple of 16 from a
+// 16-byte aligned source) copied into LDS by the workgroup, global memory
+// straight into LDS; the caller waits (s_waitcnt 0, then a barrier).
+__device__ __forceinline__ void stage_weights(const uint16_t* __restrict__ src, int bytes, uint16_t* lds) {
+  const int lane = threadIdx.x & 63, ng = bytes >> 4;
+  for (int q0 = (int)(threadIdx.x & ~63u); q0 < ng; q0 += blockDim.x)
+    if (q0 + lane < ng)
+      __builtin_amdgcn_global_load_lds(reinterpret_cast<const uint32_t*>(src) + 4 * (q0 + lane),
+                                       (__attribute__((address_space(3))) void*)(lds + 8 * q0), 16, 0, 0);
+}
+
+// LDS of the fused pass (elements): two ping-pong activation buffers and the
+// current layer's weights.
+constexpr int kFuseA = 15 * 24 * 32 > kH0 * kW0 * 2 ? 15 * 24 * 32 : kH0 * kW0 * 2;  // input, layer 2 out
+constexpr int kFuseB = 30 * 47 * 16;                                                  // layer 1 and 3 out
+constexpr int kFuseW = 64 * 9 * 64;                                                   // layer 4's weights
+static_assert(kHs[1] == 30 && kWs[1] == 47 && kC[1] == 16 && kHs[2] == 15 && kWs[2] == 24 && kC[2] == 32 &&
+                  kHs[3] * kWs[3] * kC[3] <= kFuseB && kC[3] * 9 * kC[4] <= kFuseW,
+              "fused buffers follow the layer shapes");
+constexpr int kFuseThreads = 512;
+
+// Inference: the input and the four convolutions of sample blockIdx.x in one
+// workgroup, the activations never leaving LDS and each layer's weights
+// staged in LDS before it runs; layer 4's output goes to a4 ([B][4][6][64], as
+// the layer-by-layer forward writes it) for the head.
+__global__ __launch_bounds__(kFuseThreads) void conv_net_fused(const uint8_t* const* __restrict__ refs,
+                                                               const uint8_t* const* __restrict__ curs,
+                                                               const uint16_t* __restrict__ Pb,
+                                                               const float* __restrict__ P, uint16_t* __restrict__ a4,
+                                                               float* __restrict__ out, double* __restrict__ rel) {
+  __shared__ __align__(16) uint16_t bufA[kFuseA];
+  __shared__ float sh_g[64], sh_h1[64], sh_out[kOut];
+  __shared__ __align__(16) uint16_t bufB[kFuseB];
+  __shared__ __align__(16) uint16_t bufW[kFuseW];
+  const int b = blockIdx.x;
+  const Offsets o = offsets();
+  stage_weights(Pb + o.w[0], kC[1] * 9 * kC[0] * 2, bufW);
+  const uint8_t* ref = refs[b];
+  const uint8_t* cur = curs[b];
+  for (int r = threadIdx.x; r < kH0 * kW0; r += blockDim.x) {  // (I - 128) / 64, as input_from_pairs
+    bufA[2 * r] = f2bf(((float)ref[r] - 128.0f) * (1.0f / 64.0f));
+    bufA[2 * r + 1] = f2bf(((float)cur[r] - 128.0f) * (1.0f / 64.0f));
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  conv_sample<2, 16>(bufA, kHs[0], kWs[0], kHs[1], kWs[1], bufW, P + o.b[0], bufB);
+  __syncthreads();
+  stage_weights(Pb + o.w[1], kC[2] * 9 * kC[1] * 2, bufW);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  conv_sample<16, 32>(bufB, kHs[1], kWs[1], kHs[2], kWs[2], bufW, P + o.b[1], bufA);
+  __syncthreads();
+  stage_weights(Pb + o.w[2], kC[3] * 9 * kC[2] * 2, bufW);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  conv_sample<32, 64>(bufA, kHs[2], kWs[2], kHs[3], kWs[3], bufW, P + o.b[2], bufB);
+  __syncthreads();
+  stage_weights(Pb + o.w[3], kC[4] * 9 * kC[3] * 2, bufW);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  constexpr int N4 = kHs[4] * kWs[4] * kC[4];
+  conv_sample<64, 64>(bufB, kHs[3], kWs[3], kHs[4], kWs[4], bufW, P + o.b[3], bufA);
+  __syncthreads();
+  for (int e = threadIdx.x; e < N4; e += blockDim.x) a4[(size_t)b * N4 + e] = bufA[e];
+  // the head (head_kernel's arithmetic) and the proposal's exponential
+  const float v = head_forward(bufA, P, o, sh_g, sh_h1);
+  if (threadIdx.x < kOut) {
+    out[b * kOut + threadIdx.x] = v;
+    sh_out[threadIdx.x] = v;
+  }
+  __syncthreads();
+  if (rel && threadIdx.x == 0) propose_twist(sh_out, rel + 12 * b);
+}
+
 // ---------------------------------------------------------------- pool + FC (+ loss and its backward)
 
 // One 64-thread workgroup per sample: g = mean(a4), h1 = relu(fw1 g + fb1),
@@ -182,17 +362,8 @@ __global__ __launch_bounds__(64) void head_kernel(const uint16_t* __restrict__ a
   __shared__ float g[64], h1[64], dout[kOut], dz1[64];
   constexpr int HW = 4 * 6;
   const uint16_t* a = a4 + (size_t)b * HW * 64;
-  float s = 0.f;
-  for (int p = 0; p < HW; ++p) s += bf2f(a[p * 64 + t]);
-  g[t] = s * (1.0f / HW);
-  __syncthreads();
-  float z = P[o.fb1 + t];
-  for (int q = 0; q < 64; ++q) z = fmaf(P[o.fw1 + t * 64 + q], g[q], z);
-  h1[t] = fmaxf(z, 0.f);
-  __syncthreads();
+  const float v = head_forward(a, P, o, g, h1);
   if (t < kOut) {
-    float v = P[o.fb2 + t];
-    for (int q = 0; q < kHidden; ++q) v = fmaf(P[o.fw2 + t * kHidden + q], h1[q], v);
     out[b * kOut + t] = v;
     if (targets) {
       const float d = v - targets[b * kOut + t];
@@ -760,60 +931,18 @@ int cnn_forward_levels(dpt_cnn* c, const uint8_t* const* refs, const uint8_t* co
   std::vector<const uint8_t*> h(2 * (size_t)B);
   for (int b = 0; b < B; ++b) h[b] = refs[b], h[B + b] = curs[b];
   CNN_TRY(hipMemcpyAsync(c->d_lv, h.data(), sizeof(void*) * 2 * B, hipMemcpyHostToDevice, c->stream));
-  const int n = B * kH0 * kW0;
-  hipLaunchKernelGGL(input_from_levels, dim3((n + 255) / 256), dim3(256), 0, c->stream, c->d_lv, c->d_lv + B, B,
-                     c->act[0]);
-  CNN_TRY(hipGetLastError());
-  CNN_TRY(forward(c, B, c->stream));
-  hipLaunchKernelGGL(head_kernel, dim3(B), dim3(64), 0, c->stream, c->act[4], c->P, nullptr, B, c->out, nullptr,
-                     nullptr, nullptr);
+  hipLaunchKernelGGL(conv_net_fused, dim3(B), dim3(kFuseThreads), 0, c->stream, c->d_lv, c->d_lv + B, c->Pb, c->P,
+                     c->act[4], c->out, (double*)nullptr);
   CNN_TRY(hipGetLastError());
   CNN_TRY(hipMemcpyAsync(out_host, c->out, sizeof(float) * B * kOut, hipMemcpyDeviceToHost, c->stream));
   CNN_TRY(hipStreamSynchronize(c->stream));
   return DPT_OK;
 }
 
-namespace cnn {
-
-// The network's outputs are twists scaled to unit range: 5 degrees (in
-// radians) for the rotation part, 0.1 m for the translation part.
-__constant__ double kTwistScaleDev[6] = {0.08726646259971647, 0.08726646259971647, 0.08726646259971647,
-                                         0.1, 0.1, 0.1};
-
-// rel[b] = exp(xi_b) as 3x4 FP64, xi_b = the scaled output b (rotation first).
-__global__ void propose_kernel(const float* __restrict__ out, int B, double* __restrict__ rel) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= B) return;
-  double xi[6];
-  for (int j = 0; j < 6; ++j) xi[j] = (double)out[kOut * b + j] * kTwistScaleDev[j];
-  const double th2 = fma(xi[0], xi[0], fma(xi[1], xi[1], xi[2] * xi[2]));
-  double A, Bc, C;
-  if (th2 < 1e-8) {  // |w| < 1e-4: series, truncation below 1e-17
-    A = 1.0 - th2 * (1.0 / 6.0);
-    Bc = 0.5 - th2 * (1.0 / 24.0);
-    C = (1.0 / 6.0) - th2 * (1.0 / 120.0);
-  } else {
-    const double th = sqrt(th2), sn = sin(th), sh = sin(0.5 * th);
-    A = sn / th;
-    Bc = 2.0 * sh * sh / th2;
-    C = (th - sn) / (th2 * th);
-  }
-  double T[12] = {1.0, 0.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 0.0, 1.0, 0.0};
-  compose_exp(T, xi[0], xi[1], xi[2], xi[3], xi[4], xi[5], th2, A, Bc, C);
-  for (int j = 0; j < 12; ++j) rel[12 * b + j] = T[j];
-}
-
-}  // namespace cnn
-
 int cnn_propose(dpt_cnn* c, const uint8_t* const* d_lv, int B, hipStream_t s, double* rel) {
   if (B < 1 || B > c->max_batch) return cfail(DPT_E_ARG, "batch size");
-  const int n = B * kH0 * kW0;
-  hipLaunchKernelGGL(input_from_levels, dim3((n + 255) / 256), dim3(256), 0, s, d_lv, d_lv + B, B, c->act[0]);
-  CNN_TRY(hipGetLastError());
-  CNN_TRY(forward(c, B, s));
-  hipLaunchKernelGGL(head_kernel, dim3(B), dim3(64), 0, s, c->act[4], c->P, nullptr, B, c->out, nullptr, nullptr,
-                     nullptr);
-  hipLaunchKernelGGL(propose_kernel, dim3((B + 63) / 64), dim3(64), 0, s, c->out, B, rel);
+  hipLaunchKernelGGL(conv_net_fused, dim3(B), dim3(kFuseThreads), 0, s, d_lv, d_lv + B, c->Pb, c->P, c->act[4],
+                     c->out, rel);
   CNN_TRY(hipGetLastError());
   return DPT_OK;
 }

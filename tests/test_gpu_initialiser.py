@@ -120,3 +120,40 @@ def _pose_err(A, B):
     E = np.asarray(A) @ np.linalg.inv(np.asarray(B))
     ang = float(np.arccos(np.clip((np.trace(E[:3, :3]) - 1) / 2, -1, 1)))
     return ang, float(np.linalg.norm(E[:3, 3]))
+
+
+def test_fused_inference_matches_layer_by_layer(gpu_lib):
+    """The proposal's one-workgroup-per-sample convolutions (activations kept in
+    LDS) give bitwise the layer-4 activations of the layer-by-layer forward on
+    the same coarsest levels."""
+    import torch
+
+    dpt = gpu_lib
+    from paper_2607_16897_amd import initialiser as ini
+
+    S = 5
+    net = dpt.Cnn(max_batch=S)
+    net.set_params(ini.init_params(7))
+    bt = dpt.BatchTracker([synth.CAM_752] * S, dpt.make_params(levels=4), [400] * S)
+    rng = np.random.default_rng(78)
+    imgs = torch.empty((S, 2, 480, 752), dtype=torch.uint8, device="cuda")
+    dep = torch.empty((S, 2, 480, 752), dtype=torch.float32, device="cuda")
+    for s in range(S):
+        synth.render_gpu(synth.Scene(600 + s), synth.CAM_752,
+                         np.stack([np.eye(4), synth.random_perturbation(rng, 4.0, 0.08)]), imgs[s], dep[s])
+    bt.build_pyramids(dpt.SLOT_REF, [imgs[s, 0] for s in range(S)])
+    for s in range(S):
+        idx = bt.select_points(s, 400, 8)
+        d = dep[s, 0].reshape(-1)[torch.from_numpy(idx.astype(np.int64)).cuda()].double().cpu().numpy()
+        full = np.zeros(480 * 752)
+        full[idx] = d
+        bt.set_reference_points(s, synth.backproject(synth.CAM_752, full.reshape(480, 752), idx, np.eye(4)), np.eye(4))
+    bt.build_pyramids(dpt.SLOT_CUR, [imgs[s, 1] for s in range(S)])
+    net.propose(bt)
+    fused = net.activation(4, S)
+    pairs = np.ascontiguousarray(np.stack([bt.get_level(dpt.SLOT_REF, 3), bt.get_level(dpt.SLOT_CUR, 3)], axis=1))
+    net.forward(pairs)
+    np.testing.assert_array_equal(fused, net.activation(4, S))
+    assert np.count_nonzero(fused) > fused.size // 10  # a live network, not all-zero activations
+    bt.close()
+    net.close()
