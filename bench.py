@@ -632,8 +632,8 @@ def bench_cnn_train(dpt, batch: int = 256, steps: int = 50):
     return {"batch": batch, "steps": steps, "ms_per_step": round(ms, 4), "flop_per_step": flop,
             "roofline": {"bound": "mfma", "unit": "TFLOP/s", "peak": BF16_PEAK_TFLOPS, "achieved": round(tf, 3),
                          "frac": round(tf / BF16_PEAK_TFLOPS, 6),
-                         "note": "a 9.4 MFLOP-per-pair network: every layer is a few microseconds of launch-bound "
-                                 "work; the step includes the loss read back to the host"}}
+                         "note": "a 9.4 MFLOP-per-pair network: ~20 launches of 5-33 us of small-tile MFMA work, "
+                                 "latency- and launch-bound; the step includes the loss read back to the host"}}
 
 
 def bench_learned_init(dpt, n_streams: int, n_frames: int):
