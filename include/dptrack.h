@@ -210,8 +210,11 @@ enum { DPT_INIT_GIVEN = 0, DPT_INIT_CONST_VELOCITY = 1, DPT_INIT_PROPOSED = 2 };
  * first track or test hook after it waits (on the context's stream) for the
  * update.  Results are those of the single-stream form.  Inputs of an update
  * (images, depth maps) are read on the reference stream: the caller orders
- * their producers before it.  The first call allocates the second bank; the
- * call waits for both streams.  DPT_E_STATE while an update is open. */
+ * their producers before it; reading the reference back (dpt_get_pyramid of
+ * DPT_SLOT_REF) waits for the reference stream.  The stream stays the
+ * caller's and must outlive its use: until the context is destroyed or set
+ * back to one stream.  The first call allocates the second bank; the call
+ * waits for both streams.  DPT_E_STATE while an update is open. */
 int dpt_set_reference_stream(dpt_ctx* ctx, void* hip_stream);
 
 /* A HIP stream for the reference updates: default priority, not ordered with
