@@ -256,3 +256,36 @@ def test_library_streams_can_be_made_and_released(gpu_lib):
         s.close()
         assert s.cuda_stream == 0
         s.close()  # a second close is a no-op
+
+
+@pytest.mark.parametrize("slow", ["reference", "tracks"])
+def test_ordering_holds_when_one_stream_lags(gpu_lib, wins, rstream, slow):
+    """A bounded spin kernel ahead of every reference update (the tracks must
+    wait for the update) or ahead of every window track (the next update must
+    wait for the tracks still reading the bank it overwrites): the tracks stay
+    bitwise those of the one-stream context."""
+    import torch
+
+    dpt = gpu_lib
+    prm = dpt.make_params(levels=4)
+    base, _ = _run(dpt, wins, prm, (3, 128), True, None)
+    trk = dpt.Tracker(synth.CAM_752, prm, max_points=N)
+    trk.set_launch_config(3, 128)
+    trk.set_reference_stream(rstream)
+    ref_side = torch.cuda.ExternalStream(rstream.cuda_stream)
+    main_side = torch.cuda.ExternalStream(trk.stream) if trk.stream else torch.cuda.default_stream()
+    spin = 1_500_000  # shader clock cycles, under a millisecond
+    for w in wins:
+        if slow == "reference":
+            with torch.cuda.stream(ref_side):
+                torch.cuda._sleep(spin)
+        trk.build_pyramid(dpt.SLOT_REF, w["img0"])
+        trk.set_reference_from_depth(N, w["depth"], w["T0"])
+        trk.set_pose_history(w["T_prev"], w["T0"])
+        if slow == "tracks":
+            with torch.cuda.stream(main_side):
+                torch.cuda._sleep(spin)
+        trk.track_window_enqueue(w["frames"])
+    piped = trk.synchronize()
+    trk.close()
+    _assert_same(base, piped)
