@@ -289,3 +289,36 @@ def test_ordering_holds_when_one_stream_lags(gpu_lib, wins, rstream, slow):
     piped = trk.synchronize()
     trk.close()
     _assert_same(base, piped)
+
+
+@pytest.mark.parametrize("slow", ["reference", "tracks"])
+def test_batch_ordering_holds_when_one_stream_lags(gpu_lib, bwins, rstream, slow):
+    import torch
+
+    dpt = gpu_lib
+    prm = dpt.make_params(levels=4)
+    base, _ = _run_batch(dpt, bwins, prm, (3, 128), True, None)
+    bt = dpt.BatchTracker([synth.CAM_752] * S, prm, [N] * S)
+    bt.set_launch_config(3, 128)
+    bt.set_reference_stream(rstream)
+    ref_side = torch.cuda.ExternalStream(rstream.cuda_stream)
+    main_side = torch.cuda.ExternalStream(bt.stream) if bt.stream else torch.cuda.default_stream()
+    for w in range(len(bwins[0])):
+        ws = [bwins[s][w] for s in range(S)]
+        if slow == "reference":
+            with torch.cuda.stream(ref_side):
+                torch.cuda._sleep(1_500_000)
+        bt.build_pyramids(dpt.SLOT_REF, [x["img0"] for x in ws])
+        if w % 2 == 0:
+            bt.set_reference_from_depth_all(N, [x["depth"] for x in ws], np.stack([x["T0"] for x in ws]))
+        else:
+            for s, x in enumerate(ws):
+                bt.set_reference_from_depth(s, N, x["depth"], x["T0"])
+        bt.set_pose_history_all(np.stack([x["T_prev"] for x in ws]), np.stack([x["T0"] for x in ws]))
+        if slow == "tracks":
+            with torch.cuda.stream(main_side):
+                torch.cuda._sleep(1_500_000)
+        bt.track_window_enqueue([x["frames"] for x in ws])
+    piped = bt.synchronize()
+    bt.close()
+    _assert_same_batch(base, piped)
