@@ -292,7 +292,7 @@ constexpr int kFuseW = 64 * 9 * 64;                                             
 static_assert(kHs[1] == 30 && kWs[1] == 47 && kC[1] == 16 && kHs[2] == 15 && kWs[2] == 24 && kC[2] == 32 &&
                   kHs[3] * kWs[3] * kC[3] <= kFuseB && kC[3] * 9 * kC[4] <= kFuseW,
               "fused buffers follow the layer shapes");
-constexpr int kFuseThreads = 512;
+constexpr int kFuseThreads = 1024;
 
 // Inference: the input and the four convolutions of sample blockIdx.x in one
 // workgroup, the activations never leaving LDS and each layer's weights
