@@ -71,92 +71,6 @@ __host__ __device__ inline Offsets offsets() {
   return o;
 }
 
-// ---------------------------------------------------------------- input
-
-// uint8 pairs, planar [B][2][60][94] -> BF16 NHWC [B][60][94][2], (I - 128) / 64 (exact in BF16)
-__global__ void input_from_pairs(const uint8_t* __restrict__ pairs, int B, uint16_t* __restrict__ x) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;  // pixel index over B*60*94
-  if (p >= B * kH0 * kW0) return;
-  const int b = p / (kH0 * kW0), r = p % (kH0 * kW0);
-  for (int c = 0; c < 2; ++c)
-    x[2 * p + c] = f2bf(((float)pairs[((size_t)b * 2 + c) * kH0 * kW0 + r] - 128.0f) * (1.0f / 64.0f));
-}
-
-// ---------------------------------------------------------------- forward convolution (MFMA)
-
-// Implicit GEMM: rows m = output pixels (b, i, j), columns n = output channels,
-// k = (ky, kx, ci).  A wave computes 16 rows x CO columns with CO/16 MFMA tiles;
-// lane L supplies A[m0 + L%16][k0 + 4(L/16) .. +3] and B[k0 + 4(L/16) .. +3][n0 + L%16]
-// and receives D[4(L/16) + j][L%16].
-template <int CI, int CO>
-__global__ __launch_bounds__(256) void conv_fwd_mfma(const uint16_t* __restrict__ x, int H, int W, int Ho, int Wo,
-                                                     int B, const uint16_t* __restrict__ w,
-                                                     const float* __restrict__ bias, uint16_t* __restrict__ y) {
-  constexpr int K = 9 * CI, KP = (K + 15) / 16 * 16, NT = CO / 16;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int M = B * Ho * Wo;
-  const int m0 = (blockIdx.x * 4 + wave) * 16;
-  const int m = m0 + (lane & 15);
-  const int kq = lane >> 4;
-  const bool mvalid = m < M;
-  const int b = mvalid ? m / (Ho * Wo) : 0, ij = mvalid ? m % (Ho * Wo) : 0;
-  const int i = ij / Wo, j = ij % Wo;
-  float4_t acc[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = float4_t{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int ks = 0; ks < KP / 16; ++ks) {
-    const int k0 = ks * 16 + 4 * kq;
-    short4_t a;
-    if constexpr (CI % 4 == 0) {
-      const int tap = k0 / CI, c = k0 % CI;
-      const int yy = 2 * i + tap / 3 - 1, xx = 2 * j + tap % 3 - 1;
-      uint2 v = make_uint2(0u, 0u);
-      if (mvalid && yy >= 0 && yy < H && xx >= 0 && xx < W)
-        v = *reinterpret_cast<const uint2*>(x + (((size_t)b * H + yy) * W + xx) * CI + c);
-      a = short4_t{(short)(v.x & 0xffff), (short)(v.x >> 16), (short)(v.y & 0xffff), (short)(v.y >> 16)};
-    } else {
-      short e[4];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int k = k0 + t;
-        uint16_t v = 0;
-        if (k < K && mvalid) {
-          const int tap = k / CI, c = k % CI;
-          const int yy = 2 * i + tap / 3 - 1, xx = 2 * j + tap % 3 - 1;
-          if (yy >= 0 && yy < H && xx >= 0 && xx < W) v = x[(((size_t)b * H + yy) * W + xx) * CI + c];
-        }
-        e[t] = (short)v;
-      }
-      a = short4_t{e[0], e[1], e[2], e[3]};
-    }
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const int n = t * 16 + (lane & 15);
-      short4_t bv;
-      if constexpr (CI % 4 == 0) {
-        const uint2 v = *reinterpret_cast<const uint2*>(w + (size_t)n * K + k0);
-        bv = short4_t{(short)(v.x & 0xffff), (short)(v.x >> 16), (short)(v.y & 0xffff), (short)(v.y >> 16)};
-      } else {
-        short e[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) e[q] = (k0 + q < K) ? (short)w[(size_t)n * K + k0 + q] : (short)0;
-        bv = short4_t{e[0], e[1], e[2], e[3]};
-      }
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv, acc[t], 0, 0, 0);
-    }
-  }
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int n = t * 16 + (lane & 15);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int mo = m0 + 4 * kq + q;
-      if (mo < M) y[(size_t)mo * CO + n] = f2bf(fmaxf(acc[t][q] + bias[n], 0.0f));
-    }
-  }
-}
-
 // ---------------------------------------------------------------- head forward and proposal (device parts)
 
 // The network's outputs are twists scaled to unit range: 5 degrees (in
@@ -214,12 +128,15 @@ __device__ __forceinline__ float head_forward(const uint16_t* __restrict__ a, co
   return v;
 }
 
-// ---------------------------------------------------------------- fused inference convolutions
+// ---------------------------------------------------------------- forward convolutions (fused, MFMA)
 
-// One layer of one sample inside a workgroup: conv_fwd_mfma's implicit GEMM
-// (the same k order, lane layout and epilogue, so bitwise the same outputs)
-// with the sample's activations and the layer's weights in LDS.  The waves
-// take the (16-row tile, 16-channel tile) pairs in turn.
+// One layer of one sample inside a workgroup, as an implicit GEMM: rows m =
+// output pixels (i, j), columns n = output channels, k = (ky, kx, ci), stride
+// 2 and one pixel of zero padding; BF16 operands, FP32 accumulation, then bias
+// and ReLU, BF16 out.  The sample's activations and the layer's weights are in
+// LDS; the waves take the (16-row tile, 16-channel tile) pairs in turn.  Lane L
+// supplies A[m0 + L%16][k0 + 4(L/16) .. +3] and B[k0 + 4(L/16) .. +3][n0 + L%16]
+// and receives D[4(L/16) + j][L%16].
 template <int CI, int CO>
 __device__ __forceinline__ void conv_sample(const uint16_t* __restrict__ x, int H, int W, int Ho, int Wo,
                                             const uint16_t* __restrict__ w, const float* __restrict__ bias,
@@ -294,57 +211,87 @@ static_assert(kHs[1] == 30 && kWs[1] == 47 && kC[1] == 16 && kHs[2] == 15 && kWs
               "fused buffers follow the layer shapes");
 constexpr int kFuseThreads = 1024;
 
-// Inference: the input and the four convolutions of sample blockIdx.x in one
-// workgroup, the activations never leaving LDS and each layer's weights
-// staged in LDS before it runs; layer 4's output goes to a4 ([B][4][6][64], as
-// the layer-by-layer forward writes it) for the head.
-__global__ __launch_bounds__(kFuseThreads) void conv_net_fused(const uint8_t* const* __restrict__ refs,
-                                                               const uint8_t* const* __restrict__ curs,
-                                                               const uint16_t* __restrict__ Pb,
-                                                               const float* __restrict__ P, uint16_t* __restrict__ a4,
-                                                               float* __restrict__ out, double* __restrict__ rel) {
+// Where the fused pass reads and writes: the input pairs as per-sample level
+// pointers (refs, curs) or planar [B][2][60][94] bytes (pairs); act[l]
+// (non-null) receives layer l's activations for the backward pass (act[0] the
+// BF16 input), act[4] always; out (non-null) the head's outputs, rel
+// (non-null) their exponentials.
+struct FusedIO {
+  const uint8_t* const* refs;
+  const uint8_t* const* curs;
+  const uint8_t* pairs;
+  uint16_t* act[5];
+  float* out;
+  double* rel;
+};
+
+// n BF16 values (a multiple of 8) from LDS to global memory, 16 bytes a thread.
+__device__ __forceinline__ void store_act(const uint16_t* __restrict__ src, uint16_t* __restrict__ dst, int n) {
+  for (int e = 8 * (int)threadIdx.x; e < n; e += 8 * (int)blockDim.x)
+    *reinterpret_cast<uint4*>(dst + e) = *reinterpret_cast<const uint4*>(src + e);
+}
+
+// The input and the four convolutions of sample blockIdx.x in one workgroup,
+// the activations never leaving LDS (save the copies io asks for) and each
+// layer's weights staged in LDS before it runs; then, for inference, the
+// head and the proposal.
+__global__ __launch_bounds__(kFuseThreads) void conv_net_fused(FusedIO io, const uint16_t* __restrict__ Pb,
+                                                               const float* __restrict__ P) {
   __shared__ __align__(16) uint16_t bufA[kFuseA];
   __shared__ float sh_g[64], sh_h1[64], sh_out[kOut];
   __shared__ __align__(16) uint16_t bufB[kFuseB];
   __shared__ __align__(16) uint16_t bufW[kFuseW];
+  constexpr int N0 = kH0 * kW0 * 2, N1 = kHs[1] * kWs[1] * kC[1], N2 = kHs[2] * kWs[2] * kC[2],
+                N3 = kHs[3] * kWs[3] * kC[3], N4 = kHs[4] * kWs[4] * kC[4];
+  static_assert(N0 % 8 == 0 && N1 % 8 == 0 && N2 % 8 == 0 && N3 % 8 == 0 && N4 % 8 == 0, "16-byte copies");
   const int b = blockIdx.x;
   const Offsets o = offsets();
   stage_weights(Pb + o.w[0], kC[1] * 9 * kC[0] * 2, bufW);
-  const uint8_t* ref = refs[b];
-  const uint8_t* cur = curs[b];
-  for (int r = threadIdx.x; r < kH0 * kW0; r += blockDim.x) {  // (I - 128) / 64, as input_from_pairs
+  const uint8_t* ref = io.pairs ? io.pairs + (size_t)(2 * b) * kH0 * kW0 : io.refs[b];
+  const uint8_t* cur = io.pairs ? io.pairs + (size_t)(2 * b + 1) * kH0 * kW0 : io.curs[b];
+  for (int r = threadIdx.x; r < kH0 * kW0; r += blockDim.x) {  // (I - 128) / 64, exact in BF16
     bufA[2 * r] = f2bf(((float)ref[r] - 128.0f) * (1.0f / 64.0f));
     bufA[2 * r + 1] = f2bf(((float)cur[r] - 128.0f) * (1.0f / 64.0f));
   }
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
+  if (io.act[0]) store_act(bufA, io.act[0] + (size_t)b * N0, N0);
   conv_sample<2, 16>(bufA, kHs[0], kWs[0], kHs[1], kWs[1], bufW, P + o.b[0], bufB);
   __syncthreads();
   stage_weights(Pb + o.w[1], kC[2] * 9 * kC[1] * 2, bufW);
+  if (io.act[1]) store_act(bufB, io.act[1] + (size_t)b * N1, N1);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   conv_sample<16, 32>(bufB, kHs[1], kWs[1], kHs[2], kWs[2], bufW, P + o.b[1], bufA);
   __syncthreads();
   stage_weights(Pb + o.w[2], kC[3] * 9 * kC[2] * 2, bufW);
+  if (io.act[2]) store_act(bufA, io.act[2] + (size_t)b * N2, N2);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   conv_sample<32, 64>(bufA, kHs[2], kWs[2], kHs[3], kWs[3], bufW, P + o.b[2], bufB);
   __syncthreads();
   stage_weights(Pb + o.w[3], kC[4] * 9 * kC[3] * 2, bufW);
+  if (io.act[3]) store_act(bufB, io.act[3] + (size_t)b * N3, N3);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  constexpr int N4 = kHs[4] * kWs[4] * kC[4];
   conv_sample<64, 64>(bufB, kHs[3], kWs[3], kHs[4], kWs[4], bufW, P + o.b[3], bufA);
   __syncthreads();
-  for (int e = threadIdx.x; e < N4; e += blockDim.x) a4[(size_t)b * N4 + e] = bufA[e];
+  store_act(bufA, io.act[4] + (size_t)b * N4, N4);
+  if (!io.out) return;
   // the head (head_kernel's arithmetic) and the proposal's exponential
   const float v = head_forward(bufA, P, o, sh_g, sh_h1);
   if (threadIdx.x < kOut) {
-    out[b * kOut + threadIdx.x] = v;
+    io.out[b * kOut + threadIdx.x] = v;
     sh_out[threadIdx.x] = v;
   }
   __syncthreads();
-  if (rel && threadIdx.x == 0) propose_twist(sh_out, rel + 12 * b);
+  if (io.rel && threadIdx.x == 0) propose_twist(sh_out, io.rel + 12 * b);
+}
+
+// The fused pass over B samples on stream s.
+hipError_t launch_fused(const FusedIO& io, int B, const uint16_t* Pb, const float* P, hipStream_t s) {
+  hipLaunchKernelGGL(conv_net_fused, dim3(B), dim3(kFuseThreads), 0, s, io, Pb, P);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- pool + FC (+ loss and its backward)
@@ -692,20 +639,6 @@ struct BatchSum {
 
 constexpr int npad(int l) { return (9 * kC[l] + 1 + 15) / 16 * 16; }
 
-hipError_t forward(dpt_cnn* c, int B, hipStream_t s) {
-  const int M1 = B * kHs[1] * kWs[1], M2 = B * kHs[2] * kWs[2], M3 = B * kHs[3] * kWs[3], M4 = B * kHs[4] * kWs[4];
-  auto grid = [](int M) { return dim3((M + 63) / 64); };
-  hipLaunchKernelGGL((conv_fwd_mfma<2, 16>), grid(M1), dim3(256), 0, s, c->act[0], kHs[0], kWs[0], kHs[1],
-                     kWs[1], B, c->Pb + c->o.w[0], c->P + c->o.b[0], c->act[1]);
-  hipLaunchKernelGGL((conv_fwd_mfma<16, 32>), grid(M2), dim3(256), 0, s, c->act[1], kHs[1], kWs[1], kHs[2],
-                     kWs[2], B, c->Pb + c->o.w[1], c->P + c->o.b[1], c->act[2]);
-  hipLaunchKernelGGL((conv_fwd_mfma<32, 64>), grid(M3), dim3(256), 0, s, c->act[2], kHs[2], kWs[2], kHs[3],
-                     kWs[3], B, c->Pb + c->o.w[2], c->P + c->o.b[2], c->act[3]);
-  hipLaunchKernelGGL((conv_fwd_mfma<64, 64>), grid(M4), dim3(256), 0, s, c->act[3], kHs[3], kWs[3], kHs[4],
-                     kWs[4], B, c->Pb + c->o.w[3], c->P + c->o.b[3], c->act[4]);
-  return hipGetLastError();
-}
-
 template <int L>
 hipError_t bwd_layer(dpt_cnn* c, int B) {
   constexpr int CO = kC[L + 1];
@@ -733,15 +666,20 @@ hipError_t backward(dpt_cnn* c, int B) {
   return bwd_layer<0>(c, B);
 }
 
-int load_input(dpt_cnn* c, const uint8_t* pairs, int B, int on_device) {
+// The forward pass of B planar pairs (host or device) through the fused
+// kernel, every layer's activations kept for the backward pass; with head,
+// the head's outputs to c->out as well.
+int forward_pairs(dpt_cnn* c, const uint8_t* pairs, int B, int on_device, bool head) {
   const uint8_t* src = pairs;
   if (!on_device) {
     CNN_TRY(hipMemcpyAsync(c->pairs, pairs, (size_t)B * 2 * kH0 * kW0, hipMemcpyHostToDevice, c->stream));
     src = c->pairs;
   }
-  const int n = B * kH0 * kW0;
-  hipLaunchKernelGGL(input_from_pairs, dim3((n + 255) / 256), dim3(256), 0, c->stream, src, B, c->act[0]);
-  CNN_TRY(hipGetLastError());
+  FusedIO io{};
+  io.pairs = src;
+  for (int l = 0; l < 5; ++l) io.act[l] = c->act[l];
+  io.out = head ? c->out : nullptr;
+  CNN_TRY(launch_fused(io, B, c->Pb, c->P, c->stream));
   return DPT_OK;
 }
 
@@ -853,12 +791,8 @@ int dpt_cnn_get_grads(dpt_cnn* c, float* grads) {
 int dpt_cnn_forward(dpt_cnn* c, const uint8_t* pairs, int32_t B, int32_t on_device, float* out_host) {
   if (!c || !pairs || !out_host) return cfail(DPT_E_ARG, "NULL argument");
   if (B < 1 || B > c->max_batch) return cfail(DPT_E_ARG, "batch size");
-  int e = load_input(c, pairs, B, on_device);
+  int e = forward_pairs(c, pairs, B, on_device, true);
   if (e != DPT_OK) return e;
-  CNN_TRY(forward(c, B, c->stream));
-  hipLaunchKernelGGL(head_kernel, dim3(B), dim3(64), 0, c->stream, c->act[4], c->P, nullptr, B, c->out, nullptr,
-                     nullptr, nullptr);
-  CNN_TRY(hipGetLastError());
   CNN_TRY(hipMemcpyAsync(out_host, c->out, sizeof(float) * B * kOut, hipMemcpyDeviceToHost, c->stream));
   CNN_TRY(hipStreamSynchronize(c->stream));
   return DPT_OK;
@@ -872,7 +806,7 @@ int dpt_cnn_train_step(dpt_cnn* c, const uint8_t* pairs, const float* targets, i
                        int32_t on_device, float* loss_out) {
   if (!c || !pairs || !targets || !loss_out) return cfail(DPT_E_ARG, "NULL argument");
   if (B < 1 || B > c->max_batch) return cfail(DPT_E_ARG, "batch size");
-  int e = load_input(c, pairs, B, on_device);
+  int e = forward_pairs(c, pairs, B, on_device, false);
   if (e != DPT_OK) return e;
   const float* tg = targets;
   if (!on_device) {
@@ -880,7 +814,6 @@ int dpt_cnn_train_step(dpt_cnn* c, const uint8_t* pairs, const float* targets, i
     tg = c->tgt;
   }
   const Offsets& o = c->o;
-  CNN_TRY(forward(c, B, c->stream));
   hipLaunchKernelGGL(head_kernel, dim3(B), dim3(64), 0, c->stream, c->act[4], c->P, tg, B, c->out, c->sqerr, c->fcg,
                      c->dz[4]);
   const int nfc = o.total - o.fw1;
@@ -931,9 +864,9 @@ int cnn_forward_levels(dpt_cnn* c, const uint8_t* const* refs, const uint8_t* co
   std::vector<const uint8_t*> h(2 * (size_t)B);
   for (int b = 0; b < B; ++b) h[b] = refs[b], h[B + b] = curs[b];
   CNN_TRY(hipMemcpyAsync(c->d_lv, h.data(), sizeof(void*) * 2 * B, hipMemcpyHostToDevice, c->stream));
-  hipLaunchKernelGGL(conv_net_fused, dim3(B), dim3(kFuseThreads), 0, c->stream, c->d_lv, c->d_lv + B, c->Pb, c->P,
-                     c->act[4], c->out, (double*)nullptr);
-  CNN_TRY(hipGetLastError());
+  FusedIO io{};
+  io.refs = c->d_lv, io.curs = c->d_lv + B, io.act[4] = c->act[4], io.out = c->out;
+  CNN_TRY(launch_fused(io, B, c->Pb, c->P, c->stream));
   CNN_TRY(hipMemcpyAsync(out_host, c->out, sizeof(float) * B * kOut, hipMemcpyDeviceToHost, c->stream));
   CNN_TRY(hipStreamSynchronize(c->stream));
   return DPT_OK;
@@ -941,9 +874,9 @@ int cnn_forward_levels(dpt_cnn* c, const uint8_t* const* refs, const uint8_t* co
 
 int cnn_propose(dpt_cnn* c, const uint8_t* const* d_lv, int B, hipStream_t s, double* rel) {
   if (B < 1 || B > c->max_batch) return cfail(DPT_E_ARG, "batch size");
-  hipLaunchKernelGGL(conv_net_fused, dim3(B), dim3(kFuseThreads), 0, s, d_lv, d_lv + B, c->Pb, c->P, c->act[4],
-                     c->out, rel);
-  CNN_TRY(hipGetLastError());
+  FusedIO io{};
+  io.refs = d_lv, io.curs = d_lv + B, io.act[4] = c->act[4], io.out = c->out, io.rel = rel;
+  CNN_TRY(launch_fused(io, B, c->Pb, c->P, s));
   return DPT_OK;
 }
 

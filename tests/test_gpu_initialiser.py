@@ -122,10 +122,11 @@ def _pose_err(A, B):
     return ang, float(np.linalg.norm(E[:3, 3]))
 
 
-def test_fused_inference_matches_layer_by_layer(gpu_lib):
-    """The proposal's one-workgroup-per-sample convolutions (activations kept in
-    LDS) give bitwise the layer-4 activations of the layer-by-layer forward on
-    the same coarsest levels."""
+def test_level_and_pair_inputs_agree(gpu_lib):
+    """The proposal, which reads the coarsest levels through per-stream
+    pointers and keeps its activations on chip, gives bitwise the layer-4
+    activations and head outputs of the forward pass over the same levels
+    handed over as planar pairs."""
     import torch
 
     dpt = gpu_lib
@@ -150,9 +151,9 @@ def test_fused_inference_matches_layer_by_layer(gpu_lib):
         bt.set_reference_points(s, synth.backproject(synth.CAM_752, full.reshape(480, 752), idx, np.eye(4)), np.eye(4))
     bt.build_pyramids(dpt.SLOT_CUR, [imgs[s, 1] for s in range(S)])
     net.propose(bt)
-    fused = net.activation(4, S)
+    fused, out = net.activation(4, S), net.activation(5, S)
     pairs = np.ascontiguousarray(np.stack([bt.get_level(dpt.SLOT_REF, 3), bt.get_level(dpt.SLOT_CUR, 3)], axis=1))
-    net.forward(pairs)
+    np.testing.assert_array_equal(out, net.forward(pairs))
     np.testing.assert_array_equal(fused, net.activation(4, S))
     assert np.count_nonzero(fused) > fused.size // 10  # a live network, not all-zero activations
     bt.close()
