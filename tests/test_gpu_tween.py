@@ -91,3 +91,29 @@ def test_tween_state_errors_and_max_frames(gpu_lib):
     assert r3["decision"] == dpt.TWEEN_DIRECT and r3["direct_since_ref"] == 1
     rot, tr = oracle.pose_error(r3["track"]["T_cw"], frames[3][2])
     assert rot < 2e-3 and tr < 5e-3
+
+
+def test_tween_schedule_with_reference_stream(gpu_lib):
+    """The schedule's re-anchoring runs its reference updates on a second
+    stream when the context has one: every decision and pose bitwise as on one
+    stream."""
+    dpt = gpu_lib
+    cam = synth.CAM_752
+    frames = [(im, d.astype(np.float32), T) for _, im, d, T, _ in
+              synth.tween_frames(n_frames=60, jump=(40, 160), p_jump=0.05)]
+    pol = dict(max_cost=20.0, max_baseline=0.035, max_direct=12, n_points=2000, margin=8)
+    runs = []
+    rs = dpt.Stream()
+    for second in (False, True):
+        trk = dpt.Tracker(cam, dpt.make_params(levels=4), max_points=2000)
+        if second:
+            trk.set_reference_stream(rs)
+        trk.tween_set_policy(pol["max_cost"], pol["max_direct"], pol["n_points"], max_baseline=pol["max_baseline"],
+                             margin=pol["margin"])
+        runs.append(_run_gpu(dpt, trk, frames, pol))
+        trk.close()
+    rs.close()
+    a, b = runs
+    assert [r["decision"] for r in a] == [r["decision"] for r in b]
+    for ra, rb in zip(a, b):
+        np.testing.assert_array_equal(np.asarray(ra["pose"]), np.asarray(rb["pose"]))
