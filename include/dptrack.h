@@ -209,7 +209,9 @@ enum { DPT_INIT_GIVEN = 0, DPT_INIT_CONST_VELOCITY = 1, DPT_INIT_PROPOSED = 2 };
  * the tracks do not read once the tracks that read it last have run, and the
  * first track or test hook after it waits (on the context's stream) for the
  * update.  Results are those of the single-stream form.  Inputs of an update
- * (images, depth maps) are read on the reference stream: the caller orders
+ * (images, depth maps) are read on the reference stream, and so are the
+ * device frames of the first window track after it (dpt_track_window_enqueue
+ * builds that window's pyramids there, behind the update): the caller orders
  * their producers before it; reading the reference back (dpt_get_pyramid of
  * DPT_SLOT_REF) waits for the reference stream.  The stream stays the
  * caller's and must outlive its use: until the context is destroyed or set

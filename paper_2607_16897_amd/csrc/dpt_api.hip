@@ -335,12 +335,16 @@ struct dpt_ctx {
   bool have_prop = false;
   std::vector<std::pair<int, dpt_result*>> pending;  // tracks in flight: (ring slot, caller's result)
   int slot_next = 0;
-  // window tracking: box pyramids of up to win_cap consecutive frames
+  // window tracking: box pyramids of up to win_cap consecutive frames, one
+  // buffer per reference bank (the second one with a reference stream): a
+  // window's pyramids go to the buffer of the bank its track reads
   uint8_t* win = nullptr;
+  uint8_t* win_b1 = nullptr;
   int64_t win_stride = 0;  // bytes per frame pyramid, a multiple of 256
   int32_t win_cap = 0;
   uint8_t* win_staging = nullptr;  // level 0 of host frames, win_cap frames of W x H
-  WinJob* d_winjob = nullptr;      // this context's window pyramid job (device)
+  WinJob* d_winjob = nullptr;      // the window pyramid jobs (device) into win, and into win_b1
+  WinJob* d_winjob_b1 = nullptr;
   // reference stream (dpt_set_reference_stream): reference updates run there,
   // into the bank the tracks in flight do not read; the fields above hold the
   // bank last written (committed once have_ref is set)
@@ -379,7 +383,7 @@ struct dpt_ctx {
     for (void* p : {(void*)pyr[0], (void*)pyr[1], (void*)staging, (void*)x0, (void*)valid, (void*)I0, (void*)gx,
                     (void*)gy, (void*)I0h, (void*)gh, (void*)pts, (void*)sel_idx, (void*)sel_count, (void*)sel_scratch, (void*)d_out,
                     (void*)d_tot, (void*)d_fixed, (void*)d_hpart, (void*)pyrf[0], (void*)pyrf[1], (void*)win,
-                    (void*)win_staging, (void*)d_winjob})
+                    (void*)win_staging, (void*)d_winjob, (void*)win_b1, (void*)d_winjob_b1})
       if (p) (void)hipFree(p);
     if (h_out) (void)hipHostFree(h_out);
     if (h_tot) (void)hipHostFree(h_tot);
@@ -844,6 +848,7 @@ int dpt_set_reference_from_depth(dpt_ctx* c, int32_t n, int32_t margin, const fl
 namespace {
 
 int synchronize(dpt_ctx* c);
+int alloc_window_bank(dpt_ctx* c, int n_frames, uint8_t** win, WinJob** job);
 
 // Allocate the second reference bank of a context (the buffers a reference
 // update writes: reference pyramid, cache, points, fixed-H state).
@@ -864,6 +869,7 @@ int alloc_alt_bank(dpt_ctx* c) {
   if (c->I0h && ((e = dev_alloc((void**)&b.I0h, L * cap * K * sizeof(__half))) ||
                  (e = dev_alloc((void**)&b.gh, L * cap * K * sizeof(__half2)))))
     return e;
+  if (c->win_cap > 0 && (e = alloc_window_bank(c, c->win_cap, &c->win_b1, &c->d_winjob_b1)) != DPT_OK) return e;
   for (hipEvent_t* ev : {&c->ev_read[0], &c->ev_read[1], &c->ev_ready})
     if (!*ev) HIP_TRY(hipEventCreateWithFlags(ev, hipEventDisableTiming));
   return DPT_OK;
@@ -1058,11 +1064,12 @@ int ensure_engine(dpt_ctx* c) {
   }
   const RefCache r0 = refcache_of(c, 0), r1 = refcache_of(c, 1);
   if (c->eng.dirty || c->eng.h_streams[0].a.ref.n != r0.n || c->eng.h_streams[0].ref_alt.n != r1.n ||
-      c->eng.h_streams[0].ref_alt.x0 != r1.x0) {
+      c->eng.h_streams[0].ref_alt.x0 != r1.x0 || c->eng.h_streams[0].win != c->win ||
+      c->eng.h_streams[0].win_alt != c->win_b1) {
     TrackArgs a;
     fill_track_args(c, a);
     a.ref = r0;
-    c->eng.set_stream(0, a, r1, c->d_hist, c->win, c->win_stride);
+    c->eng.set_stream(0, a, r1, c->d_hist, c->win, c->win_b1, c->win_stride);
   }
   if (c->eng.dirty) HIP_TRY(c->eng.upload());
   return DPT_OK;
@@ -1239,29 +1246,44 @@ int check_track_state(dpt_ctx* c) {
 
 // Window pyramids for n_frames frames (grown on demand; nothing may be in
 // flight).  *grown tells the caller that the engines must see the new buffer.
+// One bank's window pyramid buffer of n_frames frames and its job.
+int alloc_window_bank(dpt_ctx* c, int n_frames, uint8_t** win, WinJob** job) {
+  const int64_t stride = (c->pyr_bytes + 255) / 256 * 256;
+  int e;
+  if ((e = dev_alloc((void**)win, (size_t)stride * n_frames)) != DPT_OK) return e;
+  if (!*job && (e = dev_alloc((void**)job, sizeof(WinJob))) != DPT_OK) return e;
+  WinJob j;
+  std::memset(&j, 0, sizeof j);
+  j.dst = *win;
+  j.dst_stride = stride;
+  j.g = c->pg;
+  HIP_TRY(hipMemcpy(*job, &j, sizeof j, hipMemcpyHostToDevice));
+  c->win_stride = stride;
+  return DPT_OK;
+}
+
+// Window pyramids for n_frames frames, for each bank in use (grown on demand;
+// nothing may be in flight).  *grown tells the caller that the engines must
+// see the new buffers.
 int ensure_window(dpt_ctx* c, int n_frames, bool* grown) {
   *grown = false;
   if (n_frames <= c->win_cap) return DPT_OK;
-  for (void** p : {(void**)&c->win, (void**)&c->win_staging}) {
+  for (void** p : {(void**)&c->win, (void**)&c->win_b1, (void**)&c->win_staging}) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
   }
   c->win_cap = 0;
-  const int64_t stride = (c->pyr_bytes + 255) / 256 * 256;
   int e;
-  if ((e = dev_alloc((void**)&c->win, (size_t)stride * n_frames)) != DPT_OK) return e;
-  if (!c->d_winjob && (e = dev_alloc((void**)&c->d_winjob, sizeof(WinJob))) != DPT_OK) return e;
-  WinJob j;
-  std::memset(&j, 0, sizeof j);
-  j.dst = c->win;
-  j.dst_stride = stride;
-  j.g = c->pg;
-  HIP_TRY(hipMemcpy(c->d_winjob, &j, sizeof j, hipMemcpyHostToDevice));
-  c->win_stride = stride;
+  if ((e = alloc_window_bank(c, n_frames, &c->win, &c->d_winjob)) != DPT_OK) return e;
+  if (c->phys[1].x0 && (e = alloc_window_bank(c, n_frames, &c->win_b1, &c->d_winjob_b1)) != DPT_OK) return e;
   c->win_cap = n_frames;
   *grown = true;
   return DPT_OK;
 }
+
+// The window pyramid buffer and job of the bank the fields hold.
+uint8_t* bank_win(const dpt_ctx* c) { return c->bank ? c->win_b1 : c->win; }
+WinJob* bank_winjob(const dpt_ctx* c) { return c->bank ? c->d_winjob_b1 : c->d_winjob; }
 
 // Level 0 of n_frames host frames into the context's device staging.
 int stage_window(dpt_ctx* c, const uint8_t* frames, int64_t pitch, int64_t frame_stride, int n_frames,
@@ -1370,18 +1392,25 @@ int dpt_track_window_enqueue(dpt_ctx* c, const uint8_t* frames, int64_t pitch, i
   if (init_mode == DPT_INIT_GIVEN && (!T_cw_init || !finite16(T_cw_init)))
     return fail(DPT_E_ARG, "T_cw_init missing or not finite");
   if (!use_coop(c)) return fail(DPT_E_ARG, "window tracking needs the cooperative track (launch mode AUTO or COOP)");
-  if ((e = consume_commit(c)) != DPT_OK) return e;
   if ((int)c->pending.size() + n_frames > kRing)
     return fail(DPT_E_STATE, "%d tracks in flight and %d more exceed %d: synchronise first", (int)c->pending.size(),
                 n_frames, kRing);
   if (n_frames > c->win_cap) {  // the buffers in use by tracks in flight are replaced
     if (!c->pending.empty() && (e = synchronize(c)) != DPT_OK) return e;
     HIP_TRY(hipStreamSynchronize(c->stream));
+    if (c->rstream) HIP_TRY(hipStreamSynchronize(c->rstream));
     bool grown = false;
     if ((e = ensure_window(c, n_frames, &grown)) != DPT_OK) return e;
     if (grown && c->eng_ready) c->eng.dirty = true;
   }
   if ((e = ensure_engine(c)) != DPT_OK) return e;
+  // The first window after a reference update committed on the reference
+  // stream builds its pyramids there too, behind the update (whose wait covers
+  // the tracks that last read this bank's window buffer), beside the previous
+  // window's track; the context's stream then waits for both.
+  const bool on_ref = c->rstream && c->commit_pending && frames_on_device;
+  const hipStream_t ps_stream = on_ref ? c->rstream : c->stream;
+  if (!on_ref && (e = consume_commit(c)) != DPT_OK) return e;
   const uint8_t* src = frames;
   int64_t sp = pitch, sst = frame_stride;
   if (!frames_on_device) {
@@ -1400,11 +1429,16 @@ int dpt_track_window_enqueue(dpt_ctx* c, const uint8_t* frames, int64_t pitch, i
   srcs.stride[0] = sst;
   srcs.write_l0[0] = l0_direct ? 0 : 1;
   int ps = -1;
-  if (c->prof) HIP_TRY(c->prof_pyr.begin(c->stream, &ps));
-  const bool block = sst % 8 == 0 && c->win_stride % 8 == 0 && pyramid_block_ok(c->pg, src, sp, c->win);
-  HIP_TRY(launch_pyramid_window(c->d_winjob, srcs, 1, n_frames, c->cam.width, c->cam.height, c->prm.levels, block,
-                                c->stream));
-  if (c->prof) HIP_TRY(c->prof_pyr.end(c->stream, ps));
+  const bool prof_pyr = c->prof && !on_ref;  // the profile ring times the context's stream
+  if (prof_pyr) HIP_TRY(c->prof_pyr.begin(c->stream, &ps));
+  const bool block = sst % 8 == 0 && c->win_stride % 8 == 0 && pyramid_block_ok(c->pg, src, sp, bank_win(c));
+  HIP_TRY(launch_pyramid_window(bank_winjob(c), srcs, 1, n_frames, c->cam.width, c->cam.height, c->prm.levels,
+                                block, ps_stream));
+  if (prof_pyr) HIP_TRY(c->prof_pyr.end(c->stream, ps));
+  if (on_ref) {  // the update's event now also covers the window's pyramids
+    HIP_TRY(hipEventRecord(c->ev_ready, c->rstream));
+    if ((e = consume_commit(c)) != DPT_OK) return e;
+  }
   const int slot = c->slot_next;
   for (int f = 0; f < n_frames; ++f) {
     const int mode = f == 0 && init_mode == DPT_INIT_GIVEN ? kStartGiven : kStartConstVelocity;
@@ -1618,7 +1652,8 @@ struct dpt_batch {
   StagedTable<PrecomputeArgs> pre_args;
   StagedTable<double> hist_vals;  // 24 per stream
   double** d_hist_ptrs = nullptr;  // device array of the streams' history pointers
-  WinJob* d_winjobs = nullptr;     // the streams' window pyramid jobs (device)
+  WinJob* d_winjobs[2] = {nullptr, nullptr};  // the streams' window pyramid jobs per bank (device)
+  bool winjobs_ok[2] = {false, false};         // each table matches the streams' current buffers
   double* d_prop = nullptr;        // learned start proposals, n x 3x4 FP64 (device)
   const uint8_t** d_cnn_lv = nullptr;  // the streams' coarsest reference then current levels, per bank
   bool cnn_lv_ok[2] = {false, false};
@@ -1644,7 +1679,8 @@ struct dpt_batch {
     pre_args.release();
     hist_vals.release();
     if (d_hist_ptrs) (void)hipFree(d_hist_ptrs);
-    if (d_winjobs) (void)hipFree(d_winjobs);
+    for (WinJob* t : d_winjobs)
+      if (t) (void)hipFree(t);
     if (d_prop) (void)hipFree(d_prop);
     if (d_cnn_lv) (void)hipFree(d_cnn_lv);
     for (hipEvent_t e : ev_jobs)
@@ -1702,6 +1738,26 @@ int batch_open_update(dpt_batch* b) {
 
 hipStream_t batch_ref_stream(const dpt_batch* b) { return b->rstream ? b->rstream : b->stream; }
 
+// The streams' window pyramid jobs into the buffers of `bank`, rebuilt after
+// the buffers changed (nothing in flight reads the table then).
+int batch_winjobs(dpt_batch* b, int bank, WinJob** out) {
+  if (!b->winjobs_ok[bank]) {
+    if (!b->d_winjobs[bank] && hipMalloc(&b->d_winjobs[bank], sizeof(WinJob) * b->n) != hipSuccess) {
+      (void)hipGetLastError();
+      b->d_winjobs[bank] = nullptr;
+      return fail(DPT_E_OOM, "window job table allocation failed");
+    }
+    for (int s = 0; s < b->n; ++s) {
+      const WinJob* j = bank ? b->ctx[s]->d_winjob_b1 : b->ctx[s]->d_winjob;
+      if (!j) return fail(DPT_E_STATE, "stream %d has no window buffer for bank %d", s, bank);
+      HIP_TRY(hipMemcpy(b->d_winjobs[bank] + s, j, sizeof(WinJob), hipMemcpyDeviceToDevice));
+    }
+    b->winjobs_ok[bank] = true;
+  }
+  *out = b->d_winjobs[bank];
+  return DPT_OK;
+}
+
 int batch_chunks(const dpt_batch* b, int s) {
   const dpt_ctx* c = b->ctx[s];
   const int n = std::max(c->n_points, std::max(c->bank_n[0], c->bank_n[1]));  // the chunks cover both banks
@@ -1752,6 +1808,7 @@ int build_groups(dpt_batch* b) {
       fill_track_args(b->ctx[cur[k]], a);
       a.ref = refcache_of(b->ctx[cur[k]], 0);
       g->set_stream((int)k, a, refcache_of(b->ctx[cur[k]], 1), b->ctx[cur[k]]->d_hist, b->ctx[cur[k]]->win,
+                    b->ctx[cur[k]]->win_b1,
                     b->ctx[cur[k]]->win_stride);
     }
     b->groups.push_back(g);
@@ -1854,7 +1911,9 @@ void refresh_groups(dpt_batch* b) {
       const dpt_ctx* c = b->ctx[ss[k]];
       const RefCache r0 = refcache_of(c, 0), r1 = refcache_of(c, 1);
       const CoopStream& hs = g->h_streams[k];
-      if (hs.a.ref.n == r0.n && hs.ref_alt.n == r1.n && hs.ref_alt.x0 == r1.x0) continue;
+      if (hs.a.ref.n == r0.n && hs.ref_alt.n == r1.n && hs.ref_alt.x0 == r1.x0 && hs.win == c->win &&
+          hs.win_alt == c->win_b1)
+        continue;
       if (batch_chunks(b, ss[k]) > hs.n_chunks) {
         b->groups_dirty = true;
         break;
@@ -1862,7 +1921,7 @@ void refresh_groups(dpt_batch* b) {
       TrackArgs a;
       fill_track_args(c, a);
       a.ref = r0;
-      g->set_stream((int)k, a, r1, c->d_hist, c->win, c->win_stride);
+      g->set_stream((int)k, a, r1, c->d_hist, c->win, c->win_b1, c->win_stride);
     }
   }
 }
@@ -2056,6 +2115,7 @@ int dpt_batch_set_reference_stream(dpt_batch* b, void* hip_stream) {
       if ((e = alloc_alt_bank(c)) != DPT_OK) return e;
       if (fresh) c->alt = c->phys[1], c->bank_n[1] = 0;
     }
+    b->winjobs_ok[1] = false;  // the streams' bank-1 window buffers may be new
     if (b->d_static[DPT_SLOT_REF] && !b->d_static[2]) {  // the second bank's reference pyramid table
       std::vector<PyrJob> t(b->n);
       for (int s = 0; s < b->n; ++s) {
@@ -2360,7 +2420,7 @@ int dpt_batch_track_window_enqueue(dpt_batch* b, const uint8_t* const* frames, c
       if (!finite16(T_cw_init + 16 * s)) return fail(DPT_E_ARG, "T_cw_init %d not finite", s);
   }
   if (!batch_use_coop(b)) return fail(DPT_E_ARG, "window tracking needs the cooperative track (launch mode AUTO or COOP)");
-  if ((e = batch_close_update(b)) != DPT_OK || (e = batch_consume(b)) != DPT_OK) return e;
+  if ((e = batch_close_update(b)) != DPT_OK) return e;
   if ((int)b->pending.size() + n_frames > kRing)
     return fail(DPT_E_STATE, "%d batched tracks in flight and %d more exceed %d: synchronise first",
                 (int)b->pending.size(), n_frames, kRing);
@@ -2368,19 +2428,22 @@ int dpt_batch_track_window_enqueue(dpt_batch* b, const uint8_t* const* frames, c
   for (int s = 0; s < b->n; ++s) need |= n_frames > b->ctx[s]->win_cap;
   if (need) {  // new buffers: finish what is in flight, then regroup with them
     if ((e = batch_synchronize(b)) != DPT_OK) return e;
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    if (b->rstream) HIP_TRY(hipStreamSynchronize(b->rstream));
     for (int s = 0; s < b->n; ++s) {
       bool grown = false;
       if ((e = ensure_window(b->ctx[s], n_frames, &grown)) != DPT_OK) return e;
     }
-    if (!b->d_winjobs && hipMalloc(&b->d_winjobs, sizeof(WinJob) * b->n) != hipSuccess) {
-      (void)hipGetLastError();
-      b->d_winjobs = nullptr;
-      return fail(DPT_E_OOM, "window job table allocation failed");
-    }
-    for (int s = 0; s < b->n; ++s)
-      HIP_TRY(hipMemcpy(b->d_winjobs + s, b->ctx[s]->d_winjob, sizeof(WinJob), hipMemcpyDeviceToDevice));
+    b->winjobs_ok[0] = b->winjobs_ok[1] = false;
     b->clear_groups();
   }
+  // as for a context: the first window after a committed update builds its
+  // pyramids on the reference stream, behind the update
+  const bool on_ref = b->rstream && b->commit_pending && frames_on_device;
+  const hipStream_t pst = on_ref ? b->rstream : b->stream;
+  if (!on_ref && (e = batch_consume(b)) != DPT_OK) return e;
+  WinJob* winjobs = nullptr;
+  if ((e = batch_winjobs(b, b->bank, &winjobs)) != DPT_OK) return e;
   refresh_groups(b);
   if (b->groups_dirty) {  // regrouping frees the rings: finish and fill what is in flight first
     if (!b->pending.empty() && (e = batch_synchronize(b)) != DPT_OK) return e;
@@ -2402,7 +2465,8 @@ int dpt_batch_track_window_enqueue(dpt_batch* b, const uint8_t* const* frames, c
   }
   // pyramids of every stream's frames, up to kPyrArgJobs streams per launch
   int ps = -1;
-  if (b->prof) HIP_TRY(b->prof_pyr.begin(b->stream, &ps));
+  const bool prof_pyr = b->prof && !on_ref;  // the profile ring times the batch's stream
+  if (prof_pyr) HIP_TRY(b->prof_pyr.begin(b->stream, &ps));
   for (int s0 = 0; s0 < b->n; s0 += kPyrArgJobs) {
     const int m = std::min(kPyrArgJobs, b->n - s0);
     PyrWinSrc srcs;
@@ -2419,12 +2483,15 @@ int dpt_batch_track_window_enqueue(dpt_batch* b, const uint8_t* const* frames, c
       max_h = std::max(max_h, c->cam.height);
       // every frame's source rows and window pyramid aligned like the first's
       block = block && sst[s0 + k] % 8 == 0 && c->win_stride % 8 == 0 &&
-              pyramid_block_ok(c->pg, src[s0 + k], sp[s0 + k], c->win);
+              pyramid_block_ok(c->pg, src[s0 + k], sp[s0 + k], bank_win(c));
     }
-    HIP_TRY(launch_pyramid_window(b->d_winjobs + s0, srcs, m, n_frames, max_w, max_h, b->ctx[0]->prm.levels, block,
-                                  b->stream));
+    HIP_TRY(launch_pyramid_window(winjobs + s0, srcs, m, n_frames, max_w, max_h, b->ctx[0]->prm.levels, block, pst));
   }
-  if (b->prof) HIP_TRY(b->prof_pyr.end(b->stream, ps));
+  if (prof_pyr) HIP_TRY(b->prof_pyr.end(b->stream, ps));
+  if (on_ref) {  // the update's event now also covers the windows' pyramids
+    HIP_TRY(hipEventRecord(b->ev_ready, b->rstream));
+    if ((e = batch_consume(b)) != DPT_OK) return e;
+  }
   const int slot = b->slot_next;
   for (int f = 0; f < n_frames; ++f) {
     const int mode = f == 0 && init_mode == DPT_INIT_GIVEN ? kStartGiven : kStartConstVelocity;

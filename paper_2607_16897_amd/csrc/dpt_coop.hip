@@ -484,9 +484,10 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
       reinterpret_cast<uint32_t*>(&ss)[j] = src[j];
   }
   __syncthreads();
-  if (start[w.x].bank) {  // the stream's second reference bank
+  if (start[w.x].bank) {  // the stream's second reference bank, and its window pyramids
     for (int j = threadIdx.x; j < (int)(sizeof(RefCache) / 4); j += blockDim.x)
       reinterpret_cast<uint32_t*>(&ss.a.ref)[j] = reinterpret_cast<const uint32_t*>(&ss.ref_alt)[j];
+    if (threadIdx.x == 0) ss.win = ss.win_alt;
     __syncthreads();
   }
   start_pose(start + w.x, ss.hist, sh_T0, sh_rw, sh_h0, sh_h1, sh_m1, sh_m2, &sh_l0, &sh_l0_stride);
@@ -934,13 +935,14 @@ void CoopEngine::release() {
 }
 
 void CoopEngine::set_stream(int k, const TrackArgs& a, const RefCache& alt, double* hist, const uint8_t* win,
-                            int64_t win_stride) {
+                            const uint8_t* win_alt, int64_t win_stride) {
   CoopStream& c = h_streams[k];
   c.a = a;
   c.a.out = nullptr;  // results go to the launch's slot of h_out
   c.ref_alt = alt;
   c.hist = hist;
   c.win = win;
+  c.win_alt = win_alt;
   c.win_stride = win_stride;
   const int n = std::max(a.ref.n, alt.n);  // the chunks cover the larger bank; the other leaves some idle
   c.n_chunks = n > 0 ? (n + ppc - 1) / ppc : 1;

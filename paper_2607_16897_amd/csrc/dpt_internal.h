@@ -165,7 +165,8 @@ struct CoopStream {
   RefCache ref_alt;    // bank 1 (a reference stream in use), read when the launch's start slot says so
   uint64_t* partials;  // [2][2][n_chunks][32] chunk sums (copy: L2, device scope; parity), word = (tag << 32) | float bits
   double* hist;        // the stream's last two poses T_cw, 2 x 3x4 row-major FP64 (device)
-  const uint8_t* win;  // window tracking: the pyramids of consecutive frames, win_stride bytes apart
+  const uint8_t* win;      // window tracking: the pyramids of consecutive frames, win_stride bytes apart
+  const uint8_t* win_alt;  // bank 1's window pyramids, read with bank 1's reference
   int64_t win_stride;
   int32_t n_chunks;
   int32_t pad;
@@ -255,7 +256,8 @@ struct CoopEngine {
   hipError_t init(int n_streams, const int* max_points, int chunk, int ppc, bool xcd_pack, hipStream_t s);
   void release();
   // a.ref: the stream's reference bank 0, alt: bank 1 (the same as bank 0 without a reference stream)
-  void set_stream(int k, const TrackArgs& a, const RefCache& alt, double* hist, const uint8_t* win, int64_t win_stride);
+  void set_stream(int k, const TrackArgs& a, const RefCache& alt, double* hist, const uint8_t* win,
+                  const uint8_t* win_alt, int64_t win_stride);
   hipError_t upload();
   int grid() const;
   StartSlot* start(int slot) { return h_start + (size_t)slot * n; }
