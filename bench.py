@@ -1216,7 +1216,7 @@ def main():
     if "batched" in legs:
         out["batched"] = {
             "sequences": bench_batched_sequences(dpt, synth, args.batch_streams, max(2, args.steps // 4), 1),
-            "mixed": bench_batched_mixed(dpt, synth, args.batch_streams, 32, 1, keep=c3_keep),
+            "mixed": bench_batched_mixed(dpt, synth, args.batch_streams, 32, 3, keep=c3_keep),
         }
         for o in (out["batched"]["sequences"], out["batched"]["sequences"]["mixed_precision"]):
             r = o["roofline"]  # the window launches' working set lives in L2 and the last-level cache
