@@ -171,15 +171,16 @@ __device__ __forceinline__ bool exchange_wide(const uint64_t* partials, int nch,
 }
 
 // Block sum of acc[NV] (after each thread accumulated its point), exchanged
-// across the stream's chunks; the totals land in sh_tot.  Returns false on
-// timeout (same value in every thread).  NV = 32 or 16.  WIDE: streams of
-// more than kPollBatch chunks are polled by the whole workgroup (exchange_wide,
-// sh_grp: blockDim floats of LDS); otherwise wave 0 polls alone.
+// across the stream's chunks; the totals land in sh_tot and, in every thread,
+// in tot.  Returns false on timeout (same value in every thread).  NV = 32 or
+// 16.  WIDE: streams of more than kPollBatch chunks are polled by the whole
+// workgroup (exchange_wide, sh_grp: blockDim floats of LDS); otherwise wave 0
+// polls alone.
 template <bool KAHAN, int NV, bool WIDE>
 __device__ __forceinline__ bool stream_total(float (&acc)[NV], float* sh_red, float* sh_tot, int* sh_ok,
                                              uint64_t* partials, int chunk, int nch, uint32_t tag,
-                                             int spin_limit, float* sh_grp, uint64_t* t_bar = nullptr,
-                                             int* polls = nullptr) {
+                                             int spin_limit, float* sh_grp, float (&tot)[NV],
+                                             uint64_t* t_bar = nullptr, int* polls = nullptr) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   constexpr int PER_ROW = NV / 4;  // values per 16-lane row after the wave reduction
   if constexpr (NV == 32)
@@ -220,13 +221,21 @@ __device__ __forceinline__ bool stream_total(float (&acc)[NV], float* sh_red, fl
       if (lane == 0) *sh_ok = ok ? 1 : 0;
     }
   }
+  bool ok;
   if (WIDE && nch > kPollBatch) {
-    const bool ok = exchange_wide<KAHAN, NV>(partials, nch, tag, spin_limit, sh_grp, sh_tot);
+    ok = exchange_wide<KAHAN, NV>(partials, nch, tag, spin_limit, sh_grp, sh_tot);
     __syncthreads();
-    return ok;
+  } else {
+    __syncthreads();
+    ok = *sh_ok != 0;
   }
-  __syncthreads();
-  return *sh_ok != 0;
+  // every total requested with the verdict, before any test of either: left to
+  // itself the compiler reads each behind the branch that first needs it, one
+  // LDS round trip per test on the iteration's path
+#pragma unroll
+  for (int j = 0; j < NV; ++j) tot[j] = sh_tot[j];
+  asm volatile("" ::: "memory");
+  return ok;
 }
 
 // 3x4 rigid transforms (row-major [R | t]) in FP64, one output element per
@@ -492,6 +501,7 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
   }
   start_pose(start + w.x, ss.hist, sh_T0, sh_rw, sh_h0, sh_h1, sh_m1, sh_m2, &sh_l0, &sh_l0_stride);
   const TrackArgs& a = ss.a;
+  const IterParams ip(a);
   const PatRegs pregs = pattern_regs(a.pat);
   const int chunk = w.y, nch = ss.n_chunks;
   const int i = chunk * PPC + (int)threadIdx.x / TPP;
@@ -566,7 +576,7 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
       bool converged = false;
       const int it0 = iterations;
       if constexpr (kCycleProfile) cy_fr[1] += clock64() - cl0;
-      for (int it = 0; it < a.max_iters; ++it) {
+      for (int it = 0; it < ip.max_iters; ++it) {
         uint64_t c0 = 0, c1 = 0, c2 = 0;
         if constexpr (kCycleProfile) c0 = clock64();
         float acc[NV];
@@ -575,12 +585,13 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
         if constexpr (GENERIC)
           accumulate_point_generic<false, PIX, NV>(a, a.pat, g, img, T, pr, sub, acc);
         else
-          accumulate_point8<false, PR, NV, NS>(a, pregs, offs, g, reinterpret_cast<const uint8_t*>(img), tile, T,
+          accumulate_point8<false, PR, NV, NS>(ip, pregs, offs, g, reinterpret_cast<const uint8_t*>(img), tile, T,
                                                pr, acc, sub == 0);
         if constexpr (kCycleProfile) c1 = clock64();
         int polls = 0;
+        float tot[NV];
         if (!stream_total<MIXED, NV, GENERIC>(acc, sh_red, sh_tot, &sh_ok, ss.partials, chunk, nch, tag, spin_limit,
-                                              sh_grp, &c2, &polls)) {
+                                              sh_grp, tot, &c2, &polls)) {
           timed_out = stop = true;
           break;
         }
@@ -588,8 +599,8 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
         if constexpr (kCycleProfile) c3 = clock64();
         ++tag;
         // the 8-pixel kernels count samples as 8 per point outside the final pass
-        samples += GENERIC ? (int64_t)(int)sh_tot[sN] : 8 * (int64_t)(int)sh_tot[sP];  // counts < 2^24: exact
-        if ((int)sh_tot[sP] < a.min_points) {
+        samples += GENERIC ? (int64_t)(int)tot[sN] : 8 * (int64_t)(int)tot[sP];  // counts < 2^24: exact
+        if ((int)tot[sP] < ip.min_points) {
           status = 2;  // too few points
           stop = true;
           break;
@@ -600,16 +611,16 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
           const float* fac = sh_fac[FIXED ? (l & 1) : 0];
           bad = fac[27] != 0.0f;
           float stepf = 0.0f;
-          if (!bad) solve_fixed(fac, fac + 21, sh_tot + kFixB, T, &stepf);
+          if (!bad) solve_fixed(fac, fac + 21, tot + kFixB, T, &stepf);
           step = stepf;
         } else if (MIXED) {
-          bad = solve_update_d(sh_tot, Td, &step);
+          bad = solve_update_d(tot, Td, &step);
           if (!bad)
 #pragma unroll
             for (int j = 0; j < 12; ++j) T[j] = (float)Td[j];
         } else {
           float stepf;
-          bad = solve_update(sh_tot, T, &stepf);
+          bad = solve_update(tot, T, &stepf);
           step = stepf;
         }
         if constexpr (kCycleProfile) {
@@ -622,7 +633,7 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
           break;
         }
         ++iterations;
-        if (step < (double)a.step_eps) {
+        if (step < (double)ip.step_eps) {
           converged = true;
           break;
         }
@@ -650,10 +661,11 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
         }
         int offs[NS];
         lane_offsets<NS>(pregs, g.W, sub, offs);
-        accumulate_point8<true, PR, NV, NS>(a, pregs, offs, g, WIN ? cur0 : cur + g.off, tile0, T, pr, acc, sub == 0);
+        accumulate_point8<true, PR, NV, NS>(ip, pregs, offs, g, WIN ? cur0 : cur + g.off, tile0, T, pr, acc, sub == 0);
       }
+      float tot[NV];
       if (!stream_total<MIXED, NV, GENERIC>(acc, sh_red, sh_tot, &sh_ok, ss.partials, chunk, nch, tag, spin_limit,
-                                            sh_grp))
+                                            sh_grp, tot))
         timed_out = true;
       ++tag;
     }

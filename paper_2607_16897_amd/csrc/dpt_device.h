@@ -908,6 +908,16 @@ __device__ __forceinline__ void pattern_offsets(const PatRegs& pat, int W, int (
   for (int k = 0; k < 8; ++k) off[k] = (int)pat.dy[k] * W + (int)pat.dx[k];
 }
 
+// The scalar track parameters an iteration reads, copied to registers once
+// per launch: the cooperative kernel keeps its TrackArgs in LDS, where a field
+// read after a workgroup barrier is an LDS round trip on the iteration's path.
+struct IterParams {
+  float huber_k, z_min, step_eps;
+  int max_iters, min_points;
+  __device__ explicit IterParams(const TrackArgs& a)
+      : huber_k(a.huber_k), z_min(a.z_min), step_eps(a.step_eps), max_iters(a.max_iters), min_points(a.min_points) {}
+};
+
 // accumulate_point for the 8-pixel pattern, with the taps read from the
 // workgroup's LDS copy of the level where every point of the wave lies inside
 // it (else from global memory, as accumulate_point).  The pattern offsets are
@@ -921,7 +931,7 @@ __device__ __forceinline__ void pattern_offsets(const PatRegs& pat, int W, int (
 // own samples' normal-equation terms, which sum to the point's (the terms are
 // linear in m and v); the first thread counts the point.
 template <bool COST_ONLY, class PR, int NV = 32, int NS = 8>
-__device__ __forceinline__ void accumulate_point8(const TrackArgs& a, const PatRegs& pat, const int (&off)[NS],
+__device__ __forceinline__ void accumulate_point8(const IterParams& a, const PatRegs& pat, const int (&off)[NS],
                                                   const LevelGeom& g, const uint8_t* __restrict__ img,
                                                   const Tile8& tile, const float* T, const PR& pr,
                                                   float (&acc)[NV], bool first = true) {
