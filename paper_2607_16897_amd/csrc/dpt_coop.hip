@@ -41,6 +41,22 @@ __device__ __forceinline__ void publish_word(uint64_t* fast, uint64_t* slow, uin
   __hip_atomic_store(slow, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The value lane (lane ^ D) holds, D = 16 or 32, moved within the register
+// file (v_permlane16_swap / v_permlane32_swap exchange the rows, or the
+// halves, of two registers) instead of through the LDS crossbar.
+template <int D>
+__device__ __forceinline__ float lane_xor(float x) {
+  static_assert(D == 16 || D == 32, "row or half swap");
+  const uint32_t u = __float_as_uint(x);
+  if constexpr (D == 32) {
+    const auto r = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+    return __uint_as_float((threadIdx.x & 32) ? r[0] : r[1]);
+  } else {
+    const auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+    return __uint_as_float((threadIdx.x & 16) ? r[0] : r[1]);
+  }
+}
+
 // Wave 0 only.  Publish this chunk's column sums (`mine`, lanes < NV) under
 // `tag`, wait until all nch chunks of the stream published theirs, and return
 // the stream totals (lanes < NV).  False on timeout.  A chunk's words are 32
@@ -86,15 +102,15 @@ __device__ __forceinline__ bool exchange_partials(uint64_t* partials, int chunk,
       }
     }
     if (__all(ok)) {
-      if constexpr (G == 4) s += __shfl_xor(s, 16, 64);  // (g0 + g1), (g2 + g3)
+      if constexpr (G == 4) s += lane_xor<16>(s);  // (g0 + g1), (g2 + g3)
       if constexpr (KAHAN) {  // the two compensated sums: (s0 - c0) + (s1 - c1)
-        const float ps = __shfl_xor(s, 32, 64), pc = __shfl_xor(comp, 32, 64);
+        const float ps = lane_xor<32>(s), pc = lane_xor<32>(comp);
         const float lo_s = q == 0 ? s : ps, lo_c = q == 0 ? comp : pc;
         const float hi_s = q == 0 ? ps : s, hi_c = q == 0 ? pc : comp;
         const float y = hi_s - (lo_c + hi_c);
         s = lo_s + y;
       } else {
-        s += __shfl_xor(s, 32, 64);
+        s += lane_xor<32>(s);
       }
       *total = s;
       if (kCycleProfile && polls) *polls = t + 1;
@@ -175,13 +191,13 @@ __device__ __forceinline__ bool exchange_wide(const uint64_t* partials, int nch,
 // in tot.  Returns false on timeout (same value in every thread).  NV = 32 or
 // 16.  WIDE: streams of more than kPollBatch chunks are polled by the whole
 // workgroup (exchange_wide, sh_grp: blockDim floats of LDS); otherwise wave 0
-// polls alone.
-template <bool KAHAN, int NV, bool WIDE>
+// polls alone.  NW: the workgroup's waves (blockDim / 64).
+template <bool KAHAN, int NV, bool WIDE, int NW>
 __device__ __forceinline__ bool stream_total(float (&acc)[NV], float* sh_red, float* sh_tot, int* sh_ok,
                                              uint64_t* partials, int chunk, int nch, uint32_t tag,
                                              int spin_limit, float* sh_grp, float (&tot)[NV],
                                              uint64_t* t_bar = nullptr, int* polls = nullptr) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   constexpr int PER_ROW = NV / 4;  // values per 16-lane row after the wave reduction
   if constexpr (NV == 32)
     wave_reduce32(acc);
@@ -196,7 +212,8 @@ __device__ __forceinline__ bool stream_total(float (&acc)[NV], float* sh_red, fl
   if (wave == 0) {
     float s = 0.0f, comp = 0.0f;
     if (lane < NV) {
-      for (int w = 0; w < nw; ++w) {
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {  // all NW reads in flight at once, then the sum in wave order
         const float x = sh_red[w * NV + lane];
         if (KAHAN) {
           const float y = x - comp;
@@ -375,9 +392,10 @@ constexpr int kBandMargin = 4;
 // points span at pose T, widened by kBandMargin and cut to the tile's size.
 // Copies the 16-byte granules that overlap those rows (each holds at least one
 // byte of them, so none crosses into a page the level does not touch).
-// Block-wide; the caller has finished every read of the previous tile.
-template <class PR>
-__device__ __forceinline__ Tile8 stage_tile(const TrackArgs& a, const PatRegs& pat, const LevelGeom& g,
+// Block-wide (NW waves); the caller has finished every read of the previous
+// tile.
+template <int NW, class PR>
+__device__ __forceinline__ Tile8 stage_tile(const IterParams& a, const PatRegs& pat, const LevelGeom& g,
                                             const uint8_t* img, const float* T, const PR& pr, uint8_t* tile_mem,
                                             int tile_bytes, int* sh_band) {
   const int W = g.W, H = g.H;
@@ -396,11 +414,12 @@ __device__ __forceinline__ Tile8 stage_tile(const TrackArgs& a, const PatRegs& p
       rlo = min(rlo, __shfl_xor(rlo, d, 64));
       rhi = max(rhi, __shfl_xor(rhi, d, 64));
     }
-    const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int wave = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) sh_band[2 * wave] = rlo, sh_band[2 * wave + 1] = rhi;
     __syncthreads();
     rlo = INT_MAX, rhi = INT_MIN;
-    for (int w = 0; w < nw; ++w) rlo = min(rlo, sh_band[2 * w]), rhi = max(rhi, sh_band[2 * w + 1]);
+#pragma unroll
+    for (int w = 0; w < NW; ++w) rlo = min(rlo, sh_band[2 * w]), rhi = max(rhi, sh_band[2 * w + 1]);
     if (rlo <= rhi) {
       lo = max(0, rlo - kBandMargin);
       hi = min(H - 1, rhi + kBandMargin);
@@ -560,7 +579,7 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
         else
           load_point(a, l, i, pr);
         lane_offsets<NS>(pregs, g.W, sub, offs);
-        tile = stage_tile(a, pregs, g, reinterpret_cast<const uint8_t*>(img), T, pr, sh_tile, tile_bytes, sh_band);
+        tile = stage_tile<CH / 64>(ip, pregs, g, reinterpret_cast<const uint8_t*>(img), T, pr, sh_tile, tile_bytes, sh_band);
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (l == 0) tile0 = tile, at0 = true;
@@ -590,8 +609,8 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
         if constexpr (kCycleProfile) c1 = clock64();
         int polls = 0;
         float tot[NV];
-        if (!stream_total<MIXED, NV, GENERIC>(acc, sh_red, sh_tot, &sh_ok, ss.partials, chunk, nch, tag, spin_limit,
-                                              sh_grp, tot, &c2, &polls)) {
+        if (!stream_total<MIXED, NV, GENERIC, CH / 64>(acc, sh_red, sh_tot, &sh_ok, ss.partials, chunk, nch, tag,
+                                                       spin_limit, sh_grp, tot, &c2, &polls)) {
           timed_out = stop = true;
           break;
         }
@@ -664,8 +683,8 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
         accumulate_point8<true, PR, NV, NS>(ip, pregs, offs, g, WIN ? cur0 : cur + g.off, tile0, T, pr, acc, sub == 0);
       }
       float tot[NV];
-      if (!stream_total<MIXED, NV, GENERIC>(acc, sh_red, sh_tot, &sh_ok, ss.partials, chunk, nch, tag, spin_limit,
-                                            sh_grp, tot))
+      if (!stream_total<MIXED, NV, GENERIC, CH / 64>(acc, sh_red, sh_tot, &sh_ok, ss.partials, chunk, nch, tag,
+                                                     spin_limit, sh_grp, tot))
         timed_out = true;
       ++tag;
     }
