@@ -36,7 +36,8 @@ constexpr int kSlowPollMask = 7;
 
 // Publish one partial word: the group-scope store (kept in the XCD's L2, no
 // write-through) to `fast`, the device-scope one to `slow`.
-__device__ __forceinline__ void publish_word(uint64_t* fast, uint64_t* slow, uint64_t w) {
+__device__ __forceinline__ void publish_word(__attribute__((address_space(1))) uint64_t* fast,
+                                             __attribute__((address_space(1))) uint64_t* slow, uint64_t w) {
   asm volatile("global_store_dwordx2 %0, %1, off sc0" : : "v"(fast), "v"(w) : "memory");
   __hip_atomic_store(slow, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -71,33 +72,40 @@ __device__ __forceinline__ bool exchange_partials(uint64_t* partials, int chunk,
   static_assert(G == 2 || G == 4, "32 or 16 values per chunk");
   static_assert(!(KAHAN && G != 2), "compensated sums use 32 values");
   const int lane = threadIdx.x & 63, q = lane / NV, v = lane % NV;
-  uint64_t* buf = partials + (size_t)(tag & 1u) * nch * 32;
-  uint64_t* slow = partials + (size_t)(2 + (tag & 1u)) * nch * 32;
+  // global-memory pointers: global loads and stores, which unlike flat ones
+  // leave the LDS counter alone and skip the aperture check
+  using gptr = __attribute__((address_space(1))) uint64_t*;
+  gptr buf = (gptr)(partials + (size_t)(tag & 1u) * nch * 32);
+  gptr slow = (gptr)(partials + (size_t)(2 + (tag & 1u)) * nch * 32);
   const uint64_t hi = (uint64_t)tag << 32;
   if (lane < NV) publish_word(&buf[chunk * 32 + lane], &slow[chunk * 32 + lane], hi | __float_as_uint(mine));
   const int per = (nch + G - 1) / G, cb = q * per, ce = cb + per < nch ? cb + per : nch;
   for (int t = 0; t < spin_limit; ++t) {
-    const uint64_t* rb = (t & kSlowPollMask) == kSlowPollMask ? slow : buf;
+    const gptr rb = (t & kSlowPollMask) == kSlowPollMask ? slow : buf;
     float s = 0.0f, comp = 0.0f;
     int ok = 1;
     for (int c0 = cb; c0 < ce; c0 += kPollBatch) {
+      // a batch of loads in flight, then the checks, with no branch between
+      // the loads: past its range's end a lane re-reads the range's last
+      // chunk and leaves the word out
       uint64_t w[kPollBatch];
 #pragma unroll
-      for (int j = 0; j < kPollBatch; ++j)  // a batch of loads in flight, then the checks
-        w[j] = c0 + j < ce ? __hip_atomic_load(&rb[(c0 + j) * 32 + v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                           : hi;
+      for (int j = 0; j < kPollBatch; ++j)
+        w[j] = __hip_atomic_load(&rb[min(c0 + j, ce - 1) * 32 + v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 #pragma unroll
       for (int j = 0; j < kPollBatch; ++j) {
-        if (c0 + j >= ce) break;
-        ok &= (uint32_t)(w[j] >> 32) == tag;
+        const bool in = c0 + j < ce;
+        ok &= !in | ((uint32_t)(w[j] >> 32) == tag);
         const float x = __uint_as_float((uint32_t)w[j]);
         if (KAHAN) {
           const float y = x - comp;
           const float u = s + y;
-          comp = (u - s) - y;
-          s = u;
+          const float cn = (u - s) - y;
+          s = in ? u : s;
+          comp = in ? cn : comp;
         } else {
-          s += x;
+          const float u = s + x;
+          s = in ? u : s;
         }
       }
     }
@@ -227,8 +235,9 @@ __device__ __forceinline__ bool stream_total(float (&acc)[NV], float* sh_red, fl
     }
     if (WIDE && nch > kPollBatch) {  // publish; the whole workgroup polls below
       if (lane < NV)
-        publish_word(&partials[(size_t)(tag & 1u) * nch * 32 + chunk * 32 + lane],
-                     &partials[(size_t)(2 + (tag & 1u)) * nch * 32 + chunk * 32 + lane],
+        publish_word((__attribute__((address_space(1))) uint64_t*)&partials[(size_t)(tag & 1u) * nch * 32 + chunk * 32 + lane],
+                     (__attribute__((address_space(1))) uint64_t*)&partials[(size_t)(2 + (tag & 1u)) * nch * 32 +
+                                                                           chunk * 32 + lane],
                      ((uint64_t)tag << 32) | __float_as_uint(s));
     } else {
       float tot = s;
