@@ -46,16 +46,38 @@ __device__ __forceinline__ void publish_word(__attribute__((address_space(1))) u
 // file (v_permlane16_swap / v_permlane32_swap exchange the rows, or the
 // halves, of two registers) instead of through the LDS crossbar.
 template <int D>
-__device__ __forceinline__ float lane_xor(float x) {
+__device__ __forceinline__ uint32_t lane_xor_u(uint32_t u) {
   static_assert(D == 16 || D == 32, "row or half swap");
-  const uint32_t u = __float_as_uint(x);
   if constexpr (D == 32) {
     const auto r = __builtin_amdgcn_permlane32_swap(u, u, false, false);
-    return __uint_as_float((threadIdx.x & 32) ? r[0] : r[1]);
+    return (threadIdx.x & 32) ? r[0] : r[1];
   } else {
     const auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
-    return __uint_as_float((threadIdx.x & 16) ? r[0] : r[1]);
+    return (threadIdx.x & 16) ? r[0] : r[1];
   }
+}
+
+template <int D>
+__device__ __forceinline__ float lane_xor(float x) {
+  return __uint_as_float(lane_xor_u<D>(__float_as_uint(x)));
+}
+
+// Row rotation within 16 lanes (DPP row_ror:K) of an integer.
+template <int K>
+__device__ __forceinline__ int dpp_ror_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x120 + K, 0xf, 0xf, false);
+}
+
+// The wave's minimum of lo and maximum of hi, in every lane: DPP rotations
+// within each 16-lane row, then the row and half-wave swaps, with no LDS
+// round trip between the steps.  All 64 lanes active.
+__device__ __forceinline__ void wave_min_max(int& lo, int& hi) {
+  lo = min(lo, dpp_ror_i<8>(lo)), hi = max(hi, dpp_ror_i<8>(hi));
+  lo = min(lo, dpp_ror_i<4>(lo)), hi = max(hi, dpp_ror_i<4>(hi));
+  lo = min(lo, dpp_ror_i<2>(lo)), hi = max(hi, dpp_ror_i<2>(hi));
+  lo = min(lo, dpp_ror_i<1>(lo)), hi = max(hi, dpp_ror_i<1>(hi));
+  lo = min(lo, (int)lane_xor_u<16>((uint32_t)lo)), hi = max(hi, (int)lane_xor_u<16>((uint32_t)hi));
+  lo = min(lo, (int)lane_xor_u<32>((uint32_t)lo)), hi = max(hi, (int)lane_xor_u<32>((uint32_t)hi));
 }
 
 // Wave 0 only.  Publish this chunk's column sums (`mine`, lanes < NV) under
@@ -138,36 +160,38 @@ template <bool KAHAN, int NV>
 __device__ __forceinline__ bool exchange_wide(const uint64_t* partials, int nch, uint32_t tag, int spin_limit,
                                               float* sh_grp, float* sh_tot) {
   const int t = threadIdx.x, v = t & 31, q = t >> 5, G = blockDim.x >> 5;
-  const uint64_t* buf = partials + (size_t)(tag & 1u) * nch * 32;
-  const uint64_t* slow = partials + (size_t)(2 + (tag & 1u)) * nch * 32;
-  const uint64_t hi = (uint64_t)tag << 32;
+  // global-memory pointers and no branch between a batch's loads, as in
+  // exchange_partials: past the last chunk a lane re-reads it and drops the word
+  using gptr = const __attribute__((address_space(1))) uint64_t*;
+  const gptr buf = (gptr)(partials + (size_t)(tag & 1u) * nch * 32);
+  const gptr slow = (gptr)(partials + (size_t)(2 + (tag & 1u)) * nch * 32);
   float s = 0.0f, comp = 0.0f;
   bool ok = true;
   if (v < NV) {
     ok = false;
     for (int it = 0; it < spin_limit && !ok; ++it) {
-      const uint64_t* rb = (it & kSlowPollMask) == kSlowPollMask ? slow : buf;
+      const gptr rb = (it & kSlowPollMask) == kSlowPollMask ? slow : buf;
       s = 0.0f, comp = 0.0f;
       ok = true;
       for (int c0 = q; c0 < nch; c0 += 4 * G) {
         uint64_t w[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int c = c0 + j * G;
-          w[j] = c < nch ? __hip_atomic_load(&rb[c * 32 + v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : hi;
-        }
+        for (int j = 0; j < 4; ++j)
+          w[j] = __hip_atomic_load(&rb[min(c0 + j * G, nch - 1) * 32 + v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          if (c0 + j * G >= nch) break;
-          ok &= (uint32_t)(w[j] >> 32) == tag;
+          const bool in = c0 + j * G < nch;
+          ok &= !in | ((uint32_t)(w[j] >> 32) == tag);
           const float x = __uint_as_float((uint32_t)w[j]);
           if (KAHAN) {
             const float y = x - comp;
             const float u = s + y;
-            comp = (u - s) - y;
-            s = u;
+            const float cn = (u - s) - y;
+            s = in ? u : s;
+            comp = in ? cn : comp;
           } else {
-            s += x;
+            const float u = s + x;
+            s = in ? u : s;
           }
         }
       }
@@ -418,11 +442,7 @@ __device__ __forceinline__ Tile8 stage_tile(const IterParams& a, const PatRegs& 
     const bool ok = pr.ok & (Z > a.z_min) & inside(g, pat, u, v);
     const int iv = (int)floorf(ok ? v : 0.0f);
     int rlo = ok ? iv + (int)pat.dy_min : INT_MAX, rhi = ok ? iv + (int)pat.dy_max + 1 : INT_MIN;
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) {
-      rlo = min(rlo, __shfl_xor(rlo, d, 64));
-      rhi = max(rhi, __shfl_xor(rhi, d, 64));
-    }
+    wave_min_max(rlo, rhi);
     const int wave = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) sh_band[2 * wave] = rlo, sh_band[2 * wave + 1] = rhi;
     __syncthreads();
