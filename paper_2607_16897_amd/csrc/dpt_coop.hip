@@ -426,15 +426,18 @@ constexpr int kBandMargin = 4;
 // Copies the 16-byte granules that overlap those rows (each holds at least one
 // byte of them, so none crosses into a page the level does not touch).
 // Block-wide (NW waves); the caller has finished every read of the previous
-// tile.
+// tile.  The points' geometry arrives as loaded (raw) and is completed into pr
+// here: before the band is computed from it, or, for a whole level, after the
+// copy is issued, so the copy's latency and the point loads' overlap.
 template <int NW, class PR>
 __device__ __forceinline__ Tile8 stage_tile(const IterParams& a, const PatRegs& pat, const LevelGeom& g,
-                                            const uint8_t* img, const float* T, const PR& pr, uint8_t* tile_mem,
-                                            int tile_bytes, int* sh_band) {
+                                            const uint8_t* img, const float* T, PR& pr, GeoRaw& raw,
+                                            uint8_t* tile_mem, int tile_bytes, int* sh_band) {
   const int W = g.W, H = g.H;
   const int rows_fit = (tile_bytes - 32) / W;
   int lo = 0, hi = H - 1;
   if (rows_fit < H) {
+    finish_geometry(pr, raw);
     float X, Y, Z;
     transform(T, pr.X0, pr.Y0, pr.Z0, X, Y, Z);
     const float iz = __builtin_amdgcn_rcpf(Z);
@@ -469,6 +472,7 @@ __device__ __forceinline__ Tile8 stage_tile(const IterParams& a, const PatRegs& 
       __builtin_amdgcn_global_load_lds(reinterpret_cast<const uint32_t*>(s0 + 16 * (uintptr_t)q),
                                        (__attribute__((address_space(3))) void*)(tile_mem + 16 * q0), 16, 0, 0);
   }
+  if (rows_fit >= H) finish_geometry(pr, raw);
   Tile8 t;
   t.lds = (const __attribute__((address_space(3))) uint8_t*)(tile_mem);
   t.lo = lo, t.hi = hi, t.delta = delta, t.bytes = ng * 16;
@@ -603,12 +607,11 @@ __global__ __launch_bounds__(CH, 2) void coop_track_kernel(const CoopStream* __r
       if constexpr (GENERIC) {
         load_point_geo(a, l, i, pr);
       } else {
-        if constexpr (LPP == 2)
-          load_point(a, l, i, sub, pr);
-        else
-          load_point(a, l, i, pr);
+        GeoRaw raw;
+        load_point_raw(a, l, i, sub, pr, raw);
         lane_offsets<NS>(pregs, g.W, sub, offs);
-        tile = stage_tile<CH / 64>(ip, pregs, g, reinterpret_cast<const uint8_t*>(img), T, pr, sh_tile, tile_bytes, sh_band);
+        tile = stage_tile<CH / 64>(ip, pregs, g, reinterpret_cast<const uint8_t*>(img), T, pr, raw, sh_tile, tile_bytes,
+                                   sh_band);
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (l == 0) tile0 = tile, at0 = true;

@@ -687,6 +687,25 @@ struct PointRegsH4 {
   __device__ __forceinline__ float gy(int k) const { return __high2float(g_[k]); }
 };
 
+// A load through a generic pointer into device memory, issued as a global
+// (not flat) load: a flat load also counts on the LDS counter, so the next
+// wait for LDS data would wait for it as well.
+// The value moves as a plain word or word vector: HIP's vector structs copy
+// through a generic reference, which would turn the load back into a flat one.
+template <class T>
+__device__ __forceinline__ T gload(const T* p) {
+  static_assert(sizeof(T) == 1 || sizeof(T) == 4 || sizeof(T) == 8 || sizeof(T) == 16, "word or word vector");
+  using W = typename std::conditional<
+      sizeof(T) == 1, uint8_t,
+      typename std::conditional<sizeof(T) == 4, uint32_t,
+                                typename std::conditional<sizeof(T) == 8, uint32_t __attribute__((ext_vector_type(2))),
+                                                          uint32_t __attribute__((ext_vector_type(4)))>::type>::type>::type;
+  const W w = *(const __attribute__((address_space(1))) W*)p;
+  T t;
+  __builtin_memcpy(&t, &w, sizeof(T));
+  return t;
+}
+
 // Load point i's registers for level l.  Branch-free: a point past the map
 // (i >= n) reads entry 0 instead, and the geometry of an unusable point is
 // selected to finite values (its warp Jacobian multiplies masked zeros); the
@@ -697,8 +716,26 @@ __device__ __forceinline__ bool load_geometry(const TrackArgs& a, int l, int i, 
   const bool in = i < a.ref.n;
   const int j = in ? i : 0;
   e = lo + j;
-  p = a.ref.x0[j];
-  return in & (a.ref.valid[e] != 0);
+  p = gload(a.ref.x0 + j);
+  return in & (gload(a.ref.valid + e) != 0);
+}
+
+// A point's geometry as loaded (world point, validity byte, inside the map),
+// before any use of the loaded words.
+struct GeoRaw {
+  float x, y, z;
+  uint32_t valid;
+  bool in;
+};
+
+__device__ __forceinline__ void load_geometry_raw(const TrackArgs& a, int l, int i, GeoRaw& r, int64_t& e) {
+  const int64_t lo = (int64_t)l * a.ref.cap;
+  r.in = i < a.ref.n;
+  const int j = r.in ? i : 0;
+  e = lo + j;
+  const float4 p = gload(a.ref.x0 + j);
+  r.x = p.x, r.y = p.y, r.z = p.z;
+  r.valid = gload(a.ref.valid + e);
 }
 
 template <class PR>
@@ -713,15 +750,14 @@ __device__ __forceinline__ void set_geometry(PR& pr, bool ok, const float4& p) {
   pr.yp = ok ? p.y * iz : 0.0f;
 }
 
-__device__ __forceinline__ void load_point(const TrackArgs& a, int l, int i, PointRegs& pr) {
-  float4 p;
-  int64_t e;
-  const bool ok = load_geometry(a, l, i, p, e);
-  set_geometry(pr, ok, p);
+// The template registers of cache entry e: all 8 samples, or (PR4 variants)
+// the four of thread `sub` of the point's pair.
+__device__ __forceinline__ void load_template(const TrackArgs& a, int64_t e, int, PointRegs& pr) {
   const float4* q0 = reinterpret_cast<const float4*>(a.ref.I0 + e * 8);
   const float4* qx = reinterpret_cast<const float4*>(a.ref.gx + e * 8);
   const float4* qy = reinterpret_cast<const float4*>(a.ref.gy + e * 8);
-  const float4 a0 = q0[0], a1 = q0[1], b0 = qx[0], b1 = qx[1], c0 = qy[0], c1 = qy[1];
+  const float4 a0 = gload(q0), a1 = gload(q0 + 1), b0 = gload(qx), b1 = gload(qx + 1), c0 = gload(qy),
+               c1 = gload(qy + 1);
   const float t0[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
   const float t1[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
   const float t2[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
@@ -729,27 +765,18 @@ __device__ __forceinline__ void load_point(const TrackArgs& a, int l, int i, Poi
   for (int k = 0; k < 8; ++k) pr.i0_[k] = t0[k], pr.gx_[k] = t1[k], pr.gy_[k] = t2[k];
 }
 
-// Thread `sub` (0 or 1) of point i's pair: its four samples of the cache.
-__device__ __forceinline__ void load_point(const TrackArgs& a, int l, int i, int sub, PointRegs4& pr) {
-  float4 p;
-  int64_t e;
-  const bool ok = load_geometry(a, l, i, p, e);
-  set_geometry(pr, ok, p);
-  const float4 a0 = reinterpret_cast<const float4*>(a.ref.I0 + e * 8)[sub];
-  const float4 b0 = reinterpret_cast<const float4*>(a.ref.gx + e * 8)[sub];
-  const float4 c0 = reinterpret_cast<const float4*>(a.ref.gy + e * 8)[sub];
+__device__ __forceinline__ void load_template(const TrackArgs& a, int64_t e, int sub, PointRegs4& pr) {
+  const float4 a0 = gload(reinterpret_cast<const float4*>(a.ref.I0 + e * 8) + sub);
+  const float4 b0 = gload(reinterpret_cast<const float4*>(a.ref.gx + e * 8) + sub);
+  const float4 c0 = gload(reinterpret_cast<const float4*>(a.ref.gy + e * 8) + sub);
   pr.i0_[0] = a0.x, pr.i0_[1] = a0.y, pr.i0_[2] = a0.z, pr.i0_[3] = a0.w;
   pr.gx_[0] = b0.x, pr.gx_[1] = b0.y, pr.gx_[2] = b0.z, pr.gx_[3] = b0.w;
   pr.gy_[0] = c0.x, pr.gy_[1] = c0.y, pr.gy_[2] = c0.z, pr.gy_[3] = c0.w;
 }
 
-__device__ __forceinline__ void load_point(const TrackArgs& a, int l, int i, int sub, PointRegsH4& pr) {
-  float4 p;
-  int64_t e;
-  const bool ok = load_geometry(a, l, i, p, e);
-  set_geometry(pr, ok, p);
-  const uint2 h = reinterpret_cast<const uint2*>(a.ref.I0h + e * 8)[sub];
-  const uint4 g = reinterpret_cast<const uint4*>(a.ref.gh + e * 8)[sub];
+__device__ __forceinline__ void load_template(const TrackArgs& a, int64_t e, int sub, PointRegsH4& pr) {
+  const uint2 h = gload(reinterpret_cast<const uint2*>(a.ref.I0h + e * 8) + sub);
+  const uint4 g = gload(reinterpret_cast<const uint4*>(a.ref.gh + e * 8) + sub);
   const uint32_t hw[2] = {h.x, h.y};
   const uint32_t gw[4] = {g.x, g.y, g.z, g.w};
 #pragma unroll
@@ -765,14 +792,10 @@ __device__ __forceinline__ void load_point(const TrackArgs& a, int l, int i, int
   }
 }
 
-__device__ __forceinline__ void load_point(const TrackArgs& a, int l, int i, PointRegsH& pr) {
-  float4 p;
-  int64_t e;
-  const bool ok = load_geometry(a, l, i, p, e);
-  set_geometry(pr, ok, p);
-  const uint4 h = *reinterpret_cast<const uint4*>(a.ref.I0h + e * 8);
+__device__ __forceinline__ void load_template(const TrackArgs& a, int64_t e, int, PointRegsH& pr) {
+  const uint4 h = gload(reinterpret_cast<const uint4*>(a.ref.I0h + e * 8));
   const uint4* q = reinterpret_cast<const uint4*>(a.ref.gh + e * 8);
-  const uint4 g0 = q[0], g1 = q[1];
+  const uint4 g0 = gload(q), g1 = gload(q + 1);
   const uint32_t hw[4] = {h.x, h.y, h.z, h.w};
   const uint32_t gw[8] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w};
 #pragma unroll
@@ -786,6 +809,40 @@ __device__ __forceinline__ void load_point(const TrackArgs& a, int l, int i, Poi
     __builtin_memcpy(&v, &gw[k], 4);
     pr.g_[k] = v;
   }
+}
+
+// Point i's registers for level l: one thread per point (sub ignored), or
+// thread `sub` (0 or 1) of the point's pair for the PR4 variants.
+template <class PR>
+__device__ __forceinline__ void load_point(const TrackArgs& a, int l, int i, int sub, PR& pr) {
+  float4 p;
+  int64_t e;
+  const bool ok = load_geometry(a, l, i, p, e);
+  set_geometry(pr, ok, p);
+  load_template(a, e, sub, pr);
+}
+
+template <class PR>
+__device__ __forceinline__ void load_point(const TrackArgs& a, int l, int i, PR& pr) {
+  load_point(a, l, i, 0, pr);
+}
+
+// As load_point, with the geometry left as loaded (r): the cooperative kernel
+// issues these loads, then its level tile's copy, and only then waits for them
+// (finish_geometry), so both latencies overlap.
+template <class PR>
+__device__ __forceinline__ void load_point_raw(const TrackArgs& a, int l, int i, int sub, PR& pr, GeoRaw& r) {
+  int64_t e;
+  load_geometry_raw(a, l, i, r, e);
+  load_template(a, e, sub, pr);
+}
+
+// The wait for the geometry words happens here (the empty asm reads them), not
+// earlier: the compiler may not compute with them before this point.
+template <class PR>
+__device__ __forceinline__ void finish_geometry(PR& pr, GeoRaw& r) {
+  asm volatile("" : "+v"(r.x), "+v"(r.y), "+v"(r.z), "+v"(r.valid) : : "memory");
+  set_geometry(pr, r.in & (r.valid != 0), make_float4(r.x, r.y, r.z, 0.0f));
 }
 
 // Add one point's normal-equation terms (Eq.(2), Eq.(5)) at relative pose T.
@@ -1113,8 +1170,8 @@ __device__ __forceinline__ void accumulate_point_generic(const TrackArgs& a, con
       // an unusable point reads the level's first taps
       const int off = ((q0.iv + (int)pat.dy[kk]) * W + q0.iu + (int)pat.dx[kk]) & -(int)ok;
       t00[j] = gimg[off], t10[j] = gimg[off + 1], t01[j] = gimg[off + W], t11[j] = gimg[off + W + 1];
-      i0[j] = a.ref.I0[pg.s0 + kk];
-      if (!COST_ONLY) gxs[j] = a.ref.gx[pg.s0 + kk], gys[j] = a.ref.gy[pg.s0 + kk];
+      i0[j] = gload(a.ref.I0 + pg.s0 + kk);
+      if (!COST_ONLY) gxs[j] = gload(a.ref.gx + pg.s0 + kk), gys[j] = gload(a.ref.gy + pg.s0 + kk);
     }
 #pragma unroll
     for (int j = 0; j < B; ++j) {
