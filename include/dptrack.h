@@ -425,8 +425,9 @@ int dpt_set_launch_config(dpt_ctx* ctx, int32_t mode, int32_t chunk);
  * partial sums `polls` times without seeing them all gives up, and its frame
  * (and, in a window track, the frames after it) ends with status
  * DPT_TRACK_TIMEOUT; the next synchronisation then reports DPT_E_HIP and resets
- * the exchange, so later tracks start clean.  Default 4194304 (seconds of
- * polling; reached only if the chunks were not co-resident).  polls = 0 makes
+ * the exchange, so later tracks start clean.  Default 4194304 (about a second
+ * of polling, a poll round being one memory round trip; reached only if the
+ * chunks were not co-resident).  polls = 0 makes
  * every cross-chunk wait give up at once, which exercises that path; a map of
  * one chunk never waits.  DPT_E_ARG for polls < 0. */
 #define DPT_DEFAULT_SPIN_LIMIT 4194304

@@ -146,7 +146,8 @@ __device__ __forceinline__ bool exchange_partials(uint64_t* partials, int chunk,
       if (kCycleProfile && polls) *polls = t + 1;
       return true;
     }
-    __builtin_amdgcn_s_sleep(1);
+    // no sleep between rounds: a round is already a memory round trip, and
+    // the next one starts as soon as this one has shown a word missing
   }
   return false;
 }
