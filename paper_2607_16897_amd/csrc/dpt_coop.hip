@@ -161,8 +161,9 @@ template <bool KAHAN, int NV>
 __device__ __forceinline__ bool exchange_wide(const uint64_t* partials, int nch, uint32_t tag, int spin_limit,
                                               float* sh_grp, float* sh_tot) {
   const int t = threadIdx.x, v = t & 31, q = t >> 5, G = blockDim.x >> 5;
-  // global-memory pointers and no branch between a batch's loads, as in
-  // exchange_partials: past the last chunk a lane re-reads it and drops the word
+  // global-memory pointers, no branch between a batch's loads and no sleep
+  // between rounds, as in exchange_partials: past the last chunk a lane
+  // re-reads it and drops the word
   using gptr = const __attribute__((address_space(1))) uint64_t*;
   const gptr buf = (gptr)(partials + (size_t)(tag & 1u) * nch * 32);
   const gptr slow = (gptr)(partials + (size_t)(2 + (tag & 1u)) * nch * 32);
@@ -196,7 +197,6 @@ __device__ __forceinline__ bool exchange_wide(const uint64_t* partials, int nch,
           }
         }
       }
-      if (!ok) __builtin_amdgcn_s_sleep(1);
     }
     sh_grp[q * NV + v] = s;
   }
